@@ -1,0 +1,289 @@
+"""FP64 CPU oracle of the funnel transform (Wei, Feng, Zheng, arXiv 1904.09409).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or links
+this module: only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline
+leg of ``bench.py`` may use it.  It shares no code with the HIP library.
+
+Every stage is the plain definition written out in float64 with explicit DFT
+matrices (a matrix product is the only library primitive used) and direct
+per-row linear interpolation, in the order the paper gives the steps
+(Sec. 3.1): FFT along y -> NVMT -> FFT along x' -> inverse FFT along omega_2.
+
+Conventions (readings of the paper, each one listed with its reason in the
+design notes of the repository):
+
+* image ``I[r, c]``: N rows (height, y), M columns (width, x), both even.
+* expansion (Sec. 4.2): the image is padded with zero rows to a total height
+  ``Np`` (default N+M, i.e. M/2 rows above and below); the centre of the
+  Cartesian frame is the frame centre, ``y = r' - Np/2`` and ``x = c - M/2``.
+* omega_max = pi, so the NVMT ratio of frequency row n2 is ``s = 2 n2 / Np``
+  and the slope step is 2/M (Eq. 22).
+* only the top half of the spectrum, ``n2 = 1 .. Np/2-1``, is resampled; the
+  bottom half follows by conjugate symmetry (Sec. 3.1); the DC and Nyquist
+  rows are dropped.
+* forward DFTs are unnormalised, the final inverse DFT carries 1/Np.
+* parameter plane ``P[y + Np/2, m1 + M/2]`` is real; the brightness is |P|.
+  A line ``y = k x + b`` (centred) peaks at ``m1 = -k M/2``, ``y = b``
+  (Eq. 19 with the sign of Eq. 13); the paper's slope index is m = -m1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "padded_length", "expand", "spectrum_y", "nvmt", "dft_x", "idft_y",
+    "forward_regular", "forward_inverse", "forward",
+    "adjoint_regular", "adjoint_inverse", "adjoint",
+    "boundary_mask", "peaks_list", "peak_params",
+]
+
+
+# --------------------------------------------------------------------------
+# Forward transform, Sec. 3.1
+# --------------------------------------------------------------------------
+
+def padded_length(N: int, M: int, padded_len: int = 0) -> int:
+    """Length of the expanded axis (Sec. 4.2): N+M by default.  An explicit
+    even length >= N may be asked for; lengths below N+M give up the
+    intercept-wrap protection of the expansion (Eq. 20, Fig. 6)."""
+    Np = N + M if padded_len == 0 else int(padded_len)
+    if Np < N or Np % 2:
+        raise ValueError("padded length must be even and >= N")
+    return Np
+
+
+def expand(img: np.ndarray, Np: int) -> np.ndarray:
+    """Sec. 4.2: place the N image rows in an Np-row zero frame with
+    (Np-N)//2 zero rows above them."""
+    N, M = img.shape
+    top = (Np - N) // 2
+    out = np.zeros((Np, M), dtype=np.float64)
+    out[top:top + N] = img
+    return out
+
+
+def _ydft_matrix(Np: int) -> np.ndarray:
+    """E[n2-1, r'] = exp(-j 2 pi n2 y / Np), y = r' - Np/2, n2 = 1..Np/2-1."""
+    n2 = np.arange(1, Np // 2)
+    y = np.arange(Np) - Np // 2
+    return np.exp(-2j * np.pi * np.outer(n2, y) / Np)
+
+
+def _xdft_matrix(M: int) -> np.ndarray:
+    """W[x'+M/2, m1+M/2] = exp(-j 2 pi m1 x' / M) over centred x', m1."""
+    x = np.arange(M) - M // 2
+    return np.exp(-2j * np.pi * np.outer(x, x) / M)
+
+
+def spectrum_y(img_pad: np.ndarray) -> np.ndarray:
+    """Sec. 3.1 first step (Eq. 16): DFT of every column along y.
+
+    Returns S[n2-1, c] = sum_y I_pad[y, c] exp(-j 2 pi n2 y / Np) for the top
+    half n2 = 1 .. Np/2-1 (negative n2 follow by conjugation, Sec. 3.1)."""
+    return _ydft_matrix(img_pad.shape[0]) @ img_pad
+
+
+def nvmt(S: np.ndarray, Np: int) -> np.ndarray:
+    """Sec. 3.1 second step, Eq. 17: the nonlinear variable-metric transform
+    x' = s x with s = omega_2/omega_max = 2 n2 / Np, realised by linear
+    interpolation (the O(M^2) option of Sec. V): g[x'] = f(x'/s).
+
+    f[i] = S[n2, i - M/2] for 0 <= i < M and 0 outside.  The fractional array
+    position i_p = x'/s + M/2 = (x' Np + M n2) / (2 n2) is split with an exact
+    integer floor, i0 = floor(num/den), t = (num - i0 den)/den."""
+    h, M = S.shape
+    xp = np.arange(M, dtype=np.int64) - M // 2
+    g = np.zeros_like(S)
+    for n2 in range(1, h + 1):
+        f = S[n2 - 1]
+        num = xp * Np + M * n2
+        den = 2 * n2
+        i0 = num // den
+        t = (num - i0 * den) / den
+        ok0 = (i0 >= 0) & (i0 < M)
+        ok1 = (i0 + 1 >= 0) & (i0 + 1 < M)
+        f0 = np.where(ok0, f[np.clip(i0, 0, M - 1)], 0.0)
+        f1 = np.where(ok1, f[np.clip(i0 + 1, 0, M - 1)], 0.0)
+        g[n2 - 1] = (1.0 - t) * f0 + t * f1
+    return g
+
+
+def dft_x(g: np.ndarray) -> np.ndarray:
+    """Sec. 3.1 third step: DFT along x' of every row,
+    G[n2, m1] = sum_x' g[n2, x'] exp(-j 2 pi m1 x' / M), centred x', m1."""
+    return g @ _xdft_matrix(g.shape[1])
+
+
+def idft_y(G: np.ndarray, Np: int) -> np.ndarray:
+    """Sec. 3.1 fourth step (Eq. 19 / P(omega_1, y)): inverse DFT along omega_2.
+
+    The bottom half of the spectrum is completed by G[-n2] = conj(G[n2]); the
+    DC and Nyquist rows are zero.  P[y, m1] = (1/Np) sum_n2 G[n2, m1]
+    exp(+j 2 pi n2 y / Np), y = -Np/2 .. Np/2-1.  The result is real; its
+    imaginary part is checked to be rounding noise."""
+    h, M = G.shape
+    full = np.zeros((Np, M), dtype=np.complex128)   # row index n2 + Np/2
+    n2 = np.arange(1, h + 1)
+    full[n2 + Np // 2] = G
+    full[-n2 + Np // 2] = np.conj(G)
+    y = np.arange(Np) - Np // 2
+    Winv = np.exp(2j * np.pi * np.outer(y, y) / Np)
+    P = (Winv @ full) / Np
+    scale = max(1.0, float(np.abs(P.real).max()))
+    if np.abs(P.imag).max() > 1e-9 * scale:
+        raise AssertionError("inverse DFT of a Hermitian spectrum is not real")
+    return P.real
+
+
+def forward_regular(img: np.ndarray, padded_len: int = 0) -> np.ndarray:
+    """Funnel transform (Sec. 3.1) of one image on its expanded frame
+    (Sec. 4.2): the regular parameter space, slopes in (-1, 1].
+    Returns P[Np, M] in float64."""
+    img = np.asarray(img, dtype=np.float64)
+    N, M = img.shape
+    Np = padded_length(N, M, padded_len)
+    S = spectrum_y(expand(img, Np))
+    return idft_y(dft_x(nvmt(S, Np)), Np)
+
+
+def forward_inverse(img: np.ndarray, padded_len: int = 0) -> np.ndarray:
+    """Inverse funnel transform (Sec. 3.1, dual form; Remark 1): the same four
+    steps with the roles of x and y exchanged, i.e. the funnel transform of the
+    transposed image.  Returns P_inv[Np, N]: rows are the x-intercept, columns
+    the inverse-slope bin."""
+    img = np.asarray(img, dtype=np.float64)
+    return forward_regular(img.T, padded_len)
+
+
+def forward(img: np.ndarray, padded_len: int = 0):
+    """Both parameter spaces (Sec. 4.1): (regular, inverse)."""
+    return forward_regular(img, padded_len), forward_inverse(img, padded_len)
+
+
+# --------------------------------------------------------------------------
+# Adjoint (transpose of the real-linear map image -> plane)
+# --------------------------------------------------------------------------
+
+def _nvmt_transpose(dg: np.ndarray, Np: int) -> np.ndarray:
+    """Transpose of ``nvmt``: each interpolation weight sends dg[x'] back to
+    the two samples it was read from."""
+    h, M = dg.shape
+    xp = np.arange(M, dtype=np.int64) - M // 2
+    dS = np.zeros_like(dg)
+    for n2 in range(1, h + 1):
+        num = xp * Np + M * n2
+        den = 2 * n2
+        i0 = num // den
+        t = (num - i0 * den) / den
+        row = np.zeros(M, dtype=np.complex128)
+        ok0 = (i0 >= 0) & (i0 < M)
+        ok1 = (i0 + 1 >= 0) & (i0 + 1 < M)
+        np.add.at(row, i0[ok0], (1.0 - t[ok0]) * dg[n2 - 1, ok0])
+        np.add.at(row, i0[ok1] + 1, t[ok1] * dg[n2 - 1, ok1])
+        dS[n2 - 1] = row
+    return dS
+
+
+def adjoint_regular(dP: np.ndarray, N: int, M: int, padded_len: int = 0) -> np.ndarray:
+    """Transpose of ``forward_regular`` under the real inner products of
+    image and plane: dI = A^T B^T C^T dP, where C is the Hermitian inverse DFT,
+    B the NVMT followed by the x' DFT and A the expansion plus y DFT."""
+    dP = np.asarray(dP, dtype=np.float64)
+    Np = padded_length(N, M, padded_len)
+    assert dP.shape == (Np, M)
+    # C^T: P = (1/Np) sum_n2 2 Re(G[n2] e^{+j theta})  =>  dG = (2/Np) sum_y dP e^{-j theta}
+    dG = (2.0 / Np) * (_ydft_matrix(Np) @ dP)
+    # B^T: conjugate transpose of the x' DFT, then the transposed interpolation
+    dg = dG @ np.conj(_xdft_matrix(M)).T
+    dS = _nvmt_transpose(dg, Np)
+    # A^T: S = E I_pad with real I_pad  =>  dI_pad = Re(E^H dS), then crop
+    dI_pad = np.real(np.conj(_ydft_matrix(Np)).T @ dS)
+    top = (Np - N) // 2
+    return dI_pad[top:top + N]
+
+
+def adjoint_inverse(dPinv: np.ndarray, N: int, M: int, padded_len: int = 0) -> np.ndarray:
+    """Transpose of ``forward_inverse``."""
+    return adjoint_regular(dPinv, M, N, padded_len).T
+
+
+def adjoint(dP: np.ndarray, dPinv: np.ndarray, N: int, M: int, padded_len: int = 0) -> np.ndarray:
+    """Transpose of ``forward`` (both spaces): the two image gradients add."""
+    return adjoint_regular(dP, N, M, padded_len) + adjoint_inverse(dPinv, N, M, padded_len)
+
+
+# --------------------------------------------------------------------------
+# Peak detection (Sec. 4.4) and peak -> line parameters (Eqs. 22-25)
+# --------------------------------------------------------------------------
+
+def boundary_mask(N: int, M: int, Np: int) -> np.ndarray:
+    """Cells of a regular plane (Np x M) where the artificial top and bottom
+    borders created by the expansion focus (Sec. 4.2, removed in Sec. VI):
+    slope bins m1 in {-1, 0, 1} and rows within 2 of y = -N/2 or y = N/2.
+    For the inverse plane call with (M, N, Np)."""
+    mask = np.zeros((Np, M), dtype=bool)
+    cols = np.array([-1, 0, 1]) + M // 2
+    for edge in (-N // 2, N // 2):
+        rows = np.arange(edge - 2, edge + 2) + Np // 2
+        rows = rows[(rows >= 0) & (rows < Np)]
+        mask[np.ix_(rows, cols)] = True
+    return mask
+
+
+def peaks_list(B: np.ndarray, K: int, T: float, radius: int = 1,
+               mask: np.ndarray | None = None, wrap: bool = True) -> list[int]:
+    """The list-based peak detection of Sec. 4.4, literally.
+
+    Every cell goes on a candidate list sorted by brightness, descending (ties:
+    lower linear index first).  Cells are visited in that order; a cell joins
+    the detected list if no cell of its (2r+1)^2 neighbourhood has been
+    visited before, and is marked visited either way.  The loop stops at K
+    detections or at the first cell darker than T.  Cells inside ``mask`` are
+    visited but never detected.  The neighbourhood wraps around the plane
+    (which is periodic in both axes, Eqs. 20-21) unless ``wrap`` is False.
+    Returns the linear indices of the detected cells in detection order."""
+    B = np.asarray(B)
+    rows, cols = B.shape
+    flat = B.ravel()
+    order = np.lexsort((np.arange(flat.size), -flat))
+    visited = np.zeros((rows, cols), dtype=bool)
+    off = np.arange(-radius, radius + 1)
+    detected: list[int] = []
+    if K <= 0:
+        return detected
+    for idx in order:
+        v = flat[idx]
+        if v < T:
+            break
+        r, c = divmod(int(idx), cols)
+        rr, cc = r + off, c + off
+        if wrap:
+            rr, cc = rr % rows, cc % cols
+        else:
+            rr, cc = rr[(rr >= 0) & (rr < rows)], cc[(cc >= 0) & (cc < cols)]
+        seen = visited[np.ix_(rr, cc)].any()
+        visited[r, c] = True
+        if not seen and not (mask is not None and mask[r, c]):
+            detected.append(int(idx))
+            if len(detected) == K:
+                break
+    return detected
+
+
+def peak_params(row: int, col: int, N: int, M: int, Np: int, space: str = "regular"):
+    """Eqs. 22-25: cell -> line parameters, in pixel-index coordinates.
+
+    Regular space (plane Np x M): m1 = col - M/2, slope k = -2 m1 / M (the
+    paper's m is -m1), centred intercept y = row - Np/2; the line is
+    ``row = k * col + b`` with b = y - k M/2 + N/2.
+    Inverse space (plane Np x N): n1 = col - N/2, inverse slope
+    k_inv = -2 n1 / N, centred x-intercept xb = row - Np/2; the line is
+    ``col = k_inv * row + b_x`` with b_x = xb - k_inv N/2 + M/2.
+    Returns (slope, intercept) of the respective form."""
+    if space == "regular":
+        k = -2.0 * (col - M // 2) / M
+        y = row - Np // 2
+        return k, y - k * M / 2 + N / 2
+    kinv = -2.0 * (col - N // 2) / N
+    xb = row - Np // 2
+    return kinv, xb - kinv * N / 2 + M / 2

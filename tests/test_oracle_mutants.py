@@ -1,0 +1,118 @@
+"""Each plausible mistake planted in the oracle (on the CPU) must be caught by
+at least one pin, which shows the pins constrain every stage."""
+import numpy as np
+import pytest
+
+import pins
+from oracle import funnel_oracle as O
+
+
+def _swap_lerp_weights(S, Np):
+    h, M = S.shape
+    xp = np.arange(M, dtype=np.int64) - M // 2
+    g = np.zeros_like(S)
+    for n2 in range(1, h + 1):
+        f = S[n2 - 1]
+        num = xp * Np + M * n2
+        i0 = num // (2 * n2)
+        t = (num - i0 * 2 * n2) / (2 * n2)
+        f0 = np.where((i0 >= 0) & (i0 < M), f[np.clip(i0, 0, M - 1)], 0)
+        f1 = np.where((i0 + 1 >= 0) & (i0 + 1 < M), f[np.clip(i0 + 1, 0, M - 1)], 0)
+        g[n2 - 1] = t * f0 + (1 - t) * f1
+    return g
+
+
+def _omega_max_2pi(S, Np):
+    # reads omega_max as 2*pi: s = n2 / Np
+    h, M = S.shape
+    return _REAL["nvmt"](S, 2 * Np)
+
+
+def _conj_spectrum_sign(img_pad):
+    return np.conj(_REAL["spectrum_y"](img_pad))
+
+
+def _xdft_wrong_sign(g):
+    return np.conj(_REAL["dft_x"](np.conj(g)))
+
+
+def _no_conj_completion(G, Np):
+    h, M = G.shape
+    full = np.zeros((Np, M), complex)
+    n2 = np.arange(1, h + 1)
+    full[n2 + Np // 2] = G
+    full[-n2 + Np // 2] = G                     # missing conjugate
+    y = np.arange(Np) - Np // 2
+    return ((np.exp(2j * np.pi * np.outer(y, y) / Np) @ full) / Np).real
+
+
+def _no_expansion_offset(img, Np):
+    N, M = img.shape
+    out = np.zeros((Np, M))
+    out[:N] = img                                # image placed at the top
+    return out
+
+
+def _adjoint_missing_two(dP, N, M, padded_len=0):
+    return 0.5 * _REAL["adjoint_regular"](dP, N, M, padded_len)
+
+
+def _peaks_only_detected_suppress(B, K, T, radius=1, mask=None, wrap=True):
+    # marks only detected cells as visited (a plausible misreading)
+    rows, cols = B.shape
+    flat = B.ravel()
+    order = np.lexsort((np.arange(flat.size), -flat))
+    det_mask = np.zeros((rows, cols), bool)
+    off = np.arange(-radius, radius + 1)
+    out = []
+    for idx in order:
+        if flat[idx] < T or len(out) == K:
+            break
+        r, c = divmod(int(idx), cols)
+        rr, cc = r + off, c + off
+        if wrap:
+            rr, cc = rr % rows, cc % cols
+        else:
+            rr, cc = rr[(rr >= 0) & (rr < rows)], cc[(cc >= 0) & (cc < cols)]
+        if not det_mask[np.ix_(rr, cc)].any() and not (mask is not None and mask[r, c]):
+            det_mask[r, c] = True
+            out.append(int(idx))
+    return out
+
+
+_REAL = {name: getattr(O, name) for name in
+         ("nvmt", "spectrum_y", "dft_x", "idft_y", "expand", "adjoint_regular", "peaks_list")}
+
+ALL_CHECKS = [
+    pins.check_spectrum_is_library_fft, pins.check_xdft_is_library_fft,
+    pins.check_ydft_inverse_is_library_ifft, pins.check_parseval,
+    pins.check_nvmt_exact_on_linear_rows, pins.check_nvmt_funnel_support,
+    pins.check_point_to_line, pins.check_line_to_point, pins.check_fig9_worked_example,
+    pins.check_fig6_intercept_wrap, pins.check_fig7_slope_wrap,
+    pins.check_shift_equivariance, pins.check_adjoint_dot, pins.check_adjoint_dense,
+    pins.check_peaks_equal_local_maxima,
+]
+
+MUTANTS = {
+    "lerp weights swapped": ("nvmt", _swap_lerp_weights),
+    "omega_max read as 2 pi": ("nvmt", _omega_max_2pi),
+    "y DFT exponent sign": ("spectrum_y", _conj_spectrum_sign),
+    "x DFT exponent sign": ("dft_x", _xdft_wrong_sign),
+    "Hermitian completion without conjugate": ("idft_y", _no_conj_completion),
+    "expansion not centred": ("expand", _no_expansion_offset),
+    "adjoint loses factor 2": ("adjoint_regular", _adjoint_missing_two),
+    "peak list suppresses only by detected cells": ("peaks_list", _peaks_only_detected_suppress),
+}
+
+
+@pytest.mark.parametrize("name", list(MUTANTS))
+def test_mutant_is_caught(name, monkeypatch):
+    attr, fn = MUTANTS[name]
+    monkeypatch.setattr(O, attr, fn)
+    caught = []
+    for check in ALL_CHECKS:
+        try:
+            check(O)
+        except (AssertionError, ValueError, IndexError):
+            caught.append(check.__name__)
+    assert caught, f"no pin catches: {name}"
