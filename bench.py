@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Throughput of the funnel transform forward + adjoint on one MI355X.
+
+Workload: a batch of 32 synthetic 1024x1024 float32 line images (5 mixed
+ridge/step lines each, Gaussian noise), both parameter spaces (Np = 2048).
+One step = funnel_forward of the batch + funnel_adjoint of the loss gradient
+(sign of P at every line's focus cell).  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0     # MI355X HBM3E, AMD published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def focus_cells(lines, N, M, Np):
+    """(space, row, col) where each line focuses (Eq. 19): regular space for
+    lines row = k col + b, inverse space for transposed lines."""
+    out = []
+    for ln in lines:
+        if not ln.transposed:
+            bc = ln.b + ln.k * M / 2 - N / 2
+            out.append((0, int(round(bc)) + Np // 2, (int(round(-ln.k * M / 2)) + M // 2) % M))
+        else:
+            bc = ln.b + ln.k * N / 2 - M / 2
+            out.append((1, int(round(bc)) + Np // 2, (int(round(-ln.k * N / 2)) + N // 2) % N))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--size", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-images", type=int, default=2, help="images in the CPU oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(images are independent: a multi-GPU run would shard the batch)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1904_09409_amd import funnel as F
+    from paper_1904_09409_amd import synth
+
+    F.load_library()  # fails loudly if the HIP library is missing
+    B, N, M = args.batch, args.size, args.size
+    log(f"generating {B} synthetic {N}x{M} images")
+    t0 = time.time()
+    imgs = synth.batch("grad", count=B, size=N, seed=0)
+    host = synth.stack(imgs)
+    log(f"  {time.time() - t0:.1f} s")
+
+    plan = F.FunnelPlan(B, N, M, 0, F.FT_SPACE_BOTH)
+    Np = plan.Np
+    x = torch.from_numpy(host).cuda()
+    planes = plan.forward(x)
+    torch.cuda.synchronize()
+    # loss = sum over lines of |P| at the focus cell -> dL/dP = sign(P) there
+    dP = torch.zeros_like(planes)
+    views = plan.views(planes)
+    dviews = plan.views(dP)
+    for b, im in enumerate(imgs):
+        for sp, r, c in focus_cells(im.lines, N, M, Np):
+            src = views.regular if sp == 0 else views.inverse
+            dst = dviews.regular if sp == 0 else dviews.inverse
+            dst[b, r, c] = torch.sign(src[b, r, c])
+    dI = torch.empty_like(x)
+    torch.cuda.synchronize()
+
+    def step():
+        plan.forward(x, planes)
+        plan.adjoint(dP, dI)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(args.steps):
+        step()
+    end.record()
+    torch.cuda.synchronize()
+    ms_per_step = start.elapsed_time(end) / args.steps
+    mpix = B * N * M / (ms_per_step * 1e-3) / 1e6
+
+    # per-kernel event times over a second timed region of the same launches
+    F.funnel_profile_enable(plan.handle, args.steps * 16)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    kernels = F.funnel_profile_read(plan.handle)
+    F.funnel_profile_disable(plan.handle)
+    for k in kernels:
+        k["avg_ms"] = k["total_ms"] / k["launches"]
+        k["gbps"] = k["bytes_per_launch"] / k["avg_ms"] / 1e6
+    kernels.sort(key=lambda k: -k["total_ms"])
+    dom = kernels[0]
+    step_bytes = sum(k["bytes_per_launch"] * k["launches"] for k in kernels) / args.steps
+    step_kernel_ms = sum(k["total_ms"] for k in kernels) / args.steps
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(imgs[: args.cpu_images], dP, plan, N, M)
+
+    out = {
+        "metric": "Mpixel/s funnel fwd+adjoint, 1024^2 fp32 batch; % of HBM roofline",
+        "value": round(mpix, 1),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{B} x {N}x{M} fp32 synthetic line images (5 ridge/step lines, noise), "
+                        f"regular+inverse space, Np={Np}, forward + adjoint",
+            "batch": B, "rows": N, "cols": M, "padded_len": Np, "spaces": "both",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom["name"],
+            "achieved": round(dom["gbps"], 1),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(dom["gbps"] / HBM_PEAK_GBPS, 4),
+            "traffic": None,
+            "step_algorithmic_gbps": round(step_bytes / (ms_per_step * 1e6), 1),
+            "step_frac": round(step_bytes / (ms_per_step * 1e6) / HBM_PEAK_GBPS, 4),
+            "step_bytes": step_bytes,
+            "kernel_ms_sum": round(step_kernel_ms, 4),
+        },
+        "kernels": [{"name": k["name"], "avg_ms": round(k["avg_ms"], 4),
+                     "bytes": k["bytes_per_launch"], "gbps": round(k["gbps"], 1)} for k in kernels],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(imgs, dP, plan, N, M):
+    """The FP64 oracle, as it stands, on a bounded sample: forward (both
+    spaces) and adjoint of a few images of the same workload."""
+    from oracle import funnel_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    Np = plan.Np
+    dPh = dP.cpu().numpy()
+    t0 = time.time()
+    for b, im in enumerate(imgs):
+        O.forward(im.image, Np)
+        reg = dPh[b, : Np * M].reshape(Np, M).astype(np.float64)
+        inv = dPh[b, Np * M:].reshape(Np, N).astype(np.float64)
+        O.adjoint(reg, inv, N, M, Np)
+    dt = time.time() - t0
+    n = len(imgs)
+    return {"value": round(n * N * M / dt / 1e6, 4), "unit": "Mpixel/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n} of the {plan.batch} {N}x{M} images, forward both spaces + adjoint, {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * funnel.h -- C ABI of the MI355X (gfx950) funnel-transform library.
+ *
+ * The funnel transform (Wei, Feng, Zheng, "Funnel Transform for Straight Line
+ * Detection", arXiv 1904.09409) maps a grayscale image to a slope-intercept
+ * parameter plane in which every straight line focuses to a peak.  It is three
+ * 1D Fourier transforms around the nonlinear variable-metric transform (NVMT),
+ * Sec. 3.1:
+ *
+ *   S(x, w2)   = DFT_y  of the expanded image            (Sec. 3.1 step 1, Sec. 4.2)
+ *   g(x', w2)  = S(x'/s, w2), s = w2/w_max               (step 2, Eq. 17; linear
+ *                                                          interpolation, Sec. V)
+ *   G(w1, w2)  = DFT_x' of g                             (step 3)
+ *   P(w1, y)   = inverse DFT_w2 of G                     (step 4, Eq. 19)
+ *
+ * The regular space covers slopes in (-1, 1]; the inverse space is the same
+ * transform of the transposed image and covers the steeper lines (Sec. 4.1,
+ * Sec. 4.2).  Peaks of |P| are found by the list rule of Sec. 4.4 and read as
+ * line parameters by Eqs. 22-25.
+ *
+ * Conventions fixed by this library (the paper leaves them open):
+ *   - image I[r][c]: N rows (height), M columns (width), row-major float32,
+ *     N and M even and >= 4; images of a batch are contiguous (stride N*M).
+ *   - expansion (Sec. 4.2): the y axis is padded to Np = N+M (or padded_len)
+ *     with (Np-N)/2 zero rows on top; the frame centre is the origin:
+ *     y = r' - Np/2, x = c - M/2.
+ *   - w_max = pi, hence s = 2 n2 / Np for frequency row n2 = 1 .. Np/2-1; the
+ *     DC and Nyquist rows are zero and negative rows follow by conjugate
+ *     symmetry (Sec. 3.1).
+ *   - NVMT: g[x'] = (1-t) f[i0] + t f[i0+1], i0 = floor((x' Np + M n2)/(2 n2))
+ *     by exact integer division, f = S row indexed from 0 at x = -M/2, zero
+ *     outside [0, M).
+ *   - forward DFTs unnormalised; the last inverse DFT carries 1/Np.
+ *   - regular plane: float32 P[Np][M], row = y + Np/2, column = m1 + M/2; a
+ *     line row = k*col + b focuses at m1 = -k M/2, y = b + k M/2 - N/2.
+ *     Inverse plane: float32 P_inv[Np][N], the same for the transposed image.
+ *   - the planes of one image are contiguous: regular first, then inverse
+ *     (for the spaces the plan computes); images follow each other with the
+ *     stride given by funnel_plane_elems().
+ *
+ * Ownership and threading: the caller owns every image, plane, peak and
+ * workspace buffer (device memory).  A plan owns only its constant tables.
+ * funnel_forward / funnel_adjoint / funnel_peaks never allocate, never
+ * synchronise and never print: they enqueue kernels on the given stream and
+ * return.  Plans are immutable after creation and may be used from several
+ * streams at once if every concurrent call gets its own workspace.
+ *
+ * Errors: every call validates its arguments on the host before any device
+ * work; on error it returns a status, writes nothing and keeps a message for
+ * funnel_last_error() (thread-local).  Device pointers must be 16-byte
+ * aligned.  Faults of already-enqueued kernels surface as FT_ERR_HIP from a
+ * later call or from the caller's stream synchronisation.
+ */
+#ifndef FUNNEL_H
+#define FUNNEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FT_OK = 0,
+  FT_ERR_INVALID_ARG = 1,       /* NULL pointer, bad count, bad flag, NaN threshold ... */
+  FT_ERR_UNSUPPORTED_SIZE = 2,  /* a transform length this build has no kernel for */
+  FT_ERR_MISALIGNED = 3,        /* a device pointer not 16-byte aligned */
+  FT_ERR_WORKSPACE_TOO_SMALL = 4,
+  FT_ERR_NO_DEVICE = 5,         /* no HIP device, or the plan's device is not current */
+  FT_ERR_HIP = 6,               /* a HIP runtime call failed */
+  FT_ERR_OUT_OF_MEMORY = 7      /* plan creation could not allocate its tables */
+} ft_status;
+
+/* Which parameter spaces a plan computes (Sec. 4.1). */
+enum { FT_SPACE_REGULAR = 1, FT_SPACE_INVERSE = 2, FT_SPACE_BOTH = 3 };
+
+/* Arithmetic of the DFT stages. */
+enum { FT_PREC_FP32 = 0 };
+
+/* funnel_peaks flags. */
+enum {
+  FT_PEAK_CLAMP_BORDER = 1u,     /* neighbourhood clamped at the plane edge instead of wrapping */
+  FT_PEAK_KEEP_PAD_BOUNDARY = 2u /* do not drop the cells where the expansion borders focus */
+};
+
+typedef struct ft_plan ft_plan;
+
+typedef struct {
+  int32_t batch;       /* number of images, >= 1 */
+  int32_t rows;        /* N, image height, even, >= 4 */
+  int32_t cols;        /* M, image width, even, >= 4 */
+  int32_t padded_len;  /* Np; 0 means N+M (Sec. 4.2); else even and >= N+M */
+  int32_t spaces;      /* FT_SPACE_REGULAR, FT_SPACE_INVERSE or FT_SPACE_BOTH */
+  int32_t precision;   /* FT_PREC_FP32 */
+  uint32_t flags;      /* reserved, must be 0 */
+} ft_plan_desc;
+
+/* One detected peak (Sec. 4.4) and its line (Eqs. 22-25).
+ * space 0 (regular): the line is row = slope*col + intercept;
+ * space 1 (inverse): the line is col = slope*row + intercept
+ * (pixel-index coordinates of the input image, pixel centres at integers). */
+typedef struct {
+  int32_t image;
+  int32_t space;
+  int32_t row;         /* plane row (intercept bin) */
+  int32_t col;         /* plane column (slope bin) */
+  float value;         /* brightness |P| */
+  float slope;
+  float intercept;
+} ft_peak;
+
+/* Create a plan on the current HIP device: validates the description, builds
+ * the radix schedule of every transform length and uploads the FP64-derived
+ * twiddle tables (the only allocation the library makes).
+ * Returns FT_ERR_UNSUPPORTED_SIZE when a length has no compiled kernel. */
+ft_status funnel_plan_create(const ft_plan_desc* desc, ft_plan** out);
+
+/* Release the plan's tables.  NULL is accepted. */
+void funnel_plan_destroy(ft_plan* plan);
+
+/* Bytes of device workspace funnel_forward and funnel_adjoint need. */
+ft_status funnel_workspace_size(const ft_plan* plan, size_t* bytes);
+
+/* Floats of parameter plane per image (regular Np*M and/or inverse Np*N). */
+ft_status funnel_plane_elems(const ft_plan* plan, size_t* floats_per_image);
+
+/* Padded length Np the plan uses. */
+ft_status funnel_padded_len(const ft_plan* plan, int32_t* np);
+
+/* Forward funnel transform of a batch (Sec. 3.1 on the expanded image of
+ * Sec. 4.2, for the spaces of the plan).
+ *   images : device, float32 [batch][N][M]
+ *   planes : device, float32 [batch][funnel_plane_elems], overwritten with P
+ *            (signed; the brightness is |P|)
+ *   ws     : device workspace of at least funnel_workspace_size bytes
+ *   stream : hipStream_t (NULL = default stream) */
+ft_status funnel_forward(const ft_plan* plan, const float* images, float* planes,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint (transpose) of funnel_forward under the real inner products of
+ * images and planes: d_images = F^T d_planes, the two spaces' contributions
+ * summed.  d_images is overwritten.  Same layouts as funnel_forward.
+ * Implemented as the transposed passes: (2/Np) DFT along y, conjugate DFT
+ * along x' followed by the transposed interpolation (a gather with at most
+ * two taps, no atomics), and the real part of the conjugate y DFT cropped to
+ * the image rows. */
+ft_status funnel_adjoint(const ft_plan* plan, const float* d_planes, float* d_images,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of device workspace funnel_peaks needs for a given K. */
+ft_status funnel_peaks_workspace_size(const ft_plan* plan, int32_t K, size_t* bytes);
+
+/* List-based peak detection of Sec. 4.4 on |P| of every plane: the first K
+ * cells, in the order (|P| descending, linear index ascending), that precede
+ * every other cell of their (2*radius+1)^2 neighbourhood, have |P| >= threshold
+ * and are not border cells of the expansion (rows within 2 of y = +-N/2 at
+ * slope bins -1..1; for the inverse plane N -> M) unless
+ * FT_PEAK_KEEP_PAD_BOUNDARY is set.  This equals the visiting-list procedure
+ * of the paper exactly.
+ *   planes  : device, as written by funnel_forward
+ *   K       : 1 .. 256
+ *   radius  : 1 .. 8
+ *   peaks   : device, ft_peak [batch][n_spaces][K], entries beyond the count
+ *             are left unspecified
+ *   n_found : device, int32 [batch][n_spaces]
+ * Spaces are ordered regular then inverse, as in the plane layout. */
+ft_status funnel_peaks(const ft_plan* plan, const float* planes, int32_t K, float threshold,
+                       int32_t radius, uint32_t flags, ft_peak* peaks, int32_t* n_found,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* ---- kernel timing (for measurement tools) ----
+ * When enabled on a plan, every funnel_forward / funnel_adjoint call records a
+ * HIP event pair around each kernel it launches, on the call's stream, and
+ * notes that kernel's algorithmic HBM bytes (each input read once, each
+ * output written once).  Enabling allocates the events (up to max_records
+ * launches are kept; later launches are not recorded).  A plan being profiled
+ * must not be used from two host threads at once. */
+typedef struct {
+  char name[40];          /* pass name, e.g. "regular.A" */
+  int32_t launches;       /* launches recorded */
+  float total_ms;         /* summed event time */
+  double bytes_per_launch;/* algorithmic bytes moved by one launch */
+} ft_kernel_time;
+
+ft_status funnel_profile_enable(ft_plan* plan, int32_t max_records);
+/* Synchronises on the recorded events, aggregates them per kernel name into
+ * out[0 .. *n-1] (at most cap entries) and clears the records. */
+ft_status funnel_profile_read(ft_plan* plan, ft_kernel_time* out, int32_t cap, int32_t* n);
+ft_status funnel_profile_disable(ft_plan* plan);
+
+/* Human-readable name of a status. */
+const char* funnel_status_string(ft_status status);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* funnel_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FUNNEL_H */

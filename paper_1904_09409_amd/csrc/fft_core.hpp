@@ -1,0 +1,335 @@
+// fft_core.hpp -- device building blocks of the funnel transform's 1D DFTs.
+//
+// A transform of length L is computed by P cooperating threads with the
+// Stockham self-sorting formulation: for a pass of radix R after the radices
+// already applied (product NS), butterfly j reads x[j + r L/R], r = 0..R-1,
+// multiplies input r by w_L^(r (j mod NS) L/(NS R)), takes the R-point DFT and
+// writes output q to (j/NS) NS R + (j mod NS) + q NS.  The first pass reads
+// through a caller functor (a global load, or the NVMT gather) and the last
+// pass writes through another, so only the exchanges in between touch LDS.
+// Radix schedules are fixed at compile time from the factorisation of L
+// (16/8/4/2 for the power-of-two part, then 7, 5, 3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace funnel {
+
+// ---------------------------------------------------------------- complex ops
+
+__device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 c_mul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 c_mul_mi(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// multiply by exp(-+ i 2 pi m / R) given (cos, sin) of 2 pi m / R
+template <bool INV>
+__device__ __forceinline__ float2 c_rot(float2 a, float c, float s) {
+  const float ss = INV ? s : -s;
+  return make_float2(a.x * c - a.y * ss, a.x * ss + a.y * c);
+}
+
+// ---------------------------------------------------------------- radix plan
+
+struct RadixPlan {
+  int n;
+  int r[24];
+};
+
+constexpr RadixPlan radix_plan(int L) {
+  RadixPlan p{0, {}};
+  int rem = L, a = 0;
+  while (rem % 2 == 0) { rem /= 2; ++a; }
+  while (a >= 4) { p.r[p.n++] = 16; a -= 4; }
+  if (a == 3) p.r[p.n++] = 8;
+  else if (a == 2) p.r[p.n++] = 4;
+  else if (a == 1) p.r[p.n++] = 2;
+  while (rem % 7 == 0) { p.r[p.n++] = 7; rem /= 7; }
+  while (rem % 5 == 0) { p.r[p.n++] = 5; rem /= 5; }
+  while (rem % 3 == 0) { p.r[p.n++] = 3; rem /= 3; }
+  if (rem != 1) p.n = 0;  // not 7-smooth: rejected at compile time below
+  return p;
+}
+
+constexpr int max_radix(int L) {
+  RadixPlan p = radix_plan(L);
+  int m = 1;
+  for (int i = 0; i < p.n; ++i) m = p.r[i] > m ? p.r[i] : m;
+  return m;
+}
+
+// threads cooperating on one transform of length L
+constexpr int threads_per_transform(int L) { return L / max_radix(L); }
+
+// ---------------------------------------------------------------- small DFTs
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2& a0, float2& a1) {
+  const float2 t = a0;
+  a0 = c_add(t, a1);
+  a1 = c_sub(t, a1);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 t0 = c_add(a0, a2), t1 = c_sub(a0, a2);
+  const float2 t2 = c_add(a1, a3), t3 = c_mul_mi<INV>(c_sub(a1, a3));
+  a0 = c_add(t0, t2);
+  a2 = c_sub(t0, t2);
+  a1 = c_add(t1, t3);
+  a3 = c_sub(t1, t3);
+}
+
+// cos and sin of 2 pi m / 16
+__device__ constexpr float kCos16[16] = {
+    1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508978f,
+    0.0f, -0.38268343236508978f, -0.70710678118654752f, -0.92387953251128674f,
+    -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508978f,
+    0.0f, 0.38268343236508978f, 0.70710678118654752f, 0.92387953251128674f};
+__device__ constexpr float kSin16[16] = {
+    0.0f, 0.38268343236508978f, 0.70710678118654752f, 0.92387953251128674f,
+    1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508978f,
+    0.0f, -0.38268343236508978f, -0.70710678118654752f, -0.92387953251128674f,
+    -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508978f};
+
+template <int R, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<2, INV> {
+  __device__ static __forceinline__ void run(float2* v) { dft2<INV>(v[0], v[1]); }
+};
+
+template <bool INV>
+struct Dft<4, INV> {
+  __device__ static __forceinline__ void run(float2* v) { dft4<INV>(v[0], v[1], v[2], v[3]); }
+};
+
+// 8 = 2 x 4: even and odd 4-point DFTs, then one twiddled radix-2 stage
+template <bool INV>
+struct Dft<8, INV> {
+  __device__ static __forceinline__ void run(float2* v) {
+    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<INV>(e0, e1, e2, e3);
+    dft4<INV>(o0, o1, o2, o3);
+    o1 = c_rot<INV>(o1, kCos16[2], kSin16[2]);
+    o2 = c_mul_mi<INV>(o2);
+    o3 = c_rot<INV>(o3, kCos16[6], kSin16[6]);
+    v[0] = c_add(e0, o0); v[4] = c_sub(e0, o0);
+    v[1] = c_add(e1, o1); v[5] = c_sub(e1, o1);
+    v[2] = c_add(e2, o2); v[6] = c_sub(e2, o2);
+    v[3] = c_add(e3, o3); v[7] = c_sub(e3, o3);
+  }
+};
+
+// 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
+template <bool INV>
+struct Dft<16, INV> {
+  __device__ static __forceinline__ void run(float2* v) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+    // v[n2 + 4 k1] now holds Y[n2][k1]; twiddle by w16^(n2 k1)
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+      for (int k1 = 1; k1 < 4; ++k1) {
+        const int m = (n2 * k1) & 15;
+        v[n2 + 4 * k1] = c_rot<INV>(v[n2 + 4 * k1], kCos16[m], kSin16[m]);
+      }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4<INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // v[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4x4 index
+    float2 t[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t[i] = v[i];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[4 * k1 + k2];
+  }
+};
+
+// odd prime radices by the symmetric form: t_n = a_n + a_{R-n}, d_n = a_n - a_{R-n},
+// X_k = a0 + sum_n C(nk) t_n -+ i sum_n S(nk) d_n,  X_{R-k} with the opposite sign
+template <int R>
+struct OddTrig;
+template <>
+struct OddTrig<3> {
+  __device__ static constexpr float c(int m) { return m == 0 ? 1.0f : -0.5f; }
+  __device__ static constexpr float s(int m) {
+    return m == 0 ? 0.0f : (m == 1 ? 0.86602540378443865f : -0.86602540378443865f);
+  }
+};
+template <>
+struct OddTrig<5> {
+  __device__ static constexpr float c(int m) {
+    return m == 0 ? 1.0f : (m == 1 || m == 4) ? 0.30901699437494742f : -0.80901699437494742f;
+  }
+  __device__ static constexpr float s(int m) {
+    return m == 0 ? 0.0f
+           : m == 1 ? 0.95105651629515357f
+           : m == 2 ? 0.58778525229247313f
+           : m == 3 ? -0.58778525229247313f
+                    : -0.95105651629515357f;
+  }
+};
+template <>
+struct OddTrig<7> {
+  __device__ static constexpr float c(int m) {
+    return m == 0 ? 1.0f
+           : (m == 1 || m == 6) ? 0.62348980185873353f
+           : (m == 2 || m == 5) ? -0.22252093395631440f
+                                : -0.90096886790241913f;
+  }
+  __device__ static constexpr float s(int m) {
+    return m == 0 ? 0.0f
+           : m == 1 ? 0.78183148246802981f
+           : m == 2 ? 0.97492791218182361f
+           : m == 3 ? 0.43388373911755812f
+           : m == 4 ? -0.43388373911755812f
+           : m == 5 ? -0.97492791218182361f
+                    : -0.78183148246802981f;
+  }
+};
+
+template <int R, bool INV>
+struct DftOdd {
+  __device__ static __forceinline__ void run(float2* v) {
+    constexpr int H = (R - 1) / 2;
+    float2 t[H + 1], d[H + 1];
+#pragma unroll
+    for (int n = 1; n <= H; ++n) {
+      t[n] = c_add(v[n], v[R - n]);
+      d[n] = c_sub(v[n], v[R - n]);
+    }
+    const float2 a0 = v[0];
+    float2 x0 = a0;
+#pragma unroll
+    for (int n = 1; n <= H; ++n) x0 = c_add(x0, t[n]);
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+      float2 re = a0, im = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int n = 1; n <= H; ++n) {
+        const int m = (n * k) % R;
+        re.x += OddTrig<R>::c(m) * t[n].x;
+        re.y += OddTrig<R>::c(m) * t[n].y;
+        im.x += OddTrig<R>::s(m) * d[n].x;
+        im.y += OddTrig<R>::s(m) * d[n].y;
+      }
+      // forward: X_k = re - i im, X_{R-k} = re + i im ; inverse: signs swapped
+      const float2 mi = INV ? make_float2(-im.y, im.x) : make_float2(im.y, -im.x);
+      v[k] = c_add(re, mi);
+      v[R - k] = c_sub(re, mi);
+    }
+    v[0] = x0;
+  }
+};
+template <bool INV>
+struct Dft<3, INV> : DftOdd<3, INV> {};
+template <bool INV>
+struct Dft<5, INV> : DftOdd<5, INV> {};
+template <bool INV>
+struct Dft<7, INV> : DftOdd<7, INV> {};
+
+// ---------------------------------------------------------------- LDS layouts
+
+// Several transforms interleaved (transform index fastest); a pad float2 every
+// 16 elements keeps radix-16 strides off a single bank.
+template <int LINES>
+struct LayInter {
+  __device__ static __forceinline__ int addr(int line, int idx) { return (idx + (idx >> 4)) * LINES + line; }
+  static constexpr int size(int L) { return (L + L / 16 + 1) * LINES; }
+};
+
+// One transform after another.
+template <int LINES, int L>
+struct LayRow {
+  static constexpr int kStride = L + L / 16 + 1;
+  __device__ static __forceinline__ int addr(int line, int idx) { return line * kStride + idx + (idx >> 4); }
+  static constexpr int size(int) { return kStride * LINES; }
+};
+
+// ---------------------------------------------------------------- Stockham driver
+
+// FL: float2 (int idx) -- input element idx of this thread's transform (first pass)
+// LS: void (int idx, float2 v) -- output element idx (last pass)
+// Every thread of the block must call run(); t in [0, P) identifies the thread
+// within its transform, line selects the transform's LDS region.
+template <int L, int P, bool INV, class Lay>
+struct Fft {
+  static constexpr RadixPlan kPlan = radix_plan(L);
+  static_assert(kPlan.n > 0, "transform length must be 7-smooth");
+
+  template <int I, int NS, class FL, class LS>
+  __device__ static __forceinline__ void pass(int line, int t, float2* lds, const float2* __restrict__ tw,
+                                              FL& fl, LS& ls) {
+    constexpr int R = kPlan.r[I];
+    constexpr int NB = L / R;
+    constexpr int BPT = (NB + P - 1) / P;
+    constexpr bool FIRST = (I == 0);
+    constexpr bool LAST = (I == kPlan.n - 1);
+    float2 v[BPT][R];
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      const int j = t + b * P;
+      if ((NB % P == 0) || j < NB) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int idx = j + r * NB;
+          if constexpr (FIRST) v[b][r] = fl(idx);
+          else v[b][r] = lds[Lay::addr(line, idx)];
+        }
+        if constexpr (NS > 1) {
+          const int k = j % NS;
+          constexpr int STRIDE = L / (NS * R);
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            float2 w = tw[r * k * STRIDE];
+            if (INV) w.y = -w.y;
+            v[b][r] = c_mul(v[b][r], w);
+          }
+        }
+        Dft<R, INV>::run(v[b]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      const int j = t + b * P;
+      if ((NB % P == 0) || j < NB) {
+        const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int idx = base + q * NS;
+          if constexpr (LAST) ls(idx, v[b][q]);
+          else lds[Lay::addr(line, idx)] = v[b][q];
+        }
+      }
+    }
+    if constexpr (!LAST) {
+      __syncthreads();
+      pass<I + 1, NS * R>(line, t, lds, tw, fl, ls);
+    }
+  }
+
+  template <class FL, class LS>
+  __device__ static __forceinline__ void run(int line, int t, float2* lds, const float2* __restrict__ tw, FL& fl,
+                                             LS& ls) {
+    pass<0, 1>(line, t, lds, tw, fl, ls);
+  }
+};
+
+// floor(a / b) and ceil(a / b) for b > 0 and any sign of a
+__device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+__device__ __forceinline__ int ceil_div(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
+
+}  // namespace funnel

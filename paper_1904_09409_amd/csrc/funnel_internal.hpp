@@ -1,0 +1,34 @@
+// funnel_internal.hpp -- launchers shared between the kernel and API units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <type_traits>
+
+#include "../../include/funnel.h"
+
+namespace funnel {
+
+bool length_supported(int L);
+
+// real lines (zero-padded to L) -> half spectrum rows 1..L/2-1, times scale*(-1)^k
+hipError_t launch_r2c(int L, bool trans, const float* in, float2* out, int nlines, int lin, int off,
+                      long long in_img, long long out_img, float scale, const float2* tw, int batch,
+                      hipStream_t s);
+
+// half spectrum rows 1..L/2-1 -> real lines, rows [r0, r0+nout) stored (or added)
+hipError_t launch_c2r(int L, bool trans, bool accum, const float2* in, float* out, int nlines, int r0, int nout,
+                      long long in_img, long long out_img, float scale, const float2* tw, int batch,
+                      hipStream_t s);
+
+// per frequency row: NVMT gather + DFT along x' (forward) or its transpose (adjoint), in place
+hipError_t launch_row(int M, bool adj, float2* data, int Lp, int h, long long img_stride, const float2* tw,
+                      int batch, hipStream_t s);
+
+size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K);
+int peaks_tiles(int rows, int cols);
+hipError_t launch_peaks(const float* planes, long long plane_stride, int batch, int nspaces, const int* rows,
+                        const int* cols, const int* himg, const long long* offset, int K, float thr, int radius,
+                        int wrap, int keep_border, ft_peak* peaks, int32_t* n_found, void* ws, hipStream_t s);
+
+}  // namespace funnel

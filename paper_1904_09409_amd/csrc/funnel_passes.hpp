@@ -1,0 +1,313 @@
+// funnel_passes.hpp -- the three passes of the funnel transform and of its
+// adjoint, for gfx950.
+//
+// Pass A  (Sec. 3.1 step 1, Sec. 4.2): DFT along y of every column of the
+//         expanded image; only rows n2 = 1 .. Np/2-1 of the half spectrum are
+//         kept (the rest follow by conjugate symmetry).  Two real columns ride
+//         in one complex transform (z = a + i b) and are separated afterwards.
+// Pass B  (steps 2 and 3, Eq. 17): per frequency row, the NVMT as a linear-
+//         interpolation gather from the LDS copy of the row, fused into the
+//         first butterfly pass of the DFT along x'.
+// Pass C  (step 4): Hermitian inverse DFT along omega_2 of every column,
+//         again two columns per complex transform, scaled by 1/Np.
+// The inverse space (dual form, Sec. 3.1) is pass A reading image rows
+// instead of columns; passes B and C are unchanged.  The adjoint runs the
+// transposed passes in reverse order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "fft_core.hpp"
+#include "funnel_internal.hpp"
+
+namespace funnel {
+
+// ------------------------------------------------------------------ tiling
+
+constexpr int pow2_floor(int x) {
+  int p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
+}
+
+template <int L>
+struct ColCfg {
+  static constexpr int P = threads_per_transform(L);
+  // column pairs per block: a power of two that fits 1024 threads and ~150 KB of LDS
+  static constexpr int lines_by_threads = 1024 / P > 0 ? 1024 / P : 1;
+  static constexpr int lines_by_lds = (150 * 1024) / (8 * (L + L / 16 + 1));
+  static constexpr int LINES0 = lines_by_threads < lines_by_lds ? lines_by_threads : lines_by_lds;
+  static constexpr int LINES = pow2_floor(LINES0 > 16 ? 16 : (LINES0 < 1 ? 1 : LINES0));
+  static constexpr int THREADS = LINES * P;
+};
+
+template <int M>
+struct RowCfg {
+  static constexpr int P = threads_per_transform(M);
+  static constexpr int rows_by_threads = 256 / P > 0 ? 256 / P : 1;
+  static constexpr int rows_by_lds = (64 * 1024) / (8 * (M + M / 16 + 1));
+  static constexpr int ROWS0 = rows_by_threads < rows_by_lds ? rows_by_threads : rows_by_lds;
+  static constexpr int ROWS = ROWS0 < 1 ? 1 : ROWS0;
+  static constexpr int THREADS = ROWS * P;
+};
+
+// ------------------------------------------------------------------ pass A / adjoint of C
+//
+// Real lines of length `lin` placed at offset `off` in a zero frame of length
+// L -> half spectrum X[k], k = 1 .. L/2-1, times scale * (-1)^k (the (-1)^k
+// moves the origin to the frame centre).  TRANS = false: lines are the
+// columns of a row-major [lin][nlines] array; TRANS = true: lines are the rows
+// of a row-major [nlines][lin] array.  Output: complex [L/2-1][nlines].
+template <int L, bool TRANS>
+__global__ void __launch_bounds__(ColCfg<L>::THREADS)
+    k_r2c_half(const float* __restrict__ in, float2* __restrict__ out, int nlines, int lin, int off,
+               long long in_img, long long out_img, float scale, const float2* __restrict__ tw) {
+  using Cfg = ColCfg<L>;
+  constexpr int P = Cfg::P, LINES = Cfg::LINES, H = L / 2 - 1;
+  using Lay = typename std::conditional<TRANS, LayRow<LINES, L>, LayInter<LINES>>::type;
+  __shared__ float2 lds[Lay::size(L)];
+
+  const int tid = threadIdx.x;
+  const int pair = TRANS ? tid / P : tid % LINES;
+  const int t = TRANS ? tid % P : tid / LINES;
+  const int npairs = nlines >> 1;
+  const int pg = blockIdx.x * LINES + pair;
+  const bool active = pg < npairs;
+  const float* src = in + (long long)blockIdx.y * in_img;
+
+  auto fl = [&](int idx) -> float2 {
+    const int r = idx - off;
+    float2 z = make_float2(0.f, 0.f);
+    if (active && r >= 0 && r < lin) {
+      if constexpr (TRANS) {
+        z.x = src[(long long)(2 * pg) * lin + r];
+        z.y = src[(long long)(2 * pg + 1) * lin + r];
+      } else {
+        z = *reinterpret_cast<const float2*>(src + (long long)r * nlines + 2 * pg);
+      }
+    }
+    return z;
+  };
+  auto ls = [&](int idx, float2 v) { lds[Lay::addr(pair, idx)] = v; };
+  Fft<L, P, false, Lay>::run(pair, t, lds, tw, fl, ls);
+  __syncthreads();
+
+  // separate the two real columns: A = (Z_k + conj Z_{L-k})/2, B = (Z_k - conj Z_{L-k})/(2i)
+  float4* dst = reinterpret_cast<float4*>(out + (long long)blockIdx.y * out_img);
+  const int halfw = nlines >> 1;  // float4 per output row
+  for (int e = tid; e < H * LINES; e += Cfg::THREADS) {
+    const int p = e % LINES, k = 1 + e / LINES;
+    const int pgl = blockIdx.x * LINES + p;
+    if (pgl >= npairs) continue;
+    const float2 zk = lds[Lay::addr(p, k)], zm = lds[Lay::addr(p, L - k)];
+    const float sc = (k & 1) ? -0.5f * scale : 0.5f * scale;
+    const float ux = zk.x - zm.x, uy = zk.y + zm.y;
+    float4 o;
+    o.x = sc * (zk.x + zm.x);
+    o.y = sc * (zk.y - zm.y);
+    o.z = sc * uy;
+    o.w = -sc * ux;
+    dst[(long long)(k - 1) * halfw + pgl] = o;
+  }
+}
+
+// ------------------------------------------------------------------ pass C / adjoint of A
+//
+// Half spectrum X[k], k = 1 .. L/2-1 (complex [L/2-1][nlines]) -> real lines
+// x[r] = scale * sum_k X~[k] e^{+i 2 pi k r / L} over the Hermitian completion
+// X~[k] = (-1)^k X[k], X~[L-k] = conj X~[k], X~[0] = X~[L/2] = 0.  Only rows
+// r in [r0, r0 + nout) are stored.  TRANS = false: out is [nout][nlines];
+// TRANS = true: out is [nlines][nout].  ACCUM adds to out instead of storing.
+template <int L, bool TRANS, bool ACCUM>
+__global__ void __launch_bounds__(ColCfg<L>::THREADS)
+    k_c2r_half(const float2* __restrict__ in, float* __restrict__ out, int nlines, int r0, int nout,
+               long long in_img, long long out_img, float scale, const float2* __restrict__ tw) {
+  using Cfg = ColCfg<L>;
+  constexpr int P = Cfg::P, LINES = Cfg::LINES, H = L / 2 - 1;
+  using Lay = typename std::conditional<TRANS, LayRow<LINES, L>, LayInter<LINES>>::type;
+  static_assert((L / 2) * LINES * 2 <= Lay::size(L), "staging must fit the transform buffer");
+  __shared__ float2 lds[Lay::size(L)];
+  float4* stg = reinterpret_cast<float4*>(lds);
+
+  const int tid = threadIdx.x;
+  const int pair = TRANS ? tid / P : tid % LINES;
+  const int t = TRANS ? tid % P : tid / LINES;
+  const int npairs = nlines >> 1;
+  const int pg = blockIdx.x * LINES + pair;
+  const bool active = pg < npairs;
+
+  const float4* src = reinterpret_cast<const float4*>(in + (long long)blockIdx.y * in_img);
+  for (int e = tid; e < H * LINES; e += Cfg::THREADS) {
+    const int p = e % LINES, k = 1 + e / LINES;
+    const int pgl = blockIdx.x * LINES + p;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (pgl < npairs) v = src[(long long)(k - 1) * npairs + pgl];
+    if (k & 1) v = make_float4(-v.x, -v.y, -v.z, -v.w);
+    stg[k * LINES + p] = v;
+  }
+  __syncthreads();
+
+  auto fl = [&](int idx) -> float2 {
+    if (idx == 0 || idx == L / 2) return make_float2(0.f, 0.f);
+    if (idx < L / 2) {
+      const float4 v = stg[idx * LINES + pair];
+      return make_float2(v.x - v.w, v.y + v.z);  // A + iB
+    }
+    const float4 v = stg[(L - idx) * LINES + pair];
+    return make_float2(v.x + v.w, v.z - v.y);    // conj(A) + i conj(B)
+  };
+  float* dst = out + (long long)blockIdx.y * out_img;
+  auto ls = [&](int idx, float2 z) {
+    const int r = idx - r0;
+    if (!active || r < 0 || r >= nout) return;
+    const float a = scale * z.x, b = scale * z.y;
+    if constexpr (TRANS) {
+      float* pa = dst + (long long)(2 * pg) * nout + r;
+      float* pb = pa + nout;
+      if constexpr (ACCUM) { *pa += a; *pb += b; }
+      else { *pa = a; *pb = b; }
+    } else {
+      float2* p2 = reinterpret_cast<float2*>(dst + (long long)r * nlines + 2 * pg);
+      if constexpr (ACCUM) { float2 o = *p2; o.x += a; o.y += b; *p2 = o; }
+      else *p2 = make_float2(a, b);
+    }
+  };
+  Fft<L, P, true, Lay>::run(pair, t, lds, tw, fl, ls);
+}
+
+// ------------------------------------------------------------------ pass B and its adjoint
+//
+// data: complex [h][M], row n2-1 holds frequency row n2 (in-place).
+// Forward: g[x'] = (1-t) f[i0] + t f[i0+1] with i0 = floor((x' Lp + M n2)/(2 n2)),
+//          then G[m1] = sum_x' g[x'] e^{-i 2 pi m1 x'/M} over centred x', m1.
+// Adjoint: dg[x'] = sum_m1 dG[m1] e^{+i 2 pi m1 x'/M}, then
+//          dS[i] = (1-t_a) dg[x_a] + t_b dg[x_b] where x_a is the sample whose
+//          i0 is i and x_b the one whose i0 is i-1 (at most one each, as the
+//          sampling ratio 2 n2 / Lp is below 1).
+template <int M, bool ADJ>
+__global__ void __launch_bounds__(RowCfg<M>::THREADS)
+    k_row_nvmt(float2* __restrict__ data, int Lp, int h, long long img_stride, const float2* __restrict__ tw) {
+  using Cfg = RowCfg<M>;
+  constexpr int P = Cfg::P, ROWS = Cfg::ROWS;
+  using Lay = LayRow<ROWS, M>;
+  __shared__ float2 lds[Lay::size(M)];
+
+  const int tid = threadIdx.x;
+  const int row = tid / P, t = tid % P;
+  const int n2 = blockIdx.x * ROWS + row + 1;
+  const bool active = n2 <= h;
+  float2* base = data + (long long)blockIdx.y * img_stride;
+
+  for (int e = tid; e < ROWS * M; e += Cfg::THREADS) {
+    const int rr = e / M, i = e % M;
+    const int n2r = blockIdx.x * ROWS + rr + 1;
+    float2 v = make_float2(0.f, 0.f);
+    if (n2r <= h) v = base[(long long)(n2r - 1) * M + i];
+    if (ADJ && (i & 1)) v = make_float2(-v.x, -v.y);
+    lds[Lay::addr(rr, i)] = v;
+  }
+  __syncthreads();
+
+  const int den = 2 * n2;
+  const int mn2 = M * n2;
+  if constexpr (!ADJ) {
+    auto fl = [&](int q) -> float2 {
+      const int num = (q - M / 2) * Lp + mn2;
+      const int i0 = floor_div(num, den);
+      const float tt = (float)(num - i0 * den) / (float)den;
+      float2 f0 = make_float2(0.f, 0.f), f1 = make_float2(0.f, 0.f);
+      if (i0 >= 0 && i0 < M) f0 = lds[Lay::addr(row, i0)];
+      if (i0 + 1 >= 0 && i0 + 1 < M) f1 = lds[Lay::addr(row, i0 + 1)];
+      const float s = (q & 1) ? -1.f : 1.f;
+      return make_float2(s * ((1.f - tt) * f0.x + tt * f1.x), s * ((1.f - tt) * f0.y + tt * f1.y));
+    };
+    auto ls = [&](int p, float2 v) {
+      if (!active) return;
+      if ((p + M / 2) & 1) v = make_float2(-v.x, -v.y);
+      base[(long long)(n2 - 1) * M + p] = v;
+    };
+    Fft<M, P, false, Lay>::run(row, t, lds, tw, fl, ls);
+  } else {
+    auto fl = [&](int p) -> float2 { return lds[Lay::addr(row, p)]; };
+    auto ls = [&](int q, float2 v) {
+      if ((q + M / 2) & 1) v = make_float2(-v.x, -v.y);
+      lds[Lay::addr(row, q)] = v;
+    };
+    Fft<M, P, true, Lay>::run(row, t, lds, tw, fl, ls);
+    __syncthreads();
+    if (!active) return;
+    for (int i = t; i < M; i += P) {
+      float2 acc = make_float2(0.f, 0.f);
+      // sample with i0 == i
+      const int xa = ceil_div(i * den - mn2, Lp);
+      const int na = xa * Lp + mn2;
+      if (xa >= -M / 2 && xa < M / 2 && na < (i + 1) * den) {
+        const float w = 1.f - (float)(na - i * den) / (float)den;
+        const float2 g = lds[Lay::addr(row, xa + M / 2)];
+        acc.x += w * g.x;
+        acc.y += w * g.y;
+      }
+      // sample with i0 == i-1
+      const int xb = ceil_div((i - 1) * den - mn2, Lp);
+      const int nb = xb * Lp + mn2;
+      if (xb >= -M / 2 && xb < M / 2 && nb < i * den) {
+        const float w = (float)(nb - (i - 1) * den) / (float)den;
+        const float2 g = lds[Lay::addr(row, xb + M / 2)];
+        acc.x += w * g.x;
+        acc.y += w * g.y;
+      }
+      base[(long long)(n2 - 1) * M + i] = acc;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <int L>
+hipError_t launch_r2c_t(bool trans, const float* in, float2* out, int nlines, int lin, int off,
+                               long long in_img, long long out_img, float scale, const float2* tw, int batch,
+                               hipStream_t s) {
+  using Cfg = ColCfg<L>;
+  dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
+  if (trans)
+    k_r2c_half<L, true><<<grid, block, 0, s>>>(in, out, nlines, lin, off, in_img, out_img, scale, tw);
+  else
+    k_r2c_half<L, false><<<grid, block, 0, s>>>(in, out, nlines, lin, off, in_img, out_img, scale, tw);
+  return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_c2r_t(bool trans, bool accum, const float2* in, float* out, int nlines, int r0, int nout,
+                               long long in_img, long long out_img, float scale, const float2* tw, int batch,
+                               hipStream_t s) {
+  using Cfg = ColCfg<L>;
+  dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
+  if (trans) {
+    if (accum)
+      k_c2r_half<L, true, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img, scale, tw);
+    else
+      k_c2r_half<L, true, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img, scale, tw);
+  } else {
+    if (accum)
+      k_c2r_half<L, false, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img, scale, tw);
+    else
+      k_c2r_half<L, false, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img, scale, tw);
+  }
+  return hipGetLastError();
+}
+
+template <int M>
+hipError_t launch_row_t(bool adj, float2* data, int Lp, int h, long long img_stride, const float2* tw,
+                               int batch, hipStream_t s) {
+  using Cfg = RowCfg<M>;
+  dim3 grid((h + Cfg::ROWS - 1) / Cfg::ROWS, batch), block(Cfg::THREADS);
+  if (adj)
+    k_row_nvmt<M, true><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
+  else
+    k_row_nvmt<M, false><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
+  return hipGetLastError();
+}
+
+}  // namespace funnel

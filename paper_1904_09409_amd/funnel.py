@@ -1,0 +1,325 @@
+"""Python binding of libfunnel (the C ABI in include/funnel.h).
+
+Argument marshalling only: every step of the transform runs in the library's
+HIP kernels.  PyTorch supplies device memory and the current HIP stream.  The
+library must have been built (``python -m paper_1904_09409_amd.build``); there
+is no fallback path, and a missing library raises at load time.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libfunnel.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "funnel.h")
+
+FT_OK = 0
+FT_ERR_INVALID_ARG = 1
+FT_ERR_UNSUPPORTED_SIZE = 2
+FT_ERR_MISALIGNED = 3
+FT_ERR_WORKSPACE_TOO_SMALL = 4
+FT_ERR_NO_DEVICE = 5
+FT_ERR_HIP = 6
+FT_ERR_OUT_OF_MEMORY = 7
+
+FT_SPACE_REGULAR = 1
+FT_SPACE_INVERSE = 2
+FT_SPACE_BOTH = 3
+FT_PREC_FP32 = 0
+FT_PEAK_CLAMP_BORDER = 1
+FT_PEAK_KEEP_PAD_BOUNDARY = 2
+
+
+class ft_plan_desc(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
+                ("padded_len", ctypes.c_int32), ("spaces", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class ft_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_float),
+                ("bytes_per_launch", ctypes.c_double)]
+
+
+PEAK_DTYPE = np.dtype([("image", np.int32), ("space", np.int32), ("row", np.int32), ("col", np.int32),
+                       ("value", np.float32), ("slope", np.float32), ("intercept", np.float32)])
+PEAK_WORDS = PEAK_DTYPE.itemsize // 4   # 7 x 4 bytes
+
+
+class FunnelError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)}: {msg}")
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libfunnel.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1904_09409_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, sz, i32, u32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_uint32
+    sigs = {
+        "funnel_plan_create": ([ctypes.POINTER(ft_plan_desc), ctypes.POINTER(vp)], ctypes.c_int),
+        "funnel_plan_destroy": ([vp], None),
+        "funnel_workspace_size": ([vp, ctypes.POINTER(sz)], ctypes.c_int),
+        "funnel_plane_elems": ([vp, ctypes.POINTER(sz)], ctypes.c_int),
+        "funnel_padded_len": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
+        "funnel_forward": ([vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "funnel_adjoint": ([vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "funnel_peaks_workspace_size": ([vp, i32, ctypes.POINTER(sz)], ctypes.c_int),
+        "funnel_peaks": ([vp, vp, i32, ctypes.c_float, i32, u32, vp, vp, vp, sz, vp], ctypes.c_int),
+        "funnel_profile_enable": ([vp, i32], ctypes.c_int),
+        "funnel_profile_read": ([vp, ctypes.POINTER(ft_kernel_time), i32, ctypes.POINTER(i32)], ctypes.c_int),
+        "funnel_profile_disable": ([vp], ctypes.c_int),
+        "funnel_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "funnel_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def header_functions(path: str = HEADER_PATH) -> list[str]:
+    """Names of the functions the public header declares."""
+    text = open(path).read()
+    return sorted(set(re.findall(r"\b(funnel_[a-z_]+)\s*\(", text)))
+
+
+def status_string(status: int) -> str:
+    return load_library().funnel_status_string(int(status)).decode()
+
+
+def last_error() -> str:
+    return load_library().funnel_last_error().decode()
+
+
+def _check(status: int, where: str):
+    if status != FT_OK:
+        raise FunnelError(status, where, last_error())
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ raw ABI (same names)
+
+def funnel_plan_create(batch: int, rows: int, cols: int, padded_len: int = 0,
+                       spaces: int = FT_SPACE_BOTH, precision: int = FT_PREC_FP32, flags: int = 0) -> int:
+    lib = load_library()
+    d = ft_plan_desc(batch, rows, cols, padded_len, spaces, precision, flags)
+    h = ctypes.c_void_p()
+    _check(lib.funnel_plan_create(ctypes.byref(d), ctypes.byref(h)), "funnel_plan_create")
+    return h.value
+
+
+def funnel_plan_destroy(plan: int) -> None:
+    load_library().funnel_plan_destroy(plan)
+
+
+def funnel_workspace_size(plan: int) -> int:
+    v = ctypes.c_size_t()
+    _check(load_library().funnel_workspace_size(plan, ctypes.byref(v)), "funnel_workspace_size")
+    return v.value
+
+
+def funnel_plane_elems(plan: int) -> int:
+    v = ctypes.c_size_t()
+    _check(load_library().funnel_plane_elems(plan, ctypes.byref(v)), "funnel_plane_elems")
+    return v.value
+
+
+def funnel_padded_len(plan: int) -> int:
+    v = ctypes.c_int32()
+    _check(load_library().funnel_padded_len(plan, ctypes.byref(v)), "funnel_padded_len")
+    return v.value
+
+
+def funnel_forward(plan: int, images, planes, ws, stream=None) -> None:
+    _check(load_library().funnel_forward(plan, _ptr(images), _ptr(planes), _ptr(ws),
+                                         ws.numel() * ws.element_size(), _stream(stream)), "funnel_forward")
+
+
+def funnel_adjoint(plan: int, d_planes, d_images, ws, stream=None) -> None:
+    _check(load_library().funnel_adjoint(plan, _ptr(d_planes), _ptr(d_images), _ptr(ws),
+                                         ws.numel() * ws.element_size(), _stream(stream)), "funnel_adjoint")
+
+
+def funnel_peaks_workspace_size(plan: int, K: int) -> int:
+    v = ctypes.c_size_t()
+    _check(load_library().funnel_peaks_workspace_size(plan, K, ctypes.byref(v)), "funnel_peaks_workspace_size")
+    return v.value
+
+
+def funnel_peaks(plan: int, planes, K: int, threshold: float, radius: int, flags: int,
+                 peaks, n_found, ws, stream=None) -> None:
+    _check(load_library().funnel_peaks(plan, _ptr(planes), int(K), float(threshold), int(radius), int(flags),
+                                       _ptr(peaks), _ptr(n_found), _ptr(ws), ws.numel() * ws.element_size(),
+                                       _stream(stream)), "funnel_peaks")
+
+
+def funnel_profile_enable(plan: int, max_records: int) -> None:
+    _check(load_library().funnel_profile_enable(plan, int(max_records)), "funnel_profile_enable")
+
+
+def funnel_profile_read(plan: int, cap: int = 64) -> list[dict]:
+    """Per-kernel event times recorded since profiling was enabled (or last read)."""
+    arr = (ft_kernel_time * cap)()
+    n = ctypes.c_int32()
+    _check(load_library().funnel_profile_read(plan, arr, cap, ctypes.byref(n)), "funnel_profile_read")
+    return [dict(name=arr[i].name.decode(), launches=arr[i].launches, total_ms=arr[i].total_ms,
+                 bytes_per_launch=arr[i].bytes_per_launch) for i in range(n.value)]
+
+
+def funnel_profile_disable(plan: int) -> None:
+    _check(load_library().funnel_profile_disable(plan), "funnel_profile_disable")
+
+
+# ------------------------------------------------------------------ convenience layer
+
+@dataclass
+class PlaneViews:
+    regular: object = None   # torch view [B, Np, M]
+    inverse: object = None   # torch view [B, Np, N]
+
+
+class FunnelPlan:
+    """A plan plus its workspace for a fixed batch shape on the current device."""
+
+    def __init__(self, batch: int, rows: int, cols: int, padded_len: int = 0,
+                 spaces: int = FT_SPACE_BOTH):
+        import torch
+        self.batch, self.N, self.M, self.spaces = batch, rows, cols, spaces
+        self.handle = funnel_plan_create(batch, rows, cols, padded_len, spaces)
+        self.Np = funnel_padded_len(self.handle)
+        self.plane_elems = funnel_plane_elems(self.handle)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        ws = funnel_workspace_size(self.handle)
+        self.ws = torch.empty(max(ws, 256), dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                funnel_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    @property
+    def nspaces(self) -> int:
+        return 2 if self.spaces == FT_SPACE_BOTH else 1
+
+    def new_planes(self):
+        import torch
+        return torch.empty((self.batch, self.plane_elems), dtype=torch.float32, device=self.device)
+
+    def views(self, planes) -> PlaneViews:
+        v = PlaneViews()
+        off = 0
+        if self.spaces & FT_SPACE_REGULAR:
+            n = self.Np * self.M
+            v.regular = planes[:, off:off + n].view(self.batch, self.Np, self.M)
+            off += n
+        if self.spaces & FT_SPACE_INVERSE:
+            n = self.Np * self.N
+            v.inverse = planes[:, off:off + n].view(self.batch, self.Np, self.N)
+        return v
+
+    def _check_images(self, images):
+        import torch
+        if images.dtype != torch.float32 or not images.is_contiguous() or images.device != self.device:
+            raise ValueError("images must be contiguous float32 on the plan's device")
+        if tuple(images.shape) != (self.batch, self.N, self.M):
+            raise ValueError(f"images must have shape {(self.batch, self.N, self.M)}")
+
+    def forward(self, images, planes=None, stream=None):
+        self._check_images(images)
+        if planes is None:
+            planes = self.new_planes()
+        funnel_forward(self.handle, images, planes, self.ws, stream)
+        return planes
+
+    def adjoint(self, d_planes, d_images=None, stream=None):
+        import torch
+        d_planes = d_planes.reshape(self.batch, self.plane_elems)
+        if not d_planes.is_contiguous():
+            d_planes = d_planes.contiguous()
+        if d_images is None:
+            d_images = torch.empty((self.batch, self.N, self.M), dtype=torch.float32, device=self.device)
+        funnel_adjoint(self.handle, d_planes, d_images, self.ws, stream)
+        return d_images
+
+    def peaks(self, planes, K: int = 16, threshold: float = 0.0, radius: int = 1, flags: int = 0,
+              stream=None):
+        """Returns (records int32 [B, nspaces, K, 7] on the device, counts int32 [B, nspaces])."""
+        import torch
+        ws = torch.empty(max(funnel_peaks_workspace_size(self.handle, K), 256), dtype=torch.uint8,
+                         device=self.device)
+        rec = torch.empty((self.batch, self.nspaces, K, PEAK_WORDS), dtype=torch.int32, device=self.device)
+        cnt = torch.empty((self.batch, self.nspaces), dtype=torch.int32, device=self.device)
+        funnel_peaks(self.handle, planes, K, threshold, radius, flags, rec, cnt, ws, stream)
+        return rec, cnt
+
+
+def peaks_to_numpy(rec, cnt) -> list:
+    """Device peak records -> list (per image) of lists (per space) of numpy records."""
+    r = rec.cpu().numpy()
+    c = cnt.cpu().numpy()
+    out = []
+    for b in range(r.shape[0]):
+        per = []
+        for s in range(r.shape[1]):
+            per.append(np.ascontiguousarray(r[b, s, :c[b, s]]).view(PEAK_DTYPE).reshape(-1))
+        out.append(per)
+    return out
+
+
+def _autograd():
+    import torch
+
+    class FunnelTransform(torch.autograd.Function):
+        """planes = F(images); the backward applies the hand-written adjoint.
+        The operator is linear, so nothing is saved for the backward."""
+
+        @staticmethod
+        def forward(ctx, images, plan: FunnelPlan):
+            ctx.plan = plan
+            return plan.forward(images.contiguous())
+
+        @staticmethod
+        def backward(ctx, grad_planes):
+            return ctx.plan.adjoint(grad_planes.contiguous()), None
+
+    return FunnelTransform
+
+
+_FT = None
+
+
+def funnel_transform(images, plan: FunnelPlan):
+    """Differentiable forward: ``planes = funnel_transform(images, plan)``."""
+    global _FT
+    if _FT is None:
+        _FT = _autograd()
+    return _FT.apply(images, plan)

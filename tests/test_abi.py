@@ -1,0 +1,73 @@
+"""The C-ABI library on the CPU: it loads, exports every function the public
+header declares, and rejects bad arguments before touching a device."""
+import ctypes
+
+import pytest
+
+from paper_1904_09409_amd import funnel as F
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return F.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = F.header_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    for code, name in [(0, "FT_OK"), (1, "FT_ERR_INVALID_ARG"), (2, "FT_ERR_UNSUPPORTED_SIZE"),
+                       (3, "FT_ERR_MISALIGNED"), (4, "FT_ERR_WORKSPACE_TOO_SMALL"),
+                       (5, "FT_ERR_NO_DEVICE"), (6, "FT_ERR_HIP"), (7, "FT_ERR_OUT_OF_MEMORY")]:
+        assert F.status_string(code) == name
+
+
+def _create(lib, **kw):
+    d = dict(batch=1, rows=64, cols=64, padded_len=0, spaces=3, precision=0, flags=0)
+    d.update(kw)
+    desc = F.ft_plan_desc(**d)
+    h = ctypes.c_void_p(12345)
+    st = lib.funnel_plan_create(ctypes.byref(desc), ctypes.byref(h))
+    return st, h.value
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(batch=0), F.FT_ERR_INVALID_ARG),
+    (dict(rows=63), F.FT_ERR_INVALID_ARG),
+    (dict(cols=2), F.FT_ERR_INVALID_ARG),
+    (dict(spaces=0), F.FT_ERR_INVALID_ARG),
+    (dict(spaces=4), F.FT_ERR_INVALID_ARG),
+    (dict(precision=7), F.FT_ERR_INVALID_ARG),
+    (dict(flags=1), F.FT_ERR_INVALID_ARG),
+    (dict(padded_len=100), F.FT_ERR_INVALID_ARG),      # < rows + cols
+    (dict(padded_len=131), F.FT_ERR_INVALID_ARG),      # odd
+    (dict(rows=62, cols=64), F.FT_ERR_UNSUPPORTED_SIZE),   # 126 = 2*3^2*7 has no kernel
+    (dict(rows=44, cols=20), F.FT_ERR_UNSUPPORTED_SIZE),   # 64 ok, row length 44 = 4*11 not 7-smooth
+])
+def test_plan_create_rejects(lib, kw, code):
+    st, h = _create(lib, **kw)
+    assert st == code, (st, F.last_error())
+    assert h is None          # *out cleared, nothing allocated
+    assert F.last_error()
+
+
+def test_null_arguments(lib):
+    assert lib.funnel_plan_create(None, None) == F.FT_ERR_INVALID_ARG
+    assert lib.funnel_forward(None, None, None, None, 0, None) == F.FT_ERR_INVALID_ARG
+    assert lib.funnel_adjoint(None, None, None, None, 0, None) == F.FT_ERR_INVALID_ARG
+    assert lib.funnel_peaks(None, None, 4, 0.0, 1, 0, None, None, None, 0, None) == F.FT_ERR_INVALID_ARG
+    n = ctypes.c_size_t()
+    assert lib.funnel_workspace_size(None, ctypes.byref(n)) == F.FT_ERR_INVALID_ARG
+    lib.funnel_plan_destroy(None)
+
+
+def test_valid_plan_without_device(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    st, h = _create(lib, batch=2, rows=128, cols=128)
+    assert st == F.FT_ERR_NO_DEVICE
