@@ -117,6 +117,8 @@ def main():
     step_bytes = sum(k["bytes_per_launch"] * k["launches"] for k in kernels) / args.steps
     step_kernel_ms = sum(k["total_ms"] for k in kernels) / args.steps
 
+    copy_gbps, copy_ms = copy_bandwidth(torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(imgs[: args.cpu_images], dP, plan, N, M)
@@ -151,12 +153,34 @@ def main():
             "step_frac": round(step_bytes / (ms_per_step * 1e6) / HBM_PEAK_GBPS, 4),
             "step_bytes": step_bytes,
             "kernel_ms_sum": round(step_kernel_ms, 4),
+            "copy_gbps": round(copy_gbps, 1),
+            "copy_ms": round(copy_ms, 4),
+            "frac_of_copy": round(dom["gbps"] / copy_gbps, 4),
         },
         "kernels": [{"name": k["name"], "avg_ms": round(k["avg_ms"], 4),
                      "bytes": k["bytes_per_launch"], "gbps": round(k["gbps"], 1)} for k in kernels],
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy of 1 GiB (read + write counted): the practical
+    HBM ceiling on this GPU, and a reference kernel of known traffic."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    return 2 * nbytes / ms / 1e6, ms
 
 
 def cpu_baseline(imgs, dP, plan, N, M):

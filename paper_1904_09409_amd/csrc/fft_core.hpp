@@ -333,3 +333,166 @@ __device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b :
 __device__ __forceinline__ int ceil_div(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
 
 }  // namespace funnel
+
+namespace funnel {
+
+// ---------------------------------------------------------------- register-resident engine
+//
+// FftR keeps the E = L/P elements of a thread in registers for the whole
+// transform; pass I sees them as BPT_I butterflies of radix R_I (E = BPT_I R_I
+// for every pass, so P must divide every L/R_I).  Between passes the data goes
+// through LDS once.  With SPLIT the real and the imaginary parts are exchanged
+// one after the other through a float buffer of half the size, which lets two
+// blocks share a compute unit.
+//
+// Butterfly maps: slot b of pass I is butterfly t + P b, except in a PAIRED
+// pass, where slot 2c is ja = t + P c (ja < NB/2) and slot 2c+1 its Hermitian
+// partner NB - ja (NB/2 for ja = 0).  In the first pass (NS = 1) partners read
+// inputs idx and L - idx; in the last pass (NS = NB) they write outputs idx and
+// L - idx.  Keeping both in one thread lets a real-input transform separate
+// its two columns, and a Hermitian inverse build its input, in registers.
+
+constexpr RadixPlan reversed(RadixPlan p) {
+  RadixPlan q = p;
+  for (int i = 0; i < p.n; ++i) q.r[i] = p.r[p.n - 1 - i];
+  return q;
+}
+
+// REV runs the radices smallest-first (the pairing needs an even number of
+// butterflies per thread in the paired pass).
+template <int L, int P, bool INV, bool REV = false>
+struct FftR {
+  static constexpr RadixPlan kPlan = REV ? reversed(radix_plan(L)) : radix_plan(L);
+  static constexpr int E = L / P;
+  static_assert(kPlan.n > 0, "transform length must be 7-smooth");
+
+  template <int I>
+  static constexpr int ns() {
+    int p = 1;
+    for (int i = 0; i < I; ++i) p *= kPlan.r[i];
+    return p;
+  }
+  template <int I>
+  static constexpr bool fits() {
+    return (L / kPlan.r[I]) % P == 0;
+  }
+
+  template <int I, bool PAIRED>
+  __device__ static __forceinline__ int bfly(int t, int b) {
+    constexpr int NB = L / kPlan.r[I];
+    if constexpr (!PAIRED) {
+      return t + P * b;
+    } else {
+      const int ja = t + P * (b >> 1);
+      if ((b & 1) == 0) return ja;
+      return ja == 0 ? NB / 2 : NB - ja;
+    }
+  }
+
+  // twiddle (base from the table, powers by balanced products) + R-point DFT
+  template <int I, bool PAIRED>
+  __device__ static __forceinline__ void compute(float2 (&v)[E], int t, const float2* __restrict__ tw) {
+    constexpr int R = kPlan.r[I], NS = ns<I>(), BPT = E / R;
+    static_assert(fits<I>(), "P must divide L/R for every pass");
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      float2* x = v + b * R;
+      if constexpr (NS > 1) {
+        const int j = bfly<I, PAIRED>(t, b);
+        const int k = j % NS;
+        float2 w[R];
+        w[1] = tw[k * (L / (NS * R))];
+        if (INV) w[1].y = -w[1].y;
+#pragma unroll
+        for (int r = 2; r < R; ++r) w[r] = c_mul(w[r / 2], w[r - r / 2]);
+#pragma unroll
+        for (int r = 1; r < R; ++r) x[r] = c_mul(x[r], w[r]);
+      }
+      Dft<R, INV>::run(x);
+    }
+  }
+
+  // LDS exchange: outputs of pass I -> inputs of pass I+1.  Lay::addr(line, idx)
+  // addresses a float (SPLIT) or float2 slot.
+  template <int I, bool PAIRED_OUT, bool PAIRED_IN, bool SPLIT, class Lay, class Buf>
+  __device__ static __forceinline__ void exchange(float2 (&v)[E], int line, int t, Buf* lds) {
+    constexpr int R = kPlan.r[I], NS = ns<I>(), BPT = E / R;
+    constexpr int R2 = kPlan.r[I + 1], NB2 = L / R2, BPT2 = E / R2;
+    if constexpr (!SPLIT) {
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < BPT; ++b) {
+        const int j = bfly<I, PAIRED_OUT>(t, b);
+        const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int q = 0; q < R; ++q) lds[Lay::addr(line, base + q * NS)] = v[b * R + q];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < BPT2; ++b) {
+        const int j = bfly<I + 1, PAIRED_IN>(t, b);
+#pragma unroll
+        for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[Lay::addr(line, j + r * NB2)];
+      }
+    } else {
+#pragma unroll
+      for (int part = 0; part < 2; ++part) {
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < BPT; ++b) {
+          const int j = bfly<I, PAIRED_OUT>(t, b);
+          const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+          for (int q = 0; q < R; ++q) lds[Lay::addr(line, base + q * NS)] = part ? v[b * R + q].y : v[b * R + q].x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < BPT2; ++b) {
+          const int j = bfly<I + 1, PAIRED_IN>(t, b);
+#pragma unroll
+          for (int r = 0; r < R2; ++r) {
+            const float f = lds[Lay::addr(line, j + r * NB2)];
+            if (part) v[b * R2 + r].y = f;
+            else v[b * R2 + r].x = f;
+          }
+        }
+      }
+    }
+  }
+
+  // All passes after the caller loaded pass 0's inputs into v (with the
+  // PAIRED_FIRST map).  On return v holds the last pass's outputs (with the
+  // PAIRED_LAST map): slot b, output q is element j + q * (L / R_last).
+  template <bool PAIRED_FIRST, bool PAIRED_LAST, bool SPLIT, class Lay, class Buf, int I = 0>
+  __device__ static __forceinline__ void run(float2 (&v)[E], int line, int t, Buf* lds,
+                                             const float2* __restrict__ tw) {
+    constexpr bool FIRST = I == 0, LAST = I == kPlan.n - 1;
+    constexpr bool PAIRED = (FIRST && PAIRED_FIRST) || (LAST && PAIRED_LAST);
+    compute<I, PAIRED>(v, t, tw);
+    if constexpr (!LAST) {
+      constexpr bool NEXT_PAIRED = (I + 1 == kPlan.n - 1) && PAIRED_LAST;
+      exchange<I, PAIRED, NEXT_PAIRED, SPLIT, Lay>(v, line, t, lds);
+      run<PAIRED_FIRST, PAIRED_LAST, SPLIT, Lay, Buf, I + 1>(v, line, t, lds, tw);
+    }
+  }
+};
+
+// Layouts for the register engine: element slots of LINES transforms,
+// transform index fastest, one pad slot every 16 elements.
+template <int LINES>
+struct LayInterR {
+  __device__ static __forceinline__ int addr(int line, int idx) { return (idx + (idx >> 4)) * LINES + line; }
+  static constexpr int size(int L) { return (L + L / 16 + 1) * LINES; }
+};
+
+// Map the linear block index so that consecutive logical tiles run on the same
+// XCD (blocks are dealt round-robin over the 8 XCDs): neighbouring column tiles
+// then share their cache lines in one L2.
+__device__ __forceinline__ int xcd_remap(int lin, int total) {
+  constexpr int X = 8;
+  const int xcd = lin % X, slot = lin / X;
+  const int q = total / X, r = total % X;
+  return xcd * q + (xcd < r ? xcd : r) + slot;
+}
+
+}  // namespace funnel

@@ -263,12 +263,320 @@ __global__ void __launch_bounds__(RowCfg<M>::THREADS)
   }
 }
 
+// ------------------------------------------------------------------ register-resident column passes
+//
+// Power-of-two lengths >= 128.  Each thread keeps 32 elements of one transform
+// in registers (P = L/32 threads per transform), LINES column pairs per block,
+// real and imaginary parts exchanged separately through a float LDS buffer.
+// The R2C kernel keeps each output k and its mirror L-k in one thread, so the
+// two real columns are separated in registers and written straight to HBM;
+// the C2R kernel builds its Hermitian input the same way from one read of
+// each stored coefficient.
+
+template <int L>
+struct FastCfg {
+  static constexpr bool ok = (L >= 128) && ((L & (L - 1)) == 0) && L <= 4096;
+  // 16 elements per thread, except where a radix-16-only schedule would leave
+  // one butterfly per thread in the paired pass
+  static constexpr int E = (L == 256 || L == 4096) ? 32 : 16;
+  static constexpr int P = L / E;
+  static constexpr int LINES0 = 512 / P;
+  static constexpr int LINES = LINES0 > 16 ? 16 : (LINES0 < 1 ? 1 : LINES0);
+  static constexpr int THREADS = LINES * P;
+};
+
+__device__ __forceinline__ float2 herm_direct(float4 x) { return make_float2(x.x - x.w, x.y + x.z); }  // A + iB
+__device__ __forceinline__ float2 herm_mirror(float4 x) { return make_float2(x.x + x.w, x.z - x.y); }  // conj A + i conj B
+
+template <int L, bool TRANS>
+__global__ void __launch_bounds__(FastCfg<L>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+    k_r2c_fast(const float* __restrict__ in, float2* __restrict__ out, int nlines, int lin, int off,
+               long long in_img, long long out_img, float scale, const float2* __restrict__ tw, int tiles) {
+  using Cfg = FastCfg<L>;
+  constexpr int P = Cfg::P, E = Cfg::E, LINES = Cfg::LINES, H = L / 2 - 1;
+  using Eng = FftR<L, P, false, false>;
+  constexpr RadixPlan PL = Eng::kPlan;
+  constexpr int R0 = PL.r[0], NB0 = L / R0;
+  constexpr int RL = PL.r[PL.n - 1], NBL = L / RL, BPTL = E / RL;
+  using Lay = LayInterR<LINES>;
+  __shared__ float lds[Lay::size(L)];
+
+  const int logical = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int tile = logical % tiles, img = logical / tiles;
+  const int tid = threadIdx.x, pair = tid % LINES, t = tid / LINES;
+  const int npairs = nlines >> 1;
+  const int pg = tile * LINES + pair;
+  const bool active = pg < npairs;
+  const float* src = in + (long long)img * in_img;
+
+  float2 v[E];
+#pragma unroll
+  for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int rr = t + P * b + r * NB0 - off;
+      float2 z = make_float2(0.f, 0.f);
+      if (active && rr >= 0 && rr < lin) {
+        if constexpr (TRANS) {
+          z.x = src[(long long)(2 * pg) * lin + rr];
+          z.y = src[(long long)(2 * pg + 1) * lin + rr];
+        } else {
+          z = *reinterpret_cast<const float2*>(src + (long long)rr * nlines + 2 * pg);
+        }
+      }
+      v[b * R0 + r] = z;
+    }
+  Eng::template run<false, true, true, Lay>(v, pair, t, lds, tw);
+  if (!active) return;
+
+  float4* dst = reinterpret_cast<float4*>(out + (long long)img * out_img);
+  auto emit = [&](int k, float2 zk, float2 zm) {
+    // A = (Z_k + conj Z_{L-k})/2, B = (Z_k - conj Z_{L-k})/(2i), times scale (-1)^k
+    const float sc = (k & 1) ? -0.5f * scale : 0.5f * scale;
+    const float ux = zk.x - zm.x, uy = zk.y + zm.y;
+    dst[(long long)(k - 1) * npairs + pg] = make_float4(sc * (zk.x + zm.x), sc * (zk.y - zm.y), sc * uy, -sc * ux);
+  };
+#pragma unroll
+  for (int c = 0; c < BPTL / 2; ++c) {
+    const int ja = t + P * c;
+    const bool zero = ja == 0;
+    const int jb = zero ? NBL / 2 : NBL - ja;
+    const float2* va = v + (2 * c) * RL;
+    const float2* vb = v + (2 * c + 1) * RL;
+#pragma unroll
+    for (int q = 0; q < RL; ++q) {
+      const int ka = ja + q * NBL;
+      if (ka >= 1 && ka <= H) emit(ka, va[q], zero ? va[(RL - q) % RL] : vb[RL - 1 - q]);
+      const int kb = jb + q * NBL;
+      if (kb >= 1 && kb <= H) emit(kb, vb[q], zero ? vb[RL - 1 - q] : va[RL - 1 - q]);
+    }
+  }
+}
+
+template <int L, bool TRANS, bool ACCUM>
+__global__ void __launch_bounds__(FastCfg<L>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+    k_c2r_fast(const float2* __restrict__ in, float* __restrict__ out, int nlines, int r0, int nout,
+               long long in_img, long long out_img, float scale, const float2* __restrict__ tw, int tiles) {
+  using Cfg = FastCfg<L>;
+  constexpr int P = Cfg::P, E = Cfg::E, LINES = Cfg::LINES;
+  using Eng = FftR<L, P, true, true>;
+  constexpr RadixPlan PL = Eng::kPlan;
+  constexpr int R0 = PL.r[0], NB0 = L / R0, BPT0 = E / R0;
+  constexpr int RL = PL.r[PL.n - 1], NBL = L / RL, BPTL = E / RL;
+  using Lay = LayInterR<LINES>;
+  __shared__ float lds[Lay::size(L)];
+
+  const int logical = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int tile = logical % tiles, img = logical / tiles;
+  const int tid = threadIdx.x, pair = tid % LINES, t = tid / LINES;
+  const int npairs = nlines >> 1;
+  const int pg = tile * LINES + pair;
+  const bool active = pg < npairs;
+  const float4* src = reinterpret_cast<const float4*>(in + (long long)img * in_img);
+
+  auto load = [&](int k) -> float4 {  // stored coefficient k (1 .. L/2-1) times (-1)^k; 0 for k = 0
+    float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (active && k >= 1) x = src[(long long)(k - 1) * npairs + pg];
+    if (k & 1) x = make_float4(-x.x, -x.y, -x.z, -x.w);
+    return x;
+  };
+  float2 v[E];
+#pragma unroll
+  for (int c = 0; c < BPT0 / 2; ++c) {
+    const int ja = t + P * c;
+    const bool zero = ja == 0;
+    const int jb = zero ? NB0 / 2 : NB0 - ja;
+    float4 xa[R0 / 2], xb[R0 / 2];
+#pragma unroll
+    for (int r = 0; r < R0 / 2; ++r) {
+      xa[r] = load(ja + r * NB0);
+      xb[r] = load(jb + r * NB0);
+    }
+    // Butterfly ja reads inputs ja + r NB0: for r < R0/2 the stored coefficient
+    // itself, above R0/2 the mirror L - idx = jb + (R0-1-r) NB0.  Butterfly jb
+    // likewise mirrors ja's coefficients.  For ja = 0 both butterflies are their
+    // own partners (inputs r NB0 and NB0/2 + r NB0), and r = 0, R0/2 of ja are
+    // the zero DC and Nyquist rows.
+    float2* va = v + (2 * c) * R0;
+    float2* vb = v + (2 * c + 1) * R0;
+#pragma unroll
+    for (int r = 0; r < R0 / 2; ++r) {
+      va[r] = herm_direct(xa[r]);
+      vb[r] = herm_direct(xb[r]);
+      va[R0 - 1 - r] = herm_mirror(xb[r]);
+      vb[R0 - 1 - r] = herm_mirror(zero ? xb[r] : xa[r]);
+    }
+    if (zero) {
+      va[0] = make_float2(0.f, 0.f);
+      va[R0 / 2] = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int r = 1; r < R0 / 2; ++r) va[R0 - r] = herm_mirror(xa[r]);
+    }
+  }
+  Eng::template run<true, false, true, Lay>(v, pair, t, lds, tw);
+  if (!active) return;
+
+  float* dst = out + (long long)img * out_img;
+#pragma unroll
+  for (int b = 0; b < BPTL; ++b) {
+    const int j = t + P * b;
+#pragma unroll
+    for (int q = 0; q < RL; ++q) {
+      const int r = j + q * NBL - r0;
+      if (r < 0 || r >= nout) continue;
+      const float a = scale * v[b * RL + q].x, bb = scale * v[b * RL + q].y;
+      if constexpr (TRANS) {
+        float* pa = dst + (long long)(2 * pg) * nout + r;
+        float* pb = pa + nout;
+        if constexpr (ACCUM) { *pa += a; *pb += bb; }
+        else { *pa = a; *pb = bb; }
+      } else {
+        float2* p2 = reinterpret_cast<float2*>(dst + (long long)r * nlines + 2 * pg);
+        if constexpr (ACCUM) { float2 o = *p2; o.x += a; o.y += bb; *p2 = o; }
+        else *p2 = make_float2(a, bb);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ register-resident row pass
+//
+// Power-of-two row lengths >= 64: 16 elements per thread, ROWS rows per block.
+// The whole row is staged in LDS with 16-byte loads issued before any use;
+// the NVMT gather feeds the first butterfly pass directly from that copy.
+
+template <int M>
+struct RowFastCfg {
+  static constexpr bool ok = (M >= 64) && ((M & (M - 1)) == 0) && M <= 4096;
+  static constexpr int E = 16;
+  static constexpr int P = M / E;
+  static constexpr int ROWS = 256 / P > 0 ? 256 / P : 1;
+  static constexpr int THREADS = ROWS * P;
+};
+
+template <int M, bool ADJ>
+__global__ void __launch_bounds__(RowFastCfg<M>::THREADS)
+    k_row_fast(float2* __restrict__ data, int Lp, int h, long long img_stride, const float2* __restrict__ tw) {
+  using Cfg = RowFastCfg<M>;
+  constexpr int P = Cfg::P, E = Cfg::E, ROWS = Cfg::ROWS;
+  using Eng = FftR<M, P, ADJ, false>;
+  constexpr RadixPlan PL = Eng::kPlan;
+  constexpr int R0 = PL.r[0], NB0 = M / R0, BPT0 = E / R0;
+  constexpr int RL = PL.r[PL.n - 1], NBL = M / RL, BPTL = E / RL;
+  using Lay = LayRow<ROWS, M>;
+  __shared__ float2 lds[Lay::size(M)];
+
+  const int tid = threadIdx.x;
+  const int row = tid / P, t = tid % P;
+  const int n2 = blockIdx.x * ROWS + row + 1;
+  const bool active = n2 <= h;
+  float2* rowp = data + (long long)blockIdx.y * img_stride + (long long)(n2 - 1) * M;
+
+  {  // stage this thread's share of its row: E/2 float4 loads, all in flight
+    float4 st[E / 2];
+    const float4* src4 = reinterpret_cast<const float4*>(rowp);
+#pragma unroll
+    for (int i = 0; i < E / 2; ++i) st[i] = active ? src4[t + P * i] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < E / 2; ++i) {
+      const int e0 = 2 * (t + P * i);
+      float4 x = st[i];
+      if (ADJ) { x.z = -x.z; x.w = -x.w; }   // (-1)^p on the odd element
+      lds[Lay::addr(row, e0)] = make_float2(x.x, x.y);
+      lds[Lay::addr(row, e0 + 1)] = make_float2(x.z, x.w);
+    }
+  }
+  __syncthreads();
+
+  const int den = 2 * n2;
+  const int mn2 = M * n2;
+  float2 v[E];
+  if constexpr (!ADJ) {
+#pragma unroll
+    for (int b = 0; b < BPT0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        const int q = t + P * b + r * NB0;
+        const int num = (q - M / 2) * Lp + mn2;
+        const int i0 = floor_div(num, den);
+        const float tt = (float)(num - i0 * den) / (float)den;
+        float2 f0 = make_float2(0.f, 0.f), f1 = make_float2(0.f, 0.f);
+        if (i0 >= 0 && i0 < M) f0 = lds[Lay::addr(row, i0)];
+        if (i0 + 1 >= 0 && i0 + 1 < M) f1 = lds[Lay::addr(row, i0 + 1)];
+        const float sg = (q & 1) ? -1.f : 1.f;
+        v[b * R0 + r] = make_float2(sg * ((1.f - tt) * f0.x + tt * f1.x), sg * ((1.f - tt) * f0.y + tt * f1.y));
+      }
+    Eng::template run<false, false, false, Lay>(v, row, t, lds, tw);
+    if (!active) return;
+#pragma unroll
+    for (int b = 0; b < BPTL; ++b)
+#pragma unroll
+      for (int q = 0; q < RL; ++q) {
+        const int p = t + P * b + q * NBL;
+        float2 g = v[b * RL + q];
+        if ((p + M / 2) & 1) g = make_float2(-g.x, -g.y);
+        rowp[p] = g;
+      }
+  } else {
+#pragma unroll
+    for (int b = 0; b < BPT0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[b * R0 + r] = lds[Lay::addr(row, t + P * b + r * NB0)];
+    Eng::template run<false, false, false, Lay>(v, row, t, lds, tw);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPTL; ++b)
+#pragma unroll
+      for (int q = 0; q < RL; ++q) {
+        const int x = t + P * b + q * NBL;
+        float2 g = v[b * RL + q];
+        if ((x + M / 2) & 1) g = make_float2(-g.x, -g.y);
+        lds[Lay::addr(row, x)] = g;
+      }
+    __syncthreads();
+    if (!active) return;
+    // transposed interpolation as a gather: at most two samples land on i
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = t + P * e;
+      float2 acc = make_float2(0.f, 0.f);
+      const int xa = ceil_div(i * den - mn2, Lp);
+      const int na = xa * Lp + mn2;
+      if (xa >= -M / 2 && xa < M / 2 && na < (i + 1) * den) {
+        const float w = 1.f - (float)(na - i * den) / (float)den;
+        const float2 g = lds[Lay::addr(row, xa + M / 2)];
+        acc.x += w * g.x;
+        acc.y += w * g.y;
+      }
+      const int xb = ceil_div((i - 1) * den - mn2, Lp);
+      const int nb = xb * Lp + mn2;
+      if (xb >= -M / 2 && xb < M / 2 && nb < i * den) {
+        const float w = (float)(nb - (i - 1) * den) / (float)den;
+        const float2 g = lds[Lay::addr(row, xb + M / 2)];
+        acc.x += w * g.x;
+        acc.y += w * g.y;
+      }
+      rowp[i] = acc;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <int L>
 hipError_t launch_r2c_t(bool trans, const float* in, float2* out, int nlines, int lin, int off,
                                long long in_img, long long out_img, float scale, const float2* tw, int batch,
                                hipStream_t s) {
+  if constexpr (FastCfg<L>::ok) {
+    using F = FastCfg<L>;
+    const int tiles = (nlines / 2 + F::LINES - 1) / F::LINES;
+    dim3 grid(tiles, batch), block(F::THREADS);
+    if (trans)
+      k_r2c_fast<L, true><<<grid, block, 0, s>>>(in, out, nlines, lin, off, in_img, out_img, scale, tw, tiles);
+    else
+      k_r2c_fast<L, false><<<grid, block, 0, s>>>(in, out, nlines, lin, off, in_img, out_img, scale, tw, tiles);
+    return hipGetLastError();
+  }
   using Cfg = ColCfg<L>;
   dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
   if (trans)
@@ -282,6 +590,22 @@ template <int L>
 hipError_t launch_c2r_t(bool trans, bool accum, const float2* in, float* out, int nlines, int r0, int nout,
                                long long in_img, long long out_img, float scale, const float2* tw, int batch,
                                hipStream_t s) {
+  if constexpr (FastCfg<L>::ok) {
+    using F = FastCfg<L>;
+    const int tiles = (nlines / 2 + F::LINES - 1) / F::LINES;
+    dim3 grid(tiles, batch), block(F::THREADS);
+#define FUNNEL_C2R_FAST(TR, AC) \
+  k_c2r_fast<L, TR, AC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img, scale, tw, tiles)
+    if (trans) {
+      if (accum) FUNNEL_C2R_FAST(true, true);
+      else FUNNEL_C2R_FAST(true, false);
+    } else {
+      if (accum) FUNNEL_C2R_FAST(false, true);
+      else FUNNEL_C2R_FAST(false, false);
+    }
+#undef FUNNEL_C2R_FAST
+    return hipGetLastError();
+  }
   using Cfg = ColCfg<L>;
   dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
   if (trans) {
@@ -301,6 +625,15 @@ hipError_t launch_c2r_t(bool trans, bool accum, const float2* in, float* out, in
 template <int M>
 hipError_t launch_row_t(bool adj, float2* data, int Lp, int h, long long img_stride, const float2* tw,
                                int batch, hipStream_t s) {
+  if constexpr (RowFastCfg<M>::ok) {
+    using F = RowFastCfg<M>;
+    dim3 grid((h + F::ROWS - 1) / F::ROWS, batch), block(F::THREADS);
+    if (adj)
+      k_row_fast<M, true><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
+    else
+      k_row_fast<M, false><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
+    return hipGetLastError();
+  }
   using Cfg = RowCfg<M>;
   dim3 grid((h + Cfg::ROWS - 1) / Cfg::ROWS, batch), block(Cfg::THREADS);
   if (adj)
