@@ -51,6 +51,7 @@ def main():
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=2, help="images in the CPU oracle sample")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default tile variants")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -71,6 +72,9 @@ def main():
 
     plan = F.FunnelPlan(B, N, M, 0, F.FT_SPACE_BOTH)
     Np = plan.Np
+    tuned = None
+    if not args.no_autotune:
+        tuned = F.funnel_autotune(plan.handle)   # set-up, outside the timed region
     x = torch.from_numpy(host).cuda()
     planes = plan.forward(x)
     torch.cuda.synchronize()
@@ -160,6 +164,8 @@ def main():
         "kernels": [{"name": k["name"], "avg_ms": round(k["avg_ms"], 4),
                      "bytes": k["bytes_per_launch"], "gbps": round(k["gbps"], 1)} for k in kernels],
         "cpu_baseline": cpu,
+        "tile_variants": F.funnel_plan_variants(plan.handle),
+        "autotuned": tuned is not None,
     }
     print(json.dumps(out), flush=True)
 

@@ -189,6 +189,29 @@ ft_status funnel_profile_enable(ft_plan* plan, int32_t max_records);
 ft_status funnel_profile_read(ft_plan* plan, ft_kernel_time* out, int32_t cap, int32_t* n);
 ft_status funnel_profile_disable(ft_plan* plan);
 
+/* ---- tile variants and autotuning ----
+ * Every pass kernel exists in several tile shapes (elements per thread,
+ * columns or rows per block).  A plan starts from a default per launch;
+ * funnel_autotune times every shape of every launch on the plan's real sizes
+ * (allocating and freeing its own scratch buffers and synchronising the
+ * stream) and keeps the fastest.  Launches ("roles") are numbered
+ *   0..5  forward  regular A, B, C, inverse A, B, C
+ *   6..11 adjoint  regular Ct, Bt, At, inverse Ct, Bt, At
+ * A plan being tuned must not be used concurrently. */
+typedef struct {
+  char name[40];       /* role name, e.g. "fwd.regular.C" */
+  int32_t variant;     /* chosen tile variant */
+  int32_t n_tried;     /* variants timed */
+  float ms;            /* best time of one launch */
+  float ms_default;    /* time of the variant the plan had before */
+} ft_tune_result;
+
+ft_status funnel_autotune(ft_plan* plan, void* stream, ft_tune_result* out, int32_t cap, int32_t* n);
+/* Current variant of each of the 12 roles (-1 for roles the plan does not run). */
+ft_status funnel_plan_variants(const ft_plan* plan, int32_t* variants, int32_t cap);
+/* Force one role's variant; FT_ERR_INVALID_ARG if that shape has no kernel. */
+ft_status funnel_plan_set_variant(ft_plan* plan, int32_t role, int32_t variant);
+
 /* Human-readable name of a status. */
 const char* funnel_status_string(ft_status status);
 

@@ -34,7 +34,28 @@ struct ft_plan {
   size_t off_inv_plane;       // floats from the image's plane block to the inverse plane
   size_t ws_bytes;            // forward / adjoint workspace
   size_t ws_off_inv;          // bytes from ws to the inverse-space spectrum
+  int variant[12];            // tile variant of each pass launch (see Role)
 };
+
+// The twelve kernel launches: three passes per space, forward and adjoint.
+enum Role {
+  FA_REG, FB_REG, FC_REG, FA_INV, FB_INV, FC_INV,
+  AC_REG, AB_REG, AA_REG, AC_INV, AB_INV, AA_INV, NROLES
+};
+static const char* const kRoleName[NROLES] = {
+    "fwd.regular.A", "fwd.regular.B", "fwd.regular.C", "fwd.inverse.A", "fwd.inverse.B", "fwd.inverse.C",
+    "adj.regular.Ct", "adj.regular.Bt", "adj.regular.At", "adj.inverse.Ct", "adj.inverse.Bt", "adj.inverse.At"};
+
+static bool role_is_row(int r) { return r == FB_REG || r == FB_INV || r == AB_REG || r == AB_INV; }
+static bool role_regular(int r) { return r <= FC_REG || (r >= AC_REG && r <= AA_REG); }
+static bool role_active(const ft_plan* p, int r) {
+  return (p->spaces & (role_regular(r) ? FT_SPACE_REGULAR : FT_SPACE_INVERSE)) != 0;
+}
+static unsigned role_mask(const ft_plan* p, int r) {
+  if (!role_is_row(r)) return funnel::col_variant_mask(p->Np);
+  return funnel::row_variant_mask(role_regular(r) ? p->M : p->N);
+}
+
 
 namespace {
 
@@ -168,6 +189,14 @@ ft_status funnel_plan_create(const ft_plan_desc* d, ft_plan** out) {
   p->ws_off_inv = s_reg;
   p->ws_bytes = s_reg + s_inv;
 
+  // default tile variants: the lowest-numbered one each kernel has
+  for (int r = 0; r < NROLES; ++r) {
+    const unsigned m = role_mask(p, r);
+    p->variant[r] = 0;
+    for (int v = 0; v < funnel::kMaxVariants; ++v)
+      if (m & (1u << v)) { p->variant[r] = v; break; }
+  }
+
   // twiddle tables for Np, M and N, back to back
   p->tw_np = 0;
   p->tw_m = (size_t)Np;
@@ -233,52 +262,82 @@ static ft_status check_call(const ft_plan* p, const void* a, const void* b, cons
   return FT_OK;
 }
 
+// Algorithmic HBM bytes of one launch: each input read once, each output
+// written once (a read-modify-write output counts twice).
+static double role_bytes(const ft_plan* p, int r) {
+  const double B = p->batch, N = p->N, M = p->M, Np = p->Np, h = p->h;
+  const double W = role_regular(r) ? M : N;  // lines of the spectrum
+  switch (r) {
+    case FA_REG: case FA_INV: return B * (4.0 * N * M + 8.0 * h * W);
+    case FB_REG: case FB_INV: case AB_REG: case AB_INV: return B * 16.0 * h * W;
+    case FC_REG: case FC_INV: return B * (8.0 * h * W + 4.0 * Np * W);
+    case AC_REG: case AC_INV: return B * (4.0 * Np * W + 8.0 * h * W);
+    case AA_REG: return B * (8.0 * h * M + 4.0 * N * M);
+    case AA_INV: return B * (8.0 * h * N + ((p->spaces & FT_SPACE_REGULAR) ? 8.0 : 4.0) * N * M);
+  }
+  return 0.0;
+}
+
+// One pass launch.  src: images (forward) or plane gradients (adjoint);
+// dst: planes (forward) or image gradients (adjoint).
+static hipError_t run_role(const ft_plan* p, int r, int v, const float* src, float* dst, char* w, hipStream_t s) {
+  const int B = p->batch, N = p->N, M = p->M, Np = p->Np, h = p->h;
+  const long long img = (long long)N * M, pst = (long long)p->plane_elems;
+  const float2* tw_np = p->tw + p->tw_np;
+  float2* Sr = reinterpret_cast<float2*>(w);
+  float2* Si = reinterpret_cast<float2*>(w + p->ws_off_inv);
+  const long long sr = (long long)h * M, si = (long long)h * N;
+  const bool reg = p->spaces & FT_SPACE_REGULAR;
+  switch (r) {
+    // forward, regular space: y DFT of the image columns on the expanded frame,
+    // NVMT + x' DFT per frequency row, Hermitian inverse y DFT
+    case FA_REG: return funnel::launch_r2c(Np, v, false, src, Sr, M, N, (Np - N) / 2, img, sr, 1.0f, tw_np, B, s);
+    case FB_REG: return funnel::launch_row(M, v, false, Sr, Np, h, sr, p->tw + p->tw_m, B, s);
+    case FC_REG:
+      return funnel::launch_c2r(Np, v, false, false, Sr, dst, M, 0, Np, sr, pst, 1.0f / Np, tw_np, B, s);
+    // forward, inverse space: the same on the transposed image (rows read directly)
+    case FA_INV: return funnel::launch_r2c(Np, v, true, src, Si, N, M, (Np - M) / 2, img, si, 1.0f, tw_np, B, s);
+    case FB_INV: return funnel::launch_row(N, v, false, Si, Np, h, si, p->tw + p->tw_n, B, s);
+    case FC_INV:
+      return funnel::launch_c2r(Np, v, false, false, Si, dst + p->off_inv_plane, N, 0, Np, si, pst, 1.0f / Np,
+                                tw_np, B, s);
+    // adjoint, regular space: (2/Np) y DFT of the plane columns, conjugate x'
+    // DFT + transposed interpolation, real part of the conjugate y DFT cropped
+    case AC_REG: return funnel::launch_r2c(Np, v, false, src, Sr, M, Np, 0, pst, sr, 2.0f / Np, tw_np, B, s);
+    case AB_REG: return funnel::launch_row(M, v, true, Sr, Np, h, sr, p->tw + p->tw_m, B, s);
+    case AA_REG:
+      return funnel::launch_c2r(Np, v, false, false, Sr, dst, M, (Np - N) / 2, N, sr, img, 0.5f, tw_np, B, s);
+    // adjoint, inverse space: transposed write into the image rows, added to
+    // the regular space's result when both spaces are computed
+    case AC_INV:
+      return funnel::launch_r2c(Np, v, false, src + p->off_inv_plane, Si, N, Np, 0, pst, si, 2.0f / Np, tw_np, B,
+                                s);
+    case AB_INV: return funnel::launch_row(N, v, true, Si, Np, h, si, p->tw + p->tw_n, B, s);
+    case AA_INV:
+      return funnel::launch_c2r(Np, v, true, reg, Si, dst, N, (Np - M) / 2, M, si, img, 0.5f, tw_np, B, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+static ft_status run_roles(const ft_plan* p, int first, int last, const float* src, float* dst, void* ws,
+                           hipStream_t s) {
+  (void)hipGetLastError();
+  char* w = static_cast<char*>(ws);
+  for (int r = first; r <= last; ++r) {
+    if (!role_active(p, r)) continue;
+    hipError_t e = timed(p, s, kRoleName[r], role_bytes(p, r),
+                         [&] { return run_role(p, r, p->variant[r], src, dst, w, s); });
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  }
+  return ok();
+}
+
 ft_status funnel_forward(const ft_plan* p, const float* images, float* planes, void* ws, size_t ws_bytes,
                          void* stream) {
   ft_status st = check_call(p, images, planes, ws, ws_bytes);
   if (st != FT_OK) return st;
   if ((st = check_device(p)) != FT_OK) return st;
-  (void)hipGetLastError();
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int B = p->batch, N = p->N, M = p->M, Np = p->Np, h = p->h;
-  const long long img = (long long)N * M, pst = (long long)p->plane_elems;
-  char* w = static_cast<char*>(ws);
-  const float2* tw_np = p->tw + p->tw_np;
-  hipError_t e = hipSuccess;
-  const double b = B;
-  if (p->spaces & FT_SPACE_REGULAR) {
-    float2* S = reinterpret_cast<float2*>(w);
-    const long long sst = (long long)h * M;
-    // pass A: columns of the image, (Np-N)/2 zero rows above
-    e = timed(p, s, "fwd.regular.A", b * (4.0 * N * M + 8.0 * h * M), [&] {
-      return funnel::launch_r2c(Np, false, images, S, M, N, (Np - N) / 2, img, sst, 1.0f, tw_np, B, s);
-    });
-    if (e == hipSuccess)
-      e = timed(p, s, "fwd.regular.B", b * 16.0 * h * M,
-                [&] { return funnel::launch_row(M, false, S, Np, h, sst, p->tw + p->tw_m, B, s); });
-    if (e == hipSuccess)
-      e = timed(p, s, "fwd.regular.C", b * (8.0 * h * M + 4.0 * Np * M), [&] {
-        return funnel::launch_c2r(Np, false, false, S, planes, M, 0, Np, sst, pst, 1.0f / Np, tw_np, B, s);
-      });
-  }
-  if (e == hipSuccess && (p->spaces & FT_SPACE_INVERSE)) {
-    float2* S = reinterpret_cast<float2*>(w + p->ws_off_inv);
-    const long long sst = (long long)h * N;
-    // pass A of the dual form: rows of the image, (Np-M)/2 zero columns on the left
-    e = timed(p, s, "fwd.inverse.A", b * (4.0 * N * M + 8.0 * h * N), [&] {
-      return funnel::launch_r2c(Np, true, images, S, N, M, (Np - M) / 2, img, sst, 1.0f, tw_np, B, s);
-    });
-    if (e == hipSuccess)
-      e = timed(p, s, "fwd.inverse.B", b * 16.0 * h * N,
-                [&] { return funnel::launch_row(N, false, S, Np, h, sst, p->tw + p->tw_n, B, s); });
-    if (e == hipSuccess)
-      e = timed(p, s, "fwd.inverse.C", b * (8.0 * h * N + 4.0 * Np * N), [&] {
-        return funnel::launch_c2r(Np, false, false, S, planes + p->off_inv_plane, N, 0, Np, sst, pst, 1.0f / Np,
-                                  tw_np, B, s);
-      });
-  }
-  if (e != hipSuccess) return hip_fail(e, "kernel launch");
-  return ok();
+  return run_roles(p, FA_REG, FC_INV, images, planes, ws, static_cast<hipStream_t>(stream));
 }
 
 ft_status funnel_adjoint(const ft_plan* p, const float* d_planes, float* d_images, void* ws, size_t ws_bytes,
@@ -286,49 +345,102 @@ ft_status funnel_adjoint(const ft_plan* p, const float* d_planes, float* d_image
   ft_status st = check_call(p, d_planes, d_images, ws, ws_bytes);
   if (st != FT_OK) return st;
   if ((st = check_device(p)) != FT_OK) return st;
-  (void)hipGetLastError();
+  return run_roles(p, AC_REG, AA_INV, d_planes, d_images, ws, static_cast<hipStream_t>(stream));
+}
+
+ft_status funnel_autotune(ft_plan* p, void* stream, ft_tune_result* out, int32_t cap, int32_t* n) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  if (cap < 0 || (cap > 0 && (!out || !n))) return fail(FT_ERR_INVALID_ARG, "bad result buffer");
+  ft_status st = check_device(p);
+  if (st != FT_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int B = p->batch, N = p->N, M = p->M, Np = p->Np, h = p->h;
-  const long long img = (long long)N * M, pst = (long long)p->plane_elems;
-  char* w = static_cast<char*>(ws);
-  const float2* tw_np = p->tw + p->tw_np;
-  hipError_t e = hipSuccess;
-  const bool reg = p->spaces & FT_SPACE_REGULAR;
-  const double b = B;
-  if (reg) {
-    float2* S = reinterpret_cast<float2*>(w);
-    const long long sst = (long long)h * M;
-    // C^T: (2/Np) DFT along y of every plane column, rows 1..h
-    e = timed(p, s, "adj.regular.Ct", b * (4.0 * Np * M + 8.0 * h * M), [&] {
-      return funnel::launch_r2c(Np, false, d_planes, S, M, Np, 0, pst, sst, 2.0f / Np, tw_np, B, s);
-    });
-    // B^T: conjugate DFT along x', transposed interpolation
-    if (e == hipSuccess)
-      e = timed(p, s, "adj.regular.Bt", b * 16.0 * h * M,
-                [&] { return funnel::launch_row(M, true, S, Np, h, sst, p->tw + p->tw_m, B, s); });
-    // A^T: Re of the conjugate y DFT, image rows only
-    if (e == hipSuccess)
-      e = timed(p, s, "adj.regular.At", b * (8.0 * h * M + 4.0 * N * M), [&] {
-        return funnel::launch_c2r(Np, false, false, S, d_images, M, (Np - N) / 2, N, sst, img, 0.5f, tw_np, B, s);
-      });
+  const size_t img_bytes = (size_t)p->batch * p->N * p->M * sizeof(float);
+  const size_t pl_bytes = (size_t)p->batch * p->plane_elems * sizeof(float);
+  void *a = nullptr, *b = nullptr, *w = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&] {
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (w) (void)hipFree(w);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  // a holds images or plane gradients, b planes or image gradients: size both for the larger
+  const size_t big = img_bytes > pl_bytes ? img_bytes : pl_bytes;
+  if (hipMalloc(&a, big) != hipSuccess || hipMalloc(&b, big) != hipSuccess ||
+      hipMalloc(&w, p->ws_bytes ? p->ws_bytes : 256) != hipSuccess) {
+    cleanup();
+    return fail(FT_ERR_OUT_OF_MEMORY, "autotune scratch allocation failed");
   }
-  if (e == hipSuccess && (p->spaces & FT_SPACE_INVERSE)) {
-    float2* S = reinterpret_cast<float2*>(w + p->ws_off_inv);
-    const long long sst = (long long)h * N;
-    e = timed(p, s, "adj.inverse.Ct", b * (4.0 * Np * N + 8.0 * h * N), [&] {
-      return funnel::launch_r2c(Np, false, d_planes + p->off_inv_plane, S, N, Np, 0, pst, sst, 2.0f / Np, tw_np, B,
-                                s);
-    });
-    if (e == hipSuccess)
-      e = timed(p, s, "adj.inverse.Bt", b * 16.0 * h * N,
-                [&] { return funnel::launch_row(N, true, S, Np, h, sst, p->tw + p->tw_n, B, s); });
-    // transposed write into the image rows; adds to the regular space's result
-    if (e == hipSuccess)
-      e = timed(p, s, "adj.inverse.At", b * (8.0 * h * N + (reg ? 8.0 : 4.0) * N * M), [&] {
-        return funnel::launch_c2r(Np, true, reg, S, d_images, N, (Np - M) / 2, M, sst, img, 0.5f, tw_np, B, s);
-      });
+  if (hipMemsetAsync(a, 0, big, s) != hipSuccess || hipMemsetAsync(b, 0, big, s) != hipSuccess ||
+      hipMemsetAsync(w, 0, p->ws_bytes ? p->ws_bytes : 256, s) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(FT_ERR_HIP, "autotune set-up failed");
   }
-  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  FtProfiler* saved = p->prof;
+  p->prof = nullptr;
+  int count = 0;
+  for (int r = 0; r < NROLES; ++r) {
+    if (!role_active(p, r)) continue;
+    const unsigned mask = role_mask(p, r);
+    float best = 1e30f, first_ms = -1.f;
+    int best_v = p->variant[r], tried = 0;
+    for (int v = 0; v < funnel::kMaxVariants; ++v) {
+      if (!(mask & (1u << v))) continue;
+      float ms_min = 1e30f;
+      hipError_t e = hipSuccess;
+      for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = run_role(p, r, v, static_cast<float*>(a), static_cast<float*>(b),
+                                          static_cast<char*>(w), s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && rep > 0 && ms < ms_min) ms_min = ms;
+      }
+      if (e != hipSuccess) {
+        p->prof = saved;
+        cleanup();
+        return hip_fail(e, "autotune launch");
+      }
+      if (v == p->variant[r]) first_ms = ms_min;
+      ++tried;
+      if (ms_min < best) {
+        best = ms_min;
+        best_v = v;
+      }
+    }
+    p->variant[r] = best_v;
+    if (count < cap) {
+      std::memset(&out[count], 0, sizeof(ft_tune_result));
+      std::snprintf(out[count].name, sizeof(out[count].name), "%s", kRoleName[r]);
+      out[count].variant = best_v;
+      out[count].n_tried = tried;
+      out[count].ms = best;
+      out[count].ms_default = first_ms;
+    }
+    ++count;
+  }
+  p->prof = saved;
+  cleanup();
+  if (n) *n = count < cap ? count : cap;
+  return ok();
+}
+
+ft_status funnel_plan_variants(const ft_plan* p, int32_t* variants, int32_t cap) {
+  if (!p || !variants || cap < 1) return fail(FT_ERR_INVALID_ARG, "plan and variants must be non-NULL");
+  for (int r = 0; r < NROLES && r < cap; ++r) variants[r] = role_active(p, r) ? p->variant[r] : -1;
+  return ok();
+}
+
+ft_status funnel_plan_set_variant(ft_plan* p, int32_t role, int32_t variant) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  if (role < 0 || role >= NROLES) return fail(FT_ERR_INVALID_ARG, "role must be in 0..%d", NROLES - 1);
+  if (variant < 0 || variant >= funnel::kMaxVariants || !(role_mask(p, role) & (1u << variant)))
+    return fail(FT_ERR_INVALID_ARG, "variant %d has no kernel for role %s", variant, kRoleName[role]);
+  p->variant[role] = variant;
   return ok();
 }
 

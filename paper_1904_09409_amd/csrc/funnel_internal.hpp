@@ -11,18 +11,24 @@ namespace funnel {
 
 bool length_supported(int L);
 
+// bit v set: tile variant v has a kernel for this length (bit 0 alone: the
+// generic kernel)
+unsigned col_variant_mask(int L);
+unsigned row_variant_mask(int M);
+constexpr int kMaxVariants = 8;
+
 // real lines (zero-padded to L) -> half spectrum rows 1..L/2-1, times scale*(-1)^k
-hipError_t launch_r2c(int L, bool trans, const float* in, float2* out, int nlines, int lin, int off,
+hipError_t launch_r2c(int L, int variant, bool trans, const float* in, float2* out, int nlines, int lin, int off,
                       long long in_img, long long out_img, float scale, const float2* tw, int batch,
                       hipStream_t s);
 
 // half spectrum rows 1..L/2-1 -> real lines, rows [r0, r0+nout) stored (or added)
-hipError_t launch_c2r(int L, bool trans, bool accum, const float2* in, float* out, int nlines, int r0, int nout,
+hipError_t launch_c2r(int L, int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0, int nout,
                       long long in_img, long long out_img, float scale, const float2* tw, int batch,
                       hipStream_t s);
 
 // per frequency row: NVMT gather + DFT along x' (forward) or its transpose (adjoint), in place
-hipError_t launch_row(int M, bool adj, float2* data, int Lp, int h, long long img_stride, const float2* tw,
+hipError_t launch_row(int M, int variant, bool adj, float2* data, int Lp, int h, long long img_stride, const float2* tw,
                       int batch, hipStream_t s);
 
 size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K);

@@ -273,26 +273,37 @@ __global__ void __launch_bounds__(RowCfg<M>::THREADS)
 // the C2R kernel builds its Hermitian input the same way from one read of
 // each stored coefficient.
 
-template <int L>
+template <int L, int E_, int LINES_>
 struct FastCfg {
-  static constexpr bool ok = (L >= 128) && ((L & (L - 1)) == 0) && L <= 4096;
-  // 16 elements per thread, except where a radix-16-only schedule would leave
-  // one butterfly per thread in the paired pass
-  static constexpr int E = (L == 256 || L == 4096) ? 32 : 16;
-  static constexpr int P = L / E;
-  static constexpr int LINES0 = 512 / P;
-  static constexpr int LINES = LINES0 > 16 ? 16 : (LINES0 < 1 ? 1 : LINES0);
+  static constexpr int E = E_;
+  static constexpr int LINES = LINES_;
+  static constexpr int P = L / E > 0 ? L / E : 1;
   static constexpr int THREADS = LINES * P;
+  static constexpr int rmin() {
+    const RadixPlan p = radix_plan(L);
+    int m = 1 << 30;
+    for (int i = 0; i < p.n; ++i) m = p.r[i] < m ? p.r[i] : m;
+    return m;
+  }
+  // power of two, every pass divides evenly, the paired pass (smallest radix)
+  // has an even number of butterflies per thread, and the block fits
+  static constexpr bool valid = (L >= 128) && ((L & (L - 1)) == 0) && L <= 4096 && L % E == 0 &&
+                                (E % rmin() == 0) && ((E / rmin()) % 2 == 0) && THREADS >= 64 &&
+                                THREADS <= 1024 && (L + L / 16 + 1) * LINES * 4 <= 150 * 1024;
 };
+
+// column-pass variants: (elements per thread, column pairs per block)
+#define FUNNEL_COL_VARIANTS(X) X(0, 16, 4) X(1, 16, 8) X(2, 16, 16) X(3, 32, 4) X(4, 32, 8) X(5, 32, 16)
+constexpr int kColVariants = 6;
 
 __device__ __forceinline__ float2 herm_direct(float4 x) { return make_float2(x.x - x.w, x.y + x.z); }  // A + iB
 __device__ __forceinline__ float2 herm_mirror(float4 x) { return make_float2(x.x + x.w, x.z - x.y); }  // conj A + i conj B
 
-template <int L, bool TRANS>
-__global__ void __launch_bounds__(FastCfg<L>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+template <int L, int E_, int LINES_, bool TRANS>
+__global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
     k_r2c_fast(const float* __restrict__ in, float2* __restrict__ out, int nlines, int lin, int off,
                long long in_img, long long out_img, float scale, const float2* __restrict__ tw, int tiles) {
-  using Cfg = FastCfg<L>;
+  using Cfg = FastCfg<L, E_, LINES_>;
   constexpr int P = Cfg::P, E = Cfg::E, LINES = Cfg::LINES, H = L / 2 - 1;
   using Eng = FftR<L, P, false, false>;
   constexpr RadixPlan PL = Eng::kPlan;
@@ -353,11 +364,11 @@ __global__ void __launch_bounds__(FastCfg<L>::THREADS) __attribute__((amdgpu_wav
   }
 }
 
-template <int L, bool TRANS, bool ACCUM>
-__global__ void __launch_bounds__(FastCfg<L>::THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+template <int L, int E_, int LINES_, bool TRANS, bool ACCUM>
+__global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
     k_c2r_fast(const float2* __restrict__ in, float* __restrict__ out, int nlines, int r0, int nout,
                long long in_img, long long out_img, float scale, const float2* __restrict__ tw, int tiles) {
-  using Cfg = FastCfg<L>;
+  using Cfg = FastCfg<L, E_, LINES_>;
   constexpr int P = Cfg::P, E = Cfg::E, LINES = Cfg::LINES;
   using Eng = FftR<L, P, true, true>;
   constexpr RadixPlan PL = Eng::kPlan;
@@ -445,19 +456,25 @@ __global__ void __launch_bounds__(FastCfg<L>::THREADS) __attribute__((amdgpu_wav
 // The whole row is staged in LDS with 16-byte loads issued before any use;
 // the NVMT gather feeds the first butterfly pass directly from that copy.
 
-template <int M>
+template <int M, int E_, int TPB>
 struct RowFastCfg {
-  static constexpr bool ok = (M >= 64) && ((M & (M - 1)) == 0) && M <= 4096;
-  static constexpr int E = 16;
-  static constexpr int P = M / E;
-  static constexpr int ROWS = 256 / P > 0 ? 256 / P : 1;
+  static constexpr int E = E_;
+  static constexpr int P = M / E > 0 ? M / E : 1;
+  static constexpr int ROWS = TPB / P > 0 ? TPB / P : 1;
   static constexpr int THREADS = ROWS * P;
+  static constexpr bool valid = (M >= 64) && ((M & (M - 1)) == 0) && M <= 4096 && M % E == 0 && P >= 1 &&
+                                (M / 16) % P == 0 && THREADS <= 1024 && THREADS >= 32 &&
+                                (M + M / 16 + 1) * ROWS * 8 <= 64 * 1024;
 };
 
-template <int M, bool ADJ>
-__global__ void __launch_bounds__(RowFastCfg<M>::THREADS)
+// row-pass variants: (elements per thread, target threads per block)
+#define FUNNEL_ROW_VARIANTS(X) X(0, 16, 256) X(1, 16, 128) X(2, 16, 512) X(3, 32, 256)
+constexpr int kRowVariants = 4;
+
+template <int M, int E_, int TPB, bool ADJ>
+__global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
     k_row_fast(float2* __restrict__ data, int Lp, int h, long long img_stride, const float2* __restrict__ tw) {
-  using Cfg = RowFastCfg<M>;
+  using Cfg = RowFastCfg<M, E_, TPB>;
   constexpr int P = Cfg::P, E = Cfg::E, ROWS = Cfg::ROWS;
   using Eng = FftR<M, P, ADJ, false>;
   constexpr RadixPlan PL = Eng::kPlan;
@@ -564,19 +581,48 @@ __global__ void __launch_bounds__(RowFastCfg<M>::THREADS)
 // ------------------------------------------------------------------ launchers
 
 template <int L>
-hipError_t launch_r2c_t(bool trans, const float* in, float2* out, int nlines, int lin, int off,
-                               long long in_img, long long out_img, float scale, const float2* tw, int batch,
-                               hipStream_t s) {
-  if constexpr (FastCfg<L>::ok) {
-    using F = FastCfg<L>;
-    const int tiles = (nlines / 2 + F::LINES - 1) / F::LINES;
-    dim3 grid(tiles, batch), block(F::THREADS);
-    if (trans)
-      k_r2c_fast<L, true><<<grid, block, 0, s>>>(in, out, nlines, lin, off, in_img, out_img, scale, tw, tiles);
-    else
-      k_r2c_fast<L, false><<<grid, block, 0, s>>>(in, out, nlines, lin, off, in_img, out_img, scale, tw, tiles);
-    return hipGetLastError();
+unsigned col_variant_mask_t() {
+  unsigned m = 0;
+#define FUNNEL_V(i, e, l) if constexpr (FastCfg<L, e, l>::valid) m |= 1u << i;
+  FUNNEL_COL_VARIANTS(FUNNEL_V)
+#undef FUNNEL_V
+  return m ? m : 1u;  // lengths without a register-resident kernel: the generic one, variant 0
+}
+
+template <int M>
+unsigned row_variant_mask_t() {
+  unsigned m = 0;
+#define FUNNEL_V(i, e, t) if constexpr (RowFastCfg<M, e, t>::valid) m |= 1u << i;
+  FUNNEL_ROW_VARIANTS(FUNNEL_V)
+#undef FUNNEL_V
+  return m ? m : 1u;
+}
+
+template <int L>
+hipError_t launch_r2c_t(int variant, bool trans, const float* in, float2* out, int nlines, int lin, int off,
+                        long long in_img, long long out_img, float scale, const float2* tw, int batch,
+                        hipStream_t s) {
+  switch (variant) {
+#define FUNNEL_V(i, e, l)                                                                                      \
+  case i:                                                                                                      \
+    if constexpr (FastCfg<L, e, l>::valid) {                                                                   \
+      using F = FastCfg<L, e, l>;                                                                              \
+      const int tiles = (nlines / 2 + F::LINES - 1) / F::LINES;                                                \
+      dim3 grid(tiles, batch), block(F::THREADS);                                                              \
+      if (trans)                                                                                               \
+        k_r2c_fast<L, e, l, true><<<grid, block, 0, s>>>(in, out, nlines, lin, off, in_img, out_img, scale, tw, \
+                                                          tiles);                                              \
+      else                                                                                                     \
+        k_r2c_fast<L, e, l, false><<<grid, block, 0, s>>>(in, out, nlines, lin, off, in_img, out_img, scale,   \
+                                                           tw, tiles);                                         \
+      return hipGetLastError();                                                                                \
+    }                                                                                                          \
+    break;
+    FUNNEL_COL_VARIANTS(FUNNEL_V)
+#undef FUNNEL_V
+    default: break;
   }
+  if (col_variant_mask_t<L>() != 1u || variant != 0) return hipErrorInvalidValue;
   using Cfg = ColCfg<L>;
   dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
   if (trans)
@@ -587,25 +633,39 @@ hipError_t launch_r2c_t(bool trans, const float* in, float2* out, int nlines, in
 }
 
 template <int L>
-hipError_t launch_c2r_t(bool trans, bool accum, const float2* in, float* out, int nlines, int r0, int nout,
-                               long long in_img, long long out_img, float scale, const float2* tw, int batch,
-                               hipStream_t s) {
-  if constexpr (FastCfg<L>::ok) {
-    using F = FastCfg<L>;
-    const int tiles = (nlines / 2 + F::LINES - 1) / F::LINES;
-    dim3 grid(tiles, batch), block(F::THREADS);
-#define FUNNEL_C2R_FAST(TR, AC) \
-  k_c2r_fast<L, TR, AC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img, scale, tw, tiles)
-    if (trans) {
-      if (accum) FUNNEL_C2R_FAST(true, true);
-      else FUNNEL_C2R_FAST(true, false);
-    } else {
-      if (accum) FUNNEL_C2R_FAST(false, true);
-      else FUNNEL_C2R_FAST(false, false);
-    }
-#undef FUNNEL_C2R_FAST
-    return hipGetLastError();
+hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0,
+                        int nout, long long in_img, long long out_img, float scale, const float2* tw, int batch,
+                        hipStream_t s) {
+  switch (variant) {
+#define FUNNEL_V(i, e, l)                                                                                      \
+  case i:                                                                                                      \
+    if constexpr (FastCfg<L, e, l>::valid) {                                                                   \
+      using F = FastCfg<L, e, l>;                                                                              \
+      const int tiles = (nlines / 2 + F::LINES - 1) / F::LINES;                                                \
+      dim3 grid(tiles, batch), block(F::THREADS);                                                              \
+      if (trans) {                                                                                             \
+        if (accum)                                                                                             \
+          k_c2r_fast<L, e, l, true, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img,   \
+                                                                 scale, tw, tiles);                            \
+        else                                                                                                   \
+          k_c2r_fast<L, e, l, true, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img,  \
+                                                                  scale, tw, tiles);                           \
+      } else {                                                                                                 \
+        if (accum)                                                                                             \
+          k_c2r_fast<L, e, l, false, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img,  \
+                                                                  scale, tw, tiles);                           \
+        else                                                                                                   \
+          k_c2r_fast<L, e, l, false, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img, \
+                                                                   scale, tw, tiles);                          \
+      }                                                                                                        \
+      return hipGetLastError();                                                                                \
+    }                                                                                                          \
+    break;
+    FUNNEL_COL_VARIANTS(FUNNEL_V)
+#undef FUNNEL_V
+    default: break;
   }
+  if (col_variant_mask_t<L>() != 1u || variant != 0) return hipErrorInvalidValue;
   using Cfg = ColCfg<L>;
   dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
   if (trans) {
@@ -623,17 +683,26 @@ hipError_t launch_c2r_t(bool trans, bool accum, const float2* in, float* out, in
 }
 
 template <int M>
-hipError_t launch_row_t(bool adj, float2* data, int Lp, int h, long long img_stride, const float2* tw,
-                               int batch, hipStream_t s) {
-  if constexpr (RowFastCfg<M>::ok) {
-    using F = RowFastCfg<M>;
-    dim3 grid((h + F::ROWS - 1) / F::ROWS, batch), block(F::THREADS);
-    if (adj)
-      k_row_fast<M, true><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
-    else
-      k_row_fast<M, false><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
-    return hipGetLastError();
+hipError_t launch_row_t(int variant, bool adj, float2* data, int Lp, int h, long long img_stride,
+                        const float2* tw, int batch, hipStream_t s) {
+  switch (variant) {
+#define FUNNEL_V(i, e, tpb)                                                                       \
+  case i:                                                                                         \
+    if constexpr (RowFastCfg<M, e, tpb>::valid) {                                                 \
+      using F = RowFastCfg<M, e, tpb>;                                                            \
+      dim3 grid((h + F::ROWS - 1) / F::ROWS, batch), block(F::THREADS);                           \
+      if (adj)                                                                                    \
+        k_row_fast<M, e, tpb, true><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);          \
+      else                                                                                        \
+        k_row_fast<M, e, tpb, false><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);         \
+      return hipGetLastError();                                                                   \
+    }                                                                                             \
+    break;
+    FUNNEL_ROW_VARIANTS(FUNNEL_V)
+#undef FUNNEL_V
+    default: break;
   }
+  if (row_variant_mask_t<M>() != 1u || variant != 0) return hipErrorInvalidValue;
   using Cfg = RowCfg<M>;
   dim3 grid((h + Cfg::ROWS - 1) / Cfg::ROWS, batch), block(Cfg::THREADS);
   if (adj)

@@ -46,6 +46,11 @@ class ft_kernel_time(ctypes.Structure):
                 ("bytes_per_launch", ctypes.c_double)]
 
 
+class ft_tune_result(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("variant", ctypes.c_int32), ("n_tried", ctypes.c_int32),
+                ("ms", ctypes.c_float), ("ms_default", ctypes.c_float)]
+
+
 PEAK_DTYPE = np.dtype([("image", np.int32), ("space", np.int32), ("row", np.int32), ("col", np.int32),
                        ("value", np.float32), ("slope", np.float32), ("intercept", np.float32)])
 PEAK_WORDS = PEAK_DTYPE.itemsize // 4   # 7 x 4 bytes
@@ -82,6 +87,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "funnel_profile_enable": ([vp, i32], ctypes.c_int),
         "funnel_profile_read": ([vp, ctypes.POINTER(ft_kernel_time), i32, ctypes.POINTER(i32)], ctypes.c_int),
         "funnel_profile_disable": ([vp], ctypes.c_int),
+        "funnel_autotune": ([vp, vp, ctypes.POINTER(ft_tune_result), i32, ctypes.POINTER(i32)], ctypes.c_int),
+        "funnel_plan_variants": ([vp, ctypes.POINTER(i32), i32], ctypes.c_int),
+        "funnel_plan_set_variant": ([vp, i32, i32], ctypes.c_int),
         "funnel_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "funnel_last_error": ([], ctypes.c_char_p),
     }
@@ -193,6 +201,24 @@ def funnel_profile_read(plan: int, cap: int = 64) -> list[dict]:
 
 def funnel_profile_disable(plan: int) -> None:
     _check(load_library().funnel_profile_disable(plan), "funnel_profile_disable")
+
+
+def funnel_autotune(plan: int, stream=None, cap: int = 16) -> list[dict]:
+    arr = (ft_tune_result * cap)()
+    n = ctypes.c_int32()
+    _check(load_library().funnel_autotune(plan, _stream(stream), arr, cap, ctypes.byref(n)), "funnel_autotune")
+    return [dict(name=arr[i].name.decode(), variant=arr[i].variant, n_tried=arr[i].n_tried, ms=arr[i].ms,
+                 ms_default=arr[i].ms_default) for i in range(n.value)]
+
+
+def funnel_plan_variants(plan: int) -> list[int]:
+    arr = (ctypes.c_int32 * 12)()
+    _check(load_library().funnel_plan_variants(plan, arr, 12), "funnel_plan_variants")
+    return list(arr)
+
+
+def funnel_plan_set_variant(plan: int, role: int, variant: int) -> None:
+    _check(load_library().funnel_plan_set_variant(plan, int(role), int(variant)), "funnel_plan_set_variant")
 
 
 # ------------------------------------------------------------------ convenience layer
