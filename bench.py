@@ -122,6 +122,11 @@ def main():
     step_kernel_ms = sum(k["total_ms"] for k in kernels) / args.steps
 
     copy_gbps, copy_ms = copy_bandwidth(torch)
+    roles = ["fwd.regular.A", "fwd.regular.B", "fwd.regular.C", "fwd.inverse.A", "fwd.inverse.B", "fwd.inverse.C",
+             "adj.regular.Ct", "adj.regular.Bt", "adj.regular.At", "adj.inverse.Ct", "adj.inverse.Bt",
+             "adj.inverse.At"]
+    variants = F.funnel_plan_variants(plan.handle)
+    traffic = measured_traffic(dom["name"], variants[roles.index(dom["name"])])
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -152,7 +157,8 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(dom["gbps"] / HBM_PEAK_GBPS, 4),
-            "traffic": None,
+            "traffic": (traffic or {}).get("bytes"),
+            "traffic_detail": traffic,
             "step_algorithmic_gbps": round(step_bytes / (ms_per_step * 1e6), 1),
             "step_frac": round(step_bytes / (ms_per_step * 1e6) / HBM_PEAK_GBPS, 4),
             "step_bytes": step_bytes,
@@ -164,10 +170,32 @@ def main():
         "kernels": [{"name": k["name"], "avg_ms": round(k["avg_ms"], 4),
                      "bytes": k["bytes_per_launch"], "gbps": round(k["gbps"], 1)} for k in kernels],
         "cpu_baseline": cpu,
-        "tile_variants": F.funnel_plan_variants(plan.handle),
+        "tile_variants": variants,
         "autotuned": tuned is not None,
     }
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(launch: str, variant: int):
+    """HBM bytes of one launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE table, if the kernel sources are unchanged since it was taken."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "funnel_fwd_adj_32x1024_traffic.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_1904_09409_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + glob.glob(os.path.join(csrc, "*.hip"))):
+        h.update(open(f, "rb").read())
+    if h.hexdigest() != t.get("source_hash") or launch not in t.get("launches", {}):
+        return None
+    e = t["launches"][launch]
+    if e.get("variant") != variant:
+        return None
+    return {"bytes": e["read_bytes"] + e["write_bytes"], "read_bytes": e["read_bytes"],
+            "write_bytes": e["write_bytes"], "kernel": e["kernel"]}
 
 
 def copy_bandwidth(torch, nbytes=1 << 30, reps=10):

@@ -428,6 +428,26 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
   if (!active) return;
 
   float* dst = out + (long long)img * out_img;
+  float2 old[E];
+  if constexpr (ACCUM) {
+    // read every old value first so the adds do not serialise on memory latency
+#pragma unroll
+    for (int b = 0; b < BPTL; ++b)
+#pragma unroll
+      for (int q = 0; q < RL; ++q) {
+        const int r = t + P * b + q * NBL - r0;
+        float2 o = make_float2(0.f, 0.f);
+        if (r >= 0 && r < nout) {
+          if constexpr (TRANS) {
+            o.x = dst[(long long)(2 * pg) * nout + r];
+            o.y = dst[(long long)(2 * pg + 1) * nout + r];
+          } else {
+            o = *reinterpret_cast<const float2*>(dst + (long long)r * nlines + 2 * pg);
+          }
+        }
+        old[b * RL + q] = o;
+      }
+  }
 #pragma unroll
   for (int b = 0; b < BPTL; ++b) {
     const int j = t + P * b;
@@ -435,16 +455,16 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
     for (int q = 0; q < RL; ++q) {
       const int r = j + q * NBL - r0;
       if (r < 0 || r >= nout) continue;
-      const float a = scale * v[b * RL + q].x, bb = scale * v[b * RL + q].y;
+      float a = scale * v[b * RL + q].x, bb = scale * v[b * RL + q].y;
+      if constexpr (ACCUM) {
+        a += old[b * RL + q].x;
+        bb += old[b * RL + q].y;
+      }
       if constexpr (TRANS) {
-        float* pa = dst + (long long)(2 * pg) * nout + r;
-        float* pb = pa + nout;
-        if constexpr (ACCUM) { *pa += a; *pb += bb; }
-        else { *pa = a; *pb = bb; }
+        dst[(long long)(2 * pg) * nout + r] = a;
+        dst[(long long)(2 * pg + 1) * nout + r] = bb;
       } else {
-        float2* p2 = reinterpret_cast<float2*>(dst + (long long)r * nlines + 2 * pg);
-        if constexpr (ACCUM) { float2 o = *p2; o.x += a; o.y += bb; *p2 = o; }
-        else *p2 = make_float2(a, bb);
+        *reinterpret_cast<float2*>(dst + (long long)r * nlines + 2 * pg) = make_float2(a, bb);
       }
     }
   }
