@@ -116,16 +116,43 @@ typedef struct {
  * Returns FT_ERR_UNSUPPORTED_SIZE when a length has no compiled kernel. */
 ft_status funnel_plan_create(const ft_plan_desc* desc, ft_plan** out);
 
+/* One image of a ragged batch.  Images of different sizes go in one call;
+ * each image's planes (regular then inverse, Np = rows+cols) start at
+ * plane_offset.  Offsets are in floats from the images / planes base and must
+ * be multiples of 4 (16-byte alignment).  The caller keeps the regions
+ * disjoint; the library cannot see the buffers' extent. */
+typedef struct {
+  int32_t rows;          /* N, even, >= 4 */
+  int32_t cols;          /* M, even, >= 4 */
+  int64_t image_offset;  /* floats from the images base */
+  int64_t plane_offset;  /* floats from the planes base */
+} ft_image_desc;
+
+/* Create a plan for a ragged batch: images are grouped into size classes,
+ * each with its own radix schedule, tile variants, twiddles and workspace
+ * region.  The classes of a call run concurrently on streams the plan owns,
+ * forked from and joined back to the caller's stream with events (the call
+ * is still stream-ordered and can be captured into a graph).  A ragged plan
+ * must not be used from two host threads at once. */
+ft_status funnel_plan_create_ragged(const ft_image_desc* images, int32_t count, int32_t spaces, ft_plan** out);
+
 /* Release the plan's tables.  NULL is accepted. */
 void funnel_plan_destroy(ft_plan* plan);
 
 /* Bytes of device workspace funnel_forward and funnel_adjoint need. */
 ft_status funnel_workspace_size(const ft_plan* plan, size_t* bytes);
 
-/* Floats of parameter plane per image (regular Np*M and/or inverse Np*N). */
+/* Floats of parameter plane per image (regular Np*M and/or inverse Np*N);
+ * for a ragged plan, the extent of the whole planes buffer. */
 ft_status funnel_plane_elems(const ft_plan* plan, size_t* floats_per_image);
 
-/* Padded length Np the plan uses. */
+/* Floats the images and the planes buffers of a call must span. */
+ft_status funnel_buffer_elems(const ft_plan* plan, size_t* image_floats, size_t* plane_floats);
+
+/* Number of size classes (1 for a uniform batch). */
+ft_status funnel_plan_classes(const ft_plan* plan, int32_t* n);
+
+/* Padded length Np the plan uses (uniform plans only). */
 ft_status funnel_padded_len(const ft_plan* plan, int32_t* np);
 
 /* Forward funnel transform of a batch (Sec. 3.1 on the expanded image of
@@ -147,6 +174,18 @@ ft_status funnel_forward(const ft_plan* plan, const float* images, float* planes
  * the image rows. */
 ft_status funnel_adjoint(const ft_plan* plan, const float* d_planes, float* d_images,
                          void* ws, size_t ws_bytes, void* stream);
+
+/* ---- graphs ----
+ * Capture the launches of funnel_forward and/or funnel_adjoint with fixed
+ * buffers into an executable HIP graph, built once and replayed with one
+ * call.  The graph reads and writes the buffers given here on every launch.
+ * Building a graph synchronises nothing and allocates only the graph. */
+enum { FT_GRAPH_FORWARD = 1u, FT_GRAPH_ADJOINT = 2u };
+typedef struct ft_graph ft_graph;
+ft_status funnel_graph_create(const ft_plan* plan, uint32_t what, const float* images, float* planes,
+                              const float* d_planes, float* d_images, void* ws, size_t ws_bytes, ft_graph** out);
+ft_status funnel_graph_launch(const ft_graph* graph, void* stream);
+void funnel_graph_destroy(ft_graph* graph);
 
 /* Bytes of device workspace funnel_peaks needs for a given K. */
 ft_status funnel_peaks_workspace_size(const ft_plan* plan, int32_t K, size_t* bytes);
@@ -197,6 +236,7 @@ ft_status funnel_profile_disable(ft_plan* plan);
  * stream) and keeps the fastest.  Launches ("roles") are numbered
  *   0..5  forward  regular A, B, C, inverse A, B, C
  *   6..11 adjoint  regular Ct, Bt, At, inverse Ct, Bt, At
+ * For a ragged plan, class c's launches are roles 12*c .. 12*c+11.
  * A plan being tuned must not be used concurrently. */
 typedef struct {
   char name[40];       /* role name, e.g. "fwd.regular.C" */
@@ -207,7 +247,7 @@ typedef struct {
 } ft_tune_result;
 
 ft_status funnel_autotune(ft_plan* plan, void* stream, ft_tune_result* out, int32_t cap, int32_t* n);
-/* Current variant of each of the 12 roles (-1 for roles the plan does not run). */
+/* Current variant of each role, 12 per size class (-1 for roles the plan does not run). */
 ft_status funnel_plan_variants(const ft_plan* plan, int32_t* variants, int32_t cap);
 /* Force one role's variant; FT_ERR_INVALID_ARG if that shape has no kernel. */
 ft_status funnel_plan_set_variant(ft_plan* plan, int32_t role, int32_t variant);

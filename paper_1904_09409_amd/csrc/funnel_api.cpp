@@ -1,15 +1,27 @@
 // funnel_api.cpp -- the C ABI declared in include/funnel.h: argument
 // validation (host only, before any device work), plans with their FP64-derived
-// twiddle tables, workspace layout and the order of the passes.
+// twiddle tables, workspace layout, the order of the passes, ragged batches,
+// graphs, autotuning and kernel timing.
+//
+// A plan is a list of size classes.  A uniform batch is one class with
+// uniform strides; a ragged batch groups its images by (rows, cols), each
+// class with its own radix schedule, tile variants, twiddles, workspace region
+// and device tables of per-image offsets.  The classes of a ragged plan run on
+// their own streams (default priority), forked from and joined back to the
+// caller's stream by events, so they overlap on the device -- eagerly or
+// inside a captured graph.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/funnel.h"
@@ -19,43 +31,52 @@
 struct FtProfiler {
   int cap = 0, used = 0;
   std::vector<hipEvent_t> ev0, ev1;
-  std::vector<const char*> name;
+  std::vector<std::string> name;
   std::vector<double> bytes;
 };
 
-struct ft_plan {
-  FtProfiler* prof;           // optional, owned
-  int device;
-  int batch, N, M, Np, h;
-  int spaces;                 // FT_SPACE_* bits
-  float2* tw;                 // device twiddle tables
-  size_t tw_np, tw_m, tw_n;   // offsets (float2) of the tables for Np, M, N
-  size_t plane_elems;         // floats of plane per image
-  size_t off_inv_plane;       // floats from the image's plane block to the inverse plane
-  size_t ws_bytes;            // forward / adjoint workspace
-  size_t ws_off_inv;          // bytes from ws to the inverse-space spectrum
-  int variant[12];            // tile variant of each pass launch (see Role)
-};
-
-// The twelve kernel launches: three passes per space, forward and adjoint.
-enum Role {
-  FA_REG, FB_REG, FC_REG, FA_INV, FB_INV, FC_INV,
-  AC_REG, AB_REG, AA_REG, AC_INV, AB_INV, AA_INV, NROLES
-};
+// The twelve kernel launches of a class: three passes per space, forward and adjoint.
+enum Role { FA_REG, FB_REG, FC_REG, FA_INV, FB_INV, FC_INV, AC_REG, AB_REG, AA_REG, AC_INV, AB_INV, AA_INV, NROLES };
 static const char* const kRoleName[NROLES] = {
     "fwd.regular.A", "fwd.regular.B", "fwd.regular.C", "fwd.inverse.A", "fwd.inverse.B", "fwd.inverse.C",
     "adj.regular.Ct", "adj.regular.Bt", "adj.regular.At", "adj.inverse.Ct", "adj.inverse.Bt", "adj.inverse.At"};
 
-static bool role_is_row(int r) { return r == FB_REG || r == FB_INV || r == AB_REG || r == AB_INV; }
-static bool role_regular(int r) { return r <= FC_REG || (r >= AC_REG && r <= AA_REG); }
-static bool role_active(const ft_plan* p, int r) {
-  return (p->spaces & (role_regular(r) ? FT_SPACE_REGULAR : FT_SPACE_INVERSE)) != 0;
-}
-static unsigned role_mask(const ft_plan* p, int r) {
-  if (!role_is_row(r)) return funnel::col_variant_mask(p->Np);
-  return funnel::row_variant_mask(role_regular(r) ? p->M : p->N);
-}
+struct FtClass {
+  int N = 0, M = 0, Np = 0, h = 0, count = 0;
+  size_t tw_np = 0, tw_m = 0, tw_n = 0;   // float2 offsets of this class's tables in plan->tw
+  size_t ws_reg = 0, ws_inv = 0;          // byte offsets of the half spectra in the workspace
+  size_t off_inv_plane = 0;               // floats from an image's plane block to its inverse plane
+  long long img_stride = 0, plane_stride = 0;
+  const long long* d_img_off = nullptr;   // ragged: class-local image -> element offset
+  const long long* d_plane_off = nullptr;
+  const int* d_gidx = nullptr;            // ragged: class-local image -> caller's image index
+  std::vector<int> images;                // caller's image indices (host copy)
+  int variant[NROLES] = {};
+  hipStream_t stream = nullptr;           // ragged plans with several classes
+  hipEvent_t done = nullptr;
+};
 
+struct ft_plan {
+  FtProfiler* prof = nullptr;
+  int device = 0;
+  int spaces = 0;
+  int batch = 0;
+  bool ragged = false;
+  std::vector<FtClass> cls;
+  float2* tw = nullptr;
+  void* tables = nullptr;
+  size_t ws_bytes = 0;
+  size_t plane_elems = 0;   // uniform: floats per image; ragged: extent of the whole planes buffer
+  size_t image_extent = 0;  // floats of the images buffer
+  size_t plane_extent = 0;  // floats of the planes buffer
+  hipEvent_t fork = nullptr;
+};
+
+struct ft_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
 
 namespace {
 
@@ -99,9 +120,35 @@ void fill_twiddles(float2* dst, int L) {
   }
 }
 
+bool role_is_row(int r) { return r == FB_REG || r == FB_INV || r == AB_REG || r == AB_INV; }
+bool role_regular(int r) { return r <= FC_REG || (r >= AC_REG && r <= AA_REG); }
+bool role_active(const ft_plan* p, int r) {
+  return (p->spaces & (role_regular(r) ? FT_SPACE_REGULAR : FT_SPACE_INVERSE)) != 0;
+}
+unsigned role_mask(const FtClass& c, int r) {
+  if (!role_is_row(r)) return funnel::col_variant_mask(c.Np);
+  return funnel::row_variant_mask(role_regular(r) ? c.M : c.N);
+}
+
+// Algorithmic HBM bytes of one launch: each input read once, each output
+// written once (a read-modify-write output counts twice).
+double role_bytes(const ft_plan* p, const FtClass& c, int r) {
+  const double B = c.count, N = c.N, M = c.M, Np = c.Np, h = c.h;
+  const double W = role_regular(r) ? M : N;  // lines of the spectrum
+  switch (r) {
+    case FA_REG: case FA_INV: return B * (4.0 * N * M + 8.0 * h * W);
+    case FB_REG: case FB_INV: case AB_REG: case AB_INV: return B * 16.0 * h * W;
+    case FC_REG: case FC_INV: return B * (8.0 * h * W + 4.0 * Np * W);
+    case AC_REG: case AC_INV: return B * (4.0 * Np * W + 8.0 * h * W);
+    case AA_REG: return B * (8.0 * h * M + 4.0 * N * M);
+    case AA_INV: return B * (8.0 * h * N + ((p->spaces & FT_SPACE_REGULAR) ? 8.0 : 4.0) * N * M);
+  }
+  return 0.0;
+}
+
 // Run one launch, bracketed by events when the plan is being profiled.
 template <class Fn>
-hipError_t timed(const ft_plan* p, hipStream_t s, const char* name, double bytes, Fn&& fn) {
+hipError_t timed(const ft_plan* p, hipStream_t s, const std::string& name, double bytes, Fn&& fn) {
   FtProfiler* pr = p->prof;
   if (!pr || pr->used >= pr->cap) return fn();
   const int i = pr->used++;
@@ -119,6 +166,213 @@ void free_profiler(FtProfiler* pr) {
   for (auto ev : pr->ev0) (void)hipEventDestroy(ev);
   for (auto ev : pr->ev1) (void)hipEventDestroy(ev);
   delete pr;
+}
+
+void free_plan(ft_plan* p) {
+  if (!p) return;
+  free_profiler(p->prof);
+  for (auto& c : p->cls) {
+    if (c.stream) (void)hipStreamDestroy(c.stream);
+    if (c.done) (void)hipEventDestroy(c.done);
+  }
+  if (p->fork) (void)hipEventDestroy(p->fork);
+  if (p->tw) (void)hipFree(p->tw);
+  if (p->tables) (void)hipFree(p->tables);
+  delete p;
+}
+
+// One pass launch of class c.  src: images (forward) or plane gradients
+// (adjoint); dst: planes (forward) or image gradients (adjoint).
+hipError_t run_role(const ft_plan* p, const FtClass& c, int r, int v, const float* src, float* dst, char* w,
+                    hipStream_t s) {
+  const int B = c.count, N = c.N, M = c.M, Np = c.Np, h = c.h;
+  const float2* tw_np = p->tw + c.tw_np;
+  float2* Sr = reinterpret_cast<float2*>(w + c.ws_reg);
+  float2* Si = reinterpret_cast<float2*>(w + c.ws_inv);
+  const long long sr = (long long)h * M, si = (long long)h * N;
+  const bool reg = p->spaces & FT_SPACE_REGULAR;
+  using funnel::ImgMap;
+  // where each launch's input and output of image i start
+  const ImgMap img_to_sr{c.img_stride, sr, c.d_img_off, nullptr};
+  const ImgMap img_to_si{c.img_stride, si, c.d_img_off, nullptr};
+  const ImgMap sr_to_pl{sr, c.plane_stride, nullptr, c.d_plane_off};
+  const ImgMap si_to_pl{si, c.plane_stride, nullptr, c.d_plane_off};
+  const ImgMap pl_to_sr{c.plane_stride, sr, c.d_plane_off, nullptr};
+  const ImgMap pl_to_si{c.plane_stride, si, c.d_plane_off, nullptr};
+  const ImgMap sr_to_img{sr, c.img_stride, nullptr, c.d_img_off};
+  const ImgMap si_to_img{si, c.img_stride, nullptr, c.d_img_off};
+  switch (r) {
+    // forward, regular space: y DFT of the image columns on the expanded frame,
+    // NVMT + x' DFT per frequency row, Hermitian inverse y DFT
+    case FA_REG: return funnel::launch_r2c(Np, v, false, src, Sr, M, N, (Np - N) / 2, img_to_sr, 1.0f, tw_np, B, s);
+    case FB_REG: return funnel::launch_row(M, v, false, Sr, Np, h, sr, p->tw + c.tw_m, B, s);
+    case FC_REG:
+      return funnel::launch_c2r(Np, v, false, false, Sr, dst, M, 0, Np, sr_to_pl, 1.0f / Np, tw_np, B, s);
+    // forward, inverse space: the same on the transposed image (rows read directly)
+    case FA_INV: return funnel::launch_r2c(Np, v, true, src, Si, N, M, (Np - M) / 2, img_to_si, 1.0f, tw_np, B, s);
+    case FB_INV: return funnel::launch_row(N, v, false, Si, Np, h, si, p->tw + c.tw_n, B, s);
+    case FC_INV:
+      return funnel::launch_c2r(Np, v, false, false, Si, dst + c.off_inv_plane, N, 0, Np, si_to_pl, 1.0f / Np,
+                                tw_np, B, s);
+    // adjoint, regular space: (2/Np) y DFT of the plane columns, conjugate x'
+    // DFT + transposed interpolation, real part of the conjugate y DFT cropped
+    case AC_REG: return funnel::launch_r2c(Np, v, false, src, Sr, M, Np, 0, pl_to_sr, 2.0f / Np, tw_np, B, s);
+    case AB_REG: return funnel::launch_row(M, v, true, Sr, Np, h, sr, p->tw + c.tw_m, B, s);
+    case AA_REG:
+      return funnel::launch_c2r(Np, v, false, false, Sr, dst, M, (Np - N) / 2, N, sr_to_img, 0.5f, tw_np, B, s);
+    // adjoint, inverse space: transposed write into the image rows, added to
+    // the regular space's result when both spaces are computed
+    case AC_INV:
+      return funnel::launch_r2c(Np, v, false, src + c.off_inv_plane, Si, N, Np, 0, pl_to_si, 2.0f / Np, tw_np, B,
+                                s);
+    case AB_INV: return funnel::launch_row(N, v, true, Si, Np, h, si, p->tw + c.tw_n, B, s);
+    case AA_INV:
+      return funnel::launch_c2r(Np, v, true, reg, Si, dst, N, (Np - M) / 2, M, si_to_img, 0.5f, tw_np, B, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+std::string role_label(const ft_plan* p, int ci, int r) {
+  if (p->cls.size() == 1) return kRoleName[r];
+  return "c" + std::to_string(ci) + "." + kRoleName[r];
+}
+
+// Enqueue roles [first, last] of every class: on the caller's stream for a
+// single class, else on the class streams between a fork and a join.
+hipError_t enqueue_roles(const ft_plan* p, int first, int last, const float* src, float* dst, char* w,
+                         hipStream_t s) {
+  const bool fork = p->cls.size() > 1;
+  hipError_t e = hipSuccess;
+  if (fork) e = hipEventRecord(p->fork, s);
+  for (size_t ci = 0; ci < p->cls.size() && e == hipSuccess; ++ci) {
+    const FtClass& c = p->cls[ci];
+    hipStream_t cs = fork ? c.stream : s;
+    if (fork) e = hipStreamWaitEvent(cs, p->fork, 0);
+    for (int r = first; r <= last && e == hipSuccess; ++r) {
+      if (!role_active(p, r)) continue;
+      e = timed(p, cs, role_label(p, (int)ci, r), role_bytes(p, c, r),
+                [&] { return run_role(p, c, r, c.variant[r], src, dst, w, cs); });
+    }
+    if (fork && e == hipSuccess) e = hipEventRecord(c.done, cs);
+  }
+  for (size_t ci = 0; fork && ci < p->cls.size() && e == hipSuccess; ++ci)
+    e = hipStreamWaitEvent(s, p->cls[ci].done, 0);
+  return e;
+}
+
+ft_status check_call(const ft_plan* p, const void* a, const void* b, const void* ws, size_t ws_bytes) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  if (!a || !b || !ws) return fail(FT_ERR_INVALID_ARG, "input, output and workspace must be non-NULL");
+  if (!aligned16(a) || !aligned16(b) || !aligned16(ws))
+    return fail(FT_ERR_MISALIGNED, "device pointers must be 16-byte aligned");
+  if (ws_bytes < p->ws_bytes)
+    return fail(FT_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, p->ws_bytes);
+  return FT_OK;
+}
+
+ft_status validate_shape(int N, int M, int spaces, long long Np) {
+  if (N < 4 || M < 4 || (N & 1) || (M & 1))
+    return fail(FT_ERR_INVALID_ARG, "rows and cols must be even and >= 4 (got %d x %d)", N, M);
+  if (Np > (1 << 20) || M > (1 << 20) || N > (1 << 20))
+    return fail(FT_ERR_UNSUPPORTED_SIZE, "transform length too large");
+  if (!funnel::length_supported((int)Np))
+    return fail(FT_ERR_UNSUPPORTED_SIZE, "no kernel for padded length %lld", Np);
+  if ((spaces & FT_SPACE_REGULAR) && !funnel::length_supported(M))
+    return fail(FT_ERR_UNSUPPORTED_SIZE, "no kernel for row length %d (image width)", M);
+  if ((spaces & FT_SPACE_INVERSE) && !funnel::length_supported(N))
+    return fail(FT_ERR_UNSUPPORTED_SIZE, "no kernel for row length %d (image height)", N);
+  return FT_OK;
+}
+
+size_t class_plane_floats(int spaces, const FtClass& c) {
+  return ((spaces & FT_SPACE_REGULAR) ? (size_t)c.Np * c.M : 0) +
+         ((spaces & FT_SPACE_INVERSE) ? (size_t)c.Np * c.N : 0);
+}
+
+// Shared tail of plan creation: geometry per class, workspace layout, default
+// variants, twiddles, device tables, streams.  offsets: for ragged plans, per
+// class the (image offset, plane offset) of each image; empty for uniform.
+ft_status finish_plan(ft_plan* p, const std::vector<std::vector<std::pair<long long, long long>>>& offsets) {
+  size_t ws = 0, ntw = 0;
+  for (auto& c : p->cls) {
+    c.h = c.Np / 2 - 1;
+    c.off_inv_plane = (p->spaces & FT_SPACE_REGULAR) ? (size_t)c.Np * c.M : 0;
+    c.ws_reg = ws;
+    if (p->spaces & FT_SPACE_REGULAR) ws += align_up((size_t)c.count * c.h * c.M * sizeof(float2), 256);
+    c.ws_inv = ws;
+    if (p->spaces & FT_SPACE_INVERSE) ws += align_up((size_t)c.count * c.h * c.N * sizeof(float2), 256);
+    c.tw_np = ntw;
+    ntw += c.Np;
+    c.tw_m = ntw;
+    ntw += c.M;
+    c.tw_n = ntw;
+    ntw += c.N;
+    for (int r = 0; r < NROLES; ++r) {
+      const unsigned m = role_mask(c, r);
+      c.variant[r] = 0;
+      for (int v = 0; v < funnel::kMaxVariants; ++v)
+        if (m & (1u << v)) {
+          c.variant[r] = v;
+          break;
+        }
+    }
+  }
+  p->ws_bytes = ws;
+
+  int dev = -1, ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(FT_ERR_NO_DEVICE, "no HIP device");
+  if (hipGetDevice(&dev) != hipSuccess) return fail(FT_ERR_NO_DEVICE, "no current HIP device");
+  p->device = dev;
+
+  std::vector<float2> host(ntw);
+  for (auto& c : p->cls) {
+    fill_twiddles(host.data() + c.tw_np, c.Np);
+    fill_twiddles(host.data() + c.tw_m, c.M);
+    fill_twiddles(host.data() + c.tw_n, c.N);
+  }
+  hipError_t e = hipMalloc(&p->tw, ntw * sizeof(float2));
+  if (e != hipSuccess) return fail(FT_ERR_OUT_OF_MEMORY, "hipMalloc of twiddle tables: %s", hipGetErrorString(e));
+  e = hipMemcpy(p->tw, host.data(), ntw * sizeof(float2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy of twiddle tables");
+
+  if (!offsets.empty()) {
+    // one allocation: image offsets, plane offsets (int64) of all classes, then image indices (int32)
+    size_t n = 0;
+    for (auto& c : p->cls) n += c.count;
+    std::vector<long long> l64(2 * n);
+    std::vector<int> i32(n);
+    size_t k = 0;
+    for (size_t ci = 0; ci < p->cls.size(); ++ci)
+      for (size_t j = 0; j < offsets[ci].size(); ++j, ++k) {
+        l64[k] = offsets[ci][j].first;
+        l64[n + k] = offsets[ci][j].second;
+        i32[k] = p->cls[ci].images[j];
+      }
+    const size_t bytes = 2 * n * sizeof(long long) + n * sizeof(int);
+    e = hipMalloc(&p->tables, bytes);
+    if (e != hipSuccess) return fail(FT_ERR_OUT_OF_MEMORY, "hipMalloc of offset tables: %s", hipGetErrorString(e));
+    char* t = static_cast<char*>(p->tables);
+    e = hipMemcpy(t, l64.data(), 2 * n * sizeof(long long), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(t + 2 * n * sizeof(long long), i32.data(), n * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy of offset tables");
+    size_t base = 0;
+    for (auto& c : p->cls) {
+      c.d_img_off = reinterpret_cast<const long long*>(t) + base;
+      c.d_plane_off = reinterpret_cast<const long long*>(t) + n + base;
+      c.d_gidx = reinterpret_cast<const int*>(t + 2 * n * sizeof(long long)) + base;
+      base += c.count;
+    }
+  }
+  if (p->cls.size() > 1) {
+    if (hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess)
+      return fail(FT_ERR_HIP, "hipEventCreate failed");
+    for (auto& c : p->cls)
+      if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&c.done, hipEventDisableTiming) != hipSuccess)
+        return fail(FT_ERR_HIP, "stream or event creation failed");
+  }
+  return FT_OK;
 }
 
 }  // namespace
@@ -152,87 +406,97 @@ ft_status funnel_plan_create(const ft_plan_desc* d, ft_plan** out) {
   if (d->precision != FT_PREC_FP32) return fail(FT_ERR_INVALID_ARG, "unknown precision %d", d->precision);
   if (d->flags != 0) return fail(FT_ERR_INVALID_ARG, "unknown plan flags 0x%x", d->flags);
   const long long N = d->rows, M = d->cols;
-  long long Np = d->padded_len == 0 ? N + M : d->padded_len;
+  const long long Np = d->padded_len == 0 ? N + M : d->padded_len;
   if (d->padded_len < 0 || (Np & 1) || Np < N + M)
     return fail(FT_ERR_INVALID_ARG, "padded_len must be 0 or even and >= rows+cols (got %d)", d->padded_len);
-  if (Np > (1 << 20) || M > (1 << 20) || N > (1 << 20))
-    return fail(FT_ERR_UNSUPPORTED_SIZE, "transform length too large");
-  const bool reg = d->spaces & FT_SPACE_REGULAR, inv = d->spaces & FT_SPACE_INVERSE;
-  if (!funnel::length_supported((int)Np))
-    return fail(FT_ERR_UNSUPPORTED_SIZE, "no kernel for padded length %lld", Np);
-  if (reg && !funnel::length_supported((int)M))
-    return fail(FT_ERR_UNSUPPORTED_SIZE, "no kernel for row length %lld (image width)", M);
-  if (inv && !funnel::length_supported((int)N))
-    return fail(FT_ERR_UNSUPPORTED_SIZE, "no kernel for row length %lld (image height)", N);
-  const long long h = Np / 2 - 1;
-  const long long plane_elems = (reg ? Np * M : 0) + (inv ? Np * N : 0);
-  if ((long long)d->batch * plane_elems > (1ll << 40))
-    return fail(FT_ERR_INVALID_ARG, "batch too large");
-
-  int dev = -1, ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(FT_ERR_NO_DEVICE, "no HIP device");
-  if (hipGetDevice(&dev) != hipSuccess) return fail(FT_ERR_NO_DEVICE, "no current HIP device");
+  ft_status st = validate_shape((int)N, (int)M, d->spaces, Np);
+  if (st != FT_OK) return st;
 
   ft_plan* p = new (std::nothrow) ft_plan();
   if (!p) return fail(FT_ERR_OUT_OF_MEMORY, "host allocation failed");
-  p->device = dev;
-  p->batch = d->batch;
-  p->N = (int)N;
-  p->M = (int)M;
-  p->Np = (int)Np;
-  p->h = (int)h;
   p->spaces = d->spaces;
-  p->plane_elems = (size_t)plane_elems;
-  p->off_inv_plane = reg ? (size_t)(Np * M) : 0;
-  const size_t s_reg = reg ? align_up((size_t)d->batch * h * M * sizeof(float2), 256) : 0;
-  const size_t s_inv = inv ? align_up((size_t)d->batch * h * N * sizeof(float2), 256) : 0;
-  p->ws_off_inv = s_reg;
-  p->ws_bytes = s_reg + s_inv;
-
-  // default tile variants: the lowest-numbered one each kernel has
-  for (int r = 0; r < NROLES; ++r) {
-    const unsigned m = role_mask(p, r);
-    p->variant[r] = 0;
-    for (int v = 0; v < funnel::kMaxVariants; ++v)
-      if (m & (1u << v)) { p->variant[r] = v; break; }
+  p->batch = d->batch;
+  p->cls.resize(1);
+  FtClass& c = p->cls[0];
+  c.N = (int)N;
+  c.M = (int)M;
+  c.Np = (int)Np;
+  c.count = d->batch;
+  p->plane_elems = class_plane_floats(p->spaces, c);
+  c.img_stride = N * M;
+  c.plane_stride = (long long)p->plane_elems;
+  p->image_extent = (size_t)d->batch * N * M;
+  p->plane_extent = (size_t)d->batch * p->plane_elems;
+  if ((long long)p->plane_extent > (1ll << 40)) {
+    free_plan(p);
+    return fail(FT_ERR_INVALID_ARG, "batch too large");
   }
-
-  // twiddle tables for Np, M and N, back to back
-  p->tw_np = 0;
-  p->tw_m = (size_t)Np;
-  p->tw_n = p->tw_m + (size_t)M;
-  const size_t ntw = p->tw_n + (size_t)N;
-  float2* host = new (std::nothrow) float2[ntw];
-  if (!host) {
-    delete p;
-    return fail(FT_ERR_OUT_OF_MEMORY, "host allocation failed");
-  }
-  fill_twiddles(host + p->tw_np, (int)Np);
-  fill_twiddles(host + p->tw_m, (int)M);
-  fill_twiddles(host + p->tw_n, (int)N);
-  hipError_t e = hipMalloc(&p->tw, ntw * sizeof(float2));
-  if (e != hipSuccess) {
-    delete[] host;
-    delete p;
-    return fail(FT_ERR_OUT_OF_MEMORY, "hipMalloc of twiddle tables: %s", hipGetErrorString(e));
-  }
-  e = hipMemcpy(p->tw, host, ntw * sizeof(float2), hipMemcpyHostToDevice);
-  delete[] host;
-  if (e != hipSuccess) {
-    (void)hipFree(p->tw);
-    delete p;
-    return hip_fail(e, "hipMemcpy of twiddle tables");
+  st = finish_plan(p, {});
+  if (st != FT_OK) {
+    free_plan(p);
+    return st;
   }
   *out = p;
   return ok();
 }
 
-void funnel_plan_destroy(ft_plan* p) {
-  if (!p) return;
-  free_profiler(p->prof);
-  if (p->tw) (void)hipFree(p->tw);
-  delete p;
+ft_status funnel_plan_create_ragged(const ft_image_desc* images, int32_t count, int32_t spaces, ft_plan** out) {
+  if (!images || !out) return fail(FT_ERR_INVALID_ARG, "images and out must be non-NULL");
+  *out = nullptr;
+  if (count < 1) return fail(FT_ERR_INVALID_ARG, "count must be >= 1 (got %d)", count);
+  if (spaces < FT_SPACE_REGULAR || spaces > FT_SPACE_BOTH)
+    return fail(FT_ERR_INVALID_ARG, "spaces must be 1, 2 or 3 (got %d)", spaces);
+  std::map<std::pair<int, int>, int> index;
+  std::vector<std::vector<std::pair<long long, long long>>> offs;
+  ft_plan* p = new (std::nothrow) ft_plan();
+  if (!p) return fail(FT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  p->spaces = spaces;
+  p->batch = count;
+  p->ragged = true;
+  for (int i = 0; i < count; ++i) {
+    const ft_image_desc& d = images[i];
+    ft_status st = validate_shape(d.rows, d.cols, spaces, (long long)d.rows + d.cols);
+    if (st == FT_OK && (d.image_offset < 0 || d.plane_offset < 0 || (d.image_offset & 3) || (d.plane_offset & 3)))
+      st = fail(FT_ERR_MISALIGNED, "offsets must be non-negative multiples of 4 floats");
+    if (st != FT_OK) {
+      const std::string m = g_err;
+      free_plan(p);
+      return fail(st, "image %d: %s", i, m.c_str());
+    }
+    const auto key = std::make_pair(d.rows, d.cols);
+    auto it = index.find(key);
+    int ci;
+    if (it == index.end()) {
+      ci = (int)p->cls.size();
+      index[key] = ci;
+      p->cls.emplace_back();
+      offs.emplace_back();
+      FtClass& c = p->cls.back();
+      c.N = d.rows;
+      c.M = d.cols;
+      c.Np = d.rows + d.cols;
+    } else {
+      ci = it->second;
+    }
+    FtClass& c = p->cls[ci];
+    c.images.push_back(i);
+    c.count += 1;
+    offs[ci].emplace_back(d.image_offset, d.plane_offset);
+    const size_t pf = class_plane_floats(spaces, c);
+    p->image_extent = std::max(p->image_extent, (size_t)d.image_offset + (size_t)d.rows * d.cols);
+    p->plane_extent = std::max(p->plane_extent, (size_t)d.plane_offset + pf);
+  }
+  p->plane_elems = p->plane_extent;
+  ft_status st = finish_plan(p, offs);
+  if (st != FT_OK) {
+    free_plan(p);
+    return st;
+  }
+  *out = p;
+  return ok();
 }
+
+void funnel_plan_destroy(ft_plan* p) { free_plan(p); }
 
 ft_status funnel_workspace_size(const ft_plan* p, size_t* bytes) {
   if (!p || !bytes) return fail(FT_ERR_INVALID_ARG, "plan and bytes must be non-NULL");
@@ -246,89 +510,17 @@ ft_status funnel_plane_elems(const ft_plan* p, size_t* n) {
   return ok();
 }
 
-ft_status funnel_padded_len(const ft_plan* p, int32_t* np) {
-  if (!p || !np) return fail(FT_ERR_INVALID_ARG, "plan and out must be non-NULL");
-  *np = p->Np;
+ft_status funnel_buffer_elems(const ft_plan* p, size_t* image_floats, size_t* plane_floats) {
+  if (!p || !image_floats || !plane_floats) return fail(FT_ERR_INVALID_ARG, "pointers must be non-NULL");
+  *image_floats = p->image_extent;
+  *plane_floats = p->plane_extent;
   return ok();
 }
 
-static ft_status check_call(const ft_plan* p, const void* a, const void* b, const void* ws, size_t ws_bytes) {
-  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
-  if (!a || !b || !ws) return fail(FT_ERR_INVALID_ARG, "input, output and workspace must be non-NULL");
-  if (!aligned16(a) || !aligned16(b) || !aligned16(ws))
-    return fail(FT_ERR_MISALIGNED, "device pointers must be 16-byte aligned");
-  if (ws_bytes < p->ws_bytes)
-    return fail(FT_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, p->ws_bytes);
-  return FT_OK;
-}
-
-// Algorithmic HBM bytes of one launch: each input read once, each output
-// written once (a read-modify-write output counts twice).
-static double role_bytes(const ft_plan* p, int r) {
-  const double B = p->batch, N = p->N, M = p->M, Np = p->Np, h = p->h;
-  const double W = role_regular(r) ? M : N;  // lines of the spectrum
-  switch (r) {
-    case FA_REG: case FA_INV: return B * (4.0 * N * M + 8.0 * h * W);
-    case FB_REG: case FB_INV: case AB_REG: case AB_INV: return B * 16.0 * h * W;
-    case FC_REG: case FC_INV: return B * (8.0 * h * W + 4.0 * Np * W);
-    case AC_REG: case AC_INV: return B * (4.0 * Np * W + 8.0 * h * W);
-    case AA_REG: return B * (8.0 * h * M + 4.0 * N * M);
-    case AA_INV: return B * (8.0 * h * N + ((p->spaces & FT_SPACE_REGULAR) ? 8.0 : 4.0) * N * M);
-  }
-  return 0.0;
-}
-
-// One pass launch.  src: images (forward) or plane gradients (adjoint);
-// dst: planes (forward) or image gradients (adjoint).
-static hipError_t run_role(const ft_plan* p, int r, int v, const float* src, float* dst, char* w, hipStream_t s) {
-  const int B = p->batch, N = p->N, M = p->M, Np = p->Np, h = p->h;
-  const long long img = (long long)N * M, pst = (long long)p->plane_elems;
-  const float2* tw_np = p->tw + p->tw_np;
-  float2* Sr = reinterpret_cast<float2*>(w);
-  float2* Si = reinterpret_cast<float2*>(w + p->ws_off_inv);
-  const long long sr = (long long)h * M, si = (long long)h * N;
-  const bool reg = p->spaces & FT_SPACE_REGULAR;
-  switch (r) {
-    // forward, regular space: y DFT of the image columns on the expanded frame,
-    // NVMT + x' DFT per frequency row, Hermitian inverse y DFT
-    case FA_REG: return funnel::launch_r2c(Np, v, false, src, Sr, M, N, (Np - N) / 2, img, sr, 1.0f, tw_np, B, s);
-    case FB_REG: return funnel::launch_row(M, v, false, Sr, Np, h, sr, p->tw + p->tw_m, B, s);
-    case FC_REG:
-      return funnel::launch_c2r(Np, v, false, false, Sr, dst, M, 0, Np, sr, pst, 1.0f / Np, tw_np, B, s);
-    // forward, inverse space: the same on the transposed image (rows read directly)
-    case FA_INV: return funnel::launch_r2c(Np, v, true, src, Si, N, M, (Np - M) / 2, img, si, 1.0f, tw_np, B, s);
-    case FB_INV: return funnel::launch_row(N, v, false, Si, Np, h, si, p->tw + p->tw_n, B, s);
-    case FC_INV:
-      return funnel::launch_c2r(Np, v, false, false, Si, dst + p->off_inv_plane, N, 0, Np, si, pst, 1.0f / Np,
-                                tw_np, B, s);
-    // adjoint, regular space: (2/Np) y DFT of the plane columns, conjugate x'
-    // DFT + transposed interpolation, real part of the conjugate y DFT cropped
-    case AC_REG: return funnel::launch_r2c(Np, v, false, src, Sr, M, Np, 0, pst, sr, 2.0f / Np, tw_np, B, s);
-    case AB_REG: return funnel::launch_row(M, v, true, Sr, Np, h, sr, p->tw + p->tw_m, B, s);
-    case AA_REG:
-      return funnel::launch_c2r(Np, v, false, false, Sr, dst, M, (Np - N) / 2, N, sr, img, 0.5f, tw_np, B, s);
-    // adjoint, inverse space: transposed write into the image rows, added to
-    // the regular space's result when both spaces are computed
-    case AC_INV:
-      return funnel::launch_r2c(Np, v, false, src + p->off_inv_plane, Si, N, Np, 0, pst, si, 2.0f / Np, tw_np, B,
-                                s);
-    case AB_INV: return funnel::launch_row(N, v, true, Si, Np, h, si, p->tw + p->tw_n, B, s);
-    case AA_INV:
-      return funnel::launch_c2r(Np, v, true, reg, Si, dst, N, (Np - M) / 2, M, si, img, 0.5f, tw_np, B, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-static ft_status run_roles(const ft_plan* p, int first, int last, const float* src, float* dst, void* ws,
-                           hipStream_t s) {
-  (void)hipGetLastError();
-  char* w = static_cast<char*>(ws);
-  for (int r = first; r <= last; ++r) {
-    if (!role_active(p, r)) continue;
-    hipError_t e = timed(p, s, kRoleName[r], role_bytes(p, r),
-                         [&] { return run_role(p, r, p->variant[r], src, dst, w, s); });
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
-  }
+ft_status funnel_padded_len(const ft_plan* p, int32_t* np) {
+  if (!p || !np) return fail(FT_ERR_INVALID_ARG, "plan and out must be non-NULL");
+  if (p->ragged) return fail(FT_ERR_INVALID_ARG, "a ragged plan has one padded length per size class");
+  *np = p->cls[0].Np;
   return ok();
 }
 
@@ -337,7 +529,11 @@ ft_status funnel_forward(const ft_plan* p, const float* images, float* planes, v
   ft_status st = check_call(p, images, planes, ws, ws_bytes);
   if (st != FT_OK) return st;
   if ((st = check_device(p)) != FT_OK) return st;
-  return run_roles(p, FA_REG, FC_INV, images, planes, ws, static_cast<hipStream_t>(stream));
+  (void)hipGetLastError();
+  hipError_t e = enqueue_roles(p, FA_REG, FC_INV, images, planes, static_cast<char*>(ws),
+                               static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return ok();
 }
 
 ft_status funnel_adjoint(const ft_plan* p, const float* d_planes, float* d_images, void* ws, size_t ws_bytes,
@@ -345,8 +541,68 @@ ft_status funnel_adjoint(const ft_plan* p, const float* d_planes, float* d_image
   ft_status st = check_call(p, d_planes, d_images, ws, ws_bytes);
   if (st != FT_OK) return st;
   if ((st = check_device(p)) != FT_OK) return st;
-  return run_roles(p, AC_REG, AA_INV, d_planes, d_images, ws, static_cast<hipStream_t>(stream));
+  (void)hipGetLastError();
+  hipError_t e = enqueue_roles(p, AC_REG, AA_INV, d_planes, d_images, static_cast<char*>(ws),
+                               static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return ok();
 }
+
+// ------------------------------------------------------------------ graphs
+
+ft_status funnel_graph_create(const ft_plan* p, uint32_t what, const float* images, float* planes,
+                              const float* d_planes, float* d_images, void* ws, size_t ws_bytes, ft_graph** out) {
+  if (!p || !out) return fail(FT_ERR_INVALID_ARG, "plan and out must be non-NULL");
+  *out = nullptr;
+  if (what == 0 || (what & ~(uint32_t)(FT_GRAPH_FORWARD | FT_GRAPH_ADJOINT)))
+    return fail(FT_ERR_INVALID_ARG, "what must combine FT_GRAPH_FORWARD and FT_GRAPH_ADJOINT");
+  ft_status st = FT_OK;
+  if (what & FT_GRAPH_FORWARD) st = check_call(p, images, planes, ws, ws_bytes);
+  if (st == FT_OK && (what & FT_GRAPH_ADJOINT)) st = check_call(p, d_planes, d_images, ws, ws_bytes);
+  if (st != FT_OK) return st;
+  if ((st = check_device(p)) != FT_OK) return st;
+  if (p->prof) return fail(FT_ERR_INVALID_ARG, "disable profiling before capturing a graph");
+  ft_graph* g = new (std::nothrow) ft_graph();
+  if (!g) return fail(FT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  g->device = p->device;
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  hipError_t le = hipSuccess;
+  if (e == hipSuccess) {
+    if (what & FT_GRAPH_FORWARD) le = enqueue_roles(p, FA_REG, FC_INV, images, planes, static_cast<char*>(ws), cs);
+    if (le == hipSuccess && (what & FT_GRAPH_ADJOINT))
+      le = enqueue_roles(p, AC_REG, AA_INV, d_planes, d_images, static_cast<char*>(ws), cs);
+    e = hipStreamEndCapture(cs, &g->graph);
+  }
+  if (e == hipSuccess && le == hipSuccess) e = hipGraphInstantiateWithFlags(&g->exec, g->graph, 0);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (e != hipSuccess || le != hipSuccess) {
+    funnel_graph_destroy(g);
+    return hip_fail(le != hipSuccess ? le : e, "graph capture");
+  }
+  *out = g;
+  return ok();
+}
+
+ft_status funnel_graph_launch(const ft_graph* g, void* stream) {
+  if (!g || !g->exec) return fail(FT_ERR_INVALID_ARG, "graph is NULL");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != g->device)
+    return fail(FT_ERR_NO_DEVICE, "graph was built on device %d", g->device);
+  hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return ok();
+}
+
+void funnel_graph_destroy(ft_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+// ------------------------------------------------------------------ tuning
 
 ft_status funnel_autotune(ft_plan* p, void* stream, ft_tune_result* out, int32_t cap, int32_t* n) {
   if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
@@ -354,8 +610,8 @@ ft_status funnel_autotune(ft_plan* p, void* stream, ft_tune_result* out, int32_t
   ft_status st = check_device(p);
   if (st != FT_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t img_bytes = (size_t)p->batch * p->N * p->M * sizeof(float);
-  const size_t pl_bytes = (size_t)p->batch * p->plane_elems * sizeof(float);
+  const size_t big = std::max(p->image_extent, p->plane_extent) * sizeof(float);
+  const size_t wsb = p->ws_bytes ? p->ws_bytes : 256;
   void *a = nullptr, *b = nullptr, *w = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   auto cleanup = [&] {
@@ -365,63 +621,63 @@ ft_status funnel_autotune(ft_plan* p, void* stream, ft_tune_result* out, int32_t
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
   };
-  // a holds images or plane gradients, b planes or image gradients: size both for the larger
-  const size_t big = img_bytes > pl_bytes ? img_bytes : pl_bytes;
-  if (hipMalloc(&a, big) != hipSuccess || hipMalloc(&b, big) != hipSuccess ||
-      hipMalloc(&w, p->ws_bytes ? p->ws_bytes : 256) != hipSuccess) {
+  if (hipMalloc(&a, big) != hipSuccess || hipMalloc(&b, big) != hipSuccess || hipMalloc(&w, wsb) != hipSuccess) {
     cleanup();
     return fail(FT_ERR_OUT_OF_MEMORY, "autotune scratch allocation failed");
   }
   if (hipMemsetAsync(a, 0, big, s) != hipSuccess || hipMemsetAsync(b, 0, big, s) != hipSuccess ||
-      hipMemsetAsync(w, 0, p->ws_bytes ? p->ws_bytes : 256, s) != hipSuccess ||
-      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      hipMemsetAsync(w, 0, wsb, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
     cleanup();
     return fail(FT_ERR_HIP, "autotune set-up failed");
   }
   FtProfiler* saved = p->prof;
   p->prof = nullptr;
   int count = 0;
-  for (int r = 0; r < NROLES; ++r) {
-    if (!role_active(p, r)) continue;
-    const unsigned mask = role_mask(p, r);
-    float best = 1e30f, first_ms = -1.f;
-    int best_v = p->variant[r], tried = 0;
-    for (int v = 0; v < funnel::kMaxVariants; ++v) {
-      if (!(mask & (1u << v))) continue;
-      float ms_min = 1e30f;
-      hipError_t e = hipSuccess;
-      for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
-        e = hipEventRecord(e0, s);
-        if (e == hipSuccess) e = run_role(p, r, v, static_cast<float*>(a), static_cast<float*>(b),
-                                          static_cast<char*>(w), s);
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e == hipSuccess && rep > 0 && ms < ms_min) ms_min = ms;
+  for (size_t ci = 0; ci < p->cls.size(); ++ci) {
+    FtClass& c = p->cls[ci];
+    for (int r = 0; r < NROLES; ++r) {
+      if (!role_active(p, r)) continue;
+      const unsigned mask = role_mask(c, r);
+      float best = 1e30f, first_ms = -1.f;
+      int best_v = c.variant[r], tried = 0;
+      for (int v = 0; v < funnel::kMaxVariants; ++v) {
+        if (!(mask & (1u << v))) continue;
+        float ms_min = 1e30f;
+        hipError_t e = hipSuccess;
+        for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+          e = hipEventRecord(e0, s);
+          if (e == hipSuccess)
+            e = run_role(p, c, r, v, static_cast<float*>(a), static_cast<float*>(b), static_cast<char*>(w), s);
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e == hipSuccess && rep > 0 && ms < ms_min) ms_min = ms;
+        }
+        if (e != hipSuccess) {
+          p->prof = saved;
+          cleanup();
+          return hip_fail(e, "autotune launch");
+        }
+        if (v == c.variant[r]) first_ms = ms_min;
+        ++tried;
+        if (ms_min < best) {
+          best = ms_min;
+          best_v = v;
+        }
       }
-      if (e != hipSuccess) {
-        p->prof = saved;
-        cleanup();
-        return hip_fail(e, "autotune launch");
+      c.variant[r] = best_v;
+      if (count < cap) {
+        std::memset(&out[count], 0, sizeof(ft_tune_result));
+        std::snprintf(out[count].name, sizeof(out[count].name), "%s", role_label(p, (int)ci, r).c_str());
+        out[count].variant = best_v;
+        out[count].n_tried = tried;
+        out[count].ms = best;
+        out[count].ms_default = first_ms;
       }
-      if (v == p->variant[r]) first_ms = ms_min;
-      ++tried;
-      if (ms_min < best) {
-        best = ms_min;
-        best_v = v;
-      }
+      ++count;
     }
-    p->variant[r] = best_v;
-    if (count < cap) {
-      std::memset(&out[count], 0, sizeof(ft_tune_result));
-      std::snprintf(out[count].name, sizeof(out[count].name), "%s", kRoleName[r]);
-      out[count].variant = best_v;
-      out[count].n_tried = tried;
-      out[count].ms = best;
-      out[count].ms_default = first_ms;
-    }
-    ++count;
   }
   p->prof = saved;
   cleanup();
@@ -431,18 +687,30 @@ ft_status funnel_autotune(ft_plan* p, void* stream, ft_tune_result* out, int32_t
 
 ft_status funnel_plan_variants(const ft_plan* p, int32_t* variants, int32_t cap) {
   if (!p || !variants || cap < 1) return fail(FT_ERR_INVALID_ARG, "plan and variants must be non-NULL");
-  for (int r = 0; r < NROLES && r < cap; ++r) variants[r] = role_active(p, r) ? p->variant[r] : -1;
+  int k = 0;
+  for (const auto& c : p->cls)
+    for (int r = 0; r < NROLES && k < cap; ++r, ++k) variants[k] = role_active(p, r) ? c.variant[r] : -1;
   return ok();
 }
 
 ft_status funnel_plan_set_variant(ft_plan* p, int32_t role, int32_t variant) {
   if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
-  if (role < 0 || role >= NROLES) return fail(FT_ERR_INVALID_ARG, "role must be in 0..%d", NROLES - 1);
-  if (variant < 0 || variant >= funnel::kMaxVariants || !(role_mask(p, role) & (1u << variant)))
-    return fail(FT_ERR_INVALID_ARG, "variant %d has no kernel for role %s", variant, kRoleName[role]);
-  p->variant[role] = variant;
+  if (role < 0 || role >= (int)p->cls.size() * NROLES)
+    return fail(FT_ERR_INVALID_ARG, "role must be in 0..%d", (int)p->cls.size() * NROLES - 1);
+  const int ci = role / NROLES, r = role % NROLES;
+  if (variant < 0 || variant >= funnel::kMaxVariants || !(role_mask(p->cls[ci], r) & (1u << variant)))
+    return fail(FT_ERR_INVALID_ARG, "variant %d has no kernel for role %s", variant, kRoleName[r]);
+  p->cls[ci].variant[r] = variant;
   return ok();
 }
+
+ft_status funnel_plan_classes(const ft_plan* p, int32_t* n) {
+  if (!p || !n) return fail(FT_ERR_INVALID_ARG, "plan and n must be non-NULL");
+  *n = (int32_t)p->cls.size();
+  return ok();
+}
+
+// ------------------------------------------------------------------ timing
 
 ft_status funnel_profile_enable(ft_plan* p, int32_t max_records) {
   if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
@@ -455,7 +723,7 @@ ft_status funnel_profile_enable(ft_plan* p, int32_t max_records) {
   pr->cap = max_records;
   pr->ev0.resize(max_records);
   pr->ev1.resize(max_records);
-  pr->name.assign(max_records, nullptr);
+  pr->name.assign(max_records, std::string());
   pr->bytes.assign(max_records, 0.0);
   for (int i = 0; i < max_records; ++i) {
     if (hipEventCreate(&pr->ev0[i]) != hipSuccess || hipEventCreate(&pr->ev1[i]) != hipSuccess) {
@@ -483,11 +751,11 @@ ft_status funnel_profile_read(ft_plan* p, ft_kernel_time* out, int32_t cap, int3
     e = hipEventElapsedTime(&ms, pr->ev0[i], pr->ev1[i]);
     if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
     int k = 0;
-    while (k < cnt && std::strcmp(out[k].name, pr->name[i]) != 0) ++k;
+    while (k < cnt && pr->name[i] != out[k].name) ++k;
     if (k == cnt) {
       if (cnt == cap) continue;
       std::memset(&out[k], 0, sizeof(ft_kernel_time));
-      std::snprintf(out[k].name, sizeof(out[k].name), "%s", pr->name[i]);
+      std::snprintf(out[k].name, sizeof(out[k].name), "%s", pr->name[i].c_str());
       out[k].bytes_per_launch = pr->bytes[i];
       ++cnt;
     }
@@ -506,17 +774,20 @@ ft_status funnel_profile_disable(ft_plan* p) {
   return ok();
 }
 
+// ------------------------------------------------------------------ peaks
+
 ft_status funnel_peaks_workspace_size(const ft_plan* p, int32_t K, size_t* bytes) {
   if (!p || !bytes) return fail(FT_ERR_INVALID_ARG, "plan and bytes must be non-NULL");
   if (K < 1 || K > 256) return fail(FT_ERR_INVALID_ARG, "K must be in 1..256 (got %d)", K);
   const int ns = (p->spaces == FT_SPACE_BOTH) ? 2 : 1;
-  int tiles = 0;
-  if (p->spaces & FT_SPACE_REGULAR) tiles = funnel::peaks_tiles(p->Np, p->M);
-  if (p->spaces & FT_SPACE_INVERSE) {
-    const int t = funnel::peaks_tiles(p->Np, p->N);
-    tiles = t > tiles ? t : tiles;
+  size_t total = 0;
+  for (const auto& c : p->cls) {
+    int tiles = 0;
+    if (p->spaces & FT_SPACE_REGULAR) tiles = funnel::peaks_tiles(c.Np, c.M);
+    if (p->spaces & FT_SPACE_INVERSE) tiles = std::max(tiles, funnel::peaks_tiles(c.Np, c.N));
+    total += align_up(funnel::peaks_workspace_bytes(c.count * ns, tiles, K), 256);
   }
-  *bytes = funnel::peaks_workspace_bytes(p->batch * ns, tiles, K);
+  *bytes = total;
   return ok();
 }
 
@@ -537,19 +808,36 @@ ft_status funnel_peaks(const ft_plan* p, const float* planes, int32_t K, float t
   if (ws_bytes < need) return fail(FT_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
   if ((st = check_device(p)) != FT_OK) return st;
   (void)hipGetLastError();
-  int rows[2], cols[2], himg[2];
-  long long off[2];
-  int ns = 0;
-  if (p->spaces & FT_SPACE_REGULAR) {
-    rows[ns] = p->Np; cols[ns] = p->M; himg[ns] = p->N; off[ns] = 0; ++ns;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ns = (p->spaces == FT_SPACE_BOTH) ? 2 : 1;
+  const bool fork = p->cls.size() > 1;
+  hipError_t e = hipSuccess;
+  if (fork) e = hipEventRecord(p->fork, s);
+  char* w = static_cast<char*>(ws);
+  for (size_t ci = 0; ci < p->cls.size() && e == hipSuccess; ++ci) {
+    const FtClass& c = p->cls[ci];
+    hipStream_t cs = fork ? c.stream : s;
+    if (fork) e = hipStreamWaitEvent(cs, p->fork, 0);
+    int rows[2], cols[2], himg[2], tiles = 0, k = 0;
+    long long off[2];
+    if (p->spaces & FT_SPACE_REGULAR) {
+      rows[k] = c.Np; cols[k] = c.M; himg[k] = c.N; off[k] = 0; ++k;
+      tiles = funnel::peaks_tiles(c.Np, c.M);
+    }
+    if (p->spaces & FT_SPACE_INVERSE) {
+      rows[k] = c.Np; cols[k] = c.N; himg[k] = c.M; off[k] = (long long)c.off_inv_plane; ++k;
+      tiles = std::max(tiles, funnel::peaks_tiles(c.Np, c.N));
+    }
+    const funnel::ImgMap map{0, c.plane_stride, nullptr, c.d_plane_off};
+    if (e == hipSuccess)
+      e = funnel::launch_peaks(planes, map, c.d_gidx, c.count, ns, rows, cols, himg, off, K, threshold, radius,
+                               (flags & FT_PEAK_CLAMP_BORDER) ? 0 : 1, (flags & FT_PEAK_KEEP_PAD_BOUNDARY) ? 1 : 0,
+                               peaks, n_found, w, cs);
+    w += align_up(funnel::peaks_workspace_bytes(c.count * ns, tiles, K), 256);
+    if (fork && e == hipSuccess) e = hipEventRecord(c.done, cs);
   }
-  if (p->spaces & FT_SPACE_INVERSE) {
-    rows[ns] = p->Np; cols[ns] = p->N; himg[ns] = p->M; off[ns] = (long long)p->off_inv_plane; ++ns;
-  }
-  hipError_t e = funnel::launch_peaks(planes, (long long)p->plane_elems, p->batch, ns, rows, cols, himg, off, K,
-                                      threshold, radius, (flags & FT_PEAK_CLAMP_BORDER) ? 0 : 1,
-                                      (flags & FT_PEAK_KEEP_PAD_BOUNDARY) ? 1 : 0, peaks, n_found, ws,
-                                      static_cast<hipStream_t>(stream));
+  for (size_t ci = 0; fork && ci < p->cls.size() && e == hipSuccess; ++ci)
+    e = hipStreamWaitEvent(s, p->cls[ci].done, 0);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return ok();
 }

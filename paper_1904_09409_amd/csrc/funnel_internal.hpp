@@ -9,6 +9,16 @@
 
 namespace funnel {
 
+// Where image i's input and output start (elements): uniform strides, or
+// per-image offset tables in device memory (ragged batches).
+struct ImgMap {
+  long long in_stride, out_stride;
+  const long long* in_off;
+  const long long* out_off;
+  __host__ __device__ long long in(int i) const { return in_off ? in_off[i] : (long long)i * in_stride; }
+  __host__ __device__ long long out(int i) const { return out_off ? out_off[i] : (long long)i * out_stride; }
+};
+
 bool length_supported(int L);
 
 // bit v set: tile variant v has a kernel for this length (bit 0 alone: the
@@ -19,13 +29,11 @@ constexpr int kMaxVariants = 8;
 
 // real lines (zero-padded to L) -> half spectrum rows 1..L/2-1, times scale*(-1)^k
 hipError_t launch_r2c(int L, int variant, bool trans, const float* in, float2* out, int nlines, int lin, int off,
-                      long long in_img, long long out_img, float scale, const float2* tw, int batch,
-                      hipStream_t s);
+                      ImgMap map, float scale, const float2* tw, int batch, hipStream_t s);
 
 // half spectrum rows 1..L/2-1 -> real lines, rows [r0, r0+nout) stored (or added)
-hipError_t launch_c2r(int L, int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0, int nout,
-                      long long in_img, long long out_img, float scale, const float2* tw, int batch,
-                      hipStream_t s);
+hipError_t launch_c2r(int L, int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0,
+                      int nout, ImgMap map, float scale, const float2* tw, int batch, hipStream_t s);
 
 // per frequency row: NVMT gather + DFT along x' (forward) or its transpose (adjoint), in place
 hipError_t launch_row(int M, int variant, bool adj, float2* data, int Lp, int h, long long img_stride, const float2* tw,
@@ -33,7 +41,7 @@ hipError_t launch_row(int M, int variant, bool adj, float2* data, int Lp, int h,
 
 size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K);
 int peaks_tiles(int rows, int cols);
-hipError_t launch_peaks(const float* planes, long long plane_stride, int batch, int nspaces, const int* rows,
+hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int batch, int nspaces, const int* rows,
                         const int* cols, const int* himg, const long long* offset, int K, float thr, int radius,
                         int wrap, int keep_border, ft_peak* peaks, int32_t* n_found, void* ws, hipStream_t s);
 

@@ -13,12 +13,10 @@ template <int M>
 unsigned row_variant_mask_t();
 template <int L>
 hipError_t launch_r2c_t(int variant, bool trans, const float* in, float2* out, int nlines, int lin, int off,
-                        long long in_img, long long out_img, float scale, const float2* tw, int batch,
-                        hipStream_t s);
+                        ImgMap map, float scale, const float2* tw, int batch, hipStream_t s);
 template <int L>
 hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0,
-                        int nout, long long in_img, long long out_img, float scale, const float2* tw, int batch,
-                        hipStream_t s);
+                        int nout, ImgMap map, float scale, const float2* tw, int batch, hipStream_t s);
 template <int M>
 hipError_t launch_row_t(int variant, bool adj, float2* data, int Lp, int h, long long img_stride,
                         const float2* tw, int batch, hipStream_t s);
@@ -51,24 +49,22 @@ unsigned row_variant_mask(int M) {
 }
 
 hipError_t launch_r2c(int L, int variant, bool trans, const float* in, float2* out, int nlines, int lin, int off,
-                      long long in_img, long long out_img, float scale, const float2* tw, int batch,
-                      hipStream_t s) {
+                      ImgMap map, float scale, const float2* tw, int batch, hipStream_t s) {
   switch (L) {
 #define CASE(n) \
-  case n: return launch_r2c_t<n>(variant, trans, in, out, nlines, lin, off, in_img, out_img, scale, tw, batch, s);
+  case n: return launch_r2c_t<n>(variant, trans, in, out, nlines, lin, off, map, scale, tw, batch, s);
     FUNNEL_LENGTHS(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_c2r(int L, int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0, int nout,
-                      long long in_img, long long out_img, float scale, const float2* tw, int batch,
-                      hipStream_t s) {
+hipError_t launch_c2r(int L, int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0,
+                      int nout, ImgMap map, float scale, const float2* tw, int batch, hipStream_t s) {
   switch (L) {
 #define CASE(n)                                                                                         \
   case n:                                                                                               \
-    return launch_c2r_t<n>(variant, trans, accum, in, out, nlines, r0, nout, in_img, out_img, scale, tw, batch, s);
+    return launch_c2r_t<n>(variant, trans, accum, in, out, nlines, r0, nout, map, scale, tw, batch, s);
     FUNNEL_LENGTHS(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;

@@ -6,10 +6,10 @@ namespace funnel {
 #define INST(n)                                                                                              \
   template unsigned col_variant_mask_t<n>();                                                                 \
   template unsigned row_variant_mask_t<n>();                                                                 \
-  template hipError_t launch_r2c_t<n>(int, bool, const float*, float2*, int, int, int, long long, long long,  \
-                                      float, const float2*, int, hipStream_t);                               \
-  template hipError_t launch_c2r_t<n>(int, bool, bool, const float2*, float*, int, int, int, long long,      \
-                                      long long, float, const float2*, int, hipStream_t);                    \
+  template hipError_t launch_r2c_t<n>(int, bool, const float*, float2*, int, int, int, ImgMap, float,       \
+                                      const float2*, int, hipStream_t);                               \
+  template hipError_t launch_c2r_t<n>(int, bool, bool, const float2*, float*, int, int, int, ImgMap, float,  \
+                                      const float2*, int, hipStream_t);                    \
   template hipError_t launch_row_t<n>(int, bool, float2*, int, int, long long, const float2*, int, hipStream_t);
 FUNNEL_LENGTHS_G3(INST)
 #undef INST

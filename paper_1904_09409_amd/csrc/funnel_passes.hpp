@@ -21,6 +21,7 @@
 
 #include "fft_core.hpp"
 #include "funnel_internal.hpp"
+#include "funnel_internal.hpp"
 
 namespace funnel {
 
@@ -63,7 +64,7 @@ struct RowCfg {
 template <int L, bool TRANS>
 __global__ void __launch_bounds__(ColCfg<L>::THREADS)
     k_r2c_half(const float* __restrict__ in, float2* __restrict__ out, int nlines, int lin, int off,
-               long long in_img, long long out_img, float scale, const float2* __restrict__ tw) {
+               ImgMap map, float scale, const float2* __restrict__ tw) {
   using Cfg = ColCfg<L>;
   constexpr int P = Cfg::P, LINES = Cfg::LINES, H = L / 2 - 1;
   using Lay = typename std::conditional<TRANS, LayRow<LINES, L>, LayInter<LINES>>::type;
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(ColCfg<L>::THREADS)
   const int npairs = nlines >> 1;
   const int pg = blockIdx.x * LINES + pair;
   const bool active = pg < npairs;
-  const float* src = in + (long long)blockIdx.y * in_img;
+  const float* src = in + map.in(blockIdx.y);
 
   auto fl = [&](int idx) -> float2 {
     const int r = idx - off;
@@ -95,7 +96,7 @@ __global__ void __launch_bounds__(ColCfg<L>::THREADS)
   __syncthreads();
 
   // separate the two real columns: A = (Z_k + conj Z_{L-k})/2, B = (Z_k - conj Z_{L-k})/(2i)
-  float4* dst = reinterpret_cast<float4*>(out + (long long)blockIdx.y * out_img);
+  float4* dst = reinterpret_cast<float4*>(out + map.out(blockIdx.y));
   const int halfw = nlines >> 1;  // float4 per output row
   for (int e = tid; e < H * LINES; e += Cfg::THREADS) {
     const int p = e % LINES, k = 1 + e / LINES;
@@ -123,7 +124,7 @@ __global__ void __launch_bounds__(ColCfg<L>::THREADS)
 template <int L, bool TRANS, bool ACCUM>
 __global__ void __launch_bounds__(ColCfg<L>::THREADS)
     k_c2r_half(const float2* __restrict__ in, float* __restrict__ out, int nlines, int r0, int nout,
-               long long in_img, long long out_img, float scale, const float2* __restrict__ tw) {
+               ImgMap map, float scale, const float2* __restrict__ tw) {
   using Cfg = ColCfg<L>;
   constexpr int P = Cfg::P, LINES = Cfg::LINES, H = L / 2 - 1;
   using Lay = typename std::conditional<TRANS, LayRow<LINES, L>, LayInter<LINES>>::type;
@@ -138,7 +139,7 @@ __global__ void __launch_bounds__(ColCfg<L>::THREADS)
   const int pg = blockIdx.x * LINES + pair;
   const bool active = pg < npairs;
 
-  const float4* src = reinterpret_cast<const float4*>(in + (long long)blockIdx.y * in_img);
+  const float4* src = reinterpret_cast<const float4*>(in + map.in(blockIdx.y));
   for (int e = tid; e < H * LINES; e += Cfg::THREADS) {
     const int p = e % LINES, k = 1 + e / LINES;
     const int pgl = blockIdx.x * LINES + p;
@@ -158,7 +159,7 @@ __global__ void __launch_bounds__(ColCfg<L>::THREADS)
     const float4 v = stg[(L - idx) * LINES + pair];
     return make_float2(v.x + v.w, v.z - v.y);    // conj(A) + i conj(B)
   };
-  float* dst = out + (long long)blockIdx.y * out_img;
+  float* dst = out + map.out(blockIdx.y);
   auto ls = [&](int idx, float2 z) {
     const int r = idx - r0;
     if (!active || r < 0 || r >= nout) return;
@@ -302,7 +303,7 @@ __device__ __forceinline__ float2 herm_mirror(float4 x) { return make_float2(x.x
 template <int L, int E_, int LINES_, bool TRANS>
 __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
     k_r2c_fast(const float* __restrict__ in, float2* __restrict__ out, int nlines, int lin, int off,
-               long long in_img, long long out_img, float scale, const float2* __restrict__ tw, int tiles) {
+               ImgMap map, float scale, const float2* __restrict__ tw, int tiles) {
   using Cfg = FastCfg<L, E_, LINES_>;
   constexpr int P = Cfg::P, E = Cfg::E, LINES = Cfg::LINES, H = L / 2 - 1;
   using Eng = FftR<L, P, false, false>;
@@ -318,7 +319,7 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
   const int npairs = nlines >> 1;
   const int pg = tile * LINES + pair;
   const bool active = pg < npairs;
-  const float* src = in + (long long)img * in_img;
+  const float* src = in + map.in(img);
 
   float2 v[E];
 #pragma unroll
@@ -340,7 +341,7 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
   Eng::template run<false, true, true, Lay>(v, pair, t, lds, tw);
   if (!active) return;
 
-  float4* dst = reinterpret_cast<float4*>(out + (long long)img * out_img);
+  float4* dst = reinterpret_cast<float4*>(out + map.out(img));
   auto emit = [&](int k, float2 zk, float2 zm) {
     // A = (Z_k + conj Z_{L-k})/2, B = (Z_k - conj Z_{L-k})/(2i), times scale (-1)^k
     const float sc = (k & 1) ? -0.5f * scale : 0.5f * scale;
@@ -367,7 +368,7 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
 template <int L, int E_, int LINES_, bool TRANS, bool ACCUM>
 __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
     k_c2r_fast(const float2* __restrict__ in, float* __restrict__ out, int nlines, int r0, int nout,
-               long long in_img, long long out_img, float scale, const float2* __restrict__ tw, int tiles) {
+               ImgMap map, float scale, const float2* __restrict__ tw, int tiles) {
   using Cfg = FastCfg<L, E_, LINES_>;
   constexpr int P = Cfg::P, E = Cfg::E, LINES = Cfg::LINES;
   using Eng = FftR<L, P, true, true>;
@@ -383,7 +384,7 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
   const int npairs = nlines >> 1;
   const int pg = tile * LINES + pair;
   const bool active = pg < npairs;
-  const float4* src = reinterpret_cast<const float4*>(in + (long long)img * in_img);
+  const float4* src = reinterpret_cast<const float4*>(in + map.in(img));
 
   auto load = [&](int k) -> float4 {  // stored coefficient k (1 .. L/2-1) times (-1)^k; 0 for k = 0
     float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -427,7 +428,7 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
   Eng::template run<true, false, true, Lay>(v, pair, t, lds, tw);
   if (!active) return;
 
-  float* dst = out + (long long)img * out_img;
+  float* dst = out + map.out(img);
   float2 old[E];
   if constexpr (ACCUM) {
     // read every old value first so the adds do not serialise on memory latency
@@ -620,7 +621,7 @@ unsigned row_variant_mask_t() {
 
 template <int L>
 hipError_t launch_r2c_t(int variant, bool trans, const float* in, float2* out, int nlines, int lin, int off,
-                        long long in_img, long long out_img, float scale, const float2* tw, int batch,
+                        ImgMap map, float scale, const float2* tw, int batch,
                         hipStream_t s) {
   switch (variant) {
 #define FUNNEL_V(i, e, l)                                                                                      \
@@ -630,10 +631,10 @@ hipError_t launch_r2c_t(int variant, bool trans, const float* in, float2* out, i
       const int tiles = (nlines / 2 + F::LINES - 1) / F::LINES;                                                \
       dim3 grid(tiles, batch), block(F::THREADS);                                                              \
       if (trans)                                                                                               \
-        k_r2c_fast<L, e, l, true><<<grid, block, 0, s>>>(in, out, nlines, lin, off, in_img, out_img, scale, tw, \
+        k_r2c_fast<L, e, l, true><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, \
                                                           tiles);                                              \
       else                                                                                                     \
-        k_r2c_fast<L, e, l, false><<<grid, block, 0, s>>>(in, out, nlines, lin, off, in_img, out_img, scale,   \
+        k_r2c_fast<L, e, l, false><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale,   \
                                                            tw, tiles);                                         \
       return hipGetLastError();                                                                                \
     }                                                                                                          \
@@ -646,15 +647,15 @@ hipError_t launch_r2c_t(int variant, bool trans, const float* in, float2* out, i
   using Cfg = ColCfg<L>;
   dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
   if (trans)
-    k_r2c_half<L, true><<<grid, block, 0, s>>>(in, out, nlines, lin, off, in_img, out_img, scale, tw);
+    k_r2c_half<L, true><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw);
   else
-    k_r2c_half<L, false><<<grid, block, 0, s>>>(in, out, nlines, lin, off, in_img, out_img, scale, tw);
+    k_r2c_half<L, false><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw);
   return hipGetLastError();
 }
 
 template <int L>
 hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0,
-                        int nout, long long in_img, long long out_img, float scale, const float2* tw, int batch,
+                        int nout, ImgMap map, float scale, const float2* tw, int batch,
                         hipStream_t s) {
   switch (variant) {
 #define FUNNEL_V(i, e, l)                                                                                      \
@@ -665,17 +666,17 @@ hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, f
       dim3 grid(tiles, batch), block(F::THREADS);                                                              \
       if (trans) {                                                                                             \
         if (accum)                                                                                             \
-          k_c2r_fast<L, e, l, true, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img,   \
+          k_c2r_fast<L, e, l, true, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map,   \
                                                                  scale, tw, tiles);                            \
         else                                                                                                   \
-          k_c2r_fast<L, e, l, true, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img,  \
+          k_c2r_fast<L, e, l, true, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map,  \
                                                                   scale, tw, tiles);                           \
       } else {                                                                                                 \
         if (accum)                                                                                             \
-          k_c2r_fast<L, e, l, false, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img,  \
+          k_c2r_fast<L, e, l, false, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map,  \
                                                                   scale, tw, tiles);                           \
         else                                                                                                   \
-          k_c2r_fast<L, e, l, false, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img, \
+          k_c2r_fast<L, e, l, false, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, \
                                                                    scale, tw, tiles);                          \
       }                                                                                                        \
       return hipGetLastError();                                                                                \
@@ -690,14 +691,14 @@ hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, f
   dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
   if (trans) {
     if (accum)
-      k_c2r_half<L, true, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img, scale, tw);
+      k_c2r_half<L, true, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
     else
-      k_c2r_half<L, true, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img, scale, tw);
+      k_c2r_half<L, true, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
   } else {
     if (accum)
-      k_c2r_half<L, false, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img, scale, tw);
+      k_c2r_half<L, false, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
     else
-      k_c2r_half<L, false, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, in_img, out_img, scale, tw);
+      k_c2r_half<L, false, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
   }
   return hipGetLastError();
 }

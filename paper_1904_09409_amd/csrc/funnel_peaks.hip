@@ -64,14 +64,16 @@ __device__ __forceinline__ void bitonic_sort(uint64_t* a) {
   }
 }
 
+// Per-image plane blocks start at map.out(img); gidx maps the launch's image
+// index to the caller's (ragged batches), NULL meaning the identity.
 __global__ void __launch_bounds__(kPeakThreads)
-    k_peaks_tile(const float* __restrict__ planes, long long plane_stride, PlaneGeom g0, PlaneGeom g1, int nspaces,
-                 int tiles, int K, float thr, int radius, int wrap, int keep_border, uint64_t* __restrict__ out) {
+    k_peaks_tile(const float* __restrict__ planes, ImgMap map, PlaneGeom g0, PlaneGeom g1, int nspaces, int tiles,
+                 int K, float thr, int radius, int wrap, int keep_border, uint64_t* __restrict__ out) {
   __shared__ uint64_t keys[kPeakTile];
   const int plane = blockIdx.y;                 // image * nspaces + space
   const int img = plane / nspaces, sp = plane % nspaces;
   const PlaneGeom g = sp == 0 ? g0 : g1;
-  const float* P = planes + (long long)img * plane_stride + g.offset;
+  const float* P = planes + map.out(img) + g.offset;
   const int ncell = g.rows * g.cols;
   const int tile = blockIdx.x;
 
@@ -107,14 +109,15 @@ __global__ void __launch_bounds__(kPeakThreads)
 }
 
 __global__ void __launch_bounds__(kMergeThreads)
-    k_peaks_merge(const float* __restrict__ planes, long long plane_stride, PlaneGeom g0, PlaneGeom g1,
-                  int nspaces, int tiles, int K, const uint64_t* __restrict__ cand, ft_peak* __restrict__ peaks,
-                  int32_t* __restrict__ n_found) {
+    k_peaks_merge(const float* __restrict__ planes, ImgMap map, const int* __restrict__ gidx, PlaneGeom g0,
+                  PlaneGeom g1, int nspaces, int tiles, int K, const uint64_t* __restrict__ cand,
+                  ft_peak* __restrict__ peaks, int32_t* __restrict__ n_found) {
   __shared__ uint64_t keys[kMergeLen];
   const int plane = blockIdx.x;
   const int img = plane / nspaces, sp = plane % nspaces;
+  const int gimg = gidx ? gidx[img] : img;
   const PlaneGeom g = sp == 0 ? g0 : g1;
-  const float* P = planes + (long long)img * plane_stride + g.offset;
+  const float* P = planes + map.out(img) + g.offset;
   const uint64_t* src = cand + (long long)plane * tiles * K;
   const long long total = (long long)tiles * K;
 
@@ -132,12 +135,12 @@ __global__ void __launch_bounds__(kMergeThreads)
   // records
   int count = 0;
   for (int i = 0; i < K; ++i) count += keys[i] != kNoKey;
-  ft_peak* dst = peaks + (long long)plane * K;
+  ft_peak* dst = peaks + ((long long)gimg * nspaces + sp) * K;
   for (int i = threadIdx.x; i < count; i += kMergeThreads) {
     const int c = (int)(uint32_t)(keys[i] & 0xffffffffu);
     const int r = c / g.cols, col = c % g.cols;
     ft_peak pk;
-    pk.image = img;
+    pk.image = gimg;
     pk.space = sp;
     pk.row = r;
     pk.col = col;
@@ -147,7 +150,7 @@ __global__ void __launch_bounds__(kMergeThreads)
     pk.intercept = (float)(r - g.rows / 2) - slope * (float)(g.cols / 2) + (float)(g.himg / 2);
     dst[i] = pk;
   }
-  if (threadIdx.x == 0) n_found[plane] = count;
+  if (threadIdx.x == 0) n_found[(long long)gimg * nspaces + sp] = count;
 }
 
 size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K) {
@@ -156,7 +159,7 @@ size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K) {
 
 int peaks_tiles(int rows, int cols) { return (int)(((long long)rows * cols + kPeakTile - 1) / kPeakTile); }
 
-hipError_t launch_peaks(const float* planes, long long plane_stride, int batch, int nspaces, const int* rows,
+hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int batch, int nspaces, const int* rows,
                         const int* cols, const int* himg, const long long* offset, int K, float thr, int radius,
                         int wrap, int keep_border, ft_peak* peaks, int32_t* n_found, void* ws, hipStream_t s) {
   PlaneGeom g[2];
@@ -169,11 +172,11 @@ hipError_t launch_peaks(const float* planes, long long plane_stride, int batch, 
   if (nspaces == 1) g[1] = g[0];
   uint64_t* cand = static_cast<uint64_t*>(ws);
   dim3 grid1(tiles, batch * nspaces);
-  k_peaks_tile<<<grid1, kPeakThreads, 0, s>>>(planes, plane_stride, g[0], g[1], nspaces, tiles, K, thr, radius, wrap,
+  k_peaks_tile<<<grid1, kPeakThreads, 0, s>>>(planes, map, g[0], g[1], nspaces, tiles, K, thr, radius, wrap,
                                               keep_border, cand);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_peaks_merge<<<batch * nspaces, kMergeThreads, 0, s>>>(planes, plane_stride, g[0], g[1], nspaces, tiles, K, cand,
+  k_peaks_merge<<<batch * nspaces, kMergeThreads, 0, s>>>(planes, map, gidx, g[0], g[1], nspaces, tiles, K, cand,
                                                           peaks, n_found);
   return hipGetLastError();
 }

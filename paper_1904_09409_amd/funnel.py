@@ -33,12 +33,19 @@ FT_SPACE_BOTH = 3
 FT_PREC_FP32 = 0
 FT_PEAK_CLAMP_BORDER = 1
 FT_PEAK_KEEP_PAD_BOUNDARY = 2
+FT_GRAPH_FORWARD = 1
+FT_GRAPH_ADJOINT = 2
 
 
 class ft_plan_desc(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int32), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
                 ("padded_len", ctypes.c_int32), ("spaces", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class ft_image_desc(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
+                ("image_offset", ctypes.c_int64), ("plane_offset", ctypes.c_int64)]
 
 
 class ft_kernel_time(ctypes.Structure):
@@ -77,6 +84,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     sigs = {
         "funnel_plan_create": ([ctypes.POINTER(ft_plan_desc), ctypes.POINTER(vp)], ctypes.c_int),
         "funnel_plan_destroy": ([vp], None),
+        "funnel_plan_create_ragged": ([ctypes.POINTER(ft_image_desc), i32, i32, ctypes.POINTER(vp)], ctypes.c_int),
+        "funnel_buffer_elems": ([vp, ctypes.POINTER(sz), ctypes.POINTER(sz)], ctypes.c_int),
+        "funnel_plan_classes": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
+        "funnel_graph_create": ([vp, u32, vp, vp, vp, vp, vp, sz, ctypes.POINTER(vp)], ctypes.c_int),
+        "funnel_graph_launch": ([vp, vp], ctypes.c_int),
+        "funnel_graph_destroy": ([vp], None),
         "funnel_workspace_size": ([vp, ctypes.POINTER(sz)], ctypes.c_int),
         "funnel_plane_elems": ([vp, ctypes.POINTER(sz)], ctypes.c_int),
         "funnel_padded_len": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
@@ -143,6 +156,46 @@ def funnel_plan_create(batch: int, rows: int, cols: int, padded_len: int = 0,
 
 def funnel_plan_destroy(plan: int) -> None:
     load_library().funnel_plan_destroy(plan)
+
+
+def funnel_plan_create_ragged(shapes, image_offsets, plane_offsets, spaces: int = FT_SPACE_BOTH) -> int:
+    n = len(shapes)
+    arr = (ft_image_desc * n)()
+    for i, ((r, c), io, po) in enumerate(zip(shapes, image_offsets, plane_offsets)):
+        arr[i] = ft_image_desc(int(r), int(c), int(io), int(po))
+    h = ctypes.c_void_p()
+    _check(load_library().funnel_plan_create_ragged(arr, n, spaces, ctypes.byref(h)), "funnel_plan_create_ragged")
+    return h.value
+
+
+def funnel_buffer_elems(plan: int) -> tuple[int, int]:
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().funnel_buffer_elems(plan, ctypes.byref(a), ctypes.byref(b)), "funnel_buffer_elems")
+    return a.value, b.value
+
+
+def funnel_plan_classes(plan: int) -> int:
+    v = ctypes.c_int32()
+    _check(load_library().funnel_plan_classes(plan, ctypes.byref(v)), "funnel_plan_classes")
+    return v.value
+
+
+def funnel_graph_create(plan: int, what: int, images=None, planes=None, d_planes=None, d_images=None,
+                        ws=None) -> int:
+    h = ctypes.c_void_p()
+    ptr = lambda t: None if t is None else _ptr(t)
+    _check(load_library().funnel_graph_create(plan, what, ptr(images), ptr(planes), ptr(d_planes), ptr(d_images),
+                                              _ptr(ws), ws.numel() * ws.element_size(), ctypes.byref(h)),
+           "funnel_graph_create")
+    return h.value
+
+
+def funnel_graph_launch(graph: int, stream=None) -> None:
+    _check(load_library().funnel_graph_launch(graph, _stream(stream)), "funnel_graph_launch")
+
+
+def funnel_graph_destroy(graph: int) -> None:
+    load_library().funnel_graph_destroy(graph)
 
 
 def funnel_workspace_size(plan: int) -> int:
@@ -212,8 +265,9 @@ def funnel_autotune(plan: int, stream=None, cap: int = 16) -> list[dict]:
 
 
 def funnel_plan_variants(plan: int) -> list[int]:
-    arr = (ctypes.c_int32 * 12)()
-    _check(load_library().funnel_plan_variants(plan, arr, 12), "funnel_plan_variants")
+    n = 12 * funnel_plan_classes(plan)
+    arr = (ctypes.c_int32 * n)()
+    _check(load_library().funnel_plan_variants(plan, arr, n), "funnel_plan_variants")
     return list(arr)
 
 
@@ -306,6 +360,113 @@ class FunnelPlan:
         cnt = torch.empty((self.batch, self.nspaces), dtype=torch.int32, device=self.device)
         funnel_peaks(self.handle, planes, K, threshold, radius, flags, rec, cnt, ws, stream)
         return rec, cnt
+
+
+class RaggedPlan:
+    """A plan for a batch of images of different sizes, packed back to back
+    (each image's floats, then each image's plane block, 16-byte aligned)."""
+
+    def __init__(self, shapes, spaces: int = FT_SPACE_BOTH):
+        import torch
+        self.shapes = [(int(r), int(c)) for r, c in shapes]
+        self.spaces = spaces
+        self.nspaces = 2 if spaces == FT_SPACE_BOTH else 1
+        self.image_offsets, self.plane_offsets = [], []
+        io = po = 0
+        for (r, c) in self.shapes:
+            self.image_offsets.append(io)
+            self.plane_offsets.append(po)
+            io += (r * c + 3) // 4 * 4
+            np_ = r + c
+            pf = (np_ * c if spaces & FT_SPACE_REGULAR else 0) + (np_ * r if spaces & FT_SPACE_INVERSE else 0)
+            po += (pf + 3) // 4 * 4
+        self.handle = funnel_plan_create_ragged(self.shapes, self.image_offsets, self.plane_offsets, spaces)
+        self.image_floats, self.plane_floats = funnel_buffer_elems(self.handle)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.ws = torch.empty(max(funnel_workspace_size(self.handle), 256), dtype=torch.uint8, device=self.device)
+        self.batch = len(self.shapes)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                funnel_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def pack(self, images):
+        """List of [N, M] float32 arrays -> one flat device tensor."""
+        import torch
+        buf = np.zeros(self.image_floats, dtype=np.float32)
+        for img, off in zip(images, self.image_offsets):
+            buf[off:off + img.size] = np.asarray(img, dtype=np.float32).ravel()
+        return torch.from_numpy(buf).to(self.device)
+
+    def unpack_images(self, flat):
+        h = flat.cpu().numpy()
+        return [h[o:o + r * c].reshape(r, c) for (r, c), o in zip(self.shapes, self.image_offsets)]
+
+    def unpack_planes(self, flat):
+        """Flat planes tensor -> list of (regular or None, inverse or None) numpy arrays."""
+        h = flat.cpu().numpy()
+        out = []
+        for (r, c), o in zip(self.shapes, self.plane_offsets):
+            np_ = r + c
+            reg = inv = None
+            if self.spaces & FT_SPACE_REGULAR:
+                reg = h[o:o + np_ * c].reshape(np_, c)
+                o += np_ * c
+            if self.spaces & FT_SPACE_INVERSE:
+                inv = h[o:o + np_ * r].reshape(np_, r)
+            out.append((reg, inv))
+        return out
+
+    def new_planes(self):
+        import torch
+        return torch.zeros(self.plane_floats, dtype=torch.float32, device=self.device)
+
+    def forward(self, images_flat, planes=None, stream=None):
+        if planes is None:
+            planes = self.new_planes()
+        funnel_forward(self.handle, images_flat, planes, self.ws, stream)
+        return planes
+
+    def adjoint(self, d_planes, d_images=None, stream=None):
+        import torch
+        if d_images is None:
+            d_images = torch.zeros(self.image_floats, dtype=torch.float32, device=self.device)
+        funnel_adjoint(self.handle, d_planes, d_images, self.ws, stream)
+        return d_images
+
+    def peaks(self, planes, K: int = 16, threshold: float = 0.0, radius: int = 1, flags: int = 0, stream=None):
+        import torch
+        ws = torch.empty(max(funnel_peaks_workspace_size(self.handle, K), 256), dtype=torch.uint8,
+                         device=self.device)
+        rec = torch.empty((self.batch, self.nspaces, K, PEAK_WORDS), dtype=torch.int32, device=self.device)
+        cnt = torch.empty((self.batch, self.nspaces), dtype=torch.int32, device=self.device)
+        funnel_peaks(self.handle, planes, K, threshold, radius, flags, rec, cnt, ws, stream)
+        return rec, cnt
+
+
+class FunnelGraph:
+    """An executable graph of a plan's forward and/or adjoint on fixed buffers."""
+
+    def __init__(self, plan, what: int, images=None, planes=None, d_planes=None, d_images=None):
+        self.handle = funnel_graph_create(plan.handle, what, images, planes, d_planes, d_images, plan.ws)
+        self._keep = (plan, images, planes, d_planes, d_images)
+
+    def launch(self, stream=None):
+        funnel_graph_launch(self.handle, stream)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                funnel_graph_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
 
 
 def peaks_to_numpy(rec, cnt) -> list:

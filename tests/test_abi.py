@@ -71,3 +71,34 @@ def test_valid_plan_without_device(lib):
         pytest.skip("a GPU is visible")
     st, h = _create(lib, batch=2, rows=128, cols=128)
     assert st == F.FT_ERR_NO_DEVICE
+
+
+def _ragged(lib, descs, spaces=3):
+    arr = (F.ft_image_desc * max(len(descs), 1))()
+    for i, d in enumerate(descs):
+        arr[i] = F.ft_image_desc(*d)
+    h = ctypes.c_void_p(777)
+    st = lib.funnel_plan_create_ragged(arr, len(descs), spaces, ctypes.byref(h))
+    return st, h.value
+
+
+@pytest.mark.parametrize("descs,spaces,code", [
+    ([], 3, F.FT_ERR_INVALID_ARG),                                   # no images
+    ([(64, 64, 0, 0)], 0, F.FT_ERR_INVALID_ARG),                     # bad spaces
+    ([(64, 64, 0, 0), (63, 64, 4096, 8192)], 3, F.FT_ERR_INVALID_ARG),   # odd rows
+    ([(64, 64, 2, 0)], 3, F.FT_ERR_MISALIGNED),                      # image offset not a multiple of 4
+    ([(64, 64, 0, 6)], 3, F.FT_ERR_MISALIGNED),                      # plane offset not a multiple of 4
+    ([(64, 64, -4, 0)], 3, F.FT_ERR_MISALIGNED),                     # negative offset
+    ([(62, 64, 0, 0)], 3, F.FT_ERR_UNSUPPORTED_SIZE),                # 126 has no kernel
+])
+def test_ragged_plan_rejects(lib, descs, spaces, code):
+    st, h = _ragged(lib, descs, spaces)
+    assert st == code, (st, F.last_error())
+    assert h is None
+
+
+def test_graph_null_arguments(lib):
+    h = ctypes.c_void_p(5)
+    assert lib.funnel_graph_create(None, 1, None, None, None, None, None, 0, ctypes.byref(h)) == F.FT_ERR_INVALID_ARG
+    assert lib.funnel_graph_launch(None, None) == F.FT_ERR_INVALID_ARG
+    lib.funnel_graph_destroy(None)

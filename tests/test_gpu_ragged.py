@@ -1,0 +1,137 @@
+"""Ragged batches (images of several sizes in one call) and graph replays."""
+import numpy as np
+import pytest
+
+from helpers import rel_l2
+from oracle import funnel_oracle as O
+from paper_1904_09409_amd import funnel as F
+from paper_1904_09409_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+SHAPES = [(240, 320), (96, 160), (64, 64), (128, 128), (240, 320), (40, 24), (96, 160)]
+
+
+def ragged_images(shapes, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.random(s).astype(np.float32) for s in shapes]
+
+
+def test_ragged_forward_adjoint_match_oracle():
+    import torch
+    say(f"ragged parity {SHAPES}")
+    plan = F.RaggedPlan(SHAPES)
+    imgs = ragged_images(SHAPES, 3)
+    x = plan.pack(imgs)
+    planes = plan.forward(x)
+    rng = np.random.default_rng(4)
+    dP = rng.standard_normal(plan.plane_floats).astype(np.float32)
+    dI = plan.adjoint(torch.from_numpy(dP).cuda())
+    torch.cuda.synchronize()
+    got = plan.unpack_planes(planes)
+    got_d = plan.unpack_images(dI)
+    dpl = plan.unpack_planes(torch.from_numpy(dP))
+    for i, ((N, M), img) in enumerate(zip(SHAPES, imgs)):
+        r, v = O.forward(img.astype(np.float64))
+        assert rel_l2(got[i][0], r) <= TOL and rel_l2(got[i][1], v) <= TOL, i
+        want = O.adjoint(dpl[i][0].astype(np.float64), dpl[i][1].astype(np.float64), N, M)
+        assert rel_l2(got_d[i], want) <= TOL, i
+
+
+def test_ragged_matches_uniform_plans_bitwise():
+    """A size class of a ragged batch runs the same kernels as a uniform plan."""
+    import torch
+    say("ragged vs uniform bitwise")
+    shapes = [(96, 160), (64, 64), (96, 160), (64, 64), (64, 64)]
+    imgs = ragged_images(shapes, 9)
+    rp = F.RaggedPlan(shapes)
+    planes = rp.unpack_planes(rp.forward(rp.pack(imgs)))
+    for shape in set(shapes):
+        idx = [i for i, s in enumerate(shapes) if s == shape]
+        up = F.FunnelPlan(len(idx), *shape)
+        out = up.forward(torch.from_numpy(np.stack([imgs[i] for i in idx])).cuda())
+        v = up.views(out)
+        for k, i in enumerate(idx):
+            assert np.array_equal(v.regular[k].cpu().numpy(), planes[i][0])
+            assert np.array_equal(v.inverse[k].cpu().numpy(), planes[i][1])
+
+
+def test_ragged_peaks_use_caller_image_index():
+    import torch
+    say("ragged peaks")
+    shapes = [(128, 128), (96, 160), (128, 128)]
+    imgs = [synth.mixed_lines(N, M, 3, 0.05, np.random.default_rng(70 + i)).image for i, (N, M) in enumerate(shapes)]
+    plan = F.RaggedPlan(shapes)
+    planes = plan.forward(plan.pack(imgs))
+    rec, cnt = plan.peaks(planes, K=6)
+    got = F.peaks_to_numpy(rec, cnt)
+    host = plan.unpack_planes(planes)
+    for i, (N, M) in enumerate(shapes):
+        for s in range(2):
+            Bp = np.abs(host[i][s]).astype(np.float64)
+            mask = O.boundary_mask(N, M, N + M) if s == 0 else O.boundary_mask(M, N, N + M)
+            want = O.peaks_list(Bp, 6, 0.0, 1, mask, True)
+            g = got[i][s]
+            W = M if s == 0 else N
+            assert [int(r) * W + int(c) for r, c in zip(g["row"], g["col"])] == want
+            assert all(int(im) == i for im in g["image"])
+
+
+def test_ragged_workload_sample():
+    """Images drawn from the 240x320 / 480x640 / 720x1280 / 1080x1920 mix;
+    one image of each size class compared with the oracle."""
+    import torch
+    say("ragged workload sample (12 images)")
+    ims = synth.batch("ragged", count=12, seed=0)
+    shapes = [im.image.shape for im in ims]
+    plan = F.RaggedPlan(shapes)
+    planes = plan.forward(plan.pack([im.image for im in ims]))
+    torch.cuda.synchronize()
+    host = plan.unpack_planes(planes)
+    seen = set()
+    for i, im in enumerate(ims):
+        if shapes[i] in seen:
+            continue
+        seen.add(shapes[i])
+        r, v = O.forward(im.image.astype(np.float64))
+        e = max(rel_l2(host[i][0], r), rel_l2(host[i][1], v))
+        say(f"  image {i} {shapes[i]}: rel L2 {e:.2e}")
+        assert e <= TOL
+
+
+@pytest.mark.parametrize("ragged", [False, True])
+def test_graph_replays_match_eager(ragged):
+    """Capture forward + adjoint into a graph; replay it several times with
+    eager work in between; every replay equals the eager result bitwise."""
+    import torch
+    say(f"graph replay ragged={ragged}")
+    if ragged:
+        plan = F.RaggedPlan([(96, 160), (64, 64), (96, 160)])
+        x = plan.pack(ragged_images(plan.shapes, 5))
+        planes = plan.new_planes()
+        dP = torch.randn(plan.plane_floats, device="cuda")
+        dI = torch.zeros(plan.image_floats, device="cuda")
+    else:
+        plan = F.FunnelPlan(4, 128, 128)
+        x = torch.rand((4, 128, 128), device="cuda")
+        planes = plan.new_planes()
+        dP = torch.randn_like(planes)
+        dI = torch.zeros_like(x)
+    g = F.FunnelGraph(plan, F.FT_GRAPH_FORWARD | F.FT_GRAPH_ADJOINT, x, planes, dP, dI)
+    ref_p = plan.forward(x).clone()
+    ref_d = plan.adjoint(dP).clone()
+    for rep in range(3):
+        planes.zero_()
+        dI.fill_(7.0)
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(planes, ref_p), rep
+        assert torch.equal(dI, ref_d), rep
+        plan.forward(x * 0.5)          # eager work between replays
+        torch.cuda.synchronize()
