@@ -52,6 +52,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-images", type=int, default=2, help="images in the CPU oracle sample")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default tile variants")
+    ap.add_argument("--workload", choices=["grad", "ragged"], default="grad",
+                    help="grad: the 32 x 1024^2 batch (default); ragged: 256 images of mixed sizes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -63,6 +65,8 @@ def main():
     from paper_1904_09409_amd import synth
 
     F.load_library()  # fails loudly if the HIP library is missing
+    if args.workload == "ragged":
+        return ragged_bench(args, torch, F, synth)
     B, N, M = args.batch, args.size, args.size
     log(f"generating {B} synthetic {N}x{M} images")
     t0 = time.time()
@@ -172,6 +176,72 @@ def main():
         "cpu_baseline": cpu,
         "tile_variants": variants,
         "autotuned": tuned is not None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def ragged_bench(args, torch, F, synth, count=256):
+    """Forward + adjoint of 256 images drawn from 240x320 / 480x640 /
+    720x1280 / 1080x1920 (H x W), both spaces, in three schedules: the ragged
+    plan's concurrent size classes called eagerly, the same calls replayed as
+    one HIP graph, and one uniform plan per size class run back to back."""
+    log(f"generating {count} ragged synthetic images")
+    ims = synth.batch("ragged", count=count, seed=0)
+    shapes = [im.image.shape for im in ims]
+    px = sum(int(np.prod(s)) for s in shapes)
+    plan = F.RaggedPlan(shapes)
+    if not args.no_autotune:
+        F.funnel_autotune(plan.handle)
+    x = plan.pack([im.image for im in ims])
+    planes = plan.forward(x)
+    dP = torch.randn_like(planes)
+    dI = plan.adjoint(dP)
+    torch.cuda.synchronize()
+
+    def timeit(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(args.steps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / args.steps
+
+    eager_ms = timeit(lambda: (plan.forward(x, planes), plan.adjoint(dP, dI)))
+    graph = F.FunnelGraph(plan, F.FT_GRAPH_FORWARD | F.FT_GRAPH_ADJOINT, x, planes, dP, dI)
+    graph_ms = timeit(graph.launch)
+    # per-size baseline: one uniform plan per size class, launched one after another
+    by = {}
+    for i, s in enumerate(shapes):
+        by.setdefault(tuple(s), []).append(i)
+    uni = []
+    for s, idx in by.items():
+        p = F.FunnelPlan(len(idx), *s)
+        if not args.no_autotune:
+            F.funnel_autotune(p.handle)
+        xi = torch.from_numpy(np.stack([ims[i].image for i in idx])).cuda()
+        pi = p.forward(xi)
+        uni.append((p, xi, pi, torch.randn_like(pi), torch.empty_like(xi)))
+    torch.cuda.synchronize()
+
+    def seq():
+        for p, xi, pi, dpi, dii in uni:
+            p.forward(xi, pi)
+            p.adjoint(dpi, dii)
+
+    seq_ms = timeit(seq)
+    out = {
+        "metric": "Mpixel/s funnel fwd+adjoint, ragged 256-image mix (240x320..1080x1920), fp32",
+        "value": round(px / (graph_ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(graph_ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{count} ragged images, {px / 1e6:.1f} Mpixel, both spaces, forward + adjoint",
+                   "size_classes": {f"{s[0]}x{s[1]}": len(v) for s, v in by.items()}},
+        "schedules_ms": {"graph": round(graph_ms, 4), "eager_concurrent_classes": round(eager_ms, 4),
+                         "sequential_per_size_plans": round(seq_ms, 4)},
     }
     print(json.dumps(out), flush=True)
 
