@@ -50,7 +50,8 @@ def main():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-images", type=int, default=2, help="images in the CPU oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="the CPU oracle sample takes whole images until this much time has passed")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default tile variants")
     ap.add_argument("--workload", choices=["grad", "ragged"], default="grad",
                     help="grad: the 32 x 1024^2 batch (default); ragged: 256 images of mixed sizes")
@@ -134,7 +135,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(imgs[: args.cpu_images], dP, plan, N, M)
+        cpu = cpu_baseline(imgs, dP, plan, N, M, args.cpu_seconds)
 
     out = {
         "metric": "Mpixel/s funnel fwd+adjoint, 1024^2 fp32 batch; % of HBM roofline",
@@ -287,9 +288,10 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes / ms / 1e6, ms
 
 
-def cpu_baseline(imgs, dP, plan, N, M):
+def cpu_baseline(imgs, dP, plan, N, M, seconds):
     """The FP64 oracle, as it stands, on a bounded sample: forward (both
-    spaces) and adjoint of a few images of the same workload."""
+    spaces) and adjoint of whole images of the same workload, one after the
+    other, until `seconds` have passed."""
     from oracle import funnel_oracle as O
     try:
         from threadpoolctl import threadpool_info
@@ -299,13 +301,16 @@ def cpu_baseline(imgs, dP, plan, N, M):
     Np = plan.Np
     dPh = dP.cpu().numpy()
     t0 = time.time()
+    n = 0
     for b, im in enumerate(imgs):
         O.forward(im.image, Np)
         reg = dPh[b, : Np * M].reshape(Np, M).astype(np.float64)
         inv = dPh[b, Np * M:].reshape(Np, N).astype(np.float64)
         O.adjoint(reg, inv, N, M, Np)
+        n += 1
+        if time.time() - t0 >= seconds:
+            break
     dt = time.time() - t0
-    n = len(imgs)
     return {"value": round(n * N * M / dt / 1e6, 4), "unit": "Mpixel/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{n} of the {plan.batch} {N}x{M} images, forward both spaces + adjoint, {dt:.1f} s"}
 
