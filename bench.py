@@ -53,8 +53,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="the CPU oracle sample takes whole images until this much time has passed")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default tile variants")
-    ap.add_argument("--workload", choices=["grad", "ragged"], default="grad",
-                    help="grad: the 32 x 1024^2 batch (default); ragged: 256 images of mixed sizes")
+    ap.add_argument("--workload", choices=["grad", "ragged", "precision"], default="grad",
+                    help="grad: the 32 x 1024^2 batch (default); ragged: 256 images of mixed sizes; "
+                         "precision: 8 x 2048^2 in FP32 and with the split-precision matrix-core passes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -68,6 +69,8 @@ def main():
     F.load_library()  # fails loudly if the HIP library is missing
     if args.workload == "ragged":
         return ragged_bench(args, torch, F, synth)
+    if args.workload == "precision":
+        return precision_bench(args, torch, F, synth)
     B, N, M = args.batch, args.size, args.size
     log(f"generating {B} synthetic {N}x{M} images")
     t0 = time.time()
@@ -243,6 +246,71 @@ def ragged_bench(args, torch, F, synth, count=256):
                    "size_classes": {f"{s[0]}x{s[1]}": len(v) for s, v in by.items()}},
         "schedules_ms": {"graph": round(graph_ms, 4), "eager_concurrent_classes": round(eager_ms, 4),
                          "sequential_per_size_plans": round(seq_ms, 4)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def precision_bench(args, torch, F, synth, B=8, size=2048):
+    """Forward + adjoint of 8 x 2048^2 images (10 lines, sigma 0.1), both
+    spaces, with FP32 butterflies and with the BF16 / FP16 hi+lo matrix-core
+    DFT passes; each plan autotuned.  value = the FP32 path; the line also
+    carries every precision's step time and per-launch HBM rates."""
+    log(f"generating {B} synthetic {size}x{size} images")
+    imgs = synth.batch("precision", count=B, size=size, seed=0)
+    x = torch.from_numpy(synth.stack(imgs)).cuda()
+    res = {}
+    for name, prec in (("fp32", F.FT_PREC_FP32), ("bf16x3", F.FT_PREC_BF16X3), ("fp16x3", F.FT_PREC_FP16X3)):
+        plan = F.FunnelPlan(B, size, size, 0, F.FT_SPACE_BOTH, prec)
+        if not args.no_autotune:
+            F.funnel_autotune(plan.handle)
+        planes = plan.forward(x)
+        dP = torch.randn_like(planes)
+        dI = torch.empty_like(x)
+        torch.cuda.synchronize()
+
+        def step():
+            plan.forward(x, planes)
+            plan.adjoint(dP, dI)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(args.steps):
+            step()
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / args.steps
+        F.funnel_profile_enable(plan.handle, args.steps * 16)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        kernels = F.funnel_profile_read(plan.handle)
+        F.funnel_profile_disable(plan.handle)
+        step_bytes = sum(k["bytes_per_launch"] * k["launches"] for k in kernels) / args.steps
+        for k in kernels:
+            k["avg_ms"] = k["total_ms"] / k["launches"]
+            k["gbps"] = k["bytes_per_launch"] / k["avg_ms"] / 1e6
+        kernels.sort(key=lambda k: -k["total_ms"])
+        res[name] = {"ms_per_step": round(ms, 4), "mpix_s": round(B * size * size / (ms * 1e-3) / 1e6, 1),
+                     "step_algorithmic_gbps": round(step_bytes / (ms * 1e6), 1),
+                     "kernels": [{"name": k["name"], "avg_ms": round(k["avg_ms"], 4), "gbps": round(k["gbps"], 1)}
+                                 for k in kernels],
+                     "tile_variants": F.funnel_plan_variants(plan.handle)}
+        log(f"  {name}: {ms:.4f} ms/step")
+        del plan, planes, dP, dI
+    dom = res["fp32"]["kernels"][0]
+    out = {
+        "metric": "Mpixel/s funnel fwd+adjoint, 8 x 2048^2 batch: FP32 and split-precision matrix-core DFT passes",
+        "value": res["fp32"]["mpix_s"], "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["fp32"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{B} x {size}x{size} fp32 synthetic line images (10 lines, sigma 0.1), "
+                               f"both spaces, Np={2 * size}, forward + adjoint"},
+        "roofline": {"bound": "hbm", "kernel": dom["name"], "achieved": dom["gbps"], "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(dom["gbps"] / HBM_PEAK_GBPS, 4)},
+        "precisions": res,
     }
     print(json.dumps(out), flush=True)
 

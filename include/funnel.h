@@ -75,8 +75,19 @@ typedef enum {
 /* Which parameter spaces a plan computes (Sec. 4.1). */
 enum { FT_SPACE_REGULAR = 1, FT_SPACE_INVERSE = 2, FT_SPACE_BOTH = 3 };
 
-/* Arithmetic of the DFT stages. */
-enum { FT_PREC_FP32 = 0 };
+/* Arithmetic of the DFT stages.
+ *   FT_PREC_FP32   : FP32 butterflies (the reference path).
+ *   FT_PREC_BF16X3 : every radix-16 / radix-8 DFT stage as a matrix-core
+ *                    product with split operands, X = X_hi + X_lo and
+ *                    W = W_hi + W_lo in BF16, keeping the three products
+ *                    hi*hi + hi*lo + lo*hi, FP32 accumulation.
+ *   FT_PREC_FP16X3 : the same in FP16, operands scaled per butterfly by a
+ *                    power of two.
+ * Twiddle factors, the NVMT coordinates and weights, and all data between
+ * stages stay FP32 in every mode.  The split precisions need power-of-two
+ * lengths: Np in 128 .. 4096 and the row lengths (M, and N for the inverse
+ * space) in 64 .. 4096; other shapes give FT_ERR_UNSUPPORTED_SIZE. */
+enum { FT_PREC_FP32 = 0, FT_PREC_BF16X3 = 1, FT_PREC_FP16X3 = 2 };
 
 /* funnel_peaks flags. */
 enum {
@@ -92,7 +103,7 @@ typedef struct {
   int32_t cols;        /* M, image width, even, >= 4 */
   int32_t padded_len;  /* Np; 0 means N+M (Sec. 4.2); else even and >= N+M */
   int32_t spaces;      /* FT_SPACE_REGULAR, FT_SPACE_INVERSE or FT_SPACE_BOTH */
-  int32_t precision;   /* FT_PREC_FP32 */
+  int32_t precision;   /* FT_PREC_FP32, FT_PREC_BF16X3 or FT_PREC_FP16X3 */
   uint32_t flags;      /* reserved, must be 0 */
 } ft_plan_desc;
 

@@ -389,7 +389,10 @@ struct FftR {
     }
   }
 
-  // twiddle (base from the table, powers by balanced products) + R-point DFT
+  // twiddle (base from the table, powers by balanced products) + R-point DFT.
+  // One table read per butterfly instead of R - 1 keeps the memory pipeline
+  // free for the data; the powers carry the table entry's rounding times r
+  // (a few 1e-7 relative, well inside the FP32 error budget).
   template <int I, bool PAIRED>
   __device__ static __forceinline__ void compute(float2 (&v)[E], int t, const float2* __restrict__ tw) {
     constexpr int R = kPlan.r[I], NS = ns<I>(), BPT = E / R;

@@ -61,6 +61,7 @@ struct ft_plan {
   int device = 0;
   int spaces = 0;
   int batch = 0;
+  int prec = 0;             // FT_PREC_*
   bool ragged = false;
   std::vector<FtClass> cls;
   float2* tw = nullptr;
@@ -125,9 +126,9 @@ bool role_regular(int r) { return r <= FC_REG || (r >= AC_REG && r <= AA_REG); }
 bool role_active(const ft_plan* p, int r) {
   return (p->spaces & (role_regular(r) ? FT_SPACE_REGULAR : FT_SPACE_INVERSE)) != 0;
 }
-unsigned role_mask(const FtClass& c, int r) {
-  if (!role_is_row(r)) return funnel::col_variant_mask(c.Np);
-  return funnel::row_variant_mask(role_regular(r) ? c.M : c.N);
+unsigned role_mask(const ft_plan* p, const FtClass& c, int r) {
+  if (!role_is_row(r)) return funnel::col_variant_mask(c.Np, p->prec);
+  return funnel::row_variant_mask(role_regular(r) ? c.M : c.N, p->prec);
 }
 
 // Algorithmic HBM bytes of one launch: each input read once, each output
@@ -204,30 +205,30 @@ hipError_t run_role(const ft_plan* p, const FtClass& c, int r, int v, const floa
   switch (r) {
     // forward, regular space: y DFT of the image columns on the expanded frame,
     // NVMT + x' DFT per frequency row, Hermitian inverse y DFT
-    case FA_REG: return funnel::launch_r2c(Np, v, false, src, Sr, M, N, (Np - N) / 2, img_to_sr, 1.0f, tw_np, B, s);
-    case FB_REG: return funnel::launch_row(M, v, false, Sr, Np, h, sr, p->tw + c.tw_m, B, s);
+    case FA_REG: return funnel::launch_r2c(Np, v, p->prec, false, src, Sr, M, N, (Np - N) / 2, img_to_sr, 1.0f, tw_np, B, s);
+    case FB_REG: return funnel::launch_row(M, v, p->prec, false, Sr, Np, h, sr, p->tw + c.tw_m, B, s);
     case FC_REG:
-      return funnel::launch_c2r(Np, v, false, false, Sr, dst, M, 0, Np, sr_to_pl, 1.0f / Np, tw_np, B, s);
+      return funnel::launch_c2r(Np, v, p->prec, false, false, Sr, dst, M, 0, Np, sr_to_pl, 1.0f / Np, tw_np, B, s);
     // forward, inverse space: the same on the transposed image (rows read directly)
-    case FA_INV: return funnel::launch_r2c(Np, v, true, src, Si, N, M, (Np - M) / 2, img_to_si, 1.0f, tw_np, B, s);
-    case FB_INV: return funnel::launch_row(N, v, false, Si, Np, h, si, p->tw + c.tw_n, B, s);
+    case FA_INV: return funnel::launch_r2c(Np, v, p->prec, true, src, Si, N, M, (Np - M) / 2, img_to_si, 1.0f, tw_np, B, s);
+    case FB_INV: return funnel::launch_row(N, v, p->prec, false, Si, Np, h, si, p->tw + c.tw_n, B, s);
     case FC_INV:
-      return funnel::launch_c2r(Np, v, false, false, Si, dst + c.off_inv_plane, N, 0, Np, si_to_pl, 1.0f / Np,
+      return funnel::launch_c2r(Np, v, p->prec, false, false, Si, dst + c.off_inv_plane, N, 0, Np, si_to_pl, 1.0f / Np,
                                 tw_np, B, s);
     // adjoint, regular space: (2/Np) y DFT of the plane columns, conjugate x'
     // DFT + transposed interpolation, real part of the conjugate y DFT cropped
-    case AC_REG: return funnel::launch_r2c(Np, v, false, src, Sr, M, Np, 0, pl_to_sr, 2.0f / Np, tw_np, B, s);
-    case AB_REG: return funnel::launch_row(M, v, true, Sr, Np, h, sr, p->tw + c.tw_m, B, s);
+    case AC_REG: return funnel::launch_r2c(Np, v, p->prec, false, src, Sr, M, Np, 0, pl_to_sr, 2.0f / Np, tw_np, B, s);
+    case AB_REG: return funnel::launch_row(M, v, p->prec, true, Sr, Np, h, sr, p->tw + c.tw_m, B, s);
     case AA_REG:
-      return funnel::launch_c2r(Np, v, false, false, Sr, dst, M, (Np - N) / 2, N, sr_to_img, 0.5f, tw_np, B, s);
+      return funnel::launch_c2r(Np, v, p->prec, false, false, Sr, dst, M, (Np - N) / 2, N, sr_to_img, 0.5f, tw_np, B, s);
     // adjoint, inverse space: transposed write into the image rows, added to
     // the regular space's result when both spaces are computed
     case AC_INV:
-      return funnel::launch_r2c(Np, v, false, src + c.off_inv_plane, Si, N, Np, 0, pl_to_si, 2.0f / Np, tw_np, B,
+      return funnel::launch_r2c(Np, v, p->prec, false, src + c.off_inv_plane, Si, N, Np, 0, pl_to_si, 2.0f / Np, tw_np, B,
                                 s);
-    case AB_INV: return funnel::launch_row(N, v, true, Si, Np, h, si, p->tw + c.tw_n, B, s);
+    case AB_INV: return funnel::launch_row(N, v, p->prec, true, Si, Np, h, si, p->tw + c.tw_n, B, s);
     case AA_INV:
-      return funnel::launch_c2r(Np, v, true, reg, Si, dst, N, (Np - M) / 2, M, si_to_img, 0.5f, tw_np, B, s);
+      return funnel::launch_c2r(Np, v, p->prec, true, reg, Si, dst, N, (Np - M) / 2, M, si_to_img, 0.5f, tw_np, B, s);
   }
   return hipErrorInvalidValue;
 }
@@ -308,7 +309,7 @@ ft_status finish_plan(ft_plan* p, const std::vector<std::vector<std::pair<long l
     c.tw_n = ntw;
     ntw += c.N;
     for (int r = 0; r < NROLES; ++r) {
-      const unsigned m = role_mask(c, r);
+      const unsigned m = role_mask(p, c, r);
       c.variant[r] = 0;
       for (int v = 0; v < funnel::kMaxVariants; ++v)
         if (m & (1u << v)) {
@@ -403,7 +404,8 @@ ft_status funnel_plan_create(const ft_plan_desc* d, ft_plan** out) {
     return fail(FT_ERR_INVALID_ARG, "rows and cols must be even and >= 4 (got %d x %d)", d->rows, d->cols);
   if (d->spaces < FT_SPACE_REGULAR || d->spaces > FT_SPACE_BOTH)
     return fail(FT_ERR_INVALID_ARG, "spaces must be 1, 2 or 3 (got %d)", d->spaces);
-  if (d->precision != FT_PREC_FP32) return fail(FT_ERR_INVALID_ARG, "unknown precision %d", d->precision);
+  if (d->precision < FT_PREC_FP32 || d->precision > FT_PREC_FP16X3)
+    return fail(FT_ERR_INVALID_ARG, "unknown precision %d", d->precision);
   if (d->flags != 0) return fail(FT_ERR_INVALID_ARG, "unknown plan flags 0x%x", d->flags);
   const long long N = d->rows, M = d->cols;
   const long long Np = d->padded_len == 0 ? N + M : d->padded_len;
@@ -411,11 +413,25 @@ ft_status funnel_plan_create(const ft_plan_desc* d, ft_plan** out) {
     return fail(FT_ERR_INVALID_ARG, "padded_len must be 0 or even and >= rows+cols (got %d)", d->padded_len);
   ft_status st = validate_shape((int)N, (int)M, d->spaces, Np);
   if (st != FT_OK) return st;
+  if (d->precision != FT_PREC_FP32) {
+    // the matrix-core passes cover power-of-two lengths with a register-resident tile
+    const char* what = nullptr;
+    int len = 0;
+    if (!funnel::col_variant_mask((int)Np, d->precision)) what = "padded length", len = (int)Np;
+    else if ((d->spaces & FT_SPACE_REGULAR) && !funnel::row_variant_mask((int)M, d->precision))
+      what = "row length (image width)", len = (int)M;
+    else if ((d->spaces & FT_SPACE_INVERSE) && !funnel::row_variant_mask((int)N, d->precision))
+      what = "row length (image height)", len = (int)N;
+    if (what)
+      return fail(FT_ERR_UNSUPPORTED_SIZE, "precision %d has no kernel for %s %d (powers of two only)", d->precision,
+                  what, len);
+  }
 
   ft_plan* p = new (std::nothrow) ft_plan();
   if (!p) return fail(FT_ERR_OUT_OF_MEMORY, "host allocation failed");
   p->spaces = d->spaces;
   p->batch = d->batch;
+  p->prec = d->precision;
   p->cls.resize(1);
   FtClass& c = p->cls[0];
   c.N = (int)N;
@@ -638,7 +654,7 @@ ft_status funnel_autotune(ft_plan* p, void* stream, ft_tune_result* out, int32_t
     FtClass& c = p->cls[ci];
     for (int r = 0; r < NROLES; ++r) {
       if (!role_active(p, r)) continue;
-      const unsigned mask = role_mask(c, r);
+      const unsigned mask = role_mask(p, c, r);
       float best = 1e30f, first_ms = -1.f;
       int best_v = c.variant[r], tried = 0;
       for (int v = 0; v < funnel::kMaxVariants; ++v) {
@@ -698,7 +714,7 @@ ft_status funnel_plan_set_variant(ft_plan* p, int32_t role, int32_t variant) {
   if (role < 0 || role >= (int)p->cls.size() * NROLES)
     return fail(FT_ERR_INVALID_ARG, "role must be in 0..%d", (int)p->cls.size() * NROLES - 1);
   const int ci = role / NROLES, r = role % NROLES;
-  if (variant < 0 || variant >= funnel::kMaxVariants || !(role_mask(p->cls[ci], r) & (1u << variant)))
+  if (variant < 0 || variant >= funnel::kMaxVariants || !(role_mask(p, p->cls[ci], r) & (1u << variant)))
     return fail(FT_ERR_INVALID_ARG, "variant %d has no kernel for role %s", variant, kRoleName[r]);
   p->cls[ci].variant[r] = variant;
   return ok();

@@ -19,24 +19,30 @@ struct ImgMap {
   __host__ __device__ long long out(int i) const { return out_off ? out_off[i] : (long long)i * out_stride; }
 };
 
+// arithmetic of the DFT passes: FP32 butterflies, or matrix-core products
+// with BF16 / FP16 hi + lo operands and FP32 accumulation (same values as
+// FT_PREC_* in funnel.h)
+enum Prec : int { kPrecFP32 = 0, kPrecBF16x3 = 1, kPrecFP16x3 = 2 };
+
 bool length_supported(int L);
 
-// bit v set: tile variant v has a kernel for this length (bit 0 alone: the
-// generic kernel)
-unsigned col_variant_mask(int L);
-unsigned row_variant_mask(int M);
+// bit v set: tile variant v has a kernel for this length and precision
+// (kPrecFP32 bit 0 alone: the generic kernel; split precisions: 0 when the
+// length has no matrix-core kernel)
+unsigned col_variant_mask(int L, int prec);
+unsigned row_variant_mask(int M, int prec);
 constexpr int kMaxVariants = 8;
 
 // real lines (zero-padded to L) -> half spectrum rows 1..L/2-1, times scale*(-1)^k
-hipError_t launch_r2c(int L, int variant, bool trans, const float* in, float2* out, int nlines, int lin, int off,
+hipError_t launch_r2c(int L, int variant, int prec, bool trans, const float* in, float2* out, int nlines, int lin, int off,
                       ImgMap map, float scale, const float2* tw, int batch, hipStream_t s);
 
 // half spectrum rows 1..L/2-1 -> real lines, rows [r0, r0+nout) stored (or added)
-hipError_t launch_c2r(int L, int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0,
+hipError_t launch_c2r(int L, int variant, int prec, bool trans, bool accum, const float2* in, float* out, int nlines, int r0,
                       int nout, ImgMap map, float scale, const float2* tw, int batch, hipStream_t s);
 
 // per frequency row: NVMT gather + DFT along x' (forward) or its transpose (adjoint), in place
-hipError_t launch_row(int M, int variant, bool adj, float2* data, int Lp, int h, long long img_stride, const float2* tw,
+hipError_t launch_row(int M, int variant, int prec, bool adj, float2* data, int Lp, int h, long long img_stride, const float2* tw,
                       int batch, hipStream_t s);
 
 size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K);

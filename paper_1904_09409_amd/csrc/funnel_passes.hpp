@@ -20,7 +20,7 @@
 #include <type_traits>
 
 #include "fft_core.hpp"
-#include "funnel_internal.hpp"
+#include "fft_mfma.hpp"
 #include "funnel_internal.hpp"
 
 namespace funnel {
@@ -300,13 +300,13 @@ constexpr int kColVariants = 6;
 __device__ __forceinline__ float2 herm_direct(float4 x) { return make_float2(x.x - x.w, x.y + x.z); }  // A + iB
 __device__ __forceinline__ float2 herm_mirror(float4 x) { return make_float2(x.x + x.w, x.z - x.y); }  // conj A + i conj B
 
-template <int L, int E_, int LINES_, bool TRANS>
+template <int L, int E_, int LINES_, bool TRANS, int PREC>
 __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
     k_r2c_fast(const float* __restrict__ in, float2* __restrict__ out, int nlines, int lin, int off,
                ImgMap map, float scale, const float2* __restrict__ tw, int tiles) {
   using Cfg = FastCfg<L, E_, LINES_>;
   constexpr int P = Cfg::P, E = Cfg::E, LINES = Cfg::LINES, H = L / 2 - 1;
-  using Eng = FftR<L, P, false, false>;
+  using Eng = typename EngSel<PREC, L, P, false, false, LINES, true>::type;
   constexpr RadixPlan PL = Eng::kPlan;
   constexpr int R0 = PL.r[0], NB0 = L / R0;
   constexpr int RL = PL.r[PL.n - 1], NBL = L / RL, BPTL = E / RL;
@@ -365,13 +365,13 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
   }
 }
 
-template <int L, int E_, int LINES_, bool TRANS, bool ACCUM>
+template <int L, int E_, int LINES_, bool TRANS, bool ACCUM, int PREC>
 __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
     k_c2r_fast(const float2* __restrict__ in, float* __restrict__ out, int nlines, int r0, int nout,
                ImgMap map, float scale, const float2* __restrict__ tw, int tiles) {
   using Cfg = FastCfg<L, E_, LINES_>;
   constexpr int P = Cfg::P, E = Cfg::E, LINES = Cfg::LINES;
-  using Eng = FftR<L, P, true, true>;
+  using Eng = typename EngSel<PREC, L, P, true, true, LINES, true>::type;
   constexpr RadixPlan PL = Eng::kPlan;
   constexpr int R0 = PL.r[0], NB0 = L / R0, BPT0 = E / R0;
   constexpr int RL = PL.r[PL.n - 1], NBL = L / RL, BPTL = E / RL;
@@ -492,12 +492,12 @@ struct RowFastCfg {
 #define FUNNEL_ROW_VARIANTS(X) X(0, 16, 256) X(1, 16, 128) X(2, 16, 512) X(3, 32, 256)
 constexpr int kRowVariants = 4;
 
-template <int M, int E_, int TPB, bool ADJ>
+template <int M, int E_, int TPB, bool ADJ, int PREC>
 __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
     k_row_fast(float2* __restrict__ data, int Lp, int h, long long img_stride, const float2* __restrict__ tw) {
   using Cfg = RowFastCfg<M, E_, TPB>;
   constexpr int P = Cfg::P, E = Cfg::E, ROWS = Cfg::ROWS;
-  using Eng = FftR<M, P, ADJ, false>;
+  using Eng = typename EngSel<PREC, M, P, ADJ, false, ROWS, false>::type;
   constexpr RadixPlan PL = Eng::kPlan;
   constexpr int R0 = PL.r[0], NB0 = M / R0, BPT0 = E / R0;
   constexpr int RL = PL.r[PL.n - 1], NBL = M / RL, BPTL = E / RL;
@@ -600,137 +600,149 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
 }
 
 // ------------------------------------------------------------------ launchers
+//
+// PREC = kPrecFP32 runs FftR; the split-precision values run FftM and exist
+// only for the register-resident tile variants FftM fits.
 
-template <int L>
+template <int L, int PREC>
 unsigned col_variant_mask_t() {
   unsigned m = 0;
-#define FUNNEL_V(i, e, l) if constexpr (FastCfg<L, e, l>::valid) m |= 1u << i;
+#define FUNNEL_V(i, e, l) \
+  if constexpr (FastCfg<L, e, l>::valid && (PREC == kPrecFP32 || mfma_fits(L, e, FastCfg<L, e, l>::THREADS))) m |= 1u << i;
   FUNNEL_COL_VARIANTS(FUNNEL_V)
 #undef FUNNEL_V
+  if (PREC != kPrecFP32) return m;
   return m ? m : 1u;  // lengths without a register-resident kernel: the generic one, variant 0
 }
 
-template <int M>
+template <int M, int PREC>
 unsigned row_variant_mask_t() {
   unsigned m = 0;
-#define FUNNEL_V(i, e, t) if constexpr (RowFastCfg<M, e, t>::valid) m |= 1u << i;
+#define FUNNEL_V(i, e, t) \
+  if constexpr (RowFastCfg<M, e, t>::valid && (PREC == kPrecFP32 || mfma_fits(M, e, RowFastCfg<M, e, t>::THREADS))) m |= 1u << i;
   FUNNEL_ROW_VARIANTS(FUNNEL_V)
 #undef FUNNEL_V
+  if (PREC != kPrecFP32) return m;
   return m ? m : 1u;
 }
 
-template <int L>
+template <int L, int PREC>
 hipError_t launch_r2c_t(int variant, bool trans, const float* in, float2* out, int nlines, int lin, int off,
-                        ImgMap map, float scale, const float2* tw, int batch,
-                        hipStream_t s) {
+                        ImgMap map, float scale, const float2* tw, int batch, hipStream_t s) {
   switch (variant) {
-#define FUNNEL_V(i, e, l)                                                                                      \
-  case i:                                                                                                      \
-    if constexpr (FastCfg<L, e, l>::valid) {                                                                   \
-      using F = FastCfg<L, e, l>;                                                                              \
-      const int tiles = (nlines / 2 + F::LINES - 1) / F::LINES;                                                \
-      dim3 grid(tiles, batch), block(F::THREADS);                                                              \
-      if (trans)                                                                                               \
-        k_r2c_fast<L, e, l, true><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, \
-                                                          tiles);                                              \
-      else                                                                                                     \
-        k_r2c_fast<L, e, l, false><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale,   \
-                                                           tw, tiles);                                         \
-      return hipGetLastError();                                                                                \
-    }                                                                                                          \
+#define FUNNEL_V(i, e, l)                                                                                    \
+  case i:                                                                                                    \
+    if constexpr (FastCfg<L, e, l>::valid && (PREC == kPrecFP32 || mfma_fits(L, e, FastCfg<L, e, l>::THREADS))) { \
+      using F = FastCfg<L, e, l>;                                                                            \
+      const int tiles = (nlines / 2 + F::LINES - 1) / F::LINES;                                              \
+      dim3 grid(tiles, batch), block(F::THREADS);                                                            \
+      if (trans)                                                                                             \
+        k_r2c_fast<L, e, l, true, PREC><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, tiles); \
+      else                                                                                                   \
+        k_r2c_fast<L, e, l, false, PREC><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, tiles); \
+      return hipGetLastError();                                                                              \
+    }                                                                                                        \
     break;
     FUNNEL_COL_VARIANTS(FUNNEL_V)
 #undef FUNNEL_V
     default: break;
   }
-  if (col_variant_mask_t<L>() != 1u || variant != 0) return hipErrorInvalidValue;
-  using Cfg = ColCfg<L>;
-  dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
-  if (trans)
-    k_r2c_half<L, true><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw);
-  else
-    k_r2c_half<L, false><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw);
-  return hipGetLastError();
-}
-
-template <int L>
-hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0,
-                        int nout, ImgMap map, float scale, const float2* tw, int batch,
-                        hipStream_t s) {
-  switch (variant) {
-#define FUNNEL_V(i, e, l)                                                                                      \
-  case i:                                                                                                      \
-    if constexpr (FastCfg<L, e, l>::valid) {                                                                   \
-      using F = FastCfg<L, e, l>;                                                                              \
-      const int tiles = (nlines / 2 + F::LINES - 1) / F::LINES;                                                \
-      dim3 grid(tiles, batch), block(F::THREADS);                                                              \
-      if (trans) {                                                                                             \
-        if (accum)                                                                                             \
-          k_c2r_fast<L, e, l, true, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map,   \
-                                                                 scale, tw, tiles);                            \
-        else                                                                                                   \
-          k_c2r_fast<L, e, l, true, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map,  \
-                                                                  scale, tw, tiles);                           \
-      } else {                                                                                                 \
-        if (accum)                                                                                             \
-          k_c2r_fast<L, e, l, false, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map,  \
-                                                                  scale, tw, tiles);                           \
-        else                                                                                                   \
-          k_c2r_fast<L, e, l, false, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, \
-                                                                   scale, tw, tiles);                          \
-      }                                                                                                        \
-      return hipGetLastError();                                                                                \
-    }                                                                                                          \
-    break;
-    FUNNEL_COL_VARIANTS(FUNNEL_V)
-#undef FUNNEL_V
-    default: break;
-  }
-  if (col_variant_mask_t<L>() != 1u || variant != 0) return hipErrorInvalidValue;
-  using Cfg = ColCfg<L>;
-  dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
-  if (trans) {
-    if (accum)
-      k_c2r_half<L, true, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
-    else
-      k_c2r_half<L, true, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
+  if constexpr (PREC != kPrecFP32) {
+    return hipErrorInvalidValue;
   } else {
-    if (accum)
-      k_c2r_half<L, false, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
+    if (col_variant_mask_t<L, PREC>() != 1u || variant != 0) return hipErrorInvalidValue;
+    using Cfg = ColCfg<L>;
+    dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
+    if (trans)
+      k_r2c_half<L, true><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw);
     else
-      k_c2r_half<L, false, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
+      k_r2c_half<L, false><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw);
+    return hipGetLastError();
   }
-  return hipGetLastError();
 }
 
-template <int M>
+template <int L, int PREC>
+hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0,
+                        int nout, ImgMap map, float scale, const float2* tw, int batch, hipStream_t s) {
+  switch (variant) {
+#define FUNNEL_V(i, e, l)                                                                                    \
+  case i:                                                                                                    \
+    if constexpr (FastCfg<L, e, l>::valid && (PREC == kPrecFP32 || mfma_fits(L, e, FastCfg<L, e, l>::THREADS))) { \
+      using F = FastCfg<L, e, l>;                                                                            \
+      const int tiles = (nlines / 2 + F::LINES - 1) / F::LINES;                                              \
+      dim3 grid(tiles, batch), block(F::THREADS);                                                            \
+      if (trans) {                                                                                           \
+        if (accum)                                                                                           \
+          k_c2r_fast<L, e, l, true, true, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
+        else                                                                                                 \
+          k_c2r_fast<L, e, l, true, false, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
+      } else {                                                                                               \
+        if (accum)                                                                                           \
+          k_c2r_fast<L, e, l, false, true, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
+        else                                                                                                 \
+          k_c2r_fast<L, e, l, false, false, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
+      }                                                                                                      \
+      return hipGetLastError();                                                                              \
+    }                                                                                                        \
+    break;
+    FUNNEL_COL_VARIANTS(FUNNEL_V)
+#undef FUNNEL_V
+    default: break;
+  }
+  if constexpr (PREC != kPrecFP32) {
+    return hipErrorInvalidValue;
+  } else {
+    if (col_variant_mask_t<L, PREC>() != 1u || variant != 0) return hipErrorInvalidValue;
+    using Cfg = ColCfg<L>;
+    dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
+    if (trans) {
+      if (accum)
+        k_c2r_half<L, true, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
+      else
+        k_c2r_half<L, true, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
+    } else {
+      if (accum)
+        k_c2r_half<L, false, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
+      else
+        k_c2r_half<L, false, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
+    }
+    return hipGetLastError();
+  }
+}
+
+template <int M, int PREC>
 hipError_t launch_row_t(int variant, bool adj, float2* data, int Lp, int h, long long img_stride,
                         const float2* tw, int batch, hipStream_t s) {
   switch (variant) {
-#define FUNNEL_V(i, e, tpb)                                                                       \
-  case i:                                                                                         \
-    if constexpr (RowFastCfg<M, e, tpb>::valid) {                                                 \
-      using F = RowFastCfg<M, e, tpb>;                                                            \
-      dim3 grid((h + F::ROWS - 1) / F::ROWS, batch), block(F::THREADS);                           \
-      if (adj)                                                                                    \
-        k_row_fast<M, e, tpb, true><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);          \
-      else                                                                                        \
-        k_row_fast<M, e, tpb, false><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);         \
-      return hipGetLastError();                                                                   \
-    }                                                                                             \
+#define FUNNEL_V(i, e, tpb)                                                                                    \
+  case i:                                                                                                      \
+    if constexpr (RowFastCfg<M, e, tpb>::valid &&                                                              \
+                  (PREC == kPrecFP32 || mfma_fits(M, e, RowFastCfg<M, e, tpb>::THREADS))) {                    \
+      using F = RowFastCfg<M, e, tpb>;                                                                         \
+      dim3 grid((h + F::ROWS - 1) / F::ROWS, batch), block(F::THREADS);                                        \
+      if (adj)                                                                                                 \
+        k_row_fast<M, e, tpb, true, PREC><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);                 \
+      else                                                                                                     \
+        k_row_fast<M, e, tpb, false, PREC><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);                \
+      return hipGetLastError();                                                                                \
+    }                                                                                                          \
     break;
     FUNNEL_ROW_VARIANTS(FUNNEL_V)
 #undef FUNNEL_V
     default: break;
   }
-  if (row_variant_mask_t<M>() != 1u || variant != 0) return hipErrorInvalidValue;
-  using Cfg = RowCfg<M>;
-  dim3 grid((h + Cfg::ROWS - 1) / Cfg::ROWS, batch), block(Cfg::THREADS);
-  if (adj)
-    k_row_nvmt<M, true><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
-  else
-    k_row_nvmt<M, false><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
-  return hipGetLastError();
+  if constexpr (PREC != kPrecFP32) {
+    return hipErrorInvalidValue;
+  } else {
+    if (row_variant_mask_t<M, PREC>() != 1u || variant != 0) return hipErrorInvalidValue;
+    using Cfg = RowCfg<M>;
+    dim3 grid((h + Cfg::ROWS - 1) / Cfg::ROWS, batch), block(Cfg::THREADS);
+    if (adj)
+      k_row_nvmt<M, true><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
+    else
+      k_row_nvmt<M, false><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
+    return hipGetLastError();
+  }
 }
 
 }  // namespace funnel

@@ -31,6 +31,8 @@ FT_SPACE_REGULAR = 1
 FT_SPACE_INVERSE = 2
 FT_SPACE_BOTH = 3
 FT_PREC_FP32 = 0
+FT_PREC_BF16X3 = 1
+FT_PREC_FP16X3 = 2
 FT_PEAK_CLAMP_BORDER = 1
 FT_PEAK_KEEP_PAD_BOUNDARY = 2
 FT_GRAPH_FORWARD = 1
@@ -287,10 +289,11 @@ class FunnelPlan:
     """A plan plus its workspace for a fixed batch shape on the current device."""
 
     def __init__(self, batch: int, rows: int, cols: int, padded_len: int = 0,
-                 spaces: int = FT_SPACE_BOTH):
+                 spaces: int = FT_SPACE_BOTH, precision: int = FT_PREC_FP32):
         import torch
         self.batch, self.N, self.M, self.spaces = batch, rows, cols, spaces
-        self.handle = funnel_plan_create(batch, rows, cols, padded_len, spaces)
+        self.precision = precision
+        self.handle = funnel_plan_create(batch, rows, cols, padded_len, spaces, precision)
         self.Np = funnel_padded_len(self.handle)
         self.plane_elems = funnel_plane_elems(self.handle)
         self.device = torch.device("cuda", torch.cuda.current_device())

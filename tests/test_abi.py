@@ -47,6 +47,12 @@ def _create(lib, **kw):
     (dict(padded_len=131), F.FT_ERR_INVALID_ARG),      # odd
     (dict(rows=62, cols=64), F.FT_ERR_UNSUPPORTED_SIZE),   # 126 = 2*3^2*7 has no kernel
     (dict(rows=44, cols=20), F.FT_ERR_UNSUPPORTED_SIZE),   # 64 ok, row length 44 = 4*11 not 7-smooth
+    (dict(precision=-1), F.FT_ERR_INVALID_ARG),
+    # the split precisions run power-of-two lengths only
+    (dict(rows=96, cols=160, precision=F.FT_PREC_BF16X3), F.FT_ERR_UNSUPPORTED_SIZE),
+    (dict(rows=64, cols=96, padded_len=256, precision=F.FT_PREC_FP16X3), F.FT_ERR_UNSUPPORTED_SIZE),
+    (dict(rows=96, cols=64, padded_len=256, spaces=3, precision=F.FT_PREC_BF16X3), F.FT_ERR_UNSUPPORTED_SIZE),
+    (dict(rows=16, cols=16, precision=F.FT_PREC_BF16X3), F.FT_ERR_UNSUPPORTED_SIZE),   # Np 32
 ])
 def test_plan_create_rejects(lib, kw, code):
     st, h = _create(lib, **kw)
@@ -71,6 +77,9 @@ def test_valid_plan_without_device(lib):
         pytest.skip("a GPU is visible")
     st, h = _create(lib, batch=2, rows=128, cols=128)
     assert st == F.FT_ERR_NO_DEVICE
+    for prec in (F.FT_PREC_BF16X3, F.FT_PREC_FP16X3):
+        st, h = _create(lib, batch=2, rows=1024, cols=1024, precision=prec)
+        assert st == F.FT_ERR_NO_DEVICE
 
 
 def _ragged(lib, descs, spaces=3):

@@ -1,0 +1,189 @@
+"""Split-precision DFT passes on the matrix cores (BF16 or FP16 hi + lo
+operands, three products, FP32 accumulation) against the FP64 oracle, beside
+the FP32 path.
+
+Tolerances (rel L2 over a plane or an image gradient), from the arithmetic:
+splitting x = hi + lo leaves |x - hi - lo| <= u^2 |x|, and the dropped
+lo*lo product is <= u^2 |a||x|, with u = 2^-8 (BF16) or 2^-11 (FP16), so each
+matrix-core stage adds a relative error of about u^2 rms (1.5e-5 for BF16,
+2.4e-7 for FP16).  A forward or adjoint path has nine such stages (three
+radix-16/8 stages in each of its three passes), which add in quadrature
+(3 u^2), and the last pass (Hermitian inverse DFT, DC and Nyquist rows
+dropped) amplifies relative errors up to about 2x on these images (measured
+on the FP32 path against FP64).  Estimate 6 u^2: 9e-5 (BF16 x3) and 1.5e-6
+(FP16 x3, where the FP32 rounding floor of the radix-16 passes, about 1e-6
+at 2048^2, adds to it).  Bounds: 1.5e-4 and 3e-6.
+"""
+import numpy as np
+import pytest
+
+import pins
+from helpers import rel_l2
+from oracle import funnel_oracle as O
+from paper_1904_09409_amd import funnel as F
+from paper_1904_09409_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+PRECS = [F.FT_PREC_BF16X3, F.FT_PREC_FP16X3]
+NAMES = {F.FT_PREC_FP32: "fp32", F.FT_PREC_BF16X3: "bf16x3", F.FT_PREC_FP16X3: "fp16x3"}
+TOL = {F.FT_PREC_FP32: 1e-5, F.FT_PREC_BF16X3: 1.5e-4, F.FT_PREC_FP16X3: 3e-6}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def split_planes(flat, N, M, Np, spaces):
+    out, off = [], 0
+    if spaces & F.FT_SPACE_REGULAR:
+        out.append(flat[off:off + Np * M].reshape(Np, M))
+        off += Np * M
+    if spaces & F.FT_SPACE_INVERSE:
+        out.append(flat[off:off + Np * N].reshape(Np, N))
+    return out
+
+
+def oracle_adjoint(dflat, N, M, Np, spaces):
+    parts = split_planes(dflat.astype(np.float64), N, M, Np, spaces)
+    if spaces == F.FT_SPACE_REGULAR:
+        return O.adjoint_regular(parts[0], N, M, Np)
+    if spaces == F.FT_SPACE_INVERSE:
+        return O.adjoint_inverse(parts[0], N, M, Np)
+    return O.adjoint(parts[0], parts[1], N, M, Np)
+
+
+@pytest.mark.parametrize("prec", PRECS, ids=[NAMES[p] for p in PRECS])
+@pytest.mark.parametrize("N,M,Np,spaces", [
+    (64, 64, 0, 3),        # Np 128 = 16*8, rows 64 = 8*8
+    (128, 128, 0, 3),      # Np 256 = 16*16, rows 128
+    (256, 256, 0, 3),      # Np 512 = 8*8*8, rows 256
+    (128, 256, 512, 3),    # non-square, padded beyond N + M
+    (256, 128, 512, 2),    # inverse space only
+    (512, 512, 0, 1),      # Np 1024 = 16*8*8, rows 512
+])
+def test_forward_adjoint_parity(prec, N, M, Np, spaces):
+    import torch
+    say(f"{NAMES[prec]}: {N}x{M} Np={Np} spaces={spaces}")
+    B = 3
+    imgs = [synth.mixed_lines(N, M, (3, 6), 0.1, np.random.default_rng([7, N, M, i])) for i in range(B)]
+    x = torch.from_numpy(np.stack([im.image for im in imgs])).cuda()
+    plan = F.FunnelPlan(B, N, M, Np, spaces, prec)
+    planes = plan.forward(x)
+    g = torch.Generator(device="cpu").manual_seed(N * 7 + M)
+    dP = torch.randn((B, plan.plane_elems), generator=g, dtype=torch.float32)
+    dI = plan.adjoint(dP.cuda())
+    torch.cuda.synchronize()
+    P = planes.cpu().numpy()
+    G = dI.cpu().numpy()
+    worst = 0.0
+    for b in range(B):
+        ref = O.forward(imgs[b].image.astype(np.float64), plan.Np)
+        want = [ref[0]] if spaces == 1 else ([ref[1]] if spaces == 2 else list(ref))
+        errs = [rel_l2(got, exp) for got, exp in zip(split_planes(P[b], N, M, plan.Np, spaces), want)]
+        errs.append(rel_l2(G[b], oracle_adjoint(dP[b].numpy(), N, M, plan.Np, spaces)))
+        worst = max(worst, *errs)
+    say(f"  worst rel L2 (planes and gradient) {worst:.2e}")
+    assert worst <= TOL[prec]
+
+
+# ---------------------------------------------------------------- 8 x 2048^2 workload
+
+SAMPLES = (0, 7)
+_cache = {}
+
+
+def workload():
+    """The 8 x 2048^2 batch (10 lines, sigma 0.1), the peak-loss gradient from
+    the FP32 planes, and the oracle's planes, gradients and peak lists for the
+    sampled images (computed once)."""
+    if _cache:
+        return _cache
+    import torch
+    say("precision workload 8 x 2048^2: FP32 reference run + oracle on samples")
+    imgs = synth.batch("precision", count=8, size=2048, seed=0)
+    x = torch.from_numpy(synth.stack(imgs)).cuda()
+    plan = F.FunnelPlan(8, 2048, 2048)
+    planes = plan.forward(x)
+    dP = torch.zeros_like(planes)
+    v, dv = plan.views(planes), plan.views(dP)
+    for b, im in enumerate(imgs):
+        for ln in im.lines:
+            space, r, c = pins.expected_cell(ln, 2048, 2048, plan.Np)
+            src, dst = (v.regular, dv.regular) if space == "regular" else (v.inverse, dv.inverse)
+            dst[b, r, c] = torch.sign(src[b, r, c])
+    torch.cuda.synchronize()
+    Np = plan.Np
+    mask = O.boundary_mask(2048, 2048, Np)
+    dPh = dP.cpu().numpy()
+    ref = {}
+    for b in SAMPLES:
+        pr, pi = O.forward(imgs[b].image.astype(np.float64), Np)
+        d = O.adjoint(dPh[b, :Np * 2048].reshape(Np, 2048).astype(np.float64),
+                      dPh[b, Np * 2048:].reshape(Np, 2048).astype(np.float64), 2048, 2048, Np)
+        ref[b] = (pr, pi, d)
+    _cache.update(x=x, dP=dP, ref=ref, Np=Np, mask=mask)
+    return _cache
+
+
+def decidable_prefix(Bp, lst, nm, mask, eps):
+    """Largest K such that the first K peaks of any plane within eps/2 of Bp
+    (element-wise) are the oracle's first K: the first K+1 listed values are
+    more than eps apart, and every cell at or above the (K+1)-th value (less
+    eps) differs from its largest neighbour by more than eps, so no local
+    maximum near the cut can appear, vanish or swap.  The threshold is 0 here,
+    which |P| always meets."""
+    vals = [Bp.flat[i] for i in lst]
+    for K in range(len(lst) - 1, 0, -1):
+        if any(abs(a - b) <= eps for a, b in zip(vals[:K], vals[1:K + 1])):
+            continue
+        region = (Bp >= vals[K] - eps) & ~mask
+        if np.any(np.abs(Bp - nm)[region] <= eps):
+            continue
+        return K
+    return 0
+
+
+def check_peaks(got_rec, b, planes_ref, mask, delta, K=16):
+    """GPU peak list against the oracle's on its decidable prefix."""
+    from test_gpu_peaks import nb_max
+    decided = []
+    for s, Pref in enumerate(planes_ref):
+        Bp = np.abs(Pref)
+        lst = O.peaks_list(Bp, K + 1, 0.0, 1, mask, True)
+        k = decidable_prefix(Bp, lst, nb_max(Bp, 1, True), mask, 2.5 * delta[s])
+        g = got_rec[b][s]
+        got = [int(r) * Bp.shape[1] + int(c) for r, c in zip(g["row"], g["col"])]
+        assert got[:k] == lst[:k], (b, s, k)
+        decided.append(k)
+    say(f"    image {b}: peaks identical to the oracle's on decidable prefixes {decided}")
+    return decided
+
+
+@pytest.mark.parametrize("prec", [F.FT_PREC_FP32] + PRECS, ids=["fp32"] + [NAMES[p] for p in PRECS])
+def test_precision_workload_2048(prec):
+    """8 x 2048^2, both spaces, forward + adjoint of the peak loss in the
+    given precision: rel L2 of planes and gradient against the oracle on two
+    sampled images, and the first 16 peaks of every sampled plane identical to
+    the oracle's wherever its ordering margin exceeds the measured error."""
+    import torch
+    w = workload()
+    say(f"  {NAMES[prec]}")
+    plan = F.FunnelPlan(8, 2048, 2048, 0, F.FT_SPACE_BOTH, prec)
+    planes = plan.forward(w["x"])
+    dI = plan.adjoint(w["dP"])
+    rec, cnt = plan.peaks(planes, K=16)
+    torch.cuda.synchronize()
+    got = F.peaks_to_numpy(rec, cnt)
+    v = plan.views(planes)
+    decided = []
+    for b in SAMPLES:
+        pr, pi, d = w["ref"][b]
+        gr, gi = v.regular[b].cpu().numpy(), v.inverse[b].cpu().numpy()
+        e_r, e_i = rel_l2(gr, pr), rel_l2(gi, pi)
+        e_d = rel_l2(dI[b].cpu().numpy(), d)
+        say(f"    image {b}: rel L2 regular {e_r:.2e} inverse {e_i:.2e} adjoint {e_d:.2e}")
+        assert max(e_r, e_i, e_d) <= TOL[prec]
+        delta = [np.abs(np.abs(gr) - np.abs(pr)).max(), np.abs(np.abs(gi) - np.abs(pi)).max()]
+        decided += check_peaks(got, b, (pr, pi), w["mask"], delta)
+    assert min(decided) >= 1 and sum(decided) >= 8, decided
