@@ -256,6 +256,8 @@ struct LayRow {
   static constexpr int kStride = L + L / 16 + 1;
   __device__ static __forceinline__ int addr(int line, int idx) { return line * kStride + idx + (idx >> 4); }
   static constexpr int size(int) { return kStride * LINES; }
+  // addr(line, x + d) = addr(line, x) + coff(d) when (x mod 16) + (d mod 16) < 16
+  static constexpr int coff(int d) { return d + (d >> 4); }
 };
 
 // ---------------------------------------------------------------- Stockham driver
@@ -417,48 +419,93 @@ struct FftR {
 
   // LDS exchange: outputs of pass I -> inputs of pass I+1.  Lay::addr(line, idx)
   // addresses a float (SPLIT) or float2 slot.
-  template <int I, bool PAIRED_OUT, bool PAIRED_IN, bool SPLIT, class Lay, class Buf>
-  __device__ static __forceinline__ void exchange(float2 (&v)[E], int line, int t, Buf* lds) {
+  //
+  // Unpaired maps put every index of a thread at x(t) + d with d a
+  // compile-time constant and no carry out of the low 4 bits of x(t), so the
+  // address is one per-thread base plus an immediate (Lay::coff): writes of a
+  // pass with NS | P (x = (t/NS) NS R + t mod NS, d = P R b + q NS; for the
+  // power-of-two radices here x mod 16 + d mod 16 < 16), reads when 16 divides
+  // P and L/R (x = t, d = P b + r L/R).  Paired maps keep per-slot addresses.
+  // (checked exhaustively at compile time: every thread t, slot and offset)
+  template <int I, bool PAIRED_OUT>
+  static constexpr bool lin_write() {
+    constexpr int R = kPlan.r[I], NS = ns<I>();
+    if (PAIRED_OUT || P % NS != 0) return false;
+    for (int t = 0; t < P; ++t)
+      for (int b = 0; b < E / R; ++b)
+        for (int q = 0; q < R; ++q) {
+          const int j = t + P * b, x = (t / NS) * NS * R + t % NS, d = P * R * b + q * NS;
+          if (x + d != (j / NS) * NS * R + j % NS + q * NS || x % 16 + d % 16 >= 16) return false;
+        }
+    return true;
+  }
+  template <int I, bool PAIRED_IN>
+  static constexpr bool lin_read() {
+    constexpr int R = kPlan.r[I], NB = L / R;
+    if (PAIRED_IN) return false;
+    for (int t = 0; t < P; ++t)
+      for (int b = 0; b < E / R; ++b)
+        for (int r = 0; r < R; ++r)
+          if (t % 16 + (P * b + r * NB) % 16 >= 16) return false;
+    return true;
+  }
+
+  template <int I, bool PAIRED_OUT, class Lay, class Buf, class GET>
+  __device__ static __forceinline__ void xwrite(int line, int t, Buf* lds, GET get) {
     constexpr int R = kPlan.r[I], NS = ns<I>(), BPT = E / R;
-    constexpr int R2 = kPlan.r[I + 1], NB2 = L / R2, BPT2 = E / R2;
-    if constexpr (!SPLIT) {
-      __syncthreads();
+    if constexpr (lin_write<I, PAIRED_OUT>()) {
+      Buf* base = lds + Lay::addr(line, (t / NS) * NS * R + t % NS);
+#pragma unroll
+      for (int b = 0; b < BPT; ++b)
+#pragma unroll
+        for (int q = 0; q < R; ++q) base[Lay::coff(P * R * b + q * NS)] = get(b * R + q);
+    } else {
 #pragma unroll
       for (int b = 0; b < BPT; ++b) {
         const int j = bfly<I, PAIRED_OUT>(t, b);
         const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-        for (int q = 0; q < R; ++q) lds[Lay::addr(line, base + q * NS)] = v[b * R + q];
+        for (int q = 0; q < R; ++q) lds[Lay::addr(line, base + q * NS)] = get(b * R + q);
       }
-      __syncthreads();
+    }
+  }
+
+  template <int I, bool PAIRED_IN, class Lay, class Buf, class PUT>
+  __device__ static __forceinline__ void xread(int line, int t, const Buf* lds, PUT put) {
+    constexpr int R2 = kPlan.r[I], NB2 = L / R2, BPT2 = E / R2;
+    if constexpr (lin_read<I, PAIRED_IN>()) {
+      const Buf* base = lds + Lay::addr(line, t);
+#pragma unroll
+      for (int b = 0; b < BPT2; ++b)
+#pragma unroll
+        for (int r = 0; r < R2; ++r) put(b * R2 + r, base[Lay::coff(P * b + r * NB2)]);
+    } else {
 #pragma unroll
       for (int b = 0; b < BPT2; ++b) {
-        const int j = bfly<I + 1, PAIRED_IN>(t, b);
+        const int j = bfly<I, PAIRED_IN>(t, b);
 #pragma unroll
-        for (int r = 0; r < R2; ++r) v[b * R2 + r] = lds[Lay::addr(line, j + r * NB2)];
+        for (int r = 0; r < R2; ++r) put(b * R2 + r, lds[Lay::addr(line, j + r * NB2)]);
       }
+    }
+  }
+
+  template <int I, bool PAIRED_OUT, bool PAIRED_IN, bool SPLIT, class Lay, class Buf>
+  __device__ static __forceinline__ void exchange(float2 (&v)[E], int line, int t, Buf* lds) {
+    if constexpr (!SPLIT) {
+      __syncthreads();
+      xwrite<I, PAIRED_OUT, Lay>(line, t, lds, [&](int s) { return v[s]; });
+      __syncthreads();
+      xread<I + 1, PAIRED_IN, Lay>(line, t, lds, [&](int s, float2 f) { v[s] = f; });
     } else {
 #pragma unroll
       for (int part = 0; part < 2; ++part) {
         __syncthreads();
-#pragma unroll
-        for (int b = 0; b < BPT; ++b) {
-          const int j = bfly<I, PAIRED_OUT>(t, b);
-          const int base = (j / NS) * NS * R + (j % NS);
-#pragma unroll
-          for (int q = 0; q < R; ++q) lds[Lay::addr(line, base + q * NS)] = part ? v[b * R + q].y : v[b * R + q].x;
-        }
+        xwrite<I, PAIRED_OUT, Lay>(line, t, lds, [&](int s) { return part ? v[s].y : v[s].x; });
         __syncthreads();
-#pragma unroll
-        for (int b = 0; b < BPT2; ++b) {
-          const int j = bfly<I + 1, PAIRED_IN>(t, b);
-#pragma unroll
-          for (int r = 0; r < R2; ++r) {
-            const float f = lds[Lay::addr(line, j + r * NB2)];
-            if (part) v[b * R2 + r].y = f;
-            else v[b * R2 + r].x = f;
-          }
-        }
+        xread<I + 1, PAIRED_IN, Lay>(line, t, lds, [&](int s, float f) {
+          if (part) v[s].y = f;
+          else v[s].x = f;
+        });
       }
     }
   }
@@ -486,6 +533,8 @@ template <int LINES>
 struct LayInterR {
   __device__ static __forceinline__ int addr(int line, int idx) { return (idx + (idx >> 4)) * LINES + line; }
   static constexpr int size(int L) { return (L + L / 16 + 1) * LINES; }
+  // addr(line, x + d) = addr(line, x) + coff(d) when (x mod 16) + (d mod 16) < 16
+  static constexpr int coff(int d) { return (d + (d >> 4)) * LINES; }
 };
 
 // Map the linear block index so that consecutive logical tiles run on the same
