@@ -282,6 +282,10 @@ ft_status validate_shape(int N, int M, int spaces, long long Np) {
     return fail(FT_ERR_UNSUPPORTED_SIZE, "no kernel for row length %d (image width)", M);
   if ((spaces & FT_SPACE_INVERSE) && !funnel::length_supported(N))
     return fail(FT_ERR_UNSUPPORTED_SIZE, "no kernel for row length %d (image height)", N);
+  // the kernels address one image's image, plane and spectrum blocks with
+  // 32-bit byte offsets
+  if (Np * (long long)(M > N ? M : N) * 8 >= (1ll << 31))
+    return fail(FT_ERR_UNSUPPORTED_SIZE, "per-image planes of %lld x %d exceed 2 GiB", Np, M > N ? M : N);
   return FT_OK;
 }
 

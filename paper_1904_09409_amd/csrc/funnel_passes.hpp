@@ -297,6 +297,57 @@ struct FastCfg {
 #define FUNNEL_COL_VARIANTS(X) X(0, 16, 4) X(1, 16, 8) X(2, 16, 16) X(3, 32, 4) X(4, 32, 8) X(5, 32, 16)
 constexpr int kColVariants = 6;
 
+// Raw buffer access: 32-bit byte offsets from a per-block base, and hardware
+// range checking (offsets at or beyond `bytes`, including negative offsets,
+// read 0 and drop stores), which replaces per-element bounds tests and
+// 64-bit address arithmetic in the column kernels.
+struct GBuf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ GBuf(const void* base, long long bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
+                                            (int)(bytes < 0x7fffffffll ? bytes : 0x7fffffffll), 0x00020000)) {}
+  // (values move through vector registers component by component: a bit_cast
+  // to HIP's float2/float4 structs would go through scratch memory)
+  __device__ __forceinline__ float ld1(int off) const {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  }
+  __device__ __forceinline__ float2 ld2(int off) const {
+    const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    return make_float2(__uint_as_float(u[0]), __uint_as_float(u[1]));
+  }
+  __device__ __forceinline__ float4 ld4(int off) const {
+    const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return make_float4(__uint_as_float(u[0]), __uint_as_float(u[1]), __uint_as_float(u[2]), __uint_as_float(u[3]));
+  }
+  __device__ __forceinline__ void st1(float v, int off) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+  }
+  __device__ __forceinline__ void st2(float2 v, int off) const {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    const u2 u = {__float_as_uint(v.x), __float_as_uint(v.y)};
+    __builtin_amdgcn_raw_buffer_store_b64(u, r, off, 0, 0);
+  }
+  __device__ __forceinline__ void st4(float4 v, int off) const {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    const u4 u = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w)};
+    __builtin_amdgcn_raw_buffer_store_b128(u, r, off, 0, 0);
+  }
+};
+
+__device__ __forceinline__ float2 sel2(bool c, float2 a, float2 b) {
+  return make_float2(c ? a.x : b.x, c ? a.y : b.y);
+}
+
+// Pass A output for frequency row k of column pair pg, from Z_k and Z_{L-k}
+// of the pair's complex transform: A = (Z_k + conj Z_{L-k})/2 and
+// B = (Z_k - conj Z_{L-k})/(2i), times scale (-1)^k.  Rows outside 1 .. H fall
+// outside the buffer and are dropped.
+__device__ __forceinline__ void emit_pair(GBuf dst, int k, float2 zk, float2 zm, float scale, int npairs, int pg) {
+  const float sc = (k & 1) ? -0.5f * scale : 0.5f * scale;
+  const float ux = zk.x - zm.x, uy = zk.y + zm.y;
+  dst.st4(make_float4(sc * (zk.x + zm.x), sc * (zk.y - zm.y), sc * uy, -sc * ux), ((k - 1) * npairs + pg) * 16);
+}
+
 __device__ __forceinline__ float2 herm_direct(float4 x) { return make_float2(x.x - x.w, x.y + x.z); }  // A + iB
 __device__ __forceinline__ float2 herm_mirror(float4 x) { return make_float2(x.x + x.w, x.z - x.y); }  // conj A + i conj B
 
@@ -319,35 +370,37 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
   const int npairs = nlines >> 1;
   const int pg = tile * LINES + pair;
   const bool active = pg < npairs;
-  const float* src = in + map.in(img);
+  // one image's lin x nlines block (rows of the padded frame off .. off+lin-1)
+  const GBuf src(in + map.in(img), (long long)lin * nlines * 4);
 
   float2 v[E];
+  if constexpr (TRANS) {
+    // line 2pg and 2pg+1 of the image rows; rows outside [0, lin) are zero
+    const int o0 = (2 * pg * lin + t - off) * 4;
 #pragma unroll
-  for (int b = 0; b < E / R0; ++b)
+    for (int b = 0; b < E / R0; ++b)
 #pragma unroll
-    for (int r = 0; r < R0; ++r) {
-      const int rr = t + P * b + r * NB0 - off;
-      float2 z = make_float2(0.f, 0.f);
-      if (active && rr >= 0 && rr < lin) {
-        if constexpr (TRANS) {
-          z.x = src[(long long)(2 * pg) * lin + rr];
-          z.y = src[(long long)(2 * pg + 1) * lin + rr];
-        } else {
-          z = *reinterpret_cast<const float2*>(src + (long long)rr * nlines + 2 * pg);
-        }
+      for (int r = 0; r < R0; ++r) {
+        const int rr = t + P * b + r * NB0 - off;
+        const int o = o0 + (P * b + r * NB0) * 4;
+        float2 z = make_float2(0.f, 0.f);
+        if (active && (unsigned)rr < (unsigned)lin) z = make_float2(src.ld1(o), src.ld1(o + lin * 4));
+        v[b * R0 + r] = z;
       }
-      v[b * R0 + r] = z;
-    }
+  } else {
+    // columns 2pg, 2pg+1; rows outside [0, lin) fall outside the buffer and read 0
+    const int o0 = ((t - off) * nlines + 2 * pg) * 4;
+    const int rs = nlines * 4;
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[b * R0 + r] = src.ld2(o0 + (P * b + r * NB0) * rs);
+  }
   Eng::template run<false, true, true, Lay>(v, pair, t, lds, tw);
   if (!active) return;
 
-  float4* dst = reinterpret_cast<float4*>(out + map.out(img));
-  auto emit = [&](int k, float2 zk, float2 zm) {
-    // A = (Z_k + conj Z_{L-k})/2, B = (Z_k - conj Z_{L-k})/(2i), times scale (-1)^k
-    const float sc = (k & 1) ? -0.5f * scale : 0.5f * scale;
-    const float ux = zk.x - zm.x, uy = zk.y + zm.y;
-    dst[(long long)(k - 1) * npairs + pg] = make_float4(sc * (zk.x + zm.x), sc * (zk.y - zm.y), sc * uy, -sc * ux);
-  };
+  // half-spectrum rows 1 .. H: rows k outside that range fall outside the buffer
+  const GBuf dst(out + map.out(img), (long long)H * npairs * 16);
 #pragma unroll
   for (int c = 0; c < BPTL / 2; ++c) {
     const int ja = t + P * c;
@@ -357,10 +410,12 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
     const float2* vb = v + (2 * c + 1) * RL;
 #pragma unroll
     for (int q = 0; q < RL; ++q) {
-      const int ka = ja + q * NBL;
-      if (ka >= 1 && ka <= H) emit(ka, va[q], zero ? va[(RL - q) % RL] : vb[RL - 1 - q]);
-      const int kb = jb + q * NBL;
-      if (kb >= 1 && kb <= H) emit(kb, vb[q], zero ? vb[RL - 1 - q] : va[RL - 1 - q]);
+      // partners chosen by value (a select of array elements would make the
+      // compiler keep the arrays in scratch memory)
+      const float2 pa = sel2(zero, va[(RL - q) % RL], vb[RL - 1 - q]);
+      const float2 pb = sel2(zero, vb[RL - 1 - q], va[RL - 1 - q]);
+      emit_pair(dst, ja + q * NBL, va[q], pa, scale, npairs, pg);
+      emit_pair(dst, jb + q * NBL, vb[q], pb, scale, npairs, pg);
     }
   }
 }
@@ -384,11 +439,11 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
   const int npairs = nlines >> 1;
   const int pg = tile * LINES + pair;
   const bool active = pg < npairs;
-  const float4* src = reinterpret_cast<const float4*>(in + map.in(img));
+  // half-spectrum rows 1 .. L/2-1; row 0 (and anything outside) reads 0
+  const GBuf src(in + map.in(img), (long long)(L / 2 - 1) * npairs * 16);
 
-  auto load = [&](int k) -> float4 {  // stored coefficient k (1 .. L/2-1) times (-1)^k; 0 for k = 0
-    float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (active && k >= 1) x = src[(long long)(k - 1) * npairs + pg];
+  auto load = [src, npairs, pg](int k) -> float4 {  // coefficient k (1 .. L/2-1) times (-1)^k; 0 for k = 0
+    float4 x = src.ld4(((k - 1) * npairs + pg) * 16);
     if (k & 1) x = make_float4(-x.x, -x.y, -x.z, -x.w);
     return x;
   };
@@ -428,7 +483,11 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
   Eng::template run<true, false, true, Lay>(v, pair, t, lds, tw);
   if (!active) return;
 
-  float* dst = out + map.out(img);
+  // one image's nout x nlines block (or nlines x nout, transposed)
+  const GBuf dst(out + map.out(img), (long long)nout * nlines * 4);
+  // output row r = t + P b + q NBL - r0: offsets at o0 + (P b + q NBL) * step
+  const int o0 = TRANS ? (2 * pg * nout + t - r0) * 4 : ((t - r0) * nlines + 2 * pg) * 4;
+  const int step = TRANS ? 4 : nlines * 4;
   float2 old[E];
   if constexpr (ACCUM) {
     // read every old value first so the adds do not serialise on memory latency
@@ -436,36 +495,29 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
     for (int b = 0; b < BPTL; ++b)
 #pragma unroll
       for (int q = 0; q < RL; ++q) {
-        const int r = t + P * b + q * NBL - r0;
-        float2 o = make_float2(0.f, 0.f);
-        if (r >= 0 && r < nout) {
-          if constexpr (TRANS) {
-            o.x = dst[(long long)(2 * pg) * nout + r];
-            o.y = dst[(long long)(2 * pg + 1) * nout + r];
-          } else {
-            o = *reinterpret_cast<const float2*>(dst + (long long)r * nlines + 2 * pg);
-          }
-        }
-        old[b * RL + q] = o;
+        const int o = o0 + (P * b + q * NBL) * step;
+        if constexpr (TRANS) old[b * RL + q] = make_float2(dst.ld1(o), dst.ld1(o + nout * 4));
+        else old[b * RL + q] = dst.ld2(o);
       }
   }
 #pragma unroll
   for (int b = 0; b < BPTL; ++b) {
-    const int j = t + P * b;
 #pragma unroll
     for (int q = 0; q < RL; ++q) {
-      const int r = j + q * NBL - r0;
-      if (r < 0 || r >= nout) continue;
+      const int r = t + P * b + q * NBL - r0;
+      const int o = o0 + (P * b + q * NBL) * step;
       float a = scale * v[b * RL + q].x, bb = scale * v[b * RL + q].y;
       if constexpr (ACCUM) {
         a += old[b * RL + q].x;
         bb += old[b * RL + q].y;
       }
       if constexpr (TRANS) {
-        dst[(long long)(2 * pg) * nout + r] = a;
-        dst[(long long)(2 * pg + 1) * nout + r] = bb;
+        // rows outside [0, nout) would land in the neighbouring line
+        if (r < 0 || r >= nout) continue;
+        dst.st1(a, o);
+        dst.st1(bb, o + nout * 4);
       } else {
-        *reinterpret_cast<float2*>(dst + (long long)r * nlines + 2 * pg) = make_float2(a, bb);
+        dst.st2(make_float2(a, bb), o);   // rows outside [0, nout) fall outside the buffer
       }
     }
   }
