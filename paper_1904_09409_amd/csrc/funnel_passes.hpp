@@ -33,25 +33,46 @@ constexpr int pow2_floor(int x) {
   return p;
 }
 
-template <int L>
+// LDS-resident kernels (any 7-smooth length).  Variant V sets the threads
+// per transform P (each thread takes ceil(L/R / P) butterflies of a radix-R
+// pass) and with it how many column pairs share a block:
+//   V = 0: P = L / (largest radix), pairs a power of two <= 16;
+//   V = 1: P <= 128, as many pairs as 1024 threads and ~150 KB of LDS allow;
+//   V = 2: P <= 64, likewise.
+// More pairs per block means wider row segments in HBM for the column
+// passes; fewer threads per transform means more butterflies per thread.
+constexpr int kGenVariants = 3;
+
+template <int L, int V = 0>
 struct ColCfg {
-  static constexpr int P = threads_per_transform(L);
-  // column pairs per block: a power of two that fits 1024 threads and ~150 KB of LDS
+  static constexpr int TPT = threads_per_transform(L);
+  static constexpr int P = V == 0 ? TPT : (V == 1 ? (TPT < 128 ? TPT : 128) : (TPT < 64 ? TPT : 64));
   static constexpr int lines_by_threads = 1024 / P > 0 ? 1024 / P : 1;
   static constexpr int lines_by_lds = (150 * 1024) / (8 * (L + L / 16 + 1));
   static constexpr int LINES0 = lines_by_threads < lines_by_lds ? lines_by_threads : lines_by_lds;
-  static constexpr int LINES = pow2_floor(LINES0 > 16 ? 16 : (LINES0 < 1 ? 1 : LINES0));
+  static constexpr int LINES = V == 0 ? pow2_floor(LINES0 > 16 ? 16 : (LINES0 < 1 ? 1 : LINES0))
+                                      : (LINES0 < 1 ? 1 : LINES0);
   static constexpr int THREADS = LINES * P;
+  // a variant other than 0 exists only where it differs from variant 0
+  static constexpr bool distinct() {
+    return V == 0 || (V < kGenVariants && (P != ColCfg<L, 0>::P || LINES != ColCfg<L, 0>::LINES) &&
+                      (V == 1 || P != ColCfg<L, 1>::P));
+  }
 };
 
-template <int M>
+// V = 0: up to 256 threads per block; V = 1: up to 512
+constexpr int kGenRowVariants = 2;
+
+template <int M, int V = 0>
 struct RowCfg {
   static constexpr int P = threads_per_transform(M);
-  static constexpr int rows_by_threads = 256 / P > 0 ? 256 / P : 1;
+  static constexpr int TPB = V == 0 ? 256 : 512;
+  static constexpr int rows_by_threads = TPB / P > 0 ? TPB / P : 1;
   static constexpr int rows_by_lds = (64 * 1024) / (8 * (M + M / 16 + 1));
   static constexpr int ROWS0 = rows_by_threads < rows_by_lds ? rows_by_threads : rows_by_lds;
   static constexpr int ROWS = ROWS0 < 1 ? 1 : ROWS0;
   static constexpr int THREADS = ROWS * P;
+  static constexpr bool distinct() { return V == 0 || (V < kGenRowVariants && ROWS != RowCfg<M, 0>::ROWS); }
 };
 
 // ------------------------------------------------------------------ pass A / adjoint of C
@@ -61,11 +82,11 @@ struct RowCfg {
 // moves the origin to the frame centre).  TRANS = false: lines are the
 // columns of a row-major [lin][nlines] array; TRANS = true: lines are the rows
 // of a row-major [nlines][lin] array.  Output: complex [L/2-1][nlines].
-template <int L, bool TRANS>
-__global__ void __launch_bounds__(ColCfg<L>::THREADS)
+template <int L, bool TRANS, int V>
+__global__ void __launch_bounds__((ColCfg<L, V>::THREADS))
     k_r2c_half(const float* __restrict__ in, float2* __restrict__ out, int nlines, int lin, int off,
                ImgMap map, float scale, const float2* __restrict__ tw) {
-  using Cfg = ColCfg<L>;
+  using Cfg = ColCfg<L, V>;
   constexpr int P = Cfg::P, LINES = Cfg::LINES, H = L / 2 - 1;
   using Lay = typename std::conditional<TRANS, LayRow<LINES, L>, LayInter<LINES>>::type;
   __shared__ float2 lds[Lay::size(L)];
@@ -121,11 +142,11 @@ __global__ void __launch_bounds__(ColCfg<L>::THREADS)
 // X~[k] = (-1)^k X[k], X~[L-k] = conj X~[k], X~[0] = X~[L/2] = 0.  Only rows
 // r in [r0, r0 + nout) are stored.  TRANS = false: out is [nout][nlines];
 // TRANS = true: out is [nlines][nout].  ACCUM adds to out instead of storing.
-template <int L, bool TRANS, bool ACCUM>
-__global__ void __launch_bounds__(ColCfg<L>::THREADS)
+template <int L, bool TRANS, bool ACCUM, int V>
+__global__ void __launch_bounds__((ColCfg<L, V>::THREADS))
     k_c2r_half(const float2* __restrict__ in, float* __restrict__ out, int nlines, int r0, int nout,
                ImgMap map, float scale, const float2* __restrict__ tw) {
-  using Cfg = ColCfg<L>;
+  using Cfg = ColCfg<L, V>;
   constexpr int P = Cfg::P, LINES = Cfg::LINES, H = L / 2 - 1;
   using Lay = typename std::conditional<TRANS, LayRow<LINES, L>, LayInter<LINES>>::type;
   static_assert((L / 2) * LINES * 2 <= Lay::size(L), "staging must fit the transform buffer");
@@ -187,10 +208,10 @@ __global__ void __launch_bounds__(ColCfg<L>::THREADS)
 //          dS[i] = (1-t_a) dg[x_a] + t_b dg[x_b] where x_a is the sample whose
 //          i0 is i and x_b the one whose i0 is i-1 (at most one each, as the
 //          sampling ratio 2 n2 / Lp is below 1).
-template <int M, bool ADJ>
-__global__ void __launch_bounds__(RowCfg<M>::THREADS)
+template <int M, bool ADJ, int V>
+__global__ void __launch_bounds__((RowCfg<M, V>::THREADS))
     k_row_nvmt(float2* __restrict__ data, int Lp, int h, long long img_stride, const float2* __restrict__ tw) {
-  using Cfg = RowCfg<M>;
+  using Cfg = RowCfg<M, V>;
   constexpr int P = Cfg::P, ROWS = Cfg::ROWS;
   using Lay = LayRow<ROWS, M>;
   __shared__ float2 lds[Lay::size(M)];
@@ -663,8 +684,12 @@ unsigned col_variant_mask_t() {
   if constexpr (FastCfg<L, e, l>::valid && (PREC == kPrecFP32 || mfma_fits(L, e, FastCfg<L, e, l>::THREADS))) m |= 1u << i;
   FUNNEL_COL_VARIANTS(FUNNEL_V)
 #undef FUNNEL_V
-  if (PREC != kPrecFP32) return m;
-  return m ? m : 1u;  // lengths without a register-resident kernel: the generic one, variant 0
+  if (PREC != kPrecFP32 || m) return m;
+  // lengths without a register-resident kernel: the LDS-resident variants
+  m = 1u;
+  if constexpr (ColCfg<L, 1>::distinct()) m |= 2u;
+  if constexpr (ColCfg<L, 2>::distinct()) m |= 4u;
+  return m;
 }
 
 template <int M, int PREC>
@@ -674,8 +699,10 @@ unsigned row_variant_mask_t() {
   if constexpr (RowFastCfg<M, e, t>::valid && (PREC == kPrecFP32 || mfma_fits(M, e, RowFastCfg<M, e, t>::THREADS))) m |= 1u << i;
   FUNNEL_ROW_VARIANTS(FUNNEL_V)
 #undef FUNNEL_V
-  if (PREC != kPrecFP32) return m;
-  return m ? m : 1u;
+  if (PREC != kPrecFP32 || m) return m;
+  m = 1u;
+  if constexpr (RowCfg<M, 1>::distinct()) m |= 2u;
+  return m;
 }
 
 template <int L, int PREC>
@@ -702,14 +729,23 @@ hipError_t launch_r2c_t(int variant, bool trans, const float* in, float2* out, i
   if constexpr (PREC != kPrecFP32) {
     return hipErrorInvalidValue;
   } else {
-    if (col_variant_mask_t<L, PREC>() != 1u || variant != 0) return hipErrorInvalidValue;
-    using Cfg = ColCfg<L>;
-    dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
-    if (trans)
-      k_r2c_half<L, true><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw);
-    else
-      k_r2c_half<L, false><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw);
-    return hipGetLastError();
+    const unsigned m = col_variant_mask_t<L, PREC>();
+    if (variant < 0 || variant >= kGenVariants || !(m & (1u << variant)) || (m & ~7u)) return hipErrorInvalidValue;
+    auto go = [&](auto vc) {
+      constexpr int V = decltype(vc)::value;
+      if constexpr (ColCfg<L, V>::distinct()) {
+        using Cfg = ColCfg<L, V>;
+        dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
+        if (trans)
+          k_r2c_half<L, true, V><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw);
+        else
+          k_r2c_half<L, false, V><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw);
+      }
+      return hipGetLastError();
+    };
+    if (variant == 0) return go(std::integral_constant<int, 0>());
+    if (variant == 1) return go(std::integral_constant<int, 1>());
+    return go(std::integral_constant<int, 2>());
   }
 }
 
@@ -744,21 +780,30 @@ hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, f
   if constexpr (PREC != kPrecFP32) {
     return hipErrorInvalidValue;
   } else {
-    if (col_variant_mask_t<L, PREC>() != 1u || variant != 0) return hipErrorInvalidValue;
-    using Cfg = ColCfg<L>;
-    dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
-    if (trans) {
-      if (accum)
-        k_c2r_half<L, true, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
-      else
-        k_c2r_half<L, true, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
-    } else {
-      if (accum)
-        k_c2r_half<L, false, true><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
-      else
-        k_c2r_half<L, false, false><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
-    }
-    return hipGetLastError();
+    const unsigned m = col_variant_mask_t<L, PREC>();
+    if (variant < 0 || variant >= kGenVariants || !(m & (1u << variant)) || (m & ~7u)) return hipErrorInvalidValue;
+    auto go = [&](auto vc) {
+      constexpr int V = decltype(vc)::value;
+      if constexpr (ColCfg<L, V>::distinct()) {
+        using Cfg = ColCfg<L, V>;
+        dim3 grid((nlines / 2 + Cfg::LINES - 1) / Cfg::LINES, batch), block(Cfg::THREADS);
+        if (trans) {
+          if (accum)
+            k_c2r_half<L, true, true, V><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
+          else
+            k_c2r_half<L, true, false, V><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
+        } else {
+          if (accum)
+            k_c2r_half<L, false, true, V><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
+          else
+            k_c2r_half<L, false, false, V><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw);
+        }
+      }
+      return hipGetLastError();
+    };
+    if (variant == 0) return go(std::integral_constant<int, 0>());
+    if (variant == 1) return go(std::integral_constant<int, 1>());
+    return go(std::integral_constant<int, 2>());
   }
 }
 
@@ -786,14 +831,23 @@ hipError_t launch_row_t(int variant, bool adj, float2* data, int Lp, int h, long
   if constexpr (PREC != kPrecFP32) {
     return hipErrorInvalidValue;
   } else {
-    if (row_variant_mask_t<M, PREC>() != 1u || variant != 0) return hipErrorInvalidValue;
-    using Cfg = RowCfg<M>;
-    dim3 grid((h + Cfg::ROWS - 1) / Cfg::ROWS, batch), block(Cfg::THREADS);
-    if (adj)
-      k_row_nvmt<M, true><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
-    else
-      k_row_nvmt<M, false><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
-    return hipGetLastError();
+    const unsigned m = row_variant_mask_t<M, PREC>();
+    if (variant < 0 || variant >= kGenRowVariants || !(m & (1u << variant)) || (m & ~3u))
+      return hipErrorInvalidValue;
+    auto go = [&](auto vc) {
+      constexpr int V = decltype(vc)::value;
+      if constexpr (RowCfg<M, V>::distinct()) {
+        using Cfg = RowCfg<M, V>;
+        dim3 grid((h + Cfg::ROWS - 1) / Cfg::ROWS, batch), block(Cfg::THREADS);
+        if (adj)
+          k_row_nvmt<M, true, V><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
+        else
+          k_row_nvmt<M, false, V><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
+      }
+      return hipGetLastError();
+    };
+    if (variant == 0) return go(std::integral_constant<int, 0>());
+    return go(std::integral_constant<int, 1>());
   }
 }
 
