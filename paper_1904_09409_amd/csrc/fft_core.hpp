@@ -340,12 +340,10 @@ namespace funnel {
 
 // ---------------------------------------------------------------- register-resident engine
 //
-// FftR keeps the E = L/P elements of a thread in registers for the whole
-// transform; pass I sees them as BPT_I butterflies of radix R_I (E = BPT_I R_I
-// for every pass, so P must divide every L/R_I).  Between passes the data goes
-// through LDS once.  With SPLIT the real and the imaginary parts are exchanged
-// one after the other through a float buffer of half the size, which lets two
-// blocks share a compute unit.
+// FftR keeps a thread's elements in registers for the whole transform; pass I
+// sees them as BPT_I butterflies of radix R_I, and between passes the data
+// goes through LDS once.  With SPLIT the real and the imaginary parts are
+// exchanged one after the other through a float buffer of half the size.
 //
 // Butterfly maps: slot b of pass I is butterfly t + P b, except in a PAIRED
 // pass, where slot 2c is ja = t + P c (ja < NB/2) and slot 2c+1 its Hermitian
@@ -353,6 +351,12 @@ namespace funnel {
 // inputs idx and L - idx; in the last pass (NS = NB) they write outputs idx and
 // L - idx.  Keeping both in one thread lets a real-input transform separate
 // its two columns, and a Hermitian inverse build its input, in registers.
+//
+// BPT_I = ceil(NB_I / P) (pairs: ceil(NB_I/2 / P)), so P need not divide the
+// butterfly counts of mixed-radix lengths: slots past the last butterfly are
+// computed on whatever they hold and never written to LDS or read from it
+// (ok() is false there).  When P divides every count the guards fold away.
+// Registers: v[EM], EM = the largest BPT_I R_I over the passes.
 
 constexpr RadixPlan reversed(RadixPlan p) {
   RadixPlan q = p;
@@ -360,23 +364,44 @@ constexpr RadixPlan reversed(RadixPlan p) {
   return q;
 }
 
-// REV runs the radices smallest-first (the pairing needs an even number of
-// butterflies per thread in the paired pass).
+constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// REV runs the radices smallest-first (for the radix-16 lengths the pairing
+// then falls on the small last radix of the forward order).
 template <int L, int P, bool INV, bool REV = false>
 struct FftR {
   static constexpr RadixPlan kPlan = REV ? reversed(radix_plan(L)) : radix_plan(L);
-  static constexpr int E = L / P;
   static_assert(kPlan.n > 0, "transform length must be 7-smooth");
+
+  template <int I, bool PAIRED>
+  static constexpr int bpt() {
+    constexpr int NB = L / kPlan.r[I];
+    return PAIRED ? 2 * cdiv(NB / 2, P) : cdiv(NB, P);
+  }
+  // every butterfly slot of pass I is a real butterfly for every thread
+  template <int I, bool PAIRED>
+  static constexpr bool exact() {
+    constexpr int NB = L / kPlan.r[I];
+    return PAIRED ? (NB / 2) % P == 0 : NB % P == 0;
+  }
+  static constexpr int slots() {
+    int m = 0;
+    for (int i = 0; i < kPlan.n; ++i) {
+      const int NB = L / kPlan.r[i];
+      const int a = cdiv(NB, P) * kPlan.r[i], b = 2 * cdiv(NB / 2, P) * kPlan.r[i];
+      m = a > m ? a : m;
+      m = b > m ? b : m;
+    }
+    return m;
+  }
+  static constexpr int EM = slots();
+  static constexpr int E = EM;
 
   template <int I>
   static constexpr int ns() {
     int p = 1;
     for (int i = 0; i < I; ++i) p *= kPlan.r[i];
     return p;
-  }
-  template <int I>
-  static constexpr bool fits() {
-    return (L / kPlan.r[I]) % P == 0;
   }
 
   template <int I, bool PAIRED>
@@ -390,15 +415,22 @@ struct FftR {
       return ja == 0 ? NB / 2 : NB - ja;
     }
   }
+  // slot b of pass I holds a butterfly of this thread
+  template <int I, bool PAIRED>
+  __device__ static __forceinline__ bool ok(int t, int b) {
+    constexpr int NB = L / kPlan.r[I];
+    if constexpr (exact<I, PAIRED>()) return true;
+    else if constexpr (PAIRED) return t + P * (b >> 1) < NB / 2;
+    else return t + P * b < NB;
+  }
 
   // twiddle (base from the table, powers by balanced products) + R-point DFT.
   // One table read per butterfly instead of R - 1 keeps the memory pipeline
   // free for the data; the powers carry the table entry's rounding times r
   // (a few 1e-7 relative, well inside the FP32 error budget).
   template <int I, bool PAIRED>
-  __device__ static __forceinline__ void compute(float2 (&v)[E], int t, const float2* __restrict__ tw) {
-    constexpr int R = kPlan.r[I], NS = ns<I>(), BPT = E / R;
-    static_assert(fits<I>(), "P must divide L/R for every pass");
+  __device__ static __forceinline__ void compute(float2 (&v)[EM], int t, const float2* __restrict__ tw) {
+    constexpr int R = kPlan.r[I], NS = ns<I>(), BPT = bpt<I, PAIRED>();
 #pragma unroll
     for (int b = 0; b < BPT; ++b) {
       float2* x = v + b * R;
@@ -420,19 +452,18 @@ struct FftR {
   // LDS exchange: outputs of pass I -> inputs of pass I+1.  Lay::addr(line, idx)
   // addresses a float (SPLIT) or float2 slot.
   //
-  // Unpaired maps put every index of a thread at x(t) + d with d a
+  // Unpaired exact maps put every index of a thread at x(t) + d with d a
   // compile-time constant and no carry out of the low 4 bits of x(t), so the
   // address is one per-thread base plus an immediate (Lay::coff): writes of a
-  // pass with NS | P (x = (t/NS) NS R + t mod NS, d = P R b + q NS; for the
-  // power-of-two radices here x mod 16 + d mod 16 < 16), reads when 16 divides
-  // P and L/R (x = t, d = P b + r L/R).  Paired maps keep per-slot addresses.
+  // pass with NS | P (x = (t/NS) NS R + t mod NS, d = P R b + q NS), reads
+  // with x = t, d = P b + r L/R.  Other maps keep per-slot addresses.
   // (checked exhaustively at compile time: every thread t, slot and offset)
   template <int I, bool PAIRED_OUT>
   static constexpr bool lin_write() {
     constexpr int R = kPlan.r[I], NS = ns<I>();
-    if (PAIRED_OUT || P % NS != 0) return false;
+    if (PAIRED_OUT || !exact<I, false>() || P % NS != 0) return false;
     for (int t = 0; t < P; ++t)
-      for (int b = 0; b < E / R; ++b)
+      for (int b = 0; b < bpt<I, false>(); ++b)
         for (int q = 0; q < R; ++q) {
           const int j = t + P * b, x = (t / NS) * NS * R + t % NS, d = P * R * b + q * NS;
           if (x + d != (j / NS) * NS * R + j % NS + q * NS || x % 16 + d % 16 >= 16) return false;
@@ -442,9 +473,9 @@ struct FftR {
   template <int I, bool PAIRED_IN>
   static constexpr bool lin_read() {
     constexpr int R = kPlan.r[I], NB = L / R;
-    if (PAIRED_IN) return false;
+    if (PAIRED_IN || !exact<I, false>()) return false;
     for (int t = 0; t < P; ++t)
-      for (int b = 0; b < E / R; ++b)
+      for (int b = 0; b < bpt<I, false>(); ++b)
         for (int r = 0; r < R; ++r)
           if (t % 16 + (P * b + r * NB) % 16 >= 16) return false;
     return true;
@@ -452,7 +483,7 @@ struct FftR {
 
   template <int I, bool PAIRED_OUT, class Lay, class Buf, class GET>
   __device__ static __forceinline__ void xwrite(int line, int t, Buf* lds, GET get) {
-    constexpr int R = kPlan.r[I], NS = ns<I>(), BPT = E / R;
+    constexpr int R = kPlan.r[I], NS = ns<I>(), BPT = bpt<I, PAIRED_OUT>();
     if constexpr (lin_write<I, PAIRED_OUT>()) {
       Buf* base = lds + Lay::addr(line, (t / NS) * NS * R + t % NS);
 #pragma unroll
@@ -462,6 +493,7 @@ struct FftR {
     } else {
 #pragma unroll
       for (int b = 0; b < BPT; ++b) {
+        if (!ok<I, PAIRED_OUT>(t, b)) continue;
         const int j = bfly<I, PAIRED_OUT>(t, b);
         const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
@@ -472,7 +504,7 @@ struct FftR {
 
   template <int I, bool PAIRED_IN, class Lay, class Buf, class PUT>
   __device__ static __forceinline__ void xread(int line, int t, const Buf* lds, PUT put) {
-    constexpr int R2 = kPlan.r[I], NB2 = L / R2, BPT2 = E / R2;
+    constexpr int R2 = kPlan.r[I], NB2 = L / R2, BPT2 = bpt<I, PAIRED_IN>();
     if constexpr (lin_read<I, PAIRED_IN>()) {
       const Buf* base = lds + Lay::addr(line, t);
 #pragma unroll
@@ -482,6 +514,7 @@ struct FftR {
     } else {
 #pragma unroll
       for (int b = 0; b < BPT2; ++b) {
+        if (!ok<I, PAIRED_IN>(t, b)) continue;
         const int j = bfly<I, PAIRED_IN>(t, b);
 #pragma unroll
         for (int r = 0; r < R2; ++r) put(b * R2 + r, lds[Lay::addr(line, j + r * NB2)]);
@@ -490,7 +523,7 @@ struct FftR {
   }
 
   template <int I, bool PAIRED_OUT, bool PAIRED_IN, bool SPLIT, class Lay, class Buf>
-  __device__ static __forceinline__ void exchange(float2 (&v)[E], int line, int t, Buf* lds) {
+  __device__ static __forceinline__ void exchange(float2 (&v)[EM], int line, int t, Buf* lds) {
     if constexpr (!SPLIT) {
       __syncthreads();
       xwrite<I, PAIRED_OUT, Lay>(line, t, lds, [&](int s) { return v[s]; });
@@ -511,10 +544,11 @@ struct FftR {
   }
 
   // All passes after the caller loaded pass 0's inputs into v (with the
-  // PAIRED_FIRST map).  On return v holds the last pass's outputs (with the
-  // PAIRED_LAST map): slot b, output q is element j + q * (L / R_last).
+  // PAIRED_FIRST map, slots b with ok<0>).  On return v holds the last pass's
+  // outputs (with the PAIRED_LAST map): slot b, output q is element
+  // j + q * (L / R_last), for the slots with ok<last>.
   template <bool PAIRED_FIRST, bool PAIRED_LAST, bool SPLIT, class Lay, class Buf, int I = 0>
-  __device__ static __forceinline__ void run(float2 (&v)[E], int line, int t, Buf* lds,
+  __device__ static __forceinline__ void run(float2 (&v)[EM], int line, int t, Buf* lds,
                                              const float2* __restrict__ tw) {
     constexpr bool FIRST = I == 0, LAST = I == kPlan.n - 1;
     constexpr bool PAIRED = (FIRST && PAIRED_FIRST) || (LAST && PAIRED_LAST);

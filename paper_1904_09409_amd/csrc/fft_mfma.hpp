@@ -122,8 +122,14 @@ struct FftM {
   static constexpr RadixPlan kPlan = Outer::kPlan;  // the caller-facing layout
   static constexpr RadixPlan kM = mfma_plan(L);
   static constexpr int E = L / P;
+  static constexpr int EM = E;
   static constexpr int THREADS = NLINES * P;
   static_assert(kM.n > 0, "matrix-core passes need a power-of-two length in 64 .. 4096");
+  // caller-facing butterfly counts and guards: FftR's (exact for powers of two)
+  template <int I, bool PAIRED>
+  static constexpr int bpt() { return Outer::template bpt<I, PAIRED>(); }
+  template <int I, bool PAIRED>
+  __device__ static __forceinline__ bool ok(int t, int b) { return Outer::template ok<I, PAIRED>(t, b); }
   static_assert(THREADS % 64 == 0, "whole waves");
   static_assert(E % 4 == 0, "four elements per lane and group");
 

@@ -27,11 +27,11 @@ enum Prec : int { kPrecFP32 = 0, kPrecBF16x3 = 1, kPrecFP16x3 = 2 };
 bool length_supported(int L);
 
 // bit v set: tile variant v has a kernel for this length and precision
-// (kPrecFP32 bit 0 alone: the generic kernel; split precisions: 0 when the
-// length has no matrix-core kernel)
+// (register-resident tiles first, then the LDS-resident ones for FP32; split
+// precisions: 0 when the length has no matrix-core kernel)
 unsigned col_variant_mask(int L, int prec);
 unsigned row_variant_mask(int M, int prec);
-constexpr int kMaxVariants = 8;
+constexpr int kMaxVariants = 12;
 
 // real lines (zero-padded to L) -> half spectrum rows 1..L/2-1, times scale*(-1)^k
 hipError_t launch_r2c(int L, int variant, int prec, bool trans, const float* in, float2* out, int nlines, int lin, int off,

@@ -297,9 +297,10 @@ __global__ void __launch_bounds__((RowCfg<M, V>::THREADS))
 
 template <int L, int E_, int LINES_>
 struct FastCfg {
-  static constexpr int E = E_;
   static constexpr int LINES = LINES_;
-  static constexpr int P = L / E > 0 ? L / E : 1;
+  static constexpr bool POW2 = (L & (L - 1)) == 0;
+  // threads per transform: L / E for powers of two, ceil(L / E) otherwise
+  static constexpr int P = POW2 ? (L / E_ > 0 ? L / E_ : 1) : cdiv(L, E_);
   static constexpr int THREADS = LINES * P;
   static constexpr int rmin() {
     const RadixPlan p = radix_plan(L);
@@ -307,10 +308,25 @@ struct FastCfg {
     for (int i = 0; i < p.n; ++i) m = p.r[i] < m ? p.r[i] : m;
     return m;
   }
-  // power of two, every pass divides evenly, the paired pass (smallest radix)
-  // has an even number of butterflies per thread, and the block fits
-  static constexpr bool valid = (L >= 128) && ((L & (L - 1)) == 0) && L <= 4096 && L % E == 0 &&
-                                (E % rmin() == 0) && ((E / rmin()) % 2 == 0) && THREADS >= 64 &&
+  static constexpr int em() {
+    const int a = FftR<L, P, false, false>::EM, b = FftR<L, P, true, true>::EM;
+    return a > b ? a : b;
+  }
+  // registers per thread (the larger of the forward and the reversed engine)
+  static constexpr int E = em();
+  static constexpr bool pow2_ok() {
+    // every pass divides evenly and the paired pass (smallest radix) has an
+    // even number of butterflies per thread
+    return L % E_ == 0 && E_ % rmin() == 0 && (E_ / rmin()) % 2 == 0;
+  }
+  static constexpr bool mixed_ok() {
+    // the paired pass (the last radix of the forward order, the first of the
+    // reversed one) pairs butterflies j and NB - j, so NB must be even; at
+    // most 1.5 E_ registers of data per thread
+    const RadixPlan p = radix_plan(L);
+    return p.n > 0 && (L / p.r[p.n - 1]) % 2 == 0 && em() * 2 <= 3 * E_ && P >= 2;
+  }
+  static constexpr bool valid = (L >= 128) && L <= 4096 && (POW2 ? pow2_ok() : mixed_ok()) && THREADS >= 64 &&
                                 THREADS <= 1024 && (L + L / 16 + 1) * LINES * 4 <= 150 * 1024;
 };
 
@@ -377,11 +393,13 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
     k_r2c_fast(const float* __restrict__ in, float2* __restrict__ out, int nlines, int lin, int off,
                ImgMap map, float scale, const float2* __restrict__ tw, int tiles) {
   using Cfg = FastCfg<L, E_, LINES_>;
-  constexpr int P = Cfg::P, E = Cfg::E, LINES = Cfg::LINES, H = L / 2 - 1;
+  constexpr int P = Cfg::P, LINES = Cfg::LINES, H = L / 2 - 1;
   using Eng = typename EngSel<PREC, L, P, false, false, LINES, true>::type;
+  constexpr int E = Eng::EM;
   constexpr RadixPlan PL = Eng::kPlan;
-  constexpr int R0 = PL.r[0], NB0 = L / R0;
-  constexpr int RL = PL.r[PL.n - 1], NBL = L / RL, BPTL = E / RL;
+  constexpr int LAST = PL.n - 1;
+  constexpr int R0 = PL.r[0], NB0 = L / R0, BPT0 = Eng::template bpt<0, false>();
+  constexpr int RL = PL.r[LAST], NBL = L / RL, BPTL = Eng::template bpt<LAST, true>();
   using Lay = LayInterR<LINES>;
   __shared__ float lds[Lay::size(L)];
 
@@ -399,13 +417,14 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
     // line 2pg and 2pg+1 of the image rows; rows outside [0, lin) are zero
     const int o0 = (2 * pg * lin + t - off) * 4;
 #pragma unroll
-    for (int b = 0; b < E / R0; ++b)
+    for (int b = 0; b < BPT0; ++b)
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
         const int rr = t + P * b + r * NB0 - off;
         const int o = o0 + (P * b + r * NB0) * 4;
         float2 z = make_float2(0.f, 0.f);
-        if (active && (unsigned)rr < (unsigned)lin) z = make_float2(src.ld1(o), src.ld1(o + lin * 4));
+        if (active && Eng::template ok<0, false>(t, b) && (unsigned)rr < (unsigned)lin)
+          z = make_float2(src.ld1(o), src.ld1(o + lin * 4));
         v[b * R0 + r] = z;
       }
   } else {
@@ -413,9 +432,11 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
     const int o0 = ((t - off) * nlines + 2 * pg) * 4;
     const int rs = nlines * 4;
 #pragma unroll
-    for (int b = 0; b < E / R0; ++b)
+    for (int b = 0; b < BPT0; ++b)
 #pragma unroll
-      for (int r = 0; r < R0; ++r) v[b * R0 + r] = src.ld2(o0 + (P * b + r * NB0) * rs);
+      for (int r = 0; r < R0; ++r)
+        v[b * R0 + r] = Eng::template ok<0, false>(t, b) ? src.ld2(o0 + (P * b + r * NB0) * rs)
+                                                         : make_float2(0.f, 0.f);
   }
   Eng::template run<false, true, true, Lay>(v, pair, t, lds, tw);
   if (!active) return;
@@ -424,6 +445,7 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
   const GBuf dst(out + map.out(img), (long long)H * npairs * 16);
 #pragma unroll
   for (int c = 0; c < BPTL / 2; ++c) {
+    if (!Eng::template ok<LAST, true>(t, 2 * c)) continue;
     const int ja = t + P * c;
     const bool zero = ja == 0;
     const int jb = zero ? NBL / 2 : NBL - ja;
@@ -446,11 +468,13 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
     k_c2r_fast(const float2* __restrict__ in, float* __restrict__ out, int nlines, int r0, int nout,
                ImgMap map, float scale, const float2* __restrict__ tw, int tiles) {
   using Cfg = FastCfg<L, E_, LINES_>;
-  constexpr int P = Cfg::P, E = Cfg::E, LINES = Cfg::LINES;
+  constexpr int P = Cfg::P, LINES = Cfg::LINES;
   using Eng = typename EngSel<PREC, L, P, true, true, LINES, true>::type;
+  constexpr int E = Eng::EM;
   constexpr RadixPlan PL = Eng::kPlan;
-  constexpr int R0 = PL.r[0], NB0 = L / R0, BPT0 = E / R0;
-  constexpr int RL = PL.r[PL.n - 1], NBL = L / RL, BPTL = E / RL;
+  constexpr int LAST = PL.n - 1;
+  constexpr int R0 = PL.r[0], NB0 = L / R0, BPT0 = Eng::template bpt<0, true>();
+  constexpr int RL = PL.r[LAST], NBL = L / RL, BPTL = Eng::template bpt<LAST, false>();
   using Lay = LayInterR<LINES>;
   __shared__ float lds[Lay::size(L)];
 
@@ -468,37 +492,46 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
     if (k & 1) x = make_float4(-x.x, -x.y, -x.z, -x.w);
     return x;
   };
+  // Butterfly ja reads inputs ja + r NB0.  Below L/2 (r < NA) they are stored
+  // coefficients; above, the mirror L - idx = jb + (R0-1-r) NB0 is one of
+  // jb's stored coefficients, and jb (r < NBH stored) likewise mirrors ja's.
+  // For ja = 0 the butterflies 0 and NB0/2 are their own partners; index 0
+  // (DC, read as 0 from outside the buffer) and L/2 (Nyquist) are zero.
+  constexpr int NA = (R0 + 1) / 2, NBH = R0 / 2;
   float2 v[E];
 #pragma unroll
+  for (int s2 = 0; s2 < E; ++s2) v[s2] = make_float2(0.f, 0.f);
+#pragma unroll
   for (int c = 0; c < BPT0 / 2; ++c) {
+    if (!Eng::template ok<0, true>(t, 2 * c)) continue;
     const int ja = t + P * c;
     const bool zero = ja == 0;
     const int jb = zero ? NB0 / 2 : NB0 - ja;
-    float4 xa[R0 / 2], xb[R0 / 2];
+    float4 xa[NA], xb[NBH > 0 ? NBH : 1];
 #pragma unroll
-    for (int r = 0; r < R0 / 2; ++r) {
-      xa[r] = load(ja + r * NB0);
-      xb[r] = load(jb + r * NB0);
-    }
-    // Butterfly ja reads inputs ja + r NB0: for r < R0/2 the stored coefficient
-    // itself, above R0/2 the mirror L - idx = jb + (R0-1-r) NB0.  Butterfly jb
-    // likewise mirrors ja's coefficients.  For ja = 0 both butterflies are their
-    // own partners (inputs r NB0 and NB0/2 + r NB0), and r = 0, R0/2 of ja are
-    // the zero DC and Nyquist rows.
+    for (int r = 0; r < NA; ++r) xa[r] = load(ja + r * NB0);
+#pragma unroll
+    for (int r = 0; r < NBH; ++r) xb[r] = load(jb + r * NB0);
     float2* va = v + (2 * c) * R0;
     float2* vb = v + (2 * c + 1) * R0;
+    if (!zero) {
 #pragma unroll
-    for (int r = 0; r < R0 / 2; ++r) {
-      va[r] = herm_direct(xa[r]);
-      vb[r] = herm_direct(xb[r]);
-      va[R0 - 1 - r] = herm_mirror(xb[r]);
-      vb[R0 - 1 - r] = herm_mirror(zero ? xb[r] : xa[r]);
-    }
-    if (zero) {
-      va[0] = make_float2(0.f, 0.f);
-      va[R0 / 2] = make_float2(0.f, 0.f);
+      for (int r = 0; r < R0; ++r) {
+        va[r] = r < NA ? herm_direct(xa[r]) : herm_mirror(xb[R0 - 1 - r]);
+        vb[r] = r < NBH ? herm_direct(xb[r]) : herm_mirror(xa[R0 - 1 - r]);
+      }
+    } else {
 #pragma unroll
-      for (int r = 1; r < R0 / 2; ++r) va[R0 - r] = herm_mirror(xa[r]);
+      for (int r = 0; r < R0; ++r) {
+        // butterfly 0: inputs r NB0 (mirror (R0 - r) NB0); Nyquist at r = R0/2 for even R0
+        if (r < NA) va[r] = herm_direct(xa[r]);
+        else if (2 * r == R0) va[r] = make_float2(0.f, 0.f);
+        else va[r] = herm_mirror(xa[R0 - r]);
+        // butterfly NB0/2: inputs NB0/2 + r NB0 (mirror (R0-1-r)); Nyquist at r = (R0-1)/2 for odd R0
+        if (r < NBH) vb[r] = herm_direct(xb[r]);
+        else if (2 * r + 1 == R0) vb[r] = make_float2(0.f, 0.f);
+        else vb[r] = herm_mirror(xb[R0 - 1 - r]);
+      }
     }
   }
   Eng::template run<true, false, true, Lay>(v, pair, t, lds, tw);
@@ -523,6 +556,7 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
   }
 #pragma unroll
   for (int b = 0; b < BPTL; ++b) {
+    if (!Eng::template ok<LAST, false>(t, b)) continue;
 #pragma unroll
     for (int q = 0; q < RL; ++q) {
       const int r = t + P * b + q * NBL - r0;
@@ -552,13 +586,14 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
 
 template <int M, int E_, int TPB>
 struct RowFastCfg {
-  static constexpr int E = E_;
-  static constexpr int P = M / E > 0 ? M / E : 1;
+  static constexpr bool POW2 = (M & (M - 1)) == 0;
+  static constexpr int P = POW2 ? (M / E_ > 0 ? M / E_ : 1) : cdiv(M, E_);
   static constexpr int ROWS = TPB / P > 0 ? TPB / P : 1;
   static constexpr int THREADS = ROWS * P;
-  static constexpr bool valid = (M >= 64) && ((M & (M - 1)) == 0) && M <= 4096 && M % E == 0 && P >= 1 &&
-                                (M / 16) % P == 0 && THREADS <= 1024 && THREADS >= 32 &&
-                                (M + M / 16 + 1) * ROWS * 8 <= 64 * 1024;
+  static constexpr int E = FftR<M, P, false, false>::EM;   // registers per thread
+  static constexpr bool valid = (M >= 64) && M <= 4096 && radix_plan(M).n > 0 && P >= 2 &&
+                                (POW2 ? (M % E_ == 0 && (M / 16) % P == 0) : E * 2 <= 3 * E_) &&
+                                THREADS <= 1024 && THREADS >= 32 && (M + M / 16 + 1) * ROWS * 8 <= 64 * 1024;
 };
 
 // row-pass variants: (elements per thread, target threads per block)
@@ -569,11 +604,15 @@ template <int M, int E_, int TPB, bool ADJ, int PREC>
 __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
     k_row_fast(float2* __restrict__ data, int Lp, int h, long long img_stride, const float2* __restrict__ tw) {
   using Cfg = RowFastCfg<M, E_, TPB>;
-  constexpr int P = Cfg::P, E = Cfg::E, ROWS = Cfg::ROWS;
+  constexpr int P = Cfg::P, ROWS = Cfg::ROWS;
   using Eng = typename EngSel<PREC, M, P, ADJ, false, ROWS, false>::type;
+  constexpr int E = Eng::EM;
   constexpr RadixPlan PL = Eng::kPlan;
-  constexpr int R0 = PL.r[0], NB0 = M / R0, BPT0 = E / R0;
-  constexpr int RL = PL.r[PL.n - 1], NBL = M / RL, BPTL = E / RL;
+  constexpr int LAST = PL.n - 1;
+  constexpr int R0 = PL.r[0], NB0 = M / R0, BPT0 = Eng::template bpt<0, false>();
+  constexpr int RL = PL.r[LAST], NBL = M / RL, BPTL = Eng::template bpt<LAST, false>();
+  constexpr int ES = cdiv(M / 2, P);   // float4 (two elements) per thread when staging the row
+  constexpr int EG = cdiv(M, P);       // elements per thread in the transposed gather
   using Lay = LayRow<ROWS, M>;
   __shared__ float2 lds[Lay::size(M)];
 
@@ -583,13 +622,15 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
   const bool active = n2 <= h;
   float2* rowp = data + (long long)blockIdx.y * img_stride + (long long)(n2 - 1) * M;
 
-  {  // stage this thread's share of its row: E/2 float4 loads, all in flight
-    float4 st[E / 2];
+  {  // stage this thread's share of its row: ES float4 loads, all in flight
+    float4 st[ES];
     const float4* src4 = reinterpret_cast<const float4*>(rowp);
 #pragma unroll
-    for (int i = 0; i < E / 2; ++i) st[i] = active ? src4[t + P * i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = 0; i < ES; ++i)
+      st[i] = active && ((M / 2) % P == 0 || t + P * i < M / 2) ? src4[t + P * i] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-    for (int i = 0; i < E / 2; ++i) {
+    for (int i = 0; i < ES; ++i) {
+      if ((M / 2) % P != 0 && t + P * i >= M / 2) continue;
       const int e0 = 2 * (t + P * i);
       float4 x = st[i];
       if (ADJ) { x.z = -x.z; x.w = -x.w; }   // (-1)^p on the odd element
@@ -602,11 +643,14 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
   const int den = 2 * n2;
   const int mn2 = M * n2;
   float2 v[E];
+#pragma unroll
+  for (int s2 = 0; s2 < E; ++s2) v[s2] = make_float2(0.f, 0.f);
   if constexpr (!ADJ) {
 #pragma unroll
     for (int b = 0; b < BPT0; ++b)
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
+        if (!Eng::template ok<0, false>(t, b)) continue;
         const int q = t + P * b + r * NB0;
         const int num = (q - M / 2) * Lp + mn2;
         const int i0 = floor_div(num, den);
@@ -623,6 +667,7 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
     for (int b = 0; b < BPTL; ++b)
 #pragma unroll
       for (int q = 0; q < RL; ++q) {
+        if (!Eng::template ok<LAST, false>(t, b)) continue;
         const int p = t + P * b + q * NBL;
         float2 g = v[b * RL + q];
         if ((p + M / 2) & 1) g = make_float2(-g.x, -g.y);
@@ -632,13 +677,15 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
 #pragma unroll
     for (int b = 0; b < BPT0; ++b)
 #pragma unroll
-      for (int r = 0; r < R0; ++r) v[b * R0 + r] = lds[Lay::addr(row, t + P * b + r * NB0)];
+      for (int r = 0; r < R0; ++r)
+        if (Eng::template ok<0, false>(t, b)) v[b * R0 + r] = lds[Lay::addr(row, t + P * b + r * NB0)];
     Eng::template run<false, false, false, Lay>(v, row, t, lds, tw);
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < BPTL; ++b)
 #pragma unroll
       for (int q = 0; q < RL; ++q) {
+        if (!Eng::template ok<LAST, false>(t, b)) continue;
         const int x = t + P * b + q * NBL;
         float2 g = v[b * RL + q];
         if ((x + M / 2) & 1) g = make_float2(-g.x, -g.y);
@@ -648,8 +695,9 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
     if (!active) return;
     // transposed interpolation as a gather: at most two samples land on i
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
+    for (int e = 0; e < EG; ++e) {
       const int i = t + P * e;
+      if (M % P != 0 && i >= M) continue;
       float2 acc = make_float2(0.f, 0.f);
       const int xa = ceil_div(i * den - mn2, Lp);
       const int na = xa * Lp + mn2;
@@ -684,11 +732,11 @@ unsigned col_variant_mask_t() {
   if constexpr (FastCfg<L, e, l>::valid && (PREC == kPrecFP32 || mfma_fits(L, e, FastCfg<L, e, l>::THREADS))) m |= 1u << i;
   FUNNEL_COL_VARIANTS(FUNNEL_V)
 #undef FUNNEL_V
-  if (PREC != kPrecFP32 || m) return m;
-  // lengths without a register-resident kernel: the LDS-resident variants
-  m = 1u;
-  if constexpr (ColCfg<L, 1>::distinct()) m |= 2u;
-  if constexpr (ColCfg<L, 2>::distinct()) m |= 4u;
+  if (PREC != kPrecFP32) return m;
+  // the LDS-resident variants, numbered from kColVariants
+  m |= 1u << kColVariants;
+  if constexpr (ColCfg<L, 1>::distinct()) m |= 1u << (kColVariants + 1);
+  if constexpr (ColCfg<L, 2>::distinct()) m |= 1u << (kColVariants + 2);
   return m;
 }
 
@@ -699,9 +747,10 @@ unsigned row_variant_mask_t() {
   if constexpr (RowFastCfg<M, e, t>::valid && (PREC == kPrecFP32 || mfma_fits(M, e, RowFastCfg<M, e, t>::THREADS))) m |= 1u << i;
   FUNNEL_ROW_VARIANTS(FUNNEL_V)
 #undef FUNNEL_V
-  if (PREC != kPrecFP32 || m) return m;
-  m = 1u;
-  if constexpr (RowCfg<M, 1>::distinct()) m |= 2u;
+  if (PREC != kPrecFP32) return m;
+  // the LDS-resident variants, numbered from kRowVariants
+  m |= 1u << kRowVariants;
+  if constexpr (RowCfg<M, 1>::distinct()) m |= 1u << (kRowVariants + 1);
   return m;
 }
 
@@ -730,7 +779,9 @@ hipError_t launch_r2c_t(int variant, bool trans, const float* in, float2* out, i
     return hipErrorInvalidValue;
   } else {
     const unsigned m = col_variant_mask_t<L, PREC>();
-    if (variant < 0 || variant >= kGenVariants || !(m & (1u << variant)) || (m & ~7u)) return hipErrorInvalidValue;
+    if (variant < kColVariants || variant >= kColVariants + kGenVariants || !(m & (1u << variant)))
+      return hipErrorInvalidValue;
+    variant -= kColVariants;
     auto go = [&](auto vc) {
       constexpr int V = decltype(vc)::value;
       if constexpr (ColCfg<L, V>::distinct()) {
@@ -781,7 +832,9 @@ hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, f
     return hipErrorInvalidValue;
   } else {
     const unsigned m = col_variant_mask_t<L, PREC>();
-    if (variant < 0 || variant >= kGenVariants || !(m & (1u << variant)) || (m & ~7u)) return hipErrorInvalidValue;
+    if (variant < kColVariants || variant >= kColVariants + kGenVariants || !(m & (1u << variant)))
+      return hipErrorInvalidValue;
+    variant -= kColVariants;
     auto go = [&](auto vc) {
       constexpr int V = decltype(vc)::value;
       if constexpr (ColCfg<L, V>::distinct()) {
@@ -832,8 +885,9 @@ hipError_t launch_row_t(int variant, bool adj, float2* data, int Lp, int h, long
     return hipErrorInvalidValue;
   } else {
     const unsigned m = row_variant_mask_t<M, PREC>();
-    if (variant < 0 || variant >= kGenRowVariants || !(m & (1u << variant)) || (m & ~3u))
+    if (variant < kRowVariants || variant >= kRowVariants + kGenRowVariants || !(m & (1u << variant)))
       return hipErrorInvalidValue;
+    variant -= kRowVariants;
     auto go = [&](auto vc) {
       constexpr int V = decltype(vc)::value;
       if constexpr (RowCfg<M, V>::distinct()) {

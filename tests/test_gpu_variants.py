@@ -44,7 +44,7 @@ def test_every_variant_matches_oracle(N, M):
     dPc = dP.cuda()
     defaults = F.funnel_plan_variants(plan.handle)
     covered = 0
-    for v in range(8):
+    for v in range(12):
         roles = []
         for r in range(12):
             try:
