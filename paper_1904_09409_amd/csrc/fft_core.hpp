@@ -330,6 +330,18 @@ struct Fft {
   }
 };
 
+// floor(a / d) for d > 0 from a float reciprocal inv = 1/d: the estimate is
+// within one of the quotient while |a| < 2^26 and |a / d| < 2^21, and one
+// remainder test makes it exact (larger quotients may stay off by one; the
+// callers only use quotients that land in a row of at most 4096 samples).
+__device__ __forceinline__ int floor_div_rcp(int a, int d, float inv) {
+  int q = (int)floorf((float)a * inv);
+  const int r = a - q * d;
+  q += (r >= d) - (r < 0);
+  return q;
+}
+__device__ __forceinline__ int ceil_div_rcp(int a, int d, float inv) { return -floor_div_rcp(-a, d, inv); }
+
 // floor(a / b) and ceil(a / b) for b > 0 and any sign of a
 __device__ __forceinline__ int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 __device__ __forceinline__ int ceil_div(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }

@@ -141,8 +141,8 @@ double role_bytes(const ft_plan* p, const FtClass& c, int r) {
     case FB_REG: case FB_INV: case AB_REG: case AB_INV: return B * 16.0 * h * W;
     case FC_REG: case FC_INV: return B * (8.0 * h * W + 4.0 * Np * W);
     case AC_REG: case AC_INV: return B * (4.0 * Np * W + 8.0 * h * W);
-    case AA_REG: return B * (8.0 * h * M + 4.0 * N * M);
-    case AA_INV: return B * (8.0 * h * N + ((p->spaces & FT_SPACE_REGULAR) ? 8.0 : 4.0) * N * M);
+    case AA_REG: return B * (8.0 * h * M + ((p->spaces & FT_SPACE_INVERSE) ? 8.0 : 4.0) * N * M);
+    case AA_INV: return B * (8.0 * h * N + 4.0 * N * M);
   }
   return 0.0;
 }
@@ -191,7 +191,7 @@ hipError_t run_role(const ft_plan* p, const FtClass& c, int r, int v, const floa
   float2* Sr = reinterpret_cast<float2*>(w + c.ws_reg);
   float2* Si = reinterpret_cast<float2*>(w + c.ws_inv);
   const long long sr = (long long)h * M, si = (long long)h * N;
-  const bool reg = p->spaces & FT_SPACE_REGULAR;
+  const bool inv = p->spaces & FT_SPACE_INVERSE;
   using funnel::ImgMap;
   // where each launch's input and output of image i start
   const ImgMap img_to_sr{c.img_stride, sr, c.d_img_off, nullptr};
@@ -219,16 +219,18 @@ hipError_t run_role(const ft_plan* p, const FtClass& c, int r, int v, const floa
     // DFT + transposed interpolation, real part of the conjugate y DFT cropped
     case AC_REG: return funnel::launch_r2c(Np, v, p->prec, false, src, Sr, M, Np, 0, pl_to_sr, 2.0f / Np, tw_np, B, s);
     case AB_REG: return funnel::launch_row(M, v, p->prec, true, Sr, Np, h, sr, p->tw + c.tw_m, B, s);
+    // (the inverse space runs first; the regular space's columns add to its result)
     case AA_REG:
-      return funnel::launch_c2r(Np, v, p->prec, false, false, Sr, dst, M, (Np - N) / 2, N, sr_to_img, 0.5f, tw_np, B, s);
-    // adjoint, inverse space: transposed write into the image rows, added to
-    // the regular space's result when both spaces are computed
+      return funnel::launch_c2r(Np, v, p->prec, false, inv, Sr, dst, M, (Np - N) / 2, N, sr_to_img, 0.5f, tw_np, B,
+                                s);
+    // adjoint, inverse space: transposed write into the image rows
     case AC_INV:
       return funnel::launch_r2c(Np, v, p->prec, false, src + c.off_inv_plane, Si, N, Np, 0, pl_to_si, 2.0f / Np, tw_np, B,
                                 s);
     case AB_INV: return funnel::launch_row(N, v, p->prec, true, Si, Np, h, si, p->tw + c.tw_n, B, s);
     case AA_INV:
-      return funnel::launch_c2r(Np, v, p->prec, true, reg, Si, dst, N, (Np - M) / 2, M, si_to_img, 0.5f, tw_np, B, s);
+      return funnel::launch_c2r(Np, v, p->prec, true, false, Si, dst, N, (Np - M) / 2, M, si_to_img, 0.5f, tw_np, B,
+                                s);
   }
   return hipErrorInvalidValue;
 }
@@ -238,9 +240,16 @@ std::string role_label(const ft_plan* p, int ci, int r) {
   return "c" + std::to_string(ci) + "." + kRoleName[r];
 }
 
-// Enqueue roles [first, last] of every class: on the caller's stream for a
+// Launch order: forward A, B, C of the regular then the inverse space; the
+// adjoint runs the inverse space first (its transposed pass writes dI) and the
+// regular space's column pass adds to it (a read-modify-write of dI's columns
+// is cheaper than one of its rows).
+static const int kForwardOrder[] = {FA_REG, FB_REG, FC_REG, FA_INV, FB_INV, FC_INV};
+static const int kAdjointOrder[] = {AC_INV, AB_INV, AA_INV, AC_REG, AB_REG, AA_REG};
+
+// Enqueue the roles of `order` for every class: on the caller's stream for a
 // single class, else on the class streams between a fork and a join.
-hipError_t enqueue_roles(const ft_plan* p, int first, int last, const float* src, float* dst, char* w,
+hipError_t enqueue_roles(const ft_plan* p, const int* order, const float* src, float* dst, char* w,
                          hipStream_t s) {
   const bool fork = p->cls.size() > 1;
   hipError_t e = hipSuccess;
@@ -249,7 +258,8 @@ hipError_t enqueue_roles(const ft_plan* p, int first, int last, const float* src
     const FtClass& c = p->cls[ci];
     hipStream_t cs = fork ? c.stream : s;
     if (fork) e = hipStreamWaitEvent(cs, p->fork, 0);
-    for (int r = first; r <= last && e == hipSuccess; ++r) {
+    for (int i = 0; i < 6 && e == hipSuccess; ++i) {
+      const int r = order[i];
       if (!role_active(p, r)) continue;
       e = timed(p, cs, role_label(p, (int)ci, r), role_bytes(p, c, r),
                 [&] { return run_role(p, c, r, c.variant[r], src, dst, w, cs); });
@@ -550,7 +560,7 @@ ft_status funnel_forward(const ft_plan* p, const float* images, float* planes, v
   if (st != FT_OK) return st;
   if ((st = check_device(p)) != FT_OK) return st;
   (void)hipGetLastError();
-  hipError_t e = enqueue_roles(p, FA_REG, FC_INV, images, planes, static_cast<char*>(ws),
+  hipError_t e = enqueue_roles(p, kForwardOrder, images, planes, static_cast<char*>(ws),
                                static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return ok();
@@ -562,7 +572,7 @@ ft_status funnel_adjoint(const ft_plan* p, const float* d_planes, float* d_image
   if (st != FT_OK) return st;
   if ((st = check_device(p)) != FT_OK) return st;
   (void)hipGetLastError();
-  hipError_t e = enqueue_roles(p, AC_REG, AA_INV, d_planes, d_images, static_cast<char*>(ws),
+  hipError_t e = enqueue_roles(p, kAdjointOrder, d_planes, d_images, static_cast<char*>(ws),
                                static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return ok();
@@ -590,9 +600,9 @@ ft_status funnel_graph_create(const ft_plan* p, uint32_t what, const float* imag
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   hipError_t le = hipSuccess;
   if (e == hipSuccess) {
-    if (what & FT_GRAPH_FORWARD) le = enqueue_roles(p, FA_REG, FC_INV, images, planes, static_cast<char*>(ws), cs);
+    if (what & FT_GRAPH_FORWARD) le = enqueue_roles(p, kForwardOrder, images, planes, static_cast<char*>(ws), cs);
     if (le == hipSuccess && (what & FT_GRAPH_ADJOINT))
-      le = enqueue_roles(p, AC_REG, AA_INV, d_planes, d_images, static_cast<char*>(ws), cs);
+      le = enqueue_roles(p, kAdjointOrder, d_planes, d_images, static_cast<char*>(ws), cs);
     e = hipStreamEndCapture(cs, &g->graph);
   }
   if (e == hipSuccess && le == hipSuccess) e = hipGraphInstantiateWithFlags(&g->exec, g->graph, 0);

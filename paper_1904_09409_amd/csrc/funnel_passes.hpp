@@ -234,11 +234,12 @@ __global__ void __launch_bounds__((RowCfg<M, V>::THREADS))
 
   const int den = 2 * n2;
   const int mn2 = M * n2;
+  const float rden = 1.0f / (float)den, rlp = 1.0f / (float)Lp;
   if constexpr (!ADJ) {
     auto fl = [&](int q) -> float2 {
       const int num = (q - M / 2) * Lp + mn2;
-      const int i0 = floor_div(num, den);
-      const float tt = (float)(num - i0 * den) / (float)den;
+      const int i0 = floor_div_rcp(num, den, rden);
+      const float tt = (float)(num - i0 * den) * rden;
       float2 f0 = make_float2(0.f, 0.f), f1 = make_float2(0.f, 0.f);
       if (i0 >= 0 && i0 < M) f0 = lds[Lay::addr(row, i0)];
       if (i0 + 1 >= 0 && i0 + 1 < M) f1 = lds[Lay::addr(row, i0 + 1)];
@@ -263,19 +264,19 @@ __global__ void __launch_bounds__((RowCfg<M, V>::THREADS))
     for (int i = t; i < M; i += P) {
       float2 acc = make_float2(0.f, 0.f);
       // sample with i0 == i
-      const int xa = ceil_div(i * den - mn2, Lp);
+      const int xa = ceil_div_rcp(i * den - mn2, Lp, rlp);
       const int na = xa * Lp + mn2;
       if (xa >= -M / 2 && xa < M / 2 && na < (i + 1) * den) {
-        const float w = 1.f - (float)(na - i * den) / (float)den;
+        const float w = 1.f - (float)(na - i * den) * rden;
         const float2 g = lds[Lay::addr(row, xa + M / 2)];
         acc.x += w * g.x;
         acc.y += w * g.y;
       }
       // sample with i0 == i-1
-      const int xb = ceil_div((i - 1) * den - mn2, Lp);
+      const int xb = ceil_div_rcp((i - 1) * den - mn2, Lp, rlp);
       const int nb = xb * Lp + mn2;
       if (xb >= -M / 2 && xb < M / 2 && nb < i * den) {
-        const float w = (float)(nb - (i - 1) * den) / (float)den;
+        const float w = (float)(nb - (i - 1) * den) * rden;
         const float2 g = lds[Lay::addr(row, xb + M / 2)];
         acc.x += w * g.x;
         acc.y += w * g.y;
@@ -544,7 +545,8 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
   const int step = TRANS ? 4 : nlines * 4;
   float2 old[E];
   if constexpr (ACCUM) {
-    // read every old value first so the adds do not serialise on memory latency
+    // read every old value first so the adds do not serialise on memory
+    // latency (reading them before the transform instead was measured slower)
 #pragma unroll
     for (int b = 0; b < BPTL; ++b)
 #pragma unroll
@@ -642,6 +644,7 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
 
   const int den = 2 * n2;
   const int mn2 = M * n2;
+  const float rden = 1.0f / (float)den, rlp = 1.0f / (float)Lp;
   float2 v[E];
 #pragma unroll
   for (int s2 = 0; s2 < E; ++s2) v[s2] = make_float2(0.f, 0.f);
@@ -653,8 +656,8 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
         if (!Eng::template ok<0, false>(t, b)) continue;
         const int q = t + P * b + r * NB0;
         const int num = (q - M / 2) * Lp + mn2;
-        const int i0 = floor_div(num, den);
-        const float tt = (float)(num - i0 * den) / (float)den;
+        const int i0 = floor_div_rcp(num, den, rden);
+        const float tt = (float)(num - i0 * den) * rden;
         float2 f0 = make_float2(0.f, 0.f), f1 = make_float2(0.f, 0.f);
         if (i0 >= 0 && i0 < M) f0 = lds[Lay::addr(row, i0)];
         if (i0 + 1 >= 0 && i0 + 1 < M) f1 = lds[Lay::addr(row, i0 + 1)];
@@ -699,18 +702,18 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
       const int i = t + P * e;
       if (M % P != 0 && i >= M) continue;
       float2 acc = make_float2(0.f, 0.f);
-      const int xa = ceil_div(i * den - mn2, Lp);
+      const int xa = ceil_div_rcp(i * den - mn2, Lp, rlp);
       const int na = xa * Lp + mn2;
       if (xa >= -M / 2 && xa < M / 2 && na < (i + 1) * den) {
-        const float w = 1.f - (float)(na - i * den) / (float)den;
+        const float w = 1.f - (float)(na - i * den) * rden;
         const float2 g = lds[Lay::addr(row, xa + M / 2)];
         acc.x += w * g.x;
         acc.y += w * g.y;
       }
-      const int xb = ceil_div((i - 1) * den - mn2, Lp);
+      const int xb = ceil_div_rcp((i - 1) * den - mn2, Lp, rlp);
       const int nb = xb * Lp + mn2;
       if (xb >= -M / 2 && xb < M / 2 && nb < i * den) {
-        const float w = (float)(nb - (i - 1) * den) / (float)den;
+        const float w = (float)(nb - (i - 1) * den) * rden;
         const float2 g = lds[Lay::addr(row, xb + M / 2)];
         acc.x += w * g.x;
         acc.y += w * g.y;
