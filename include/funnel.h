@@ -242,9 +242,11 @@ ft_status funnel_profile_disable(ft_plan* plan);
 /* ---- tile variants and autotuning ----
  * Every pass kernel exists in several tile shapes (elements per thread,
  * columns or rows per block).  A plan starts from a default per launch;
- * funnel_autotune times every shape of every launch on the plan's real sizes
- * (allocating and freeing its own scratch buffers and synchronising the
- * stream) and keeps the fastest.  Launches ("roles") are numbered
+ * funnel_autotune tries every shape of every launch on the plan's real sizes,
+ * one launch after the other in two sweeps, scoring each by the time of its size class's
+ * whole forward + adjoint chain (allocating and freeing its own scratch
+ * buffers and synchronising the stream), and keeps the best.  The reported
+ * times (ft_tune_result.ms, ms_default) are those chain times.  Launches ("roles") are numbered
  *   0..5  forward  regular A, B, C, inverse A, B, C
  *   6..11 adjoint  regular Ct, Bt, At, inverse Ct, Bt, At
  * For a ragged plan, class c's launches are roles 12*c .. 12*c+11.
@@ -253,8 +255,8 @@ typedef struct {
   char name[40];       /* role name, e.g. "fwd.regular.C" */
   int32_t variant;     /* chosen tile variant */
   int32_t n_tried;     /* variants timed */
-  float ms;            /* best time of one launch */
-  float ms_default;    /* time of the variant the plan had before */
+  float ms;            /* best chain time with the chosen variant */
+  float ms_default;    /* chain time with the variant the plan had before */
 } ft_tune_result;
 
 ft_status funnel_autotune(ft_plan* plan, void* stream, ft_tune_result* out, int32_t cap, int32_t* n);

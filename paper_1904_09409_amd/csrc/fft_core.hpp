@@ -396,13 +396,18 @@ struct FftR {
     constexpr int NB = L / kPlan.r[I];
     return PAIRED ? (NB / 2) % P == 0 : NB % P == 0;
   }
+  // the paired pass is the first one of a reversed engine (Hermitian input)
+  // and the last one of a forward engine (two real columns out)
   static constexpr int slots() {
     int m = 0;
     for (int i = 0; i < kPlan.n; ++i) {
       const int NB = L / kPlan.r[i];
-      const int a = cdiv(NB, P) * kPlan.r[i], b = 2 * cdiv(NB / 2, P) * kPlan.r[i];
+      const int a = cdiv(NB, P) * kPlan.r[i];
       m = a > m ? a : m;
-      m = b > m ? b : m;
+      if (i == (REV ? 0 : kPlan.n - 1)) {
+        const int b = 2 * cdiv(NB / 2, P) * kPlan.r[i];
+        m = b > m ? b : m;
+      }
     }
     return m;
   }
@@ -562,6 +567,7 @@ struct FftR {
   template <bool PAIRED_FIRST, bool PAIRED_LAST, bool SPLIT, class Lay, class Buf, int I = 0>
   __device__ static __forceinline__ void run(float2 (&v)[EM], int line, int t, Buf* lds,
                                              const float2* __restrict__ tw) {
+    static_assert(!(PAIRED_FIRST && !REV) && !(PAIRED_LAST && REV), "EM counts the paired pass of this order only");
     constexpr bool FIRST = I == 0, LAST = I == kPlan.n - 1;
     constexpr bool PAIRED = (FIRST && PAIRED_FIRST) || (LAST && PAIRED_LAST);
     compute<I, PAIRED>(v, t, tw);

@@ -664,6 +664,9 @@ ft_status funnel_autotune(ft_plan* p, void* stream, ft_tune_result* out, int32_t
   FtProfiler* saved = p->prof;
   p->prof = nullptr;
   int count = 0;
+  // coordinate descent over the launches, two sweeps (a launch's best shape
+  // can depend on its neighbours' shapes); results report the last sweep
+  for (int sweep = 0; sweep < 2; ++sweep)
   for (size_t ci = 0; ci < p->cls.size(); ++ci) {
     FtClass& c = p->cls[ci];
     for (int r = 0; r < NROLES; ++r) {
@@ -673,18 +676,31 @@ ft_status funnel_autotune(ft_plan* p, void* stream, ft_tune_result* out, int32_t
       int best_v = c.variant[r], tried = 0;
       for (int v = 0; v < funnel::kMaxVariants; ++v) {
         if (!(mask & (1u << v))) continue;
+        // Score a variant by the time of the class's whole forward + adjoint
+        // chain (the quantity a caller pays): a launch timed on its own, or
+        // even inside the chain, misjudges how it overlaps with and warms the
+        // caches for its neighbours.  Best of 7 chains after one warm-up.
         float ms_min = 1e30f;
         hipError_t e = hipSuccess;
-        for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+        const int keep = c.variant[r];
+        c.variant[r] = v;
+        float* img = static_cast<float*>(a);
+        float* pln = static_cast<float*>(b);
+        for (int rep = 0; rep < 8 && e == hipSuccess; ++rep) {
           e = hipEventRecord(e0, s);
-          if (e == hipSuccess)
-            e = run_role(p, c, r, v, static_cast<float*>(a), static_cast<float*>(b), static_cast<char*>(w), s);
+          for (int k = 0; k < 12 && e == hipSuccess; ++k) {
+            const int rr = k < 6 ? kForwardOrder[k] : kAdjointOrder[k - 6];
+            if (!role_active(p, rr)) continue;
+            const bool fwd = k < 6;
+            e = run_role(p, c, rr, c.variant[rr], fwd ? img : pln, fwd ? pln : img, static_cast<char*>(w), s);
+          }
           if (e == hipSuccess) e = hipEventRecord(e1, s);
           if (e == hipSuccess) e = hipEventSynchronize(e1);
           float ms = 0.f;
           if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
           if (e == hipSuccess && rep > 0 && ms < ms_min) ms_min = ms;
         }
+        c.variant[r] = keep;
         if (e != hipSuccess) {
           p->prof = saved;
           cleanup();
@@ -698,6 +714,7 @@ ft_status funnel_autotune(ft_plan* p, void* stream, ft_tune_result* out, int32_t
         }
       }
       c.variant[r] = best_v;
+      if (sweep == 0) continue;
       if (count < cap) {
         std::memset(&out[count], 0, sizeof(ft_tune_result));
         std::snprintf(out[count].name, sizeof(out[count].name), "%s", role_label(p, (int)ci, r).c_str());

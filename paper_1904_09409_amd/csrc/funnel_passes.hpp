@@ -288,16 +288,24 @@ __global__ void __launch_bounds__((RowCfg<M, V>::THREADS))
 
 // ------------------------------------------------------------------ register-resident column passes
 //
-// Power-of-two lengths >= 128.  Each thread keeps 32 elements of one transform
-// in registers (P = L/32 threads per transform), LINES column pairs per block,
+// Lengths 128 .. 4096.  Each thread keeps about E elements of one transform in
+// registers (P threads per transform), LINES column pairs per transform group,
 // real and imaginary parts exchanged separately through a float LDS buffer.
 // The R2C kernel keeps each output k and its mirror L-k in one thread, so the
 // two real columns are separated in registers and written straight to HBM;
 // the C2R kernel builds its Hermitian input the same way from one read of
 // each stored coefficient.
+//
+// NT > 1: a block owns NT adjacent groups of LINES pairs.  It issues the loads
+// of all groups first and then transforms and stores them one after the other
+// through the same LDS buffer, so the later groups' loads are in flight during
+// the first transform and the first group's stores drain during the later
+// ones (the LDS barriers do not wait for global memory).  The row segments in
+// HBM are NT * LINES pairs wide.
 
-template <int L, int E_, int LINES_>
+template <int L, int E_, int LINES_, int NT_ = 1>
 struct FastCfg {
+  static constexpr int NT = NT_;
   static constexpr int LINES = LINES_;
   static constexpr bool POW2 = (L & (L - 1)) == 0;
   // threads per transform: L / E for powers of two, ceil(L / E) otherwise
@@ -328,12 +336,14 @@ struct FastCfg {
     return p.n > 0 && (L / p.r[p.n - 1]) % 2 == 0 && em() * 2 <= 3 * E_ && P >= 2;
   }
   static constexpr bool valid = (L >= 128) && L <= 4096 && (POW2 ? pow2_ok() : mixed_ok()) && THREADS >= 64 &&
-                                THREADS <= 1024 && (L + L / 16 + 1) * LINES * 4 <= 150 * 1024;
+                                THREADS <= 1024 && (L + L / 16 + 1) * LINES * 4 <= 150 * 1024 &&
+                                (NT == 1 || em() * NT <= 2 * E_);
 };
 
-// column-pass variants: (elements per thread, column pairs per block)
-#define FUNNEL_COL_VARIANTS(X) X(0, 16, 4) X(1, 16, 8) X(2, 16, 16) X(3, 32, 4) X(4, 32, 8) X(5, 32, 16)
-constexpr int kColVariants = 6;
+// column-pass variants: (elements per thread, column pairs per group, groups per block)
+#define FUNNEL_COL_VARIANTS(X) \
+  X(0, 16, 4, 1) X(1, 16, 8, 1) X(2, 16, 16, 1) X(3, 32, 4, 1) X(4, 32, 8, 1) X(5, 32, 16, 1) X(6, 16, 8, 2) X(7, 16, 4, 2)
+constexpr int kColVariants = 8;
 
 // Raw buffer access: 32-bit byte offsets from a per-block base, and hardware
 // range checking (offsets at or beyond `bytes`, including negative offsets,
@@ -389,11 +399,11 @@ __device__ __forceinline__ void emit_pair(GBuf dst, int k, float2 zk, float2 zm,
 __device__ __forceinline__ float2 herm_direct(float4 x) { return make_float2(x.x - x.w, x.y + x.z); }  // A + iB
 __device__ __forceinline__ float2 herm_mirror(float4 x) { return make_float2(x.x + x.w, x.z - x.y); }  // conj A + i conj B
 
-template <int L, int E_, int LINES_, bool TRANS, int PREC>
-__global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
+template <int L, int E_, int LINES_, int NT, bool TRANS, int PREC>
+__global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS))
     k_r2c_fast(const float* __restrict__ in, float2* __restrict__ out, int nlines, int lin, int off,
                ImgMap map, float scale, const float2* __restrict__ tw, int tiles) {
-  using Cfg = FastCfg<L, E_, LINES_>;
+  using Cfg = FastCfg<L, E_, LINES_, NT>;
   constexpr int P = Cfg::P, LINES = Cfg::LINES, H = L / 2 - 1;
   using Eng = typename EngSel<PREC, L, P, false, false, LINES, true>::type;
   constexpr int E = Eng::EM;
@@ -408,67 +418,74 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
   const int tile = logical % tiles, img = logical / tiles;
   const int tid = threadIdx.x, pair = tid % LINES, t = tid / LINES;
   const int npairs = nlines >> 1;
-  const int pg = tile * LINES + pair;
-  const bool active = pg < npairs;
   // one image's lin x nlines block (rows of the padded frame off .. off+lin-1)
   const GBuf src(in + map.in(img), (long long)lin * nlines * 4);
 
-  float2 v[E];
-  if constexpr (TRANS) {
-    // line 2pg and 2pg+1 of the image rows; rows outside [0, lin) are zero
-    const int o0 = (2 * pg * lin + t - off) * 4;
+  float2 v[NT][E];
 #pragma unroll
-    for (int b = 0; b < BPT0; ++b)
+  for (int g = 0; g < NT; ++g) {
+    const int pg = (tile * NT + g) * LINES + pair;
+    const bool active = pg < npairs;
+    if constexpr (TRANS) {
+      // line 2pg and 2pg+1 of the image rows; rows outside [0, lin) are zero
+      const int o0 = (2 * pg * lin + t - off) * 4;
 #pragma unroll
-      for (int r = 0; r < R0; ++r) {
-        const int rr = t + P * b + r * NB0 - off;
-        const int o = o0 + (P * b + r * NB0) * 4;
-        float2 z = make_float2(0.f, 0.f);
-        if (active && Eng::template ok<0, false>(t, b) && (unsigned)rr < (unsigned)lin)
-          z = make_float2(src.ld1(o), src.ld1(o + lin * 4));
-        v[b * R0 + r] = z;
-      }
-  } else {
-    // columns 2pg, 2pg+1; rows outside [0, lin) fall outside the buffer and read 0
-    const int o0 = ((t - off) * nlines + 2 * pg) * 4;
-    const int rs = nlines * 4;
+      for (int b = 0; b < BPT0; ++b)
 #pragma unroll
-    for (int b = 0; b < BPT0; ++b)
+        for (int r = 0; r < R0; ++r) {
+          const int rr = t + P * b + r * NB0 - off;
+          const int o = o0 + (P * b + r * NB0) * 4;
+          float2 z = make_float2(0.f, 0.f);
+          if (active && Eng::template ok<0, false>(t, b) && (unsigned)rr < (unsigned)lin)
+            z = make_float2(src.ld1(o), src.ld1(o + lin * 4));
+          v[g][b * R0 + r] = z;
+        }
+    } else {
+      // columns 2pg, 2pg+1; rows outside [0, lin) fall outside the buffer and read 0
+      const int o0 = ((t - off) * nlines + 2 * pg) * 4;
+      const int rs = nlines * 4;
 #pragma unroll
-      for (int r = 0; r < R0; ++r)
-        v[b * R0 + r] = Eng::template ok<0, false>(t, b) ? src.ld2(o0 + (P * b + r * NB0) * rs)
-                                                         : make_float2(0.f, 0.f);
+      for (int b = 0; b < BPT0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r)
+          v[g][b * R0 + r] = Eng::template ok<0, false>(t, b) ? src.ld2(o0 + (P * b + r * NB0) * rs)
+                                                              : make_float2(0.f, 0.f);
+    }
   }
-  Eng::template run<false, true, true, Lay>(v, pair, t, lds, tw);
-  if (!active) return;
 
   // half-spectrum rows 1 .. H: rows k outside that range fall outside the buffer
   const GBuf dst(out + map.out(img), (long long)H * npairs * 16);
 #pragma unroll
-  for (int c = 0; c < BPTL / 2; ++c) {
-    if (!Eng::template ok<LAST, true>(t, 2 * c)) continue;
-    const int ja = t + P * c;
-    const bool zero = ja == 0;
-    const int jb = zero ? NBL / 2 : NBL - ja;
-    const float2* va = v + (2 * c) * RL;
-    const float2* vb = v + (2 * c + 1) * RL;
+  for (int g = 0; g < NT; ++g) {
+    Eng::template run<false, true, true, Lay>(v[g], pair, t, lds, tw);
+    const int pg = (tile * NT + g) * LINES + pair;
+    if (pg >= npairs) continue;
 #pragma unroll
-    for (int q = 0; q < RL; ++q) {
-      // partners chosen by value (a select of array elements would make the
-      // compiler keep the arrays in scratch memory)
-      const float2 pa = sel2(zero, va[(RL - q) % RL], vb[RL - 1 - q]);
-      const float2 pb = sel2(zero, vb[RL - 1 - q], va[RL - 1 - q]);
-      emit_pair(dst, ja + q * NBL, va[q], pa, scale, npairs, pg);
-      emit_pair(dst, jb + q * NBL, vb[q], pb, scale, npairs, pg);
+    for (int c = 0; c < BPTL / 2; ++c) {
+      if (!Eng::template ok<LAST, true>(t, 2 * c)) continue;
+      const int ja = t + P * c;
+      const bool zero = ja == 0;
+      const int jb = zero ? NBL / 2 : NBL - ja;
+      const float2* va = v[g] + (2 * c) * RL;
+      const float2* vb = v[g] + (2 * c + 1) * RL;
+#pragma unroll
+      for (int q = 0; q < RL; ++q) {
+        // partners chosen by value (a select of array elements would make the
+        // compiler keep the arrays in scratch memory)
+        const float2 pa = sel2(zero, va[(RL - q) % RL], vb[RL - 1 - q]);
+        const float2 pb = sel2(zero, vb[RL - 1 - q], va[RL - 1 - q]);
+        emit_pair(dst, ja + q * NBL, va[q], pa, scale, npairs, pg);
+        emit_pair(dst, jb + q * NBL, vb[q], pb, scale, npairs, pg);
+      }
     }
   }
 }
 
-template <int L, int E_, int LINES_, bool TRANS, bool ACCUM, int PREC>
-__global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
+template <int L, int E_, int LINES_, int NT, bool TRANS, bool ACCUM, int PREC>
+__global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS))
     k_c2r_fast(const float2* __restrict__ in, float* __restrict__ out, int nlines, int r0, int nout,
                ImgMap map, float scale, const float2* __restrict__ tw, int tiles) {
-  using Cfg = FastCfg<L, E_, LINES_>;
+  using Cfg = FastCfg<L, E_, LINES_, NT>;
   constexpr int P = Cfg::P, LINES = Cfg::LINES;
   using Eng = typename EngSel<PREC, L, P, true, true, LINES, true>::type;
   constexpr int E = Eng::EM;
@@ -483,98 +500,104 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_>::THREADS))
   const int tile = logical % tiles, img = logical / tiles;
   const int tid = threadIdx.x, pair = tid % LINES, t = tid / LINES;
   const int npairs = nlines >> 1;
-  const int pg = tile * LINES + pair;
-  const bool active = pg < npairs;
   // half-spectrum rows 1 .. L/2-1; row 0 (and anything outside) reads 0
   const GBuf src(in + map.in(img), (long long)(L / 2 - 1) * npairs * 16);
 
-  auto load = [src, npairs, pg](int k) -> float4 {  // coefficient k (1 .. L/2-1) times (-1)^k; 0 for k = 0
-    float4 x = src.ld4(((k - 1) * npairs + pg) * 16);
-    if (k & 1) x = make_float4(-x.x, -x.y, -x.z, -x.w);
-    return x;
-  };
   // Butterfly ja reads inputs ja + r NB0.  Below L/2 (r < NA) they are stored
   // coefficients; above, the mirror L - idx = jb + (R0-1-r) NB0 is one of
   // jb's stored coefficients, and jb (r < NBH stored) likewise mirrors ja's.
   // For ja = 0 the butterflies 0 and NB0/2 are their own partners; index 0
   // (DC, read as 0 from outside the buffer) and L/2 (Nyquist) are zero.
   constexpr int NA = (R0 + 1) / 2, NBH = R0 / 2;
-  float2 v[E];
+  float2 v[NT][E];
 #pragma unroll
-  for (int s2 = 0; s2 < E; ++s2) v[s2] = make_float2(0.f, 0.f);
+  for (int g = 0; g < NT; ++g) {
+    const int pg = (tile * NT + g) * LINES + pair;
+    auto load = [src, npairs, pg](int k) -> float4 {  // coefficient k (1 .. L/2-1) times (-1)^k; 0 for k = 0
+      float4 x = src.ld4(((k - 1) * npairs + pg) * 16);
+      if (k & 1) x = make_float4(-x.x, -x.y, -x.z, -x.w);
+      return x;
+    };
 #pragma unroll
-  for (int c = 0; c < BPT0 / 2; ++c) {
-    if (!Eng::template ok<0, true>(t, 2 * c)) continue;
-    const int ja = t + P * c;
-    const bool zero = ja == 0;
-    const int jb = zero ? NB0 / 2 : NB0 - ja;
-    float4 xa[NA], xb[NBH > 0 ? NBH : 1];
+    for (int s2 = 0; s2 < E; ++s2) v[g][s2] = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int r = 0; r < NA; ++r) xa[r] = load(ja + r * NB0);
+    for (int c = 0; c < BPT0 / 2; ++c) {
+      if (!Eng::template ok<0, true>(t, 2 * c)) continue;
+      const int ja = t + P * c;
+      const bool zero = ja == 0;
+      const int jb = zero ? NB0 / 2 : NB0 - ja;
+      float4 xa[NA], xb[NBH > 0 ? NBH : 1];
 #pragma unroll
-    for (int r = 0; r < NBH; ++r) xb[r] = load(jb + r * NB0);
-    float2* va = v + (2 * c) * R0;
-    float2* vb = v + (2 * c + 1) * R0;
-    if (!zero) {
+      for (int r = 0; r < NA; ++r) xa[r] = load(ja + r * NB0);
 #pragma unroll
-      for (int r = 0; r < R0; ++r) {
-        va[r] = r < NA ? herm_direct(xa[r]) : herm_mirror(xb[R0 - 1 - r]);
-        vb[r] = r < NBH ? herm_direct(xb[r]) : herm_mirror(xa[R0 - 1 - r]);
-      }
-    } else {
+      for (int r = 0; r < NBH; ++r) xb[r] = load(jb + r * NB0);
+      float2* va = v[g] + (2 * c) * R0;
+      float2* vb = v[g] + (2 * c + 1) * R0;
+      if (!zero) {
 #pragma unroll
-      for (int r = 0; r < R0; ++r) {
-        // butterfly 0: inputs r NB0 (mirror (R0 - r) NB0); Nyquist at r = R0/2 for even R0
-        if (r < NA) va[r] = herm_direct(xa[r]);
-        else if (2 * r == R0) va[r] = make_float2(0.f, 0.f);
-        else va[r] = herm_mirror(xa[R0 - r]);
-        // butterfly NB0/2: inputs NB0/2 + r NB0 (mirror (R0-1-r)); Nyquist at r = (R0-1)/2 for odd R0
-        if (r < NBH) vb[r] = herm_direct(xb[r]);
-        else if (2 * r + 1 == R0) vb[r] = make_float2(0.f, 0.f);
-        else vb[r] = herm_mirror(xb[R0 - 1 - r]);
+        for (int r = 0; r < R0; ++r) {
+          va[r] = r < NA ? herm_direct(xa[r]) : herm_mirror(xb[R0 - 1 - r]);
+          vb[r] = r < NBH ? herm_direct(xb[r]) : herm_mirror(xa[R0 - 1 - r]);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+          // butterfly 0: inputs r NB0 (mirror (R0 - r) NB0); Nyquist at r = R0/2 for even R0
+          if (r < NA) va[r] = herm_direct(xa[r]);
+          else if (2 * r == R0) va[r] = make_float2(0.f, 0.f);
+          else va[r] = herm_mirror(xa[R0 - r]);
+          // butterfly NB0/2: inputs NB0/2 + r NB0 (mirror (R0-1-r)); Nyquist at r = (R0-1)/2 for odd R0
+          if (r < NBH) vb[r] = herm_direct(xb[r]);
+          else if (2 * r + 1 == R0) vb[r] = make_float2(0.f, 0.f);
+          else vb[r] = herm_mirror(xb[R0 - 1 - r]);
+        }
       }
     }
   }
-  Eng::template run<true, false, true, Lay>(v, pair, t, lds, tw);
-  if (!active) return;
 
   // one image's nout x nlines block (or nlines x nout, transposed)
   const GBuf dst(out + map.out(img), (long long)nout * nlines * 4);
-  // output row r = t + P b + q NBL - r0: offsets at o0 + (P b + q NBL) * step
-  const int o0 = TRANS ? (2 * pg * nout + t - r0) * 4 : ((t - r0) * nlines + 2 * pg) * 4;
   const int step = TRANS ? 4 : nlines * 4;
-  float2 old[E];
-  if constexpr (ACCUM) {
-    // read every old value first so the adds do not serialise on memory
-    // latency (reading them before the transform instead was measured slower)
 #pragma unroll
-    for (int b = 0; b < BPTL; ++b)
+  for (int g = 0; g < NT; ++g) {
+    Eng::template run<true, false, true, Lay>(v[g], pair, t, lds, tw);
+    const int pg = (tile * NT + g) * LINES + pair;
+    if (pg >= npairs) continue;
+    // output row r = t + P b + q NBL - r0: offsets at o0 + (P b + q NBL) * step
+    const int o0 = TRANS ? (2 * pg * nout + t - r0) * 4 : ((t - r0) * nlines + 2 * pg) * 4;
+    float2 old[E];
+    if constexpr (ACCUM) {
+      // read every old value first so the adds do not serialise on memory
+      // latency (reading them before the transform instead was measured slower)
+#pragma unroll
+      for (int b = 0; b < BPTL; ++b)
+#pragma unroll
+        for (int q = 0; q < RL; ++q) {
+          const int o = o0 + (P * b + q * NBL) * step;
+          if constexpr (TRANS) old[b * RL + q] = make_float2(dst.ld1(o), dst.ld1(o + nout * 4));
+          else old[b * RL + q] = dst.ld2(o);
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < BPTL; ++b) {
+      if (!Eng::template ok<LAST, false>(t, b)) continue;
 #pragma unroll
       for (int q = 0; q < RL; ++q) {
+        const int r = t + P * b + q * NBL - r0;
         const int o = o0 + (P * b + q * NBL) * step;
-        if constexpr (TRANS) old[b * RL + q] = make_float2(dst.ld1(o), dst.ld1(o + nout * 4));
-        else old[b * RL + q] = dst.ld2(o);
-      }
-  }
-#pragma unroll
-  for (int b = 0; b < BPTL; ++b) {
-    if (!Eng::template ok<LAST, false>(t, b)) continue;
-#pragma unroll
-    for (int q = 0; q < RL; ++q) {
-      const int r = t + P * b + q * NBL - r0;
-      const int o = o0 + (P * b + q * NBL) * step;
-      float a = scale * v[b * RL + q].x, bb = scale * v[b * RL + q].y;
-      if constexpr (ACCUM) {
-        a += old[b * RL + q].x;
-        bb += old[b * RL + q].y;
-      }
-      if constexpr (TRANS) {
-        // rows outside [0, nout) would land in the neighbouring line
-        if (r < 0 || r >= nout) continue;
-        dst.st1(a, o);
-        dst.st1(bb, o + nout * 4);
-      } else {
-        dst.st2(make_float2(a, bb), o);   // rows outside [0, nout) fall outside the buffer
+        float a = scale * v[g][b * RL + q].x, bb = scale * v[g][b * RL + q].y;
+        if constexpr (ACCUM) {
+          a += old[b * RL + q].x;
+          bb += old[b * RL + q].y;
+        }
+        if constexpr (TRANS) {
+          // rows outside [0, nout) would land in the neighbouring line
+          if (r < 0 || r >= nout) continue;
+          dst.st1(a, o);
+          dst.st1(bb, o + nout * 4);
+        } else {
+          dst.st2(make_float2(a, bb), o);   // rows outside [0, nout) fall outside the buffer
+        }
       }
     }
   }
@@ -731,8 +754,9 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
 template <int L, int PREC>
 unsigned col_variant_mask_t() {
   unsigned m = 0;
-#define FUNNEL_V(i, e, l) \
-  if constexpr (FastCfg<L, e, l>::valid && (PREC == kPrecFP32 || mfma_fits(L, e, FastCfg<L, e, l>::THREADS))) m |= 1u << i;
+#define FUNNEL_V(i, e, l, nt)                                                                             \
+  if constexpr (FastCfg<L, e, l, nt>::valid && (PREC == kPrecFP32 || (nt == 1 && mfma_fits(L, e, FastCfg<L, e, l, nt>::THREADS)))) \
+    m |= 1u << i;
   FUNNEL_COL_VARIANTS(FUNNEL_V)
 #undef FUNNEL_V
   if (PREC != kPrecFP32) return m;
@@ -761,16 +785,17 @@ template <int L, int PREC>
 hipError_t launch_r2c_t(int variant, bool trans, const float* in, float2* out, int nlines, int lin, int off,
                         ImgMap map, float scale, const float2* tw, int batch, hipStream_t s) {
   switch (variant) {
-#define FUNNEL_V(i, e, l)                                                                                    \
+#define FUNNEL_V(i, e, l, nt)                                                                                \
   case i:                                                                                                    \
-    if constexpr (FastCfg<L, e, l>::valid && (PREC == kPrecFP32 || mfma_fits(L, e, FastCfg<L, e, l>::THREADS))) { \
-      using F = FastCfg<L, e, l>;                                                                            \
-      const int tiles = (nlines / 2 + F::LINES - 1) / F::LINES;                                              \
+    if constexpr (FastCfg<L, e, l, nt>::valid &&                                                             \
+                  (PREC == kPrecFP32 || (nt == 1 && mfma_fits(L, e, FastCfg<L, e, l, nt>::THREADS)))) {                    \
+      using F = FastCfg<L, e, l, nt>;                                                                        \
+      const int tiles = (nlines / 2 + F::LINES * nt - 1) / (F::LINES * nt);                                  \
       dim3 grid(tiles, batch), block(F::THREADS);                                                            \
       if (trans)                                                                                             \
-        k_r2c_fast<L, e, l, true, PREC><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, tiles); \
+        k_r2c_fast<L, e, l, nt, true, PREC><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, tiles); \
       else                                                                                                   \
-        k_r2c_fast<L, e, l, false, PREC><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, tiles); \
+        k_r2c_fast<L, e, l, nt, false, PREC><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, tiles); \
       return hipGetLastError();                                                                              \
     }                                                                                                        \
     break;
@@ -807,22 +832,23 @@ template <int L, int PREC>
 hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0,
                         int nout, ImgMap map, float scale, const float2* tw, int batch, hipStream_t s) {
   switch (variant) {
-#define FUNNEL_V(i, e, l)                                                                                    \
+#define FUNNEL_V(i, e, l, nt)                                                                                \
   case i:                                                                                                    \
-    if constexpr (FastCfg<L, e, l>::valid && (PREC == kPrecFP32 || mfma_fits(L, e, FastCfg<L, e, l>::THREADS))) { \
-      using F = FastCfg<L, e, l>;                                                                            \
-      const int tiles = (nlines / 2 + F::LINES - 1) / F::LINES;                                              \
+    if constexpr (FastCfg<L, e, l, nt>::valid &&                                                             \
+                  (PREC == kPrecFP32 || (nt == 1 && mfma_fits(L, e, FastCfg<L, e, l, nt>::THREADS)))) {                    \
+      using F = FastCfg<L, e, l, nt>;                                                                        \
+      const int tiles = (nlines / 2 + F::LINES * nt - 1) / (F::LINES * nt);                                  \
       dim3 grid(tiles, batch), block(F::THREADS);                                                            \
       if (trans) {                                                                                           \
         if (accum)                                                                                           \
-          k_c2r_fast<L, e, l, true, true, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
+          k_c2r_fast<L, e, l, nt, true, true, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
         else                                                                                                 \
-          k_c2r_fast<L, e, l, true, false, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
+          k_c2r_fast<L, e, l, nt, true, false, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
       } else {                                                                                               \
         if (accum)                                                                                           \
-          k_c2r_fast<L, e, l, false, true, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
+          k_c2r_fast<L, e, l, nt, false, true, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
         else                                                                                                 \
-          k_c2r_fast<L, e, l, false, false, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
+          k_c2r_fast<L, e, l, nt, false, false, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
       }                                                                                                      \
       return hipGetLastError();                                                                              \
     }                                                                                                        \
