@@ -53,6 +53,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="the CPU oracle sample takes whole images until this much time has passed")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default tile variants")
+    ap.add_argument("--variants", type=str, default="",
+                    help="comma-separated tile variant per launch (role order of funnel_plan_variants); "
+                         "skips the autotuner, so counter runs time the variants a timed run picked")
     ap.add_argument("--workload", choices=["grad", "ragged", "precision"], default="grad",
                     help="grad: the 32 x 1024^2 batch (default); ragged: 256 images of mixed sizes; "
                          "precision: 8 x 2048^2 in FP32 and with the split-precision matrix-core passes")
@@ -81,7 +84,10 @@ def main():
     plan = F.FunnelPlan(B, N, M, 0, F.FT_SPACE_BOTH)
     Np = plan.Np
     tuned = None
-    if not args.no_autotune:
+    if args.variants:
+        for role, v in enumerate(int(t) for t in args.variants.split(",")):
+            F.funnel_plan_set_variant(plan.handle, role, v)
+    elif not args.no_autotune:
         tuned = F.funnel_autotune(plan.handle)   # set-up, outside the timed region
     x = torch.from_numpy(host).cuda()
     planes = plan.forward(x)
