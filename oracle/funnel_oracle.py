@@ -22,6 +22,10 @@ design notes of the repository):
   bottom half follows by conjugate symmetry (Sec. 3.1); the DC and Nyquist
   rows are dropped.
 * forward DFTs are unnormalised, the final inverse DFT carries 1/Np.
+* two NVMT realisations: ``"linear"`` interpolation (Sec. V's O(M^2)
+  option, the default) and ``"chirpz"``, the band-limited resampling the
+  paper adopts (opening of Sec. IV), written out as the scaled-frequency DFT
+  it equals.
 * parameter plane ``P[y + Np/2, m1 + M/2]`` is real; the brightness is |P|.
   A line ``y = k x + b`` (centred) peaks at ``m1 = -k M/2``, ``y = b``
   (Eq. 19 with the sign of Eq. 13); the paper's slope index is m = -m1.
@@ -32,6 +36,7 @@ import numpy as np
 
 __all__ = [
     "padded_length", "expand", "spectrum_y", "nvmt", "dft_x", "idft_y",
+    "nvmt_dft_chirpz", "NVMT_KINDS",
     "forward_regular", "forward_inverse", "forward",
     "adjoint_regular", "adjoint_inverse", "adjoint",
     "boundary_mask", "peaks_list", "peak_params",
@@ -114,6 +119,41 @@ def dft_x(g: np.ndarray) -> np.ndarray:
     return g @ _xdft_matrix(g.shape[1])
 
 
+def nvmt_dft_chirpz(S: np.ndarray, Np: int) -> np.ndarray:
+    """NVMT by band-limited resampling fused with the x' DFT (Sec. 3.1's
+    second and third steps, realised the way the opening of Sec. IV adopts:
+    chirp-z interpolation instead of the linear one; Remark 1).
+
+    The row f(x) = S[n2, x] is read as a band-limited function; resampling it
+    as g(x') = f(x'/s) scales its spectrum, so the DFT of the resampled row is
+    the row's own DTFT at the scaled frequencies s m1 / M, times s:
+
+        G[n2, m1] = s sum_x S[n2, x] exp(-j 2 pi s m1 x / M),  s = 2 n2 / Np,
+
+    centred x and m1 in [-M/2, M/2).  Written out as that sum with the phase
+    s m1 x / M = 2 n2 m1 x / (Np M) reduced exactly in integers."""
+    h, M = S.shape
+    x = np.arange(M, dtype=np.int64) - M // 2
+    period = Np * M
+    G = np.empty_like(S, dtype=np.complex128)
+    for n2 in range(1, h + 1):
+        ph = np.mod(2 * n2 * np.outer(x, x), period)          # [m1, x]
+        E = np.exp(-2j * np.pi * ph / period)
+        G[n2 - 1] = (2.0 * n2 / Np) * (E @ S[n2 - 1])
+    return G
+
+
+NVMT_KINDS = ("linear", "chirpz")
+
+
+def _resample_and_dft(S: np.ndarray, Np: int, kind: str) -> np.ndarray:
+    if kind == "linear":
+        return dft_x(nvmt(S, Np))
+    if kind == "chirpz":
+        return nvmt_dft_chirpz(S, Np)
+    raise ValueError(f"unknown NVMT kind {kind!r}")
+
+
 def idft_y(G: np.ndarray, Np: int) -> np.ndarray:
     """Sec. 3.1 fourth step (Eq. 19 / P(omega_1, y)): inverse DFT along omega_2.
 
@@ -135,7 +175,7 @@ def idft_y(G: np.ndarray, Np: int) -> np.ndarray:
     return P.real
 
 
-def forward_regular(img: np.ndarray, padded_len: int = 0) -> np.ndarray:
+def forward_regular(img: np.ndarray, padded_len: int = 0, nvmt_kind: str = "linear") -> np.ndarray:
     """Funnel transform (Sec. 3.1) of one image on its expanded frame
     (Sec. 4.2): the regular parameter space, slopes in (-1, 1].
     Returns P[Np, M] in float64."""
@@ -143,21 +183,21 @@ def forward_regular(img: np.ndarray, padded_len: int = 0) -> np.ndarray:
     N, M = img.shape
     Np = padded_length(N, M, padded_len)
     S = spectrum_y(expand(img, Np))
-    return idft_y(dft_x(nvmt(S, Np)), Np)
+    return idft_y(_resample_and_dft(S, Np, nvmt_kind), Np)
 
 
-def forward_inverse(img: np.ndarray, padded_len: int = 0) -> np.ndarray:
+def forward_inverse(img: np.ndarray, padded_len: int = 0, nvmt_kind: str = "linear") -> np.ndarray:
     """Inverse funnel transform (Sec. 3.1, dual form; Remark 1): the same four
     steps with the roles of x and y exchanged, i.e. the funnel transform of the
     transposed image.  Returns P_inv[Np, N]: rows are the x-intercept, columns
     the inverse-slope bin."""
     img = np.asarray(img, dtype=np.float64)
-    return forward_regular(img.T, padded_len)
+    return forward_regular(img.T, padded_len, nvmt_kind)
 
 
-def forward(img: np.ndarray, padded_len: int = 0):
+def forward(img: np.ndarray, padded_len: int = 0, nvmt_kind: str = "linear"):
     """Both parameter spaces (Sec. 4.1): (regular, inverse)."""
-    return forward_regular(img, padded_len), forward_inverse(img, padded_len)
+    return forward_regular(img, padded_len, nvmt_kind), forward_inverse(img, padded_len, nvmt_kind)
 
 
 # --------------------------------------------------------------------------
@@ -184,7 +224,23 @@ def _nvmt_transpose(dg: np.ndarray, Np: int) -> np.ndarray:
     return dS
 
 
-def adjoint_regular(dP: np.ndarray, N: int, M: int, padded_len: int = 0) -> np.ndarray:
+def _nvmt_dft_chirpz_transpose(dG: np.ndarray, Np: int) -> np.ndarray:
+    """Conjugate transpose of ``nvmt_dft_chirpz``: the kernel
+    s exp(-j 2 pi s m1 x / M) is symmetric in (m1, x), so its adjoint is
+    dS[n2, x] = s sum_m1 dG[n2, m1] exp(+j 2 pi s m1 x / M)."""
+    h, M = dG.shape
+    x = np.arange(M, dtype=np.int64) - M // 2
+    period = Np * M
+    dS = np.empty_like(dG, dtype=np.complex128)
+    for n2 in range(1, h + 1):
+        ph = np.mod(2 * n2 * np.outer(x, x), period)          # [x, m1]
+        E = np.exp(2j * np.pi * ph / period)
+        dS[n2 - 1] = (2.0 * n2 / Np) * (E @ dG[n2 - 1])
+    return dS
+
+
+def adjoint_regular(dP: np.ndarray, N: int, M: int, padded_len: int = 0,
+                    nvmt_kind: str = "linear") -> np.ndarray:
     """Transpose of ``forward_regular`` under the real inner products of
     image and plane: dI = A^T B^T C^T dP, where C is the Hermitian inverse DFT,
     B the NVMT followed by the x' DFT and A the expansion plus y DFT."""
@@ -193,23 +249,31 @@ def adjoint_regular(dP: np.ndarray, N: int, M: int, padded_len: int = 0) -> np.n
     assert dP.shape == (Np, M)
     # C^T: P = (1/Np) sum_n2 2 Re(G[n2] e^{+j theta})  =>  dG = (2/Np) sum_y dP e^{-j theta}
     dG = (2.0 / Np) * (_ydft_matrix(Np) @ dP)
-    # B^T: conjugate transpose of the x' DFT, then the transposed interpolation
-    dg = dG @ np.conj(_xdft_matrix(M)).T
-    dS = _nvmt_transpose(dg, Np)
+    if nvmt_kind == "linear":
+        # B^T: conjugate transpose of the x' DFT, then the transposed interpolation
+        dg = dG @ np.conj(_xdft_matrix(M)).T
+        dS = _nvmt_transpose(dg, Np)
+    elif nvmt_kind == "chirpz":
+        dS = _nvmt_dft_chirpz_transpose(dG, Np)
+    else:
+        raise ValueError(f"unknown NVMT kind {nvmt_kind!r}")
     # A^T: S = E I_pad with real I_pad  =>  dI_pad = Re(E^H dS), then crop
     dI_pad = np.real(np.conj(_ydft_matrix(Np)).T @ dS)
     top = (Np - N) // 2
     return dI_pad[top:top + N]
 
 
-def adjoint_inverse(dPinv: np.ndarray, N: int, M: int, padded_len: int = 0) -> np.ndarray:
+def adjoint_inverse(dPinv: np.ndarray, N: int, M: int, padded_len: int = 0,
+                    nvmt_kind: str = "linear") -> np.ndarray:
     """Transpose of ``forward_inverse``."""
-    return adjoint_regular(dPinv, M, N, padded_len).T
+    return adjoint_regular(dPinv, M, N, padded_len, nvmt_kind).T
 
 
-def adjoint(dP: np.ndarray, dPinv: np.ndarray, N: int, M: int, padded_len: int = 0) -> np.ndarray:
+def adjoint(dP: np.ndarray, dPinv: np.ndarray, N: int, M: int, padded_len: int = 0,
+            nvmt_kind: str = "linear") -> np.ndarray:
     """Transpose of ``forward`` (both spaces): the two image gradients add."""
-    return adjoint_regular(dP, N, M, padded_len) + adjoint_inverse(dPinv, N, M, padded_len)
+    return (adjoint_regular(dP, N, M, padded_len, nvmt_kind) +
+            adjoint_inverse(dPinv, N, M, padded_len, nvmt_kind))
 
 
 # --------------------------------------------------------------------------

@@ -304,7 +304,7 @@ def check_linearity(O):
 
 # ----------------------------------------------------------------- adjoint
 
-def check_adjoint_dot(O):
+def check_adjoint_dot(O, kind="linear"):
     """<F x, y> = <x, F^T y> for both spaces together."""
     rng = np.random.default_rng(41)
     for (N, M) in [(8, 8), (10, 6), (16, 12)]:
@@ -312,23 +312,23 @@ def check_adjoint_dot(O):
         x = rng.standard_normal((N, M))
         y0 = rng.standard_normal((Np, M))
         y1 = rng.standard_normal((Np, N))
-        P, Pi = O.forward(x)
+        P, Pi = O.forward(x, 0, kind)
         lhs = (P * y0).sum() + (Pi * y1).sum()
-        rhs = (x * O.adjoint(y0, y1, N, M)).sum()
+        rhs = (x * O.adjoint(y0, y1, N, M, 0, kind)).sum()
         assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
 
 
-def dense_forward(O, N, M, space):
+def dense_forward(O, N, M, space, kind="linear"):
     f = O.forward_regular if space == "regular" else O.forward_inverse
     cols = []
     for i in range(N * M):
         e = np.zeros(N * M)
         e[i] = 1.0
-        cols.append(f(e.reshape(N, M)).ravel())
+        cols.append(f(e.reshape(N, M), 0, kind).ravel())
     return np.stack(cols, axis=1)
 
 
-def dense_adjoint(O, N, M, space):
+def dense_adjoint(O, N, M, space, kind="linear"):
     Np = N + M
     shape = (Np, M) if space == "regular" else (Np, N)
     f = O.adjoint_regular if space == "regular" else O.adjoint_inverse
@@ -336,16 +336,16 @@ def dense_adjoint(O, N, M, space):
     for j in range(shape[0] * shape[1]):
         e = np.zeros(shape[0] * shape[1])
         e[j] = 1.0
-        rows.append(f(e.reshape(shape), N, M).ravel())
+        rows.append(f(e.reshape(shape), N, M, 0, kind).ravel())
     return np.stack(rows, axis=1)
 
 
-def check_adjoint_dense(O, N=8, M=8):
+def check_adjoint_dense(O, N=8, M=8, kind="linear"):
     """The adjoint applied to every unit plane equals the transpose of the
     forward applied to every unit image."""
     for space in ("regular", "inverse"):
-        F = dense_forward(O, N, M, space)
-        Ft = dense_adjoint(O, N, M, space)
+        F = dense_forward(O, N, M, space, kind)
+        Ft = dense_adjoint(O, N, M, space, kind)
         assert np.abs(Ft - F.T).max() <= 1e-12 * np.abs(F).max()
 
 
@@ -449,3 +449,114 @@ def check_peak_params(O):
             assert abs(kd) <= 1.0 / width + 1e-12
             if abs(kk - k) < 0.5:
                 assert abs(bb - ln.b) <= 0.5 + (1.0 / width) * width / 2 + 1e-9
+
+
+# ----------------------------------------------------------------- chirp-z (band-limited) NVMT
+
+def ramp_kernel(t, Np):
+    """h(t) = (1/Np) sum over n2 != 0, Np/2 of |2 n2 / Np| exp(j 2 pi n2 t / Np):
+    the ramp filter of the y DFT's rows, as a real cosine sum."""
+    n = np.arange(1, Np // 2)
+    t = np.asarray(t, dtype=np.float64)
+    return (2.0 / Np) * (np.cos(2 * np.pi * np.multiply.outer(t, n) / Np) * (2.0 * n / Np)).sum(axis=-1)
+
+
+def slant_stack(img, Np):
+    """Band-limited funnel transform evaluated in the image domain: every
+    pixel (x, y0) spreads the ramp kernel along its line y = y0 + 2 m1 x / M
+    of the parameter plane (point-to-line mapping, Eq. 13 with omega_max = pi,
+    under the ramp weighting |s| of the NVMT):
+        P(m1, y) = sum_{x, y0} I(x, y0) h(y - y0 - 2 m1 x / M).
+    This is the chirp-z funnel transform composed in closed form; it shares
+    no step with the oracle's DFT route."""
+    N, M = img.shape
+    top = (Np - N) // 2
+    m1 = np.arange(M) - M // 2
+    y = np.arange(Np) - Np // 2
+    P = np.zeros((Np, M))
+    for r in range(N):
+        for c in range(M):
+            if img[r, c] == 0.0:
+                continue
+            x, y0 = c - M // 2, r + top - Np // 2
+            P += img[r, c] * ramp_kernel(y[:, None] - y0 - 2.0 * m1[None, :] * x / M, Np)
+    return P
+
+
+def check_chirpz_slant_stack(O):
+    """The chirp-z oracle equals the slant-stack closed form in both spaces,
+    for the default and an enlarged padded length, square and not."""
+    rng = np.random.default_rng(51)
+    for (N, M, pl) in [(8, 8, 0), (16, 12, 0), (10, 14, 30), (12, 6, 0)]:
+        img = rng.random((N, M))
+        Np = O.padded_length(N, M, pl)
+        P, Pi = O.forward(img, pl, "chirpz")
+        for got, want in ((P, slant_stack(img, Np)), (Pi, slant_stack(img.T, Np))):
+            assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), (N, M, pl)
+
+
+def check_chirpz_special_rows(O):
+    """Rows whose ratio s is 1/2 or 1/4 are zero-padded DFTs: with K = 1/s,
+    G[m1] = s * FFT_{K M}(row placed at x mod K M)[m1 mod K M]."""
+    rng = np.random.default_rng(52)
+    M, Np = 24, 48
+    h = Np // 2 - 1
+    S = rng.standard_normal((h, M)) + 1j * rng.standard_normal((h, M))
+    G = O.nvmt_dft_chirpz(S, Np)
+    x = np.arange(M) - M // 2
+    for K in (2, 4):
+        n2 = Np // (2 * K)
+        a = np.zeros(K * M, dtype=np.complex128)
+        a[x % (K * M)] = S[n2 - 1]
+        want = np.fft.fft(a)[x % (K * M)] / K
+        assert np.abs(G[n2 - 1] - want).max() <= 1e-12 * np.abs(want).max(), K
+
+
+def check_chirpz_point_to_line(O):
+    """A one-pixel image at centred (u, v) maps to the ramp kernel centred on
+    the line y = v + 2 u m1 / M: in every slope column where that offset is a
+    whole number of rows, the column's maximum sits exactly on the line."""
+    N = M = 64
+    Np = N + M
+    for (u, v) in [(16, 5), (-16, -9), (8, 0), (-24, 13)]:
+        img = np.zeros((N, M))
+        img[v + N // 2, u + M // 2] = 1.0
+        P = O.forward_regular(img, 0, "chirpz")
+        checked = 0
+        for col in range(M):
+            m1 = col - M // 2
+            if (2 * u * m1) % M:
+                continue
+            y = v + 2 * u * m1 // M
+            assert int(np.argmax(P[:, col])) == (y + Np // 2) % Np, (u, v, m1)
+            checked += 1
+        assert checked >= M // 4
+
+
+def check_chirpz_line_to_point(O):
+    """Eq. 19 holds for the band-limited NVMT as for the linear one: a long
+    ridge line focuses within one cell of (m1 = -k M/2, y = b)."""
+    rng = np.random.default_rng(23)
+    N = M = 64
+    Np = N + M
+    for trial in range(6):
+        transposed = bool(trial % 2)
+        k = float(rng.uniform(-0.9, 0.9))
+        extent = M if transposed else N
+        b = float(rng.uniform(0.3 * extent, 0.7 * extent)) - k * extent / 2
+        ln = synth.Line("ridge", transposed, k, b, width=1.0)
+        img = synth.render(N, M, [ln], 0.0, rng, bg=0.0)
+        space, er, ec = expected_cell(ln, N, M, Np)
+        P = O.forward_regular(img, 0, "chirpz") if space == "regular" else O.forward_inverse(img, 0, "chirpz")
+        B = np.abs(P)
+        r, c = np.unravel_index(np.argmax(B), B.shape)
+        assert torus_dist(r, er, B.shape[0]) <= 1 and torus_dist(c, ec, B.shape[1]) <= 1, \
+            (trial, space, (r, c), (er, ec))
+
+
+def check_chirpz_adjoint_dot(O):
+    check_adjoint_dot(O, "chirpz")
+
+
+def check_chirpz_adjoint_dense(O):
+    check_adjoint_dense(O, 8, 8, "chirpz")

@@ -53,8 +53,8 @@ def _no_expansion_offset(img, Np):
     return out
 
 
-def _adjoint_missing_two(dP, N, M, padded_len=0):
-    return 0.5 * _REAL["adjoint_regular"](dP, N, M, padded_len)
+def _adjoint_missing_two(dP, N, M, padded_len=0, kind="linear"):
+    return 0.5 * _REAL["adjoint_regular"](dP, N, M, padded_len, kind)
 
 
 def _peaks_only_detected_suppress(B, K, T, radius=1, mask=None, wrap=True):
@@ -80,8 +80,45 @@ def _peaks_only_detected_suppress(B, K, T, radius=1, mask=None, wrap=True):
     return out
 
 
+def _chirpz_rows(S, Np, sign=-1.0, ratio=2, scale=True, period_rows=None):
+    # the fused chirp-z NVMT with one planted change; s = ratio n2 / Np
+    h, M = S.shape
+    x = np.arange(M, dtype=np.int64) - M // 2
+    G = np.empty_like(S, dtype=complex)
+    for n2 in range(1, h + 1):
+        s = ratio * n2 / Np
+        period = (period_rows or Np) * M
+        ph = np.mod(ratio * n2 * np.outer(x, x), period)
+        E = np.exp(sign * 2j * np.pi * ph / period)
+        G[n2 - 1] = (s if scale else 1.0) * (E @ S[n2 - 1])
+    return G
+
+
+def _chirpz_wrong_sign(S, Np):
+    return _chirpz_rows(S, Np, sign=+1.0)
+
+
+def _chirpz_no_ratio_factor(S, Np):
+    return _chirpz_rows(S, Np, scale=False)
+
+
+def _chirpz_ratio_halved(S, Np):
+    # reads omega_max as 2*pi: s = n2 / Np
+    return _chirpz_rows(S, Np, ratio=1)
+
+
+def _chirpz_phase_period_M(S, Np):
+    # reduces the integer phase modulo 2 M instead of Np M
+    return _chirpz_rows(S, Np, period_rows=2)
+
+
+def _chirpz_transpose_no_conj(dG, Np):
+    return _chirpz_rows(dG, Np)
+
+
 _REAL = {name: getattr(O, name) for name in
-         ("nvmt", "spectrum_y", "dft_x", "idft_y", "expand", "adjoint_regular", "peaks_list")}
+         ("nvmt", "spectrum_y", "dft_x", "idft_y", "expand", "adjoint_regular", "peaks_list",
+          "nvmt_dft_chirpz", "_nvmt_dft_chirpz_transpose")}
 
 ALL_CHECKS = [
     pins.check_spectrum_is_library_fft, pins.check_xdft_is_library_fft,
@@ -91,6 +128,9 @@ ALL_CHECKS = [
     pins.check_fig6_intercept_wrap, pins.check_fig7_slope_wrap,
     pins.check_shift_equivariance, pins.check_adjoint_dot, pins.check_adjoint_dense,
     pins.check_peaks_equal_local_maxima,
+    pins.check_chirpz_slant_stack, pins.check_chirpz_special_rows,
+    pins.check_chirpz_point_to_line, pins.check_chirpz_line_to_point,
+    pins.check_chirpz_adjoint_dot, pins.check_chirpz_adjoint_dense,
 ]
 
 MUTANTS = {
@@ -102,6 +142,11 @@ MUTANTS = {
     "expansion not centred": ("expand", _no_expansion_offset),
     "adjoint loses factor 2": ("adjoint_regular", _adjoint_missing_two),
     "peak list suppresses only by detected cells": ("peaks_list", _peaks_only_detected_suppress),
+    "chirp-z exponent sign": ("nvmt_dft_chirpz", _chirpz_wrong_sign),
+    "chirp-z without the ratio factor s": ("nvmt_dft_chirpz", _chirpz_no_ratio_factor),
+    "chirp-z ratio read as n2 / Np": ("nvmt_dft_chirpz", _chirpz_ratio_halved),
+    "chirp-z phase reduced modulo 2 M": ("nvmt_dft_chirpz", _chirpz_phase_period_M),
+    "chirp-z adjoint without conjugate": ("_nvmt_dft_chirpz_transpose", _chirpz_transpose_no_conj),
 }
 
 

@@ -24,6 +24,12 @@ CHECKS = [
     pins.check_adjoint_finite_difference,
     pins.check_peaks_equal_local_maxima,
     pins.check_peak_params,
+    pins.check_chirpz_slant_stack,
+    pins.check_chirpz_special_rows,
+    pins.check_chirpz_point_to_line,
+    pins.check_chirpz_line_to_point,
+    pins.check_chirpz_adjoint_dot,
+    pins.check_chirpz_adjoint_dense,
 ]
 
 
