@@ -56,7 +56,7 @@ def main():
     ap.add_argument("--variants", type=str, default="",
                     help="comma-separated tile variant per launch (role order of funnel_plan_variants); "
                          "skips the autotuner, so counter runs time the variants a timed run picked")
-    ap.add_argument("--workload", choices=["grad", "ragged", "precision"], default="grad",
+    ap.add_argument("--workload", choices=["grad", "chirpz", "ragged", "precision"], default="grad",
                     help="grad: the 32 x 1024^2 batch (default); ragged: 256 images of mixed sizes; "
                          "precision: 8 x 2048^2 in FP32 and with the split-precision matrix-core passes")
     args = ap.parse_args()
@@ -81,7 +81,8 @@ def main():
     host = synth.stack(imgs)
     log(f"  {time.time() - t0:.1f} s")
 
-    plan = F.FunnelPlan(B, N, M, 0, F.FT_SPACE_BOTH)
+    nvmt = "chirpz" if args.workload == "chirpz" else "linear"
+    plan = F.FunnelPlan(B, N, M, 0, F.FT_SPACE_BOTH, nvmt=nvmt)
     Np = plan.Np
     tuned = None
     if args.variants:
@@ -140,14 +141,15 @@ def main():
              "adj.regular.Ct", "adj.regular.Bt", "adj.regular.At", "adj.inverse.Ct", "adj.inverse.Bt",
              "adj.inverse.At"]
     variants = F.funnel_plan_variants(plan.handle)
-    traffic = measured_traffic(dom["name"], variants[roles.index(dom["name"])])
+    traffic = measured_traffic(dom["name"], variants[roles.index(dom["name"])], nvmt)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(imgs, dP, plan, N, M, args.cpu_seconds)
+        cpu = cpu_baseline(imgs, dP, plan, N, M, args.cpu_seconds, nvmt)
 
     out = {
-        "metric": "Mpixel/s funnel fwd+adjoint, 1024^2 fp32 batch; % of HBM roofline",
+        "metric": ("Mpixel/s funnel fwd+adjoint, 1024^2 fp32 batch; % of HBM roofline" if nvmt == "linear" else
+                   "Mpixel/s funnel fwd+adjoint with the chirp-z NVMT, 1024^2 fp32 batch; % of HBM roofline"),
         "value": round(mpix, 1),
         "unit": "Mpixel/s",
         "n_gpus": 1,
@@ -161,8 +163,9 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{B} x {N}x{M} fp32 synthetic line images (5 ridge/step lines, noise), "
-                        f"regular+inverse space, Np={Np}, forward + adjoint",
-            "batch": B, "rows": N, "cols": M, "padded_len": Np, "spaces": "both",
+                        f"regular+inverse space, Np={Np}, forward + adjoint"
+                        + (", chirp-z NVMT" if nvmt == "chirpz" else ""),
+            "batch": B, "rows": N, "cols": M, "padded_len": Np, "spaces": "both", "nvmt": nvmt,
         },
         "roofline": {
             "bound": "hbm",
@@ -321,12 +324,13 @@ def precision_bench(args, torch, F, synth, B=8, size=2048):
     print(json.dumps(out), flush=True)
 
 
-def measured_traffic(launch: str, variant: int):
+def measured_traffic(launch: str, variant: int, nvmt: str = "linear"):
     """HBM bytes of one launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE table, if the kernel sources are unchanged since it was taken."""
     import glob
     import hashlib
-    path = os.path.join(ROOT, "profiles", "funnel_fwd_adj_32x1024_traffic.json")
+    name = "funnel_fwd_adj_32x1024_traffic.json" if nvmt == "linear" else "funnel_chirpz_32x1024_traffic.json"
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
@@ -362,10 +366,14 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes / ms / 1e6, ms
 
 
-def cpu_baseline(imgs, dP, plan, N, M, seconds):
+def cpu_baseline(imgs, dP, plan, N, M, seconds, nvmt="linear"):
     """The FP64 oracle, as it stands, on a bounded sample: forward (both
     spaces) and adjoint of whole images of the same workload, one after the
-    other, until `seconds` have passed."""
+    other, until `seconds` have passed.  The chirp-z oracle (a dense
+    scaled-frequency DFT per frequency row) takes about a minute per image, so
+    its sample is the regular space of one image, forward + adjoint; the
+    inverse space of a square image is the same work, so the rate counts
+    half a pixel per pixel of that sample."""
     from oracle import funnel_oracle as O
     try:
         from threadpoolctl import threadpool_info
@@ -374,6 +382,29 @@ def cpu_baseline(imgs, dP, plan, N, M, seconds):
         cores = os.cpu_count() or 1
     Np = plan.Np
     dPh = dP.cpu().numpy()
+    if nvmt == "chirpz":
+        # the y-DFT stages of one image's regular space in full, the row stage
+        # (chirp-z NVMT + x' DFT and its transpose) on its first k frequency
+        # rows, scaled by h / k (every row costs the same)
+        img = np.asarray(imgs[0].image, dtype=np.float64)
+        h, k = Np // 2 - 1, 160
+        d = dPh[0, : Np * M].reshape(Np, M).astype(np.float64)
+        t0 = time.time()
+        S = O.spectrum_y(O.expand(img, Np))
+        dG = (2.0 / Np) * (O._ydft_matrix(Np) @ d)
+        t1 = time.time()
+        G = O.nvmt_dft_chirpz(S[:k], Np)
+        O._nvmt_dft_chirpz_transpose(dG[:k], Np)
+        t2 = time.time()
+        O.idft_y(np.concatenate([G, S[k:]]), Np)               # C on a full-size spectrum
+        np.real(np.conj(O._ydft_matrix(Np)).T @ dG)            # the adjoint's A^T on a full-size one
+        t3 = time.time()
+        est = (t1 - t0) + (t2 - t1) * h / k + (t3 - t2)
+        return {"value": round(0.5 * N * M / est / 1e6, 4), "unit": "Mpixel/s", "cores": int(cores),
+                "kind": "oracle",
+                "sample": f"regular space of 1 of the {plan.batch} {N}x{M} images, forward + adjoint: y DFTs "
+                          f"in full, the chirp-z row stage on {k} of its {h} frequency rows scaled by {h}/{k} "
+                          f"({t3 - t0:.1f} s timed, {est:.1f} s estimated), counted as half of the image's work"}
     t0 = time.time()
     n = 0
     for b, im in enumerate(imgs):

@@ -89,6 +89,20 @@ enum { FT_SPACE_REGULAR = 1, FT_SPACE_INVERSE = 2, FT_SPACE_BOTH = 3 };
  * space) in 64 .. 4096; other shapes give FT_ERR_UNSUPPORTED_SIZE. */
 enum { FT_PREC_FP32 = 0, FT_PREC_BF16X3 = 1, FT_PREC_FP16X3 = 2 };
 
+/* ft_plan_desc flags.
+ *   FT_PLAN_NVMT_CHIRPZ : realise the NVMT by band-limited (chirp-z)
+ *     resampling, the way the paper adopts at the opening of Sec. IV, instead
+ *     of linear interpolation (Sec. V's O(M^2) option, the default).  Each
+ *     frequency row n2 (ratio s = 2 n2 / Np) then gets, fused with the DFT
+ *     along x', G[m1] = s sum_x S[x] exp(-j 2 pi s m1 x / W) over centred x
+ *     and m1 in [-W/2, W/2), W = M (regular space) or N (inverse space): the
+ *     resampled row's spectrum without interpolation attenuation.  It is
+ *     computed by Bluestein's algorithm with FFTs of length 2W; the plan holds
+ *     FP64-derived chirp tables of 24 * (Np/2 - 1) * W bytes per space.
+ *     FP32 only; row lengths W must be powers of two in 64 .. 2048, else
+ *     FT_ERR_UNSUPPORTED_SIZE.  Ragged plans use linear interpolation. */
+enum { FT_PLAN_NVMT_CHIRPZ = 1u };
+
 /* funnel_peaks flags. */
 enum {
   FT_PEAK_CLAMP_BORDER = 1u,     /* neighbourhood clamped at the plane edge instead of wrapping */
@@ -104,7 +118,7 @@ typedef struct {
   int32_t padded_len;  /* Np; 0 means N+M (Sec. 4.2); else even and >= N+M */
   int32_t spaces;      /* FT_SPACE_REGULAR, FT_SPACE_INVERSE or FT_SPACE_BOTH */
   int32_t precision;   /* FT_PREC_FP32, FT_PREC_BF16X3 or FT_PREC_FP16X3 */
-  uint32_t flags;      /* reserved, must be 0 */
+  uint32_t flags;      /* 0 or FT_PLAN_NVMT_CHIRPZ */
 } ft_plan_desc;
 
 /* One detected peak (Sec. 4.4) and its line (Eqs. 22-25).

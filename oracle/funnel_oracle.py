@@ -39,6 +39,7 @@ __all__ = [
     "nvmt_dft_chirpz", "NVMT_KINDS",
     "forward_regular", "forward_inverse", "forward",
     "adjoint_regular", "adjoint_inverse", "adjoint",
+    "forward_regular_columns", "adjoint_regular_columns",
     "boundary_mask", "peaks_list", "peak_params",
 ]
 
@@ -198,6 +199,60 @@ def forward_inverse(img: np.ndarray, padded_len: int = 0, nvmt_kind: str = "line
 def forward(img: np.ndarray, padded_len: int = 0, nvmt_kind: str = "linear"):
     """Both parameter spaces (Sec. 4.1): (regular, inverse)."""
     return forward_regular(img, padded_len, nvmt_kind), forward_inverse(img, padded_len, nvmt_kind)
+
+
+def forward_regular_columns(img: np.ndarray, cols, padded_len: int = 0,
+                            nvmt_kind: str = "linear") -> np.ndarray:
+    """Columns ``cols`` (array indices m1 + M/2) of ``forward_regular``, for
+    checking large planes on a sample: the same four steps, with the x' DFT
+    and the inverse y DFT evaluated only for the asked slope bins.
+    Returns P[:, cols], shape (Np, len(cols))."""
+    img = np.asarray(img, dtype=np.float64)
+    N, M = img.shape
+    Np = padded_length(N, M, padded_len)
+    cols = np.asarray(cols, dtype=np.int64)
+    S = spectrum_y(expand(img, Np))
+    h = S.shape[0]
+    m1 = cols - M // 2
+    x = np.arange(M, dtype=np.int64) - M // 2
+    if nvmt_kind == "linear":
+        G = nvmt(S, Np) @ np.exp(-2j * np.pi * np.outer(x, m1) / M)
+    elif nvmt_kind == "chirpz":
+        G = np.empty((h, len(cols)), dtype=np.complex128)
+        period = Np * M
+        for n2 in range(1, h + 1):
+            ph = np.mod(2 * n2 * np.outer(x, m1), period)
+            G[n2 - 1] = (2.0 * n2 / Np) * (S[n2 - 1] @ np.exp(-2j * np.pi * ph / period))
+    else:
+        raise ValueError(f"unknown NVMT kind {nvmt_kind!r}")
+    return idft_y(G, Np)
+
+
+def adjoint_regular_columns(dP: np.ndarray, N: int, M: int, cols, padded_len: int = 0,
+                            nvmt_kind: str = "linear") -> np.ndarray:
+    """Columns ``cols`` (array indices x + M/2) of ``adjoint_regular``: the
+    full C^T, then B^T and A^T evaluated only for the asked image columns.
+    Returns dI[:, cols], shape (N, len(cols))."""
+    dP = np.asarray(dP, dtype=np.float64)
+    Np = padded_length(N, M, padded_len)
+    cols = np.asarray(cols, dtype=np.int64)
+    dG = (2.0 / Np) * (_ydft_matrix(Np) @ dP)
+    h = dG.shape[0]
+    if nvmt_kind == "linear":
+        dS = _nvmt_transpose(dG @ np.conj(_xdft_matrix(M)).T, Np)[:, cols]
+    elif nvmt_kind == "chirpz":
+        x = cols - M // 2
+        m1 = np.arange(M, dtype=np.int64) - M // 2
+        period = Np * M
+        dS = np.empty((h, len(cols)), dtype=np.complex128)
+        for n2 in range(1, h + 1):
+            ph = np.mod(2 * n2 * np.outer(m1, x), period)
+            dS[n2 - 1] = (2.0 * n2 / Np) * (dG[n2 - 1] @ np.exp(2j * np.pi * ph / period))
+    else:
+        raise ValueError(f"unknown NVMT kind {nvmt_kind!r}")
+    dI_pad = np.real(np.conj(_ydft_matrix(Np)).T @ dS)
+    top = (Np - N) // 2
+    return dI_pad[top:top + N]
 
 
 # --------------------------------------------------------------------------

@@ -44,6 +44,8 @@ static const char* const kRoleName[NROLES] = {
 struct FtClass {
   int N = 0, M = 0, Np = 0, h = 0, count = 0;
   size_t tw_np = 0, tw_m = 0, tw_n = 0;   // float2 offsets of this class's tables in plan->tw
+  size_t tw_2m = 0, tw_2n = 0;            // chirp-z plans: twiddles of the length-2W transforms
+  size_t cz_m = 0, wz_m = 0, cz_n = 0, wz_n = 0;   // chirp-z plans: float2 offsets in plan->chirp
   size_t ws_reg = 0, ws_inv = 0;          // byte offsets of the half spectra in the workspace
   size_t off_inv_plane = 0;               // floats from an image's plane block to its inverse plane
   long long img_stride = 0, plane_stride = 0;
@@ -62,9 +64,11 @@ struct ft_plan {
   int spaces = 0;
   int batch = 0;
   int prec = 0;             // FT_PREC_*
+  bool chirpz = false;      // FT_PLAN_NVMT_CHIRPZ: band-limited NVMT in the row passes
   bool ragged = false;
   std::vector<FtClass> cls;
   float2* tw = nullptr;
+  float2* chirp = nullptr;  // chirp-z plans: per-row chirp spectra and chirps
   void* tables = nullptr;
   size_t ws_bytes = 0;
   size_t plane_elems = 0;   // uniform: floats per image; ragged: extent of the whole planes buffer
@@ -128,7 +132,8 @@ bool role_active(const ft_plan* p, int r) {
 }
 unsigned role_mask(const ft_plan* p, const FtClass& c, int r) {
   if (!role_is_row(r)) return funnel::col_variant_mask(c.Np, p->prec);
-  return funnel::row_variant_mask(role_regular(r) ? c.M : c.N, p->prec);
+  const int W = role_regular(r) ? c.M : c.N;
+  return p->chirpz ? funnel::chirp_variant_mask(W) : funnel::row_variant_mask(W, p->prec);
 }
 
 // Algorithmic HBM bytes of one launch: each input read once, each output
@@ -138,7 +143,8 @@ double role_bytes(const ft_plan* p, const FtClass& c, int r) {
   const double W = role_regular(r) ? M : N;  // lines of the spectrum
   switch (r) {
     case FA_REG: case FA_INV: return B * (4.0 * N * M + 8.0 * h * W);
-    case FB_REG: case FB_INV: case AB_REG: case AB_INV: return B * 16.0 * h * W;
+    // chirp-z rows also read the row's chirp spectrum (2W) and chirp (W) once
+    case FB_REG: case FB_INV: case AB_REG: case AB_INV: return B * 16.0 * h * W + (p->chirpz ? 24.0 * h * W : 0.0);
     case FC_REG: case FC_INV: return B * (8.0 * h * W + 4.0 * Np * W);
     case AC_REG: case AC_INV: return B * (4.0 * Np * W + 8.0 * h * W);
     case AA_REG: return B * (8.0 * h * M + ((p->spaces & FT_SPACE_INVERSE) ? 8.0 : 4.0) * N * M);
@@ -178,6 +184,7 @@ void free_plan(ft_plan* p) {
   }
   if (p->fork) (void)hipEventDestroy(p->fork);
   if (p->tw) (void)hipFree(p->tw);
+  if (p->chirp) (void)hipFree(p->chirp);
   if (p->tables) (void)hipFree(p->tables);
   delete p;
 }
@@ -206,19 +213,28 @@ hipError_t run_role(const ft_plan* p, const FtClass& c, int r, int v, const floa
     // forward, regular space: y DFT of the image columns on the expanded frame,
     // NVMT + x' DFT per frequency row, Hermitian inverse y DFT
     case FA_REG: return funnel::launch_r2c(Np, v, p->prec, false, src, Sr, M, N, (Np - N) / 2, img_to_sr, 1.0f, tw_np, B, s);
-    case FB_REG: return funnel::launch_row(M, v, p->prec, false, Sr, Np, h, sr, p->tw + c.tw_m, B, s);
+    case FB_REG:
+      if (p->chirpz)
+        return funnel::launch_chirp(M, v, false, Sr, h, sr, p->chirp + c.cz_m, p->chirp + c.wz_m, p->tw + c.tw_2m, B, s);
+      return funnel::launch_row(M, v, p->prec, false, Sr, Np, h, sr, p->tw + c.tw_m, B, s);
     case FC_REG:
       return funnel::launch_c2r(Np, v, p->prec, false, false, Sr, dst, M, 0, Np, sr_to_pl, 1.0f / Np, tw_np, B, s);
     // forward, inverse space: the same on the transposed image (rows read directly)
     case FA_INV: return funnel::launch_r2c(Np, v, p->prec, true, src, Si, N, M, (Np - M) / 2, img_to_si, 1.0f, tw_np, B, s);
-    case FB_INV: return funnel::launch_row(N, v, p->prec, false, Si, Np, h, si, p->tw + c.tw_n, B, s);
+    case FB_INV:
+      if (p->chirpz)
+        return funnel::launch_chirp(N, v, false, Si, h, si, p->chirp + c.cz_n, p->chirp + c.wz_n, p->tw + c.tw_2n, B, s);
+      return funnel::launch_row(N, v, p->prec, false, Si, Np, h, si, p->tw + c.tw_n, B, s);
     case FC_INV:
       return funnel::launch_c2r(Np, v, p->prec, false, false, Si, dst + c.off_inv_plane, N, 0, Np, si_to_pl, 1.0f / Np,
                                 tw_np, B, s);
     // adjoint, regular space: (2/Np) y DFT of the plane columns, conjugate x'
     // DFT + transposed interpolation, real part of the conjugate y DFT cropped
     case AC_REG: return funnel::launch_r2c(Np, v, p->prec, false, src, Sr, M, Np, 0, pl_to_sr, 2.0f / Np, tw_np, B, s);
-    case AB_REG: return funnel::launch_row(M, v, p->prec, true, Sr, Np, h, sr, p->tw + c.tw_m, B, s);
+    case AB_REG:
+      if (p->chirpz)
+        return funnel::launch_chirp(M, v, true, Sr, h, sr, p->chirp + c.cz_m, p->chirp + c.wz_m, p->tw + c.tw_2m, B, s);
+      return funnel::launch_row(M, v, p->prec, true, Sr, Np, h, sr, p->tw + c.tw_m, B, s);
     // (the inverse space runs first; the regular space's columns add to its result)
     case AA_REG:
       return funnel::launch_c2r(Np, v, p->prec, false, inv, Sr, dst, M, (Np - N) / 2, N, sr_to_img, 0.5f, tw_np, B,
@@ -227,7 +243,10 @@ hipError_t run_role(const ft_plan* p, const FtClass& c, int r, int v, const floa
     case AC_INV:
       return funnel::launch_r2c(Np, v, p->prec, false, src + c.off_inv_plane, Si, N, Np, 0, pl_to_si, 2.0f / Np, tw_np, B,
                                 s);
-    case AB_INV: return funnel::launch_row(N, v, p->prec, true, Si, Np, h, si, p->tw + c.tw_n, B, s);
+    case AB_INV:
+      if (p->chirpz)
+        return funnel::launch_chirp(N, v, true, Si, h, si, p->chirp + c.cz_n, p->chirp + c.wz_n, p->tw + c.tw_2n, B, s);
+      return funnel::launch_row(N, v, p->prec, true, Si, Np, h, si, p->tw + c.tw_n, B, s);
     case AA_INV:
       return funnel::launch_c2r(Np, v, p->prec, true, false, Si, dst, N, (Np - M) / 2, M, si_to_img, 0.5f, tw_np, B,
                                 s);
@@ -322,6 +341,12 @@ ft_status finish_plan(ft_plan* p, const std::vector<std::vector<std::pair<long l
     ntw += c.M;
     c.tw_n = ntw;
     ntw += c.N;
+    if (p->chirpz) {
+      c.tw_2m = ntw;
+      ntw += 2 * (size_t)c.M;
+      c.tw_2n = ntw;
+      ntw += 2 * (size_t)c.N;
+    }
     for (int r = 0; r < NROLES; ++r) {
       const unsigned m = role_mask(p, c, r);
       c.variant[r] = 0;
@@ -344,11 +369,43 @@ ft_status finish_plan(ft_plan* p, const std::vector<std::vector<std::pair<long l
     fill_twiddles(host.data() + c.tw_np, c.Np);
     fill_twiddles(host.data() + c.tw_m, c.M);
     fill_twiddles(host.data() + c.tw_n, c.N);
+    if (p->chirpz) {
+      fill_twiddles(host.data() + c.tw_2m, 2 * c.M);
+      fill_twiddles(host.data() + c.tw_2n, 2 * c.N);
+    }
   }
   hipError_t e = hipMalloc(&p->tw, ntw * sizeof(float2));
   if (e != hipSuccess) return fail(FT_ERR_OUT_OF_MEMORY, "hipMalloc of twiddle tables: %s", hipGetErrorString(e));
   e = hipMemcpy(p->tw, host.data(), ntw * sizeof(float2), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy of twiddle tables");
+
+  if (p->chirpz) {
+    // per space and frequency row: the chirp spectrum (2W) and the chirp (W)
+    size_t nch = 0;
+    for (auto& c : p->cls) {
+      if (p->spaces & FT_SPACE_REGULAR) {
+        c.cz_m = nch;
+        nch += (size_t)c.h * 2 * c.M;
+        c.wz_m = nch;
+        nch += (size_t)c.h * c.M;
+      }
+      if (p->spaces & FT_SPACE_INVERSE) {
+        c.cz_n = nch;
+        nch += (size_t)c.h * 2 * c.N;
+        c.wz_n = nch;
+        nch += (size_t)c.h * c.N;
+      }
+    }
+    std::vector<float2> ch(nch);
+    for (auto& c : p->cls) {
+      if (p->spaces & FT_SPACE_REGULAR) funnel::chirp_tables(c.M, c.Np, c.h, ch.data() + c.cz_m, ch.data() + c.wz_m);
+      if (p->spaces & FT_SPACE_INVERSE) funnel::chirp_tables(c.N, c.Np, c.h, ch.data() + c.cz_n, ch.data() + c.wz_n);
+    }
+    e = hipMalloc(&p->chirp, nch * sizeof(float2));
+    if (e != hipSuccess) return fail(FT_ERR_OUT_OF_MEMORY, "hipMalloc of chirp tables: %s", hipGetErrorString(e));
+    e = hipMemcpy(p->chirp, ch.data(), nch * sizeof(float2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy of chirp tables");
+  }
 
   if (!offsets.empty()) {
     // one allocation: image offsets, plane offsets (int64) of all classes, then image indices (int32)
@@ -420,7 +477,8 @@ ft_status funnel_plan_create(const ft_plan_desc* d, ft_plan** out) {
     return fail(FT_ERR_INVALID_ARG, "spaces must be 1, 2 or 3 (got %d)", d->spaces);
   if (d->precision < FT_PREC_FP32 || d->precision > FT_PREC_FP16X3)
     return fail(FT_ERR_INVALID_ARG, "unknown precision %d", d->precision);
-  if (d->flags != 0) return fail(FT_ERR_INVALID_ARG, "unknown plan flags 0x%x", d->flags);
+  if (d->flags & ~(uint32_t)FT_PLAN_NVMT_CHIRPZ) return fail(FT_ERR_INVALID_ARG, "unknown plan flags 0x%x", d->flags);
+  const bool chirpz = (d->flags & FT_PLAN_NVMT_CHIRPZ) != 0;
   const long long N = d->rows, M = d->cols;
   const long long Np = d->padded_len == 0 ? N + M : d->padded_len;
   if (d->padded_len < 0 || (Np & 1) || Np < N + M)
@@ -441,11 +499,21 @@ ft_status funnel_plan_create(const ft_plan_desc* d, ft_plan** out) {
                   what, len);
   }
 
+  if (chirpz) {
+    if (d->precision != FT_PREC_FP32)
+      return fail(FT_ERR_UNSUPPORTED_SIZE, "the chirp-z NVMT has FP32 kernels only (precision %d)", d->precision);
+    if ((d->spaces & FT_SPACE_REGULAR) && !funnel::chirp_variant_mask((int)M))
+      return fail(FT_ERR_UNSUPPORTED_SIZE, "no chirp-z kernel for row length (image width) %lld", M);
+    if ((d->spaces & FT_SPACE_INVERSE) && !funnel::chirp_variant_mask((int)N))
+      return fail(FT_ERR_UNSUPPORTED_SIZE, "no chirp-z kernel for row length (image height) %lld", N);
+  }
+
   ft_plan* p = new (std::nothrow) ft_plan();
   if (!p) return fail(FT_ERR_OUT_OF_MEMORY, "host allocation failed");
   p->spaces = d->spaces;
   p->batch = d->batch;
   p->prec = d->precision;
+  p->chirpz = chirpz;
   p->cls.resize(1);
   FtClass& c = p->cls[0];
   c.N = (int)N;

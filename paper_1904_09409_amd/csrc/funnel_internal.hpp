@@ -45,6 +45,17 @@ hipError_t launch_c2r(int L, int variant, int prec, bool trans, bool accum, cons
 hipError_t launch_row(int M, int variant, int prec, bool adj, float2* data, int Lp, int h, long long img_stride, const float2* tw,
                       int batch, hipStream_t s);
 
+// per frequency row: band-limited (chirp-z) NVMT fused with the DFT along x'
+// (forward) or its conjugate transpose (adjoint), in place, for row length W.
+// cz: [h][2W] chirp spectra (s / 2W) DFT_2W(c'), wz: [h][W] chirps
+// exp(-j pi s x^2 / W), tw: twiddles of length 2W.  Bit v of the mask set:
+// tile variant v has a kernel for W (0: no chirp-z kernel for this length).
+unsigned chirp_variant_mask(int W);
+hipError_t launch_chirp(int W, int variant, bool adj, float2* data, int h, long long img_stride, const float2* cz,
+                        const float2* wz, const float2* tw, int batch, hipStream_t s);
+// host: the FP64-derived tables above for rows n2 = 1..h of padded length Np
+void chirp_tables(int W, int Np, int h, float2* cz, float2* wz);
+
 size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K);
 int peaks_tiles(int rows, int cols);
 hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int batch, int nspaces, const int* rows,

@@ -33,6 +33,7 @@ FT_SPACE_BOTH = 3
 FT_PREC_FP32 = 0
 FT_PREC_BF16X3 = 1
 FT_PREC_FP16X3 = 2
+FT_PLAN_NVMT_CHIRPZ = 1
 FT_PEAK_CLAMP_BORDER = 1
 FT_PEAK_KEEP_PAD_BOUNDARY = 2
 FT_GRAPH_FORWARD = 1
@@ -289,11 +290,14 @@ class FunnelPlan:
     """A plan plus its workspace for a fixed batch shape on the current device."""
 
     def __init__(self, batch: int, rows: int, cols: int, padded_len: int = 0,
-                 spaces: int = FT_SPACE_BOTH, precision: int = FT_PREC_FP32):
+                 spaces: int = FT_SPACE_BOTH, precision: int = FT_PREC_FP32, nvmt: str = "linear"):
         import torch
+        if nvmt not in ("linear", "chirpz"):
+            raise ValueError(f"nvmt must be 'linear' or 'chirpz' (got {nvmt!r})")
         self.batch, self.N, self.M, self.spaces = batch, rows, cols, spaces
-        self.precision = precision
-        self.handle = funnel_plan_create(batch, rows, cols, padded_len, spaces, precision)
+        self.precision, self.nvmt = precision, nvmt
+        flags = FT_PLAN_NVMT_CHIRPZ if nvmt == "chirpz" else 0
+        self.handle = funnel_plan_create(batch, rows, cols, padded_len, spaces, precision, flags)
         self.Np = funnel_padded_len(self.handle)
         self.plane_elems = funnel_plane_elems(self.handle)
         self.device = torch.device("cuda", torch.cuda.current_device())

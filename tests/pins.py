@@ -560,3 +560,20 @@ def check_chirpz_adjoint_dot(O):
 
 def check_chirpz_adjoint_dense(O):
     check_adjoint_dense(O, 8, 8, "chirpz")
+
+
+def check_column_samplers(O):
+    """The column samplers used on large planes return exactly the columns of
+    the whole-plane oracle (both NVMT kinds, non-default padding)."""
+    rng = np.random.default_rng(53)
+    for kind in O.NVMT_KINDS:
+        for (N, M, pl) in [(12, 16, 0), (10, 8, 24)]:
+            img = rng.random((N, M))
+            Np = O.padded_length(N, M, pl)
+            cols = np.array([0, 3, M // 2, M - 1])
+            P = O.forward_regular(img, pl, kind)
+            assert np.abs(O.forward_regular_columns(img, cols, pl, kind) - P[:, cols]).max() <= 1e-12 * np.abs(P).max()
+            dP = rng.standard_normal((Np, M))
+            dI = O.adjoint_regular(dP, N, M, pl, kind)
+            got = O.adjoint_regular_columns(dP, N, M, cols, pl, kind)
+            assert np.abs(got - dI[:, cols]).max() <= 1e-12 * np.abs(dI).max()

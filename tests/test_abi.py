@@ -42,7 +42,8 @@ def _create(lib, **kw):
     (dict(spaces=0), F.FT_ERR_INVALID_ARG),
     (dict(spaces=4), F.FT_ERR_INVALID_ARG),
     (dict(precision=7), F.FT_ERR_INVALID_ARG),
-    (dict(flags=1), F.FT_ERR_INVALID_ARG),
+    (dict(flags=2), F.FT_ERR_INVALID_ARG),
+    (dict(flags=0x80000001), F.FT_ERR_INVALID_ARG),
     (dict(padded_len=100), F.FT_ERR_INVALID_ARG),      # < rows + cols
     (dict(padded_len=131), F.FT_ERR_INVALID_ARG),      # odd
     (dict(rows=62, cols=64), F.FT_ERR_UNSUPPORTED_SIZE),   # 126 = 2*3^2*7 has no kernel
@@ -53,6 +54,11 @@ def _create(lib, **kw):
     (dict(rows=64, cols=96, padded_len=256, precision=F.FT_PREC_FP16X3), F.FT_ERR_UNSUPPORTED_SIZE),
     (dict(rows=96, cols=64, padded_len=256, spaces=3, precision=F.FT_PREC_BF16X3), F.FT_ERR_UNSUPPORTED_SIZE),
     (dict(rows=16, cols=16, precision=F.FT_PREC_BF16X3), F.FT_ERR_UNSUPPORTED_SIZE),   # Np 32
+    # the chirp-z NVMT: FP32, power-of-two row lengths 64 .. 2048 of the spaces asked for
+    (dict(flags=F.FT_PLAN_NVMT_CHIRPZ, precision=F.FT_PREC_BF16X3), F.FT_ERR_UNSUPPORTED_SIZE),
+    (dict(flags=F.FT_PLAN_NVMT_CHIRPZ, rows=64, cols=96), F.FT_ERR_UNSUPPORTED_SIZE),
+    (dict(flags=F.FT_PLAN_NVMT_CHIRPZ, rows=96, cols=64, spaces=2), F.FT_ERR_UNSUPPORTED_SIZE),
+    (dict(flags=F.FT_PLAN_NVMT_CHIRPZ, rows=32, cols=32), F.FT_ERR_UNSUPPORTED_SIZE),
 ])
 def test_plan_create_rejects(lib, kw, code):
     st, h = _create(lib, **kw)
@@ -80,6 +86,10 @@ def test_valid_plan_without_device(lib):
     for prec in (F.FT_PREC_BF16X3, F.FT_PREC_FP16X3):
         st, h = _create(lib, batch=2, rows=1024, cols=1024, precision=prec)
         assert st == F.FT_ERR_NO_DEVICE
+    # chirp-z shapes that have kernels: only the device is missing
+    for kw in (dict(rows=1024, cols=1024), dict(rows=96, cols=64, spaces=1), dict(rows=64, cols=2048, padded_len=4096)):
+        st, h = _create(lib, batch=2, flags=F.FT_PLAN_NVMT_CHIRPZ, **kw)
+        assert st == F.FT_ERR_NO_DEVICE, (kw, F.last_error())
 
 
 def _ragged(lib, descs, spaces=3):

@@ -30,6 +30,7 @@ CHECKS = [
     pins.check_chirpz_line_to_point,
     pins.check_chirpz_adjoint_dot,
     pins.check_chirpz_adjoint_dense,
+    pins.check_column_samplers,
 ]
 
 
