@@ -32,11 +32,13 @@
 
 namespace funnel {
 
-// (elements per thread, target threads per block, images per block)
-#define FUNNEL_CHIRP_VARIANTS(X) X(0, 16, 256, 8) X(1, 16, 256, 4) X(2, 16, 256, 16) X(3, 32, 256, 8)
-constexpr int kChirpVariants = 4;
+// (elements per thread, target threads per block, images per block, PF: load
+// the next image's row while the current one is transformed)
+#define FUNNEL_CHIRP_VARIANTS(X)                                                                      \
+  X(0, 16, 256, 8, 0) X(1, 16, 256, 4, 0) X(2, 16, 256, 16, 0) X(3, 16, 128, 8, 0) X(4, 16, 256, 8, 1) \
+  X(5, 16, 128, 8, 1) X(6, 16, 256, 16, 1) X(7, 16, 128, 16, 1)
 
-template <int W, int E_, int TPB, int IPB>
+template <int W, int E_, int TPB, int IPB, int PF>
 struct ChirpCfg {
   static constexpr int L = 2 * W;
   static constexpr bool POW2 = (L & (L - 1)) == 0;
@@ -53,11 +55,11 @@ struct ChirpCfg {
                                 THREADS <= 1024 && THREADS >= 32 && LayRow<ROWS, L>::size(L) * 8 <= 64 * 1024;
 };
 
-template <int W, int E_, int TPB, int IPB, bool ADJ>
-__global__ void __launch_bounds__((ChirpCfg<W, E_, TPB, IPB>::THREADS))
+template <int W, int E_, int TPB, int IPB, int PF, bool ADJ>
+__global__ void __launch_bounds__((ChirpCfg<W, E_, TPB, IPB, PF>::THREADS))
     k_row_chirp(float2* __restrict__ data, int h, int batch, long long img_stride, const float2* __restrict__ cz,
                 const float2* __restrict__ wz, const float2* __restrict__ tw) {
-  using Cfg = ChirpCfg<W, E_, TPB, IPB>;
+  using Cfg = ChirpCfg<W, E_, TPB, IPB, PF>;
   constexpr int L = Cfg::L, P = Cfg::P, ROWS = Cfg::ROWS;
   using Fwd = typename Cfg::Fwd;
   using Inv = typename Cfg::Inv;
@@ -95,15 +97,37 @@ __global__ void __launch_bounds__((ChirpCfg<W, E_, TPB, IPB>::THREADS))
     for (int r = 0; r < H0; ++r)
       wr[b * H0 + r] = Fwd::template ok<0, false>(t, b) ? wzr[t + P * b + r * NB0] : make_float2(0.f, 0.f);
 
+  // the row samples of image `img` that this thread feeds to the first pass
+  constexpr int NIN = BPT0 * H0;
+  auto load_row = [&](int img, float2 (&xin)[NIN]) {
+    const bool act = img < batch;
+    const float2* rp = data + (long long)(act ? img : 0) * img_stride + (long long)(n2 - 1) * W;
+#pragma unroll
+    for (int b = 0; b < BPT0; ++b)
+#pragma unroll
+      for (int r = 0; r < H0; ++r)
+        xin[b * H0 + r] = act && Fwd::template ok<0, false>(t, b) ? rp[t + P * b + r * NB0] : make_float2(0.f, 0.f);
+  };
+  float2 nxt[NIN];
+  if constexpr (PF) load_row(grp * IPB + row, nxt);
+
 #pragma unroll 1
   for (int it = 0; it < IPB / ROWS; ++it) {
     // re-read the twiddles every image: hoisted out of the loop they would
-    // hold about a hundred more registers and halve the occupancy
+    // hold about a hundred more registers and lower the occupancy
     const float2* twi = tw;
     asm volatile("" : "+s"(twi));
     const int img = grp * IPB + it * ROWS + row;
     const bool active = img < batch;
     float2* rowp = data + (long long)(active ? img : 0) * img_stride + (long long)(n2 - 1) * W;
+    float2 cur[NIN];
+    if constexpr (PF) {
+#pragma unroll
+      for (int i = 0; i < NIN; ++i) cur[i] = nxt[i];
+      if (it + 1 < IPB / ROWS) load_row(img + ROWS, nxt);   // in flight during the transforms
+    } else {
+      load_row(img, cur);
+    }
     float2 v[E];
 #pragma unroll
     for (int s2 = 0; s2 < E; ++s2) v[s2] = make_float2(0.f, 0.f);
@@ -111,8 +135,7 @@ __global__ void __launch_bounds__((ChirpCfg<W, E_, TPB, IPB>::THREADS))
     for (int b = 0; b < BPT0; ++b)
 #pragma unroll
       for (int r = 0; r < H0; ++r) {
-        if (!active || !Fwd::template ok<0, false>(t, b)) continue;
-        float2 x = rowp[t + P * b + r * NB0];
+        float2 x = cur[b * H0 + r];
         if (ADJ) x.y = -x.y;
         v[b * R0 + r] = c_mul(x, wr[b * H0 + r]);
       }
@@ -136,8 +159,8 @@ __global__ void __launch_bounds__((ChirpCfg<W, E_, TPB, IPB>::THREADS))
 template <int W>
 unsigned chirp_variant_mask_t() {
   unsigned m = 0;
-#define FUNNEL_V(i, e, tpb, ipb) \
-  if constexpr (ChirpCfg<W, e, tpb, ipb>::valid) m |= 1u << i;
+#define FUNNEL_V(i, e, tpb, ipb, pf) \
+  if constexpr (ChirpCfg<W, e, tpb, ipb, pf>::valid) m |= 1u << i;
   FUNNEL_CHIRP_VARIANTS(FUNNEL_V)
 #undef FUNNEL_V
   return m;
@@ -147,17 +170,17 @@ template <int W>
 hipError_t launch_chirp_t(int variant, bool adj, float2* data, int h, long long img_stride, const float2* cz,
                           const float2* wz, const float2* tw, int batch, hipStream_t s) {
   switch (variant) {
-#define FUNNEL_V(i, e, tpb, ipb)                                                                            \
-  case i:                                                                                                   \
-    if constexpr (ChirpCfg<W, e, tpb, ipb>::valid) {                                                        \
-      using F = ChirpCfg<W, e, tpb, ipb>;                                                                   \
-      dim3 grid(h * ((batch + ipb - 1) / ipb)), block(F::THREADS);                                          \
-      if (adj)                                                                                              \
-        k_row_chirp<W, e, tpb, ipb, true><<<grid, block, 0, s>>>(data, h, batch, img_stride, cz, wz, tw);  \
-      else                                                                                                  \
-        k_row_chirp<W, e, tpb, ipb, false><<<grid, block, 0, s>>>(data, h, batch, img_stride, cz, wz, tw); \
-      return hipGetLastError();                                                                             \
-    }                                                                                                       \
+#define FUNNEL_V(i, e, tpb, ipb, pf)                                                                            \
+  case i:                                                                                                       \
+    if constexpr (ChirpCfg<W, e, tpb, ipb, pf>::valid) {                                                        \
+      using F = ChirpCfg<W, e, tpb, ipb, pf>;                                                                   \
+      dim3 grid(h * ((batch + ipb - 1) / ipb)), block(F::THREADS);                                              \
+      if (adj)                                                                                                  \
+        k_row_chirp<W, e, tpb, ipb, pf, true><<<grid, block, 0, s>>>(data, h, batch, img_stride, cz, wz, tw);  \
+      else                                                                                                      \
+        k_row_chirp<W, e, tpb, ipb, pf, false><<<grid, block, 0, s>>>(data, h, batch, img_stride, cz, wz, tw); \
+      return hipGetLastError();                                                                                  \
+    }                                                                                                            \
     break;
     FUNNEL_CHIRP_VARIANTS(FUNNEL_V)
 #undef FUNNEL_V
