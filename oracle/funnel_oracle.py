@@ -41,6 +41,7 @@ __all__ = [
     "adjoint_regular", "adjoint_inverse", "adjoint",
     "forward_regular_columns", "adjoint_regular_columns",
     "boundary_mask", "peaks_list", "peak_params",
+    "line_band_profile", "line_verdict",
 ]
 
 
@@ -406,3 +407,62 @@ def peak_params(row: int, col: int, N: int, M: int, Np: int, space: str = "regul
     kinv = -2.0 * (col - N // 2) / N
     xb = row - Np // 2
     return kinv, xb - kinv * N / 2 + M / 2
+
+
+# --------------------------------------------------------------------------
+# Line verification, Sec. 4.5
+# --------------------------------------------------------------------------
+
+def line_band_profile(img: np.ndarray, space: str, slope: float, intercept: float,
+                      half_width: int = 3):
+    """Sec. 4.5 steps 1-3: the band of 2D+1 pixels (D = half_width, a 3-7
+    pixel band) centred on a candidate line, integrated along the line.
+
+    Regular space: the line is ``row = slope * col + intercept``; for every
+    column c the line's row is y_c, and the band holds the samples at rows
+    y_c + d, d = -D..D, interpolated linearly between the two neighbouring
+    pixel rows.  Inverse space: ``col = slope * row + intercept`` with the
+    roles of rows and columns exchanged.  A line position enters the band
+    when both interpolation pixels of every offset are inside the image.
+
+    The line position y_c and its integer part decide which pixels are read;
+    they are taken in the precision the candidate line is given in (float32),
+    y_c rounded once from the exact value, so that the decision does not
+    depend on the arithmetic that evaluates it.  The samples are averaged in
+    float64.  Returns (profile[2D+1], length): the mean of each offset over
+    the line positions in the band, and their number."""
+    img = np.asarray(img, dtype=np.float64)
+    if space == "inverse":
+        img = img.T
+    rows, cols = img.shape
+    D = int(half_width)
+    k = np.float32(slope)
+    b = np.float32(intercept)
+    prof = np.zeros(2 * D + 1)
+    n = 0
+    for c in range(cols):
+        y = np.float32(np.float64(k) * c + np.float64(b))   # exact, then one rounding
+        r0 = int(np.floor(y))
+        t = float(y) - r0
+        if r0 - D < 0 or r0 + D + 1 > rows - 1:
+            continue
+        for i, d in enumerate(range(-D, D + 1)):
+            prof[i] += (1.0 - t) * img[r0 + d, c] + t * img[r0 + d + 1, c]
+        n += 1
+    if n:
+        prof /= n
+    return prof, n
+
+
+def line_verdict(profile: np.ndarray, length: int, min_contrast: float, min_length: int):
+    """Sec. 4.5 step 4, in this reading: a line exists when the band profile
+    stands out from its edges, either as a ridge (centre against the mean of
+    the two outermost offsets) or as a step (one outermost offset against
+    the other), by at least ``min_contrast``, over at least ``min_length``
+    line positions.  Returns (contrast, verified)."""
+    p = np.asarray(profile, dtype=np.float64)
+    D = (len(p) - 1) // 2
+    ridge = abs(p[D] - 0.5 * (p[0] + p[2 * D]))
+    step = abs(p[2 * D] - p[0])
+    contrast = max(ridge, step)
+    return contrast, bool(length >= min_length and contrast >= min_contrast)

@@ -577,3 +577,100 @@ def check_column_samplers(O):
             dI = O.adjoint_regular(dP, N, M, pl, kind)
             got = O.adjoint_regular_columns(dP, N, M, cols, pl, kind)
             assert np.abs(got - dI[:, cols]).max() <= 1e-12 * np.abs(dI).max()
+
+
+# ----------------------------------------------------------------- line verification (Sec. 4.5)
+
+def check_verify_constant_and_ramp(O):
+    """On a constant image every offset of the band averages to the constant;
+    on a linear ramp I = a r + b c + g linear interpolation is exact, so the
+    profile is a (mean y_c + d) + b mean(c) + g over the positions in the
+    band, which for a line inside the image is every column."""
+    N, M = 48, 64
+    for D in (1, 2, 3):
+        prof, n = O.line_band_profile(np.full((N, M), 0.37), "regular", 0.25, 10.3, D)
+        assert n == M and np.allclose(prof, 0.37, rtol=0, atol=1e-12)
+    a, b, g = 0.013, -0.004, 0.5
+    r, c = np.mgrid[0:N, 0:M]
+    img = a * r + b * c + g
+    k, icpt = 0.25, 10.3
+    cols = np.arange(M)
+    ys = (np.float64(np.float32(k)) * cols + np.float64(np.float32(icpt))).astype(np.float32).astype(np.float64)
+    for D in (1, 3):
+        prof, n = O.line_band_profile(img, "regular", k, icpt, D)
+        want = a * (ys.mean() + np.arange(-D, D + 1)) + b * cols.mean() + g
+        assert n == M and np.abs(prof - want).max() <= 1e-12
+    # inverse space: col = k row + icpt over the rows, same ramp read across columns
+    prof, n = O.line_band_profile(img, "inverse", -0.3, 40.2, 2)
+    rows = np.arange(N)
+    xs = (np.float64(np.float32(-0.3)) * rows + np.float64(np.float32(40.2))).astype(np.float32).astype(np.float64)
+    want = a * rows.mean() + b * (xs.mean() + np.arange(-2, 3)) + g
+    assert n == N and np.abs(prof - want).max() <= 1e-12
+
+
+def check_verify_band_limits(O):
+    """A line position y enters the band only when the rows it reads,
+    floor(y) - D .. floor(y) + D + 1, are all inside the image (the last one
+    even when its weight is zero): a horizontal line at row 1.5 has no
+    position with D = 3 and every column with D = 1 (rows 0..3)."""
+    img = np.ones((16, 20))
+    assert O.line_band_profile(img, "regular", 0.0, 1.5, 3)[1] == 0
+    assert O.line_band_profile(img, "regular", 0.0, 1.5, 1)[1] == 20
+    assert O.line_band_profile(img, "regular", 0.0, 12.5, 2)[1] == 20     # rows 10..15
+    assert O.line_band_profile(img, "regular", 0.0, 13.0, 2)[1] == 0      # rows 11..16
+    # a slope of 1 from row 3 with D = 3: columns 0 .. 8 (rows 0..7 up to 8..15)
+    assert O.line_band_profile(img, "regular", 1.0, 3.0, 3)[1] == 9
+    # the inverse space counts rows: col = 0.5 row + 2 with D = 2 on 20 columns
+    # needs floor(x) >= 2 and floor(x) <= 16: every row of 16
+    assert O.line_band_profile(img, "inverse", 0.5, 2.0, 2)[1] == 16
+
+
+def check_verify_ridge_and_step(O):
+    """Step 4 on exact patterns: a one-pixel ridge of height H on the line is a
+    profile B, .., B + H, .., B (ridge contrast H), half of it on each of two
+    offsets when the line lies half-way between pixel rows; a step edge half
+    a pixel from the line is a profile a, .., a, (a+b)/2 ... b (step contrast
+    |b - a|); a line elsewhere on a flat background is rejected."""
+    N, M, B, H = 40, 50, 0.2, 0.6
+    img = np.full((N, M), B)
+    img[17, :] += H
+    prof, n = O.line_band_profile(img, "regular", 0.0, 17.0, 3)
+    assert n == M and np.allclose(prof, [B, B, B, B + H, B, B, B], atol=1e-12)
+    c, ok = O.line_verdict(prof, n, 0.3, 20)
+    assert abs(c - H) < 1e-12 and ok
+    prof, n = O.line_band_profile(img, "regular", 0.0, 16.5, 3)
+    assert np.allclose(prof, [B, B, B, B + H / 2, B + H / 2, B, B], atol=1e-12)
+    step = np.where(np.arange(N)[:, None] < 20, 0.1, 0.7) * np.ones((1, M))
+    prof, n = O.line_band_profile(step, "regular", 0.0, 19.5, 3)
+    assert np.allclose(prof, [0.1, 0.1, 0.1, 0.4, 0.7, 0.7, 0.7], atol=1e-12)
+    c, ok = O.line_verdict(prof, n, 0.3, 20)
+    assert abs(c - 0.6) < 1e-12 and ok
+    prof, n = O.line_band_profile(img, "regular", 0.0, 30.0, 3)
+    c, ok = O.line_verdict(prof, n, 0.05, 20)
+    assert c < 1e-12 and not ok
+    # too short: the contrast is there but the band holds fewer positions than asked
+    assert not O.line_verdict(*O.line_band_profile(img, "regular", 0.0, 17.0, 3), 0.3, M + 1)[1]
+
+
+def check_verify_fig9_wrap(O):
+    """Sec. 4.5, Fig. 9: the wrapped regular-space peak names a line that is
+    not in the image (flat band, rejected), while the same line's inverse-space
+    peak names the real line (ridge, verified)."""
+    gold = read_golden("fig9_wrap_example.txt")
+    M, N = int(gold["width_M"]), int(gold["height_N"])
+    Np = N + M
+    kinv = 1.0 / gold["slope"]
+    bx = gold["inverse_peak_m"] - kinv * N / 2 + M / 2
+    ln = synth.Line("ridge", True, kinv, bx, width=1.0)
+    img = synth.render(N, M, [ln], 0.0, np.random.default_rng(0), bg=0.2)
+    P, Pinv = O.forward(img)
+    det = O.peaks_list(np.abs(P), 1, 0.0, 1, O.boundary_mask(N, M, Np))
+    k, b = O.peak_params(*divmod(det[0], M), N, M, Np, "regular")
+    prof, n = O.line_band_profile(img, "regular", k, b, 3)
+    c_wrap, ok_wrap = O.line_verdict(prof, n, 0.2, 32)
+    Bi = np.where(O.boundary_mask(M, N, Np), 0.0, np.abs(Pinv))
+    ki, bi = O.peak_params(*np.unravel_index(np.argmax(Bi), Bi.shape), N, M, Np, "inverse")
+    prof_i, n_i = O.line_band_profile(img, "inverse", ki, bi, 3)
+    c_true, ok_true = O.line_verdict(prof_i, n_i, 0.2, 32)
+    assert not ok_wrap and ok_true, (c_wrap, c_true)
+    assert c_true > 0.3 and c_wrap < 0.05

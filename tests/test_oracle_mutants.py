@@ -116,6 +116,43 @@ def _chirpz_transpose_no_conj(dG, Np):
     return _chirpz_rows(dG, Np)
 
 
+def _band(img, space, slope, intercept, half_width=3, nearest=False, along=False, top_pad=1):
+    # the band integral with one planted change
+    img = np.asarray(img, dtype=np.float64)
+    if space == "inverse":
+        img = img.T
+    if along:
+        img = img.T
+    rows, cols = img.shape
+    D = int(half_width)
+    prof, n = np.zeros(2 * D + 1), 0
+    for c in range(cols):
+        y = np.float32(np.float64(np.float32(slope)) * c + np.float64(np.float32(intercept)))
+        r0 = int(np.floor(y))
+        t = float(y) - r0
+        if nearest:
+            r0, t = int(np.floor(y + 0.5)), 0.0
+        if r0 - D < 0 or r0 + D + top_pad > rows - 1:
+            continue
+        for i, d in enumerate(range(-D, D + 1)):
+            nxt = img[r0 + d + 1, c] if r0 + d + 1 < rows else 0.0
+            prof[i] += (1.0 - t) * img[r0 + d, c] + t * nxt
+        n += 1
+    return (prof / n if n else prof), n
+
+
+def _band_nearest(img, space, slope, intercept, half_width=3):
+    return _band(img, space, slope, intercept, half_width, nearest=True)
+
+
+def _band_along(img, space, slope, intercept, half_width=3):
+    return _band(img, space, slope, intercept, half_width, along=True)
+
+
+def _band_limit_off_by_one(img, space, slope, intercept, half_width=3):
+    return _band(img, space, slope, intercept, half_width, top_pad=0)
+
+
 _REAL = {name: getattr(O, name) for name in
          ("nvmt", "spectrum_y", "dft_x", "idft_y", "expand", "adjoint_regular", "peaks_list",
           "nvmt_dft_chirpz", "_nvmt_dft_chirpz_transpose")}
@@ -131,6 +168,8 @@ ALL_CHECKS = [
     pins.check_chirpz_slant_stack, pins.check_chirpz_special_rows,
     pins.check_chirpz_point_to_line, pins.check_chirpz_line_to_point,
     pins.check_chirpz_adjoint_dot, pins.check_chirpz_adjoint_dense,
+    pins.check_verify_constant_and_ramp, pins.check_verify_band_limits,
+    pins.check_verify_ridge_and_step, pins.check_verify_fig9_wrap,
 ]
 
 MUTANTS = {
@@ -147,6 +186,9 @@ MUTANTS = {
     "chirp-z ratio read as n2 / Np": ("nvmt_dft_chirpz", _chirpz_ratio_halved),
     "chirp-z phase reduced modulo 2 M": ("nvmt_dft_chirpz", _chirpz_phase_period_M),
     "chirp-z adjoint without conjugate": ("_nvmt_dft_chirpz_transpose", _chirpz_transpose_no_conj),
+    "band sampled at the nearest pixel": ("line_band_profile", _band_nearest),
+    "band offsets along the line's axis": ("line_band_profile", _band_along),
+    "band limit one row short": ("line_band_profile", _band_limit_off_by_one),
 }
 
 

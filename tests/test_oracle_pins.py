@@ -31,6 +31,10 @@ CHECKS = [
     pins.check_chirpz_adjoint_dot,
     pins.check_chirpz_adjoint_dense,
     pins.check_column_samplers,
+    pins.check_verify_constant_and_ramp,
+    pins.check_verify_band_limits,
+    pins.check_verify_ridge_and_step,
+    pins.check_verify_fig9_wrap,
 ]
 
 
