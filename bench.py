@@ -56,7 +56,7 @@ def main():
     ap.add_argument("--variants", type=str, default="",
                     help="comma-separated tile variant per launch (role order of funnel_plan_variants); "
                          "skips the autotuner, so counter runs time the variants a timed run picked")
-    ap.add_argument("--workload", choices=["grad", "chirpz", "ragged", "precision"], default="grad",
+    ap.add_argument("--workload", choices=["grad", "chirpz", "ragged", "precision", "verify"], default="grad",
                     help="grad: the 32 x 1024^2 batch (default); ragged: 256 images of mixed sizes; "
                          "precision: 8 x 2048^2 in FP32 and with the split-precision matrix-core passes")
     args = ap.parse_args()
@@ -74,6 +74,8 @@ def main():
         return ragged_bench(args, torch, F, synth)
     if args.workload == "precision":
         return precision_bench(args, torch, F, synth)
+    if args.workload == "verify":
+        return verify_bench(args, torch, F, synth)
     B, N, M = args.batch, args.size, args.size
     log(f"generating {B} synthetic {N}x{M} images")
     t0 = time.time()
@@ -324,6 +326,63 @@ def precision_bench(args, torch, F, synth, B=8, size=2048):
     print(json.dumps(out), flush=True)
 
 
+def verify_bench(args, torch, F, synth, K=16, D=3):
+    """Peak extraction (K per plane) and Sec. 4.5 line verification (a 7-pixel
+    band) of the 32 x 1024^2 benchmark batch, timed separately with HIP events
+    on the launch stream after one forward pass."""
+    B, N = args.batch, args.size
+    imgs = synth.batch("grad", count=B, size=N, seed=0)
+    x = torch.from_numpy(synth.stack(imgs)).cuda()
+    plan = F.FunnelPlan(B, N, N)
+    planes = plan.forward(x)
+    rec, cnt = plan.peaks(planes, K=K)
+    out = plan.verify(x, rec, cnt, D, 0.08, 64)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(args.steps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) / args.steps
+
+    ms_peaks = timed(lambda: plan.peaks(planes, K=K))
+    ms_verify = timed(lambda: plan.verify(x, rec, cnt, D, 0.08, 64, ))
+    chk = F.checks_to_numpy(out)
+    n_lines = int(cnt.sum().item())
+    # algorithmic bytes of one verification launch: every band position reads
+    # 2D+2 pixels; each peak record is read and each check record written once
+    vbytes = float(chk["length"].sum()) * (2 * D + 2) * 4 + B * plan.nspaces * K * (28 + 40)
+    gbps = vbytes / (ms_verify * 1e6)
+    res = {
+        "metric": "lines verified per second (Sec. 4.5, 7-pixel band) on the 32 x 1024^2 batch",
+        "value": round(n_lines / (ms_verify * 1e-3), 1), "unit": "lines/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_verify, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{B} x {N}x{N}, both spaces, K={K} peaks per plane, band half-width {D}",
+                   "lines": n_lines, "verified": int(chk["verified"].sum()), "peaks_ms": round(ms_peaks, 4)},
+        "roofline": {"bound": "hbm", "kernel": "k_verify", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 5), "traffic": None,
+                     "bytes_per_launch": vbytes},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def kernel_sources(nvmt: str = "linear"):
+    """The sources that define the kernels of the forward + adjoint passes
+    (their hash ties a committed counter table to the code it measured)."""
+    csrc = os.path.join(ROOT, "paper_1904_09409_amd", "csrc")
+    names = ["fft_core.hpp", "fft_mfma.hpp", "funnel_lengths.hpp", "funnel_passes.hpp"]
+    if nvmt == "chirpz":
+        names.append("funnel_chirp.hip")
+    return [os.path.join(csrc, n) for n in names]
+
+
 def measured_traffic(launch: str, variant: int, nvmt: str = "linear"):
     """HBM bytes of one launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE table, if the kernel sources are unchanged since it was taken."""
@@ -334,9 +393,8 @@ def measured_traffic(launch: str, variant: int, nvmt: str = "linear"):
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
-    csrc = os.path.join(ROOT, "paper_1904_09409_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + glob.glob(os.path.join(csrc, "*.hip"))):
+    for f in kernel_sources(nvmt):
         h.update(open(f, "rb").read())
     if h.hexdigest() != t.get("source_hash") or launch not in t.get("launches", {}):
         return None

@@ -233,6 +233,39 @@ ft_status funnel_peaks(const ft_plan* plan, const float* planes, int32_t K, floa
                        int32_t radius, uint32_t flags, ft_peak* peaks, int32_t* n_found,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* One checked candidate line (Sec. 4.5). */
+typedef struct {
+  float profile[7];   /* mean image value on the line shifted by d = -D..D across it
+                         (entries 2D+1 .. 6 are 0) */
+  float contrast;     /* max(|profile[D] - (profile[0] + profile[2D]) / 2|,
+                             |profile[2D] - profile[0]|): ridge or step edge */
+  int32_t length;     /* line positions read (columns, regular; rows, inverse) */
+  int32_t verified;   /* 1: length >= min_length and contrast >= min_contrast */
+} ft_line_check;
+
+/* Line verification of Sec. 4.5, steps 1-4, for every peak of a list written
+ * by funnel_peaks: a band of 2*half_width+1 pixels centred on the peak's
+ * candidate line (its slope and intercept; the record's space says whether
+ * the line is row = slope*col + intercept or col = slope*row + intercept) is
+ * integrated along the line and the band profile decides.  At each position
+ * along the line (every column, regular; every row, inverse) the line crosses
+ * at y = slope*pos + intercept, evaluated with one rounding; the samples
+ * y + d, d = -D..D, are linear interpolations between the two pixels across
+ * the line, and the position counts when all pixels floor(y)-D .. floor(y)+D+1
+ * are inside the image.  A wrapping peak (Fig. 9) names a line that is not
+ * in the image, so its flat band rejects it; the same line's peak in the
+ * other space verifies.
+ *   images     : device, the images the planes were computed from
+ *   peaks, n_found : device, as written by funnel_peaks with the same K
+ *   half_width : D in 1 .. 3 (a 3 .. 7 pixel band)
+ *   min_contrast, min_length : the decision (min_contrast not NaN, min_length >= 0)
+ *   out        : device, ft_line_check [batch][n_spaces][K]; slots beyond a
+ *                plane's count are zero (verified = 0)
+ * Enqueued on `stream`; no allocation, no synchronisation. */
+ft_status funnel_verify(const ft_plan* plan, const float* images, const ft_peak* peaks, const int32_t* n_found,
+                        int32_t K, int32_t half_width, float min_contrast, int32_t min_length, ft_line_check* out,
+                        void* stream);
+
 /* ---- kernel timing (for measurement tools) ----
  * When enabled on a plan, every funnel_forward / funnel_adjoint call records a
  * HIP event pair around each kernel it launches, on the call's stream, and

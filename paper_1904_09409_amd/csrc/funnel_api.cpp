@@ -945,7 +945,8 @@ ft_status funnel_peaks(const ft_plan* p, const float* planes, int32_t K, float t
     }
     const funnel::ImgMap map{0, c.plane_stride, nullptr, c.d_plane_off};
     if (e == hipSuccess)
-      e = funnel::launch_peaks(planes, map, c.d_gidx, c.count, ns, rows, cols, himg, off, K, threshold, radius,
+      e = funnel::launch_peaks(planes, map, c.d_gidx, c.count, ns, (p->spaces & FT_SPACE_REGULAR) ? 0 : 1, rows, cols,
+                               himg, off, K, threshold, radius,
                                (flags & FT_PEAK_CLAMP_BORDER) ? 0 : 1, (flags & FT_PEAK_KEEP_PAD_BOUNDARY) ? 1 : 0,
                                peaks, n_found, w, cs);
     w += align_up(funnel::peaks_workspace_bytes(c.count * ns, tiles, K), 256);
@@ -953,6 +954,33 @@ ft_status funnel_peaks(const ft_plan* p, const float* planes, int32_t K, float t
   }
   for (size_t ci = 0; fork && ci < p->cls.size() && e == hipSuccess; ++ci)
     e = hipStreamWaitEvent(s, p->cls[ci].done, 0);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return ok();
+}
+
+ft_status funnel_verify(const ft_plan* p, const float* images, const ft_peak* peaks, const int32_t* n_found,
+                        int32_t K, int32_t half_width, float min_contrast, int32_t min_length, ft_line_check* out,
+                        void* stream) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  if (!images || !peaks || !n_found || !out) return fail(FT_ERR_INVALID_ARG, "pointers must be non-NULL");
+  if (K < 1 || K > 256) return fail(FT_ERR_INVALID_ARG, "K must be in 1..256 (got %d)", K);
+  if (half_width < 1 || half_width > 3) return fail(FT_ERR_INVALID_ARG, "half_width must be in 1..3 (got %d)", half_width);
+  if (std::isnan(min_contrast)) return fail(FT_ERR_INVALID_ARG, "min_contrast is NaN");
+  if (min_length < 0) return fail(FT_ERR_INVALID_ARG, "min_length must be >= 0 (got %d)", min_length);
+  if (!aligned16(images) || !aligned16(peaks) || !aligned16(n_found) || !aligned16(out))
+    return fail(FT_ERR_MISALIGNED, "device pointers must be 16-byte aligned");
+  ft_status st = check_device(p);
+  if (st != FT_OK) return st;
+  (void)hipGetLastError();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ns = (p->spaces == FT_SPACE_BOTH) ? 2 : 1;
+  hipError_t e = hipSuccess;
+  for (size_t ci = 0; ci < p->cls.size() && e == hipSuccess; ++ci) {
+    const FtClass& c = p->cls[ci];
+    const funnel::ImgMap map{c.img_stride, 0, c.d_img_off, nullptr};
+    e = funnel::launch_verify(images, map, c.d_gidx, c.count, ns, c.N, c.M, peaks, n_found, K, half_width,
+                              min_contrast, min_length, out, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return ok();
 }

@@ -58,8 +58,16 @@ void chirp_tables(int W, int Np, int h, float2* cz, float2* wz);
 
 size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K);
 int peaks_tiles(int rows, int cols);
-hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int batch, int nspaces, const int* rows,
-                        const int* cols, const int* himg, const long long* offset, int K, float thr, int radius,
-                        int wrap, int keep_border, ft_peak* peaks, int32_t* n_found, void* ws, hipStream_t s);
+hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int batch, int nspaces, int space0,
+                        const int* rows, const int* cols, const int* himg, const long long* offset, int K, float thr,
+                        int radius, int wrap, int keep_border, ft_peak* peaks, int32_t* n_found, void* ws,
+                        hipStream_t s);
+
+// Sec. 4.5 line verification of the peak lists written by launch_peaks, for
+// the images of one size class (N x M, offsets by map.in, caller indices by
+// gidx): one record per peak slot, [image][space][K]
+hipError_t launch_verify(const float* images, ImgMap map, const int* gidx, int count, int ns, int N, int M,
+                         const ft_peak* peaks, const int32_t* n_found, int K, int D, float min_contrast,
+                         int min_length, ft_line_check* out, hipStream_t s);
 
 }  // namespace funnel

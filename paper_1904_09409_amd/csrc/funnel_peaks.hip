@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(kPeakThreads)
 
 __global__ void __launch_bounds__(kMergeThreads)
     k_peaks_merge(const float* __restrict__ planes, ImgMap map, const int* __restrict__ gidx, PlaneGeom g0,
-                  PlaneGeom g1, int nspaces, int tiles, int K, const uint64_t* __restrict__ cand,
+                  PlaneGeom g1, int nspaces, int space0, int tiles, int K, const uint64_t* __restrict__ cand,
                   ft_peak* __restrict__ peaks, int32_t* __restrict__ n_found) {
   __shared__ uint64_t keys[kMergeLen];
   const int plane = blockIdx.x;
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(kMergeThreads)
     const int r = c / g.cols, col = c % g.cols;
     ft_peak pk;
     pk.image = gimg;
-    pk.space = sp;
+    pk.space = space0 + sp;   // 0 regular, 1 inverse, whichever spaces the plan has
     pk.row = r;
     pk.col = col;
     pk.value = fabsf(P[c]);
@@ -159,9 +159,10 @@ size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K) {
 
 int peaks_tiles(int rows, int cols) { return (int)(((long long)rows * cols + kPeakTile - 1) / kPeakTile); }
 
-hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int batch, int nspaces, const int* rows,
-                        const int* cols, const int* himg, const long long* offset, int K, float thr, int radius,
-                        int wrap, int keep_border, ft_peak* peaks, int32_t* n_found, void* ws, hipStream_t s) {
+hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int batch, int nspaces, int space0,
+                        const int* rows, const int* cols, const int* himg, const long long* offset, int K, float thr,
+                        int radius, int wrap, int keep_border, ft_peak* peaks, int32_t* n_found, void* ws,
+                        hipStream_t s) {
   PlaneGeom g[2];
   int tiles = 0;
   for (int i = 0; i < nspaces; ++i) {
@@ -176,8 +177,8 @@ hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int ba
                                               keep_border, cand);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_peaks_merge<<<batch * nspaces, kMergeThreads, 0, s>>>(planes, map, gidx, g[0], g[1], nspaces, tiles, K, cand,
-                                                          peaks, n_found);
+  k_peaks_merge<<<batch * nspaces, kMergeThreads, 0, s>>>(planes, map, gidx, g[0], g[1], nspaces, space0, tiles, K,
+                                                          cand, peaks, n_found);
   return hipGetLastError();
 }
 

@@ -64,6 +64,9 @@ class ft_tune_result(ctypes.Structure):
 PEAK_DTYPE = np.dtype([("image", np.int32), ("space", np.int32), ("row", np.int32), ("col", np.int32),
                        ("value", np.float32), ("slope", np.float32), ("intercept", np.float32)])
 PEAK_WORDS = PEAK_DTYPE.itemsize // 4   # 7 x 4 bytes
+LINE_CHECK_DTYPE = np.dtype([("profile", np.float32, (7,)), ("contrast", np.float32), ("length", np.int32),
+                             ("verified", np.int32)])
+LINE_CHECK_WORDS = LINE_CHECK_DTYPE.itemsize // 4   # 10 x 4 bytes
 
 
 class FunnelError(RuntimeError):
@@ -100,6 +103,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "funnel_adjoint": ([vp, vp, vp, vp, sz, vp], ctypes.c_int),
         "funnel_peaks_workspace_size": ([vp, i32, ctypes.POINTER(sz)], ctypes.c_int),
         "funnel_peaks": ([vp, vp, i32, ctypes.c_float, i32, u32, vp, vp, vp, sz, vp], ctypes.c_int),
+        "funnel_verify": ([vp, vp, vp, vp, i32, i32, ctypes.c_float, i32, vp, vp], ctypes.c_int),
         "funnel_profile_enable": ([vp, i32], ctypes.c_int),
         "funnel_profile_read": ([vp, ctypes.POINTER(ft_kernel_time), i32, ctypes.POINTER(i32)], ctypes.c_int),
         "funnel_profile_disable": ([vp], ctypes.c_int),
@@ -242,6 +246,13 @@ def funnel_peaks(plan: int, planes, K: int, threshold: float, radius: int, flags
                                        _stream(stream)), "funnel_peaks")
 
 
+def funnel_verify(plan: int, images, peaks, n_found, K: int, half_width: int, min_contrast: float,
+                  min_length: int, out, stream=None) -> None:
+    _check(load_library().funnel_verify(plan, _ptr(images), _ptr(peaks), _ptr(n_found), int(K), int(half_width),
+                                        float(min_contrast), int(min_length), _ptr(out), _stream(stream)),
+           "funnel_verify")
+
+
 def funnel_profile_enable(plan: int, max_records: int) -> None:
     _check(load_library().funnel_profile_enable(plan, int(max_records)), "funnel_profile_enable")
 
@@ -368,6 +379,17 @@ class FunnelPlan:
         funnel_peaks(self.handle, planes, K, threshold, radius, flags, rec, cnt, ws, stream)
         return rec, cnt
 
+    def verify(self, images, rec, cnt, half_width: int = 3, min_contrast: float = 0.1, min_length: int = 32,
+               stream=None):
+        """Sec. 4.5 line verification of peak lists from peaks(): returns the
+        ft_line_check records as int32 [B, nspaces, K, 10] on the device
+        (checks_to_numpy() reads them)."""
+        import torch
+        out = torch.empty((rec.shape[0], rec.shape[1], rec.shape[2], LINE_CHECK_WORDS), dtype=torch.int32,
+                          device=self.device)
+        funnel_verify(self.handle, images, rec, cnt, rec.shape[2], half_width, min_contrast, min_length, out, stream)
+        return out
+
 
 class RaggedPlan:
     """A plan for a batch of images of different sizes, packed back to back
@@ -455,6 +477,17 @@ class RaggedPlan:
         funnel_peaks(self.handle, planes, K, threshold, radius, flags, rec, cnt, ws, stream)
         return rec, cnt
 
+    def verify(self, images, rec, cnt, half_width: int = 3, min_contrast: float = 0.1, min_length: int = 32,
+               stream=None):
+        """Sec. 4.5 line verification of peak lists from peaks(): returns the
+        ft_line_check records as int32 [B, nspaces, K, 10] on the device
+        (checks_to_numpy() reads them)."""
+        import torch
+        out = torch.empty((rec.shape[0], rec.shape[1], rec.shape[2], LINE_CHECK_WORDS), dtype=torch.int32,
+                          device=self.device)
+        funnel_verify(self.handle, images, rec, cnt, rec.shape[2], half_width, min_contrast, min_length, out, stream)
+        return out
+
 
 class FunnelGraph:
     """An executable graph of a plan's forward and/or adjoint on fixed buffers."""
@@ -474,6 +507,12 @@ class FunnelGraph:
             except Exception:
                 pass
             self.handle = None
+
+
+def checks_to_numpy(out):
+    """Device ft_line_check records [B, nspaces, K, 10] -> numpy structured array [B, nspaces, K]."""
+    a = np.ascontiguousarray(out.cpu().numpy())
+    return a.view(LINE_CHECK_DTYPE).reshape(a.shape[:3])
 
 
 def peaks_to_numpy(rec, cnt) -> list:

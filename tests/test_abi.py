@@ -72,6 +72,7 @@ def test_null_arguments(lib):
     assert lib.funnel_forward(None, None, None, None, 0, None) == F.FT_ERR_INVALID_ARG
     assert lib.funnel_adjoint(None, None, None, None, 0, None) == F.FT_ERR_INVALID_ARG
     assert lib.funnel_peaks(None, None, 4, 0.0, 1, 0, None, None, None, 0, None) == F.FT_ERR_INVALID_ARG
+    assert lib.funnel_verify(None, None, None, None, 4, 3, 0.1, 10, None, None) == F.FT_ERR_INVALID_ARG
     n = ctypes.c_size_t()
     assert lib.funnel_workspace_size(None, ctypes.byref(n)) == F.FT_ERR_INVALID_ARG
     lib.funnel_plan_destroy(None)
