@@ -10,11 +10,17 @@
 // result unique.  Each cell carries the 64-bit key (~bits(|P|) << 32 | index):
 // smaller key = earlier in the order.
 //
-// Stage 1: one block per tile of 1024 cells flags its local maxima (above the
-//          threshold, outside the expansion-border cells), sorts the keys of
-//          the tile in LDS (bitonic) and keeps its first K.
-// Stage 2: one block per plane merges the tile lists chunk by chunk, keeping
-//          a running first-K, and writes the records.  No atomics anywhere, so
+// Stage 1: one block per tile of 16 x 256 cells stages the tile and a halo of
+//          `radius` cells in LDS (coalesced row loads; the halo wraps, or holds
+//          a value that precedes nothing when the border is clamped), flags
+//          its local maxima (above the threshold, outside the expansion-border
+//          cells), one tile column per thread, and each wave extracts its
+//          first K keys by K rounds of a wave-wide minimum (no block-wide
+//          sort); a tile contributes one list per wave.
+// Stage 2: a tree of reductions: each block sorts G lists of K keys (G K <=
+//          2048) and keeps the first K, until one list per plane remains
+//          (log_G(tiles) launches, every level spread over the whole GPU).
+// Stage 3: one block per plane writes the records.  No atomics anywhere, so
 //          results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -23,10 +29,12 @@
 
 namespace funnel {
 
-constexpr int kPeakTile = 1024;     // cells per stage-1 block
-constexpr int kPeakThreads = 256;
-constexpr int kMergeLen = 2048;     // keys sorted per stage-2 step
-constexpr int kMergeThreads = 512;
+constexpr int kTileR = 16, kTileC = 256;  // stage-1 tile: rows x columns of a plane
+constexpr int kPeakThreads = 256;           // one tile column per thread
+constexpr int kMaxRadius = 8;
+constexpr int kHaloC = kTileC + 2 * kMaxRadius;
+constexpr int kMergeLen = 2048;     // keys sorted per stage-2 block
+constexpr int kMergeThreads = 256;
 constexpr uint64_t kNoKey = ~0ull;
 
 struct PlaneGeom {
@@ -66,77 +74,251 @@ __device__ __forceinline__ void bitonic_sort(uint64_t* a) {
 
 // Per-image plane blocks start at map.out(img); gidx maps the launch's image
 // index to the caller's (ragged batches), NULL meaning the identity.
+// RADIUS is the neighbourhood radius (1..8), a template parameter so that the
+// (2 RADIUS + 1)^2 - 1 comparisons of a cell unroll and their LDS reads are
+// all in flight at once.
+// Minimum over the 64 lanes of a wave, returned to every lane: within each
+// row of 16 lanes by DPP lane permutations (quad swaps, then the half-row and
+// row mirrors), then across the four rows by reading one lane of each.  All
+// lanes of the wave must be active.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));    // quad_perm 1,0,3,2
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));    // quad_perm 2,3,0,1
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));   // row_half_mirror
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));   // row_mirror
+  const uint32_t a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+  const uint32_t c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+  return min(min(a, b), min(c, d));
+}
+
+// 64-bit keys: the high words first; the low word comes from the one lane
+// holding the smallest high word, or (ties) from a second reduction over
+// the lanes that hold it
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+  const uint32_t xh = (uint32_t)(x >> 32), xl = (uint32_t)x;
+  const uint32_t hi = wave_min_u32(xh);
+  const uint64_t holders = __ballot(xh == hi);
+  uint32_t lo;
+  if (__popcll(holders) == 1) lo = __builtin_amdgcn_readlane(xl, __ffsll((unsigned long long)holders) - 1);
+  else lo = wave_min_u32(xh == hi ? xl : 0xffffffffu);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// RADIUS is the neighbourhood radius (1..8), a template parameter so that the
+// (2 RADIUS + 1)^2 - 1 comparisons of a cell unroll and their LDS reads are
+// all in flight at once.  Output: per tile, one list of K keys per wave (the
+// wave's first K local maxima, unordered past the count), [plane][tile][wave][K].
+template <int RADIUS>
 __global__ void __launch_bounds__(kPeakThreads)
     k_peaks_tile(const float* __restrict__ planes, ImgMap map, PlaneGeom g0, PlaneGeom g1, int nspaces, int tiles,
-                 int K, float thr, int radius, int wrap, int keep_border, uint64_t* __restrict__ out) {
-  __shared__ uint64_t keys[kPeakTile];
+                 int K, float thr, int wrap, int keep_border, uint64_t* __restrict__ out) {
+  constexpr int radius = RADIUS;
+  constexpr int NW = kPeakThreads / 64;
+  __shared__ float val[(kTileR + 2 * RADIUS) * kHaloC];   // |P| of tile and halo; -1: no cell (clamped border)
   const int plane = blockIdx.y;                 // image * nspaces + space
   const int img = plane / nspaces, sp = plane % nspaces;
   const PlaneGeom g = sp == 0 ? g0 : g1;
   const float* P = planes + map.out(img) + g.offset;
-  const int ncell = g.rows * g.cols;
+  const int tcn = (g.cols + kTileC - 1) / kTileC;
+  const int ntile = tcn * ((g.rows + kTileR - 1) / kTileR);
   const int tile = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint64_t* dst = out + (((long long)plane * tiles + tile) * NW + wave) * K;
+  if (tile >= ntile) {   // the other space's plane has more tiles
+    for (int i = lane; i < K; i += 64) dst[i] = kNoKey;
+    return;
+  }
+  const int r0 = (tile / tcn) * kTileR, c0 = (tile % tcn) * kTileC;
+  const int hr = kTileR + 2 * radius;
 
-  for (int e = threadIdx.x; e < kPeakTile; e += kPeakThreads) {
-    const int c = tile * kPeakTile + e;
-    uint64_t key = kNoKey;
-    if (tile < tiles && c < ncell) {
-      const float v = P[c];
-      const uint64_t me = cell_key(v, c);
-      const int r = c / g.cols, col = c % g.cols;
-      bool peak = fabsf(v) >= thr && (keep_border || !in_border(g, r, col));
-      for (int dr = -radius; peak && dr <= radius; ++dr) {
-        int rr = r + dr;
-        if (wrap) rr = (rr % g.rows + g.rows) % g.rows;
-        else if (rr < 0 || rr >= g.rows) continue;
-        for (int dc = -radius; dc <= radius; ++dc) {
-          int cc = col + dc;
-          if (wrap) cc = (cc % g.cols + g.cols) % g.cols;
-          else if (cc < 0 || cc >= g.cols) continue;
-          const int q = rr * g.cols + cc;
-          if (q == c) continue;
-          if (cell_key(P[q], q) < me) { peak = false; break; }
-        }
-      }
-      if (peak) key = me;
+  // stage the tile and its halo (rows r0-R .. r0+15+R, columns c0-R ..
+  // c0+255+R); every load of a thread is issued before the first store
+  auto src_row = [&](int lr, bool& in) {   // plane row of halo row lr (wrapped), or !in
+    int rr = r0 - radius + lr;
+    in = true;
+    if (rr < 0 || rr >= g.rows) {
+      if (wrap) rr = ((rr % g.rows) + g.rows) % g.rows;
+      else in = false;
     }
-    keys[e] = key;
+    return rr;
+  };
+  const bool vec = c0 + kTileC <= g.cols && (g.cols & 3) == 0 && ((uintptr_t)P & 15) == 0;
+  if (vec) {
+    // interior columns as 16-byte loads, the 2R side columns one by one
+    constexpr int NV = ((kTileR + 2 * radius) * (kTileC / 4) + kPeakThreads - 1) / kPeakThreads;
+    constexpr int NS = ((kTileR + 2 * radius) * 2 * radius + kPeakThreads - 1) / kPeakThreads;
+    float4 lv[NV];
+    bool lin[NV];
+    float ls[NS];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const int i = tid + kPeakThreads * j;
+      const int lr = i / (kTileC / 4), q = i % (kTileC / 4);
+      bool in;
+      const int rr = src_row(lr, in);
+      in = in && lr < hr;
+      lin[j] = in;
+      lv[j] = in ? *reinterpret_cast<const float4*>(P + (long long)rr * g.cols + c0 + 4 * q)
+                 : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int i = tid + kPeakThreads * j;
+      const int lr = i / (2 * radius), e = i % (2 * radius);
+      int cc = e < radius ? c0 - radius + e : c0 + kTileC + (e - radius);
+      bool in;
+      const int rr = src_row(lr, in);
+      in = in && lr < hr;
+      if (cc < 0 || cc >= g.cols) {
+        if (wrap) cc = ((cc % g.cols) + g.cols) % g.cols;
+        else in = false;
+      }
+      ls[j] = in ? fabsf(P[(long long)rr * g.cols + cc]) : -1.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const int i = tid + kPeakThreads * j;
+      const int lr = i / (kTileC / 4), q = i % (kTileC / 4);
+      if (lr >= hr) continue;
+      float* d = val + lr * kHaloC + radius + 4 * q;
+      const float4 x = lv[j];
+      d[0] = lin[j] ? fabsf(x.x) : -1.f;   // -1: a row beyond the clamped border
+      d[1] = lin[j] ? fabsf(x.y) : -1.f;
+      d[2] = lin[j] ? fabsf(x.z) : -1.f;
+      d[3] = lin[j] ? fabsf(x.w) : -1.f;
+    }
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int i = tid + kPeakThreads * j;
+      const int lr = i / (2 * radius), e = i % (2 * radius);
+      if (lr >= hr) continue;
+      val[lr * kHaloC + (e < radius ? e : kTileC + e)] = ls[j];
+    }
+  } else {
+    // hr rows of kHaloC columns (a few more than needed), one by one
+    constexpr int NLD = ((kTileR + 2 * radius) * kHaloC + kPeakThreads - 1) / kPeakThreads;
+    const int nhalo = hr * kHaloC;
+    float ld[NLD];
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) {
+      const int i = tid + kPeakThreads * j;
+      const int lr = i / kHaloC, lc = i % kHaloC;
+      int cc = c0 - radius + lc;
+      bool in;
+      const int rr = src_row(lr, in);
+      in = in && i < nhalo;
+      if (cc < 0 || cc >= g.cols) {
+        if (wrap) cc = ((cc % g.cols) + g.cols) % g.cols;
+        else in = false;
+      }
+      ld[j] = in ? fabsf(P[(long long)rr * g.cols + cc]) : -1.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) {
+      const int i = tid + kPeakThreads * j;
+      if (i < nhalo) val[i] = ld[j];
+    }
   }
   __syncthreads();
-  bitonic_sort<kPeakTile, kPeakThreads>(keys);
-  uint64_t* dst = out + ((long long)plane * tiles + tile) * K;
-  for (int i = threadIdx.x; i < K; i += kPeakThreads) dst[i] = i < kPeakTile ? keys[i] : kNoKey;
+
+  // local maxima under the order (|P| descending, linear index ascending),
+  // down this thread's column of the tile
+  constexpr int CPT = kTileR;   // cells per thread
+  constexpr int NS = CPT / 2;   // two cells of a column that touch are never both maxima:
+  uint64_t mine[NS];            // slot j holds the key of row 2j or 2j+1 if it is one, else kNoKey
+#pragma unroll
+  for (int j = 0; j < NS; ++j) mine[j] = kNoKey;
+  const int lc = tid, c = c0 + lc;
+#pragma unroll
+  for (int lr = 0; lr < CPT; ++lr) {
+    const int r = r0 + lr;
+    if (r >= g.rows || c >= g.cols) continue;
+    const float v = val[(lr + radius) * kHaloC + lc + radius];
+    if (!(v >= thr) || (!keep_border && in_border(g, r, c))) continue;
+    // a neighbour with a larger |P| rules the cell out; one with an equal |P|
+    // (rare) needs the index tie-break
+    bool gt = false, eq = false;
+#pragma unroll (RADIUS <= 3 ? 2 * RADIUS + 1 : 1)
+    for (int dr = -radius; dr <= radius; ++dr)
+#pragma unroll
+      for (int dc = -radius; dc <= radius; ++dc)
+        if (dr != 0 || dc != 0) {
+          const float q = val[(lr + radius + dr) * kHaloC + lc + radius + dc];   // -1: clamped border
+          gt |= q > v;
+          eq |= q == v;
+        }
+    if (gt) continue;
+    const int idx = r * g.cols + c;
+    if (eq) {
+      bool peak = true;
+      for (int dr = -radius; peak && dr <= radius; ++dr)
+        for (int dc = -radius; dc <= radius; ++dc) {
+          if (dr == 0 && dc == 0) continue;
+          if (val[(lr + radius + dr) * kHaloC + lc + radius + dc] != v) continue;
+          int rr = r + dr, cc = c + dc;
+          rr += rr < 0 ? g.rows : (rr >= g.rows ? -g.rows : 0);
+          cc += cc < 0 ? g.cols : (cc >= g.cols ? -g.cols : 0);
+          if (rr * g.cols + cc < idx) { peak = false; break; }   // (equal: the cell itself, wrapped)
+        }
+      if (!peak) continue;
+    }
+    mine[lr / 2] = cell_key(v, idx);
+  }
+
+  // the wave's first K keys: each lane sorts its slots once, then K rounds
+  // of a wave-wide minimum over the lanes' first slots; the lane holding the
+  // winner (keys are unique: exactly one) shifts its slots down.
+#pragma unroll
+  for (int a = 0; a < NS - 1; ++a)
+#pragma unroll
+    for (int b = 0; b < NS - 1 - a; ++b) {
+      const uint64_t x = mine[b], y = mine[b + 1];
+      mine[b] = x < y ? x : y;
+      mine[b + 1] = x < y ? y : x;
+    }
+  int k = 0;
+  for (; k < K; ++k) {
+    const uint64_t m = wave_min_u64(mine[0]);
+    if (m == kNoKey) break;   // uniform: the wave has no keys left
+    if (lane == 0) dst[k] = m;
+    if (mine[0] == m) {
+#pragma unroll
+      for (int j = 0; j < NS - 1; ++j) mine[j] = mine[j + 1];
+      mine[NS - 1] = kNoKey;
+    }
+  }
+  for (int i = k + lane; i < K; i += 64) dst[i] = kNoKey;
 }
 
+// Lists [plane][nin][K] -> [plane][nout][K], nout = ceil(nin / G): block
+// (j, plane) sorts lists j G .. j G + G - 1 and keeps the first K keys.
 __global__ void __launch_bounds__(kMergeThreads)
-    k_peaks_merge(const float* __restrict__ planes, ImgMap map, const int* __restrict__ gidx, PlaneGeom g0,
-                  PlaneGeom g1, int nspaces, int space0, int tiles, int K, const uint64_t* __restrict__ cand,
-                  ft_peak* __restrict__ peaks, int32_t* __restrict__ n_found) {
+    k_peaks_reduce(const uint64_t* __restrict__ in, int nin, uint64_t* __restrict__ out, int nout, int K, int G) {
   __shared__ uint64_t keys[kMergeLen];
+  const int plane = blockIdx.y, j = blockIdx.x;
+  const uint64_t* src = in + ((long long)plane * nin + (long long)j * G) * K;
+  const int avail = (nin - j * G < G ? nin - j * G : G) * K;
+  for (int i = threadIdx.x; i < kMergeLen; i += kMergeThreads) keys[i] = i < avail ? src[i] : kNoKey;
+  __syncthreads();
+  bitonic_sort<kMergeLen, kMergeThreads>(keys);
+  uint64_t* dst = out + ((long long)plane * nout + j) * K;
+  for (int i = threadIdx.x; i < K; i += kMergeThreads) dst[i] = keys[i];
+}
+
+// One sorted list of K keys per plane -> records and counts.
+__global__ void __launch_bounds__(kMergeThreads)
+    k_peaks_records(const float* __restrict__ planes, ImgMap map, const int* __restrict__ gidx, PlaneGeom g0,
+                    PlaneGeom g1, int nspaces, int space0, int K, const uint64_t* __restrict__ list,
+                    ft_peak* __restrict__ peaks, int32_t* __restrict__ n_found) {
   const int plane = blockIdx.x;
   const int img = plane / nspaces, sp = plane % nspaces;
   const int gimg = gidx ? gidx[img] : img;
   const PlaneGeom g = sp == 0 ? g0 : g1;
   const float* P = planes + map.out(img) + g.offset;
-  const uint64_t* src = cand + (long long)plane * tiles * K;
-  const long long total = (long long)tiles * K;
-
-  for (int i = threadIdx.x; i < kMergeLen; i += kMergeThreads) keys[i] = kNoKey;
-  __syncthreads();
-  const int chunk = kMergeLen - K;
-  for (long long base = 0; base < total; base += chunk) {
-    for (int i = threadIdx.x; i < chunk; i += kMergeThreads) {
-      const long long j = base + i;
-      keys[K + i] = j < total ? src[j] : kNoKey;
-    }
-    __syncthreads();
-    bitonic_sort<kMergeLen, kMergeThreads>(keys);
-  }
-  // records
-  int count = 0;
-  for (int i = 0; i < K; ++i) count += keys[i] != kNoKey;
+  const uint64_t* keys = list + (long long)plane * K;
   ft_peak* dst = peaks + ((long long)gimg * nspaces + sp) * K;
-  for (int i = threadIdx.x; i < count; i += kMergeThreads) {
+  for (int i = threadIdx.x; i < K; i += kMergeThreads) {
+    if (keys[i] == kNoKey) continue;
     const int c = (int)(uint32_t)(keys[i] & 0xffffffffu);
     const int r = c / g.cols, col = c % g.cols;
     ft_peak pk;
@@ -150,14 +332,25 @@ __global__ void __launch_bounds__(kMergeThreads)
     pk.intercept = (float)(r - g.rows / 2) - slope * (float)(g.cols / 2) + (float)(g.himg / 2);
     dst[i] = pk;
   }
-  if (threadIdx.x == 0) n_found[(long long)gimg * nspaces + sp] = count;
+  if (threadIdx.x == 0) {
+    int count = 0;   // sorted: the valid keys come first
+    while (count < K && keys[count] != kNoKey) ++count;
+    n_found[(long long)gimg * nspaces + sp] = count;
+  }
 }
 
+// lists merged per stage-2 block
+static int merge_group(int K) { return kMergeLen / K > 1 ? kMergeLen / K : 2; }
+
+// stage-1 lists, then the first reduction level's lists (later levels reuse
+// the first buffer, which is large enough for them)
 size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K) {
-  return (size_t)nplanes_total * (size_t)tiles * (size_t)K * sizeof(uint64_t);
+  const size_t lists = (size_t)tiles * (kPeakThreads / 64);
+  const size_t lvl1 = (lists + merge_group(K) - 1) / merge_group(K);
+  return (size_t)nplanes_total * (lists + lvl1) * (size_t)K * sizeof(uint64_t);
 }
 
-int peaks_tiles(int rows, int cols) { return (int)(((long long)rows * cols + kPeakTile - 1) / kPeakTile); }
+int peaks_tiles(int rows, int cols) { return ((rows + kTileR - 1) / kTileR) * ((cols + kTileC - 1) / kTileC); }
 
 hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int batch, int nspaces, int space0,
                         const int* rows, const int* cols, const int* himg, const long long* offset, int K, float thr,
@@ -173,12 +366,35 @@ hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int ba
   if (nspaces == 1) g[1] = g[0];
   uint64_t* cand = static_cast<uint64_t*>(ws);
   dim3 grid1(tiles, batch * nspaces);
-  k_peaks_tile<<<grid1, kPeakThreads, 0, s>>>(planes, map, g[0], g[1], nspaces, tiles, K, thr, radius, wrap,
-                                              keep_border, cand);
+  switch (radius) {
+#define CASE(R)                                                                                              \
+  case R:                                                                                                    \
+    k_peaks_tile<R><<<grid1, kPeakThreads, 0, s>>>(planes, map, g[0], g[1], nspaces, tiles, K, thr, wrap, keep_border, \
+                                                   cand);                                                    \
+    break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_peaks_merge<<<batch * nspaces, kMergeThreads, 0, s>>>(planes, map, gidx, g[0], g[1], nspaces, space0, tiles, K,
-                                                          cand, peaks, n_found);
+  // reduce the tile lists to one list per plane, ping-ponging between the
+  // stage-1 buffer and the level-1 buffer behind it
+  const int G = merge_group(K);
+  const int planes_n = batch * nspaces;
+  const int lists = tiles * (kPeakThreads / 64);   // one list per wave of every tile
+  uint64_t* bufs[2] = {cand, cand + (size_t)planes_n * lists * K};
+  int cur = 0, n = lists;
+  do {
+    const int nout = (n + G - 1) / G;
+    k_peaks_reduce<<<dim3(nout, planes_n), kMergeThreads, 0, s>>>(bufs[cur], n, bufs[1 - cur], nout, K, G);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    cur = 1 - cur;
+    n = nout;
+  } while (n > 1);
+  k_peaks_records<<<planes_n, kMergeThreads, 0, s>>>(planes, map, gidx, g[0], g[1], nspaces, space0, K, bufs[cur],
+                                                     peaks, n_found);
   return hipGetLastError();
 }
 
