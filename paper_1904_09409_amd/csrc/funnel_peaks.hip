@@ -56,11 +56,12 @@ __device__ __forceinline__ bool in_border(const PlaneGeom& g, int r, int c) {
   return (y >= e0 - 2 && y <= e0 + 1) || (y >= e1 - 2 && y <= e1 + 1);
 }
 
-template <int N, int THREADS>
-__device__ __forceinline__ void bitonic_sort(uint64_t* a) {
-  for (int size = 2; size <= N; size <<= 1) {
+// Bitonic sort of the first n keys of a (n a power of two, <= the array).
+template <int THREADS>
+__device__ __forceinline__ void bitonic_sort_n(uint64_t* a, int n) {
+  for (int size = 2; size <= n; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < N / 2; i += THREADS) {
+      for (int i = threadIdx.x; i < n / 2; i += THREADS) {
         const int lo = 2 * i - (i & (stride - 1));
         const int hi = lo + stride;
         const bool up = (lo & size) == 0;
@@ -298,9 +299,11 @@ __global__ void __launch_bounds__(kMergeThreads)
   const int plane = blockIdx.y, j = blockIdx.x;
   const uint64_t* src = in + ((long long)plane * nin + (long long)j * G) * K;
   const int avail = (nin - j * G < G ? nin - j * G : G) * K;
-  for (int i = threadIdx.x; i < kMergeLen; i += kMergeThreads) keys[i] = i < avail ? src[i] : kNoKey;
+  int n = 1;   // sort the keys present, padded to a power of two (>= K)
+  while (n < avail || n < K) n <<= 1;
+  for (int i = threadIdx.x; i < n; i += kMergeThreads) keys[i] = i < avail ? src[i] : kNoKey;
   __syncthreads();
-  bitonic_sort<kMergeLen, kMergeThreads>(keys);
+  bitonic_sort_n<kMergeThreads>(keys, n);
   uint64_t* dst = out + ((long long)plane * nout + j) * K;
   for (int i = threadIdx.x; i < K; i += kMergeThreads) dst[i] = keys[i];
 }
