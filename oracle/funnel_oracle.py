@@ -42,6 +42,7 @@ __all__ = [
     "forward_regular_columns", "adjoint_regular_columns",
     "boundary_mask", "peaks_list", "peak_params",
     "line_band_profile", "line_verdict",
+    "resampled_rows", "continuous_plane", "refine_peak",
 ]
 
 
@@ -466,3 +467,77 @@ def line_verdict(profile: np.ndarray, length: int, min_contrast: float, min_leng
     step = abs(p[2 * D] - p[0])
     contrast = max(ridge, step)
     return contrast, bool(length >= min_length and contrast >= min_contrast)
+
+
+# --------------------------------------------------------------------------
+# Sub-cell refinement of a peak (Eqs. 19, 22-25 at non-integer cells)
+# --------------------------------------------------------------------------
+
+def resampled_rows(img: np.ndarray, padded_len: int = 0, nvmt_kind: str = "linear") -> np.ndarray:
+    """The NVMT output rows g[n2, x'] (Sec. 3.1, second step) of the regular
+    space: for the linear NVMT the interpolated rows themselves; for the
+    chirp-z NVMT the rows whose DFT is the fused G (g = IDFT_M of G, centred
+    x' and m1)."""
+    img = np.asarray(img, dtype=np.float64)
+    N, M = img.shape
+    Np = padded_length(N, M, padded_len)
+    S = spectrum_y(expand(img, Np))
+    if nvmt_kind == "linear":
+        return nvmt(S, Np)
+    G = nvmt_dft_chirpz(S, Np)
+    return G @ np.conj(_xdft_matrix(M)).T / M
+
+
+def continuous_plane(g: np.ndarray, Np: int, m: float, y: float):
+    """The parameter plane between cells: the last two steps of Sec. 3.1 with
+    the x' DFT evaluated at a real slope bin m (the DTFT of each resampled
+    row) and the inverse y DFT at a real intercept y (its trigonometric sum),
+        P(m, y) = (2/Np) Re sum_n2 A(n2; m) exp(+j 2 pi n2 y / Np),
+        A(n2; m) = sum_x' g[n2, x'] exp(-j 2 pi m x' / M),
+    which equals the plane at integer (m, y).  Returns P and its first and
+    second derivatives: (P, P_m, P_y, P_mm, P_my, P_yy)."""
+    h, M = g.shape
+    xp = np.arange(M) - M // 2
+    n2 = np.arange(1, h + 1)
+    e = np.exp(-2j * np.pi * m * xp / M)
+    cm = -2j * np.pi * xp / M                 # d/dm of the exponent
+    A0 = g @ e
+    A1 = g @ (cm * e)
+    A2 = g @ (cm * cm * e)
+    w = np.exp(2j * np.pi * n2 * y / Np)
+    cy = 2j * np.pi * n2 / Np                 # d/dy of the exponent
+    f = 2.0 / Np
+    P = f * np.real(np.sum(A0 * w))
+    Pm = f * np.real(np.sum(A1 * w))
+    Py = f * np.real(np.sum(A0 * cy * w))
+    Pmm = f * np.real(np.sum(A2 * w))
+    Pmy = f * np.real(np.sum(A1 * cy * w))
+    Pyy = f * np.real(np.sum(A0 * cy * cy * w))
+    return P, Pm, Py, Pmm, Pmy, Pyy
+
+
+def refine_peak(g: np.ndarray, Np: int, row: int, col: int, iters: int = 4):
+    """Gradient refinement of one peak to a local maximum of |P| between
+    cells (the line parameters Eq. 19 focuses to are continuous; Eqs. 22-25
+    read them from the maximum).  From the cell's centre, `iters` safeguarded
+    Newton steps on F = sign(P) P: the Newton step when the Hessian of F is
+    negative definite, otherwise a gradient step of 0.25 cell, each component
+    clamped to 0.5 cell, the total displacement to 1 cell.  Returns the slope
+    bin m, the intercept y (centred, real) and |P| there."""
+    h, M = g.shape
+    m0, y0 = float(col - M // 2), float(row - Np // 2)
+    P0 = continuous_plane(g, Np, m0, y0)[0]
+    sg = 1.0 if P0 >= 0 else -1.0
+    m, y = m0, y0
+    for _ in range(iters):
+        P, Pm, Py, Pmm, Pmy, Pyy = (sg * v for v in continuous_plane(g, Np, m, y))
+        det = Pmm * Pyy - Pmy * Pmy
+        if Pmm < 0 and det > 0:
+            dm = -(Pyy * Pm - Pmy * Py) / det
+            dy = -(Pmm * Py - Pmy * Pm) / det
+        else:
+            nrm = np.hypot(Pm, Py)
+            dm, dy = (0.25 * Pm / nrm, 0.25 * Py / nrm) if nrm > 0 else (0.0, 0.0)
+        m = min(max(m + min(max(dm, -0.5), 0.5), m0 - 1.0), m0 + 1.0)
+        y = min(max(y + min(max(dy, -0.5), 0.5), y0 - 1.0), y0 + 1.0)
+    return m, y, abs(continuous_plane(g, Np, m, y)[0])

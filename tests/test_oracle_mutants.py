@@ -153,6 +153,43 @@ def _band_limit_off_by_one(img, space, slope, intercept, half_width=3):
     return _band(img, space, slope, intercept, half_width, top_pad=0)
 
 
+def _cont_plane(g, Np, m, y, msign=-1.0, ysign=1.0):
+    # the plane between cells with one planted change
+    h, M = g.shape
+    xp = np.arange(M) - M // 2
+    n2 = np.arange(1, h + 1)
+    e = np.exp(msign * 2j * np.pi * m * xp / M)
+    cm = msign * 2j * np.pi * xp / M
+    A0, A1, A2 = g @ e, g @ (cm * e), g @ (cm * cm * e)
+    w = np.exp(2j * np.pi * n2 * y / Np)
+    cy = ysign * 2j * np.pi * n2 / Np
+    f = 2.0 / Np
+    r = lambda a: f * np.real(np.sum(a))
+    return r(A0 * w), r(A1 * w), r(A0 * cy * w), r(A2 * w), r(A1 * cy * w), r(A0 * cy * cy * w)
+
+
+def _cont_plane_m_conj(g, Np, m, y):
+    return _cont_plane(g, Np, m, y, msign=+1.0)
+
+
+def _cont_plane_dy_sign(g, Np, m, y):
+    return _cont_plane(g, Np, m, y, ysign=-1.0)
+
+
+def _refine_descends(g, Np, row, col, iters=4):
+    # steps downhill (a sign slip in the update)
+    h, M = g.shape
+    m0, y0 = float(col - M // 2), float(row - Np // 2)
+    m, y = m0, y0
+    sg = 1.0 if O.continuous_plane(g, Np, m, y)[0] >= 0 else -1.0
+    for _ in range(iters):
+        P, Pm, Py = (sg * v for v in O.continuous_plane(g, Np, m, y)[:3])
+        nrm = np.hypot(Pm, Py) or 1.0
+        m = min(max(m - 0.25 * Pm / nrm, m0 - 1.0), m0 + 1.0)
+        y = min(max(y - 0.25 * Py / nrm, y0 - 1.0), y0 + 1.0)
+    return m, y, abs(O.continuous_plane(g, Np, m, y)[0])
+
+
 _REAL = {name: getattr(O, name) for name in
          ("nvmt", "spectrum_y", "dft_x", "idft_y", "expand", "adjoint_regular", "peaks_list",
           "nvmt_dft_chirpz", "_nvmt_dft_chirpz_transpose")}
@@ -170,6 +207,8 @@ ALL_CHECKS = [
     pins.check_chirpz_adjoint_dot, pins.check_chirpz_adjoint_dense,
     pins.check_verify_constant_and_ramp, pins.check_verify_band_limits,
     pins.check_verify_ridge_and_step, pins.check_verify_fig9_wrap,
+    pins.check_continuous_plane_cells, pins.check_continuous_plane_derivatives,
+    pins.check_refine_line_to_point, pins.check_refine_stationary,
 ]
 
 MUTANTS = {
@@ -189,6 +228,9 @@ MUTANTS = {
     "band sampled at the nearest pixel": ("line_band_profile", _band_nearest),
     "band offsets along the line's axis": ("line_band_profile", _band_along),
     "band limit one row short": ("line_band_profile", _band_limit_off_by_one),
+    "plane between cells with the slope exponent conjugated": ("continuous_plane", _cont_plane_m_conj),
+    "plane between cells with the intercept derivative's sign flipped": ("continuous_plane", _cont_plane_dy_sign),
+    "refinement stepping downhill": ("refine_peak", _refine_descends),
 }
 
 

@@ -35,6 +35,10 @@ CHECKS = [
     pins.check_verify_band_limits,
     pins.check_verify_ridge_and_step,
     pins.check_verify_fig9_wrap,
+    pins.check_continuous_plane_cells,
+    pins.check_continuous_plane_derivatives,
+    pins.check_refine_line_to_point,
+    pins.check_refine_stationary,
 ]
 
 
