@@ -327,9 +327,10 @@ def precision_bench(args, torch, F, synth, B=8, size=2048):
 
 
 def verify_bench(args, torch, F, synth, K=16, D=3):
-    """Peak extraction (K per plane) and Sec. 4.5 line verification (a 7-pixel
-    band) of the 32 x 1024^2 benchmark batch, timed separately with HIP events
-    on the launch stream after one forward pass."""
+    """Peak extraction (K per plane), Sec. 4.5 line verification (a 7-pixel
+    band) and sub-cell refinement (4 Newton steps, including its recomputation
+    of the forward spectra) of the 32 x 1024^2 benchmark batch, timed
+    separately with HIP events on the launch stream after one forward pass."""
     B, N = args.batch, args.size
     imgs = synth.batch("grad", count=B, size=N, seed=0)
     x = torch.from_numpy(synth.stack(imgs)).cuda()
@@ -352,6 +353,7 @@ def verify_bench(args, torch, F, synth, K=16, D=3):
 
     ms_peaks = timed(lambda: plan.peaks(planes, K=K))
     ms_verify = timed(lambda: plan.verify(x, rec, cnt, D, 0.08, 64, ))
+    ms_refine = timed(lambda: plan.refine(x, rec, cnt, 4))
     chk = F.checks_to_numpy(out)
     n_lines = int(cnt.sum().item())
     # algorithmic bytes of one verification launch: every band position reads
@@ -364,7 +366,8 @@ def verify_bench(args, torch, F, synth, K=16, D=3):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_verify, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{B} x {N}x{N}, both spaces, K={K} peaks per plane, band half-width {D}",
-                   "lines": n_lines, "verified": int(chk["verified"].sum()), "peaks_ms": round(ms_peaks, 4)},
+                   "lines": n_lines, "verified": int(chk["verified"].sum()), "peaks_ms": round(ms_peaks, 4),
+                   "refine_ms": round(ms_refine, 4), "refine_iters": 4},
         "roofline": {"bound": "hbm", "kernel": "k_verify", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 5), "traffic": None,
                      "bytes_per_launch": vbytes},

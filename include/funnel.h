@@ -266,6 +266,40 @@ ft_status funnel_verify(const ft_plan* plan, const float* images, const ft_peak*
                         int32_t K, int32_t half_width, float min_contrast, int32_t min_length, ft_line_check* out,
                         void* stream);
 
+/* One refined peak. */
+typedef struct {
+  float col, row;     /* real-valued plane column and row of the local maximum */
+  float value;        /* |P| there */
+  float slope;        /* Eqs. 22-25 at the refined cell, in the form of the  */
+  float intercept;    /* peak's ft_peak record (regular or inverse space)    */
+  float shift;        /* distance from the detected cell, in cells (<= 1.42) */
+} ft_refined;
+
+/* Workspace of funnel_refine for lists of K peaks per plane (>= the
+ * transform's workspace). */
+ft_status funnel_refine_workspace_size(const ft_plan* plan, int32_t K, size_t* bytes);
+
+/* Sub-cell refinement of the peaks of a funnel_peaks list.  Between cells
+ * the plane is the last two steps of Sec. 3.1 with the x' DFT evaluated at a
+ * real slope bin m (the DTFT of each NVMT-resampled row) and the inverse y
+ * DFT at a real intercept y; it equals the plane at every cell.  From each
+ * detected cell, `iters` safeguarded Newton steps climb |P| (the Newton step
+ * when the Hessian is negative definite, else a gradient step of 1/4 cell;
+ * steps clamped to 1/2 cell per axis and 1 cell in total), and Eqs. 22-25
+ * read the line at the maximum: Eq. 19 focuses a line at real-valued
+ * (m, y), so the refined parameters are closer to the line than the cell's.
+ * Recomputes the forward spectra of `images` in the workspace (passes A and
+ * B of funnel_forward), so it needs no planes.
+ *   images        : device, the images the peaks were detected in
+ *   peaks, n_found: device, as written by funnel_peaks with the same K
+ *   iters         : 0 .. 16 (0: the records describe the cells themselves)
+ *   out           : device, ft_refined [batch][n_spaces][K]; slots past a
+ *                   plane's count are zero
+ * Uniform plans only, row lengths (M, and N for the inverse space) powers of
+ * two in 64 .. 4096, else FT_ERR_UNSUPPORTED_SIZE. */
+ft_status funnel_refine(const ft_plan* plan, const float* images, const ft_peak* peaks, const int32_t* n_found,
+                        int32_t K, int32_t iters, ft_refined* out, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- kernel timing (for measurement tools) ----
  * When enabled on a plan, every funnel_forward / funnel_adjoint call records a
  * HIP event pair around each kernel it launches, on the call's stream, and

@@ -985,4 +985,79 @@ ft_status funnel_verify(const ft_plan* p, const float* images, const ft_peak* pe
   return ok();
 }
 
+namespace {
+// refinement workspace: the transform's spectra, the row sums A (3 complex
+// per row, peak and space), the iteration state
+struct RefineLayout {
+  size_t a_off, st_off, total;
+};
+RefineLayout refine_layout(const ft_plan* p, int K) {
+  const FtClass& c = p->cls[0];
+  const int ns = (p->spaces == FT_SPACE_BOTH) ? 2 : 1;
+  RefineLayout L;
+  L.a_off = align_up(p->ws_bytes, 256);
+  L.st_off = align_up(L.a_off + (size_t)c.count * ns * K * 3 * (size_t)c.h * sizeof(float2), 256);
+  L.total = align_up(L.st_off + (size_t)c.count * ns * K * funnel::refine_state_bytes(), 256);
+  return L;
+}
+}  // namespace
+
+ft_status funnel_refine_workspace_size(const ft_plan* p, int32_t K, size_t* bytes) {
+  if (!p || !bytes) return fail(FT_ERR_INVALID_ARG, "plan and bytes must be non-NULL");
+  if (K < 1 || K > 256) return fail(FT_ERR_INVALID_ARG, "K must be in 1..256 (got %d)", K);
+  if (p->cls.size() != 1 || p->ragged) return fail(FT_ERR_INVALID_ARG, "refinement needs a uniform plan");
+  *bytes = refine_layout(p, K).total;
+  return ok();
+}
+
+ft_status funnel_refine(const ft_plan* p, const float* images, const ft_peak* peaks, const int32_t* n_found,
+                        int32_t K, int32_t iters, ft_refined* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  if (!images || !peaks || !n_found || !out || !ws) return fail(FT_ERR_INVALID_ARG, "pointers must be non-NULL");
+  if (K < 1 || K > 256) return fail(FT_ERR_INVALID_ARG, "K must be in 1..256 (got %d)", K);
+  if (iters < 0 || iters > 16) return fail(FT_ERR_INVALID_ARG, "iters must be in 0..16 (got %d)", iters);
+  if (p->cls.size() != 1 || p->ragged) return fail(FT_ERR_INVALID_ARG, "refinement needs a uniform plan");
+  const FtClass& c = p->cls[0];
+  if (((p->spaces & FT_SPACE_REGULAR) && !funnel::refine_length_supported(c.M)) ||
+      ((p->spaces & FT_SPACE_INVERSE) && !funnel::refine_length_supported(c.N)))
+    return fail(FT_ERR_UNSUPPORTED_SIZE, "refinement needs power-of-two row lengths in 64..4096 (%d x %d)", c.N, c.M);
+  if (!aligned16(images) || !aligned16(peaks) || !aligned16(n_found) || !aligned16(out) || !aligned16(ws))
+    return fail(FT_ERR_MISALIGNED, "device pointers must be 16-byte aligned");
+  const RefineLayout L = refine_layout(p, K);
+  if (ws_bytes < L.total) return fail(FT_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+  ft_status st = check_device(p);
+  if (st != FT_OK) return st;
+  (void)hipGetLastError();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  const int ns = (p->spaces == FT_SPACE_BOTH) ? 2 : 1;
+  const int B = c.count, h = c.h;
+  float2* Abuf = reinterpret_cast<float2*>(w + L.a_off);
+  void* state = w + L.st_off;
+  hipError_t e = hipSuccess;
+  // the resampled rows g of each space: passes A and B of the forward, then
+  // the inverse x' DFT
+  struct Sp { int role_a, role_b, W, space_id; size_t off; size_t tw; };
+  Sp sp[2];
+  int k = 0;
+  if (p->spaces & FT_SPACE_REGULAR) sp[k++] = {FA_REG, FB_REG, c.M, 0, c.ws_reg, c.tw_m};
+  if (p->spaces & FT_SPACE_INVERSE) sp[k++] = {FA_INV, FB_INV, c.N, 1, c.ws_inv, c.tw_n};
+  for (int i = 0; i < ns && e == hipSuccess; ++i) {
+    e = run_role(p, c, sp[i].role_a, c.variant[sp[i].role_a], images, nullptr, w, s);
+    if (e == hipSuccess) e = run_role(p, c, sp[i].role_b, c.variant[sp[i].role_b], nullptr, nullptr, w, s);
+    if (e == hipSuccess)
+      e = funnel::launch_row_idft(sp[i].W, reinterpret_cast<float2*>(w + sp[i].off), h, (long long)h * sp[i].W,
+                                  p->tw + sp[i].tw, B, s);
+  }
+  if (e == hipSuccess)
+    e = funnel::launch_refine_init(peaks, n_found, B, ns, K, sp[0].W, ns > 1 ? sp[1].W : sp[0].W, c.Np, state, s);
+  for (int it = 0; it <= iters && e == hipSuccess; ++it)
+    for (int i = 0; i < ns && e == hipSuccess; ++i)
+      e = funnel::launch_refine_iter(reinterpret_cast<const float2*>(w + sp[i].off), (long long)h * sp[i].W, h,
+                                     sp[i].W, i, ns, K, B, n_found, state, Abuf, c.Np, sp[i].space_id, c.N, c.M,
+                                     it == iters ? 1 : 0, out, s);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return ok();
+}
+
 }  // extern "C"

@@ -56,6 +56,21 @@ hipError_t launch_chirp(int W, int variant, bool adj, float2* data, int h, long 
 // host: the FP64-derived tables above for rows n2 = 1..h of padded length Np
 void chirp_tables(int W, int Np, int h, float2* cz, float2* wz);
 
+// Sub-cell refinement of peaks (uniform plans, power-of-two row lengths).
+// launch_row_idft: rows G -> g (inverse x' DFT, centred, 1/W) in place.
+// launch_refine_init: iteration state from the peak lists.
+// launch_refine_iter: one iteration (final = 0) or the evaluation and the
+// records (final = 1) for space index s of the plan.
+bool refine_length_supported(int W);
+size_t refine_state_bytes();
+hipError_t launch_row_idft(int W, float2* data, int h, long long img_stride, const float2* tw, int batch,
+                           hipStream_t s);
+hipError_t launch_refine_init(const ft_peak* peaks, const int32_t* n_found, int batch, int ns, int K, int W0, int W1,
+                              int Np, void* state, hipStream_t s);
+hipError_t launch_refine_iter(const float2* g, long long img_stride, int h, int W, int s, int ns, int K, int batch,
+                              const int32_t* n_found, void* state, float2* A, int Np, int space_id, int N, int M,
+                              int final, ft_refined* out, hipStream_t st);
+
 size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K);
 int peaks_tiles(int rows, int cols);
 hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int batch, int nspaces, int space0,

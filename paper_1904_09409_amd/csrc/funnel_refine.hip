@@ -1,0 +1,309 @@
+// funnel_refine.hip -- sub-cell refinement of detected peaks.
+//
+// Between cells the parameter plane is the last two steps of Sec. 3.1 with
+// the x' DFT taken at a real slope bin m (the DTFT of each resampled row g)
+// and the inverse y DFT at a real intercept y:
+//   P(m, y) = (2/Np) Re sum_n2 A(n2; m) exp(+j 2 pi n2 y / Np),
+//   A(n2; m) = sum_x' g[n2][x'] exp(-j 2 pi m x' / W),
+// equal to the plane at integer (m, y).  Line parameters (Eqs. 22-25) read at
+// its local maximum near a detected cell are continuous, which is where
+// Eq. 19 focuses a line.  The rows g are the inverse x' DFT of the G rows a
+// forward pass leaves in the workspace.  Each iteration forms, for every
+// peak, A and its first two m-derivatives over all rows (k_refine_dtft: a
+// (rows x W) by (W x peaks) product per plane), then reduces over n2 into P,
+// its gradient and Hessian and takes one safeguarded Newton step
+// (k_refine_step).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_core.hpp"
+#include "funnel_internal.hpp"
+
+namespace funnel {
+
+// ------------------------------------------------------------------ rows G -> g
+//
+// g[x'] = (1/W) sum_m1 G[m1] exp(+j 2 pi m1 x' / W) over centred indices:
+// with array indices p = m1 + W/2 and q = x' + W/2 this is
+// (1/W) (-1)^(q + W/2) sum_p (-1)^p G[p] exp(+j 2 pi p q / W).
+constexpr int kIdftThreads = 256;
+
+template <int W>
+__global__ void __launch_bounds__(kIdftThreads) k_row_idft(float2* __restrict__ data, int h, long long img_stride,
+                                                           const float2* __restrict__ tw) {
+  constexpr int P = W / 16;
+  constexpr int ROWS = kIdftThreads / P;
+  using Eng = FftR<W, P, true, false>;
+  constexpr int E = Eng::EM;
+  constexpr RadixPlan PL = Eng::kPlan;
+  constexpr int LAST = PL.n - 1;
+  constexpr int R0 = PL.r[0], NB0 = W / R0, BPT0 = Eng::template bpt<0, false>();
+  constexpr int RL = PL.r[LAST], NBL = W / RL, BPTL = Eng::template bpt<LAST, false>();
+  using Lay = LayRow<ROWS, W>;
+  __shared__ float2 lds[Lay::size(W)];
+  const int row = threadIdx.x / P, t = threadIdx.x % P;
+  const int n2 = blockIdx.x * ROWS + row + 1;
+  const bool active = n2 <= h;
+  float2* rowp = data + (long long)blockIdx.y * img_stride + (long long)(active ? n2 - 1 : 0) * W;
+  float2 v[E];
+#pragma unroll
+  for (int s = 0; s < E; ++s) v[s] = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int b = 0; b < BPT0; ++b)
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int p = t + P * b + r * NB0;
+      float2 x = active ? rowp[p] : make_float2(0.f, 0.f);
+      if (p & 1) x = make_float2(-x.x, -x.y);
+      v[b * R0 + r] = x;
+    }
+  Eng::template run<false, false, false, Lay>(v, row, t, lds, tw);
+  if (!active) return;
+  const float inv = 1.0f / (float)W;
+#pragma unroll
+  for (int b = 0; b < BPTL; ++b)
+#pragma unroll
+    for (int q2 = 0; q2 < RL; ++q2) {
+      const int q = t + P * b + q2 * NBL;
+      const float sg = ((q + W / 2) & 1) ? -inv : inv;
+      rowp[q] = make_float2(sg * v[b * RL + q2].x, sg * v[b * RL + q2].y);
+    }
+}
+
+#define FUNNEL_REFINE_LENGTHS(X) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
+
+bool refine_length_supported(int W) {
+  switch (W) {
+#define CASE(n) case n: return true;
+    FUNNEL_REFINE_LENGTHS(CASE)
+#undef CASE
+    default: return false;
+  }
+}
+
+hipError_t launch_row_idft(int W, float2* data, int h, long long img_stride, const float2* tw, int batch,
+                           hipStream_t s) {
+  switch (W) {
+#define CASE(n)                                                                                   \
+  case n: {                                                                                       \
+    constexpr int rows = kIdftThreads / (n / 16);                                                 \
+    k_row_idft<n><<<dim3((h + rows - 1) / rows, batch), kIdftThreads, 0, s>>>(data, h, img_stride, tw); \
+    return hipGetLastError();                                                                     \
+  }
+    FUNNEL_REFINE_LENGTHS(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ------------------------------------------------------------------ iteration state
+//
+// state[(img * ns + s) * K + p] = {m, y, m0, y0, sign}: slope bin and intercept
+// (centred, real), the start cell, and the sign of P there (0 until known).
+struct RefState {
+  float m, y, m0, y0, sg;
+};
+
+__global__ void k_refine_init(const ft_peak* __restrict__ peaks, const int32_t* __restrict__ n_found, int ns, int K,
+                              int W0, int W1, int Np, RefState* __restrict__ st, int total) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int s = (i / K) % ns, p = i % K, img = i / (K * ns);
+  RefState r{0.f, 0.f, 0.f, 0.f, 0.f};
+  if (p < n_found[img * ns + s]) {
+    const ft_peak pk = peaks[i];
+    const int W = s == 0 ? W0 : W1;
+    r.m0 = r.m = (float)(pk.col - W / 2);
+    r.y0 = r.y = (float)(pk.row - Np / 2);
+  }
+  st[i] = r;
+}
+
+// ------------------------------------------------------------------ the DTFT sums
+//
+// For rows n2 of one space and peaks p of a group of 16:
+//   A0 = sum_x' g e_p,  S1 = sum_x' x' g e_p,  S2 = sum_x' x'^2 g e_p,
+// e_p(x') = exp(-j 2 pi m_p x' / W), centred x'.  A1 = (-j 2 pi / W) S1 and
+// A2 = -(2 pi / W)^2 S2 are the first two m-derivatives of A0.
+// Output layout: A[((img * ns + s) * K + p) * 3 + d][n2 - 1], d = A0, S1, S2.
+constexpr int kRefRows = 16, kRefPeaks = 16, kRefChunk = 64;
+
+__global__ void __launch_bounds__(256)
+    k_refine_dtft(const float2* __restrict__ g, long long img_stride, int h, int W, int s, int ns, int K,
+                  const int32_t* __restrict__ n_found, const RefState* __restrict__ st, float2* __restrict__ A) {
+  __shared__ float2 gt[kRefRows][kRefChunk + 1];
+  __shared__ float2 et[kRefPeaks][kRefChunk + 1];
+  __shared__ float pm[kRefPeaks];
+  __shared__ int pm0[kRefPeaks];
+  const int img = blockIdx.y, grp = blockIdx.z;
+  const int n2a = blockIdx.x * kRefRows + 1;
+  const int tid = threadIdx.x;
+  const int lr = tid / kRefPeaks, lp = tid % kRefPeaks;
+  const int cnt = n_found[img * ns + s];
+  if (grp * kRefPeaks >= cnt) return;   // uniform: no peaks in this group
+  const long long sbase = ((long long)img * ns + s) * K;
+  if (tid < kRefPeaks) {
+    const int p = grp * kRefPeaks + tid;
+    const RefState r = p < cnt ? st[sbase + p] : RefState{0.f, 0.f, 0.f, 0.f, 0.f};
+    pm0[tid] = (int)r.m0;
+    pm[tid] = r.m - r.m0;   // |u| <= 1: the offset from the start cell
+  }
+  __syncthreads();
+  const float2* gimg = g + (long long)img * img_stride;
+  float2 a0 = make_float2(0.f, 0.f), s1 = a0, s2 = a0;
+  for (int x0 = 0; x0 < W; x0 += kRefChunk) {
+    // stage 16 rows x 64 samples of g and the 16 x 64 phase factors
+    for (int i = tid; i < kRefRows * kRefChunk; i += 256) {
+      const int r = i / kRefChunk, j = i % kRefChunk;
+      const int n2 = n2a + r;
+      gt[r][j] = n2 <= h ? gimg[(long long)(n2 - 1) * W + x0 + j] : make_float2(0.f, 0.f);
+      // e_p(x') with the phase m x'/W = (m0 x' mod W)/W + u x'/W, centred x'
+      const int p = r;   // reuse the loop: 16 peaks x 64 samples
+      const int xc = x0 + j - W / 2;
+      const int whole = ((pm0[p] * xc) % W + W) % W;
+      const float frac = (float)whole / (float)W + pm[p] * (float)xc / (float)W;
+      float sn, cs;
+      sincospif(-2.0f * frac, &sn, &cs);
+      et[p][j] = make_float2(cs, sn);
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int j = 0; j < kRefChunk; ++j) {
+      const float2 gv = gt[lr][j], ev = et[lp][j];
+      const float2 t = c_mul(gv, ev);
+      const float xc = (float)(x0 + j - W / 2);
+      a0.x += t.x;
+      a0.y += t.y;
+      s1.x = fmaf(xc, t.x, s1.x);
+      s1.y = fmaf(xc, t.y, s1.y);
+      s2.x = fmaf(xc * xc, t.x, s2.x);
+      s2.y = fmaf(xc * xc, t.y, s2.y);
+    }
+    __syncthreads();
+  }
+  const int p = grp * kRefPeaks + lp, n2 = n2a + lr;
+  if (p >= cnt || n2 > h) return;
+  float2* dst = A + (sbase + p) * 3 * (long long)h + (n2 - 1);
+  dst[0] = a0;
+  dst[h] = s1;
+  dst[2 * (long long)h] = s2;
+}
+
+// ------------------------------------------------------------------ the Newton step
+//
+// One block per peak.  With w = exp(+j 2 pi n2 y / Np), c = 2 pi n2 / Np,
+// kw = 2 pi / W and f = 2 / Np:
+//   P    =  f      sum Re(A0 w)        P_y  = -f    sum c Im(A0 w)
+//   P_yy = -f      sum c^2 Re(A0 w)    P_m  =  f kw sum Im(S1 w)
+//   P_my =  f kw   sum c Re(S1 w)      P_mm = -f kw^2 sum Re(S2 w)
+// Then (thread 0) the same safeguarded step as the definition: Newton when
+// the Hessian of F = sign(P) P is negative definite, else a gradient step of
+// 1/4 cell; each component clamped to 1/2 cell, the total displacement to 1
+// cell from the start.  With `final` set P is only evaluated and the record
+// written.
+__global__ void __launch_bounds__(256)
+    k_refine_step(const float2* __restrict__ A, int h, int Np, int W, int s, int ns, int K, int space_id, int N,
+                  int M, const int32_t* __restrict__ n_found, RefState* __restrict__ st, int final,
+                  ft_refined* __restrict__ out) {
+  const int p = blockIdx.x, img = blockIdx.y, tid = threadIdx.x;
+  const long long idx = ((long long)img * ns + s) * K + p;
+  if (p >= n_found[img * ns + s]) {
+    if (final && tid == 0) {
+      ft_refined z;
+      z.col = z.row = z.value = z.slope = z.intercept = z.shift = 0.f;
+      out[idx] = z;
+    }
+    return;
+  }
+  const RefState r = st[idx];
+  const int y0 = (int)r.y0;
+  const float uy = r.y - r.y0;
+  const float2* a = A + idx * 3 * (long long)h;
+  float q[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int n2 = 1 + tid; n2 <= h; n2 += 256) {
+    // phase n2 y / Np = (n2 y0 mod Np) / Np + n2 (y - y0) / Np
+    const int whole = (int)(((long long)n2 * y0 % Np + Np) % Np);
+    const float frac = (float)whole / (float)Np + (float)n2 * uy / (float)Np;
+    float sn, cs;
+    sincospif(2.0f * frac, &sn, &cs);
+    const float c = 6.283185307179586f * (float)n2 / (float)Np;
+    const float2 a0 = a[n2 - 1], b1 = a[h + n2 - 1], b2 = a[2 * (long long)h + n2 - 1];
+    const float re0 = a0.x * cs - a0.y * sn, im0 = a0.x * sn + a0.y * cs;
+    const float re1 = b1.x * cs - b1.y * sn, im1 = b1.x * sn + b1.y * cs;
+    const float re2 = b2.x * cs - b2.y * sn;
+    q[0] += re0;
+    q[1] = fmaf(c, im0, q[1]);
+    q[2] = fmaf(c * c, re0, q[2]);
+    q[3] += im1;
+    q[4] = fmaf(c, re1, q[4]);
+    q[5] += re2;
+  }
+  __shared__ float part[256 / 64][6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) q[k] += __shfl_xor(q[k], off, 64);
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) part[tid >> 6][k] = q[k];
+  __syncthreads();
+  if (tid != 0) return;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) q[k] = part[0][k] + part[1][k] + part[2][k] + part[3][k];
+  const float f = 2.0f / (float)Np, kw = 6.283185307179586f / (float)W;
+  const float P = f * q[0];
+  RefState nr = r;
+  if (nr.sg == 0.f) nr.sg = P >= 0.f ? 1.f : -1.f;
+  if (final) {
+    ft_refined rec;
+    const int Wp = space_id == 0 ? M : N, Hp = space_id == 0 ? N : M;
+    rec.col = r.m + (float)(Wp / 2);
+    rec.row = r.y + (float)(Np / 2);
+    rec.value = fabsf(P);
+    rec.slope = -2.0f * r.m / (float)Wp;
+    rec.intercept = r.y - rec.slope * (float)(Wp / 2) + (float)(Hp / 2);
+    rec.shift = hypotf(r.m - r.m0, r.y - r.y0);
+    out[idx] = rec;
+    return;
+  }
+  const float sg = nr.sg;
+  const float Fm = sg * f * kw * q[3], Fy = -sg * f * q[1];
+  const float Fmm = -sg * f * kw * kw * q[5], Fmy = sg * f * kw * q[4], Fyy = -sg * f * q[2];
+  const float det = Fmm * Fyy - Fmy * Fmy;
+  float dm, dy;
+  if (Fmm < 0.f && det > 0.f) {
+    dm = -(Fyy * Fm - Fmy * Fy) / det;
+    dy = -(Fmm * Fy - Fmy * Fm) / det;
+  } else {
+    const float nrm = hypotf(Fm, Fy);
+    dm = nrm > 0.f ? 0.25f * Fm / nrm : 0.f;
+    dy = nrm > 0.f ? 0.25f * Fy / nrm : 0.f;
+  }
+  nr.m = fminf(fmaxf(r.m + fminf(fmaxf(dm, -0.5f), 0.5f), r.m0 - 1.f), r.m0 + 1.f);
+  nr.y = fminf(fmaxf(r.y + fminf(fmaxf(dy, -0.5f), 0.5f), r.y0 - 1.f), r.y0 + 1.f);
+  st[idx] = nr;
+}
+
+hipError_t launch_refine_init(const ft_peak* peaks, const int32_t* n_found, int batch, int ns, int K, int W0, int W1,
+                              int Np, void* state, hipStream_t s) {
+  const int total = batch * ns * K;
+  k_refine_init<<<(total + 255) / 256, 256, 0, s>>>(peaks, n_found, ns, K, W0, W1, Np, static_cast<RefState*>(state),
+                                                    total);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_iter(const float2* g, long long img_stride, int h, int W, int s, int ns, int K, int batch,
+                              const int32_t* n_found, void* state, float2* A, int Np, int space_id, int N, int M,
+                              int final, ft_refined* out, hipStream_t st) {
+  RefState* sv = static_cast<RefState*>(state);
+  dim3 g1((h + kRefRows - 1) / kRefRows, batch, (K + kRefPeaks - 1) / kRefPeaks);
+  k_refine_dtft<<<g1, 256, 0, st>>>(g, img_stride, h, W, s, ns, K, n_found, sv, A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_refine_step<<<dim3(K, batch), 256, 0, st>>>(A, h, Np, W, s, ns, K, space_id, N, M, n_found, sv, final, out);
+  return hipGetLastError();
+}
+
+size_t refine_state_bytes() { return sizeof(RefState); }
+
+}  // namespace funnel

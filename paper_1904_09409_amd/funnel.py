@@ -67,6 +67,9 @@ PEAK_WORDS = PEAK_DTYPE.itemsize // 4   # 7 x 4 bytes
 LINE_CHECK_DTYPE = np.dtype([("profile", np.float32, (7,)), ("contrast", np.float32), ("length", np.int32),
                              ("verified", np.int32)])
 LINE_CHECK_WORDS = LINE_CHECK_DTYPE.itemsize // 4   # 10 x 4 bytes
+REFINED_DTYPE = np.dtype([("col", np.float32), ("row", np.float32), ("value", np.float32), ("slope", np.float32),
+                          ("intercept", np.float32), ("shift", np.float32)])
+REFINED_WORDS = REFINED_DTYPE.itemsize // 4   # 6 x 4 bytes
 
 
 class FunnelError(RuntimeError):
@@ -104,6 +107,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "funnel_peaks_workspace_size": ([vp, i32, ctypes.POINTER(sz)], ctypes.c_int),
         "funnel_peaks": ([vp, vp, i32, ctypes.c_float, i32, u32, vp, vp, vp, sz, vp], ctypes.c_int),
         "funnel_verify": ([vp, vp, vp, vp, i32, i32, ctypes.c_float, i32, vp, vp], ctypes.c_int),
+        "funnel_refine_workspace_size": ([vp, i32, ctypes.POINTER(sz)], ctypes.c_int),
+        "funnel_refine": ([vp, vp, vp, vp, i32, i32, vp, vp, sz, vp], ctypes.c_int),
         "funnel_profile_enable": ([vp, i32], ctypes.c_int),
         "funnel_profile_read": ([vp, ctypes.POINTER(ft_kernel_time), i32, ctypes.POINTER(i32)], ctypes.c_int),
         "funnel_profile_disable": ([vp], ctypes.c_int),
@@ -253,6 +258,17 @@ def funnel_verify(plan: int, images, peaks, n_found, K: int, half_width: int, mi
            "funnel_verify")
 
 
+def funnel_refine_workspace_size(plan: int, K: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().funnel_refine_workspace_size(plan, int(K), ctypes.byref(n)), "funnel_refine_workspace_size")
+    return n.value
+
+
+def funnel_refine(plan: int, images, peaks, n_found, K: int, iters: int, out, ws, stream=None) -> None:
+    _check(load_library().funnel_refine(plan, _ptr(images), _ptr(peaks), _ptr(n_found), int(K), int(iters), _ptr(out),
+                                        _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)), "funnel_refine")
+
+
 def funnel_profile_enable(plan: int, max_records: int) -> None:
     _check(load_library().funnel_profile_enable(plan, int(max_records)), "funnel_profile_enable")
 
@@ -390,6 +406,17 @@ class FunnelPlan:
         funnel_verify(self.handle, images, rec, cnt, rec.shape[2], half_width, min_contrast, min_length, out, stream)
         return out
 
+    def refine(self, images, rec, cnt, iters: int = 4, stream=None):
+        """Sub-cell refinement of peak lists from peaks(): ft_refined records
+        as float32 [B, nspaces, K, 6] on the device (refined_to_numpy() reads
+        them)."""
+        import torch
+        K = rec.shape[2]
+        ws = torch.empty(funnel_refine_workspace_size(self.handle, K), dtype=torch.uint8, device=self.device)
+        out = torch.empty((rec.shape[0], rec.shape[1], K, REFINED_WORDS), dtype=torch.float32, device=self.device)
+        funnel_refine(self.handle, images, rec, cnt, K, iters, out, ws, stream)
+        return out
+
 
 class RaggedPlan:
     """A plan for a batch of images of different sizes, packed back to back
@@ -507,6 +534,12 @@ class FunnelGraph:
             except Exception:
                 pass
             self.handle = None
+
+
+def refined_to_numpy(out):
+    """Device ft_refined records [B, nspaces, K, 6] -> numpy structured array [B, nspaces, K]."""
+    a = np.ascontiguousarray(out.cpu().numpy())
+    return a.view(REFINED_DTYPE).reshape(a.shape[:3])
 
 
 def checks_to_numpy(out):
