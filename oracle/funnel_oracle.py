@@ -43,6 +43,9 @@ __all__ = [
     "boundary_mask", "peaks_list", "peak_params",
     "line_band_profile", "line_verdict",
     "resampled_rows", "continuous_plane", "refine_peak",
+    "padded_depth", "expand_volume", "spectrum_z", "nvmt_bilinear", "dft_xy", "idft_z",
+    "forward_volume", "forward_volume_lines", "volume_boundary_mask", "peaks_list_volume",
+    "plane_params",
 ]
 
 
@@ -541,3 +544,215 @@ def refine_peak(g: np.ndarray, Np: int, row: int, col: int, iters: int = 4):
         m = min(max(m + min(max(dm, -0.5), 0.5), m0 - 1.0), m0 + 1.0)
         y = min(max(y + min(max(dy, -0.5), 0.5), y0 - 1.0), y0 + 1.0)
     return m, y, abs(continuous_plane(g, Np, m, y)[0])
+
+
+# --------------------------------------------------------------------------
+# Funnel transform of a volume (App. A): planes <-> points
+# --------------------------------------------------------------------------
+#
+# Volume V[r, i, c]: Nz slices (z, the depth axis), Ny rows (y), Nx columns
+# (x), all even.  The App. A steps, discretised the way Sec. 3.1 is for
+# images: DFT along z of the expanded volume (Eq. A.2), the NVMT x' = s x,
+# y' = s y with s = omega_3 / omega_max = 2 n3 / Nzp (Eq. A.3), the 2D DFT
+# along x', y' (Eq. A.4) and the inverse DFT along omega_3 (Eqs. A.5, A.9).
+# A plane z = a x + b y + c (centred coordinates) focuses at
+# m1 = -a Nx/2, m2 = -b Ny/2 and z = c (Eq. A.9 with omega_max = pi); the
+# volume P[z + Nzp/2, m2 + Ny/2, m1 + Nx/2] is real.
+
+def padded_depth(Nz: int, Ny: int, Nx: int, padded_len: int = 0) -> int:
+    """Length of the expanded z axis: Nz + Ny + Nx by default.  Over the
+    volume a plane with |a|, |b| <= 1 moves by at most (Nx + Ny)/2 along z,
+    so that many zero slices on each side keep its intercept from wrapping
+    (the counterpart of the expansion of Sec. 4.2).  An explicit even length
+    >= Nz may be asked for."""
+    Nzp = Nz + Ny + Nx if padded_len == 0 else int(padded_len)
+    if Nzp < Nz or Nzp % 2:
+        raise ValueError("padded depth must be even and >= Nz")
+    return Nzp
+
+
+def expand_volume(vol: np.ndarray, Nzp: int) -> np.ndarray:
+    """The Nz slices in an Nzp-slice zero frame, (Nzp - Nz)//2 zero slices
+    in front of them."""
+    Nz, Ny, Nx = vol.shape
+    top = (Nzp - Nz) // 2
+    out = np.zeros((Nzp, Ny, Nx), dtype=np.float64)
+    out[top:top + Nz] = vol
+    return out
+
+
+def spectrum_z(vol_pad: np.ndarray) -> np.ndarray:
+    """Eq. A.2: DFT of every (y, x) line along z,
+    S[n3-1, i, c] = sum_z V_pad[z, i, c] exp(-j 2 pi n3 z / Nzp), centred z,
+    for n3 = 1 .. Nzp/2-1 (negative n3 follow by conjugation)."""
+    Nzp = vol_pad.shape[0]
+    n3 = np.arange(1, Nzp // 2)
+    z = np.arange(Nzp) - Nzp // 2
+    E = np.exp(-2j * np.pi * np.outer(n3, z) / Nzp)
+    return np.tensordot(E, vol_pad, axes=(1, 0))
+
+
+def nvmt_bilinear(S: np.ndarray, Nzp: int, n3_first: int = 1) -> np.ndarray:
+    """Eq. A.3: the NVMT x' = s x, y' = s y with s = 2 n3 / Nzp, realised by
+    bilinear interpolation (linear along each axis, the 2D form of the linear
+    option of Sec. V): g[n3, y', x'] = f(y'/s, x'/s), f = S[n3] on its integer
+    grid and zero outside it.
+
+    The fractional grid positions u = y'/s + Ny/2 = (y' Nzp + Ny n3)/(2 n3)
+    and v = (x' Nzp + Nx n3)/(2 n3) are split with exact integer floors; the
+    four neighbours carry the weights (1-t_u)(1-t_v), (1-t_u) t_v,
+    t_u (1-t_v) and t_u t_v.  Slice k of S is frequency n3 = n3_first + k."""
+    h, Ny, Nx = S.shape
+    yp = np.arange(Ny, dtype=np.int64) - Ny // 2
+    xp = np.arange(Nx, dtype=np.int64) - Nx // 2
+    g = np.zeros_like(S)
+    for k in range(h):
+        n3 = n3_first + k
+        f = S[k]
+        den = 2 * n3
+        nu = yp * Nzp + Ny * n3
+        nv = xp * Nzp + Nx * n3
+        i0 = nu // den
+        j0 = nv // den
+        tu = ((nu - i0 * den) / den)[:, None]
+        tv = ((nv - j0 * den) / den)[None, :]
+        I0, J0 = i0[:, None], j0[None, :]
+
+        def tap(ii, jj):
+            inside = (ii >= 0) & (ii < Ny) & (jj >= 0) & (jj < Nx)
+            return np.where(inside, f[np.clip(ii, 0, Ny - 1), np.clip(jj, 0, Nx - 1)], 0.0)
+
+        g[k] = ((1.0 - tu) * (1.0 - tv) * tap(I0, J0) + (1.0 - tu) * tv * tap(I0, J0 + 1)
+                + tu * (1.0 - tv) * tap(I0 + 1, J0) + tu * tv * tap(I0 + 1, J0 + 1))
+    return g
+
+
+def dft_xy(g: np.ndarray) -> np.ndarray:
+    """Eq. A.4: 2D DFT over x', y' of every slice,
+    G[n3, m2, m1] = sum_{y', x'} g[n3, y', x'] exp(-j 2 pi (m1 x'/Nx + m2 y'/Ny)),
+    centred x', y', m1, m2."""
+    h, Ny, Nx = g.shape
+    return np.matmul(np.matmul(_xdft_matrix(Ny), g), _xdft_matrix(Nx))
+
+
+def idft_z(G: np.ndarray, Nzp: int) -> np.ndarray:
+    """Eqs. A.5 / A.9: inverse DFT along omega_3, the negative half completed
+    by G[-n3] = conj(G[n3]) (DC and Nyquist zero):
+    P[z, m2, m1] = (1/Nzp) sum_n3 G[n3, m2, m1] exp(+j 2 pi n3 z / Nzp),
+    z = -Nzp/2 .. Nzp/2-1.  Real; the imaginary part is checked to be
+    rounding noise."""
+    h, Ny, Nx = G.shape
+    full = np.zeros((Nzp, Ny, Nx), dtype=np.complex128)
+    n3 = np.arange(1, h + 1)
+    full[n3 + Nzp // 2] = G
+    full[-n3 + Nzp // 2] = np.conj(G)
+    z = np.arange(Nzp) - Nzp // 2
+    Winv = np.exp(2j * np.pi * np.outer(z, z) / Nzp)
+    P = np.tensordot(Winv, full, axes=(1, 0)) / Nzp
+    scale = max(1.0, float(np.abs(P.real).max()))
+    if np.abs(P.imag).max() > 1e-9 * scale:
+        raise AssertionError("inverse DFT of a Hermitian spectrum is not real")
+    return P.real
+
+
+def forward_volume(vol: np.ndarray, padded_len: int = 0) -> np.ndarray:
+    """Funnel transform of one volume (App. A) on its expanded frame.
+    Returns P[Nzp, Ny, Nx] in float64."""
+    vol = np.asarray(vol, dtype=np.float64)
+    Nz, Ny, Nx = vol.shape
+    Nzp = padded_depth(Nz, Ny, Nx, padded_len)
+    S = spectrum_z(expand_volume(vol, Nzp))
+    return idft_z(dft_xy(nvmt_bilinear(S, Nzp)), Nzp)
+
+
+def forward_volume_lines(vol: np.ndarray, lines, padded_len: int = 0) -> np.ndarray:
+    """P[:, row, col] of forward_volume for the listed (row, col) =
+    (m2 + Ny/2, m1 + Nx/2) pairs only, for volumes too large for the whole
+    transform: the same steps, slice by slice, with Eq. A.4 evaluated at the
+    listed bins only and Eq. A.5 written as the real part of the one-sided
+    sum, P = (2/Nzp) Re sum_{n3=1}^{Nzp/2-1} G[n3] exp(+j 2 pi n3 z / Nzp).
+    Returns [Nzp, len(lines)]."""
+    vol = np.asarray(vol, dtype=np.float64)
+    Nz, Ny, Nx = vol.shape
+    Nzp = padded_depth(Nz, Ny, Nx, padded_len)
+    h = Nzp // 2 - 1
+    rows = np.array([r for r, _ in lines])
+    cols = np.array([c for _, c in lines])
+    ey = _xdft_matrix(Ny)[:, rows]           # [y', line]
+    ex = _xdft_matrix(Nx)[:, cols]           # [x', line]
+    S = spectrum_z(expand_volume(vol, Nzp))
+    G = np.empty((h, len(lines)), dtype=np.complex128)
+    for k in range(h):
+        g = nvmt_bilinear(S[k:k + 1], Nzp, k + 1)[0]
+        G[k] = np.einsum("yl,yx,xl->l", ey, g, ex)
+    z = np.arange(Nzp) - Nzp // 2
+    n3 = np.arange(1, h + 1)
+    return (2.0 / Nzp) * np.real(np.exp(2j * np.pi * np.outer(z, n3) / Nzp) @ G)
+
+
+def volume_boundary_mask(Nz: int, Ny: int, Nx: int, Nzp: int) -> np.ndarray:
+    """Cells of the parameter volume (Nzp x Ny x Nx) where the artificial
+    front and back faces created by the expansion focus (planes z = -Nz/2
+    and z = Nz/2 with a = b = 0): bins m1, m2 in {-1, 0, 1} and slices within
+    2 of either face, the same cells as the 2D border mask of Sec. 4.2 on
+    every slope bin pair next to zero."""
+    mask = np.zeros((Nzp, Ny, Nx), dtype=bool)
+    rows = np.array([-1, 0, 1]) + Ny // 2
+    cols = np.array([-1, 0, 1]) + Nx // 2
+    for edge in (-Nz // 2, Nz // 2):
+        zs = np.arange(edge - 2, edge + 2) + Nzp // 2
+        zs = zs[(zs >= 0) & (zs < Nzp)]
+        mask[np.ix_(zs, rows, cols)] = True
+    return mask
+
+
+def peaks_list_volume(B: np.ndarray, K: int, T: float, radius: int = 1,
+                      mask: np.ndarray | None = None, wrap: bool = True) -> list[int]:
+    """The list-based peak detection of Sec. 4.4 in the 3D parameter space
+    (App. A detects planes as 3D peaks): cells visited in the order
+    (brightness descending, linear index ascending); a cell is detected when
+    no cell of its (2r+1)^3 neighbourhood was visited before it; every cell
+    is marked visited; stop at K detections or the first cell below T.  Cells
+    inside ``mask`` are visited but never detected.  The neighbourhood wraps
+    (all three axes are periodic) unless ``wrap`` is False.  Returns linear
+    indices (z, row, col order) in detection order."""
+    B = np.asarray(B)
+    nz, ny, nx = B.shape
+    flat = B.ravel()
+    order = np.lexsort((np.arange(flat.size), -flat))
+    visited = np.zeros(B.shape, dtype=bool)
+    off = np.arange(-radius, radius + 1)
+    detected: list[int] = []
+    if K <= 0:
+        return detected
+    for idx in order:
+        v = flat[idx]
+        if v < T:
+            break
+        z, rem = divmod(int(idx), ny * nx)
+        r, c = divmod(rem, nx)
+        zz, rr, cc = z + off, r + off, c + off
+        if wrap:
+            zz, rr, cc = zz % nz, rr % ny, cc % nx
+        else:
+            zz = zz[(zz >= 0) & (zz < nz)]
+            rr = rr[(rr >= 0) & (rr < ny)]
+            cc = cc[(cc >= 0) & (cc < nx)]
+        seen = visited[np.ix_(zz, rr, cc)].any()
+        visited[z, r, c] = True
+        if not seen and not (mask is not None and mask[z, r, c]):
+            detected.append(int(idx))
+            if len(detected) == K:
+                break
+    return detected
+
+
+def plane_params(z: int, row: int, col: int, Nz: int, Ny: int, Nx: int, Nzp: int):
+    """Eq. A.9 read backwards: cell -> plane, in voxel-index coordinates.
+    m1 = col - Nx/2, m2 = row - Ny/2, a = -2 m1 / Nx, b = -2 m2 / Ny, centred
+    intercept c0 = z - Nzp/2; the plane is ``slice = a * column + b * row + c``
+    with c = c0 - a Nx/2 - b Ny/2 + Nz/2.  Returns (a, b, c)."""
+    a = -2.0 * (col - Nx // 2) / Nx
+    b = -2.0 * (row - Ny // 2) / Ny
+    c0 = z - Nzp // 2
+    return a, b, c0 - a * Nx / 2 - b * Ny / 2 + Nz / 2

@@ -191,3 +191,72 @@ def batch(config: str, count: int | None = None, seed: int = 0, size: int | None
 def stack(images) -> np.ndarray:
     """Stack equally sized SynthImage objects into a float32 [B, N, M] array."""
     return np.stack([im.image for im in images]).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# Volumes holding planes (the 3D form, App. A)
+# --------------------------------------------------------------------------
+#
+# Voxel (s, r, c) = (slice, row, column) has its centre at those index
+# coordinates.  A sheet is the plane ``slice = a * col + b * row + c0`` with
+# |a|, |b| <= 1, rendered like a ridge line along z: a voxel gains
+# (1 - background) times the overlap of [s - 1/2, s + 1/2] with
+# [z0 - w/2, z0 + w/2], z0 = a c + b r + c0.  Noise and clipping as for images.
+
+@dataclass
+class Sheet:
+    a: float
+    b: float
+    c: float
+    width: float = 1.0
+
+
+@dataclass
+class SynthVolume:
+    volume: np.ndarray           # float32 [Nz, Ny, Nx]
+    sheets: list = field(default_factory=list)
+    sigma: float = 0.0
+
+
+def render_volume(Nz: int, Ny: int, Nx: int, sheets, sigma: float, rng: np.random.Generator,
+                  bg: float = BACKGROUND) -> np.ndarray:
+    vol = np.full((Nz, Ny, Nx), bg, dtype=np.float64)
+    r = np.arange(Ny, dtype=np.float64)[:, None]
+    c = np.arange(Nx, dtype=np.float64)[None, :]
+    amp = 1.0 - bg
+    for sh in sheets:
+        z0 = sh.a * c + sh.b * r + sh.c
+        half = 0.5 * sh.width
+        base = np.floor(z0).astype(np.int64)
+        for d in range(-3, 4):
+            s = base + d
+            ok = (s >= 0) & (s < Nz)
+            ss = s.astype(np.float64)
+            cov = np.clip(np.minimum(ss + 0.5, z0 + half) - np.maximum(ss - 0.5, z0 - half), 0.0, 1.0)
+            rr, cc = np.nonzero(ok)
+            vol[s[ok], rr, cc] += amp * cov[ok]
+    if sigma > 0:
+        vol += rng.normal(0.0, sigma, size=vol.shape)
+    return np.clip(vol, 0.0, 1.0).astype(np.float32)
+
+
+def random_sheet(rng: np.random.Generator, Nz: int, Ny: int, Nx: int, widths=(1, 2)) -> Sheet:
+    """A sheet with |a|, |b| < 0.9 that crosses the centre slab of the volume."""
+    a = float(rng.uniform(-0.9, 0.9))
+    b = float(rng.uniform(-0.9, 0.9))
+    zc = float(rng.uniform(0.25 * Nz, 0.75 * Nz))        # slice at the volume's centre column
+    return Sheet(a, b, zc - a * Nx / 2 - b * Ny / 2, float(widths[int(rng.integers(len(widths)))]))
+
+
+def sheet_volume(Nz: int, Ny: int, Nx: int, n_sheets, sigma: float, rng: np.random.Generator) -> SynthVolume:
+    if isinstance(n_sheets, tuple):
+        n_sheets = int(rng.integers(n_sheets[0], n_sheets[1] + 1))
+    sheets = [random_sheet(rng, Nz, Ny, Nx) for _ in range(n_sheets)]
+    return SynthVolume(render_volume(Nz, Ny, Nx, sheets, sigma, rng), sheets, sigma)
+
+
+def volume_batch(count: int = 4, size: int = 256, seed: int = 0, n_sheets=(2, 6), sigma: float = 0.1):
+    """``count`` volumes of size^3 voxels, each with 2-6 sheets (widths 1-2
+    voxels) under N(0, 0.1^2) noise; volume i draws from the generator seeded
+    by (6, seed, i)."""
+    return [sheet_volume(size, size, size, n_sheets, sigma, _rng(6, seed, i)) for i in range(count)]

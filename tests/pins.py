@@ -758,3 +758,235 @@ def check_refine_stationary(O):
         if abs(m - (c - M // 2)) < 0.999 and abs(y - (r - Np // 2)) < 0.999:   # not stopped at the trust bound
             assert np.hypot(Pm, Py) <= 1e-6 * abs(Pv), (idx, Pm, Py)
             assert sg * Pmm < 0 and Pmm * Pyy - Pmy * Pmy > 0
+
+
+# ----------------------------------------------------------------- volumes (App. A)
+
+def expected_cell_volume(sh: synth.Sheet, Nz: int, Ny: int, Nx: int, Nzp: int):
+    """Plane -> point (Eq. A.9 with omega_max = pi): the sheet
+    slice = a col + b row + c has the centred intercept c + a Nx/2 + b Ny/2
+    - Nz/2 and focuses at m1 = -a Nx/2, m2 = -b Ny/2.  Returns (z, row, col)."""
+    cc = sh.c + sh.a * Nx / 2 + sh.b * Ny / 2 - Nz / 2
+    return (int(round(cc)) + Nzp // 2, (int(round(-sh.b * Ny / 2)) + Ny // 2) % Ny,
+            (int(round(-sh.a * Nx / 2)) + Nx // 2) % Nx)
+
+
+def check_spectrum_z_is_library_fft(O):
+    """Eq. A.2 on the centred frame: S[n3] = (-1)^n3 FFT_z(V_pad)[n3]."""
+    rng = np.random.default_rng(101)
+    vol = O.expand_volume(rng.random((6, 4, 6)), 20)
+    S = O.spectrum_z(vol)
+    n3 = np.arange(1, 10)
+    want = np.fft.fft(vol, axis=0)[1:10] * ((-1.0) ** n3)[:, None, None]
+    assert S.shape == (9, 4, 6) and np.abs(S - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def check_dft_xy_is_library_fft2(O):
+    """Eq. A.4 with centred indices is the shifted 2D FFT of every slice."""
+    rng = np.random.default_rng(102)
+    g = rng.standard_normal((3, 6, 10)) + 1j * rng.standard_normal((3, 6, 10))
+    want = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(g, axes=(1, 2))), axes=(1, 2))
+    assert np.abs(O.dft_xy(g) - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def check_idft_z_is_library_ifft(O):
+    """Eq. A.5: the inverse z DFT of the Hermitian-completed half spectrum
+    equals numpy's inverse FFT of the full spectrum (natural order, the
+    centred n3 carried as (-1)^n3)."""
+    rng = np.random.default_rng(103)
+    Nzp = 14
+    G = rng.standard_normal((6, 3, 4)) + 1j * rng.standard_normal((6, 3, 4))
+    full = np.zeros((Nzp, 3, 4), complex)
+    for n3 in range(1, 7):
+        full[n3] = G[n3 - 1] * (-1.0) ** n3
+        full[Nzp - n3] = np.conj(G[n3 - 1]) * (-1.0) ** n3
+    # (-1)^n3 moves the origin: slice r of the inverse FFT is z = r - Nzp/2
+    want = np.fft.ifft(full, axis=0).real
+    assert np.abs(O.idft_z(G, Nzp) - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def check_bilinear_exact_on_bilinear_slices(O):
+    """Bilinear interpolation reproduces a slice of the form
+    alpha + beta i + gamma j + delta i j exactly wherever the position
+    (u, v) = (y'/s + Ny/2, x'/s + Nx/2) lies on the grid's hull, and gives 0
+    where u or v is more than one cell outside it."""
+    Ny, Nx, Nzp = 8, 12, 40
+    h = Nzp // 2 - 1
+    al, be, ga, de = 0.3 + 0.1j, -0.2 + 0.05j, 0.15 - 0.3j, 0.02 + 0.01j
+    i = np.arange(Ny)[:, None]
+    j = np.arange(Nx)[None, :]
+    S = np.tile(al + be * i + ga * j + de * i * j, (h, 1, 1))
+    g = O.nvmt_bilinear(S, Nzp)
+    yp = (np.arange(Ny) - Ny // 2)[:, None]
+    xp = (np.arange(Nx) - Nx // 2)[None, :]
+    for n3 in range(1, h + 1):
+        s = 2.0 * n3 / Nzp
+        u, v = yp / s + Ny / 2, xp / s + Nx / 2
+        inside = (u >= 0) & (u <= Ny - 1) & (v >= 0) & (v <= Nx - 1)
+        want = al + be * u + ga * v + de * u * v
+        assert np.abs(g[n3 - 1][inside] - np.broadcast_to(want, g[n3 - 1].shape)[inside]).max(initial=0.0) < 1e-12
+        outside = (u < -1) | (u > Ny) | (v < -1) | (v > Nx)
+        assert np.abs(g[n3 - 1][np.broadcast_to(outside, g[n3 - 1].shape)]).max(initial=0.0) == 0.0
+
+
+def check_volume_reduces_to_image(O):
+    """A volume that is nonzero only in its centre row (y = 0) holds one
+    image I[z, x]; its transform is the 2D funnel transform of I on the same
+    padded length, the same for every m2 (the y' resampling of a delta at
+    y = 0 is a delta at y' = 0).  Likewise the centre column (x = 0) with
+    the 2D transform of I[z, y] for every m1.  Ties the x and y axes each to
+    the pinned 2D transform."""
+    rng = np.random.default_rng(104)
+    Nz, Ny, Nx = 10, 8, 12
+    Nzp = O.padded_depth(Nz, Ny, Nx)
+    I = rng.random((Nz, Nx))
+    vol = np.zeros((Nz, Ny, Nx))
+    vol[:, Ny // 2, :] = I
+    P3 = O.forward_volume(vol)
+    P2 = O.forward_regular(I, Nzp)
+    assert np.abs(P3 - P2[:, None, :]).max() <= 1e-11 * np.abs(P2).max()
+    J = rng.random((Nz, Ny))
+    vol = np.zeros((Nz, Ny, Nx))
+    vol[:, :, Nx // 2] = J
+    P3 = O.forward_volume(vol)
+    P2 = O.forward_regular(J, Nzp)
+    assert np.abs(P3 - P2[:, :, None]).max() <= 1e-11 * np.abs(P2).max()
+
+
+def check_volume_plane_to_point(O):
+    """Eq. A.9: a thin sheet slice = a col + b row + c focuses within one cell
+    of (z = c_centred, m2 = -b Ny/2, m1 = -a Nx/2), in a volume whose three
+    sides differ."""
+    rng = np.random.default_rng(105)
+    Nz, Ny, Nx = 24, 16, 20
+    Nzp = O.padded_depth(Nz, Ny, Nx)
+    for trial in range(6):
+        a, b = float(rng.uniform(-0.85, 0.85)), float(rng.uniform(-0.85, 0.85))
+        zc = float(rng.uniform(0.35 * Nz, 0.65 * Nz))
+        sh = synth.Sheet(a, b, zc - a * Nx / 2 - b * Ny / 2, 1.0)
+        vol = synth.render_volume(Nz, Ny, Nx, [sh], 0.0, rng, bg=0.0).astype(np.float64)
+        B = np.abs(O.forward_volume(vol))
+        got = np.unravel_index(np.argmax(B), B.shape)
+        want = expected_cell_volume(sh, Nz, Ny, Nx, Nzp)
+        for g, w, n in zip(got, want, B.shape):
+            assert torus_dist(int(g), w, n) <= 1, (trial, got, want)
+
+
+def check_volume_point_to_plane(O):
+    """Eq. A.5 with omega_max = pi: one bright voxel at centred (x0, y0, z0)
+    becomes the plane z = z0 + 2 x0 m1 / Nx + 2 y0 m2 / Ny.  As for the 2D
+    point -> line pin, linear resampling of a delta aliases, so the pin is a
+    |P|^2-weighted least-squares plane through the cells within +-6 slices of
+    the prediction over the central half of both bin ranges: intercept within
+    half a cell, both slopes within 15 %."""
+    Nz, Ny, Nx = 32, 32, 40
+    Nzp = O.padded_depth(Nz, Ny, Nx)
+    for (x0, y0, z0) in [(8, 5, 3), (-10, 6, -4), (12, -7, 0), (-6, -9, 5)]:
+        vol = np.zeros((Nz, Ny, Nx))
+        vol[z0 + Nz // 2, y0 + Ny // 2, x0 + Nx // 2] = 1.0
+        B2 = O.forward_volume(vol) ** 2
+        rows, w = [], []
+        for r in range(Ny):
+            m2 = r - Ny // 2
+            if abs(m2) > Ny // 4:
+                continue
+            for c in range(Nx):
+                m1 = c - Nx // 2
+                if abs(m1) > Nx // 4:
+                    continue
+                pred = z0 + 2.0 * x0 * m1 / Nx + 2.0 * y0 * m2 / Ny
+                for z in range(int(np.floor(pred)) - 6, int(np.floor(pred)) + 8):
+                    rows.append((1.0, m1, m2, z))
+                    w.append(B2[(z + Nzp // 2) % Nzp, r, c])
+        X = np.asarray(rows)
+        sw = np.sqrt(np.asarray(w))
+        coef = np.linalg.lstsq(X[:, :3] * sw[:, None], X[:, 3] * sw, rcond=None)[0]
+        assert abs(coef[0] - z0) <= 0.5, (x0, y0, z0, coef)
+        assert abs(coef[1] - 2.0 * x0 / Nx) <= 0.15 * abs(2.0 * x0 / Nx), (x0, y0, z0, coef)
+        assert abs(coef[2] - 2.0 * y0 / Ny) <= 0.15 * abs(2.0 * y0 / Ny), (x0, y0, z0, coef)
+
+
+def check_volume_shift_equivariance(O):
+    """Moving the content d slices along z inside the frame rolls the
+    parameter volume by d slices exactly."""
+    rng = np.random.default_rng(106)
+    Nz, Ny, Nx, d = 16, 6, 8, 3
+    vol = np.zeros((Nz, Ny, Nx))
+    vol[2:Nz - 6] = rng.random((Nz - 8, Ny, Nx))
+    P0 = O.forward_volume(vol)
+    P1 = O.forward_volume(np.roll(vol, d, axis=0))
+    assert np.abs(P1 - np.roll(P0, d, axis=0)).max() <= 1e-12 * np.abs(P0).max()
+
+
+def check_volume_lines_sampler(O):
+    """The per-line evaluation equals the whole transform on its lines."""
+    rng = np.random.default_rng(107)
+    vol = rng.random((10, 6, 8))
+    lines = [(0, 0), (3, 5), (5, 7), (2, 1)]
+    P = O.forward_volume(vol, 30)
+    L = O.forward_volume_lines(vol, lines, 30)
+    for k, (r, c) in enumerate(lines):
+        assert np.abs(L[:, k] - P[:, r, c]).max() <= 1e-12 * np.abs(P).max()
+
+
+def local_max_peaks_volume(B, K, T, radius=1, mask=None, wrap=True):
+    """Brute force in 3D, as local_max_peaks."""
+    nz, ny, nx = B.shape
+    out = []
+    for z in range(nz):
+        for r in range(ny):
+            for c in range(nx):
+                if B[z, r, c] < T or (mask is not None and mask[z, r, c]):
+                    continue
+                me = (z * ny + r) * nx + c
+                ok = True
+                for dz in range(-radius, radius + 1):
+                    for dr in range(-radius, radius + 1):
+                        for dc in range(-radius, radius + 1):
+                            zz, rr, cc = z + dz, r + dr, c + dc
+                            if wrap:
+                                zz, rr, cc = zz % nz, rr % ny, cc % nx
+                            elif not (0 <= zz < nz and 0 <= rr < ny and 0 <= cc < nx):
+                                continue
+                            q = (zz * ny + rr) * nx + cc
+                            if q == me:
+                                continue
+                            if B[zz, rr, cc] > B[z, r, c] or (B[zz, rr, cc] == B[z, r, c] and q < me):
+                                ok = False
+                if ok:
+                    out.append(me)
+    out.sort(key=lambda i: (-B.flat[i], i))
+    return out[:K]
+
+
+def check_volume_peaks_equal_local_maxima(O, trials=80):
+    """The list algorithm in 3D equals 'first K local maxima under the total
+    order', on tie-heavy volumes, with and without wrapping."""
+    rng = np.random.default_rng(108)
+    for t in range(trials):
+        shape = tuple(int(rng.integers(3, 7)) for _ in range(3))
+        B = rng.integers(0, 4, size=shape).astype(np.float64)
+        K = int(rng.integers(1, 8))
+        T = float(rng.integers(0, 3))
+        radius = int(rng.integers(1, 3))
+        wrap = bool(rng.integers(2))
+        mask = rng.random(shape) < 0.15
+        got = O.peaks_list_volume(B, K, T, radius, mask, wrap)
+        want = local_max_peaks_volume(B, K, T, radius, mask, wrap)
+        assert got == want, (t, got, want)
+
+
+def check_plane_params_round_trip(O):
+    """A cell's plane (Eq. A.9 read backwards), rendered as a thin sheet and
+    transformed, focuses back on that cell."""
+    rng = np.random.default_rng(109)
+    Nz, Ny, Nx = 20, 16, 24
+    Nzp = O.padded_depth(Nz, Ny, Nx)
+    for _ in range(5):
+        cell = (int(rng.integers(Nzp // 2 - 4, Nzp // 2 + 5)), int(rng.integers(Ny // 2 - 6, Ny // 2 + 7)),
+                int(rng.integers(Nx // 2 - 9, Nx // 2 + 10)))
+        a, b, c = O.plane_params(*cell, Nz, Ny, Nx, Nzp)
+        vol = synth.render_volume(Nz, Ny, Nx, [synth.Sheet(a, b, c, 1.0)], 0.0, rng, bg=0.0).astype(np.float64)
+        B = np.abs(O.forward_volume(vol))
+        got = tuple(int(v) for v in np.unravel_index(np.argmax(B), B.shape))
+        assert got == cell, (cell, got, (a, b, c))

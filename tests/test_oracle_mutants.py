@@ -192,7 +192,8 @@ def _refine_descends(g, Np, row, col, iters=4):
 
 _REAL = {name: getattr(O, name) for name in
          ("nvmt", "spectrum_y", "dft_x", "idft_y", "expand", "adjoint_regular", "peaks_list",
-          "nvmt_dft_chirpz", "_nvmt_dft_chirpz_transpose")}
+          "nvmt_dft_chirpz", "_nvmt_dft_chirpz_transpose",
+          "nvmt_bilinear", "spectrum_z", "dft_xy", "plane_params")}
 
 ALL_CHECKS = [
     pins.check_spectrum_is_library_fft, pins.check_xdft_is_library_fft,
@@ -209,7 +210,95 @@ ALL_CHECKS = [
     pins.check_verify_ridge_and_step, pins.check_verify_fig9_wrap,
     pins.check_continuous_plane_cells, pins.check_continuous_plane_derivatives,
     pins.check_refine_line_to_point, pins.check_refine_stationary,
+    pins.check_spectrum_z_is_library_fft, pins.check_dft_xy_is_library_fft2,
+    pins.check_idft_z_is_library_ifft, pins.check_bilinear_exact_on_bilinear_slices,
+    pins.check_volume_reduces_to_image, pins.check_volume_plane_to_point,
+    pins.check_volume_point_to_plane, pins.check_volume_shift_equivariance,
+    pins.check_volume_peaks_equal_local_maxima, pins.check_plane_params_round_trip,
 ]
+
+def _bilinear_y_weights_swapped(S, Nzp, n3_first=1):
+    h, Ny, Nx = S.shape
+    yp = np.arange(Ny, dtype=np.int64) - Ny // 2
+    xp = np.arange(Nx, dtype=np.int64) - Nx // 2
+    g = np.zeros_like(S)
+    for k in range(h):
+        n3 = n3_first + k
+        f = S[k]
+        den = 2 * n3
+        nu, nv = yp * Nzp + Ny * n3, xp * Nzp + Nx * n3
+        i0, j0 = nu // den, nv // den
+        tu = 1.0 - ((nu - i0 * den) / den)[:, None]        # weights of the two rows exchanged
+        tv = ((nv - j0 * den) / den)[None, :]
+        I0, J0 = i0[:, None], j0[None, :]
+
+        def tap(ii, jj):
+            inside = (ii >= 0) & (ii < Ny) & (jj >= 0) & (jj < Nx)
+            return np.where(inside, f[np.clip(ii, 0, Ny - 1), np.clip(jj, 0, Nx - 1)], 0.0)
+
+        g[k] = ((1 - tu) * (1 - tv) * tap(I0, J0) + (1 - tu) * tv * tap(I0, J0 + 1)
+                + tu * (1 - tv) * tap(I0 + 1, J0) + tu * tv * tap(I0 + 1, J0 + 1))
+    return g
+
+
+def _bilinear_omega_max_2pi(S, Nzp, n3_first=1):
+    return _REAL["nvmt_bilinear"](S, 2 * Nzp, n3_first)
+
+
+def _spectrum_z_conj(vol_pad):
+    return np.conj(_REAL["spectrum_z"](vol_pad))
+
+
+def _dft_xy_m2_sign(g):
+    Ny = g.shape[1]
+    y = np.arange(Ny) - Ny // 2
+    flip = np.exp(4j * np.pi * np.outer(y, y) / Ny)     # exp(-j..) -> exp(+j..) along y'
+    return np.matmul(flip, _REAL["dft_xy"](g))
+
+
+def _idft_z_no_conj(G, Nzp):
+    h, Ny, Nx = G.shape
+    full = np.zeros((Nzp, Ny, Nx), complex)
+    n3 = np.arange(1, h + 1)
+    full[n3 + Nzp // 2] = G
+    full[-n3 + Nzp // 2] = G
+    z = np.arange(Nzp) - Nzp // 2
+    return np.tensordot(np.exp(2j * np.pi * np.outer(z, z) / Nzp), full, axes=(1, 0)).real / Nzp
+
+
+def _expand_volume_front(vol, Nzp):
+    out = np.zeros((Nzp,) + vol.shape[1:])
+    out[:vol.shape[0]] = vol
+    return out
+
+
+def _peaks_volume_no_z(B, K, T, radius=1, mask=None, wrap=True):
+    # neighbourhood taken within each slice only
+    nz, ny, nx = B.shape
+    flat = B.ravel()
+    order = np.lexsort((np.arange(flat.size), -flat))
+    visited = np.zeros(B.shape, bool)
+    off = np.arange(-radius, radius + 1)
+    out = []
+    for idx in order:
+        if flat[idx] < T:
+            break
+        z, rem = divmod(int(idx), ny * nx)
+        r, c = divmod(rem, nx)
+        rr, cc = (r + off) % ny, (c + off) % nx
+        seen = visited[z][np.ix_(rr, cc)].any()
+        visited[z, r, c] = True
+        if not seen and not (mask is not None and mask[z, r, c]):
+            out.append(int(idx))
+            if len(out) == K:
+                break
+    return out
+
+
+def _plane_params_b_sign(z, row, col, Nz, Ny, Nx, Nzp):
+    a, b, c = _REAL["plane_params"](z, row, col, Nz, Ny, Nx, Nzp)
+    return a, -b, c + b * Ny
+
 
 MUTANTS = {
     "lerp weights swapped": ("nvmt", _swap_lerp_weights),
@@ -231,6 +320,14 @@ MUTANTS = {
     "plane between cells with the slope exponent conjugated": ("continuous_plane", _cont_plane_m_conj),
     "plane between cells with the intercept derivative's sign flipped": ("continuous_plane", _cont_plane_dy_sign),
     "refinement stepping downhill": ("refine_peak", _refine_descends),
+    "bilinear weights exchanged along y": ("nvmt_bilinear", _bilinear_y_weights_swapped),
+    "volume NVMT with omega_max read as 2 pi": ("nvmt_bilinear", _bilinear_omega_max_2pi),
+    "z DFT exponent sign": ("spectrum_z", _spectrum_z_conj),
+    "m2 DFT exponent sign": ("dft_xy", _dft_xy_m2_sign),
+    "z completion without conjugate": ("idft_z", _idft_z_no_conj),
+    "volume expansion not centred": ("expand_volume", _expand_volume_front),
+    "3D peaks without the z neighbours": ("peaks_list_volume", _peaks_volume_no_z),
+    "plane parameter b with the wrong sign": ("plane_params", _plane_params_b_sign),
 }
 
 

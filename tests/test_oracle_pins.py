@@ -39,6 +39,17 @@ CHECKS = [
     pins.check_continuous_plane_derivatives,
     pins.check_refine_line_to_point,
     pins.check_refine_stationary,
+    pins.check_spectrum_z_is_library_fft,
+    pins.check_dft_xy_is_library_fft2,
+    pins.check_idft_z_is_library_ifft,
+    pins.check_bilinear_exact_on_bilinear_slices,
+    pins.check_volume_reduces_to_image,
+    pins.check_volume_plane_to_point,
+    pins.check_volume_point_to_plane,
+    pins.check_volume_shift_equivariance,
+    pins.check_volume_lines_sampler,
+    pins.check_volume_peaks_equal_local_maxima,
+    pins.check_plane_params_round_trip,
 ]
 
 
