@@ -346,6 +346,99 @@ ft_status funnel_plan_variants(const ft_plan* plan, int32_t* variants, int32_t c
 /* Force one role's variant; FT_ERR_INVALID_ARG if that shape has no kernel. */
 ft_status funnel_plan_set_variant(ft_plan* plan, int32_t role, int32_t variant);
 
+/* ---- volumes (App. A) ----
+ * The funnel transform of a volume V[z][y][x] maps planes to points: the
+ * same steps with one more axis,
+ *
+ *   S(x, y, w3)   = DFT_z of the expanded volume            (Eq. A.2)
+ *   g(x', y', w3) = S(x'/s, y'/s, w3), s = w3/w_max         (Eq. A.3; bilinear
+ *                                                            interpolation)
+ *   G(w1, w2, w3) = 2D DFT over x', y'                      (Eq. A.4)
+ *   P(w1, w2, z)  = inverse DFT_w3 of G                     (Eqs. A.5, A.9)
+ *
+ * Conventions (as for images, per axis):
+ *   - volume V[s][r][c]: Nz slices (depth, z), Ny rows (y), Nx columns (x),
+ *     row-major float32, all even and >= 4; volumes of a batch are
+ *     contiguous (stride Nz*Ny*Nx).
+ *   - the z axis is expanded to Nzp = Nz + Ny + Nx (or padded_len) with
+ *     (Nzp-Nz)/2 zero slices in front: a plane with |a|, |b| <= 1 moves by at
+ *     most (Nx+Ny)/2 slices over the volume.  Centred z, y, x.
+ *   - w_max = pi, s = 2 n3 / Nzp for n3 = 1 .. Nzp/2-1; DC and Nyquist zero.
+ *   - bilinear NVMT: linear interpolation along x and along y, each as the
+ *     image NVMT (exact integer floors of (x' Nzp + Nx n3)/(2 n3) and of
+ *     (y' Nzp + Ny n3)/(2 n3)), the weights multiplied.
+ *   - parameter volume: float32 P[Nzp][Ny][Nx], slice = z + Nzp/2,
+ *     row = m2 + Ny/2, column = m1 + Nx/2.  A plane slice = a*col + b*row + c
+ *     (voxel indices, |a|, |b| <= 1) focuses at m1 = -a Nx/2, m2 = -b Ny/2,
+ *     z = c + a Nx/2 + b Ny/2 - Nz/2.  A plane steeper than that in x or y
+ *     is found in the volume with its axes permuted (the 3D counterpart of
+ *     the inverse space).
+ * Sizes with kernels: Nzp a compiled column length (as Np for images), Nx a
+ * compiled row length (as M), Ny in {32, 48, 64, 96, 128, 160, 192, 256,
+ * 320, 384, 512, 640, 768, 1024}; Nzp*Ny*Nx*4 bytes below 2 GiB.  FP32.
+ * Ownership, threading and errors as for image plans. */
+typedef struct ft_volume_plan ft_volume_plan;
+
+typedef struct {
+  int32_t batch;       /* number of volumes, >= 1 */
+  int32_t depth;       /* Nz, slices */
+  int32_t rows;        /* Ny */
+  int32_t cols;        /* Nx */
+  int32_t padded_len;  /* Nzp; 0 means Nz+Ny+Nx; else even and >= Nz+Ny+Nx */
+  uint32_t flags;      /* 0 */
+} ft_volume_desc;
+
+ft_status funnel_volume_plan_create(const ft_volume_desc* desc, ft_volume_plan** out);
+void funnel_volume_plan_destroy(ft_volume_plan* plan);
+ft_status funnel_volume_padded_len(const ft_volume_plan* plan, int32_t* nzp);
+/* Bytes of device workspace funnel_volume_forward needs: the half spectrum,
+ * (Nzp/2-1) * Ny * Nx complex values per volume. */
+ft_status funnel_volume_workspace_size(const ft_volume_plan* plan, size_t* bytes);
+
+/* Forward transform of a batch of volumes (App. A, Eqs. A.2-A.5).
+ *   volumes : device, float32 [batch][Nz][Ny][Nx]
+ *   params  : device, float32 [batch][Nzp][Ny][Nx], overwritten with P
+ *   ws      : device workspace of at least funnel_volume_workspace_size bytes
+ * Four launches: DFT along z, NVMT + DFT along x', NVMT + DFT along y'
+ * (bilinear interpolation is the product of the two linear ones), inverse
+ * DFT along w3 with 1/Nzp. */
+ft_status funnel_volume_forward(const ft_volume_plan* plan, const float* volumes, float* params, void* ws,
+                                size_t ws_bytes, void* stream);
+
+/* One detected 3D peak and its plane (Eq. A.9 read backwards). */
+typedef struct {
+  int32_t volume;
+  int32_t z;           /* parameter-volume slice (intercept bin) */
+  int32_t row;         /* m2 + Ny/2 */
+  int32_t col;         /* m1 + Nx/2 */
+  float value;         /* |P| */
+  float a, b, c;       /* the plane slice = a*col + b*row + c, voxel indices */
+} ft_plane_peak;
+
+ft_status funnel_volume_peaks_workspace_size(const ft_volume_plan* plan, int32_t K, size_t* bytes);
+/* The list rule of Sec. 4.4 in three dimensions: the first K cells, in the
+ * order (|P| descending, linear index ascending), that precede every other
+ * cell of their (2*radius+1)^3 neighbourhood (toroidal, or clamped with
+ * FT_PEAK_CLAMP_BORDER), have |P| >= threshold and are not cells where the
+ * expansion's faces focus (slices within 2 of z = -+Nz/2 at m1, m2 in
+ * {-1, 0, 1}) unless FT_PEAK_KEEP_PAD_BOUNDARY is set.
+ *   K       : 1 .. 256;  radius : 1 or 2
+ *   peaks   : device, ft_plane_peak [batch][K] (entries beyond the count unspecified)
+ *   n_found : device, int32 [batch] */
+ft_status funnel_volume_peaks(const ft_volume_plan* plan, const float* params, int32_t K, float threshold,
+                              int32_t radius, uint32_t flags, ft_plane_peak* peaks, int32_t* n_found, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* Tile variants of the four launches (roles 0 z DFT, 1 x' pass, 2 y' pass,
+ * 3 inverse w3 DFT), autotuning over the whole forward chain, and kernel
+ * timing, as for image plans. */
+ft_status funnel_volume_variants(const ft_volume_plan* plan, int32_t* variants, int32_t cap);
+ft_status funnel_volume_set_variant(ft_volume_plan* plan, int32_t role, int32_t variant);
+ft_status funnel_volume_autotune(ft_volume_plan* plan, void* stream, ft_tune_result* out, int32_t cap, int32_t* n);
+ft_status funnel_volume_profile_enable(ft_volume_plan* plan, int32_t max_records);
+ft_status funnel_volume_profile_read(ft_volume_plan* plan, ft_kernel_time* out, int32_t cap, int32_t* n);
+ft_status funnel_volume_profile_disable(ft_volume_plan* plan);
+
 /* Human-readable name of a status. */
 const char* funnel_status_string(ft_status status);
 

@@ -154,8 +154,8 @@ double role_bytes(const ft_plan* p, const FtClass& c, int r) {
 }
 
 // Run one launch, bracketed by events when the plan is being profiled.
-template <class Fn>
-hipError_t timed(const ft_plan* p, hipStream_t s, const std::string& name, double bytes, Fn&& fn) {
+template <class Plan, class Fn>
+hipError_t timed(const Plan* p, hipStream_t s, const std::string& name, double bytes, Fn&& fn) {
   FtProfiler* pr = p->prof;
   if (!pr || pr->used >= pr->cap) return fn();
   const int i = pr->used++;
@@ -216,7 +216,7 @@ hipError_t run_role(const ft_plan* p, const FtClass& c, int r, int v, const floa
     case FB_REG:
       if (p->chirpz)
         return funnel::launch_chirp(M, v, false, Sr, h, sr, p->chirp + c.cz_m, p->chirp + c.wz_m, p->tw + c.tw_2m, B, s);
-      return funnel::launch_row(M, v, p->prec, false, Sr, Np, h, sr, p->tw + c.tw_m, B, s);
+      return funnel::launch_row(M, v, p->prec, false, Sr, Np, h, 1, sr, p->tw + c.tw_m, B, s);
     case FC_REG:
       return funnel::launch_c2r(Np, v, p->prec, false, false, Sr, dst, M, 0, Np, sr_to_pl, 1.0f / Np, tw_np, B, s);
     // forward, inverse space: the same on the transposed image (rows read directly)
@@ -224,7 +224,7 @@ hipError_t run_role(const ft_plan* p, const FtClass& c, int r, int v, const floa
     case FB_INV:
       if (p->chirpz)
         return funnel::launch_chirp(N, v, false, Si, h, si, p->chirp + c.cz_n, p->chirp + c.wz_n, p->tw + c.tw_2n, B, s);
-      return funnel::launch_row(N, v, p->prec, false, Si, Np, h, si, p->tw + c.tw_n, B, s);
+      return funnel::launch_row(N, v, p->prec, false, Si, Np, h, 1, si, p->tw + c.tw_n, B, s);
     case FC_INV:
       return funnel::launch_c2r(Np, v, p->prec, false, false, Si, dst + c.off_inv_plane, N, 0, Np, si_to_pl, 1.0f / Np,
                                 tw_np, B, s);
@@ -234,7 +234,7 @@ hipError_t run_role(const ft_plan* p, const FtClass& c, int r, int v, const floa
     case AB_REG:
       if (p->chirpz)
         return funnel::launch_chirp(M, v, true, Sr, h, sr, p->chirp + c.cz_m, p->chirp + c.wz_m, p->tw + c.tw_2m, B, s);
-      return funnel::launch_row(M, v, p->prec, true, Sr, Np, h, sr, p->tw + c.tw_m, B, s);
+      return funnel::launch_row(M, v, p->prec, true, Sr, Np, h, 1, sr, p->tw + c.tw_m, B, s);
     // (the inverse space runs first; the regular space's columns add to its result)
     case AA_REG:
       return funnel::launch_c2r(Np, v, p->prec, false, inv, Sr, dst, M, (Np - N) / 2, N, sr_to_img, 0.5f, tw_np, B,
@@ -246,7 +246,7 @@ hipError_t run_role(const ft_plan* p, const FtClass& c, int r, int v, const floa
     case AB_INV:
       if (p->chirpz)
         return funnel::launch_chirp(N, v, true, Si, h, si, p->chirp + c.cz_n, p->chirp + c.wz_n, p->tw + c.tw_2n, B, s);
-      return funnel::launch_row(N, v, p->prec, true, Si, Np, h, si, p->tw + c.tw_n, B, s);
+      return funnel::launch_row(N, v, p->prec, true, Si, Np, h, 1, si, p->tw + c.tw_n, B, s);
     case AA_INV:
       return funnel::launch_c2r(Np, v, p->prec, true, false, Si, dst, N, (Np - M) / 2, M, si_to_img, 0.5f, tw_np, B,
                                 s);
@@ -827,12 +827,13 @@ ft_status funnel_plan_classes(const ft_plan* p, int32_t* n) {
 
 // ------------------------------------------------------------------ timing
 
-ft_status funnel_profile_enable(ft_plan* p, int32_t max_records) {
-  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+}  // extern "C"
+
+namespace {
+
+ft_status profiler_enable(FtProfiler*& slot, int32_t max_records) {
   if (max_records < 1 || max_records > (1 << 20))
     return fail(FT_ERR_INVALID_ARG, "max_records must be in 1..2^20 (got %d)", max_records);
-  ft_status st = check_device(p);
-  if (st != FT_OK) return st;
   FtProfiler* pr = new (std::nothrow) FtProfiler();
   if (!pr) return fail(FT_ERR_OUT_OF_MEMORY, "host allocation failed");
   pr->cap = max_records;
@@ -848,14 +849,13 @@ ft_status funnel_profile_enable(ft_plan* p, int32_t max_records) {
       return fail(FT_ERR_HIP, "hipEventCreate failed");
     }
   }
-  free_profiler(p->prof);
-  p->prof = pr;
+  free_profiler(slot);
+  slot = pr;
   return ok();
 }
 
-ft_status funnel_profile_read(ft_plan* p, ft_kernel_time* out, int32_t cap, int32_t* n) {
-  if (!p || !out || !n || cap < 1) return fail(FT_ERR_INVALID_ARG, "plan, out and n must be non-NULL, cap >= 1");
-  FtProfiler* pr = p->prof;
+ft_status profiler_read(FtProfiler* pr, ft_kernel_time* out, int32_t cap, int32_t* n) {
+  if (!out || !n || cap < 1) return fail(FT_ERR_INVALID_ARG, "out and n must be non-NULL, cap >= 1");
   *n = 0;
   if (!pr) return fail(FT_ERR_INVALID_ARG, "profiling is not enabled on this plan");
   int cnt = 0;
@@ -880,6 +880,22 @@ ft_status funnel_profile_read(ft_plan* p, ft_kernel_time* out, int32_t cap, int3
   pr->used = 0;
   *n = cnt;
   return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+ft_status funnel_profile_enable(ft_plan* p, int32_t max_records) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  ft_status st = check_device(p);
+  if (st != FT_OK) return st;
+  return profiler_enable(p->prof, max_records);
+}
+
+ft_status funnel_profile_read(ft_plan* p, ft_kernel_time* out, int32_t cap, int32_t* n) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  return profiler_read(p->prof, out, cap, n);
 }
 
 ft_status funnel_profile_disable(ft_plan* p) {
@@ -1057,6 +1073,365 @@ ft_status funnel_refine(const ft_plan* p, const float* images, const ft_peak* pe
                                      sp[i].W, i, ns, K, B, n_found, state, Abuf, c.Np, sp[i].space_id, c.N, c.M,
                                      it == iters ? 1 : 0, out, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return ok();
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ volumes (App. A)
+//
+// Four launches per forward: A (DFT along z of the Ny*Nx lines, the image
+// pass A), Bx (NVMT along x + DFT along x', the image row pass with Ny rows
+// per ratio), By (NVMT along y + DFT along y', funnel_volume.hip) and C
+// (Hermitian inverse DFT along omega_3, the image pass C), all in place on
+// one half spectrum of h * Ny * Nx complex values per volume.
+
+enum VRole { VA, VBX, VBY, VC, NVROLES };
+static const char* const kVRoleName[NVROLES] = {"volume.A", "volume.Bx", "volume.By", "volume.C"};
+
+struct ft_volume_plan {
+  FtProfiler* prof = nullptr;
+  int device = 0;
+  int batch = 0, Nz = 0, Ny = 0, Nx = 0, Nzp = 0, h = 0;
+  float2* tw = nullptr;                   // twiddles of lengths Nzp, Nx, Ny
+  size_t tw_z = 0, tw_x = 0, tw_y = 0;
+  long long vol_elems = 0, param_elems = 0, spec_elems = 0;   // per volume
+  size_t ws_bytes = 0;
+  int variant[NVROLES] = {};
+};
+
+namespace {
+
+unsigned vrole_mask(const ft_volume_plan* p, int r) {
+  switch (r) {
+    case VA: case VC: return funnel::col_variant_mask(p->Nzp, FT_PREC_FP32);
+    case VBX: return funnel::row_variant_mask(p->Nx, FT_PREC_FP32);
+    case VBY: return funnel::ycol_variant_mask(p->Ny);
+  }
+  return 0;
+}
+
+// algorithmic HBM bytes of one launch (each input read once, each output written once)
+double vrole_bytes(const ft_volume_plan* p, int r) {
+  const double B = p->batch, lines = (double)p->Ny * p->Nx, h = p->h;
+  switch (r) {
+    case VA: return B * (4.0 * p->Nz * lines + 8.0 * h * lines);
+    case VBX: case VBY: return B * 16.0 * h * lines;
+    case VC: return B * (8.0 * h * lines + 4.0 * p->Nzp * lines);
+  }
+  return 0.0;
+}
+
+hipError_t run_vrole(const ft_volume_plan* p, int r, int v, const float* src, float* dst, char* w, hipStream_t s) {
+  float2* S = reinterpret_cast<float2*>(w);
+  const int lines = p->Ny * p->Nx;
+  const long long ss = p->spec_elems;
+  using funnel::ImgMap;
+  switch (r) {
+    case VA:
+      return funnel::launch_r2c(p->Nzp, v, FT_PREC_FP32, false, src, S, lines, p->Nz, (p->Nzp - p->Nz) / 2,
+                                ImgMap{p->vol_elems, ss, nullptr, nullptr}, 1.0f, p->tw + p->tw_z, p->batch, s);
+    case VBX:
+      return funnel::launch_row(p->Nx, v, FT_PREC_FP32, false, S, p->Nzp, p->h, p->Ny, ss, p->tw + p->tw_x, p->batch,
+                                s);
+    case VBY: return funnel::launch_ycol(p->Ny, v, S, p->Nzp, p->h, p->Nx, ss, p->tw + p->tw_y, p->batch, s);
+    case VC:
+      return funnel::launch_c2r(p->Nzp, v, FT_PREC_FP32, false, false, S, dst, lines, 0, p->Nzp,
+                                ImgMap{ss, p->param_elems, nullptr, nullptr}, 1.0f / p->Nzp, p->tw + p->tw_z,
+                                p->batch, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t enqueue_volume(const ft_volume_plan* p, const float* src, float* dst, char* w, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < NVROLES && e == hipSuccess; ++r)
+    e = timed(p, s, kVRoleName[r], vrole_bytes(p, r), [&] { return run_vrole(p, r, p->variant[r], src, dst, w, s); });
+  return e;
+}
+
+ft_status check_volume_device(const ft_volume_plan* p) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(FT_ERR_NO_DEVICE, "no HIP device");
+  if (dev != p->device) return fail(FT_ERR_NO_DEVICE, "plan was created on device %d, current is %d", p->device, dev);
+  return FT_OK;
+}
+
+void free_volume_plan(ft_volume_plan* p) {
+  if (!p) return;
+  free_profiler(p->prof);
+  if (p->tw) (void)hipFree(p->tw);
+  delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+ft_status funnel_volume_plan_create(const ft_volume_desc* d, ft_volume_plan** out) {
+  if (!d || !out) return fail(FT_ERR_INVALID_ARG, "desc and out must be non-NULL");
+  *out = nullptr;
+  if (d->batch < 1) return fail(FT_ERR_INVALID_ARG, "batch must be >= 1 (got %d)", d->batch);
+  if (d->depth < 4 || d->rows < 4 || d->cols < 4 || (d->depth & 1) || (d->rows & 1) || (d->cols & 1))
+    return fail(FT_ERR_INVALID_ARG, "depth, rows and cols must be even and >= 4 (got %d x %d x %d)", d->depth,
+                d->rows, d->cols);
+  if (d->flags != 0) return fail(FT_ERR_INVALID_ARG, "unknown volume plan flags 0x%x", d->flags);
+  const long long Nz = d->depth, Ny = d->rows, Nx = d->cols;
+  const long long Nzp = d->padded_len == 0 ? Nz + Ny + Nx : d->padded_len;
+  if (d->padded_len < 0 || (Nzp & 1) || Nzp < Nz + Ny + Nx)
+    return fail(FT_ERR_INVALID_ARG, "padded_len must be 0 or even and >= depth+rows+cols (got %d)", d->padded_len);
+  if (Nzp > (1 << 20) || Nx > (1 << 20) || Ny > (1 << 20))
+    return fail(FT_ERR_UNSUPPORTED_SIZE, "transform length too large");
+  if (!funnel::length_supported((int)Nzp) || !funnel::col_variant_mask((int)Nzp, FT_PREC_FP32))
+    return fail(FT_ERR_UNSUPPORTED_SIZE, "no kernel for padded depth %lld", Nzp);
+  if (!funnel::length_supported((int)Nx) || !funnel::row_variant_mask((int)Nx, FT_PREC_FP32))
+    return fail(FT_ERR_UNSUPPORTED_SIZE, "no kernel for row length %lld (volume width)", Nx);
+  if (!funnel::ycol_variant_mask((int)Ny))
+    return fail(FT_ERR_UNSUPPORTED_SIZE, "no y' pass kernel for column length %lld (volume height)", Ny);
+  // the kernels address one volume's parameter volume and half spectrum with
+  // 32-bit byte offsets
+  if (Nzp * Ny * Nx * 4 >= (1ll << 31))
+    return fail(FT_ERR_UNSUPPORTED_SIZE, "per-volume parameter volumes of %lld x %lld x %lld exceed 2 GiB", Nzp, Ny,
+                Nx);
+
+  ft_volume_plan* p = new (std::nothrow) ft_volume_plan();
+  if (!p) return fail(FT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  p->batch = d->batch;
+  p->Nz = (int)Nz;
+  p->Ny = (int)Ny;
+  p->Nx = (int)Nx;
+  p->Nzp = (int)Nzp;
+  p->h = (int)Nzp / 2 - 1;
+  p->vol_elems = Nz * Ny * Nx;
+  p->param_elems = Nzp * Ny * Nx;
+  p->spec_elems = (long long)p->h * Ny * Nx;
+  p->ws_bytes = align_up((size_t)p->batch * p->spec_elems * sizeof(float2), 256);
+  for (int r = 0; r < NVROLES; ++r) {
+    const unsigned m = vrole_mask(p, r);
+    for (int v = 0; v < funnel::kMaxVariants; ++v)
+      if (m & (1u << v)) {
+        p->variant[r] = v;
+        break;
+      }
+  }
+  // the y' pass: prefer a tile whose column count divides the width
+  for (int v = 0; v < funnel::kMaxVariants; ++v)
+    if ((vrole_mask(p, VBY) & (1u << v)) && p->Nx % funnel::ycol_lines(v) == 0) {
+      p->variant[VBY] = v;
+      break;
+    }
+
+  int dev = -1, ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    free_volume_plan(p);
+    return fail(FT_ERR_NO_DEVICE, "no HIP device");
+  }
+  if (hipGetDevice(&dev) != hipSuccess) {
+    free_volume_plan(p);
+    return fail(FT_ERR_NO_DEVICE, "no current HIP device");
+  }
+  p->device = dev;
+  p->tw_z = 0;
+  p->tw_x = (size_t)Nzp;
+  p->tw_y = p->tw_x + (size_t)Nx;
+  const size_t ntw = p->tw_y + (size_t)Ny;
+  std::vector<float2> host(ntw);
+  fill_twiddles(host.data() + p->tw_z, (int)Nzp);
+  fill_twiddles(host.data() + p->tw_x, (int)Nx);
+  fill_twiddles(host.data() + p->tw_y, (int)Ny);
+  hipError_t e = hipMalloc(&p->tw, ntw * sizeof(float2));
+  if (e != hipSuccess) {
+    p->tw = nullptr;
+    free_volume_plan(p);
+    return fail(FT_ERR_OUT_OF_MEMORY, "hipMalloc of twiddle tables: %s", hipGetErrorString(e));
+  }
+  e = hipMemcpy(p->tw, host.data(), ntw * sizeof(float2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_volume_plan(p);
+    return hip_fail(e, "hipMemcpy of twiddle tables");
+  }
+  *out = p;
+  return ok();
+}
+
+void funnel_volume_plan_destroy(ft_volume_plan* p) { free_volume_plan(p); }
+
+ft_status funnel_volume_padded_len(const ft_volume_plan* p, int32_t* nzp) {
+  if (!p || !nzp) return fail(FT_ERR_INVALID_ARG, "plan and nzp must be non-NULL");
+  *nzp = p->Nzp;
+  return ok();
+}
+
+ft_status funnel_volume_workspace_size(const ft_volume_plan* p, size_t* bytes) {
+  if (!p || !bytes) return fail(FT_ERR_INVALID_ARG, "plan and bytes must be non-NULL");
+  *bytes = p->ws_bytes;
+  return ok();
+}
+
+ft_status funnel_volume_forward(const ft_volume_plan* p, const float* volumes, float* params, void* ws,
+                                size_t ws_bytes, void* stream) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  if (!volumes || !params || !ws) return fail(FT_ERR_INVALID_ARG, "volumes, params and workspace must be non-NULL");
+  if (!aligned16(volumes) || !aligned16(params) || !aligned16(ws))
+    return fail(FT_ERR_MISALIGNED, "device pointers must be 16-byte aligned");
+  if (ws_bytes < p->ws_bytes)
+    return fail(FT_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, p->ws_bytes);
+  ft_status st = check_volume_device(p);
+  if (st != FT_OK) return st;
+  const hipError_t e = enqueue_volume(p, volumes, params, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return ok();
+}
+
+ft_status funnel_volume_peaks_workspace_size(const ft_volume_plan* p, int32_t K, size_t* bytes) {
+  if (!p || !bytes) return fail(FT_ERR_INVALID_ARG, "plan and bytes must be non-NULL");
+  if (K < 1 || K > 256) return fail(FT_ERR_INVALID_ARG, "K must be in 1..256 (got %d)", K);
+  *bytes = funnel::vpeaks_workspace_bytes(p->batch, funnel::vpeaks_tiles(p->Nzp, p->Ny, p->Nx), K);
+  return ok();
+}
+
+ft_status funnel_volume_peaks(const ft_volume_plan* p, const float* params, int32_t K, float threshold, int32_t radius,
+                              uint32_t flags, ft_plane_peak* peaks, int32_t* n_found, void* ws, size_t ws_bytes,
+                              void* stream) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  if (!params || !peaks || !n_found || !ws)
+    return fail(FT_ERR_INVALID_ARG, "params, peaks, n_found and workspace must be non-NULL");
+  if (K < 1 || K > 256) return fail(FT_ERR_INVALID_ARG, "K must be in 1..256 (got %d)", K);
+  if (radius < 1 || radius > 2) return fail(FT_ERR_INVALID_ARG, "radius must be 1 or 2 (got %d)", radius);
+  if (std::isnan(threshold)) return fail(FT_ERR_INVALID_ARG, "threshold is NaN");
+  if (flags & ~(uint32_t)(FT_PEAK_CLAMP_BORDER | FT_PEAK_KEEP_PAD_BOUNDARY))
+    return fail(FT_ERR_INVALID_ARG, "unknown peak flags 0x%x", flags);
+  if (!aligned16(params) || !aligned16(peaks) || !aligned16(n_found) || !aligned16(ws))
+    return fail(FT_ERR_MISALIGNED, "device pointers must be 16-byte aligned");
+  size_t need = 0;
+  ft_status st = funnel_volume_peaks_workspace_size(p, K, &need);
+  if (st != FT_OK) return st;
+  if (ws_bytes < need) return fail(FT_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  st = check_volume_device(p);
+  if (st != FT_OK) return st;
+  const hipError_t e = funnel::launch_vpeaks(params, p->param_elems, p->batch, p->Nzp, p->Ny, p->Nx, p->Nz, K,
+                                             threshold, radius, (flags & FT_PEAK_CLAMP_BORDER) ? 0 : 1,
+                                             (flags & FT_PEAK_KEEP_PAD_BOUNDARY) ? 1 : 0, peaks, n_found, ws,
+                                             static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return ok();
+}
+
+ft_status funnel_volume_variants(const ft_volume_plan* p, int32_t* variants, int32_t cap) {
+  if (!p || !variants || cap < 1) return fail(FT_ERR_INVALID_ARG, "plan and variants must be non-NULL, cap >= 1");
+  for (int r = 0; r < NVROLES && r < cap; ++r) variants[r] = p->variant[r];
+  return ok();
+}
+
+ft_status funnel_volume_set_variant(ft_volume_plan* p, int32_t role, int32_t variant) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  if (role < 0 || role >= NVROLES) return fail(FT_ERR_INVALID_ARG, "role must be in 0..3 (got %d)", role);
+  if (variant < 0 || variant >= funnel::kMaxVariants || !(vrole_mask(p, role) & (1u << variant)))
+    return fail(FT_ERR_INVALID_ARG, "%s has no kernel for variant %d", kVRoleName[role], variant);
+  p->variant[role] = variant;
+  return ok();
+}
+
+ft_status funnel_volume_autotune(ft_volume_plan* p, void* stream, ft_tune_result* out, int32_t cap, int32_t* n) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  if (cap > 0 && !out) return fail(FT_ERR_INVALID_ARG, "out is NULL with cap > 0");
+  ft_status st = check_volume_device(p);
+  if (st != FT_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t vb = (size_t)p->batch * p->vol_elems * sizeof(float);
+  const size_t pb = (size_t)p->batch * p->param_elems * sizeof(float);
+  void *a = nullptr, *b = nullptr, *w = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&] {
+    (void)hipStreamSynchronize(s);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (w) (void)hipFree(w);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (hipMalloc(&a, vb) != hipSuccess || hipMalloc(&b, pb) != hipSuccess || hipMalloc(&w, p->ws_bytes) != hipSuccess) {
+    cleanup();
+    return fail(FT_ERR_OUT_OF_MEMORY, "autotune scratch allocation failed");
+  }
+  if (hipMemsetAsync(a, 0, vb, s) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(FT_ERR_HIP, "autotune set-up failed");
+  }
+  FtProfiler* saved = p->prof;
+  p->prof = nullptr;
+  int count = 0;
+  // coordinate descent over the four launches, two sweeps, each variant
+  // scored by the whole forward chain (best of 5 after one warm-up)
+  for (int sweep = 0; sweep < 2; ++sweep)
+    for (int r = 0; r < NVROLES; ++r) {
+      const unsigned mask = vrole_mask(p, r);
+      float best = 1e30f, first_ms = -1.f;
+      int best_v = p->variant[r], tried = 0;
+      for (int v = 0; v < funnel::kMaxVariants; ++v) {
+        if (!(mask & (1u << v))) continue;
+        const int keep = p->variant[r];
+        p->variant[r] = v;
+        float ms_min = 1e30f;
+        hipError_t e = hipSuccess;
+        for (int rep = 0; rep < 6 && e == hipSuccess; ++rep) {
+          e = hipEventRecord(e0, s);
+          if (e == hipSuccess)
+            e = enqueue_volume(p, static_cast<float*>(a), static_cast<float*>(b), static_cast<char*>(w), s);
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e == hipSuccess && rep > 0 && ms < ms_min) ms_min = ms;
+        }
+        p->variant[r] = keep;
+        if (e != hipSuccess) {
+          p->prof = saved;
+          cleanup();
+          return hip_fail(e, "autotune launch");
+        }
+        if (v == keep) first_ms = ms_min;
+        ++tried;
+        if (ms_min < best) {
+          best = ms_min;
+          best_v = v;
+        }
+      }
+      p->variant[r] = best_v;
+      if (sweep == 0) continue;
+      if (count < cap) {
+        std::memset(&out[count], 0, sizeof(ft_tune_result));
+        std::snprintf(out[count].name, sizeof(out[count].name), "%s", kVRoleName[r]);
+        out[count].variant = best_v;
+        out[count].n_tried = tried;
+        out[count].ms = best;
+        out[count].ms_default = first_ms;
+      }
+      ++count;
+    }
+  p->prof = saved;
+  cleanup();
+  if (n) *n = count < cap ? count : cap;
+  return ok();
+}
+
+ft_status funnel_volume_profile_enable(ft_volume_plan* p, int32_t max_records) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  ft_status st = check_volume_device(p);
+  if (st != FT_OK) return st;
+  return profiler_enable(p->prof, max_records);
+}
+
+ft_status funnel_volume_profile_read(ft_volume_plan* p, ft_kernel_time* out, int32_t cap, int32_t* n) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  return profiler_read(p->prof, out, cap, n);
+}
+
+ft_status funnel_volume_profile_disable(ft_volume_plan* p) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  free_profiler(p->prof);
+  p->prof = nullptr;
   return ok();
 }
 

@@ -41,8 +41,9 @@ hipError_t launch_r2c(int L, int variant, int prec, bool trans, const float* in,
 hipError_t launch_c2r(int L, int variant, int prec, bool trans, bool accum, const float2* in, float* out, int nlines, int r0,
                       int nout, ImgMap map, float scale, const float2* tw, int batch, hipStream_t s);
 
-// per frequency row: NVMT gather + DFT along x' (forward) or its transpose (adjoint), in place
-hipError_t launch_row(int M, int variant, int prec, bool adj, float2* data, int Lp, int h, long long img_stride, const float2* tw,
+// per frequency row (rpf data rows each, sharing that row's ratio s): NVMT
+// gather + DFT along x' (forward) or its transpose (adjoint), in place
+hipError_t launch_row(int M, int variant, int prec, bool adj, float2* data, int Lp, int h, int rpf, long long img_stride, const float2* tw,
                       int batch, hipStream_t s);
 
 // per frequency row: band-limited (chirp-z) NVMT fused with the DFT along x'
@@ -70,6 +71,22 @@ hipError_t launch_refine_init(const ft_peak* peaks, const int32_t* n_found, int 
 hipError_t launch_refine_iter(const float2* g, long long img_stride, int h, int W, int s, int ns, int K, int batch,
                               const int32_t* n_found, void* state, float2* A, int Np, int space_id, int N, int M,
                               int final, ft_refined* out, hipStream_t st);
+
+// Volumes (App. A).  The y' pass: per slice n3 (h of them, ratio 2 n3 / Lz)
+// and column of data [h][L][nx] (per volume, vol_stride complex apart),
+// linear-interpolation gather along y fused with the centred DFT along y', in
+// place.  ycol_lines: columns per block of a variant.
+unsigned ycol_variant_mask(int L);
+int ycol_lines(int variant);
+hipError_t launch_ycol(int L, int variant, float2* data, int Lz, int h, int nx, long long vol_stride,
+                       const float2* tw, int batch, hipStream_t s);
+// 3D peaks of the parameter volumes [batch][nz][ny][nx] (stride floats apart);
+// zimg: depth of the transformed volume (the faces of its expansion)
+int vpeaks_tiles(int nz, int ny, int nx);
+size_t vpeaks_workspace_bytes(int nvol, int tiles, int K);
+hipError_t launch_vpeaks(const float* params, long long stride, int batch, int nz, int ny, int nx, int zimg, int K,
+                         float thr, int radius, int wrap, int keep_border, ft_plane_peak* peaks, int32_t* n_found,
+                         void* ws, hipStream_t s);
 
 size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K);
 int peaks_tiles(int rows, int cols);

@@ -19,7 +19,7 @@ template <int L, int PREC>
 hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0,
                         int nout, ImgMap map, float scale, const float2* tw, int batch, hipStream_t s);
 template <int M, int PREC>
-hipError_t launch_row_t(int variant, bool adj, float2* data, int Lp, int h, long long img_stride,
+hipError_t launch_row_t(int variant, bool adj, float2* data, int Lp, int h, int rpf, long long img_stride,
                         const float2* tw, int batch, hipStream_t s);
 
 // lengths with split-precision kernels
@@ -118,11 +118,11 @@ hipError_t launch_c2r(int L, int variant, int prec, bool trans, bool accum, cons
   }
 }
 
-hipError_t launch_row(int M, int variant, int prec, bool adj, float2* data, int Lp, int h, long long img_stride,
+hipError_t launch_row(int M, int variant, int prec, bool adj, float2* data, int Lp, int h, int rpf, long long img_stride,
                       const float2* tw, int batch, hipStream_t s) {
   if (prec == kPrecFP32) {
     switch (M) {
-#define CASE(n) case n: return launch_row_t<n, kPrecFP32>(variant, adj, data, Lp, h, img_stride, tw, batch, s);
+#define CASE(n) case n: return launch_row_t<n, kPrecFP32>(variant, adj, data, Lp, h, rpf, img_stride, tw, batch, s);
       FUNNEL_LENGTHS(CASE)
 #undef CASE
       default: return hipErrorInvalidValue;
@@ -132,8 +132,8 @@ hipError_t launch_row(int M, int variant, int prec, bool adj, float2* data, int 
 #define CASE(n)                                                                                        \
   case n:                                                                                              \
     return prec == kPrecBF16x3                                                                         \
-               ? launch_row_t<n, kPrecBF16x3>(variant, adj, data, Lp, h, img_stride, tw, batch, s)     \
-               : launch_row_t<n, kPrecFP16x3>(variant, adj, data, Lp, h, img_stride, tw, batch, s);
+               ? launch_row_t<n, kPrecBF16x3>(variant, adj, data, Lp, h, rpf, img_stride, tw, batch, s)     \
+               : launch_row_t<n, kPrecFP16x3>(variant, adj, data, Lp, h, rpf, img_stride, tw, batch, s);
     FUNNEL_MFMA_LENGTHS(CASE)
 #undef CASE
     default: return hipErrorInvalidValue;

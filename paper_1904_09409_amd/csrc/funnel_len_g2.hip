@@ -10,7 +10,7 @@ namespace funnel {
                                       const float2*, int, hipStream_t);                               \
   template hipError_t launch_c2r_t<n, kPrecFP32>(int, bool, bool, const float2*, float*, int, int, int, ImgMap, float,  \
                                       const float2*, int, hipStream_t);                    \
-  template hipError_t launch_row_t<n, kPrecFP32>(int, bool, float2*, int, int, long long, const float2*, int, hipStream_t);
+  template hipError_t launch_row_t<n, kPrecFP32>(int, bool, float2*, int, int, int, long long, const float2*, int, hipStream_t);
 FUNNEL_LENGTHS_G2(INST)
 #undef INST
 }  // namespace funnel

@@ -201,7 +201,9 @@ __global__ void __launch_bounds__((ColCfg<L, V>::THREADS))
 
 // ------------------------------------------------------------------ pass B and its adjoint
 //
-// data: complex [h][M], row n2-1 holds frequency row n2 (in-place).
+// data: complex [h * rpf][M], rows (n2-1) rpf .. n2 rpf - 1 hold frequency row
+// n2 (rpf = 1 for images; rpf > 1 for the rows of a volume's slices, which
+// share their slice's ratio), in place.
 // Forward: g[x'] = (1-t) f[i0] + t f[i0+1] with i0 = floor((x' Lp + M n2)/(2 n2)),
 //          then G[m1] = sum_x' g[x'] e^{-i 2 pi m1 x'/M} over centred x', m1.
 // Adjoint: dg[x'] = sum_m1 dG[m1] e^{+i 2 pi m1 x'/M}, then
@@ -210,7 +212,8 @@ __global__ void __launch_bounds__((ColCfg<L, V>::THREADS))
 //          sampling ratio 2 n2 / Lp is below 1).
 template <int M, bool ADJ, int V>
 __global__ void __launch_bounds__((RowCfg<M, V>::THREADS))
-    k_row_nvmt(float2* __restrict__ data, int Lp, int h, long long img_stride, const float2* __restrict__ tw) {
+    k_row_nvmt(float2* __restrict__ data, int Lp, int h, int rpf, long long img_stride,
+               const float2* __restrict__ tw) {
   using Cfg = RowCfg<M, V>;
   constexpr int P = Cfg::P, ROWS = Cfg::ROWS;
   using Lay = LayRow<ROWS, M>;
@@ -218,15 +221,16 @@ __global__ void __launch_bounds__((RowCfg<M, V>::THREADS))
 
   const int tid = threadIdx.x;
   const int row = tid / P, t = tid % P;
-  const int n2 = blockIdx.x * ROWS + row + 1;
-  const bool active = n2 <= h;
+  const int gr = blockIdx.x * ROWS + row;   // data row; frequency row n2 = gr / rpf + 1
+  const int n2 = gr / rpf + 1;
+  const bool active = gr < h * rpf;
   float2* base = data + (long long)blockIdx.y * img_stride;
 
   for (int e = tid; e < ROWS * M; e += Cfg::THREADS) {
     const int rr = e / M, i = e % M;
-    const int n2r = blockIdx.x * ROWS + rr + 1;
+    const int grr = blockIdx.x * ROWS + rr;
     float2 v = make_float2(0.f, 0.f);
-    if (n2r <= h) v = base[(long long)(n2r - 1) * M + i];
+    if (grr < h * rpf) v = base[(long long)grr * M + i];
     if (ADJ && (i & 1)) v = make_float2(-v.x, -v.y);
     lds[Lay::addr(rr, i)] = v;
   }
@@ -249,7 +253,7 @@ __global__ void __launch_bounds__((RowCfg<M, V>::THREADS))
     auto ls = [&](int p, float2 v) {
       if (!active) return;
       if ((p + M / 2) & 1) v = make_float2(-v.x, -v.y);
-      base[(long long)(n2 - 1) * M + p] = v;
+      base[(long long)gr * M + p] = v;
     };
     Fft<M, P, false, Lay>::run(row, t, lds, tw, fl, ls);
   } else {
@@ -281,7 +285,7 @@ __global__ void __launch_bounds__((RowCfg<M, V>::THREADS))
         acc.x += w * g.x;
         acc.y += w * g.y;
       }
-      base[(long long)(n2 - 1) * M + i] = acc;
+      base[(long long)gr * M + i] = acc;
     }
   }
 }
@@ -627,7 +631,8 @@ constexpr int kRowVariants = 4;
 
 template <int M, int E_, int TPB, bool ADJ, int PREC>
 __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
-    k_row_fast(float2* __restrict__ data, int Lp, int h, long long img_stride, const float2* __restrict__ tw) {
+    k_row_fast(float2* __restrict__ data, int Lp, int h, int rpf, long long img_stride,
+               const float2* __restrict__ tw) {
   using Cfg = RowFastCfg<M, E_, TPB>;
   constexpr int P = Cfg::P, ROWS = Cfg::ROWS;
   using Eng = typename EngSel<PREC, M, P, ADJ, false, ROWS, false>::type;
@@ -643,9 +648,10 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
 
   const int tid = threadIdx.x;
   const int row = tid / P, t = tid % P;
-  const int n2 = blockIdx.x * ROWS + row + 1;
-  const bool active = n2 <= h;
-  float2* rowp = data + (long long)blockIdx.y * img_stride + (long long)(n2 - 1) * M;
+  const int gr = blockIdx.x * ROWS + row;   // data row; frequency row n2 = gr / rpf + 1
+  const int n2 = gr / rpf + 1;
+  const bool active = gr < h * rpf;
+  float2* rowp = data + (long long)blockIdx.y * img_stride + (long long)gr * M;
 
   {  // stage this thread's share of its row: ES float4 loads, all in flight
     float4 st[ES];
@@ -890,7 +896,7 @@ hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, f
 }
 
 template <int M, int PREC>
-hipError_t launch_row_t(int variant, bool adj, float2* data, int Lp, int h, long long img_stride,
+hipError_t launch_row_t(int variant, bool adj, float2* data, int Lp, int h, int rpf, long long img_stride,
                         const float2* tw, int batch, hipStream_t s) {
   switch (variant) {
 #define FUNNEL_V(i, e, tpb)                                                                                    \
@@ -898,11 +904,11 @@ hipError_t launch_row_t(int variant, bool adj, float2* data, int Lp, int h, long
     if constexpr (RowFastCfg<M, e, tpb>::valid &&                                                              \
                   (PREC == kPrecFP32 || mfma_fits(M, e, RowFastCfg<M, e, tpb>::THREADS))) {                    \
       using F = RowFastCfg<M, e, tpb>;                                                                         \
-      dim3 grid((h + F::ROWS - 1) / F::ROWS, batch), block(F::THREADS);                                        \
+      dim3 grid((h * rpf + F::ROWS - 1) / F::ROWS, batch), block(F::THREADS);                                  \
       if (adj)                                                                                                 \
-        k_row_fast<M, e, tpb, true, PREC><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);                 \
+        k_row_fast<M, e, tpb, true, PREC><<<grid, block, 0, s>>>(data, Lp, h, rpf, img_stride, tw);            \
       else                                                                                                     \
-        k_row_fast<M, e, tpb, false, PREC><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);                \
+        k_row_fast<M, e, tpb, false, PREC><<<grid, block, 0, s>>>(data, Lp, h, rpf, img_stride, tw);           \
       return hipGetLastError();                                                                                \
     }                                                                                                          \
     break;
@@ -921,11 +927,11 @@ hipError_t launch_row_t(int variant, bool adj, float2* data, int Lp, int h, long
       constexpr int V = decltype(vc)::value;
       if constexpr (RowCfg<M, V>::distinct()) {
         using Cfg = RowCfg<M, V>;
-        dim3 grid((h + Cfg::ROWS - 1) / Cfg::ROWS, batch), block(Cfg::THREADS);
+        dim3 grid((h * rpf + Cfg::ROWS - 1) / Cfg::ROWS, batch), block(Cfg::THREADS);
         if (adj)
-          k_row_nvmt<M, true, V><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
+          k_row_nvmt<M, true, V><<<grid, block, 0, s>>>(data, Lp, h, rpf, img_stride, tw);
         else
-          k_row_nvmt<M, false, V><<<grid, block, 0, s>>>(data, Lp, h, img_stride, tw);
+          k_row_nvmt<M, false, V><<<grid, block, 0, s>>>(data, Lp, h, rpf, img_stride, tw);
       }
       return hipGetLastError();
     };

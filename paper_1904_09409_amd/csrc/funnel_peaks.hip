@@ -353,6 +353,24 @@ size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K) {
   return (size_t)nplanes_total * (lists + lvl1) * (size_t)K * sizeof(uint64_t);
 }
 
+// Reduce `lists` key lists per plane to one, ping-ponging between the stage-1
+// buffer `cand` and the level-1 buffer behind it; *out: the final lists.
+static hipError_t reduce_lists(uint64_t* cand, int planes_n, int lists, int K, const uint64_t** out, hipStream_t s) {
+  const int G = merge_group(K);
+  uint64_t* bufs[2] = {cand, cand + (size_t)planes_n * lists * K};
+  int cur = 0, n = lists;
+  do {
+    const int nout = (n + G - 1) / G;
+    k_peaks_reduce<<<dim3(nout, planes_n), kMergeThreads, 0, s>>>(bufs[cur], n, bufs[1 - cur], nout, K, G);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    cur = 1 - cur;
+    n = nout;
+  } while (n > 1);
+  *out = bufs[cur];
+  return hipSuccess;
+}
+
 int peaks_tiles(int rows, int cols) { return ((rows + kTileR - 1) / kTileR) * ((cols + kTileC - 1) / kTileC); }
 
 hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int batch, int nspaces, int space0,
@@ -381,23 +399,200 @@ hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int ba
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // reduce the tile lists to one list per plane, ping-ponging between the
-  // stage-1 buffer and the level-1 buffer behind it
-  const int G = merge_group(K);
   const int planes_n = batch * nspaces;
-  const int lists = tiles * (kPeakThreads / 64);   // one list per wave of every tile
-  uint64_t* bufs[2] = {cand, cand + (size_t)planes_n * lists * K};
-  int cur = 0, n = lists;
-  do {
-    const int nout = (n + G - 1) / G;
-    k_peaks_reduce<<<dim3(nout, planes_n), kMergeThreads, 0, s>>>(bufs[cur], n, bufs[1 - cur], nout, K, G);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    cur = 1 - cur;
-    n = nout;
-  } while (n > 1);
-  k_peaks_records<<<planes_n, kMergeThreads, 0, s>>>(planes, map, gidx, g[0], g[1], nspaces, space0, K, bufs[cur],
-                                                     peaks, n_found);
+  const uint64_t* list = nullptr;
+  e = reduce_lists(cand, planes_n, tiles * (kPeakThreads / 64), K, &list, s);   // one list per wave of every tile
+  if (e != hipSuccess) return e;
+  k_peaks_records<<<planes_n, kMergeThreads, 0, s>>>(planes, map, gidx, g[0], g[1], nspaces, space0, K, list, peaks,
+                                                     n_found);
+  return hipGetLastError();
+}
+
+
+// ------------------------------------------------------------------ volumes (App. A)
+//
+// The same detector on the parameter volume of the volume transform: a cell
+// is detected when it precedes every other cell of its (2R+1)^3
+// neighbourhood (toroidal, or clamped), is >= the threshold and is not one
+// of the cells where the expansion's front and back faces focus.  Stage-1
+// tiles are 16 slices x 4 rows x 64 columns: each wave walks one row of the
+// tile (a column per lane) through the 16 slices, reading the neighbourhoods
+// from the LDS copy of the tile and its halo; stages 2 and 3 as for planes.
+constexpr int kVTileZ = 16, kVTileY = kPeakThreads / 64, kVTileX = 64;
+constexpr int kMaxVRadius = 2;
+
+struct VolGeom {
+  int nz, ny, nx;      // parameter volume: Nzp x Ny x Nx
+  int zimg;            // depth Nz of the transformed volume (its faces focus at z = -+Nz/2)
+  long long stride;    // floats per parameter volume
+};
+
+__device__ __forceinline__ bool in_face(const VolGeom& g, int z, int r, int c) {
+  const int cc = c - g.nx / 2, rr = r - g.ny / 2;
+  if (cc < -1 || cc > 1 || rr < -1 || rr > 1) return false;
+  const int y = z - g.nz / 2, e0 = -g.zimg / 2, e1 = g.zimg / 2;
+  return (y >= e0 - 2 && y <= e0 + 1) || (y >= e1 - 2 && y <= e1 + 1);
+}
+
+__device__ __forceinline__ int wrap_index(int i, int n) { return ((i % n) + n) % n; }
+
+template <int RADIUS>
+__global__ void __launch_bounds__(kPeakThreads)
+    k_vpeaks_tile(const float* __restrict__ params, VolGeom g, int K, float thr, int wrap, int keep_border,
+                  uint64_t* __restrict__ out) {
+  constexpr int R = RADIUS;
+  constexpr int HZ = kVTileZ + 2 * R, HY = kVTileY + 2 * R, HX = kVTileX + 2 * R;
+  constexpr int NW = kPeakThreads / 64;
+  __shared__ float val[HZ * HY * HX];   // |P| of tile and halo; -1: no cell (clamped border)
+  const int vol = blockIdx.y, tile = blockIdx.x;
+  const float* P = params + (long long)vol * g.stride;
+  const int tx = (g.nx + kVTileX - 1) / kVTileX, ty = (g.ny + kVTileY - 1) / kVTileY;
+  const int x0 = (tile % tx) * kVTileX, y0 = ((tile / tx) % ty) * kVTileY, z0 = (tile / (tx * ty)) * kVTileZ;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint64_t* dst = out + (((long long)vol * gridDim.x + tile) * NW + wave) * K;
+
+  // stage the tile and its halo; every load of a thread is issued before the first store
+  constexpr int NH = HZ * HY * HX, NLD = (NH + kPeakThreads - 1) / kPeakThreads;
+  float ld[NLD];
+#pragma unroll
+  for (int j = 0; j < NLD; ++j) {
+    const int i = tid + kPeakThreads * j;
+    int x = x0 - R + i % HX, y = y0 - R + (i / HX) % HY, z = z0 - R + i / (HX * HY);
+    bool in = i < NH;
+    if (wrap) {
+      x = wrap_index(x, g.nx);
+      y = wrap_index(y, g.ny);
+      z = wrap_index(z, g.nz);
+    } else {
+      in = in && x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+    }
+    ld[j] = in ? fabsf(P[((long long)z * g.ny + y) * g.nx + x]) : -1.0f;
+  }
+#pragma unroll
+  for (int j = 0; j < NLD; ++j) {
+    const int i = tid + kPeakThreads * j;
+    if (NH % kPeakThreads == 0 || i < NH) val[i] = ld[j];
+  }
+  __syncthreads();
+
+  constexpr int NS = kVTileZ / 2;   // two cells adjacent along z are never both maxima
+  uint64_t mine[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) mine[j] = kNoKey;
+  const int x = x0 + lane, y = y0 + wave;
+#pragma unroll
+  for (int lz = 0; lz < kVTileZ; ++lz) {
+    const int z = z0 + lz;
+    if (z >= g.nz || y >= g.ny || x >= g.nx) continue;
+    const int c = ((lz + R) * HY + wave + R) * HX + lane + R;
+    const float v = val[c];
+    if (!(v >= thr) || (!keep_border && in_face(g, z, y, x))) continue;
+    bool gt = false, eq = false;
+#pragma unroll
+    for (int dz = -R; dz <= R; ++dz)
+#pragma unroll
+      for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx)
+          if (dz != 0 || dy != 0 || dx != 0) {
+            const float q = val[c + (dz * HY + dy) * HX + dx];
+            gt |= q > v;
+            eq |= q == v;
+          }
+    if (gt) continue;
+    const int idx = (z * g.ny + y) * g.nx + x;
+    if (eq) {   // equal neighbours (rare): the lower linear index precedes
+      bool peak = true;
+      for (int dz = -R; peak && dz <= R; ++dz)
+        for (int dy = -R; peak && dy <= R; ++dy)
+          for (int dx = -R; dx <= R; ++dx) {
+            if ((dz == 0 && dy == 0 && dx == 0) || val[c + (dz * HY + dy) * HX + dx] != v) continue;
+            const int q = (wrap_index(z + dz, g.nz) * g.ny + wrap_index(y + dy, g.ny)) * g.nx + wrap_index(x + dx, g.nx);
+            if (q < idx) { peak = false; break; }   // (equal: the cell itself, wrapped)
+          }
+      if (!peak) continue;
+    }
+    mine[lz / 2] = cell_key(v, idx);
+  }
+
+  // the wave's first K keys, as for planes
+#pragma unroll
+  for (int a = 0; a < NS - 1; ++a)
+#pragma unroll
+    for (int b = 0; b < NS - 1 - a; ++b) {
+      const uint64_t p0 = mine[b], p1 = mine[b + 1];
+      mine[b] = p0 < p1 ? p0 : p1;
+      mine[b + 1] = p0 < p1 ? p1 : p0;
+    }
+  int k = 0;
+  for (; k < K; ++k) {
+    const uint64_t m = wave_min_u64(mine[0]);
+    if (m == kNoKey) break;
+    if (lane == 0) dst[k] = m;
+    if (mine[0] == m) {
+#pragma unroll
+      for (int j = 0; j < NS - 1; ++j) mine[j] = mine[j + 1];
+      mine[NS - 1] = kNoKey;
+    }
+  }
+  for (int i = k + lane; i < K; i += 64) dst[i] = kNoKey;
+}
+
+// One sorted list of K keys per volume -> plane records and counts.
+__global__ void __launch_bounds__(kMergeThreads)
+    k_vpeaks_records(const float* __restrict__ params, VolGeom g, int K, const uint64_t* __restrict__ list,
+                     ft_plane_peak* __restrict__ peaks, int32_t* __restrict__ n_found) {
+  const int vol = blockIdx.x;
+  const float* P = params + (long long)vol * g.stride;
+  const uint64_t* keys = list + (long long)vol * K;
+  ft_plane_peak* dst = peaks + (long long)vol * K;
+  for (int i = threadIdx.x; i < K; i += kMergeThreads) {
+    if (keys[i] == kNoKey) continue;
+    const int idx = (int)(uint32_t)(keys[i] & 0xffffffffu);
+    const int z = idx / (g.ny * g.nx), rem = idx % (g.ny * g.nx);
+    const int r = rem / g.nx, c = rem % g.nx;
+    ft_plane_peak pk;
+    pk.volume = vol;
+    pk.z = z;
+    pk.row = r;
+    pk.col = c;
+    pk.value = fabsf(P[idx]);
+    pk.a = -2.0f * (float)(c - g.nx / 2) / (float)g.nx;
+    pk.b = -2.0f * (float)(r - g.ny / 2) / (float)g.ny;
+    pk.c = (float)(z - g.nz / 2) - pk.a * (float)(g.nx / 2) - pk.b * (float)(g.ny / 2) + (float)(g.zimg / 2);
+    dst[i] = pk;
+  }
+  if (threadIdx.x == 0) {
+    int count = 0;
+    while (count < K && keys[count] != kNoKey) ++count;
+    n_found[vol] = count;
+  }
+}
+
+int vpeaks_tiles(int nz, int ny, int nx) {
+  return ((nz + kVTileZ - 1) / kVTileZ) * ((ny + kVTileY - 1) / kVTileY) * ((nx + kVTileX - 1) / kVTileX);
+}
+
+size_t vpeaks_workspace_bytes(int nvol, int tiles, int K) { return peaks_workspace_bytes(nvol, tiles, K); }
+
+hipError_t launch_vpeaks(const float* params, long long stride, int batch, int nz, int ny, int nx, int zimg, int K,
+                         float thr, int radius, int wrap, int keep_border, ft_plane_peak* peaks, int32_t* n_found,
+                         void* ws, hipStream_t s) {
+  const VolGeom g{nz, ny, nx, zimg, stride};
+  const int tiles = vpeaks_tiles(nz, ny, nx);
+  uint64_t* cand = static_cast<uint64_t*>(ws);
+  dim3 grid(tiles, batch);
+  switch (radius) {
+    case 1: k_vpeaks_tile<1><<<grid, kPeakThreads, 0, s>>>(params, g, K, thr, wrap, keep_border, cand); break;
+    case 2: k_vpeaks_tile<2><<<grid, kPeakThreads, 0, s>>>(params, g, K, thr, wrap, keep_border, cand); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint64_t* list = nullptr;
+  e = reduce_lists(cand, batch, tiles * (kPeakThreads / 64), K, &list, s);
+  if (e != hipSuccess) return e;
+  k_vpeaks_records<<<batch, kMergeThreads, 0, s>>>(params, g, K, list, peaks, n_found);
   return hipGetLastError();
 }
 

@@ -51,6 +51,11 @@ class ft_image_desc(ctypes.Structure):
                 ("image_offset", ctypes.c_int64), ("plane_offset", ctypes.c_int64)]
 
 
+class ft_volume_desc(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int32), ("depth", ctypes.c_int32), ("rows", ctypes.c_int32),
+                ("cols", ctypes.c_int32), ("padded_len", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
 class ft_kernel_time(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_float),
                 ("bytes_per_launch", ctypes.c_double)]
@@ -70,6 +75,9 @@ LINE_CHECK_WORDS = LINE_CHECK_DTYPE.itemsize // 4   # 10 x 4 bytes
 REFINED_DTYPE = np.dtype([("col", np.float32), ("row", np.float32), ("value", np.float32), ("slope", np.float32),
                           ("intercept", np.float32), ("shift", np.float32)])
 REFINED_WORDS = REFINED_DTYPE.itemsize // 4   # 6 x 4 bytes
+PLANE_PEAK_DTYPE = np.dtype([("volume", np.int32), ("z", np.int32), ("row", np.int32), ("col", np.int32),
+                             ("value", np.float32), ("a", np.float32), ("b", np.float32), ("c", np.float32)])
+PLANE_PEAK_WORDS = PLANE_PEAK_DTYPE.itemsize // 4   # 8 x 4 bytes
 
 
 class FunnelError(RuntimeError):
@@ -115,6 +123,21 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "funnel_autotune": ([vp, vp, ctypes.POINTER(ft_tune_result), i32, ctypes.POINTER(i32)], ctypes.c_int),
         "funnel_plan_variants": ([vp, ctypes.POINTER(i32), i32], ctypes.c_int),
         "funnel_plan_set_variant": ([vp, i32, i32], ctypes.c_int),
+        "funnel_volume_plan_create": ([ctypes.POINTER(ft_volume_desc), ctypes.POINTER(vp)], ctypes.c_int),
+        "funnel_volume_plan_destroy": ([vp], None),
+        "funnel_volume_padded_len": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
+        "funnel_volume_workspace_size": ([vp, ctypes.POINTER(sz)], ctypes.c_int),
+        "funnel_volume_forward": ([vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "funnel_volume_peaks_workspace_size": ([vp, i32, ctypes.POINTER(sz)], ctypes.c_int),
+        "funnel_volume_peaks": ([vp, vp, i32, ctypes.c_float, i32, u32, vp, vp, vp, sz, vp], ctypes.c_int),
+        "funnel_volume_variants": ([vp, ctypes.POINTER(i32), i32], ctypes.c_int),
+        "funnel_volume_set_variant": ([vp, i32, i32], ctypes.c_int),
+        "funnel_volume_autotune": ([vp, vp, ctypes.POINTER(ft_tune_result), i32, ctypes.POINTER(i32)],
+                                   ctypes.c_int),
+        "funnel_volume_profile_enable": ([vp, i32], ctypes.c_int),
+        "funnel_volume_profile_read": ([vp, ctypes.POINTER(ft_kernel_time), i32, ctypes.POINTER(i32)],
+                                       ctypes.c_int),
+        "funnel_volume_profile_disable": ([vp], ctypes.c_int),
         "funnel_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "funnel_last_error": ([], ctypes.c_char_p),
     }
@@ -303,6 +326,87 @@ def funnel_plan_variants(plan: int) -> list[int]:
 
 def funnel_plan_set_variant(plan: int, role: int, variant: int) -> None:
     _check(load_library().funnel_plan_set_variant(plan, int(role), int(variant)), "funnel_plan_set_variant")
+
+
+# volumes (App. A)
+
+def funnel_volume_plan_create(batch: int, depth: int, rows: int, cols: int, padded_len: int = 0,
+                              flags: int = 0) -> int:
+    lib = load_library()
+    d = ft_volume_desc(batch, depth, rows, cols, padded_len, flags)
+    h = ctypes.c_void_p()
+    _check(lib.funnel_volume_plan_create(ctypes.byref(d), ctypes.byref(h)), "funnel_volume_plan_create")
+    return h.value
+
+
+def funnel_volume_plan_destroy(plan: int) -> None:
+    load_library().funnel_volume_plan_destroy(plan)
+
+
+def funnel_volume_padded_len(plan: int) -> int:
+    n = ctypes.c_int32()
+    _check(load_library().funnel_volume_padded_len(plan, ctypes.byref(n)), "funnel_volume_padded_len")
+    return n.value
+
+
+def funnel_volume_workspace_size(plan: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().funnel_volume_workspace_size(plan, ctypes.byref(n)), "funnel_volume_workspace_size")
+    return n.value
+
+
+def funnel_volume_forward(plan: int, volumes, params, ws, stream=None) -> None:
+    _check(load_library().funnel_volume_forward(plan, _ptr(volumes), _ptr(params), _ptr(ws), ws.numel(),
+                                                _stream(stream)), "funnel_volume_forward")
+
+
+def funnel_volume_peaks_workspace_size(plan: int, K: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().funnel_volume_peaks_workspace_size(plan, int(K), ctypes.byref(n)),
+           "funnel_volume_peaks_workspace_size")
+    return n.value
+
+
+def funnel_volume_peaks(plan: int, params, K: int, threshold: float, radius: int, flags: int,
+                        peaks, n_found, ws, stream=None) -> None:
+    _check(load_library().funnel_volume_peaks(plan, _ptr(params), int(K), float(threshold), int(radius), int(flags),
+                                              _ptr(peaks), _ptr(n_found), _ptr(ws), ws.numel(), _stream(stream)),
+           "funnel_volume_peaks")
+
+
+def funnel_volume_variants(plan: int) -> list[int]:
+    arr = (ctypes.c_int32 * 4)()
+    _check(load_library().funnel_volume_variants(plan, arr, 4), "funnel_volume_variants")
+    return list(arr)
+
+
+def funnel_volume_set_variant(plan: int, role: int, variant: int) -> None:
+    _check(load_library().funnel_volume_set_variant(plan, int(role), int(variant)), "funnel_volume_set_variant")
+
+
+def funnel_volume_autotune(plan: int, stream=None, cap: int = 8) -> list[dict]:
+    arr = (ft_tune_result * cap)()
+    n = ctypes.c_int32()
+    _check(load_library().funnel_volume_autotune(plan, _stream(stream), arr, cap, ctypes.byref(n)),
+           "funnel_volume_autotune")
+    return [dict(name=arr[i].name.decode(), variant=arr[i].variant, n_tried=arr[i].n_tried, ms=arr[i].ms,
+                 ms_default=arr[i].ms_default) for i in range(n.value)]
+
+
+def funnel_volume_profile_enable(plan: int, max_records: int) -> None:
+    _check(load_library().funnel_volume_profile_enable(plan, int(max_records)), "funnel_volume_profile_enable")
+
+
+def funnel_volume_profile_read(plan: int, cap: int = 16) -> list[dict]:
+    arr = (ft_kernel_time * cap)()
+    n = ctypes.c_int32()
+    _check(load_library().funnel_volume_profile_read(plan, arr, cap, ctypes.byref(n)), "funnel_volume_profile_read")
+    return [dict(name=arr[i].name.decode(), launches=arr[i].launches, total_ms=arr[i].total_ms,
+                 bytes_per_launch=arr[i].bytes_per_launch) for i in range(n.value)]
+
+
+def funnel_volume_profile_disable(plan: int) -> None:
+    _check(load_library().funnel_volume_profile_disable(plan), "funnel_volume_profile_disable")
 
 
 # ------------------------------------------------------------------ convenience layer
@@ -589,3 +693,61 @@ def funnel_transform(images, plan: FunnelPlan):
     if _FT is None:
         _FT = _autograd()
     return _FT.apply(images, plan)
+
+
+class VolumePlan:
+    """A volume plan (App. A) plus its workspace for a fixed batch shape on
+    the current device."""
+
+    def __init__(self, batch: int, depth: int, rows: int, cols: int, padded_len: int = 0):
+        import torch
+        self.batch, self.Nz, self.Ny, self.Nx = batch, depth, rows, cols
+        self.handle = funnel_volume_plan_create(batch, depth, rows, cols, padded_len)
+        self.Nzp = funnel_volume_padded_len(self.handle)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        ws = funnel_volume_workspace_size(self.handle)
+        self.ws = torch.empty(max(ws, 256), dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                funnel_volume_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def new_params(self):
+        import torch
+        return torch.empty((self.batch, self.Nzp, self.Ny, self.Nx), dtype=torch.float32, device=self.device)
+
+    def forward(self, volumes, params=None, stream=None):
+        import torch
+        if volumes.dtype != torch.float32 or not volumes.is_contiguous() or volumes.device != self.device:
+            raise ValueError("volumes must be contiguous float32 on the plan's device")
+        if tuple(volumes.shape) != (self.batch, self.Nz, self.Ny, self.Nx):
+            raise ValueError(f"volumes must have shape {(self.batch, self.Nz, self.Ny, self.Nx)}")
+        if params is None:
+            params = self.new_params()
+        funnel_volume_forward(self.handle, volumes, params, self.ws, stream)
+        return params
+
+    def peaks(self, params, K: int = 16, threshold: float = 0.0, radius: int = 1, flags: int = 0, stream=None):
+        """Returns (records int32 [B, K, 8] on the device, counts int32 [B])."""
+        import torch
+        ws = torch.empty(max(funnel_volume_peaks_workspace_size(self.handle, K), 256), dtype=torch.uint8,
+                         device=self.device)
+        rec = torch.empty((self.batch, K, PLANE_PEAK_WORDS), dtype=torch.int32, device=self.device)
+        cnt = torch.empty((self.batch,), dtype=torch.int32, device=self.device)
+        funnel_volume_peaks(self.handle, params, K, threshold, radius, flags, rec, cnt, ws, stream)
+        return rec, cnt
+
+    def autotune(self, stream=None) -> list[dict]:
+        return funnel_volume_autotune(self.handle, stream)
+
+
+def plane_peaks_to_numpy(rec, cnt):
+    """Device plane-peak records -> list (per volume) of numpy records."""
+    r = rec.cpu().numpy()
+    c = cnt.cpu().numpy()
+    return [np.ascontiguousarray(r[b, :c[b]]).view(PLANE_PEAK_DTYPE).reshape(-1) for b in range(r.shape[0])]

@@ -122,3 +122,52 @@ def test_graph_null_arguments(lib):
     assert lib.funnel_graph_create(None, 1, None, None, None, None, None, 0, ctypes.byref(h)) == F.FT_ERR_INVALID_ARG
     assert lib.funnel_graph_launch(None, None) == F.FT_ERR_INVALID_ARG
     lib.funnel_graph_destroy(None)
+
+
+def _vcreate(lib, **kw):
+    d = dict(batch=1, depth=64, rows=64, cols=64, padded_len=0, flags=0)
+    d.update(kw)
+    desc = F.ft_volume_desc(**d)
+    h = ctypes.c_void_p(4242)
+    st = lib.funnel_volume_plan_create(ctypes.byref(desc), ctypes.byref(h))
+    return st, h.value
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(batch=0), F.FT_ERR_INVALID_ARG),
+    (dict(depth=63), F.FT_ERR_INVALID_ARG),
+    (dict(rows=2), F.FT_ERR_INVALID_ARG),
+    (dict(cols=-4), F.FT_ERR_INVALID_ARG),
+    (dict(flags=1), F.FT_ERR_INVALID_ARG),
+    (dict(padded_len=190), F.FT_ERR_INVALID_ARG),       # below depth + rows + cols
+    (dict(padded_len=193), F.FT_ERR_INVALID_ARG),       # odd
+    (dict(rows=16), F.FT_ERR_UNSUPPORTED_SIZE),         # no y' pass kernel for 16
+    (dict(rows=40), F.FT_ERR_UNSUPPORTED_SIZE),         # no y' pass kernel for 40
+    (dict(depth=60, rows=64, cols=64), F.FT_ERR_UNSUPPORTED_SIZE),   # padded depth 188 has no kernel
+    (dict(depth=1024, rows=1024, cols=1024), F.FT_ERR_UNSUPPORTED_SIZE),   # parameter volume beyond 2 GiB
+])
+def test_volume_plan_create_rejects(lib, kw, code):
+    st, h = _vcreate(lib, **kw)
+    assert st == code, (st, F.last_error())
+    assert h is None
+    assert F.last_error()
+
+
+def test_volume_null_arguments(lib):
+    assert lib.funnel_volume_plan_create(None, None) == F.FT_ERR_INVALID_ARG
+    assert lib.funnel_volume_forward(None, None, None, None, 0, None) == F.FT_ERR_INVALID_ARG
+    assert lib.funnel_volume_peaks(None, None, 4, 0.0, 1, 0, None, None, None, 0, None) == F.FT_ERR_INVALID_ARG
+    n = ctypes.c_size_t()
+    assert lib.funnel_volume_workspace_size(None, ctypes.byref(n)) == F.FT_ERR_INVALID_ARG
+    assert lib.funnel_volume_peaks_workspace_size(None, 4, ctypes.byref(n)) == F.FT_ERR_INVALID_ARG
+    assert lib.funnel_volume_set_variant(None, 0, 0) == F.FT_ERR_INVALID_ARG
+    lib.funnel_volume_plan_destroy(None)
+
+
+def test_valid_volume_plan_without_device(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    for kw in (dict(), dict(depth=256, rows=256, cols=256), dict(depth=32, rows=48, cols=16, padded_len=0)):
+        st, h = _vcreate(lib, batch=2, **kw)
+        assert st == F.FT_ERR_NO_DEVICE, (kw, F.last_error())
