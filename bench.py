@@ -56,9 +56,11 @@ def main():
     ap.add_argument("--variants", type=str, default="",
                     help="comma-separated tile variant per launch (role order of funnel_plan_variants); "
                          "skips the autotuner, so counter runs time the variants a timed run picked")
-    ap.add_argument("--workload", choices=["grad", "chirpz", "ragged", "precision", "verify"], default="grad",
+    ap.add_argument("--workload", choices=["grad", "chirpz", "ragged", "precision", "verify", "volume"],
+                    default="grad",
                     help="grad: the 32 x 1024^2 batch (default); ragged: 256 images of mixed sizes; "
-                         "precision: 8 x 2048^2 in FP32 and with the split-precision matrix-core passes")
+                         "precision: 8 x 2048^2 in FP32 and with the split-precision matrix-core passes; "
+                         "volume: plane detection in 4 volumes of 256^3 (App. A)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -76,6 +78,8 @@ def main():
         return precision_bench(args, torch, F, synth)
     if args.workload == "verify":
         return verify_bench(args, torch, F, synth)
+    if args.workload == "volume":
+        return volume_bench(args, torch, F, synth)
     B, N, M = args.batch, args.size, args.size
     log(f"generating {B} synthetic {N}x{M} images")
     t0 = time.time()
@@ -376,23 +380,134 @@ def verify_bench(args, torch, F, synth, K=16, D=3):
     print(json.dumps(res), flush=True)
 
 
+def volume_bench(args, torch, F, synth, B=4, N=256, K=16):
+    """Plane detection in volumes (App. A): one step is the forward
+    transform of 4 synthetic 256^3 volumes (2-6 sheets each, noise 0.1,
+    padded depth 768) and the 3D peak detection of their parameter volumes
+    (K = 16 per volume)."""
+    log(f"generating {B} synthetic {N}^3 volumes")
+    t0 = time.time()
+    vols = synth.volume_batch(B, N, seed=0)
+    x = torch.from_numpy(np.stack([v.volume for v in vols])).cuda()
+    log(f"  {time.time() - t0:.1f} s")
+    plan = F.VolumePlan(B, N, N, N)
+    tuned = None
+    if args.variants:
+        for role, v in enumerate(int(t) for t in args.variants.split(",")):
+            F.funnel_volume_set_variant(plan.handle, role, v)
+    elif not args.no_autotune:
+        tuned = plan.autotune()   # set-up, outside the timed region
+    P = plan.new_params()
+    pk_ws = torch.empty(F.funnel_volume_peaks_workspace_size(plan.handle, K), dtype=torch.uint8, device="cuda")
+    rec = torch.empty((B, K, F.PLANE_PEAK_WORDS), dtype=torch.int32, device="cuda")
+    cnt = torch.empty((B,), dtype=torch.int32, device="cuda")
+
+    def step():
+        plan.forward(x, P)
+        F.funnel_volume_peaks(plan.handle, P, K, 0.0, 1, 0, rec, cnt, pk_ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(args.steps):
+        step()
+    e.record()
+    torch.cuda.synchronize()
+    ms_per_step = s.elapsed_time(e) / args.steps
+    mvox = B * N ** 3 / (ms_per_step * 1e-3) / 1e6
+
+    # per-kernel event times of the forward launches over a second timed region,
+    # and the peak detection's own time around its call
+    F.funnel_volume_profile_enable(plan.handle, args.steps * 8)
+    pe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for i in range(args.steps):
+        plan.forward(x, P)
+        pe[i][0].record()
+        F.funnel_volume_peaks(plan.handle, P, K, 0.0, 1, 0, rec, cnt, pk_ws)
+        pe[i][1].record()
+    torch.cuda.synchronize()
+    kernels = F.funnel_volume_profile_read(plan.handle)
+    F.funnel_volume_profile_disable(plan.handle)
+    peaks_ms = sum(a.elapsed_time(b) for a, b in pe) / args.steps
+    for k in kernels:
+        k["avg_ms"] = k["total_ms"] / k["launches"]
+        k["gbps"] = k["bytes_per_launch"] / k["avg_ms"] / 1e6
+    kernels.sort(key=lambda k: -k["total_ms"])
+    dom = kernels[0]
+    fwd_bytes = sum(k["bytes_per_launch"] * k["launches"] for k in kernels) / args.steps
+    fwd_ms = sum(k["total_ms"] for k in kernels) / args.steps
+    roles = ["volume.A", "volume.Bx", "volume.By", "volume.C"]
+    variants = F.funnel_volume_variants(plan.handle)
+    traffic = measured_traffic(dom["name"], variants[roles.index(dom["name"])], "volume")
+    copy_gbps, copy_ms = copy_bandwidth(torch)
+    found = F.plane_peaks_to_numpy(rec, cnt)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import funnel_oracle as O
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        except Exception:
+            cores = os.cpu_count() or 1
+        t0 = time.time()
+        Po = O.forward_volume(vols[0].volume.astype(np.float64))
+        O.peaks_list_volume(np.abs(Po), K, 0.0, 1, O.volume_boundary_mask(N, N, N, plan.Nzp), True)
+        dt = time.time() - t0
+        cpu = {"value": round(N ** 3 / dt / 1e6, 4), "unit": "Mvoxel/s", "cores": int(cores), "kind": "oracle",
+               "sample": f"1 of the {B} {N}^3 volumes, forward transform + 3D peaks, {dt:.1f} s"}
+
+    out = {
+        "metric": "Mvoxel/s plane detection in volumes (App. A forward transform + 3D peaks), 4 x 256^3 fp32",
+        "value": round(mvox, 1), "unit": "Mvoxel/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{B} x {N}^3 fp32 synthetic volumes (2-6 planar sheets, noise 0.1), padded depth "
+                               f"{plan.Nzp}, forward transform + 3D peaks (K={K}, radius 1)",
+                   "batch": B, "depth": N, "rows": N, "cols": N, "padded_len": plan.Nzp},
+        "roofline": {
+            "bound": "hbm", "kernel": dom["name"], "achieved": round(dom["gbps"], 1), "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": round(dom["gbps"] / HBM_PEAK_GBPS, 4),
+            "traffic": (traffic or {}).get("bytes"), "traffic_detail": traffic,
+            "forward_algorithmic_gbps": round(fwd_bytes / (fwd_ms * 1e6), 1),
+            "forward_frac": round(fwd_bytes / (fwd_ms * 1e6) / HBM_PEAK_GBPS, 4),
+            "forward_bytes": fwd_bytes, "forward_kernel_ms": round(fwd_ms, 4), "peaks_ms": round(peaks_ms, 4),
+            "copy_gbps": round(copy_gbps, 1), "copy_ms": round(copy_ms, 4),
+            "frac_of_copy": round(dom["gbps"] / copy_gbps, 4),
+        },
+        "kernels": [{"name": k["name"], "avg_ms": round(k["avg_ms"], 4), "bytes": k["bytes_per_launch"],
+                     "gbps": round(k["gbps"], 1)} for k in kernels],
+        "planes_found": [int(len(f)) for f in found],
+        "sheets": [len(v.sheets) for v in vols],
+        "cpu_baseline": cpu, "tile_variants": variants, "autotuned": tuned is not None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def kernel_sources(nvmt: str = "linear"):
     """The sources that define the kernels of the forward + adjoint passes
-    (their hash ties a committed counter table to the code it measured)."""
+    (their hash ties a committed counter table to the code it measured);
+    "volume": the four passes of the volume transform."""
     csrc = os.path.join(ROOT, "paper_1904_09409_amd", "csrc")
     names = ["fft_core.hpp", "fft_mfma.hpp", "funnel_lengths.hpp", "funnel_passes.hpp"]
     if nvmt == "chirpz":
         names.append("funnel_chirp.hip")
+    if nvmt == "volume":
+        names.append("funnel_volume.hip")
     return [os.path.join(csrc, n) for n in names]
+
+
+TRAFFIC_TABLES = {"linear": "funnel_fwd_adj_32x1024_traffic.json", "chirpz": "funnel_chirpz_32x1024_traffic.json",
+                  "volume": "funnel_volume_4x256_traffic.json"}
 
 
 def measured_traffic(launch: str, variant: int, nvmt: str = "linear"):
     """HBM bytes of one launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE table, if the kernel sources are unchanged since it was taken."""
-    import glob
     import hashlib
-    name = "funnel_fwd_adj_32x1024_traffic.json" if nvmt == "linear" else "funnel_chirpz_32x1024_traffic.json"
-    path = os.path.join(ROOT, "profiles", name)
+    path = os.path.join(ROOT, "profiles", TRAFFIC_TABLES[nvmt])
     if not os.path.exists(path):
         return None
     t = json.load(open(path))

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fft_core.hpp"
 #include "funnel_internal.hpp"
 
 namespace funnel {
@@ -415,9 +416,12 @@ hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int ba
 // is detected when it precedes every other cell of its (2R+1)^3
 // neighbourhood (toroidal, or clamped), is >= the threshold and is not one
 // of the cells where the expansion's front and back faces focus.  Stage-1
-// tiles are 16 slices x 4 rows x 64 columns: each wave walks one row of the
-// tile (a column per lane) through the 16 slices, reading the neighbourhoods
-// from the LDS copy of the tile and its halo; stages 2 and 3 as for planes.
+// tiles are 16 slices x 4 rows x 64 columns: each thread walks one column of
+// the tile through the 16 slices over the LDS copy of the tile and its halo,
+// keeping the window maxima of the last 2R+1 slices in registers, so a cell
+// costs (2R+1)^2 LDS reads; the block's local maxima are then gathered in
+// LDS and sorted once, and the block emits its first K.  Stages 2 and 3 as
+// for planes.
 constexpr int kVTileZ = 16, kVTileY = kPeakThreads / 64, kVTileX = 64;
 constexpr int kMaxVRadius = 2;
 
@@ -434,108 +438,192 @@ __device__ __forceinline__ bool in_face(const VolGeom& g, int z, int r, int c) {
   return (y >= e0 - 2 && y <= e0 + 1) || (y >= e1 - 2 && y <= e1 + 1);
 }
 
-__device__ __forceinline__ int wrap_index(int i, int n) { return ((i % n) + n) % n; }
+// Coordinate c of a halo cell on an axis of n cells: wrapped once (R < n and
+// the tile starts inside the volume, so one step reaches every cell a real
+// cell needs; cells beyond those are clamped and never used), or !in when
+// the border is clamped.
+__device__ __forceinline__ int halo_coord(int c, int n, int wrap, bool& in) {
+  if (c < 0) {
+    if (wrap) c += n;
+    else in = false;
+  } else if (c >= n) {
+    if (wrap) {
+      c -= n;
+      c = c < n ? c : n - 1;
+    } else {
+      in = false;
+    }
+  }
+  return c;
+}
 
 template <int RADIUS>
 __global__ void __launch_bounds__(kPeakThreads)
-    k_vpeaks_tile(const float* __restrict__ params, VolGeom g, int K, float thr, int wrap, int keep_border,
+    k_vpeaks_tile(const float* __restrict__ params, VolGeom g, int tiles, int K, float thr, int wrap, int keep_border,
                   uint64_t* __restrict__ out) {
   constexpr int R = RADIUS;
   constexpr int HZ = kVTileZ + 2 * R, HY = kVTileY + 2 * R, HX = kVTileX + 2 * R;
-  constexpr int NW = kPeakThreads / 64;
-  __shared__ float val[HZ * HY * HX];   // |P| of tile and halo; -1: no cell (clamped border)
-  const int vol = blockIdx.y, tile = blockIdx.x;
+  constexpr int NSLOT = kVTileZ / 2;
+  // |P| of tile and halo (-1: no cell, clamped border); afterwards the block's keys
+  __shared__ __align__(16) float val[HZ * HY * HX];
+  static_assert(HZ * HY * HX * sizeof(float) >= kPeakThreads * NSLOT * sizeof(uint64_t), "key space");
+  // consecutive tiles (x fastest, then y, then z) share halo rows: keep them on one XCD's L2
+  const int logical = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int vol = logical / tiles, tile = logical % tiles;
   const float* P = params + (long long)vol * g.stride;
   const int tx = (g.nx + kVTileX - 1) / kVTileX, ty = (g.ny + kVTileY - 1) / kVTileY;
   const int x0 = (tile % tx) * kVTileX, y0 = ((tile / tx) % ty) * kVTileY, z0 = (tile / (tx * ty)) * kVTileZ;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  uint64_t* dst = out + (((long long)vol * gridDim.x + tile) * NW + wave) * K;
 
-  // stage the tile and its halo; every load of a thread is issued before the first store
-  constexpr int NH = HZ * HY * HX, NLD = (NH + kPeakThreads - 1) / kPeakThreads;
-  float ld[NLD];
+  // stage the tile and its halo: HZ * HY rows of HX cells; every load of a
+  // thread is issued before the first store
+  auto row_base = [&](int r, bool& in) -> long long {   // offset of halo row r's cell x = 0
+    in = r < HZ * HY;
+    const int z = halo_coord(z0 - R + r / HY, g.nz, wrap, in);
+    const int y = halo_coord(y0 - R + r % HY, g.ny, wrap, in);
+    return ((long long)z * g.ny + y) * g.nx;
+  };
+  const bool vec = x0 + kVTileX <= g.nx && (g.nx & 3) == 0 && ((uintptr_t)P & 15) == 0;
+  if (vec) {
+    // the 64 interior cells of a row as 16-byte loads, the 2R side cells one by one
+    constexpr int NV = (HZ * HY * (kVTileX / 4) + kPeakThreads - 1) / kPeakThreads;
+    constexpr int NSD = (HZ * HY * 2 * R + kPeakThreads - 1) / kPeakThreads;
+    float4 lv[NV];
+    bool lin[NV];
+    float ls[NSD];
 #pragma unroll
-  for (int j = 0; j < NLD; ++j) {
-    const int i = tid + kPeakThreads * j;
-    int x = x0 - R + i % HX, y = y0 - R + (i / HX) % HY, z = z0 - R + i / (HX * HY);
-    bool in = i < NH;
-    if (wrap) {
-      x = wrap_index(x, g.nx);
-      y = wrap_index(y, g.ny);
-      z = wrap_index(z, g.nz);
-    } else {
-      in = in && x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+    for (int j = 0; j < NV; ++j) {
+      const int i = tid + kPeakThreads * j, r = i / (kVTileX / 4), q = i % (kVTileX / 4);
+      bool in;
+      const long long b = row_base(r, in);
+      lin[j] = in;
+      lv[j] = in ? *reinterpret_cast<const float4*>(P + b + x0 + 4 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    ld[j] = in ? fabsf(P[((long long)z * g.ny + y) * g.nx + x]) : -1.0f;
-  }
 #pragma unroll
-  for (int j = 0; j < NLD; ++j) {
-    const int i = tid + kPeakThreads * j;
-    if (NH % kPeakThreads == 0 || i < NH) val[i] = ld[j];
+    for (int j = 0; j < NSD; ++j) {
+      const int i = tid + kPeakThreads * j, r = i / (2 * R), e = i % (2 * R);
+      bool in;
+      const long long b = row_base(r, in);
+      const int x = halo_coord(e < R ? x0 - R + e : x0 + kVTileX + (e - R), g.nx, wrap, in);
+      ls[j] = in ? fabsf(P[b + x]) : -1.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      const int i = tid + kPeakThreads * j, r = i / (kVTileX / 4), q = i % (kVTileX / 4);
+      if ((HZ * HY * (kVTileX / 4)) % kPeakThreads != 0 && r >= HZ * HY) continue;
+      float* d = val + r * HX + R + 4 * q;
+      d[0] = lin[j] ? fabsf(lv[j].x) : -1.f;
+      d[1] = lin[j] ? fabsf(lv[j].y) : -1.f;
+      d[2] = lin[j] ? fabsf(lv[j].z) : -1.f;
+      d[3] = lin[j] ? fabsf(lv[j].w) : -1.f;
+    }
+#pragma unroll
+    for (int j = 0; j < NSD; ++j) {
+      const int i = tid + kPeakThreads * j, r = i / (2 * R), e = i % (2 * R);
+      if ((HZ * HY * 2 * R) % kPeakThreads != 0 && r >= HZ * HY) continue;
+      val[r * HX + (e < R ? e : kVTileX + e)] = ls[j];
+    }
+  } else {
+    constexpr int NH = HZ * HY * HX, NLD = (NH + kPeakThreads - 1) / kPeakThreads;
+    float ld[NLD];
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) {
+      const int i = tid + kPeakThreads * j;
+      bool in;
+      const long long b = row_base(i / HX, in);
+      const int x = halo_coord(x0 - R + i % HX, g.nx, wrap, in);
+      ld[j] = in ? fabsf(P[b + x]) : -1.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) {
+      const int i = tid + kPeakThreads * j;
+      if (NH % kPeakThreads == 0 || i < NH) val[i] = ld[j];
+    }
   }
   __syncthreads();
 
+  // Walk down the thread's column of the tile with, for the last 2R+1 halo
+  // slices, the maximum of the (2R+1)^2 window around the column (m9) and the
+  // same without the column's own cell (m8).  A cell above the maximum of
+  // its neighbourhood without itself is a peak; a cell equal to it (an exact
+  // tie, rare) goes through the index tie-break.
   constexpr int NS = kVTileZ / 2;   // two cells adjacent along z are never both maxima
   uint64_t mine[NS];
 #pragma unroll
   for (int j = 0; j < NS; ++j) mine[j] = kNoKey;
   const int x = x0 + lane, y = y0 + wave;
+  const int lc = (wave + R) * HX + lane + R;   // this column's cell in a halo slice
+  float m9[2 * R + 1], m8[2 * R + 1];
+  auto window = [&](int hz, int j) {
+    float m = -1.f;
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+      for (int dx = -R; dx <= R; ++dx)
+        if (dy != 0 || dx != 0) m = fmaxf(m, val[hz * HY * HX + lc + dy * HX + dx]);
+    m8[j] = m;
+    m9[j] = fmaxf(m, val[hz * HY * HX + lc]);
+  };
+#pragma unroll
+  for (int j = 0; j < 2 * R; ++j) window(j, j);
 #pragma unroll
   for (int lz = 0; lz < kVTileZ; ++lz) {
-    const int z = z0 + lz;
-    if (z >= g.nz || y >= g.ny || x >= g.nx) continue;
-    const int c = ((lz + R) * HY + wave + R) * HX + lane + R;
+    window(lz + 2 * R, 2 * R);
+    float m = m8[R];
+#pragma unroll
+    for (int j = 0; j <= 2 * R; ++j)
+      if (j != R) m = fmaxf(m, m9[j]);
+#pragma unroll
+    for (int j = 0; j < 2 * R; ++j) {
+      m9[j] = m9[j + 1];
+      m8[j] = m8[j + 1];
+    }
+    const int c = (lz + R) * HY * HX + lc;
     const float v = val[c];
+    const int z = z0 + lz;
+    if (!(v >= m) || z >= g.nz || y >= g.ny || x >= g.nx) continue;
     if (!(v >= thr) || (!keep_border && in_face(g, z, y, x))) continue;
-    bool gt = false, eq = false;
-#pragma unroll
-    for (int dz = -R; dz <= R; ++dz)
-#pragma unroll
-      for (int dy = -R; dy <= R; ++dy)
-#pragma unroll
-        for (int dx = -R; dx <= R; ++dx)
-          if (dz != 0 || dy != 0 || dx != 0) {
-            const float q = val[c + (dz * HY + dy) * HX + dx];
-            gt |= q > v;
-            eq |= q == v;
-          }
-    if (gt) continue;
     const int idx = (z * g.ny + y) * g.nx + x;
-    if (eq) {   // equal neighbours (rare): the lower linear index precedes
+    if (v == m) {   // an equal neighbour: the lower linear index precedes
       bool peak = true;
       for (int dz = -R; peak && dz <= R; ++dz)
         for (int dy = -R; peak && dy <= R; ++dy)
           for (int dx = -R; dx <= R; ++dx) {
             if ((dz == 0 && dy == 0 && dx == 0) || val[c + (dz * HY + dy) * HX + dx] != v) continue;
-            const int q = (wrap_index(z + dz, g.nz) * g.ny + wrap_index(y + dy, g.ny)) * g.nx + wrap_index(x + dx, g.nx);
-            if (q < idx) { peak = false; break; }   // (equal: the cell itself, wrapped)
+            int zz = z + dz, yy = y + dy, xx = x + dx;
+            zz += zz < 0 ? g.nz : (zz >= g.nz ? -g.nz : 0);
+            yy += yy < 0 ? g.ny : (yy >= g.ny ? -g.ny : 0);
+            xx += xx < 0 ? g.nx : (xx >= g.nx ? -g.nx : 0);
+            if ((zz * g.ny + yy) * g.nx + xx < idx) { peak = false; break; }   // (equal: the cell itself, wrapped)
           }
       if (!peak) continue;
     }
     mine[lz / 2] = cell_key(v, idx);
   }
 
-  // the wave's first K keys, as for planes
+  // the block's first K keys: gather every thread's keys in LDS (over the
+  // staged values, which are no longer read), sort the keys present once,
+  // keep K.  The gather order varies from run to run; the sorted result does not.
+  __shared__ int nkeys;
+  if (tid == 0) nkeys = 0;
+  __syncthreads();
+  uint64_t* keys = reinterpret_cast<uint64_t*>(val);
 #pragma unroll
-  for (int a = 0; a < NS - 1; ++a)
-#pragma unroll
-    for (int b = 0; b < NS - 1 - a; ++b) {
-      const uint64_t p0 = mine[b], p1 = mine[b + 1];
-      mine[b] = p0 < p1 ? p0 : p1;
-      mine[b + 1] = p0 < p1 ? p1 : p0;
-    }
-  int k = 0;
-  for (; k < K; ++k) {
-    const uint64_t m = wave_min_u64(mine[0]);
-    if (m == kNoKey) break;
-    if (lane == 0) dst[k] = m;
-    if (mine[0] == m) {
-#pragma unroll
-      for (int j = 0; j < NS - 1; ++j) mine[j] = mine[j + 1];
-      mine[NS - 1] = kNoKey;
-    }
+  for (int j = 0; j < NS; ++j)
+    if (mine[j] != kNoKey) keys[atomicAdd(&nkeys, 1)] = mine[j];
+  __syncthreads();
+  const int n = nkeys;
+  uint64_t* dst = out + ((long long)vol * tiles + tile) * K;
+  if (n <= K) {
+    for (int i = tid; i < K; i += kPeakThreads) dst[i] = i < n ? keys[i] : kNoKey;
+    return;
   }
-  for (int i = k + lane; i < K; i += 64) dst[i] = kNoKey;
+  int np = 1;
+  while (np < n) np <<= 1;
+  for (int i = n + tid; i < np; i += kPeakThreads) keys[i] = kNoKey;
+  __syncthreads();
+  bitonic_sort_n<kPeakThreads>(keys, np);
+  for (int i = tid; i < K; i += kPeakThreads) dst[i] = keys[i];
 }
 
 // One sorted list of K keys per volume -> plane records and counts.
@@ -573,7 +661,11 @@ int vpeaks_tiles(int nz, int ny, int nx) {
   return ((nz + kVTileZ - 1) / kVTileZ) * ((ny + kVTileY - 1) / kVTileY) * ((nx + kVTileX - 1) / kVTileX);
 }
 
-size_t vpeaks_workspace_bytes(int nvol, int tiles, int K) { return peaks_workspace_bytes(nvol, tiles, K); }
+// stage-1 lists (one per tile), then the first reduction level's lists
+size_t vpeaks_workspace_bytes(int nvol, int tiles, int K) {
+  const size_t lvl1 = ((size_t)tiles + merge_group(K) - 1) / merge_group(K);
+  return (size_t)nvol * ((size_t)tiles + lvl1) * (size_t)K * sizeof(uint64_t);
+}
 
 hipError_t launch_vpeaks(const float* params, long long stride, int batch, int nz, int ny, int nx, int zimg, int K,
                          float thr, int radius, int wrap, int keep_border, ft_plane_peak* peaks, int32_t* n_found,
@@ -583,14 +675,14 @@ hipError_t launch_vpeaks(const float* params, long long stride, int batch, int n
   uint64_t* cand = static_cast<uint64_t*>(ws);
   dim3 grid(tiles, batch);
   switch (radius) {
-    case 1: k_vpeaks_tile<1><<<grid, kPeakThreads, 0, s>>>(params, g, K, thr, wrap, keep_border, cand); break;
-    case 2: k_vpeaks_tile<2><<<grid, kPeakThreads, 0, s>>>(params, g, K, thr, wrap, keep_border, cand); break;
+    case 1: k_vpeaks_tile<1><<<grid, kPeakThreads, 0, s>>>(params, g, tiles, K, thr, wrap, keep_border, cand); break;
+    case 2: k_vpeaks_tile<2><<<grid, kPeakThreads, 0, s>>>(params, g, tiles, K, thr, wrap, keep_border, cand); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const uint64_t* list = nullptr;
-  e = reduce_lists(cand, batch, tiles * (kPeakThreads / 64), K, &list, s);
+  e = reduce_lists(cand, batch, tiles, K, &list, s);
   if (e != hipSuccess) return e;
   k_vpeaks_records<<<batch, kMergeThreads, 0, s>>>(params, g, K, list, peaks, n_found);
   return hipGetLastError();

@@ -97,14 +97,20 @@ def test_volume_workload_256():
         say(f"  volume {b}: all {len(v.sheets)} sheets among the first 16 peaks")
 
 
-@pytest.mark.parametrize("radius,flags", [(1, 0), (2, 0), (1, F.FT_PEAK_CLAMP_BORDER), (1, F.FT_PEAK_KEEP_PAD_BOUNDARY)])
-def test_volume_peaks_exact_on_shared_volume(radius, flags):
+@pytest.mark.parametrize("shape,radius,flags", [
+    ((3, 64, 32, 64), 1, 0), ((3, 64, 32, 64), 2, 0), ((3, 64, 32, 64), 1, F.FT_PEAK_CLAMP_BORDER),
+    ((3, 64, 32, 64), 1, F.FT_PEAK_KEEP_PAD_BOUNDARY),
+    ((2, 72, 48, 40), 1, 0), ((2, 72, 48, 40), 2, F.FT_PEAK_CLAMP_BORDER),   # width below one tile
+    ((2, 48, 96, 96), 1, 0), ((2, 48, 96, 96), 2, 0),                         # a full and a partial tile per row
+])
+def test_volume_peaks_exact_on_shared_volume(shape, radius, flags):
     """The GPU's 3D peak lists equal the oracle's list procedure run on the
     very same (GPU) parameter volumes, record by record; plane parameters
-    within float rounding of Eq. A.9 read backwards."""
+    within float rounding of Eq. A.9 read backwards.  Widths that fill the
+    64-column tiles take the 16-byte staging path, the others the scalar one."""
     import torch
-    B, Nz, Ny, Nx, K = 3, 64, 32, 64, 24
-    say(f"volume peaks radius {radius} flags {flags}")
+    (B, Nz, Ny, Nx), K = shape, 24
+    say(f"volume peaks {shape} radius {radius} flags {flags}")
     vols = volumes(B, Nz, Ny, Nx, 2)
     x = torch.from_numpy(np.stack([v.volume for v in vols])).cuda()
     plan = F.VolumePlan(B, Nz, Ny, Nx)
