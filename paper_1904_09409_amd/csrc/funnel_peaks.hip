@@ -416,13 +416,15 @@ hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int ba
 // is detected when it precedes every other cell of its (2R+1)^3
 // neighbourhood (toroidal, or clamped), is >= the threshold and is not one
 // of the cells where the expansion's front and back faces focus.  Stage-1
-// tiles are 16 slices x 4 rows x 64 columns: each thread walks one column of
-// the tile through the 16 slices over the LDS copy of the tile and its halo,
+// tiles are 8 slices x 4 rows x 64 columns: each thread walks one column of
+// the tile through the 8 slices over the LDS copy of the tile and its halo,
 // keeping the window maxima of the last 2R+1 slices in registers, so a cell
 // costs (2R+1)^2 LDS reads; the block's local maxima are then gathered in
-// LDS and sorted once, and the block emits its first K.  Stages 2 and 3 as
-// for planes.
-constexpr int kVTileZ = 16, kVTileY = kPeakThreads / 64, kVTileX = 64;
+// LDS and sorted once, and the block emits its first K.  Eight slices keep
+// the LDS copy at 16 KB (R = 1), so eight blocks share a compute unit and
+// hide each other's load latency (16 slices: five blocks, 25 % slower).
+// Stages 2 and 3 as for planes.
+constexpr int kVTileZ = 8, kVTileY = kPeakThreads / 64, kVTileX = 64;
 constexpr int kMaxVRadius = 2;
 
 struct VolGeom {
@@ -433,105 +435,133 @@ struct VolGeom {
 
 __device__ __forceinline__ bool in_face(const VolGeom& g, int z, int r, int c) {
   const int cc = c - g.nx / 2, rr = r - g.ny / 2;
-  if (cc < -1 || cc > 1 || rr < -1 || rr > 1) return false;
   const int y = z - g.nz / 2, e0 = -g.zimg / 2, e1 = g.zimg / 2;
-  return (y >= e0 - 2 && y <= e0 + 1) || (y >= e1 - 2 && y <= e1 + 1);
+  return (cc >= -1) & (cc <= 1) & (rr >= -1) & (rr <= 1) &
+         (((y >= e0 - 2) & (y <= e0 + 1)) | ((y >= e1 - 2) & (y <= e1 + 1)));
 }
 
 // Coordinate c of a halo cell on an axis of n cells: wrapped once (R < n and
 // the tile starts inside the volume, so one step reaches every cell a real
 // cell needs; cells beyond those are clamped and never used), or !in when
-// the border is clamped.
+// the border is clamped.  Selects only, no branches.
 __device__ __forceinline__ int halo_coord(int c, int n, int wrap, bool& in) {
-  if (c < 0) {
-    if (wrap) c += n;
-    else in = false;
-  } else if (c >= n) {
-    if (wrap) {
-      c -= n;
-      c = c < n ? c : n - 1;
-    } else {
-      in = false;
-    }
-  }
-  return c;
+  const bool lo = c < 0, hi = c >= n;
+  in = in & ((wrap != 0) | !(lo | hi));
+  const int w = lo ? c + n : (hi ? c - n : c);
+  return w < n - 1 ? (w > 0 ? w : 0) : n - 1;
 }
 
-template <int RADIUS>
-__global__ void __launch_bounds__(kPeakThreads)
-    k_vpeaks_tile(const float* __restrict__ params, VolGeom g, int tiles, int K, float thr, int wrap, int keep_border,
-                  uint64_t* __restrict__ out) {
-  constexpr int R = RADIUS;
-  constexpr int HZ = kVTileZ + 2 * R, HY = kVTileY + 2 * R, HX = kVTileX + 2 * R;
-  constexpr int NSLOT = kVTileZ / 2;
-  // |P| of tile and halo (-1: no cell, clamped border); afterwards the block's keys
-  __shared__ __align__(16) float val[HZ * HY * HX];
-  static_assert(HZ * HY * HX * sizeof(float) >= kPeakThreads * NSLOT * sizeof(uint64_t), "key space");
-  // consecutive tiles (x fastest, then y, then z) share halo rows: keep them on one XCD's L2
-  const int logical = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-  const int vol = logical / tiles, tile = logical % tiles;
-  const float* P = params + (long long)vol * g.stride;
-  const int tx = (g.nx + kVTileX - 1) / kVTileX, ty = (g.ny + kVTileY - 1) / kVTileY;
-  const int x0 = (tile % tx) * kVTileX, y0 = ((tile / tx) % ty) * kVTileY, z0 = (tile / (tx * ty)) * kVTileZ;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// Sorts 128 keys held by one wave, element lane in a and lane + 64 in b,
+// ascending: the bitonic network with lane exchanges by shuffles (no LDS, no
+// barriers).  All 64 lanes must be active.
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
 
-  // stage the tile and its halo: HZ * HY rows of HX cells; every load of a
-  // thread is issued before the first store
-  auto row_base = [&](int r, bool& in) -> long long {   // offset of halo row r's cell x = 0
-    in = r < HZ * HY;
-    const int z = halo_coord(z0 - R + r / HY, g.nz, wrap, in);
-    const int y = halo_coord(y0 - R + r % HY, g.ny, wrap, in);
-    return ((long long)z * g.ny + y) * g.nx;
+__device__ __forceinline__ void wave_sort128(uint64_t& a, uint64_t& b, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 128; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride == 64) {   // partners in the same lane (size 128: ascending throughout)
+        const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+        a = lo;
+        b = hi;
+        continue;
+      }
+      const bool low = (lane & stride) == 0;
+      const uint64_t pa = shfl_xor_u64(a, stride), pb = shfl_xor_u64(b, stride);
+      const bool asc_a = (lane & size) == 0, asc_b = ((lane + 64) & size) == 0;
+      a = (low == asc_a) ? (a < pa ? a : pa) : (a < pa ? pa : a);
+      b = (low == asc_b) ? (b < pb ? b : pb) : (b < pb ? pb : b);
+    }
+  }
+}
+
+// Tile geometry and the staging of one tile plus its halo: HZ * HY rows of
+// HX cells, |P| in LDS (-1: no cell, beyond a clamped border).
+template <int R>
+struct VTile {
+  static constexpr int HZ = kVTileZ + 2 * R, HY = kVTileY + 2 * R, HX = kVTileX + 2 * R;
+  static constexpr int NH = HZ * HY * HX;
+  static constexpr int NV = (HZ * HY * (kVTileX / 4) + kPeakThreads - 1) / kPeakThreads;   // 16-byte loads
+  static constexpr int NSD = (HZ * HY * 2 * R + kPeakThreads - 1) / kPeakThreads;         // side cells
+  static constexpr int NLD = (NH + kPeakThreads - 1) / kPeakThreads;                     // scalar path
+  static constexpr int NSLOT = kVTileZ / 2;
+  static_assert(NH * sizeof(float) >= kPeakThreads * NSLOT * sizeof(uint64_t), "key space");
+
+  struct Origin {
+    int vol, tile, x0, y0, z0;
   };
-  const bool vec = x0 + kVTileX <= g.nx && (g.nx & 3) == 0 && ((uintptr_t)P & 15) == 0;
-  if (vec) {
-    // the 64 interior cells of a row as 16-byte loads, the 2R side cells one by one
-    constexpr int NV = (HZ * HY * (kVTileX / 4) + kPeakThreads - 1) / kPeakThreads;
-    constexpr int NSD = (HZ * HY * 2 * R + kPeakThreads - 1) / kPeakThreads;
+  __device__ static Origin origin(const VolGeom& g, int tiles, int t) {
+    const int tx = (g.nx + kVTileX - 1) / kVTileX, ty = (g.ny + kVTileY - 1) / kVTileY;
+    const int tile = t % tiles;
+    return Origin{t / tiles, tile, (tile % tx) * kVTileX, ((tile / tx) % ty) * kVTileY, (tile / (tx * ty)) * kVTileZ};
+  }
+  // offset of halo row r's cell x = 0 (in: the row exists)
+  __device__ static long long row_base(const VolGeom& g, const Origin& o, int wrap, int r, bool& in) {
+    in = r < HZ * HY;
+    const int z = halo_coord(o.z0 - R + r / HY, g.nz, wrap, in);
+    const int y = halo_coord(o.y0 - R + r % HY, g.ny, wrap, in);
+    return ((long long)z * g.ny + y) * g.nx;
+  }
+
+  // 16-byte path (the tile's 64 columns inside the volume, rows 16-byte aligned)
+  struct Regs {
     float4 lv[NV];
     bool lin[NV];
     float ls[NSD];
+  };
+  __device__ static void load_vec(const float* P, const VolGeom& g, const Origin& o, int wrap, Regs& q) {
+    const int tid = threadIdx.x;
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
-      const int i = tid + kPeakThreads * j, r = i / (kVTileX / 4), q = i % (kVTileX / 4);
+      const int i = tid + kPeakThreads * j, r = i / (kVTileX / 4), c = i % (kVTileX / 4);
       bool in;
-      const long long b = row_base(r, in);
-      lin[j] = in;
-      lv[j] = in ? *reinterpret_cast<const float4*>(P + b + x0 + 4 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
+      const long long b = row_base(g, o, wrap, r, in);
+      q.lin[j] = in;
+      q.lv[j] = in ? *reinterpret_cast<const float4*>(P + b + o.x0 + 4 * c) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
     for (int j = 0; j < NSD; ++j) {
       const int i = tid + kPeakThreads * j, r = i / (2 * R), e = i % (2 * R);
       bool in;
-      const long long b = row_base(r, in);
-      const int x = halo_coord(e < R ? x0 - R + e : x0 + kVTileX + (e - R), g.nx, wrap, in);
-      ls[j] = in ? fabsf(P[b + x]) : -1.0f;
+      const long long b = row_base(g, o, wrap, r, in);
+      const int x = halo_coord(e < R ? o.x0 - R + e : o.x0 + kVTileX + (e - R), g.nx, wrap, in);
+      q.ls[j] = in ? fabsf(P[b + x]) : -1.0f;
     }
+  }
+  __device__ static void store_vec(float* val, const Regs& q) {
+    const int tid = threadIdx.x;
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
-      const int i = tid + kPeakThreads * j, r = i / (kVTileX / 4), q = i % (kVTileX / 4);
+      const int i = tid + kPeakThreads * j, r = i / (kVTileX / 4), c = i % (kVTileX / 4);
       if ((HZ * HY * (kVTileX / 4)) % kPeakThreads != 0 && r >= HZ * HY) continue;
-      float* d = val + r * HX + R + 4 * q;
-      d[0] = lin[j] ? fabsf(lv[j].x) : -1.f;
-      d[1] = lin[j] ? fabsf(lv[j].y) : -1.f;
-      d[2] = lin[j] ? fabsf(lv[j].z) : -1.f;
-      d[3] = lin[j] ? fabsf(lv[j].w) : -1.f;
+      float* d = val + r * HX + R + 4 * c;
+      d[0] = q.lin[j] ? fabsf(q.lv[j].x) : -1.f;
+      d[1] = q.lin[j] ? fabsf(q.lv[j].y) : -1.f;
+      d[2] = q.lin[j] ? fabsf(q.lv[j].z) : -1.f;
+      d[3] = q.lin[j] ? fabsf(q.lv[j].w) : -1.f;
     }
 #pragma unroll
     for (int j = 0; j < NSD; ++j) {
       const int i = tid + kPeakThreads * j, r = i / (2 * R), e = i % (2 * R);
       if ((HZ * HY * 2 * R) % kPeakThreads != 0 && r >= HZ * HY) continue;
-      val[r * HX + (e < R ? e : kVTileX + e)] = ls[j];
+      val[r * HX + (e < R ? e : kVTileX + e)] = q.ls[j];
     }
-  } else {
-    constexpr int NH = HZ * HY * HX, NLD = (NH + kPeakThreads - 1) / kPeakThreads;
+  }
+  // any tile: cell by cell, every load issued before the first store
+  __device__ static void stage_scalar(float* val, const float* P, const VolGeom& g, const Origin& o, int wrap) {
+    const int tid = threadIdx.x;
     float ld[NLD];
 #pragma unroll
     for (int j = 0; j < NLD; ++j) {
       const int i = tid + kPeakThreads * j;
       bool in;
-      const long long b = row_base(i / HX, in);
-      const int x = halo_coord(x0 - R + i % HX, g.nx, wrap, in);
+      const long long b = row_base(g, o, wrap, i / HX, in);
+      const int x = halo_coord(o.x0 - R + i % HX, g.nx, wrap, in);
       ld[j] = in ? fabsf(P[b + x]) : -1.0f;
     }
 #pragma unroll
@@ -540,18 +570,30 @@ __global__ void __launch_bounds__(kPeakThreads)
       if (NH % kPeakThreads == 0 || i < NH) val[i] = ld[j];
     }
   }
-  __syncthreads();
+};
+
+// The local maxima of a staged tile and the tile's first K keys, written to
+// dst.  Every thread of the block calls it; it leaves val overwritten (the
+// block's keys) and returns without a final barrier.
+template <int R>
+__device__ void vtile_detect(float* val, int* nkeys, const VolGeom& g, const typename VTile<R>::Origin& o, int K,
+                             float thr, int keep_border, uint64_t* dst) {
+  using T = VTile<R>;
+  constexpr int HY = T::HY, HX = T::HX, NS = T::NSLOT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int x0 = o.x0, y0 = o.y0, z0 = o.z0;
 
   // Walk down the thread's column of the tile with, for the last 2R+1 halo
   // slices, the maximum of the (2R+1)^2 window around the column (m9) and the
   // same without the column's own cell (m8).  A cell above the maximum of
   // its neighbourhood without itself is a peak; a cell equal to it (an exact
-  // tie, rare) goes through the index tie-break.
-  constexpr int NS = kVTileZ / 2;   // two cells adjacent along z are never both maxima
-  uint64_t mine[NS];
+  // tie, rare) is resolved afterwards by the index tie-break.  The verdicts
+  // are selects, so the loop has no divergent branches.
+  uint64_t mine[NS];   // two cells adjacent along z are never both maxima: slot lz / 2
 #pragma unroll
   for (int j = 0; j < NS; ++j) mine[j] = kNoKey;
   const int x = x0 + lane, y = y0 + wave;
+  const bool in_xy = (x < g.nx) & (y < g.ny);
   const int lc = (wave + R) * HX + lane + R;   // this column's cell in a halo slice
   float m9[2 * R + 1], m8[2 * R + 1];
   auto window = [&](int hz, int j) {
@@ -566,6 +608,7 @@ __global__ void __launch_bounds__(kPeakThreads)
   };
 #pragma unroll
   for (int j = 0; j < 2 * R; ++j) window(j, j);
+  uint32_t ties = 0;
 #pragma unroll
   for (int lz = 0; lz < kVTileZ; ++lz) {
     window(lz + 2 * R, 2 * R);
@@ -578,13 +621,20 @@ __global__ void __launch_bounds__(kPeakThreads)
       m9[j] = m9[j + 1];
       m8[j] = m8[j + 1];
     }
-    const int c = (lz + R) * HY * HX + lc;
-    const float v = val[c];
+    const float v = val[(lz + R) * HY * HX + lc];
     const int z = z0 + lz;
-    if (!(v >= m) || z >= g.nz || y >= g.ny || x >= g.nx) continue;
-    if (!(v >= thr) || (!keep_border && in_face(g, z, y, x))) continue;
+    const bool ok = in_xy & (z < g.nz) & (v >= thr) & ((keep_border != 0) | !in_face(g, z, y, x));
     const int idx = (z * g.ny + y) * g.nx + x;
-    if (v == m) {   // an equal neighbour: the lower linear index precedes
+    mine[lz / 2] = (ok & (v > m)) ? cell_key(v, idx) : mine[lz / 2];
+    ties |= (ok & (v == m)) ? (1u << lz) : 0u;
+  }
+  if (ties) {   // equal neighbours: the lower linear index precedes
+    uint32_t won = 0;
+    for (uint32_t t = ties; t; t &= t - 1) {
+      const int lz = __builtin_ctz(t), z = z0 + lz;
+      const int c = (lz + R) * HY * HX + lc;
+      const float v = val[c];
+      const int idx = (z * g.ny + y) * g.nx + x;
       bool peak = true;
       for (int dz = -R; peak && dz <= R; ++dz)
         for (int dy = -R; peak && dy <= R; ++dy)
@@ -596,34 +646,77 @@ __global__ void __launch_bounds__(kPeakThreads)
             xx += xx < 0 ? g.nx : (xx >= g.nx ? -g.nx : 0);
             if ((zz * g.ny + yy) * g.nx + xx < idx) { peak = false; break; }   // (equal: the cell itself, wrapped)
           }
-      if (!peak) continue;
+      won |= peak ? (1u << lz) : 0u;
     }
-    mine[lz / 2] = cell_key(v, idx);
+#pragma unroll
+    for (int lz = 0; lz < kVTileZ; ++lz)
+      if (won & (1u << lz))
+        mine[lz / 2] = cell_key(val[(lz + R) * HY * HX + lc], ((z0 + lz) * g.ny + y) * g.nx + x);
   }
 
   // the block's first K keys: gather every thread's keys in LDS (over the
-  // staged values, which are no longer read), sort the keys present once,
-  // keep K.  The gather order varies from run to run; the sorted result does not.
-  __shared__ int nkeys;
-  if (tid == 0) nkeys = 0;
+  // staged values, which are no longer read; one atomic per wave and slot,
+  // lanes placed by their rank among the wave's keys), sort the keys present
+  // once, keep K.  The gather order varies from run to run; the sorted
+  // result does not.
+  if (tid == 0) *nkeys = 0;
   __syncthreads();
   uint64_t* keys = reinterpret_cast<uint64_t*>(val);
 #pragma unroll
-  for (int j = 0; j < NS; ++j)
-    if (mine[j] != kNoKey) keys[atomicAdd(&nkeys, 1)] = mine[j];
+  for (int j = 0; j < NS; ++j) {
+    const bool have = mine[j] != kNoKey;
+    const uint64_t b = __ballot(have);
+    if (b == 0) continue;   // uniform
+    int base = 0;
+    if (lane == 0) base = atomicAdd(nkeys, (int)__popcll(b));
+    base = __shfl(base, 0, 64);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+    if (have) keys[base + rank] = mine[j];
+  }
   __syncthreads();
-  const int n = nkeys;
-  uint64_t* dst = out + ((long long)vol * tiles + tile) * K;
+  const int n = *nkeys;
   if (n <= K) {
     for (int i = tid; i < K; i += kPeakThreads) dst[i] = i < n ? keys[i] : kNoKey;
-    return;
+  } else if (n <= 128) {   // the usual case: one wave sorts in registers
+    if (wave == 0) {
+      uint64_t a = lane < n ? keys[lane] : kNoKey, b = lane + 64 < n ? keys[lane + 64] : kNoKey;
+      wave_sort128(a, b, lane);
+      if (lane < K) dst[lane] = a;
+      if (lane + 64 < K) dst[lane + 64] = b;
+      for (int i = 128 + lane; i < K; i += 64) dst[i] = kNoKey;
+    }
+  } else {
+    int np = 1;
+    while (np < n) np <<= 1;
+    for (int i = n + tid; i < np; i += kPeakThreads) keys[i] = kNoKey;
+    __syncthreads();
+    bitonic_sort_n<kPeakThreads>(keys, np);
+    for (int i = tid; i < K; i += kPeakThreads) dst[i] = keys[i];
   }
-  int np = 1;
-  while (np < n) np <<= 1;
-  for (int i = n + tid; i < np; i += kPeakThreads) keys[i] = kNoKey;
+}
+
+// One tile per block, any volume shape.  Output: one list of K keys per tile,
+// [volume][tile][K].
+template <int RADIUS>
+__global__ void __launch_bounds__(kPeakThreads)
+    k_vpeaks_tile(const float* __restrict__ params, VolGeom g, int tiles, int K, float thr, int wrap, int keep_border,
+                  uint64_t* __restrict__ out) {
+  using T = VTile<RADIUS>;
+  __shared__ __align__(16) float val[T::NH];
+  __shared__ int nkeys;
+  // consecutive tiles (x fastest, then y, then z) share halo rows: keep them on one XCD's L2
+  const int logical = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const typename T::Origin o = T::origin(g, tiles, logical);
+  const float* P = params + (long long)o.vol * g.stride;
+  if (o.x0 + kVTileX <= g.nx && (g.nx & 3) == 0 && ((uintptr_t)P & 15) == 0) {
+    typename T::Regs q;
+    T::load_vec(P, g, o, wrap, q);
+    T::store_vec(val, q);
+  } else {
+    T::stage_scalar(val, P, g, o, wrap);
+  }
   __syncthreads();
-  bitonic_sort_n<kPeakThreads>(keys, np);
-  for (int i = tid; i < K; i += kPeakThreads) dst[i] = keys[i];
+  vtile_detect<RADIUS>(val, &nkeys, g, o, K, thr, keep_border, out + ((long long)o.vol * tiles + o.tile) * K);
 }
 
 // One sorted list of K keys per volume -> plane records and counts.
@@ -673,12 +766,10 @@ hipError_t launch_vpeaks(const float* params, long long stride, int batch, int n
   const VolGeom g{nz, ny, nx, zimg, stride};
   const int tiles = vpeaks_tiles(nz, ny, nx);
   uint64_t* cand = static_cast<uint64_t*>(ws);
+  if (radius < 1 || radius > 2) return hipErrorInvalidValue;
   dim3 grid(tiles, batch);
-  switch (radius) {
-    case 1: k_vpeaks_tile<1><<<grid, kPeakThreads, 0, s>>>(params, g, tiles, K, thr, wrap, keep_border, cand); break;
-    case 2: k_vpeaks_tile<2><<<grid, kPeakThreads, 0, s>>>(params, g, tiles, K, thr, wrap, keep_border, cand); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (radius == 1) k_vpeaks_tile<1><<<grid, kPeakThreads, 0, s>>>(params, g, tiles, K, thr, wrap, keep_border, cand);
+  else k_vpeaks_tile<2><<<grid, kPeakThreads, 0, s>>>(params, g, tiles, K, thr, wrap, keep_border, cand);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const uint64_t* list = nullptr;
