@@ -14,14 +14,17 @@
 //          `radius` cells in LDS (coalesced row loads; the halo wraps, or holds
 //          a value that precedes nothing when the border is clamped), flags
 //          its local maxima (above the threshold, outside the expansion-border
-//          cells), one tile column per thread, and each wave extracts its
-//          first K keys by K rounds of a wave-wide minimum (no block-wide
-//          sort); a tile contributes one list per wave.
+//          cells), one tile column per thread, from row-window maxima kept in
+//          registers, and each wave extracts its first K keys: by one
+//          register sort of its keys when it holds at most 128 (the usual
+//          case), else by K rounds of a wave-wide minimum; a tile contributes
+//          one list per wave.
 // Stage 2: a tree of reductions: each block sorts G lists of K keys (G K <=
 //          2048) and keeps the first K, until one list per plane remains
 //          (log_G(tiles) launches, every level spread over the whole GPU).
-// Stage 3: one block per plane writes the records.  No atomics anywhere, so
-//          results are bitwise reproducible.
+// Stage 3: one block per plane writes the records.  Lists are built from
+//          sorted keys only (the volume detector's LDS gather uses atomics,
+//          but sorts what it gathered), so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -51,10 +54,9 @@ __device__ __forceinline__ uint64_t cell_key(float v, int idx) {
 
 __device__ __forceinline__ bool in_border(const PlaneGeom& g, int r, int c) {
   const int cc = c - g.cols / 2;
-  if (cc < -1 || cc > 1) return false;
   const int y = r - g.rows / 2;
   const int e0 = -g.himg / 2, e1 = g.himg / 2;
-  return (y >= e0 - 2 && y <= e0 + 1) || (y >= e1 - 2 && y <= e1 + 1);
+  return (cc >= -1) & (cc <= 1) & (((y >= e0 - 2) & (y <= e0 + 1)) | ((y >= e1 - 2) & (y <= e1 + 1)));
 }
 
 // Bitonic sort of the first n keys of a (n a power of two, <= the array).
@@ -76,6 +78,35 @@ __device__ __forceinline__ void bitonic_sort_n(uint64_t* a, int n) {
 
 // Per-image plane blocks start at map.out(img); gidx maps the launch's image
 // index to the caller's (ragged batches), NULL meaning the identity.
+// Sorts 128 keys held by one wave, element lane in a and lane + 64 in b,
+// ascending: the bitonic network with lane exchanges by shuffles (no LDS, no
+// barriers).  All 64 lanes must be active.
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ void wave_sort128(uint64_t& a, uint64_t& b, int lane) {
+#pragma unroll
+  for (int size = 2; size <= 128; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride == 64) {   // partners in the same lane (size 128: ascending throughout)
+        const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+        a = lo;
+        b = hi;
+        continue;
+      }
+      const bool low = (lane & stride) == 0;
+      const uint64_t pa = shfl_xor_u64(a, stride), pb = shfl_xor_u64(b, stride);
+      const bool asc_a = (lane & size) == 0, asc_b = ((lane + 64) & size) == 0;
+      a = (low == asc_a) ? (a < pa ? a : pa) : (a < pa ? pa : a);
+      b = (low == asc_b) ? (b < pb ? b : pb) : (b < pb ? pb : b);
+    }
+  }
+}
+
 // RADIUS is the neighbourhood radius (1..8), a template parameter so that the
 // (2 RADIUS + 1)^2 - 1 comparisons of a cell unroll and their LDS reads are
 // all in flight at once.
@@ -224,34 +255,55 @@ __global__ void __launch_bounds__(kPeakThreads)
   __syncthreads();
 
   // local maxima under the order (|P| descending, linear index ascending),
-  // down this thread's column of the tile
+  // down this thread's column of the tile.  For the last 2R+1 halo rows the
+  // thread keeps the maximum of the row's 2R+1 cells around its column (mi)
+  // and the same without the column's own cell (me), so a cell costs 2R+1
+  // LDS reads: a cell above the maximum of its neighbourhood without itself
+  // is a peak; a cell equal to it (an exact tie, rare) takes the index
+  // tie-break afterwards.  Verdicts are selects.
   constexpr int CPT = kTileR;   // cells per thread
   constexpr int NS = CPT / 2;   // two cells of a column that touch are never both maxima:
   uint64_t mine[NS];            // slot j holds the key of row 2j or 2j+1 if it is one, else kNoKey
 #pragma unroll
   for (int j = 0; j < NS; ++j) mine[j] = kNoKey;
   const int lc = tid, c = c0 + lc;
+  const bool in_c = c < g.cols;
+  float mi[2 * RADIUS + 1], me[2 * RADIUS + 1];
+  auto rowmax = [&](int hr, int j) {
+    float m = -1.f;   // -1: clamped border
+#pragma unroll
+    for (int dc = -radius; dc <= radius; ++dc)
+      if (dc != 0) m = fmaxf(m, val[hr * kHaloC + lc + radius + dc]);
+    me[j] = m;
+    mi[j] = fmaxf(m, val[hr * kHaloC + lc + radius]);
+  };
+#pragma unroll
+  for (int j = 0; j < 2 * RADIUS; ++j) rowmax(j, j);
+  uint32_t ties = 0;
 #pragma unroll
   for (int lr = 0; lr < CPT; ++lr) {
-    const int r = r0 + lr;
-    if (r >= g.rows || c >= g.cols) continue;
-    const float v = val[(lr + radius) * kHaloC + lc + radius];
-    if (!(v >= thr) || (!keep_border && in_border(g, r, c))) continue;
-    // a neighbour with a larger |P| rules the cell out; one with an equal |P|
-    // (rare) needs the index tie-break
-    bool gt = false, eq = false;
-#pragma unroll (RADIUS <= 3 ? 2 * RADIUS + 1 : 1)
-    for (int dr = -radius; dr <= radius; ++dr)
+    rowmax(lr + 2 * RADIUS, 2 * RADIUS);
+    float m = me[RADIUS];
 #pragma unroll
-      for (int dc = -radius; dc <= radius; ++dc)
-        if (dr != 0 || dc != 0) {
-          const float q = val[(lr + radius + dr) * kHaloC + lc + radius + dc];   // -1: clamped border
-          gt |= q > v;
-          eq |= q == v;
-        }
-    if (gt) continue;
-    const int idx = r * g.cols + c;
-    if (eq) {
+    for (int j = 0; j <= 2 * RADIUS; ++j)
+      if (j != RADIUS) m = fmaxf(m, mi[j]);
+#pragma unroll
+    for (int j = 0; j < 2 * RADIUS; ++j) {
+      mi[j] = mi[j + 1];
+      me[j] = me[j + 1];
+    }
+    const int r = r0 + lr;
+    const float v = val[(lr + radius) * kHaloC + lc + radius];
+    const bool ok = in_c & (r < g.rows) & (v >= thr) & ((keep_border != 0) | !in_border(g, r, c));
+    mine[lr / 2] = (ok & (v > m)) ? cell_key(v, r * g.cols + c) : mine[lr / 2];
+    ties |= (ok & (v == m)) ? (1u << lr) : 0u;
+  }
+  if (ties) {   // equal neighbours: the lower linear index precedes
+    uint32_t won = 0;
+    for (uint32_t t = ties; t; t &= t - 1) {
+      const int lr = __builtin_ctz(t), r = r0 + lr;
+      const float v = val[(lr + radius) * kHaloC + lc + radius];
+      const int idx = r * g.cols + c;
       bool peak = true;
       for (int dr = -radius; peak && dr <= radius; ++dr)
         for (int dc = -radius; dc <= radius; ++dc) {
@@ -262,14 +314,48 @@ __global__ void __launch_bounds__(kPeakThreads)
           cc += cc < 0 ? g.cols : (cc >= g.cols ? -g.cols : 0);
           if (rr * g.cols + cc < idx) { peak = false; break; }   // (equal: the cell itself, wrapped)
         }
-      if (!peak) continue;
+      won |= peak ? (1u << lr) : 0u;
     }
-    mine[lr / 2] = cell_key(v, idx);
+#pragma unroll
+    for (int lr = 0; lr < CPT; ++lr)
+      if (won & (1u << lr)) mine[lr / 2] = cell_key(val[(lr + radius) * kHaloC + lc + radius], (r0 + lr) * g.cols + c);
   }
 
-  // the wave's first K keys: each lane sorts its slots once, then K rounds
-  // of a wave-wide minimum over the lanes' first slots; the lane holding the
+  // the wave's first K keys.  Usually the wave holds at most 128 keys: they
+  // are packed into the wave's own LDS slots (lanes placed by their rank
+  // among the wave's keys) and sorted in registers by the shuffle bitonic
+  // network.  Otherwise each lane sorts its slots, then K rounds of a
+  // wave-wide minimum over the lanes' first slots; the lane holding the
   // winner (keys are unique: exactly one) shifts its slots down.
+  __shared__ uint64_t wkeys[NW][128];
+  uint64_t bal[NS];
+  int total = 0;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    bal[j] = __ballot(mine[j] != kNoKey);
+    total += (int)__popcll(bal[j]);
+  }
+  if (total <= 128) {   // uniform over the wave
+    int base = 0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal[j] >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal[j], 0u));
+      if (mine[j] != kNoKey) wkeys[wave][base + rank] = mine[j];
+      base += (int)__popcll(bal[j]);
+    }
+    // the wave's LDS writes complete before its lanes read each other's
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint64_t a = lane < total ? wkeys[wave][lane] : kNoKey;
+    uint64_t b = lane + 64 < total ? wkeys[wave][lane + 64] : kNoKey;
+    wave_sort128(a, b, lane);
+    if (lane < K) dst[lane] = a;
+    if (lane + 64 < K) dst[lane + 64] = b;
+    for (int i = 128 + lane; i < K; i += 64) dst[i] = kNoKey;
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < NS - 1; ++a)
 #pragma unroll
@@ -449,35 +535,6 @@ __device__ __forceinline__ int halo_coord(int c, int n, int wrap, bool& in) {
   in = in & ((wrap != 0) | !(lo | hi));
   const int w = lo ? c + n : (hi ? c - n : c);
   return w < n - 1 ? (w > 0 ? w : 0) : n - 1;
-}
-
-// Sorts 128 keys held by one wave, element lane in a and lane + 64 in b,
-// ascending: the bitonic network with lane exchanges by shuffles (no LDS, no
-// barriers).  All 64 lanes must be active.
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
-  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ void wave_sort128(uint64_t& a, uint64_t& b, int lane) {
-#pragma unroll
-  for (int size = 2; size <= 128; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      if (stride == 64) {   // partners in the same lane (size 128: ascending throughout)
-        const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
-        a = lo;
-        b = hi;
-        continue;
-      }
-      const bool low = (lane & stride) == 0;
-      const uint64_t pa = shfl_xor_u64(a, stride), pb = shfl_xor_u64(b, stride);
-      const bool asc_a = (lane & size) == 0, asc_b = ((lane + 64) & size) == 0;
-      a = (low == asc_a) ? (a < pa ? a : pa) : (a < pa ? pa : a);
-      b = (low == asc_b) ? (b < pb ? b : pb) : (b < pb ? pb : b);
-    }
-  }
 }
 
 // Tile geometry and the staging of one tile plus its halo: HZ * HY rows of
