@@ -45,7 +45,7 @@ __all__ = [
     "resampled_rows", "continuous_plane", "refine_peak",
     "padded_depth", "expand_volume", "spectrum_z", "nvmt_bilinear", "dft_xy", "idft_z",
     "forward_volume", "forward_volume_lines", "volume_boundary_mask", "peaks_list_volume",
-    "plane_params",
+    "plane_params", "VOLUME_SPACES", "volume_in_space", "forward_volume_space",
 ]
 
 
@@ -756,3 +756,28 @@ def plane_params(z: int, row: int, col: int, Nz: int, Ny: int, Nx: int, Nzp: int
     b = -2.0 * (row - Ny // 2) / Ny
     c0 = z - Nzp // 2
     return a, b, c0 - a * Nx / 2 - b * Ny / 2 + Nz / 2
+
+
+# Parameter spaces of a volume.  Eq. A.9 focuses planes whose depth varies
+# by at most one slice per row and column (|a|, |b| <= 1).  A steeper plane is
+# one whose x (or y) varies slowly along the other two axes: it is found by
+# the same transform with x (or y) as the depth axis, the 3D counterpart of
+# the inverse space (Sec. 3.1, Remark 1).  In each space the transform runs on
+# the volume with axes (depth, rows, cols):
+#   "z": (z, y, x), the volume as stored;
+#   "x": (x, z, y);
+#   "y": (y, z, x);
+# and a plane reads depth = a * col + b * row + c in that space's voxel
+# indices.
+VOLUME_SPACES = {"z": (0, 1, 2), "x": (2, 0, 1), "y": (1, 0, 2)}
+
+
+def volume_in_space(vol: np.ndarray, space: str) -> np.ndarray:
+    """The volume with its axes in the space's (depth, rows, cols) order."""
+    return np.transpose(np.asarray(vol), VOLUME_SPACES[space])
+
+
+def forward_volume_space(vol: np.ndarray, space: str, padded_len: int = 0) -> np.ndarray:
+    """The volume transform in one parameter space: P[Lp][rows][cols] of the
+    volume with the space's axis order, Lp = Nz + Ny + Nx by default."""
+    return forward_volume(volume_in_space(vol, space), padded_len)

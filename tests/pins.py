@@ -990,3 +990,27 @@ def check_plane_params_round_trip(O):
         B = np.abs(O.forward_volume(vol))
         got = tuple(int(v) for v in np.unravel_index(np.argmax(B), B.shape))
         assert got == cell, (cell, got, (a, b, c))
+
+
+def check_volume_spaces_focus_steep_planes(O):
+    """Planes steeper than 45 degrees from the z axis focus in the x and y
+    spaces: a sheet x = a*y + b*z + c (or y = a*x + b*z + c), |a|, |b| < 0.85,
+    rendered in the world volume, focuses within one cell of Eq. A.9's cell of
+    that space (depth x or y, rows z, columns y or x)."""
+    rng = np.random.default_rng(110)
+    Nz, Ny, Nx = 20, 16, 24
+    Lp = Nz + Ny + Nx
+    frames = {"x": ((Nx, Nz, Ny), (1, 2, 0)), "y": ((Ny, Nz, Nx), (1, 0, 2))}
+    for space, ((D, R, C), back) in frames.items():
+        for trial in range(3):
+            a, b = float(rng.uniform(-0.85, 0.85)), float(rng.uniform(-0.85, 0.85))
+            dc = float(rng.uniform(0.35 * D, 0.65 * D))
+            sh = synth.Sheet(a, b, dc - a * C / 2 - b * R / 2, 1.0)
+            W = synth.render_volume(D, R, C, [sh], 0.0, rng, bg=0.0).astype(np.float64)
+            vol = np.transpose(W, back)                      # world axes (z, y, x)
+            assert vol.shape == (Nz, Ny, Nx)
+            B = np.abs(O.forward_volume_space(vol, space))
+            got = np.unravel_index(np.argmax(B), B.shape)
+            want = expected_cell_volume(sh, D, R, C, Lp)
+            for g, w, n in zip(got, want, B.shape):
+                assert torus_dist(int(g), w, n) <= 1, (space, trial, got, want)

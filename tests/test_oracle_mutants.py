@@ -215,6 +215,7 @@ ALL_CHECKS = [
     pins.check_volume_reduces_to_image, pins.check_volume_plane_to_point,
     pins.check_volume_point_to_plane, pins.check_volume_shift_equivariance,
     pins.check_volume_peaks_equal_local_maxima, pins.check_plane_params_round_trip,
+    pins.check_volume_spaces_focus_steep_planes,
 ]
 
 def _bilinear_y_weights_swapped(S, Nzp, n3_first=1):
@@ -328,6 +329,8 @@ MUTANTS = {
     "volume expansion not centred": ("expand_volume", _expand_volume_front),
     "3D peaks without the z neighbours": ("peaks_list_volume", _peaks_volume_no_z),
     "plane parameter b with the wrong sign": ("plane_params", _plane_params_b_sign),
+    "x space with rows and columns exchanged": ("VOLUME_SPACES", {"z": (0, 1, 2), "x": (2, 1, 0), "y": (1, 0, 2)}),
+    "y space with rows and columns exchanged": ("VOLUME_SPACES", {"z": (0, 1, 2), "x": (2, 0, 1), "y": (1, 2, 0)}),
 }
 
 

@@ -50,6 +50,7 @@ CHECKS = [
     pins.check_volume_lines_sampler,
     pins.check_volume_peaks_equal_local_maxima,
     pins.check_plane_params_round_trip,
+    pins.check_volume_spaces_focus_steep_planes,
 ]
 
 
