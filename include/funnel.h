@@ -356,27 +356,40 @@ ft_status funnel_plan_set_variant(ft_plan* plan, int32_t role, int32_t variant);
  *   G(w1, w2, w3) = 2D DFT over x', y'                      (Eq. A.4)
  *   P(w1, w2, z)  = inverse DFT_w3 of G                     (Eqs. A.5, A.9)
  *
- * Conventions (as for images, per axis):
+ * Conventions (as for images, per axis; stated for the z space):
  *   - volume V[s][r][c]: Nz slices (depth, z), Ny rows (y), Nx columns (x),
  *     row-major float32, all even and >= 4; volumes of a batch are
  *     contiguous (stride Nz*Ny*Nx).
- *   - the z axis is expanded to Nzp = Nz + Ny + Nx (or padded_len) with
- *     (Nzp-Nz)/2 zero slices in front: a plane with |a|, |b| <= 1 moves by at
+ *   - the z axis is expanded to Lp = Nz + Ny + Nx (or padded_len) with
+ *     (Lp-Nz)/2 zero slices in front: a plane with |a|, |b| <= 1 moves by at
  *     most (Nx+Ny)/2 slices over the volume.  Centred z, y, x.
- *   - w_max = pi, s = 2 n3 / Nzp for n3 = 1 .. Nzp/2-1; DC and Nyquist zero.
+ *   - w_max = pi, s = 2 n3 / Lp for n3 = 1 .. Lp/2-1; DC and Nyquist zero.
  *   - bilinear NVMT: linear interpolation along x and along y, each as the
- *     image NVMT (exact integer floors of (x' Nzp + Nx n3)/(2 n3) and of
- *     (y' Nzp + Ny n3)/(2 n3)), the weights multiplied.
- *   - parameter volume: float32 P[Nzp][Ny][Nx], slice = z + Nzp/2,
- *     row = m2 + Ny/2, column = m1 + Nx/2.  A plane slice = a*col + b*row + c
- *     (voxel indices, |a|, |b| <= 1) focuses at m1 = -a Nx/2, m2 = -b Ny/2,
- *     z = c + a Nx/2 + b Ny/2 - Nz/2.  A plane steeper than that in x or y
- *     is found in the volume with its axes permuted (the 3D counterpart of
- *     the inverse space).
- * Sizes with kernels: Nzp a compiled column length (as Np for images), Nx a
- * compiled row length (as M), Ny in {32, 48, 64, 96, 128, 160, 192, 256,
- * 320, 384, 512, 640, 768, 1024}; Nzp*Ny*Nx*4 bytes below 2 GiB.  FP32.
- * Ownership, threading and errors as for image plans. */
+ *     image NVMT (exact integer floors of (x' Lp + Nx n3)/(2 n3) and of
+ *     (y' Lp + Ny n3)/(2 n3)), the weights multiplied.
+ *   - parameter spaces.  Eq. A.9 focuses the planes whose depth changes by at
+ *     most one slice per row and column (|a|, |b| <= 1).  Steeper planes are
+ *     found by the same transform with x or y as the depth axis, the 3D
+ *     counterpart of the image's inverse space.  Each space runs on the
+ *     volume with its axes in the order (depth, rows, cols):
+ *       FT_VOL_SPACE_Z: (z, y, x), the volume as stored;
+ *       FT_VOL_SPACE_X: (x, z, y);
+ *       FT_VOL_SPACE_Y: (y, z, x).
+ *     Every space expands its depth axis to the same Lp = Nz + Ny + Nx (or
+ *     padded_len).
+ *   - parameter volume of a space: float32 P[Lp][rows][cols], slice =
+ *     z + Lp/2, row = m2 + rows/2, column = m1 + cols/2.  A plane
+ *     depth = a*col + b*row + c (the space's voxel indices, |a|, |b| <= 1)
+ *     focuses at m1 = -a cols/2, m2 = -b rows/2, z = c + a cols/2 +
+ *     b rows/2 - depth/2.  A volume's parameter volumes are contiguous in
+ *     the order z, x, y (the spaces the plan computes), and volumes follow
+ *     each other with the stride of funnel_volume_param_elems().
+ * Sizes with kernels: Lp a compiled column length (as Np for images); for
+ * each space computed, its cols a compiled row length (as M) and its rows in
+ * {32, 48, 64, 96, 128, 160, 192, 256, 320, 384, 512, 640, 768, 1024}; each
+ * parameter volume below 2 GiB.  FP32.  Ownership, threading and errors as
+ * for image plans. */
+enum { FT_VOL_SPACE_Z = 1, FT_VOL_SPACE_X = 2, FT_VOL_SPACE_Y = 4, FT_VOL_SPACE_ALL = 7 };
 typedef struct ft_volume_plan ft_volume_plan;
 
 typedef struct {
@@ -384,35 +397,44 @@ typedef struct {
   int32_t depth;       /* Nz, slices */
   int32_t rows;        /* Ny */
   int32_t cols;        /* Nx */
-  int32_t padded_len;  /* Nzp; 0 means Nz+Ny+Nx; else even and >= Nz+Ny+Nx */
+  int32_t padded_len;  /* Lp; 0 means Nz+Ny+Nx; else even and >= Nz+Ny+Nx */
+  int32_t spaces;      /* a non-empty set of FT_VOL_SPACE_Z / _X / _Y */
   uint32_t flags;      /* 0 */
 } ft_volume_desc;
 
 ft_status funnel_volume_plan_create(const ft_volume_desc* desc, ft_volume_plan** out);
 void funnel_volume_plan_destroy(ft_volume_plan* plan);
 ft_status funnel_volume_padded_len(const ft_volume_plan* plan, int32_t* nzp);
-/* Bytes of device workspace funnel_volume_forward needs: the half spectrum,
- * (Nzp/2-1) * Ny * Nx complex values per volume. */
+/* Floats of one volume's parameter volumes (all spaces of the plan). */
+ft_status funnel_volume_param_elems(const ft_volume_plan* plan, size_t* floats_per_volume);
+/* Bytes of device workspace funnel_volume_forward needs: the largest space's
+ * half spectrum, (Lp/2-1) * rows * cols complex values per volume, and for
+ * the y space a slice-transposed copy of the volumes. */
 ft_status funnel_volume_workspace_size(const ft_volume_plan* plan, size_t* bytes);
 
-/* Forward transform of a batch of volumes (App. A, Eqs. A.2-A.5).
+/* Forward transform of a batch of volumes (App. A, Eqs. A.2-A.5), in every
+ * space of the plan.
  *   volumes : device, float32 [batch][Nz][Ny][Nx]
- *   params  : device, float32 [batch][Nzp][Ny][Nx], overwritten with P
+ *   params  : device, float32 [batch][funnel_volume_param_elems], overwritten
  *   ws      : device workspace of at least funnel_volume_workspace_size bytes
- * Four launches: DFT along z, NVMT + DFT along x', NVMT + DFT along y'
- * (bilinear interpolation is the product of the two linear ones), inverse
- * DFT along w3 with 1/Nzp. */
+ * Per space four launches: DFT along the depth axis, NVMT + DFT along x',
+ * NVMT + DFT along y' (bilinear interpolation is the product of the two
+ * linear ones), inverse DFT along w3 with 1/Lp; the y space first transposes
+ * every slice so that its depth lines are contiguous. */
 ft_status funnel_volume_forward(const ft_volume_plan* plan, const float* volumes, float* params, void* ws,
                                 size_t ws_bytes, void* stream);
 
 /* One detected 3D peak and its plane (Eq. A.9 read backwards). */
 typedef struct {
   int32_t volume;
+  int32_t space;       /* 0: z space, 1: x space, 2: y space */
   int32_t z;           /* parameter-volume slice (intercept bin) */
-  int32_t row;         /* m2 + Ny/2 */
-  int32_t col;         /* m1 + Nx/2 */
+  int32_t row;         /* m2 + rows/2 */
+  int32_t col;         /* m1 + cols/2 */
   float value;         /* |P| */
-  float a, b, c;       /* the plane slice = a*col + b*row + c, voxel indices */
+  float a, b, c;       /* the plane depth = a*col + b*row + c in the space's
+                          voxel indices: z space slice = a*x + b*y + c,
+                          x space x = a*y + b*z + c, y space y = a*x + b*z + c */
 } ft_plane_peak;
 
 ft_status funnel_volume_peaks_workspace_size(const ft_volume_plan* plan, int32_t K, size_t* bytes);
@@ -423,15 +445,17 @@ ft_status funnel_volume_peaks_workspace_size(const ft_volume_plan* plan, int32_t
  * expansion's faces focus (slices within 2 of z = -+Nz/2 at m1, m2 in
  * {-1, 0, 1}) unless FT_PEAK_KEEP_PAD_BOUNDARY is set.
  *   K       : 1 .. 256;  radius : 1 or 2
- *   peaks   : device, ft_plane_peak [batch][K] (entries beyond the count unspecified)
- *   n_found : device, int32 [batch] */
+ *   peaks   : device, ft_plane_peak [batch][n_spaces][K] (entries beyond the
+ *             count unspecified), spaces in the order z, x, y
+ *   n_found : device, int32 [batch][n_spaces] */
 ft_status funnel_volume_peaks(const ft_volume_plan* plan, const float* params, int32_t K, float threshold,
                               int32_t radius, uint32_t flags, ft_plane_peak* peaks, int32_t* n_found, void* ws,
                               size_t ws_bytes, void* stream);
 
-/* Tile variants of the four launches (roles 0 z DFT, 1 x' pass, 2 y' pass,
- * 3 inverse w3 DFT), autotuning over the whole forward chain, and kernel
- * timing, as for image plans. */
+/* Tile variants of the four launches of each space (role 4*s + r, s = 0 z,
+ * 1 x, 2 y space; r = 0 depth DFT, 1 x' pass, 2 y' pass, 3 inverse w3 DFT;
+ * -1 for a space the plan does not compute), autotuning over the whole
+ * forward chain, and kernel timing, as for image plans. */
 ft_status funnel_volume_variants(const ft_volume_plan* plan, int32_t* variants, int32_t cap);
 ft_status funnel_volume_set_variant(ft_volume_plan* plan, int32_t role, int32_t variant);
 ft_status funnel_volume_autotune(ft_volume_plan* plan, void* stream, ft_tune_result* out, int32_t cap, int32_t* n);

@@ -1080,64 +1080,88 @@ ft_status funnel_refine(const ft_plan* p, const float* images, const ft_peak* pe
 
 // ------------------------------------------------------------------ volumes (App. A)
 //
-// Four launches per forward: A (DFT along z of the Ny*Nx lines, the image
-// pass A), Bx (NVMT along x + DFT along x', the image row pass with Ny rows
-// per ratio), By (NVMT along y + DFT along y', funnel_volume.hip) and C
-// (Hermitian inverse DFT along omega_3, the image pass C), all in place on
-// one half spectrum of h * Ny * Nx complex values per volume.
+// Per parameter space four launches: A (DFT along the space's depth axis of
+// its R*C lines, the image pass A; columns of the volume for the z space,
+// its rows for the x space, the rows of the slice-transposed volume for the
+// y space), Bx (NVMT along the columns + DFT along x', the image row pass
+// with R rows per ratio), By (NVMT along the rows + DFT along y',
+// funnel_volume.hip) and C (Hermitian inverse DFT along omega_3, the image
+// pass C), all in place on one half spectrum of h * R * C complex values per
+// volume, which the spaces use one after the other.
 
 enum VRole { VA, VBX, VBY, VC, NVROLES };
-static const char* const kVRoleName[NVROLES] = {"volume.A", "volume.Bx", "volume.By", "volume.C"};
+constexpr int kVSpaces = 3;   // z, x, y
+static const char* const kVRoleName[kVSpaces][NVROLES] = {
+    {"volume.A", "volume.Bx", "volume.By", "volume.C"},
+    {"volume.x.A", "volume.x.Bx", "volume.x.By", "volume.x.C"},
+    {"volume.y.A", "volume.y.Bx", "volume.y.By", "volume.y.C"}};
+
+struct VSpace {
+  bool on = false;
+  int D = 0, R = 0, C = 0;      // depth, rows and columns of the space
+  long long param_off = 0;      // floats from a volume's parameter block to this space's
+  long long spec_elems = 0;     // h * R * C complex values per volume
+  size_t tw_r = 0, tw_c = 0;    // twiddles of the y' (length R) and x' (length C) passes
+  int variant[NVROLES] = {};
+};
 
 struct ft_volume_plan {
   FtProfiler* prof = nullptr;
   int device = 0;
-  int batch = 0, Nz = 0, Ny = 0, Nx = 0, Nzp = 0, h = 0;
-  float2* tw = nullptr;                   // twiddles of lengths Nzp, Nx, Ny
-  size_t tw_z = 0, tw_x = 0, tw_y = 0;
-  long long vol_elems = 0, param_elems = 0, spec_elems = 0;   // per volume
+  int batch = 0, Nz = 0, Ny = 0, Nx = 0, Lp = 0, h = 0;
+  float2* tw = nullptr;         // twiddles of lengths Lp, Nx, Ny, Nz
+  size_t tw_l = 0;
+  long long vol_elems = 0, param_elems = 0;   // per volume; param_elems over all spaces
+  size_t ws_tp_off = 0;         // byte offset of the slice-transposed volumes (y space)
   size_t ws_bytes = 0;
-  int variant[NVROLES] = {};
+  VSpace sp[kVSpaces];
 };
 
 namespace {
 
-unsigned vrole_mask(const ft_volume_plan* p, int r) {
+unsigned vrole_mask(const ft_volume_plan* p, int si, int r) {
+  const VSpace& q = p->sp[si];
+  if (!q.on) return 0;
   switch (r) {
-    case VA: case VC: return funnel::col_variant_mask(p->Nzp, FT_PREC_FP32);
-    case VBX: return funnel::row_variant_mask(p->Nx, FT_PREC_FP32);
-    case VBY: return funnel::ycol_variant_mask(p->Ny);
+    case VA: case VC: return funnel::col_variant_mask(p->Lp, FT_PREC_FP32);
+    case VBX: return funnel::row_variant_mask(q.C, FT_PREC_FP32);
+    case VBY: return funnel::ycol_variant_mask(q.R);
   }
   return 0;
 }
 
 // algorithmic HBM bytes of one launch (each input read once, each output written once)
-double vrole_bytes(const ft_volume_plan* p, int r) {
-  const double B = p->batch, lines = (double)p->Ny * p->Nx, h = p->h;
+double vrole_bytes(const ft_volume_plan* p, int si, int r) {
+  const VSpace& q = p->sp[si];
+  const double B = p->batch, lines = (double)q.R * q.C, h = p->h;
   switch (r) {
-    case VA: return B * (4.0 * p->Nz * lines + 8.0 * h * lines);
+    case VA: return B * (4.0 * q.D * lines + 8.0 * h * lines);
     case VBX: case VBY: return B * 16.0 * h * lines;
-    case VC: return B * (8.0 * h * lines + 4.0 * p->Nzp * lines);
+    case VC: return B * (8.0 * h * lines + 4.0 * p->Lp * lines);
   }
   return 0.0;
 }
 
-hipError_t run_vrole(const ft_volume_plan* p, int r, int v, const float* src, float* dst, char* w, hipStream_t s) {
+hipError_t run_vrole(const ft_volume_plan* p, int si, int r, int v, const float* src, float* dst, char* w,
+                     hipStream_t s) {
+  const VSpace& q = p->sp[si];
   float2* S = reinterpret_cast<float2*>(w);
-  const int lines = p->Ny * p->Nx;
-  const long long ss = p->spec_elems;
+  const int lines = q.R * q.C;
+  const long long ss = q.spec_elems;
   using funnel::ImgMap;
   switch (r) {
-    case VA:
-      return funnel::launch_r2c(p->Nzp, v, FT_PREC_FP32, false, src, S, lines, p->Nz, (p->Nzp - p->Nz) / 2,
-                                ImgMap{p->vol_elems, ss, nullptr, nullptr}, 1.0f, p->tw + p->tw_z, p->batch, s);
+    case VA: {
+      // z: the volume's columns; x: its rows; y: the rows of its slice-transposed copy
+      const float* in = si == 2 ? reinterpret_cast<const float*>(w + p->ws_tp_off) : src;
+      return funnel::launch_r2c(p->Lp, v, FT_PREC_FP32, si != 0, in, S, lines, q.D, (p->Lp - q.D) / 2,
+                                ImgMap{p->vol_elems, ss, nullptr, nullptr}, 1.0f, p->tw + p->tw_l, p->batch, s);
+    }
     case VBX:
-      return funnel::launch_row(p->Nx, v, FT_PREC_FP32, false, S, p->Nzp, p->h, p->Ny, ss, p->tw + p->tw_x, p->batch,
-                                s);
-    case VBY: return funnel::launch_ycol(p->Ny, v, S, p->Nzp, p->h, p->Nx, ss, p->tw + p->tw_y, p->batch, s);
+      return funnel::launch_row(q.C, v, FT_PREC_FP32, false, S, p->Lp, p->h, q.R, ss, p->tw + q.tw_c, p->batch, s);
+    case VBY: return funnel::launch_ycol(q.R, v, S, p->Lp, p->h, q.C, ss, p->tw + q.tw_r, p->batch, s);
     case VC:
-      return funnel::launch_c2r(p->Nzp, v, FT_PREC_FP32, false, false, S, dst, lines, 0, p->Nzp,
-                                ImgMap{ss, p->param_elems, nullptr, nullptr}, 1.0f / p->Nzp, p->tw + p->tw_z,
+      return funnel::launch_c2r(p->Lp, v, FT_PREC_FP32, false, false, S, dst + q.param_off, lines, 0, p->Lp,
+                                ImgMap{ss, p->param_elems, nullptr, nullptr}, 1.0f / p->Lp, p->tw + p->tw_l,
                                 p->batch, s);
   }
   return hipErrorInvalidValue;
@@ -1145,8 +1169,17 @@ hipError_t run_vrole(const ft_volume_plan* p, int r, int v, const float* src, fl
 
 hipError_t enqueue_volume(const ft_volume_plan* p, const float* src, float* dst, char* w, hipStream_t s) {
   hipError_t e = hipSuccess;
-  for (int r = 0; r < NVROLES && e == hipSuccess; ++r)
-    e = timed(p, s, kVRoleName[r], vrole_bytes(p, r), [&] { return run_vrole(p, r, p->variant[r], src, dst, w, s); });
+  for (int si = 0; si < kVSpaces && e == hipSuccess; ++si) {
+    if (!p->sp[si].on) continue;
+    if (si == 2)
+      e = timed(p, s, "volume.y.T", 8.0 * p->batch * p->vol_elems, [&] {
+        return funnel::launch_transpose_slices(src, reinterpret_cast<float*>(w + p->ws_tp_off), p->batch * p->Nz,
+                                               p->Ny, p->Nx, s);
+      });
+    for (int r = 0; r < NVROLES && e == hipSuccess; ++r)
+      e = timed(p, s, kVRoleName[si][r], vrole_bytes(p, si, r),
+                [&] { return run_vrole(p, si, r, p->sp[si].variant[r], src, dst, w, s); });
+  }
   return e;
 }
 
@@ -1164,6 +1197,12 @@ void free_volume_plan(ft_volume_plan* p) {
   delete p;
 }
 
+int n_vspaces(const ft_volume_plan* p) {
+  int n = 0;
+  for (const auto& q : p->sp) n += q.on ? 1 : 0;
+  return n;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1175,24 +1214,33 @@ ft_status funnel_volume_plan_create(const ft_volume_desc* d, ft_volume_plan** ou
   if (d->depth < 4 || d->rows < 4 || d->cols < 4 || (d->depth & 1) || (d->rows & 1) || (d->cols & 1))
     return fail(FT_ERR_INVALID_ARG, "depth, rows and cols must be even and >= 4 (got %d x %d x %d)", d->depth,
                 d->rows, d->cols);
+  if (d->spaces < 1 || d->spaces > FT_VOL_SPACE_ALL)
+    return fail(FT_ERR_INVALID_ARG, "spaces must be a non-empty set of FT_VOL_SPACE_Z/X/Y (got %d)", d->spaces);
   if (d->flags != 0) return fail(FT_ERR_INVALID_ARG, "unknown volume plan flags 0x%x", d->flags);
   const long long Nz = d->depth, Ny = d->rows, Nx = d->cols;
-  const long long Nzp = d->padded_len == 0 ? Nz + Ny + Nx : d->padded_len;
-  if (d->padded_len < 0 || (Nzp & 1) || Nzp < Nz + Ny + Nx)
+  const long long Lp = d->padded_len == 0 ? Nz + Ny + Nx : d->padded_len;
+  if (d->padded_len < 0 || (Lp & 1) || Lp < Nz + Ny + Nx)
     return fail(FT_ERR_INVALID_ARG, "padded_len must be 0 or even and >= depth+rows+cols (got %d)", d->padded_len);
-  if (Nzp > (1 << 20) || Nx > (1 << 20) || Ny > (1 << 20))
+  if (Lp > (1 << 20) || Nx > (1 << 20) || Ny > (1 << 20) || Nz > (1 << 20))
     return fail(FT_ERR_UNSUPPORTED_SIZE, "transform length too large");
-  if (!funnel::length_supported((int)Nzp) || !funnel::col_variant_mask((int)Nzp, FT_PREC_FP32))
-    return fail(FT_ERR_UNSUPPORTED_SIZE, "no kernel for padded depth %lld", Nzp);
-  if (!funnel::length_supported((int)Nx) || !funnel::row_variant_mask((int)Nx, FT_PREC_FP32))
-    return fail(FT_ERR_UNSUPPORTED_SIZE, "no kernel for row length %lld (volume width)", Nx);
-  if (!funnel::ycol_variant_mask((int)Ny))
-    return fail(FT_ERR_UNSUPPORTED_SIZE, "no y' pass kernel for column length %lld (volume height)", Ny);
-  // the kernels address one volume's parameter volume and half spectrum with
-  // 32-bit byte offsets
-  if (Nzp * Ny * Nx * 4 >= (1ll << 31))
-    return fail(FT_ERR_UNSUPPORTED_SIZE, "per-volume parameter volumes of %lld x %lld x %lld exceed 2 GiB", Nzp, Ny,
-                Nx);
+  if (!funnel::length_supported((int)Lp) || !funnel::col_variant_mask((int)Lp, FT_PREC_FP32))
+    return fail(FT_ERR_UNSUPPORTED_SIZE, "no kernel for padded depth %lld", Lp);
+  // (depth, rows, cols) of the z, x and y spaces
+  const long long geo[kVSpaces][3] = {{Nz, Ny, Nx}, {Nx, Nz, Ny}, {Ny, Nz, Nx}};
+  static const char* const sname[kVSpaces] = {"z", "x", "y"};
+  for (int si = 0; si < kVSpaces; ++si) {
+    if (!(d->spaces & (1 << si))) continue;
+    const long long R = geo[si][1], C = geo[si][2];
+    if (!funnel::length_supported((int)C) || !funnel::row_variant_mask((int)C, FT_PREC_FP32))
+      return fail(FT_ERR_UNSUPPORTED_SIZE, "%s space: no x' pass kernel for row length %lld", sname[si], C);
+    if (!funnel::ycol_variant_mask((int)R))
+      return fail(FT_ERR_UNSUPPORTED_SIZE, "%s space: no y' pass kernel for column length %lld", sname[si], R);
+    // the kernels address one volume's parameter block and half spectrum of
+    // a space with 32-bit byte offsets
+    if (Lp * R * C * 4 >= (1ll << 31))
+      return fail(FT_ERR_UNSUPPORTED_SIZE, "%s space: per-volume parameter volumes of %lld x %lld x %lld exceed 2 GiB",
+                  sname[si], Lp, R, C);
+  }
 
   ft_volume_plan* p = new (std::nothrow) ft_volume_plan();
   if (!p) return fail(FT_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -1200,26 +1248,47 @@ ft_status funnel_volume_plan_create(const ft_volume_desc* d, ft_volume_plan** ou
   p->Nz = (int)Nz;
   p->Ny = (int)Ny;
   p->Nx = (int)Nx;
-  p->Nzp = (int)Nzp;
-  p->h = (int)Nzp / 2 - 1;
+  p->Lp = (int)Lp;
+  p->h = (int)Lp / 2 - 1;
   p->vol_elems = Nz * Ny * Nx;
-  p->param_elems = Nzp * Ny * Nx;
-  p->spec_elems = (long long)p->h * Ny * Nx;
-  p->ws_bytes = align_up((size_t)p->batch * p->spec_elems * sizeof(float2), 256);
-  for (int r = 0; r < NVROLES; ++r) {
-    const unsigned m = vrole_mask(p, r);
+  // twiddles: Lp, then Nx, Ny, Nz
+  p->tw_l = 0;
+  const size_t tw_x = (size_t)Lp, tw_y = tw_x + (size_t)Nx, tw_z = tw_y + (size_t)Ny, ntw = tw_z + (size_t)Nz;
+  const size_t tw_of[kVSpaces][2] = {{tw_y, tw_x}, {tw_z, tw_y}, {tw_z, tw_x}};   // (rows, cols) per space
+  size_t spec = 0;
+  long long off = 0;
+  for (int si = 0; si < kVSpaces; ++si) {
+    VSpace& q = p->sp[si];
+    q.on = (d->spaces & (1 << si)) != 0;
+    if (!q.on) continue;
+    q.D = (int)geo[si][0];
+    q.R = (int)geo[si][1];
+    q.C = (int)geo[si][2];
+    q.param_off = off;
+    off += Lp * q.R * q.C;
+    q.spec_elems = (long long)p->h * q.R * q.C;
+    q.tw_r = tw_of[si][0];
+    q.tw_c = tw_of[si][1];
+    const size_t b = (size_t)p->batch * q.spec_elems * sizeof(float2);
+    spec = b > spec ? b : spec;
+    for (int r = 0; r < NVROLES; ++r) {
+      const unsigned m = vrole_mask(p, si, r);
+      for (int v = 0; v < funnel::kMaxVariants; ++v)
+        if (m & (1u << v)) {
+          q.variant[r] = v;
+          break;
+        }
+    }
+    // the y' pass: prefer a tile whose column count divides the width
     for (int v = 0; v < funnel::kMaxVariants; ++v)
-      if (m & (1u << v)) {
-        p->variant[r] = v;
+      if ((vrole_mask(p, si, VBY) & (1u << v)) && q.C % funnel::ycol_lines(v) == 0) {
+        q.variant[VBY] = v;
         break;
       }
   }
-  // the y' pass: prefer a tile whose column count divides the width
-  for (int v = 0; v < funnel::kMaxVariants; ++v)
-    if ((vrole_mask(p, VBY) & (1u << v)) && p->Nx % funnel::ycol_lines(v) == 0) {
-      p->variant[VBY] = v;
-      break;
-    }
+  p->param_elems = off;
+  p->ws_tp_off = align_up(spec, 256);
+  p->ws_bytes = p->ws_tp_off + (p->sp[2].on ? align_up((size_t)p->batch * p->vol_elems * sizeof(float), 256) : 0);
 
   int dev = -1, ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -1231,14 +1300,11 @@ ft_status funnel_volume_plan_create(const ft_volume_desc* d, ft_volume_plan** ou
     return fail(FT_ERR_NO_DEVICE, "no current HIP device");
   }
   p->device = dev;
-  p->tw_z = 0;
-  p->tw_x = (size_t)Nzp;
-  p->tw_y = p->tw_x + (size_t)Nx;
-  const size_t ntw = p->tw_y + (size_t)Ny;
   std::vector<float2> host(ntw);
-  fill_twiddles(host.data() + p->tw_z, (int)Nzp);
-  fill_twiddles(host.data() + p->tw_x, (int)Nx);
-  fill_twiddles(host.data() + p->tw_y, (int)Ny);
+  fill_twiddles(host.data(), (int)Lp);
+  fill_twiddles(host.data() + tw_x, (int)Nx);
+  fill_twiddles(host.data() + tw_y, (int)Ny);
+  fill_twiddles(host.data() + tw_z, (int)Nz);
   hipError_t e = hipMalloc(&p->tw, ntw * sizeof(float2));
   if (e != hipSuccess) {
     p->tw = nullptr;
@@ -1258,7 +1324,13 @@ void funnel_volume_plan_destroy(ft_volume_plan* p) { free_volume_plan(p); }
 
 ft_status funnel_volume_padded_len(const ft_volume_plan* p, int32_t* nzp) {
   if (!p || !nzp) return fail(FT_ERR_INVALID_ARG, "plan and nzp must be non-NULL");
-  *nzp = p->Nzp;
+  *nzp = p->Lp;
+  return ok();
+}
+
+ft_status funnel_volume_param_elems(const ft_volume_plan* p, size_t* floats_per_volume) {
+  if (!p || !floats_per_volume) return fail(FT_ERR_INVALID_ARG, "plan and floats_per_volume must be non-NULL");
+  *floats_per_volume = (size_t)p->param_elems;
   return ok();
 }
 
@@ -1286,7 +1358,13 @@ ft_status funnel_volume_forward(const ft_volume_plan* p, const float* volumes, f
 ft_status funnel_volume_peaks_workspace_size(const ft_volume_plan* p, int32_t K, size_t* bytes) {
   if (!p || !bytes) return fail(FT_ERR_INVALID_ARG, "plan and bytes must be non-NULL");
   if (K < 1 || K > 256) return fail(FT_ERR_INVALID_ARG, "K must be in 1..256 (got %d)", K);
-  *bytes = funnel::vpeaks_workspace_bytes(p->batch, funnel::vpeaks_tiles(p->Nzp, p->Ny, p->Nx), K);
+  size_t need = 0;
+  for (const auto& q : p->sp) {
+    if (!q.on) continue;
+    const size_t b = funnel::vpeaks_workspace_bytes(p->batch, funnel::vpeaks_tiles(p->Lp, q.R, q.C), K);
+    need = b > need ? b : need;
+  }
+  *bytes = need;
   return ok();
 }
 
@@ -1309,26 +1387,38 @@ ft_status funnel_volume_peaks(const ft_volume_plan* p, const float* params, int3
   if (ws_bytes < need) return fail(FT_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
   st = check_volume_device(p);
   if (st != FT_OK) return st;
-  const hipError_t e = funnel::launch_vpeaks(params, p->param_elems, p->batch, p->Nzp, p->Ny, p->Nx, p->Nz, K,
-                                             threshold, radius, (flags & FT_PEAK_CLAMP_BORDER) ? 0 : 1,
-                                             (flags & FT_PEAK_KEEP_PAD_BOUNDARY) ? 1 : 0, peaks, n_found, ws,
-                                             static_cast<hipStream_t>(stream));
+  const int ns = n_vspaces(p);
+  hipError_t e = hipSuccess;
+  for (int si = 0, k = 0; si < kVSpaces && e == hipSuccess; ++si) {
+    const VSpace& q = p->sp[si];
+    if (!q.on) continue;
+    e = funnel::launch_vpeaks(params + q.param_off, p->param_elems, p->batch, p->Lp, q.R, q.C, q.D, K, threshold,
+                              radius, (flags & FT_PEAK_CLAMP_BORDER) ? 0 : 1,
+                              (flags & FT_PEAK_KEEP_PAD_BOUNDARY) ? 1 : 0, ns, k++, si, peaks, n_found, ws,
+                              static_cast<hipStream_t>(stream));
+  }
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return ok();
 }
 
 ft_status funnel_volume_variants(const ft_volume_plan* p, int32_t* variants, int32_t cap) {
   if (!p || !variants || cap < 1) return fail(FT_ERR_INVALID_ARG, "plan and variants must be non-NULL, cap >= 1");
-  for (int r = 0; r < NVROLES && r < cap; ++r) variants[r] = p->variant[r];
+  for (int k = 0; k < kVSpaces * NVROLES && k < cap; ++k) {
+    const VSpace& q = p->sp[k / NVROLES];
+    variants[k] = q.on ? q.variant[k % NVROLES] : -1;
+  }
   return ok();
 }
 
 ft_status funnel_volume_set_variant(ft_volume_plan* p, int32_t role, int32_t variant) {
   if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
-  if (role < 0 || role >= NVROLES) return fail(FT_ERR_INVALID_ARG, "role must be in 0..3 (got %d)", role);
-  if (variant < 0 || variant >= funnel::kMaxVariants || !(vrole_mask(p, role) & (1u << variant)))
-    return fail(FT_ERR_INVALID_ARG, "%s has no kernel for variant %d", kVRoleName[role], variant);
-  p->variant[role] = variant;
+  if (role < 0 || role >= kVSpaces * NVROLES)
+    return fail(FT_ERR_INVALID_ARG, "role must be in 0..%d (got %d)", kVSpaces * NVROLES - 1, role);
+  const int si = role / NVROLES, r = role % NVROLES;
+  if (!p->sp[si].on) return fail(FT_ERR_INVALID_ARG, "role %d belongs to a space the plan does not compute", role);
+  if (variant < 0 || variant >= funnel::kMaxVariants || !(vrole_mask(p, si, r) & (1u << variant)))
+    return fail(FT_ERR_INVALID_ARG, "%s has no kernel for variant %d", kVRoleName[si][r], variant);
+  p->sp[si].variant[r] = variant;
   return ok();
 }
 
@@ -1362,53 +1452,57 @@ ft_status funnel_volume_autotune(ft_volume_plan* p, void* stream, ft_tune_result
   FtProfiler* saved = p->prof;
   p->prof = nullptr;
   int count = 0;
-  // coordinate descent over the four launches, two sweeps, each variant
-  // scored by the whole forward chain (best of 5 after one warm-up)
+  // coordinate descent over the launches, two sweeps, each variant scored by
+  // the whole forward chain (best of 5 after one warm-up)
   for (int sweep = 0; sweep < 2; ++sweep)
-    for (int r = 0; r < NVROLES; ++r) {
-      const unsigned mask = vrole_mask(p, r);
-      float best = 1e30f, first_ms = -1.f;
-      int best_v = p->variant[r], tried = 0;
-      for (int v = 0; v < funnel::kMaxVariants; ++v) {
-        if (!(mask & (1u << v))) continue;
-        const int keep = p->variant[r];
-        p->variant[r] = v;
-        float ms_min = 1e30f;
-        hipError_t e = hipSuccess;
-        for (int rep = 0; rep < 6 && e == hipSuccess; ++rep) {
-          e = hipEventRecord(e0, s);
-          if (e == hipSuccess)
-            e = enqueue_volume(p, static_cast<float*>(a), static_cast<float*>(b), static_cast<char*>(w), s);
-          if (e == hipSuccess) e = hipEventRecord(e1, s);
-          if (e == hipSuccess) e = hipEventSynchronize(e1);
-          float ms = 0.f;
-          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-          if (e == hipSuccess && rep > 0 && ms < ms_min) ms_min = ms;
+    for (int si = 0; si < kVSpaces; ++si) {
+      if (!p->sp[si].on) continue;
+      for (int r = 0; r < NVROLES; ++r) {
+        const unsigned mask = vrole_mask(p, si, r);
+        int& cur = p->sp[si].variant[r];
+        float best = 1e30f, first_ms = -1.f;
+        int best_v = cur, tried = 0;
+        for (int v = 0; v < funnel::kMaxVariants; ++v) {
+          if (!(mask & (1u << v))) continue;
+          const int keep = cur;
+          cur = v;
+          float ms_min = 1e30f;
+          hipError_t e = hipSuccess;
+          for (int rep = 0; rep < 6 && e == hipSuccess; ++rep) {
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess)
+              e = enqueue_volume(p, static_cast<float*>(a), static_cast<float*>(b), static_cast<char*>(w), s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && rep > 0 && ms < ms_min) ms_min = ms;
+          }
+          cur = keep;
+          if (e != hipSuccess) {
+            p->prof = saved;
+            cleanup();
+            return hip_fail(e, "autotune launch");
+          }
+          if (v == keep) first_ms = ms_min;
+          ++tried;
+          if (ms_min < best) {
+            best = ms_min;
+            best_v = v;
+          }
         }
-        p->variant[r] = keep;
-        if (e != hipSuccess) {
-          p->prof = saved;
-          cleanup();
-          return hip_fail(e, "autotune launch");
+        cur = best_v;
+        if (sweep == 0) continue;
+        if (count < cap) {
+          std::memset(&out[count], 0, sizeof(ft_tune_result));
+          std::snprintf(out[count].name, sizeof(out[count].name), "%s", kVRoleName[si][r]);
+          out[count].variant = best_v;
+          out[count].n_tried = tried;
+          out[count].ms = best;
+          out[count].ms_default = first_ms;
         }
-        if (v == keep) first_ms = ms_min;
-        ++tried;
-        if (ms_min < best) {
-          best = ms_min;
-          best_v = v;
-        }
+        ++count;
       }
-      p->variant[r] = best_v;
-      if (sweep == 0) continue;
-      if (count < cap) {
-        std::memset(&out[count], 0, sizeof(ft_tune_result));
-        std::snprintf(out[count].name, sizeof(out[count].name), "%s", kVRoleName[r]);
-        out[count].variant = best_v;
-        out[count].n_tried = tried;
-        out[count].ms = best;
-        out[count].ms_default = first_ms;
-      }
-      ++count;
     }
   p->prof = saved;
   cleanup();

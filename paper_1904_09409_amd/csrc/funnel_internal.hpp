@@ -80,13 +80,17 @@ unsigned ycol_variant_mask(int L);
 int ycol_lines(int variant);
 hipError_t launch_ycol(int L, int variant, float2* data, int Lz, int h, int nx, long long vol_stride,
                        const float2* tw, int batch, hipStream_t s);
+// slices [ny][nx] -> [nx][ny], `slices` of them back to back
+hipError_t launch_transpose_slices(const float* in, float* out, int slices, int ny, int nx, hipStream_t s);
 // 3D peaks of the parameter volumes [batch][nz][ny][nx] (stride floats apart);
-// zimg: depth of the transformed volume (the faces of its expansion)
+// zimg: depth of the transformed volume (the faces of its expansion).
+// Records and counts go to peaks[(v * ns + sp) * K ..] and n_found[v * ns + sp],
+// each record tagged with space_id.
 int vpeaks_tiles(int nz, int ny, int nx);
 size_t vpeaks_workspace_bytes(int nvol, int tiles, int K);
 hipError_t launch_vpeaks(const float* params, long long stride, int batch, int nz, int ny, int nx, int zimg, int K,
-                         float thr, int radius, int wrap, int keep_border, ft_plane_peak* peaks, int32_t* n_found,
-                         void* ws, hipStream_t s);
+                         float thr, int radius, int wrap, int keep_border, int ns, int sp, int space_id,
+                         ft_plane_peak* peaks, int32_t* n_found, void* ws, hipStream_t s);
 
 size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K);
 int peaks_tiles(int rows, int cols);

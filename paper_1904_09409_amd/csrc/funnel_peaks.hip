@@ -778,12 +778,12 @@ __global__ void __launch_bounds__(kPeakThreads)
 
 // One sorted list of K keys per volume -> plane records and counts.
 __global__ void __launch_bounds__(kMergeThreads)
-    k_vpeaks_records(const float* __restrict__ params, VolGeom g, int K, const uint64_t* __restrict__ list,
-                     ft_plane_peak* __restrict__ peaks, int32_t* __restrict__ n_found) {
+    k_vpeaks_records(const float* __restrict__ params, VolGeom g, int K, const uint64_t* __restrict__ list, int ns,
+                     int sp, int space_id, ft_plane_peak* __restrict__ peaks, int32_t* __restrict__ n_found) {
   const int vol = blockIdx.x;
   const float* P = params + (long long)vol * g.stride;
   const uint64_t* keys = list + (long long)vol * K;
-  ft_plane_peak* dst = peaks + (long long)vol * K;
+  ft_plane_peak* dst = peaks + ((long long)vol * ns + sp) * K;
   for (int i = threadIdx.x; i < K; i += kMergeThreads) {
     if (keys[i] == kNoKey) continue;
     const int idx = (int)(uint32_t)(keys[i] & 0xffffffffu);
@@ -791,6 +791,7 @@ __global__ void __launch_bounds__(kMergeThreads)
     const int r = rem / g.nx, c = rem % g.nx;
     ft_plane_peak pk;
     pk.volume = vol;
+    pk.space = space_id;
     pk.z = z;
     pk.row = r;
     pk.col = c;
@@ -803,7 +804,7 @@ __global__ void __launch_bounds__(kMergeThreads)
   if (threadIdx.x == 0) {
     int count = 0;
     while (count < K && keys[count] != kNoKey) ++count;
-    n_found[vol] = count;
+    n_found[(long long)vol * ns + sp] = count;
   }
 }
 
@@ -818,8 +819,8 @@ size_t vpeaks_workspace_bytes(int nvol, int tiles, int K) {
 }
 
 hipError_t launch_vpeaks(const float* params, long long stride, int batch, int nz, int ny, int nx, int zimg, int K,
-                         float thr, int radius, int wrap, int keep_border, ft_plane_peak* peaks, int32_t* n_found,
-                         void* ws, hipStream_t s) {
+                         float thr, int radius, int wrap, int keep_border, int ns, int sp, int space_id,
+                         ft_plane_peak* peaks, int32_t* n_found, void* ws, hipStream_t s) {
   const VolGeom g{nz, ny, nx, zimg, stride};
   const int tiles = vpeaks_tiles(nz, ny, nx);
   uint64_t* cand = static_cast<uint64_t*>(ws);
@@ -832,7 +833,7 @@ hipError_t launch_vpeaks(const float* params, long long stride, int batch, int n
   const uint64_t* list = nullptr;
   e = reduce_lists(cand, batch, tiles, K, &list, s);
   if (e != hipSuccess) return e;
-  k_vpeaks_records<<<batch, kMergeThreads, 0, s>>>(params, g, K, list, peaks, n_found);
+  k_vpeaks_records<<<batch, kMergeThreads, 0, s>>>(params, g, K, list, ns, sp, space_id, peaks, n_found);
   return hipGetLastError();
 }
 

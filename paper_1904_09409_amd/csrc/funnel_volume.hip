@@ -156,6 +156,41 @@ hipError_t launch_ycol_t(int variant, float2* data, int Lz, int h, int nx, long 
   return hipErrorInvalidValue;
 }
 
+// The y space of a volume (depth y, rows z, columns x) reads its lines
+// along y as contiguous rows: each slice [Ny][Nx] is transposed to [Nx][Ny]
+// through a 64 x 64 LDS tile (coalesced 256-byte row reads and writes; one
+// pad column keeps the transposed reads off a single bank).
+constexpr int kTpTile = 64, kTpThreads = 256;
+
+__global__ void __launch_bounds__(kTpThreads)
+    k_transpose_slices(const float* __restrict__ in, float* __restrict__ out, int slices, int ny, int nx) {
+  __shared__ float tile[kTpTile][kTpTile + 1];
+  const int x0 = blockIdx.x * kTpTile, y0 = blockIdx.y * kTpTile;
+  const int tx = threadIdx.x % kTpTile, ty = threadIdx.x / kTpTile;
+  for (int sl = blockIdx.z; sl < slices; sl += gridDim.z) {   // same count for every thread of the block
+    const long long base = (long long)sl * ny * nx;
+#pragma unroll
+    for (int r = ty; r < kTpTile; r += kTpThreads / kTpTile) {
+      const int y = y0 + r, x = x0 + tx;
+      tile[r][tx] = (y < ny && x < nx) ? in[base + (long long)y * nx + x] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = ty; r < kTpTile; r += kTpThreads / kTpTile) {
+      const int x = x0 + r, y = y0 + tx;
+      if (x < nx && y < ny) out[base + (long long)x * ny + y] = tile[tx][r];
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_transpose_slices(const float* in, float* out, int slices, int ny, int nx, hipStream_t s) {
+  if (slices <= 0) return hipSuccess;
+  dim3 grid((nx + kTpTile - 1) / kTpTile, (ny + kTpTile - 1) / kTpTile, slices < 65535 ? slices : 65535);
+  k_transpose_slices<<<grid, kTpThreads, 0, s>>>(in, out, slices, ny, nx);
+  return hipGetLastError();
+}
+
 unsigned ycol_variant_mask(int L) {
   switch (L) {
 #define CASE(n) case n: return ycol_variant_mask_t<n>();

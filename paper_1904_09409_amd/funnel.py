@@ -34,6 +34,11 @@ FT_PREC_FP32 = 0
 FT_PREC_BF16X3 = 1
 FT_PREC_FP16X3 = 2
 FT_PLAN_NVMT_CHIRPZ = 1
+FT_VOL_SPACE_Z = 1
+FT_VOL_SPACE_X = 2
+FT_VOL_SPACE_Y = 4
+FT_VOL_SPACE_ALL = 7
+VOLUME_SPACE_NAMES = ("z", "x", "y")
 FT_PEAK_CLAMP_BORDER = 1
 FT_PEAK_KEEP_PAD_BOUNDARY = 2
 FT_GRAPH_FORWARD = 1
@@ -53,7 +58,8 @@ class ft_image_desc(ctypes.Structure):
 
 class ft_volume_desc(ctypes.Structure):
     _fields_ = [("batch", ctypes.c_int32), ("depth", ctypes.c_int32), ("rows", ctypes.c_int32),
-                ("cols", ctypes.c_int32), ("padded_len", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("cols", ctypes.c_int32), ("padded_len", ctypes.c_int32), ("spaces", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
 
 
 class ft_kernel_time(ctypes.Structure):
@@ -75,9 +81,10 @@ LINE_CHECK_WORDS = LINE_CHECK_DTYPE.itemsize // 4   # 10 x 4 bytes
 REFINED_DTYPE = np.dtype([("col", np.float32), ("row", np.float32), ("value", np.float32), ("slope", np.float32),
                           ("intercept", np.float32), ("shift", np.float32)])
 REFINED_WORDS = REFINED_DTYPE.itemsize // 4   # 6 x 4 bytes
-PLANE_PEAK_DTYPE = np.dtype([("volume", np.int32), ("z", np.int32), ("row", np.int32), ("col", np.int32),
-                             ("value", np.float32), ("a", np.float32), ("b", np.float32), ("c", np.float32)])
-PLANE_PEAK_WORDS = PLANE_PEAK_DTYPE.itemsize // 4   # 8 x 4 bytes
+PLANE_PEAK_DTYPE = np.dtype([("volume", np.int32), ("space", np.int32), ("z", np.int32), ("row", np.int32),
+                             ("col", np.int32), ("value", np.float32), ("a", np.float32), ("b", np.float32),
+                             ("c", np.float32)])
+PLANE_PEAK_WORDS = PLANE_PEAK_DTYPE.itemsize // 4   # 9 x 4 bytes
 
 
 class FunnelError(RuntimeError):
@@ -127,6 +134,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "funnel_volume_plan_destroy": ([vp], None),
         "funnel_volume_padded_len": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
         "funnel_volume_workspace_size": ([vp, ctypes.POINTER(sz)], ctypes.c_int),
+        "funnel_volume_param_elems": ([vp, ctypes.POINTER(sz)], ctypes.c_int),
         "funnel_volume_forward": ([vp, vp, vp, vp, sz, vp], ctypes.c_int),
         "funnel_volume_peaks_workspace_size": ([vp, i32, ctypes.POINTER(sz)], ctypes.c_int),
         "funnel_volume_peaks": ([vp, vp, i32, ctypes.c_float, i32, u32, vp, vp, vp, sz, vp], ctypes.c_int),
@@ -331,9 +339,9 @@ def funnel_plan_set_variant(plan: int, role: int, variant: int) -> None:
 # volumes (App. A)
 
 def funnel_volume_plan_create(batch: int, depth: int, rows: int, cols: int, padded_len: int = 0,
-                              flags: int = 0) -> int:
+                              spaces: int = FT_VOL_SPACE_Z, flags: int = 0) -> int:
     lib = load_library()
-    d = ft_volume_desc(batch, depth, rows, cols, padded_len, flags)
+    d = ft_volume_desc(batch, depth, rows, cols, padded_len, spaces, flags)
     h = ctypes.c_void_p()
     _check(lib.funnel_volume_plan_create(ctypes.byref(d), ctypes.byref(h)), "funnel_volume_plan_create")
     return h.value
@@ -346,6 +354,12 @@ def funnel_volume_plan_destroy(plan: int) -> None:
 def funnel_volume_padded_len(plan: int) -> int:
     n = ctypes.c_int32()
     _check(load_library().funnel_volume_padded_len(plan, ctypes.byref(n)), "funnel_volume_padded_len")
+    return n.value
+
+
+def funnel_volume_param_elems(plan: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().funnel_volume_param_elems(plan, ctypes.byref(n)), "funnel_volume_param_elems")
     return n.value
 
 
@@ -375,8 +389,9 @@ def funnel_volume_peaks(plan: int, params, K: int, threshold: float, radius: int
 
 
 def funnel_volume_variants(plan: int) -> list[int]:
-    arr = (ctypes.c_int32 * 4)()
-    _check(load_library().funnel_volume_variants(plan, arr, 4), "funnel_volume_variants")
+    """Tile variant of each role, 4 per space (z, x, y), -1 for spaces the plan does not compute."""
+    arr = (ctypes.c_int32 * 12)()
+    _check(load_library().funnel_volume_variants(plan, arr, 12), "funnel_volume_variants")
     return list(arr)
 
 
@@ -697,16 +712,22 @@ def funnel_transform(images, plan: FunnelPlan):
 
 class VolumePlan:
     """A volume plan (App. A) plus its workspace for a fixed batch shape on
-    the current device."""
+    the current device.  ``spaces``: FT_VOL_SPACE_Z (planes within 45 degrees
+    of the z axis), _X, _Y or FT_VOL_SPACE_ALL."""
 
-    def __init__(self, batch: int, depth: int, rows: int, cols: int, padded_len: int = 0):
+    def __init__(self, batch: int, depth: int, rows: int, cols: int, padded_len: int = 0,
+                 spaces: int = FT_VOL_SPACE_Z):
         import torch
-        self.batch, self.Nz, self.Ny, self.Nx = batch, depth, rows, cols
-        self.handle = funnel_volume_plan_create(batch, depth, rows, cols, padded_len)
-        self.Nzp = funnel_volume_padded_len(self.handle)
+        self.batch, self.Nz, self.Ny, self.Nx, self.spaces = batch, depth, rows, cols, spaces
+        self.handle = funnel_volume_plan_create(batch, depth, rows, cols, padded_len, spaces)
+        self.Lp = self.Nzp = funnel_volume_padded_len(self.handle)
+        self.param_elems = funnel_volume_param_elems(self.handle)
         self.device = torch.device("cuda", torch.cuda.current_device())
         ws = funnel_volume_workspace_size(self.handle)
         self.ws = torch.empty(max(ws, 256), dtype=torch.uint8, device=self.device)
+        # (name, rows, cols) of the spaces computed, in their order in the parameter block
+        geo = {"z": (depth, rows, cols), "x": (cols, depth, rows), "y": (rows, depth, cols)}
+        self.space_list = [(n, geo[n][1], geo[n][2]) for i, n in enumerate(VOLUME_SPACE_NAMES) if spaces & (1 << i)]
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -717,9 +738,22 @@ class VolumePlan:
                 pass
             self.handle = None
 
+    @property
+    def nspaces(self) -> int:
+        return len(self.space_list)
+
     def new_params(self):
         import torch
-        return torch.empty((self.batch, self.Nzp, self.Ny, self.Nx), dtype=torch.float32, device=self.device)
+        return torch.empty((self.batch, self.param_elems), dtype=torch.float32, device=self.device)
+
+    def views(self, params) -> dict:
+        """Per space name, the parameter volumes as [B, Lp, rows, cols] views."""
+        out, off = {}, 0
+        for name, r, c in self.space_list:
+            n = self.Lp * r * c
+            out[name] = params[:, off:off + n].view(self.batch, self.Lp, r, c)
+            off += n
+        return out
 
     def forward(self, volumes, params=None, stream=None):
         import torch
@@ -733,21 +767,22 @@ class VolumePlan:
         return params
 
     def peaks(self, params, K: int = 16, threshold: float = 0.0, radius: int = 1, flags: int = 0, stream=None):
-        """Returns (records int32 [B, K, 8] on the device, counts int32 [B])."""
+        """Returns (records int32 [B, nspaces, K, 9] on the device, counts int32 [B, nspaces])."""
         import torch
         ws = torch.empty(max(funnel_volume_peaks_workspace_size(self.handle, K), 256), dtype=torch.uint8,
                          device=self.device)
-        rec = torch.empty((self.batch, K, PLANE_PEAK_WORDS), dtype=torch.int32, device=self.device)
-        cnt = torch.empty((self.batch,), dtype=torch.int32, device=self.device)
+        rec = torch.empty((self.batch, self.nspaces, K, PLANE_PEAK_WORDS), dtype=torch.int32, device=self.device)
+        cnt = torch.empty((self.batch, self.nspaces), dtype=torch.int32, device=self.device)
         funnel_volume_peaks(self.handle, params, K, threshold, radius, flags, rec, cnt, ws, stream)
         return rec, cnt
 
     def autotune(self, stream=None) -> list[dict]:
-        return funnel_volume_autotune(self.handle, stream)
+        return funnel_volume_autotune(self.handle, stream, cap=12)
 
 
 def plane_peaks_to_numpy(rec, cnt):
-    """Device plane-peak records -> list (per volume) of numpy records."""
+    """Device plane-peak records -> list (per volume) of lists (per space) of numpy records."""
     r = rec.cpu().numpy()
     c = cnt.cpu().numpy()
-    return [np.ascontiguousarray(r[b, :c[b]]).view(PLANE_PEAK_DTYPE).reshape(-1) for b in range(r.shape[0])]
+    return [[np.ascontiguousarray(r[b, s, :c[b, s]]).view(PLANE_PEAK_DTYPE).reshape(-1) for s in range(r.shape[1])]
+            for b in range(r.shape[0])]

@@ -125,7 +125,7 @@ def test_graph_null_arguments(lib):
 
 
 def _vcreate(lib, **kw):
-    d = dict(batch=1, depth=64, rows=64, cols=64, padded_len=0, flags=0)
+    d = dict(batch=1, depth=64, rows=64, cols=64, padded_len=0, spaces=F.FT_VOL_SPACE_Z, flags=0)
     d.update(kw)
     desc = F.ft_volume_desc(**d)
     h = ctypes.c_void_p(4242)
@@ -145,6 +145,10 @@ def _vcreate(lib, **kw):
     (dict(rows=40), F.FT_ERR_UNSUPPORTED_SIZE),         # no y' pass kernel for 40
     (dict(depth=60, rows=64, cols=64), F.FT_ERR_UNSUPPORTED_SIZE),   # padded depth 188 has no kernel
     (dict(depth=1024, rows=1024, cols=1024), F.FT_ERR_UNSUPPORTED_SIZE),   # parameter volume beyond 2 GiB
+    (dict(spaces=0), F.FT_ERR_INVALID_ARG),
+    (dict(spaces=8), F.FT_ERR_INVALID_ARG),
+    (dict(depth=40, rows=160, cols=40, spaces=F.FT_VOL_SPACE_X), F.FT_ERR_UNSUPPORTED_SIZE),   # x space: rows 40
+    (dict(depth=40, rows=160, cols=40, spaces=F.FT_VOL_SPACE_Y), F.FT_ERR_UNSUPPORTED_SIZE),   # y space: rows 40
 ])
 def test_volume_plan_create_rejects(lib, kw, code):
     st, h = _vcreate(lib, **kw)
@@ -168,6 +172,8 @@ def test_valid_volume_plan_without_device(lib):
     import torch
     if torch.cuda.is_available():
         pytest.skip("a GPU is visible")
-    for kw in (dict(), dict(depth=256, rows=256, cols=256), dict(depth=32, rows=48, cols=16, padded_len=0)):
+    for kw in (dict(), dict(depth=256, rows=256, cols=256, spaces=F.FT_VOL_SPACE_ALL),
+               dict(depth=32, rows=48, cols=16, padded_len=0), dict(depth=40, rows=160, cols=40),
+               dict(depth=64, rows=32, cols=64, spaces=F.FT_VOL_SPACE_X | F.FT_VOL_SPACE_Y)):
         st, h = _vcreate(lib, batch=2, **kw)
         assert st == F.FT_ERR_NO_DEVICE, (kw, F.last_error())

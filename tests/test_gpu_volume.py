@@ -45,6 +45,7 @@ def test_every_volume_variant_matches_oracle(B, Nz, Ny, Nx, pad):
     plan = F.VolumePlan(B, Nz, Ny, Nx, pad)
     refs = [O.forward_volume(v.volume.astype(np.float64), pad) for v in vols[:2]]
     defaults = F.funnel_volume_variants(plan.handle)
+    assert defaults[4:] == [-1] * 8          # z space only
     tried = 0
     for role in (ROW_ROLE, YCOL_ROLE):
         for v in range(12):
@@ -53,7 +54,7 @@ def test_every_volume_variant_matches_oracle(B, Nz, Ny, Nx, pad):
             except F.FunnelError:
                 continue
             tried += 1
-            P = plan.forward(x)
+            P = plan.views(plan.forward(x))["z"]
             torch.cuda.synchronize()
             got = P.cpu().numpy()
             worst = max(rel_l2(got[b], refs[b]) for b in range(len(refs)))
@@ -75,7 +76,8 @@ def test_volume_workload_256():
     plan = F.VolumePlan(B, N, N, N)
     for r in plan.autotune():
         say(f"  tuned {r['name']}: variant {r['variant']} of {r['n_tried']} ({r['ms']:.3f} ms chain)")
-    P = plan.forward(x)
+    params = plan.forward(x)
+    P = plan.views(params)["z"]
     torch.cuda.synchronize()
     rng = np.random.default_rng(7)
     lines = [(int(r), int(c)) for r, c in zip(rng.integers(0, N, 6), rng.integers(0, N, 6))] + [(N // 2, N // 2)]
@@ -87,13 +89,13 @@ def test_volume_workload_256():
         assert e <= TOL
     # every sheet of every volume is detected within one cell of its Eq. A.9 cell
     from pins import expected_cell_volume, torus_dist
-    rec, cnt = plan.peaks(P, K=16)
+    rec, cnt = plan.peaks(params, K=16)
     got = F.plane_peaks_to_numpy(rec, cnt)
     for b, v in enumerate(vols):
         for sh in v.sheets:
             z, r, c = expected_cell_volume(sh, N, N, N, plan.Nzp)
             assert any(torus_dist(int(g["z"]), z, plan.Nzp) <= 1 and torus_dist(int(g["row"]), r, N) <= 1
-                       and torus_dist(int(g["col"]), c, N) <= 1 for g in got[b]), (b, sh, (z, r, c))
+                       and torus_dist(int(g["col"]), c, N) <= 1 for g in got[b][0]), (b, sh, (z, r, c))
         say(f"  volume {b}: all {len(v.sheets)} sheets among the first 16 peaks")
 
 
@@ -114,10 +116,10 @@ def test_volume_peaks_exact_on_shared_volume(shape, radius, flags):
     vols = volumes(B, Nz, Ny, Nx, 2)
     x = torch.from_numpy(np.stack([v.volume for v in vols])).cuda()
     plan = F.VolumePlan(B, Nz, Ny, Nx)
-    P = plan.forward(x)
-    rec, cnt = plan.peaks(P, K=K, threshold=0.0, radius=radius, flags=flags)
-    got = F.plane_peaks_to_numpy(rec, cnt)
-    Ph = P.abs().cpu().numpy().astype(np.float64)
+    params = plan.forward(x)
+    rec, cnt = plan.peaks(params, K=K, threshold=0.0, radius=radius, flags=flags)
+    got = [g[0] for g in F.plane_peaks_to_numpy(rec, cnt)]
+    Ph = plan.views(params)["z"].abs().cpu().numpy().astype(np.float64)
     mask = None if flags & F.FT_PEAK_KEEP_PAD_BOUNDARY else O.volume_boundary_mask(Nz, Ny, Nx, plan.Nzp)
     for b in range(B):
         want = O.peaks_list_volume(Ph[b], K, 0.0, radius, mask, wrap=not (flags & F.FT_PEAK_CLAMP_BORDER))
@@ -157,9 +159,10 @@ def test_volume_peaks_find_the_planes():
     vols = volumes(B, Nz, Ny, Nx, 3)
     x = torch.from_numpy(np.stack([v.volume for v in vols])).cuda()
     plan = F.VolumePlan(B, Nz, Ny, Nx)
-    P = plan.forward(x)
-    rec, cnt = plan.peaks(P, K=K)
-    got = F.plane_peaks_to_numpy(rec, cnt)
+    params = plan.forward(x)
+    P = plan.views(params)["z"]
+    rec, cnt = plan.peaks(params, K=K)
+    got = [g[0] for g in F.plane_peaks_to_numpy(rec, cnt)]
     mask = O.volume_boundary_mask(Nz, Ny, Nx, plan.Nzp)
     for b, v in enumerate(vols):
         Po = np.abs(O.forward_volume(v.volume.astype(np.float64)))
@@ -204,3 +207,113 @@ def test_volume_profile_and_errors():
     small = torch.empty(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(F.FunnelError):
         F.funnel_volume_forward(plan.handle, x, plan.new_params(), small)
+    with pytest.raises(F.FunnelError):
+        F.funnel_volume_set_variant(plan.handle, 5, 0)   # x space: not computed by this plan
+    plan3 = F.VolumePlan(2, 32, 32, 32, spaces=F.FT_VOL_SPACE_ALL)
+    F.funnel_volume_profile_enable(plan3.handle, 32)
+    plan3.forward(x)
+    names = {r["name"] for r in F.funnel_volume_profile_read(plan3.handle)}
+    F.funnel_volume_profile_disable(plan3.handle)
+    assert names == {f"volume.{s}{r}" for s in ("", "x.", "y.") for r in ("A", "Bx", "By", "C")} | {"volume.y.T"}
+
+
+# ---------------------------------------------------------------- x and y spaces
+
+def world_sheet(space, sh, Nz, Ny, Nx, rng):
+    """A sheet of the given space (depth = a col + b row + c in that space's
+    axes) rendered in the world volume [Nz, Ny, Nx], background 0."""
+    frame = {"z": ((Nz, Ny, Nx), (0, 1, 2)), "x": ((Nx, Nz, Ny), (1, 2, 0)), "y": ((Ny, Nz, Nx), (1, 0, 2))}
+    (D, R, C), back = frame[space]
+    return np.transpose(synth.render_volume(D, R, C, [sh], 0.0, rng, bg=0.0), back)
+
+
+@pytest.mark.parametrize("B,Nz,Ny,Nx", [(2, 64, 32, 64), (2, 48, 96, 96)])
+def test_volume_spaces_match_oracle(B, Nz, Ny, Nx):
+    """All three spaces against the oracle's transform of the volume in each
+    space's axis order, for every x' and y' tile variant of the x and y
+    spaces (whose rows and columns are the volume's other axes)."""
+    import torch
+    say(f"volume spaces {B} x {Nz}x{Ny}x{Nx}")
+    vols = volumes(B, Nz, Ny, Nx, 4)
+    x = torch.from_numpy(np.stack([v.volume for v in vols])).cuda()
+    plan = F.VolumePlan(B, Nz, Ny, Nx, spaces=F.FT_VOL_SPACE_ALL)
+    assert [n for n, _, _ in plan.space_list] == ["z", "x", "y"]
+    refs = {n: [O.forward_volume_space(v.volume.astype(np.float64), n) for v in vols] for n in ("z", "x", "y")}
+    defaults = F.funnel_volume_variants(plan.handle)
+    assert min(defaults) >= 0
+    tried = 0
+    for role in (5, 6, 9, 10):   # x space Bx, By; y space Bx, By
+        for v in range(12):
+            try:
+                F.funnel_volume_set_variant(plan.handle, role, v)
+            except F.FunnelError:
+                continue
+            tried += 1
+            views = plan.views(plan.forward(x))
+            torch.cuda.synchronize()
+            worst = max(rel_l2(views[n][b].cpu().numpy(), refs[n][b]) for n in ("z", "x", "y") for b in range(B))
+            say(f"  role {role} variant {v}: worst rel L2 over the spaces {worst:.2e}")
+            assert worst <= TOL, (role, v, worst)
+        F.funnel_volume_set_variant(plan.handle, role, defaults[role])
+    assert tried >= 6
+
+
+def test_volume_steep_planes_found():
+    """One sheet of each orientation in one volume: the z sheet focuses in
+    the z space, the steep ones (x = a y + b z + c, y = a x + b z + c) in the x
+    and y spaces, each within one cell of its Eq. A.9 cell and among the
+    first four peaks of its space; plane parameters read back within a cell."""
+    import torch
+    from pins import expected_cell_volume, torus_dist
+    Nz, Ny, Nx = 64, 32, 64
+    rng = np.random.default_rng(93)
+    geo = {"z": (Nz, Ny, Nx), "x": (Nx, Nz, Ny), "y": (Ny, Nz, Nx)}
+    sheets = {}
+    vol = np.zeros((Nz, Ny, Nx))
+    for n, (D, R, C) in geo.items():
+        a, b = float(rng.uniform(-0.7, 0.7)), float(rng.uniform(-0.7, 0.7))
+        dc = float(rng.uniform(0.4 * D, 0.6 * D))
+        sheets[n] = synth.Sheet(a, b, dc - a * C / 2 - b * R / 2, 1.0)
+        vol += world_sheet(n, sheets[n], Nz, Ny, Nx, rng)
+    vol = (vol + rng.normal(0.0, 0.02, vol.shape)).astype(np.float32)
+    plan = F.VolumePlan(1, Nz, Ny, Nx, spaces=F.FT_VOL_SPACE_ALL)
+    params = plan.forward(torch.from_numpy(vol[None].copy()).cuda())
+    rec, cnt = plan.peaks(params, K=4)
+    got = F.plane_peaks_to_numpy(rec, cnt)[0]
+    for si, n in enumerate(("z", "x", "y")):
+        D, R, C = geo[n]
+        z, r, c = expected_cell_volume(sheets[n], D, R, C, plan.Lp)
+        hit = [g for g in got[si] if torus_dist(int(g["z"]), z, plan.Lp) <= 1 and torus_dist(int(g["row"]), r, R) <= 1
+               and torus_dist(int(g["col"]), c, C) <= 1]
+        assert hit and int(hit[0]["space"]) == si, (n, (z, r, c), got[si])
+        sh = sheets[n]
+        say(f"  {n} space: sheet a={sh.a:.3f} b={sh.b:.3f} c={sh.c:.2f} -> peak a={hit[0]['a']:.3f} "
+            f"b={hit[0]['b']:.3f} c={hit[0]['c']:.2f}")
+        # within one cell of the rounded cell: half a bin of rounding plus one bin
+        assert abs(hit[0]["a"] - sh.a) <= 3.0 / C + 1e-6 and abs(hit[0]["b"] - sh.b) <= 3.0 / R + 1e-6
+
+
+def test_volume_peaks_exact_all_spaces():
+    """Each space's 3D peak list equals the oracle's list procedure on that
+    space's (GPU) parameter volumes, with that space's face cells."""
+    import torch
+    B, Nz, Ny, Nx, K = 2, 48, 96, 96, 12
+    vols = volumes(B, Nz, Ny, Nx, 5)
+    x = torch.from_numpy(np.stack([v.volume for v in vols])).cuda()
+    plan = F.VolumePlan(B, Nz, Ny, Nx, spaces=F.FT_VOL_SPACE_ALL)
+    params = plan.forward(x)
+    views = plan.views(params)
+    rec, cnt = plan.peaks(params, K=K)
+    got = F.plane_peaks_to_numpy(rec, cnt)
+    depth = {"z": Nz, "x": Nx, "y": Ny}
+    for si, (n, R, C) in enumerate(plan.space_list):
+        Ph = views[n].abs().cpu().numpy().astype(np.float64)
+        mask = O.volume_boundary_mask(depth[n], R, C, plan.Lp)
+        for b in range(B):
+            want = O.peaks_list_volume(Ph[b], K, 0.0, 1, mask, True)
+            idx = [(int(g["z"]) * R + int(g["row"])) * C + int(g["col"]) for g in got[b][si]]
+            assert idx == want, (n, b, idx[:4], want[:4])
+            assert all(int(g["space"]) == si and int(g["volume"]) == b for g in got[b][si])
+            for g in got[b][si]:
+                a, bb, c = O.plane_params(int(g["z"]), int(g["row"]), int(g["col"]), depth[n], R, C, plan.Lp)
+                assert abs(g["a"] - a) <= 1e-6 and abs(g["b"] - bb) <= 1e-6 and abs(g["c"] - c) <= 1e-4 * max(1, abs(c))
