@@ -9,8 +9,9 @@
 // its local maximum near a detected cell are continuous, which is where
 // Eq. 19 focuses a line.  The rows g are the inverse x' DFT of the G rows a
 // forward pass leaves in the workspace.  Each iteration forms, for every
-// peak, A and its first two m-derivatives over all rows (k_refine_dtft: a
-// (rows x W) by (W x peaks) product per plane), then reduces over n2 into P,
+// peak, A and its first two m-derivatives over all rows (k_refine_dtft_mfma:
+// a (rows x W) by (W x peaks) product per plane on the matrix cores), then
+// reduces over n2 into P,
 // its gradient and Hessian and takes one safeguarded Newton step
 // (k_refine_step).
 #include <hip/hip_runtime.h>
@@ -124,69 +125,151 @@ __global__ void k_refine_init(const ft_peak* __restrict__ peaks, const int32_t* 
 // For rows n2 of one space and peaks p of a group of 16:
 //   A0 = sum_x' g e_p,  S1 = sum_x' x' g e_p,  S2 = sum_x' x'^2 g e_p,
 // e_p(x') = exp(-j 2 pi m_p x' / W), centred x'.  A1 = (-j 2 pi / W) S1 and
-// A2 = -(2 pi / W)^2 S2 are the first two m-derivatives of A0.
+// A2 = -(2 pi / W)^2 S2 are the first two m-derivatives of A0.  The phase
+// m x'/W is split as (m0 x' mod W)/W + u x'/W with the start cell m0 and
+// |u| <= 1, so the large part is exact in integers.
 // Output layout: A[((img * ns + s) * K + p) * 3 + d][n2 - 1], d = A0, S1, S2.
-constexpr int kRefRows = 16, kRefPeaks = 16, kRefChunk = 64;
+constexpr int kRefPeaks = 16;
 
-__global__ void __launch_bounds__(256)
-    k_refine_dtft(const float2* __restrict__ g, long long img_stride, int h, int W, int s, int ns, int K,
-                  const int32_t* __restrict__ n_found, const RefState* __restrict__ st, float2* __restrict__ A) {
-  __shared__ float2 gt[kRefRows][kRefChunk + 1];
-  __shared__ float2 et[kRefPeaks][kRefChunk + 1];
+// The sums are a matrix product, computed on the matrix cores.  Per image,
+// with k = 2x' + c (c = 0:
+// real part, 1: imaginary part of g[n2][x']), they are one real product
+//   C[n2][o] = sum_k Gr[n2][k] B[k][o],  o < 48: real parts, o >= 48:
+//   imaginary parts of the 48 complex sums (3 per peak: e, x' e, x'^2 e),
+// B[2x'][o] = (Re, Im) of the weight, B[2x'+1][o] = (-Im, Re).  A block
+// takes 128 rows; each of its four waves 32 rows x 96 columns as three
+// 32 x 32 FP32 accumulators (v_mfma_f32_32x32x2f32, one x' per instruction).
+// Chunks of 32 samples are double-buffered in LDS: while a chunk is
+// multiplied, the next chunk's g (loaded into registers one chunk earlier)
+// and weights (the phase reduced exactly in integers as above) are written
+// to the other buffer, so there is one barrier per chunk and the staging
+// work sits between the matrix instructions.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kMRows = 128, kMChunk = 32, kMThreads = 256, kMCols = 3 * kRefPeaks;   // 48 complex columns
+
+__global__ void __launch_bounds__(kMThreads)
+    k_refine_dtft_mfma(const float2* __restrict__ g, long long img_stride, int h, int W, int s, int ns, int K,
+                       const int32_t* __restrict__ n_found, const RefState* __restrict__ st, float2* __restrict__ A) {
+  __shared__ float2 gt[2][kMRows][kMChunk + 1];   // rows x samples of g (as floats: k = 2x' + c)
+  __shared__ float bt[2][2 * kMChunk][2 * kMCols + 1];   // the real weight matrix B[k][o] of a chunk
   __shared__ float pm[kRefPeaks];
   __shared__ int pm0[kRefPeaks];
   const int img = blockIdx.y, grp = blockIdx.z;
-  const int n2a = blockIdx.x * kRefRows + 1;
-  const int tid = threadIdx.x;
-  const int lr = tid / kRefPeaks, lp = tid % kRefPeaks;
+  const int r0 = blockIdx.x * kMRows;          // first row (n2 - 1) of the block
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cnt = n_found[img * ns + s];
-  if (grp * kRefPeaks >= cnt) return;   // uniform: no peaks in this group
+  if (grp * kRefPeaks >= cnt) return;          // uniform: no peaks in this group
   const long long sbase = ((long long)img * ns + s) * K;
   if (tid < kRefPeaks) {
     const int p = grp * kRefPeaks + tid;
     const RefState r = p < cnt ? st[sbase + p] : RefState{0.f, 0.f, 0.f, 0.f, 0.f};
     pm0[tid] = (int)r.m0;
-    pm[tid] = r.m - r.m0;   // |u| <= 1: the offset from the start cell
+    pm[tid] = r.m - r.m0;
   }
-  __syncthreads();
   const float2* gimg = g + (long long)img * img_stride;
-  float2 a0 = make_float2(0.f, 0.f), s1 = a0, s2 = a0;
-  for (int x0 = 0; x0 < W; x0 += kRefChunk) {
-    // stage 16 rows x 64 samples of g and the 16 x 64 phase factors
-    for (int i = tid; i < kRefRows * kRefChunk; i += 256) {
-      const int r = i / kRefChunk, j = i % kRefChunk;
-      const int n2 = n2a + r;
-      gt[r][j] = n2 <= h ? gimg[(long long)(n2 - 1) * W + x0 + j] : make_float2(0.f, 0.f);
-      // e_p(x') with the phase m x'/W = (m0 x' mod W)/W + u x'/W, centred x'
-      const int p = r;   // reuse the loop: 16 peaks x 64 samples
-      const int xc = x0 + j - W / 2;
+
+  // g tile of a chunk: 128 rows x 32 samples = 2048 float4 (two samples each), 8 per thread
+  constexpr int NG = kMRows * kMChunk / 2 / kMThreads;
+  float4 gr[NG];
+  auto load_g = [&](int x0) {
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      const int i = tid + kMThreads * j, row = i / (kMChunk / 2), c2 = i % (kMChunk / 2);
+      gr[j] = r0 + row < h ? *reinterpret_cast<const float4*>(gimg + (long long)(r0 + row) * W + x0 + 2 * c2)
+                           : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto store_g = [&](int buf, int j0, int j1) {   // register slots j0 .. j1-1
+#pragma unroll
+    for (int j = j0; j < j1; ++j) {
+      const int i = tid + kMThreads * j, row = i / (kMChunk / 2), c2 = i % (kMChunk / 2);
+      gt[buf][row][2 * c2] = make_float2(gr[j].x, gr[j].y);
+      gt[buf][row][2 * c2 + 1] = make_float2(gr[j].z, gr[j].w);
+    }
+  };
+  auto build_w = [&](int buf, int x0, int i) {   // weight entry i of 32 samples x 16 peaks
+    {
+      const int xl = i / kRefPeaks, p = i % kRefPeaks;
+      const int xc = x0 + xl - W / 2;
       const int whole = ((pm0[p] * xc) % W + W) % W;
       const float frac = (float)whole / (float)W + pm[p] * (float)xc / (float)W;
       float sn, cs;
       sincospif(-2.0f * frac, &sn, &cs);
-      et[p][j] = make_float2(cs, sn);
+      const float fx = (float)xc;
+      // weights e, x' e, x'^2 e as B[2x'][q] = Re, B[2x'][48 + q] = Im,
+      // B[2x' + 1][q] = -Im, B[2x' + 1][48 + q] = Re
+      float* r0w = bt[buf][2 * xl];
+      float* r1w = bt[buf][2 * xl + 1];
+      float re = cs, im = sn;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int q = 3 * p + d;
+        r0w[q] = re;
+        r0w[kMCols + q] = im;
+        r1w[q] = -im;
+        r1w[kMCols + q] = re;
+        re *= fx;
+        im *= fx;
+      }
     }
-    __syncthreads();
-#pragma unroll 8
-    for (int j = 0; j < kRefChunk; ++j) {
-      const float2 gv = gt[lr][j], ev = et[lp][j];
-      const float2 t = c_mul(gv, ev);
-      const float xc = (float)(x0 + j - W / 2);
-      a0.x += t.x;
-      a0.y += t.y;
-      s1.x = fmaf(xc, t.x, s1.x);
-      s1.y = fmaf(xc, t.y, s1.y);
-      s2.x = fmaf(xc * xc, t.x, s2.x);
-      s2.y = fmaf(xc * xc, t.y, s2.y);
+  };
+
+  f32x16 acc[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
+  static_assert(kMChunk * kRefPeaks == 2 * kMThreads && NG == 8, "staging pieces below");
+  load_g(0);
+  store_g(0, 0, NG);
+  __syncthreads();   // pm, pm0
+  build_w(0, 0, tid);
+  build_w(0, 0, tid + kMThreads);
+  if (kMChunk < W) load_g(kMChunk);
+  __syncthreads();
+
+  const int li = lane & 31, lk = lane >> 5;    // operand row / column and k of this lane
+  const int nch = W / kMChunk;
+  for (int c = 0; c < nch; ++c) {
+    const int cur = c & 1, nb = cur ^ 1;
+    const bool next = c + 1 < nch, next2 = c + 2 < nch;
+    const int x1 = (c + 1) * kMChunk, x2 = (c + 2) * kMChunk;
+    // lane (li, lk) supplies A[row li][k = 2x' + lk] and B[k = 2x' + lk][column li].
+    // The next chunk is staged into the other buffer in pieces between the
+    // products (its g from registers, then the loads of the chunk after it,
+    // then its weights), so that this work issues while the matrix core runs.
+    const float* ga = reinterpret_cast<const float*>(&gt[cur][32 * wave + li][0]) + lk;
+#pragma unroll
+    for (int xl = 0; xl < kMChunk; ++xl) {
+      const float a = ga[2 * xl];
+      const float* bk = bt[cur][2 * xl + lk] + li;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bk[32 * t], acc[t], 0, 0, 0);
+      if (next) {
+        if (xl == 2) store_g(nb, 0, 4);
+        if (xl == 6) store_g(nb, 4, 8);
+        if (xl == 10 && next2) load_g(x2);
+        if (xl == 16) build_w(nb, x1, tid);
+        if (xl == 24) build_w(nb, x1, tid + kMThreads);
+      }
     }
     __syncthreads();
   }
-  const int p = grp * kRefPeaks + lp, n2 = n2a + lr;
-  if (p >= cnt || n2 > h) return;
-  float2* dst = A + (sbase + p) * 3 * (long long)h + (n2 - 1);
-  dst[0] = a0;
-  dst[h] = s1;
-  dst[2 * (long long)h] = s2;
+
+  // D[i][j] of a 32 x 32 accumulator: column j = lane mod 32, row
+  // i = 8 (v / 4) + 4 (lane / 32) + v mod 4 for register v
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const int o = 32 * t + li, q = o % kMCols, comp = o / kMCols;
+    const int p = grp * kRefPeaks + q / 3, d = q % 3;
+    if (p >= cnt) continue;
+    float* dst = reinterpret_cast<float*>(A + ((sbase + p) * 3 + d) * (long long)h) + comp;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = r0 + 32 * wave + 8 * (v / 4) + 4 * lk + (v % 4);
+      if (row < h) dst[2 * (long long)row] = acc[t][v];
+    }
+  }
 }
 
 // ------------------------------------------------------------------ the Newton step
@@ -296,8 +379,9 @@ hipError_t launch_refine_iter(const float2* g, long long img_stride, int h, int 
                               const int32_t* n_found, void* state, float2* A, int Np, int space_id, int N, int M,
                               int final, ft_refined* out, hipStream_t st) {
   RefState* sv = static_cast<RefState*>(state);
-  dim3 g1((h + kRefRows - 1) / kRefRows, batch, (K + kRefPeaks - 1) / kRefPeaks);
-  k_refine_dtft<<<g1, 256, 0, st>>>(g, img_stride, h, W, s, ns, K, n_found, sv, A);
+  if (W % kMChunk != 0) return hipErrorInvalidValue;   // every refinement length is a multiple of the chunk
+  dim3 g1((h + kMRows - 1) / kMRows, batch, (K + kRefPeaks - 1) / kRefPeaks);
+  k_refine_dtft_mfma<<<g1, kMThreads, 0, st>>>(g, img_stride, h, W, s, ns, K, n_found, sv, A);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_refine_step<<<dim3(K, batch), 256, 0, st>>>(A, h, Np, W, s, ns, K, space_id, N, M, n_found, sv, final, out);
