@@ -53,6 +53,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="the CPU oracle sample takes whole images until this much time has passed")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default tile variants")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the tile variants on this GPU even where a committed counter table names the "
+                         "variants it measured (the default starts from those, so that its traffic applies)")
     ap.add_argument("--variants", type=str, default="",
                     help="comma-separated tile variant per launch (role order of funnel_plan_variants); "
                          "skips the autotuner, so counter runs time the variants a timed run picked")
@@ -91,8 +94,10 @@ def main():
     plan = F.FunnelPlan(B, N, M, 0, F.FT_SPACE_BOTH, nvmt=nvmt)
     Np = plan.Np
     tuned = None
-    if args.variants:
-        for role, v in enumerate(int(t) for t in args.variants.split(",")):
+    measured = None if (args.variants or args.autotune or args.no_autotune) else measured_variants(nvmt, ROLES_2D)
+    if args.variants or measured:
+        vs = [int(t) for t in args.variants.split(",")] if args.variants else measured
+        for role, v in enumerate(vs):
             F.funnel_plan_set_variant(plan.handle, role, v)
     elif not args.no_autotune:
         tuned = F.funnel_autotune(plan.handle)   # set-up, outside the timed region
@@ -143,11 +148,8 @@ def main():
     step_kernel_ms = sum(k["total_ms"] for k in kernels) / args.steps
 
     copy_gbps, copy_ms = copy_bandwidth(torch)
-    roles = ["fwd.regular.A", "fwd.regular.B", "fwd.regular.C", "fwd.inverse.A", "fwd.inverse.B", "fwd.inverse.C",
-             "adj.regular.Ct", "adj.regular.Bt", "adj.regular.At", "adj.inverse.Ct", "adj.inverse.Bt",
-             "adj.inverse.At"]
     variants = F.funnel_plan_variants(plan.handle)
-    traffic = measured_traffic(dom["name"], variants[roles.index(dom["name"])], nvmt)
+    traffic = measured_traffic(dom["name"], variants[ROLES_2D.index(dom["name"])], nvmt)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -195,6 +197,7 @@ def main():
         "cpu_baseline": cpu,
         "tile_variants": variants,
         "autotuned": tuned is not None,
+        "variants_from": "counter table" if measured else ("autotuner" if tuned is not None else "given"),
     }
     print(json.dumps(out), flush=True)
 
@@ -393,8 +396,10 @@ def volume_bench(args, torch, F, synth, B=4, N=256, K=16):
     log(f"  {time.time() - t0:.1f} s")
     plan = F.VolumePlan(B, N, N, N, spaces=F.FT_VOL_SPACE_ALL)
     tuned = None
-    if args.variants:
-        for role, v in enumerate(int(t) for t in args.variants.split(",")):
+    measured = None if (args.variants or args.autotune or args.no_autotune) else measured_variants("volume", ROLES_VOL)
+    if args.variants or measured:
+        vs = [int(t) for t in args.variants.split(",")] if args.variants else measured
+        for role, v in enumerate(vs):
             if v >= 0:
                 F.funnel_volume_set_variant(plan.handle, role, v)
     elif not args.no_autotune:
@@ -440,9 +445,8 @@ def volume_bench(args, torch, F, synth, B=4, N=256, K=16):
     dom = kernels[0]
     fwd_bytes = sum(k["bytes_per_launch"] * k["launches"] for k in kernels) / args.steps
     fwd_ms = sum(k["total_ms"] for k in kernels) / args.steps
-    roles = [f"volume.{s}{r}" for s in ("", "x.", "y.") for r in ("A", "Bx", "By", "C")]
     variants = F.funnel_volume_variants(plan.handle)
-    traffic = measured_traffic(dom["name"], variants[roles.index(dom["name"])] if dom["name"] in roles else -1,
+    traffic = measured_traffic(dom["name"], variants[ROLES_VOL.index(dom["name"])] if dom["name"] in ROLES_VOL else -1,
                                "volume")
     copy_gbps, copy_ms = copy_bandwidth(torch)
     found = F.plane_peaks_to_numpy(rec, cnt)
@@ -489,6 +493,7 @@ def volume_bench(args, torch, F, synth, B=4, N=256, K=16):
         "planes_found": [[int(len(f)) for f in per] for per in found],
         "sheets": [len(v.sheets) for v in vols],
         "cpu_baseline": cpu, "tile_variants": variants, "autotuned": tuned is not None,
+        "variants_from": "counter table" if measured else ("autotuner" if tuned is not None else "given"),
     }
     print(json.dumps(out), flush=True)
 
@@ -508,11 +513,16 @@ def kernel_sources(nvmt: str = "linear"):
 
 TRAFFIC_TABLES = {"linear": "funnel_fwd_adj_32x1024_traffic.json", "chirpz": "funnel_chirpz_32x1024_traffic.json",
                   "volume": "funnel_volume_4x256_traffic.json"}
+# launch names in the role order of funnel_plan_variants / funnel_volume_variants
+ROLES_2D = ["fwd.regular.A", "fwd.regular.B", "fwd.regular.C", "fwd.inverse.A", "fwd.inverse.B", "fwd.inverse.C",
+            "adj.regular.Ct", "adj.regular.Bt", "adj.regular.At", "adj.inverse.Ct", "adj.inverse.Bt",
+            "adj.inverse.At"]
+ROLES_VOL = [f"volume.{s}{r}" for s in ("", "x.", "y.") for r in ("A", "Bx", "By", "C")]
 
 
-def measured_traffic(launch: str, variant: int, nvmt: str = "linear"):
-    """HBM bytes of one launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE table, if the kernel sources are unchanged since it was taken."""
+def _traffic_table(nvmt: str):
+    """The committed counter table of a workload, if the kernel sources still
+    hash to the value recorded in it."""
     import hashlib
     path = os.path.join(ROOT, "profiles", TRAFFIC_TABLES[nvmt])
     if not os.path.exists(path):
@@ -521,7 +531,24 @@ def measured_traffic(launch: str, variant: int, nvmt: str = "linear"):
     h = hashlib.sha256()
     for f in kernel_sources(nvmt):
         h.update(open(f, "rb").read())
-    if h.hexdigest() != t.get("source_hash") or launch not in t.get("launches", {}):
+    return t if h.hexdigest() == t.get("source_hash") else None
+
+
+def measured_variants(nvmt: str, roles):
+    """The tile variant of every launch in the committed counter table (the
+    set its profiled runs pinned), or None when the table is stale or
+    incomplete: then the autotuner picks."""
+    t = _traffic_table(nvmt)
+    if t is None or any(r not in t.get("launches", {}) for r in roles):
+        return None
+    return [int(t["launches"][r]["variant"]) for r in roles]
+
+
+def measured_traffic(launch: str, variant: int, nvmt: str = "linear"):
+    """HBM bytes of one launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE table, if the kernel sources are unchanged since it was taken."""
+    t = _traffic_table(nvmt)
+    if t is None or launch not in t.get("launches", {}):
         return None
     e = t["launches"][launch]
     if e.get("variant") != variant:
