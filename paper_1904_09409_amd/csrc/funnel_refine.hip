@@ -137,15 +137,17 @@ constexpr int kRefPeaks = 16;
 //   C[n2][o] = sum_k Gr[n2][k] B[k][o],  o < 48: real parts, o >= 48:
 //   imaginary parts of the 48 complex sums (3 per peak: e, x' e, x'^2 e),
 // B[2x'][o] = (Re, Im) of the weight, B[2x'+1][o] = (-Im, Re).  A block
-// takes 128 rows; each of its four waves 32 rows x 96 columns as three
-// 32 x 32 FP32 accumulators (v_mfma_f32_32x32x2f32, one x' per instruction).
+// takes 128 rows with twelve waves, each 32 rows x 32 columns as one
+// 32 x 32 FP32 accumulator (v_mfma_f32_32x32x2f32, one x' per instruction),
+// three waves per SIMD so that one wave's LDS waits are covered by another's
+// matrix instructions.
 // Chunks of 32 samples are double-buffered in LDS: while a chunk is
 // multiplied, the next chunk's g (loaded into registers one chunk earlier)
 // and weights (the phase reduced exactly in integers as above) are written
 // to the other buffer, so there is one barrier per chunk and the staging
 // work sits between the matrix instructions.
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-constexpr int kMRows = 128, kMChunk = 32, kMThreads = 256, kMCols = 3 * kRefPeaks;   // 48 complex columns
+constexpr int kMRows = 128, kMChunk = 32, kMThreads = 768, kMCols = 3 * kRefPeaks;   // 48 complex columns
 
 __global__ void __launch_bounds__(kMThreads)
     k_refine_dtft_mfma(const float2* __restrict__ g, long long img_stride, int h, int W, int s, int ns, int K,
@@ -168,21 +170,23 @@ __global__ void __launch_bounds__(kMThreads)
   }
   const float2* gimg = g + (long long)img * img_stride;
 
-  // g tile of a chunk: 128 rows x 32 samples = 2048 float4 (two samples each), 8 per thread
-  constexpr int NG = kMRows * kMChunk / 2 / kMThreads;
+  // g tile of a chunk: 128 rows x 32 samples = 2048 float4 (two samples each), 3 slots per thread
+  constexpr int NGT = kMRows * kMChunk / 2, NG = (NGT + kMThreads - 1) / kMThreads;
   float4 gr[NG];
   auto load_g = [&](int x0) {
 #pragma unroll
     for (int j = 0; j < NG; ++j) {
       const int i = tid + kMThreads * j, row = i / (kMChunk / 2), c2 = i % (kMChunk / 2);
-      gr[j] = r0 + row < h ? *reinterpret_cast<const float4*>(gimg + (long long)(r0 + row) * W + x0 + 2 * c2)
-                           : make_float4(0.f, 0.f, 0.f, 0.f);
+      gr[j] = i < NGT && r0 + row < h
+                  ? *reinterpret_cast<const float4*>(gimg + (long long)(r0 + row) * W + x0 + 2 * c2)
+                  : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
   auto store_g = [&](int buf, int j0, int j1) {   // register slots j0 .. j1-1
 #pragma unroll
     for (int j = j0; j < j1; ++j) {
       const int i = tid + kMThreads * j, row = i / (kMChunk / 2), c2 = i % (kMChunk / 2);
+      if (i >= NGT) continue;
       gt[buf][row][2 * c2] = make_float2(gr[j].x, gr[j].y);
       gt[buf][row][2 * c2 + 1] = make_float2(gr[j].z, gr[j].w);
     }
@@ -214,21 +218,21 @@ __global__ void __launch_bounds__(kMThreads)
     }
   };
 
-  f32x16 acc[3];
+  f32x16 acc;
 #pragma unroll
-  for (int t = 0; t < 3; ++t)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
-  static_assert(kMChunk * kRefPeaks == 2 * kMThreads && NG == 8, "staging pieces below");
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  constexpr int NW = kMChunk * kRefPeaks;   // weight entries of a chunk, one per thread at most
+  static_assert(NW <= kMThreads && NG == 3, "staging pieces below");
   load_g(0);
   store_g(0, 0, NG);
   __syncthreads();   // pm, pm0
-  build_w(0, 0, tid);
-  build_w(0, 0, tid + kMThreads);
+  if (tid < NW) build_w(0, 0, tid);
   if (kMChunk < W) load_g(kMChunk);
   __syncthreads();
 
   const int li = lane & 31, lk = lane >> 5;    // operand row / column and k of this lane
+  const int stripe = wave / 3, t = wave % 3;   // rows 32 stripe .., columns 32 t ..
+  const int o = 32 * t + li, q = o % kMCols;   // this lane's output column
   const int nch = W / kMChunk;
   for (int c = 0; c < nch; ++c) {
     const int cur = c & 1, nb = cur ^ 1;
@@ -238,19 +242,16 @@ __global__ void __launch_bounds__(kMThreads)
     // The next chunk is staged into the other buffer in pieces between the
     // products (its g from registers, then the loads of the chunk after it,
     // then its weights), so that this work issues while the matrix core runs.
-    const float* ga = reinterpret_cast<const float*>(&gt[cur][32 * wave + li][0]) + lk;
+    const float* ga = reinterpret_cast<const float*>(&gt[cur][32 * stripe + li][0]) + lk;
 #pragma unroll
     for (int xl = 0; xl < kMChunk; ++xl) {
       const float a = ga[2 * xl];
-      const float* bk = bt[cur][2 * xl + lk] + li;
-#pragma unroll
-      for (int t = 0; t < 3; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bk[32 * t], acc[t], 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bt[cur][2 * xl + lk][o], acc, 0, 0, 0);
       if (next) {
-        if (xl == 2) store_g(nb, 0, 4);
-        if (xl == 6) store_g(nb, 4, 8);
-        if (xl == 10 && next2) load_g(x2);
-        if (xl == 16) build_w(nb, x1, tid);
-        if (xl == 24) build_w(nb, x1, tid + kMThreads);
+        if (xl == 4) store_g(nb, 0, 2);
+        if (xl == 8) store_g(nb, 2, 3);
+        if (xl == 12 && next2) load_g(x2);
+        if (xl == 20 && tid < NW) build_w(nb, x1, tid);
       }
     }
     __syncthreads();
@@ -258,17 +259,14 @@ __global__ void __launch_bounds__(kMThreads)
 
   // D[i][j] of a 32 x 32 accumulator: column j = lane mod 32, row
   // i = 8 (v / 4) + 4 (lane / 32) + v mod 4 for register v
+  const int comp = o / kMCols;
+  const int p = grp * kRefPeaks + q / 3, d = q % 3;
+  if (p >= cnt) return;
+  float* dst = reinterpret_cast<float*>(A + ((sbase + p) * 3 + d) * (long long)h) + comp;
 #pragma unroll
-  for (int t = 0; t < 3; ++t) {
-    const int o = 32 * t + li, q = o % kMCols, comp = o / kMCols;
-    const int p = grp * kRefPeaks + q / 3, d = q % 3;
-    if (p >= cnt) continue;
-    float* dst = reinterpret_cast<float*>(A + ((sbase + p) * 3 + d) * (long long)h) + comp;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int row = r0 + 32 * wave + 8 * (v / 4) + 4 * lk + (v % 4);
-      if (row < h) dst[2 * (long long)row] = acc[t][v];
-    }
+  for (int v = 0; v < 16; ++v) {
+    const int row = r0 + 32 * stripe + 8 * (v / 4) + 4 * lk + (v % 4);
+    if (row < h) dst[2 * (long long)row] = acc[v];
   }
 }
 
