@@ -18,15 +18,28 @@
 //          registers, and each wave extracts its first K keys: by one
 //          register sort of its keys when it holds at most 128 (the usual
 //          case), else by K rounds of a wave-wide minimum; a tile contributes
-//          one list per wave.
-// Stage 2: a tree of reductions: each block sorts G lists of K keys (G K <=
-//          2048) and keeps the first K, until one list per plane remains
+//          one list per wave.  A wave that held K keys publishes its K-th
+//          key as the plane's cutoff (a device-wide minimum): no key after
+//          it can be among the plane's first K, since that wave alone holds
+//          K earlier ones.  Later waves drop such keys first, so most hold
+//          fewer than K and write them unsorted, with no selection at all.
+//          Blocks deal the planes round-robin, so every plane's tiles are
+//          spread over the whole launch and its cutoff exists after its
+//          first few tiles.
+// Stage 2: a tree of reductions: each block gathers the keys of G lists of
+//          K (G K <= 2048) that precede the final cutoff, sorts them and
+//          keeps the first K, until one list per plane remains
 //          (log_G(tiles) launches, every level spread over the whole GPU).
+//          Which keys a stage-1 list holds depends on timing; the cutoff
+//          only ever drops keys outside the plane's first K, so the final
+//          lists do not.
 // Stage 3: one block per plane writes the records.  Lists are built from
 //          sorted keys only (the volume detector's LDS gather uses atomics,
 //          but sorts what it gathered), so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <cmath>
 
 #include "fft_core.hpp"
 #include "funnel_internal.hpp"
@@ -37,6 +50,7 @@ constexpr int kTileR = 16, kTileC = 256;  // stage-1 tile: rows x columns of a p
 constexpr int kPeakThreads = 256;           // one tile column per thread
 constexpr int kMaxRadius = 8;
 constexpr int kHaloC = kTileC + 2 * kMaxRadius;
+constexpr int kPadL = kMaxRadius;   // LDS column of the tile's first cell: 16-byte aligned for any radius
 constexpr int kMergeLen = 2048;     // keys sorted per stage-2 block
 constexpr int kMergeThreads = 256;
 constexpr uint64_t kNoKey = ~0ull;
@@ -50,13 +64,6 @@ struct PlaneGeom {
 __device__ __forceinline__ uint64_t cell_key(float v, int idx) {
   const uint32_t b = __float_as_uint(fabsf(v));
   return ((uint64_t)(~b) << 32) | (uint32_t)idx;
-}
-
-__device__ __forceinline__ bool in_border(const PlaneGeom& g, int r, int c) {
-  const int cc = c - g.cols / 2;
-  const int y = r - g.rows / 2;
-  const int e0 = -g.himg / 2, e1 = g.himg / 2;
-  return (cc >= -1) & (cc <= 1) & (((y >= e0 - 2) & (y <= e0 + 1)) | ((y >= e1 - 2) & (y <= e1 + 1)));
 }
 
 // Bitonic sort of the first n keys of a (n a power of two, <= the array).
@@ -143,18 +150,19 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
 // wave's first K local maxima, unordered past the count), [plane][tile][wave][K].
 template <int RADIUS>
 __global__ void __launch_bounds__(kPeakThreads)
-    k_peaks_tile(const float* __restrict__ planes, ImgMap map, PlaneGeom g0, PlaneGeom g1, int nspaces, int tiles,
-                 int K, float thr, int wrap, int keep_border, uint64_t* __restrict__ out) {
+    k_peaks_tile(const float* __restrict__ planes, ImgMap map, PlaneGeom g0, PlaneGeom g1, int nspaces, int nplanes,
+                 int tiles, int K, float thr_below, int wrap, int keep_border, uint64_t* __restrict__ cut,
+                 uint64_t* __restrict__ out) {
   constexpr int radius = RADIUS;
   constexpr int NW = kPeakThreads / 64;
-  __shared__ float val[(kTileR + 2 * RADIUS) * kHaloC];   // |P| of tile and halo; -1: no cell (clamped border)
-  const int plane = blockIdx.y;                 // image * nspaces + space
+  __shared__ __align__(16) float val[(kTileR + 2 * RADIUS) * kHaloC];   // |P| of tile and halo; -1: no cell (clamped border)
+  const int plane = blockIdx.x % nplanes;       // image * nspaces + space; planes dealt round-robin
   const int img = plane / nspaces, sp = plane % nspaces;
   const PlaneGeom g = sp == 0 ? g0 : g1;
   const float* P = planes + map.out(img) + g.offset;
   const int tcn = (g.cols + kTileC - 1) / kTileC;
   const int ntile = tcn * ((g.rows + kTileR - 1) / kTileR);
-  const int tile = blockIdx.x;
+  const int tile = blockIdx.x / nplanes;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint64_t* dst = out + (((long long)plane * tiles + tile) * NW + wave) * K;
   if (tile >= ntile) {   // the other space's plane has more tiles
@@ -213,22 +221,19 @@ __global__ void __launch_bounds__(kPeakThreads)
       const int i = tid + kPeakThreads * j;
       const int lr = i / (kTileC / 4), q = i % (kTileC / 4);
       if (lr >= hr) continue;
-      float* d = val + lr * kHaloC + radius + 4 * q;
-      const float4 x = lv[j];
-      d[0] = lin[j] ? fabsf(x.x) : -1.f;   // -1: a row beyond the clamped border
-      d[1] = lin[j] ? fabsf(x.y) : -1.f;
-      d[2] = lin[j] ? fabsf(x.z) : -1.f;
-      d[3] = lin[j] ? fabsf(x.w) : -1.f;
+      const float4 x = lv[j];   // -1: a row beyond the clamped border
+      *reinterpret_cast<float4*>(val + lr * kHaloC + kPadL + 4 * q) =
+          lin[j] ? make_float4(fabsf(x.x), fabsf(x.y), fabsf(x.z), fabsf(x.w)) : make_float4(-1.f, -1.f, -1.f, -1.f);
     }
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       const int i = tid + kPeakThreads * j;
       const int lr = i / (2 * radius), e = i % (2 * radius);
       if (lr >= hr) continue;
-      val[lr * kHaloC + (e < radius ? e : kTileC + e)] = ls[j];
+      val[lr * kHaloC + kPadL + (e < radius ? e - radius : kTileC + e - radius)] = ls[j];
     }
   } else {
-    // hr rows of kHaloC columns (a few more than needed), one by one
+    // hr rows of kHaloC columns from c0 - kPadL (a few more than needed), one by one
     constexpr int NLD = ((kTileR + 2 * radius) * kHaloC + kPeakThreads - 1) / kPeakThreads;
     const int nhalo = hr * kHaloC;
     float ld[NLD];
@@ -236,7 +241,7 @@ __global__ void __launch_bounds__(kPeakThreads)
     for (int j = 0; j < NLD; ++j) {
       const int i = tid + kPeakThreads * j;
       const int lr = i / kHaloC, lc = i % kHaloC;
-      int cc = c0 - radius + lc;
+      int cc = c0 - kPadL + lc;
       bool in;
       const int rr = src_row(lr, in);
       in = in && i < nhalo;
@@ -260,22 +265,37 @@ __global__ void __launch_bounds__(kPeakThreads)
   // and the same without the column's own cell (me), so a cell costs 2R+1
   // LDS reads: a cell above the maximum of its neighbourhood without itself
   // is a peak; a cell equal to it (an exact tie, rare) takes the index
-  // tie-break afterwards.  Verdicts are selects.
+  // tie-break afterwards.  Which cells may be peaks at all (inside the
+  // plane, outside the expansion-border bands unless kept) is one bit mask
+  // per thread, and the threshold joins the neighbourhood maximum
+  // (v >= T is v > thr_below, the float just below T), so each verdict is
+  // a few compares and selects.
   constexpr int CPT = kTileR;   // cells per thread
   constexpr int NS = CPT / 2;   // two cells of a column that touch are never both maxima:
-  uint64_t mine[NS];            // slot j holds the key of row 2j or 2j+1 if it is one, else kNoKey
+  uint32_t khi[NS], klo[NS];    // slot j holds the key of row 2j or 2j+1 if it is one, else kNoKey
 #pragma unroll
-  for (int j = 0; j < NS; ++j) mine[j] = kNoKey;
+  for (int j = 0; j < NS; ++j) khi[j] = klo[j] = 0xffffffffu;
   const int lc = tid, c = c0 + lc;
-  const bool in_c = c < g.cols;
+  // per tile row (bit lr): holds cells; lies in a border band (the four
+  // centred rows y = e - 2 .. e + 1 around each image edge e = -+himg/2)
+  const uint32_t rowok = r0 + CPT <= g.rows ? (1u << CPT) - 1 : (1u << (g.rows - r0)) - 1;
+  auto band4 = [&](int first) -> uint32_t {   // bits of tile rows first - r0 .. first - r0 + 3
+    const int o = first - r0;
+    return o <= -4 || o >= CPT ? 0u : (o >= 0 ? (0xFu << o) : (0xFu >> -o)) & ((1u << CPT) - 1);
+  };
+  const uint32_t rowband = band4(g.rows / 2 - g.himg / 2 - 2) | band4(g.rows / 2 + g.himg / 2 - 2);
+  const int cc = c - g.cols / 2;
+  const bool colband = (cc >= -1) & (cc <= 1) & (keep_border == 0);
+  const uint32_t cellok = c < g.cols ? (rowok & ~(colband ? rowband : 0u)) : 0u;
+  const uint32_t base = (uint32_t)(r0 * g.cols + c);
   float mi[2 * RADIUS + 1], me[2 * RADIUS + 1];
   auto rowmax = [&](int hr, int j) {
     float m = -1.f;   // -1: clamped border
 #pragma unroll
     for (int dc = -radius; dc <= radius; ++dc)
-      if (dc != 0) m = fmaxf(m, val[hr * kHaloC + lc + radius + dc]);
+      if (dc != 0) m = fmaxf(m, val[hr * kHaloC + kPadL + lc + dc]);
     me[j] = m;
-    mi[j] = fmaxf(m, val[hr * kHaloC + lc + radius]);
+    mi[j] = fmaxf(m, val[hr * kHaloC + kPadL + lc]);
   };
 #pragma unroll
   for (int j = 0; j < 2 * RADIUS; ++j) rowmax(j, j);
@@ -292,23 +312,27 @@ __global__ void __launch_bounds__(kPeakThreads)
       mi[j] = mi[j + 1];
       me[j] = me[j + 1];
     }
-    const int r = r0 + lr;
-    const float v = val[(lr + radius) * kHaloC + lc + radius];
-    const bool ok = in_c & (r < g.rows) & (v >= thr) & ((keep_border != 0) | !in_border(g, r, c));
-    mine[lr / 2] = (ok & (v > m)) ? cell_key(v, r * g.cols + c) : mine[lr / 2];
-    ties |= (ok & (v == m)) ? (1u << lr) : 0u;
+    const float v = val[(lr + radius) * kHaloC + kPadL + lc];
+    const bool ok = (cellok >> lr) & 1u;
+    const bool take = ok & (v > fmaxf(m, thr_below));
+    khi[lr / 2] = take ? ~__float_as_uint(v) : khi[lr / 2];   // v >= 0: the key of cell_key
+    klo[lr / 2] = take ? base + (uint32_t)(lr * g.cols) : klo[lr / 2];
+    ties |= (ok & (v == m)) ? (1u << lr) : 0u;   // decided below, threshold included
   }
+  uint64_t mine[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) mine[j] = ((uint64_t)khi[j] << 32) | klo[j];
   if (ties) {   // equal neighbours: the lower linear index precedes
     uint32_t won = 0;
     for (uint32_t t = ties; t; t &= t - 1) {
       const int lr = __builtin_ctz(t), r = r0 + lr;
-      const float v = val[(lr + radius) * kHaloC + lc + radius];
+      const float v = val[(lr + radius) * kHaloC + kPadL + lc];
       const int idx = r * g.cols + c;
-      bool peak = true;
+      bool peak = v > thr_below;
       for (int dr = -radius; peak && dr <= radius; ++dr)
         for (int dc = -radius; dc <= radius; ++dc) {
           if (dr == 0 && dc == 0) continue;
-          if (val[(lr + radius + dr) * kHaloC + lc + radius + dc] != v) continue;
+          if (val[(lr + radius + dr) * kHaloC + kPadL + lc + dc] != v) continue;
           int rr = r + dr, cc = c + dc;
           rr += rr < 0 ? g.rows : (rr >= g.rows ? -g.rows : 0);
           cc += cc < 0 ? g.cols : (cc >= g.cols ? -g.cols : 0);
@@ -318,15 +342,22 @@ __global__ void __launch_bounds__(kPeakThreads)
     }
 #pragma unroll
     for (int lr = 0; lr < CPT; ++lr)
-      if (won & (1u << lr)) mine[lr / 2] = cell_key(val[(lr + radius) * kHaloC + lc + radius], (r0 + lr) * g.cols + c);
+      if (won & (1u << lr)) mine[lr / 2] = cell_key(val[(lr + radius) * kHaloC + kPadL + lc], (r0 + lr) * g.cols + c);
   }
 
-  // the wave's first K keys.  Usually the wave holds at most 128 keys: they
-  // are packed into the wave's own LDS slots (lanes placed by their rank
-  // among the wave's keys) and sorted in registers by the shuffle bitonic
-  // network.  Otherwise each lane sorts its slots, then K rounds of a
-  // wave-wide minimum over the lanes' first slots; the lane holding the
-  // winner (keys are unique: exactly one) shifts its slots down.
+  // keys after the plane's cutoff go first.  The cutoff only decreases and
+  // every value it takes is safe, so a stale read merely prunes less.
+  const uint64_t cmax = __hip_atomic_load(cut + plane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+  for (int j = 0; j < NS; ++j) mine[j] = mine[j] > cmax ? kNoKey : mine[j];
+
+  // the wave's first K keys.  Fewer than K are written as they are.  Up to
+  // 128 keys are packed into the wave's own LDS slots (lanes placed by their
+  // rank among the wave's keys) and sorted in registers by the shuffle
+  // bitonic network.  Otherwise each lane sorts its slots, then K rounds of
+  // a wave-wide minimum over the lanes' first slots; the lane holding the
+  // winner (keys are unique: exactly one) shifts its slots down.  The last
+  // two publish their K-th key.
   __shared__ uint64_t wkeys[NW][128];
   uint64_t bal[NS];
   int total = 0;
@@ -335,7 +366,19 @@ __global__ void __launch_bounds__(kPeakThreads)
     bal[j] = __ballot(mine[j] != kNoKey);
     total += (int)__popcll(bal[j]);
   }
-  if (total <= 128) {   // uniform over the wave
+  if (total < K) {   // uniform over the wave; the reduction sorts
+    int base = 0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal[j] >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal[j], 0u));
+      if (mine[j] != kNoKey) dst[base + rank] = mine[j];
+      base += (int)__popcll(bal[j]);
+    }
+    for (int i = total + lane; i < K; i += 64) dst[i] = kNoKey;
+    return;
+  }
+  if (total <= 128) {   // uniform over the wave; K <= total
     int base = 0;
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
@@ -353,7 +396,11 @@ __global__ void __launch_bounds__(kPeakThreads)
     wave_sort128(a, b, lane);
     if (lane < K) dst[lane] = a;
     if (lane + 64 < K) dst[lane + 64] = b;
-    for (int i = 128 + lane; i < K; i += 64) dst[i] = kNoKey;
+    const uint64_t src = K <= 64 ? a : b;   // the K-th key sits in lane (K - 1) mod 64
+    const int kl = (K - 1) & 63;
+    const uint64_t kth = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(src >> 32), kl) << 32) |
+                         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)src, kl);
+    if (lane == 0) atomicMin(reinterpret_cast<unsigned long long*>(cut + plane), (unsigned long long)kth);
     return;
   }
 #pragma unroll
@@ -364,31 +411,56 @@ __global__ void __launch_bounds__(kPeakThreads)
       mine[b] = x < y ? x : y;
       mine[b + 1] = x < y ? y : x;
     }
-  int k = 0;
-  for (; k < K; ++k) {
+  uint64_t last = kNoKey;
+  for (int k = 0; k < K; ++k) {   // total > 128 and total >= K: every round finds a key
     const uint64_t m = wave_min_u64(mine[0]);
-    if (m == kNoKey) break;   // uniform: the wave has no keys left
     if (lane == 0) dst[k] = m;
+    last = m;
     if (mine[0] == m) {
 #pragma unroll
       for (int j = 0; j < NS - 1; ++j) mine[j] = mine[j + 1];
       mine[NS - 1] = kNoKey;
     }
   }
-  for (int i = k + lane; i < K; i += 64) dst[i] = kNoKey;
+  if (lane == 0) atomicMin(reinterpret_cast<unsigned long long*>(cut + plane), (unsigned long long)last);
+}
+
+__global__ void k_fill_keys(uint64_t* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = kNoKey;
 }
 
 // Lists [plane][nin][K] -> [plane][nout][K], nout = ceil(nin / G): block
-// (j, plane) sorts lists j G .. j G + G - 1 and keeps the first K keys.
+// (j, plane) gathers the keys of lists j G .. j G + G - 1 that are present
+// and not after the plane's cutoff (cut: NULL for none), sorts them and
+// keeps the first K.
 __global__ void __launch_bounds__(kMergeThreads)
-    k_peaks_reduce(const uint64_t* __restrict__ in, int nin, uint64_t* __restrict__ out, int nout, int K, int G) {
+    k_peaks_reduce(const uint64_t* __restrict__ in, int nin, uint64_t* __restrict__ out, int nout, int K, int G,
+                   const uint64_t* __restrict__ cut) {
   __shared__ uint64_t keys[kMergeLen];
-  const int plane = blockIdx.y, j = blockIdx.x;
+  __shared__ int count;
+  const int plane = blockIdx.y, j = blockIdx.x, lane = threadIdx.x & 63;
   const uint64_t* src = in + ((long long)plane * nin + (long long)j * G) * K;
   const int avail = (nin - j * G < G ? nin - j * G : G) * K;
-  int n = 1;   // sort the keys present, padded to a power of two (>= K)
-  while (n < avail || n < K) n <<= 1;
-  for (int i = threadIdx.x; i < n; i += kMergeThreads) keys[i] = i < avail ? src[i] : kNoKey;
+  const uint64_t cmax = cut ? cut[plane] : kNoKey;   // stage 1 has ended: final
+  if (threadIdx.x == 0) count = 0;
+  __syncthreads();
+  for (int i0 = 0; i0 < avail; i0 += kMergeThreads) {   // same trip count for every lane
+    const int i = i0 + threadIdx.x;
+    const uint64_t key = i < avail ? src[i] : kNoKey;
+    const bool keep = key != kNoKey && key <= cmax;
+    const uint64_t bal = __ballot(keep);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    int base = 0;
+    if (lane == 0 && bal) base = atomicAdd(&count, (int)__popcll(bal));
+    base = __shfl(base, 0, 64);
+    if (keep) keys[base + rank] = key;
+  }
+  __syncthreads();
+  const int c = count;
+  int n = 1;   // sort the keys gathered, padded to a power of two (>= K, <= G K)
+  while (n < c || n < K) n <<= 1;
+  for (int i = c + threadIdx.x; i < n; i += kMergeThreads) keys[i] = kNoKey;
   __syncthreads();
   bitonic_sort_n<kMergeThreads>(keys, n);
   uint64_t* dst = out + ((long long)plane * nout + j) * K;
@@ -433,22 +505,24 @@ __global__ void __launch_bounds__(kMergeThreads)
 static int merge_group(int K) { return kMergeLen / K > 1 ? kMergeLen / K : 2; }
 
 // stage-1 lists, then the first reduction level's lists (later levels reuse
-// the first buffer, which is large enough for them)
+// the first buffer, which is large enough for them), then one cutoff key per
+// plane
 size_t peaks_workspace_bytes(int nplanes_total, int tiles, int K) {
   const size_t lists = (size_t)tiles * (kPeakThreads / 64);
   const size_t lvl1 = (lists + merge_group(K) - 1) / merge_group(K);
-  return (size_t)nplanes_total * (lists + lvl1) * (size_t)K * sizeof(uint64_t);
+  return (size_t)nplanes_total * ((lists + lvl1) * (size_t)K + 1) * sizeof(uint64_t);
 }
 
 // Reduce `lists` key lists per plane to one, ping-ponging between the stage-1
 // buffer `cand` and the level-1 buffer behind it; *out: the final lists.
-static hipError_t reduce_lists(uint64_t* cand, int planes_n, int lists, int K, const uint64_t** out, hipStream_t s) {
+static hipError_t reduce_lists(uint64_t* cand, int planes_n, int lists, int K, const uint64_t* cut,
+                               const uint64_t** out, hipStream_t s) {
   const int G = merge_group(K);
   uint64_t* bufs[2] = {cand, cand + (size_t)planes_n * lists * K};
   int cur = 0, n = lists;
   do {
     const int nout = (n + G - 1) / G;
-    k_peaks_reduce<<<dim3(nout, planes_n), kMergeThreads, 0, s>>>(bufs[cur], n, bufs[1 - cur], nout, K, G);
+    k_peaks_reduce<<<dim3(nout, planes_n), kMergeThreads, 0, s>>>(bufs[cur], n, bufs[1 - cur], nout, K, G, cut);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     cur = 1 - cur;
@@ -472,23 +546,31 @@ hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int ba
     tiles = t > tiles ? t : tiles;
   }
   if (nspaces == 1) g[1] = g[0];
+  if (radius < 1 || radius > kMaxRadius) return hipErrorInvalidValue;
+  const int planes_n = batch * nspaces;
+  const size_t lists = (size_t)tiles * (kPeakThreads / 64);
+  const size_t lvl1 = (lists + merge_group(K) - 1) / merge_group(K);
   uint64_t* cand = static_cast<uint64_t*>(ws);
-  dim3 grid1(tiles, batch * nspaces);
+  uint64_t* cut = cand + (size_t)planes_n * (lists + lvl1) * K;   // as peaks_workspace_bytes lays it out
+  k_fill_keys<<<(planes_n + 255) / 256, 256, 0, s>>>(cut, planes_n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 grid1((unsigned)(tiles * planes_n));
+  const float thr_below = std::nextafter(thr, -INFINITY);   // v >= thr  <=>  v > thr_below
   switch (radius) {
 #define CASE(R)                                                                                              \
   case R:                                                                                                    \
-    k_peaks_tile<R><<<grid1, kPeakThreads, 0, s>>>(planes, map, g[0], g[1], nspaces, tiles, K, thr, wrap, keep_border, \
-                                                   cand);                                                    \
+    k_peaks_tile<R><<<grid1, kPeakThreads, 0, s>>>(planes, map, g[0], g[1], nspaces, planes_n, tiles, K, thr_below, \
+                                                   wrap, keep_border, cut, cand);                            \
     break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: return hipErrorInvalidValue;
   }
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int planes_n = batch * nspaces;
   const uint64_t* list = nullptr;
-  e = reduce_lists(cand, planes_n, tiles * (kPeakThreads / 64), K, &list, s);   // one list per wave of every tile
+  e = reduce_lists(cand, planes_n, (int)lists, K, cut, &list, s);   // one list per wave of every tile
   if (e != hipSuccess) return e;
   k_peaks_records<<<planes_n, kMergeThreads, 0, s>>>(planes, map, gidx, g[0], g[1], nspaces, space0, K, list, peaks,
                                                      n_found);
@@ -831,7 +913,7 @@ hipError_t launch_vpeaks(const float* params, long long stride, int batch, int n
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const uint64_t* list = nullptr;
-  e = reduce_lists(cand, batch, tiles, K, &list, s);
+  e = reduce_lists(cand, batch, tiles, K, nullptr, &list, s);
   if (e != hipSuccess) return e;
   k_vpeaks_records<<<batch, kMergeThreads, 0, s>>>(params, g, K, list, ns, sp, space_id, peaks, n_found);
   return hipGetLastError();

@@ -107,6 +107,63 @@ def test_peaks_bitwise_on_shared_plane(K, T, radius, flags):
                 assert rec_["image"] == b and rec_["space"] == s
 
 
+def cutoff_planes(kind, shape, rng):
+    """|P|-like planes that drive each selection path of the tile kernel."""
+    rows, cols = shape
+    if kind == "noise":           # ~9 % local maxima: about 94 keys per wave
+        return np.abs(rng.standard_normal(shape))
+    if kind == "spikes":          # noise plus planted strong peaks, some of equal height
+        B = np.abs(rng.standard_normal(shape))
+        r, c = rng.integers(0, rows, 60), rng.integers(0, cols, 60)
+        B[r, c] = 6.0 + np.repeat(rng.uniform(0, 4, 30), 2)
+        return B
+    if kind == "checker":         # a maximum at every (even, even) cell: 256 keys per wave
+        B = 0.1 * rng.random(shape)
+        B[::2, ::2] += 1.0 + rng.random((rows // 2, cols // 2))
+        return B
+    if kind == "levels":          # six levels: exact ties everywhere
+        return np.floor(rng.random(shape) * 6.0) / 6.0
+    if kind == "smooth":          # few local maxima: most waves hold fewer than K keys
+        y = np.arange(rows)[:, None] / rows
+        x = np.arange(cols)[None, :] / cols
+        return 2.0 + np.sin(6.28 * 12 * y) * np.cos(6.28 * 20 * x) + 1e-3 * rng.random(shape)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("K,T,radius,flags", [
+    (16, 0.0, 1, 0),
+    (64, 0.0, 2, 0),
+    (16, 0.3, 1, F.FT_PEAK_CLAMP_BORDER),
+])
+def test_peaks_bitwise_full_size_planes(K, T, radius, flags):
+    """64 of the 2048 x 1024 planes of the 1024^2 workload's layout, far more
+    tiles than the GPU runs at once, so most waves see a cutoff published by
+    earlier ones: lists identical to the literal procedure on the same FP32
+    planes, for every selection path (fewer than K keys, register sort,
+    K rounds) and for exact ties."""
+    import torch
+    N = M = 1024
+    B = 32
+    kinds = ["noise", "spikes", "checker", "levels", "smooth"]
+    say(f"peaks full size {B} x 1024^2 K={K} T={T} r={radius} flags={flags}")
+    plan = F.FunnelPlan(B, N, M)
+    rng = np.random.default_rng([61, K, radius])
+    per_image = [[cutoff_planes(kinds[(2 * b + s) % len(kinds)], (plan.Np, M), rng).astype(np.float32)
+                  for s in range(2)] for b in range(B)]
+    planes = upload_planes(plan, per_image)
+    rec, cnt = plan.peaks(planes, K=K, threshold=T, radius=radius, flags=flags)
+    torch.cuda.synchronize()
+    got = F.peaks_to_numpy(rec, cnt)
+    wrap = not (flags & F.FT_PEAK_CLAMP_BORDER)
+    mask = O.boundary_mask(N, M, plan.Np)
+    for b in range(0, B, 3):   # every kind in both spaces; the oracle sorts 2 M cells per plane
+        for s in range(2):
+            want = oracle_peaks(per_image[b][s].astype(np.float64), K, T, radius, mask, wrap)
+            g = got[b][s]
+            assert [int(r) * M + int(c) for r, c in zip(g["row"], g["col"])] == want, (b, s, kinds[(2 * b + s) % 5])
+    say(f"  checked {len(range(0, B, 3)) * 2} planes")
+
+
 def test_peaks_end_to_end_where_margin_is_clear():
     """GPU planes -> GPU peaks against oracle planes -> literal list, on
     synthetic line images; lists must agree wherever the oracle's ordering
