@@ -149,7 +149,7 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
 // all in flight at once.  Output: per tile, one list of K keys per wave (the
 // wave's first K local maxima, unordered past the count), [plane][tile][wave][K].
 template <int RADIUS>
-__global__ void __launch_bounds__(kPeakThreads)
+__global__ void __launch_bounds__(kPeakThreads, 8)
     k_peaks_tile(const float* __restrict__ planes, ImgMap map, PlaneGeom g0, PlaneGeom g1, int nspaces, int nplanes,
                  int tiles, int K, float thr_below, int wrap, int keep_border, uint64_t* __restrict__ cut,
                  uint64_t* __restrict__ out) {
@@ -191,16 +191,17 @@ __global__ void __launch_bounds__(kPeakThreads)
     float4 lv[NV];
     bool lin[NV];
     float ls[NS];
+    bool lsin[NS];
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
       const int i = tid + kPeakThreads * j;
       const int lr = i / (kTileC / 4), q = i % (kTileC / 4);
       bool in;
-      const int rr = src_row(lr, in);
+      int rr = src_row(lr, in);
       in = in && lr < hr;
       lin[j] = in;
-      lv[j] = in ? *reinterpret_cast<const float4*>(P + (long long)rr * g.cols + c0 + 4 * q)
-                 : make_float4(0.f, 0.f, 0.f, 0.f);
+      rr = in ? rr : r0;   // loads are unconditional (a row of the tile stands in), so all are in flight at once
+      lv[j] = *reinterpret_cast<const float4*>(P + (long long)rr * g.cols + c0 + 4 * q);
     }
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
@@ -214,7 +215,8 @@ __global__ void __launch_bounds__(kPeakThreads)
         if (wrap) cc = ((cc % g.cols) + g.cols) % g.cols;
         else in = false;
       }
-      ls[j] = in ? fabsf(P[(long long)rr * g.cols + cc]) : -1.0f;
+      ls[j] = P[(long long)(in ? rr : r0) * g.cols + (in ? cc : c0)];
+      lsin[j] = in;
     }
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
@@ -230,13 +232,14 @@ __global__ void __launch_bounds__(kPeakThreads)
       const int i = tid + kPeakThreads * j;
       const int lr = i / (2 * radius), e = i % (2 * radius);
       if (lr >= hr) continue;
-      val[lr * kHaloC + kPadL + (e < radius ? e - radius : kTileC + e - radius)] = ls[j];
+      val[lr * kHaloC + kPadL + (e < radius ? e - radius : kTileC + e - radius)] = lsin[j] ? fabsf(ls[j]) : -1.0f;
     }
   } else {
     // hr rows of kHaloC columns from c0 - kPadL (a few more than needed), one by one
     constexpr int NLD = ((kTileR + 2 * radius) * kHaloC + kPeakThreads - 1) / kPeakThreads;
     const int nhalo = hr * kHaloC;
     float ld[NLD];
+    bool ldin[NLD];
 #pragma unroll
     for (int j = 0; j < NLD; ++j) {
       const int i = tid + kPeakThreads * j;
@@ -249,12 +252,13 @@ __global__ void __launch_bounds__(kPeakThreads)
         if (wrap) cc = ((cc % g.cols) + g.cols) % g.cols;
         else in = false;
       }
-      ld[j] = in ? fabsf(P[(long long)rr * g.cols + cc]) : -1.0f;
+      ld[j] = P[(long long)(in ? rr : r0) * g.cols + (in ? cc : c0)];   // unconditional: all in flight at once
+      ldin[j] = in;
     }
 #pragma unroll
     for (int j = 0; j < NLD; ++j) {
       const int i = tid + kPeakThreads * j;
-      if (i < nhalo) val[i] = ld[j];
+      if (i < nhalo) val[i] = ldin[j] ? fabsf(ld[j]) : -1.0f;
     }
   }
   __syncthreads();
@@ -287,7 +291,7 @@ __global__ void __launch_bounds__(kPeakThreads)
   const int cc = c - g.cols / 2;
   const bool colband = (cc >= -1) & (cc <= 1) & (keep_border == 0);
   const uint32_t cellok = c < g.cols ? (rowok & ~(colband ? rowband : 0u)) : 0u;
-  const uint32_t base = (uint32_t)(r0 * g.cols + c);
+  uint32_t idx = (uint32_t)(r0 * g.cols + c);   // linear index of the current cell
   float mi[2 * RADIUS + 1], me[2 * RADIUS + 1];
   auto rowmax = [&](int hr, int j) {
     float m = -1.f;   // -1: clamped border
@@ -316,7 +320,8 @@ __global__ void __launch_bounds__(kPeakThreads)
     const bool ok = (cellok >> lr) & 1u;
     const bool take = ok & (v > fmaxf(m, thr_below));
     khi[lr / 2] = take ? ~__float_as_uint(v) : khi[lr / 2];   // v >= 0: the key of cell_key
-    klo[lr / 2] = take ? base + (uint32_t)(lr * g.cols) : klo[lr / 2];
+    klo[lr / 2] = take ? idx : klo[lr / 2];
+    idx += (uint32_t)g.cols;
     ties |= (ok & (v == m)) ? (1u << lr) : 0u;   // decided below, threshold included
   }
   uint64_t mine[NS];
@@ -358,7 +363,10 @@ __global__ void __launch_bounds__(kPeakThreads)
   // a wave-wide minimum over the lanes' first slots; the lane holding the
   // winner (keys are unique: exactly one) shifts its slots down.  The last
   // two publish their K-th key.
-  __shared__ uint64_t wkeys[NW][128];
+  // the sort slots reuse the tile's LDS once every wave has read it
+  __syncthreads();
+  uint64_t(*wkeys)[128] = reinterpret_cast<uint64_t(*)[128]>(val);
+  static_assert(sizeof(uint64_t) * NW * 128 <= sizeof(val), "sort slots exceed the tile's LDS");
   uint64_t bal[NS];
   int total = 0;
 #pragma unroll
