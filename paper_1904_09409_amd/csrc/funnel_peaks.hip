@@ -609,13 +609,6 @@ struct VolGeom {
   long long stride;    // floats per parameter volume
 };
 
-__device__ __forceinline__ bool in_face(const VolGeom& g, int z, int r, int c) {
-  const int cc = c - g.nx / 2, rr = r - g.ny / 2;
-  const int y = z - g.nz / 2, e0 = -g.zimg / 2, e1 = g.zimg / 2;
-  return (cc >= -1) & (cc <= 1) & (rr >= -1) & (rr <= 1) &
-         (((y >= e0 - 2) & (y <= e0 + 1)) | ((y >= e1 - 2) & (y <= e1 + 1)));
-}
-
 // Coordinate c of a halo cell on an axis of n cells: wrapped once (R < n and
 // the tile starts inside the volume, so one step reaches every cell a real
 // cell needs; cells beyond those are clamped and never used), or !in when
@@ -628,10 +621,13 @@ __device__ __forceinline__ int halo_coord(int c, int n, int wrap, bool& in) {
 }
 
 // Tile geometry and the staging of one tile plus its halo: HZ * HY rows of
-// HX cells, |P| in LDS (-1: no cell, beyond a clamped border).
+// HX cells, |P| in LDS (-1: no cell, beyond a clamped border).  A row's cell
+// x0 sits at column PX, so rows and their 16-byte stores are aligned.
 template <int R>
 struct VTile {
-  static constexpr int HZ = kVTileZ + 2 * R, HY = kVTileY + 2 * R, HX = kVTileX + 2 * R;
+  static constexpr int PX = 4;
+  static_assert(R <= PX, "halo wider than the row padding");
+  static constexpr int HZ = kVTileZ + 2 * R, HY = kVTileY + 2 * R, HX = kVTileX + 2 * PX;
   static constexpr int NH = HZ * HY * HX;
   static constexpr int NV = (HZ * HY * (kVTileX / 4) + kPeakThreads - 1) / kPeakThreads;   // 16-byte loads
   static constexpr int NSD = (HZ * HY * 2 * R + kPeakThreads - 1) / kPeakThreads;         // side cells
@@ -647,6 +643,10 @@ struct VTile {
     const int tile = t % tiles;
     return Origin{t / tiles, tile, (tile % tx) * kVTileX, ((tile / tx) % ty) * kVTileY, (tile / (tx * ty)) * kVTileZ};
   }
+  // offset of the tile's first row (z0, y0), cell x = 0
+  __device__ static long long origin_row(const VolGeom& g, const Origin& o) {
+    return ((long long)o.z0 * g.ny + o.y0) * g.nx;
+  }
   // offset of halo row r's cell x = 0 (in: the row exists)
   __device__ static long long row_base(const VolGeom& g, const Origin& o, int wrap, int r, bool& in) {
     in = r < HZ * HY;
@@ -660,6 +660,7 @@ struct VTile {
     float4 lv[NV];
     bool lin[NV];
     float ls[NSD];
+    bool lsin[NSD];
   };
   __device__ static void load_vec(const float* P, const VolGeom& g, const Origin& o, int wrap, Regs& q) {
     const int tid = threadIdx.x;
@@ -669,7 +670,9 @@ struct VTile {
       bool in;
       const long long b = row_base(g, o, wrap, r, in);
       q.lin[j] = in;
-      q.lv[j] = in ? *reinterpret_cast<const float4*>(P + b + o.x0 + 4 * c) : make_float4(0.f, 0.f, 0.f, 0.f);
+      // unconditional, so all are in flight at once; a lane with nothing to
+      // stage reads the tile's own first row, which the block fetches anyway
+      q.lv[j] = *reinterpret_cast<const float4*>(P + (in ? b : origin_row(g, o)) + o.x0 + 4 * c);
     }
 #pragma unroll
     for (int j = 0; j < NSD; ++j) {
@@ -677,7 +680,8 @@ struct VTile {
       bool in;
       const long long b = row_base(g, o, wrap, r, in);
       const int x = halo_coord(e < R ? o.x0 - R + e : o.x0 + kVTileX + (e - R), g.nx, wrap, in);
-      q.ls[j] = in ? fabsf(P[b + x]) : -1.0f;
+      q.ls[j] = P[in ? b + x : origin_row(g, o) + o.x0];
+      q.lsin[j] = in;
     }
   }
   __device__ static void store_vec(float* val, const Regs& q) {
@@ -686,35 +690,37 @@ struct VTile {
     for (int j = 0; j < NV; ++j) {
       const int i = tid + kPeakThreads * j, r = i / (kVTileX / 4), c = i % (kVTileX / 4);
       if ((HZ * HY * (kVTileX / 4)) % kPeakThreads != 0 && r >= HZ * HY) continue;
-      float* d = val + r * HX + R + 4 * c;
-      d[0] = q.lin[j] ? fabsf(q.lv[j].x) : -1.f;
-      d[1] = q.lin[j] ? fabsf(q.lv[j].y) : -1.f;
-      d[2] = q.lin[j] ? fabsf(q.lv[j].z) : -1.f;
-      d[3] = q.lin[j] ? fabsf(q.lv[j].w) : -1.f;
+      const float4 x = q.lv[j];
+      *reinterpret_cast<float4*>(val + r * HX + PX + 4 * c) =
+          q.lin[j] ? make_float4(fabsf(x.x), fabsf(x.y), fabsf(x.z), fabsf(x.w)) : make_float4(-1.f, -1.f, -1.f, -1.f);
     }
 #pragma unroll
     for (int j = 0; j < NSD; ++j) {
       const int i = tid + kPeakThreads * j, r = i / (2 * R), e = i % (2 * R);
       if ((HZ * HY * 2 * R) % kPeakThreads != 0 && r >= HZ * HY) continue;
-      val[r * HX + (e < R ? e : kVTileX + e)] = q.ls[j];
+      val[r * HX + PX + (e < R ? e - R : kVTileX + e - R)] = q.lsin[j] ? fabsf(q.ls[j]) : -1.0f;
     }
   }
   // any tile: cell by cell, every load issued before the first store
   __device__ static void stage_scalar(float* val, const float* P, const VolGeom& g, const Origin& o, int wrap) {
     const int tid = threadIdx.x;
     float ld[NLD];
+    bool ldin[NLD];
 #pragma unroll
     for (int j = 0; j < NLD; ++j) {
       const int i = tid + kPeakThreads * j;
       bool in;
       const long long b = row_base(g, o, wrap, i / HX, in);
-      const int x = halo_coord(o.x0 - R + i % HX, g.nx, wrap, in);
-      ld[j] = in ? fabsf(P[b + x]) : -1.0f;
+      const int xc = o.x0 - PX + i % HX;   // the padding columns beyond the halo are staged too
+      in = in & (xc >= o.x0 - R) & (xc < o.x0 + kVTileX + R);
+      const int x = halo_coord(xc, g.nx, wrap, in);
+      ld[j] = P[in ? b + x : origin_row(g, o) + o.x0];   // unconditional: all in flight at once
+      ldin[j] = in;
     }
 #pragma unroll
     for (int j = 0; j < NLD; ++j) {
       const int i = tid + kPeakThreads * j;
-      if (NH % kPeakThreads == 0 || i < NH) val[i] = ld[j];
+      if (NH % kPeakThreads == 0 || i < NH) val[i] = ldin[j] ? fabsf(ld[j]) : -1.0f;
     }
   }
 };
@@ -724,7 +730,7 @@ struct VTile {
 // block's keys) and returns without a final barrier.
 template <int R>
 __device__ void vtile_detect(float* val, int* nkeys, const VolGeom& g, const typename VTile<R>::Origin& o, int K,
-                             float thr, int keep_border, uint64_t* dst) {
+                             float thr_below, int keep_border, uint64_t* cut, uint64_t* dst) {
   using T = VTile<R>;
   constexpr int HY = T::HY, HX = T::HX, NS = T::NSLOT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -737,11 +743,26 @@ __device__ void vtile_detect(float* val, int* nkeys, const VolGeom& g, const typ
   // tie, rare) is resolved afterwards by the index tie-break.  The verdicts
   // are selects, so the loop has no divergent branches.
   uint64_t mine[NS];   // two cells adjacent along z are never both maxima: slot lz / 2
+  uint32_t khi[NS], klo[NS];
 #pragma unroll
-  for (int j = 0; j < NS; ++j) mine[j] = kNoKey;
+  for (int j = 0; j < NS; ++j) khi[j] = klo[j] = 0xffffffffu;
   const int x = x0 + lane, y = y0 + wave;
-  const bool in_xy = (x < g.nx) & (y < g.ny);
-  const int lc = (wave + R) * HX + lane + R;   // this column's cell in a halo slice
+  // which of the column's cells may be peaks (bit lz): inside the volume and,
+  // unless kept, outside the expansion faces (four centred slices around
+  // each image face, at slope bins -1..1 in both x and y); the threshold
+  // joins the neighbourhood maximum (v >= T is v > thr_below)
+  constexpr uint32_t kAll = (1u << kVTileZ) - 1;
+  const uint32_t zok = z0 + kVTileZ <= g.nz ? kAll : (1u << (g.nz - z0)) - 1;
+  auto band4 = [&](int first) -> uint32_t {   // bits of tile slices first - z0 .. first - z0 + 3
+    const int o4 = first - z0;
+    return o4 <= -4 || o4 >= kVTileZ ? 0u : (o4 >= 0 ? (0xFu << o4) : (0xFu >> -o4)) & kAll;
+  };
+  const uint32_t zband = band4(g.nz / 2 - g.zimg / 2 - 2) | band4(g.nz / 2 + g.zimg / 2 - 2);
+  const int cx = x - g.nx / 2, cy = y - g.ny / 2;
+  const bool center = (cx >= -1) & (cx <= 1) & (cy >= -1) & (cy <= 1) & (keep_border == 0);
+  const uint32_t cellok = (x < g.nx) & (y < g.ny) ? (zok & ~(center ? zband : 0u)) : 0u;
+  uint32_t idx = (uint32_t)((z0 * g.ny + y) * g.nx + x);   // linear index of the current cell
+  const int lc = (wave + R) * HX + lane + T::PX;   // this column's cell in a halo slice
   float m9[2 * R + 1], m8[2 * R + 1];
   auto window = [&](int hz, int j) {
     float m = -1.f;
@@ -769,12 +790,15 @@ __device__ void vtile_detect(float* val, int* nkeys, const VolGeom& g, const typ
       m8[j] = m8[j + 1];
     }
     const float v = val[(lz + R) * HY * HX + lc];
-    const int z = z0 + lz;
-    const bool ok = in_xy & (z < g.nz) & (v >= thr) & ((keep_border != 0) | !in_face(g, z, y, x));
-    const int idx = (z * g.ny + y) * g.nx + x;
-    mine[lz / 2] = (ok & (v > m)) ? cell_key(v, idx) : mine[lz / 2];
-    ties |= (ok & (v == m)) ? (1u << lz) : 0u;
+    const bool ok = (cellok >> lz) & 1u;
+    const bool take = ok & (v > fmaxf(m, thr_below));
+    khi[lz / 2] = take ? ~__float_as_uint(v) : khi[lz / 2];   // v >= 0: the key of cell_key
+    klo[lz / 2] = take ? idx : klo[lz / 2];
+    idx += (uint32_t)(g.ny * g.nx);
+    ties |= (ok & (v == m)) ? (1u << lz) : 0u;   // decided below, threshold included
   }
+#pragma unroll
+  for (int j = 0; j < NS; ++j) mine[j] = ((uint64_t)khi[j] << 32) | klo[j];
   if (ties) {   // equal neighbours: the lower linear index precedes
     uint32_t won = 0;
     for (uint32_t t = ties; t; t &= t - 1) {
@@ -782,7 +806,7 @@ __device__ void vtile_detect(float* val, int* nkeys, const VolGeom& g, const typ
       const int c = (lz + R) * HY * HX + lc;
       const float v = val[c];
       const int idx = (z * g.ny + y) * g.nx + x;
-      bool peak = true;
+      bool peak = v > thr_below;
       for (int dz = -R; peak && dz <= R; ++dz)
         for (int dy = -R; peak && dy <= R; ++dy)
           for (int dx = -R; dx <= R; ++dx) {
@@ -801,11 +825,20 @@ __device__ void vtile_detect(float* val, int* nkeys, const VolGeom& g, const typ
         mine[lz / 2] = cell_key(val[(lz + R) * HY * HX + lc], ((z0 + lz) * g.ny + y) * g.nx + x);
   }
 
+  // keys after the volume's cutoff go first: the cutoff is the K-th key of
+  // a tile that held at least K, all earlier, so none of them can be among
+  // the volume's first K.  It only decreases, and every value it takes is
+  // safe, so a stale read merely prunes less.
+  const uint64_t cmax = __hip_atomic_load(cut, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+  for (int j = 0; j < NS; ++j) mine[j] = mine[j] > cmax ? kNoKey : mine[j];
+
   // the block's first K keys: gather every thread's keys in LDS (over the
   // staged values, which are no longer read; one atomic per wave and slot,
   // lanes placed by their rank among the wave's keys), sort the keys present
-  // once, keep K.  The gather order varies from run to run; the sorted
-  // result does not.
+  // once, keep K and publish the K-th as the cutoff.  Fewer than K are
+  // written unsorted (the reduction sorts).  The gather order varies from
+  // run to run; the reduced lists do not.
   if (tid == 0) *nkeys = 0;
   __syncthreads();
   uint64_t* keys = reinterpret_cast<uint64_t*>(val);
@@ -830,7 +863,11 @@ __device__ void vtile_detect(float* val, int* nkeys, const VolGeom& g, const typ
       wave_sort128(a, b, lane);
       if (lane < K) dst[lane] = a;
       if (lane + 64 < K) dst[lane + 64] = b;
-      for (int i = 128 + lane; i < K; i += 64) dst[i] = kNoKey;
+      const uint64_t src = K <= 64 ? a : b;   // n > K: the K-th key sits in lane (K - 1) mod 64
+      const int kl = (K - 1) & 63;
+      const uint64_t kth = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(src >> 32), kl) << 32) |
+                           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)src, kl);
+      if (lane == 0) atomicMin(reinterpret_cast<unsigned long long*>(cut), (unsigned long long)kth);
     }
   } else {
     int np = 1;
@@ -839,6 +876,7 @@ __device__ void vtile_detect(float* val, int* nkeys, const VolGeom& g, const typ
     __syncthreads();
     bitonic_sort_n<kPeakThreads>(keys, np);
     for (int i = tid; i < K; i += kPeakThreads) dst[i] = keys[i];
+    if (tid == 0) atomicMin(reinterpret_cast<unsigned long long*>(cut), (unsigned long long)keys[K - 1]);
   }
 }
 
@@ -846,8 +884,8 @@ __device__ void vtile_detect(float* val, int* nkeys, const VolGeom& g, const typ
 // [volume][tile][K].
 template <int RADIUS>
 __global__ void __launch_bounds__(kPeakThreads)
-    k_vpeaks_tile(const float* __restrict__ params, VolGeom g, int tiles, int K, float thr, int wrap, int keep_border,
-                  uint64_t* __restrict__ out) {
+    k_vpeaks_tile(const float* __restrict__ params, VolGeom g, int tiles, int K, float thr_below, int wrap, int keep_border,
+                  uint64_t* __restrict__ cut, uint64_t* __restrict__ out) {
   using T = VTile<RADIUS>;
   __shared__ __align__(16) float val[T::NH];
   __shared__ int nkeys;
@@ -863,7 +901,8 @@ __global__ void __launch_bounds__(kPeakThreads)
     T::stage_scalar(val, P, g, o, wrap);
   }
   __syncthreads();
-  vtile_detect<RADIUS>(val, &nkeys, g, o, K, thr, keep_border, out + ((long long)o.vol * tiles + o.tile) * K);
+  vtile_detect<RADIUS>(val, &nkeys, g, o, K, thr_below, keep_border, cut + o.vol,
+                       out + ((long long)o.vol * tiles + o.tile) * K);
 }
 
 // One sorted list of K keys per volume -> plane records and counts.
@@ -902,10 +941,11 @@ int vpeaks_tiles(int nz, int ny, int nx) {
   return ((nz + kVTileZ - 1) / kVTileZ) * ((ny + kVTileY - 1) / kVTileY) * ((nx + kVTileX - 1) / kVTileX);
 }
 
-// stage-1 lists (one per tile), then the first reduction level's lists
+// stage-1 lists (one per tile), then the first reduction level's lists, then
+// one cutoff key per volume
 size_t vpeaks_workspace_bytes(int nvol, int tiles, int K) {
   const size_t lvl1 = ((size_t)tiles + merge_group(K) - 1) / merge_group(K);
-  return (size_t)nvol * ((size_t)tiles + lvl1) * (size_t)K * sizeof(uint64_t);
+  return (size_t)nvol * (((size_t)tiles + lvl1) * (size_t)K + 1) * sizeof(uint64_t);
 }
 
 hipError_t launch_vpeaks(const float* params, long long stride, int batch, int nz, int ny, int nx, int zimg, int K,
@@ -913,15 +953,23 @@ hipError_t launch_vpeaks(const float* params, long long stride, int batch, int n
                          ft_plane_peak* peaks, int32_t* n_found, void* ws, hipStream_t s) {
   const VolGeom g{nz, ny, nx, zimg, stride};
   const int tiles = vpeaks_tiles(nz, ny, nx);
-  uint64_t* cand = static_cast<uint64_t*>(ws);
   if (radius < 1 || radius > 2) return hipErrorInvalidValue;
-  dim3 grid(tiles, batch);
-  if (radius == 1) k_vpeaks_tile<1><<<grid, kPeakThreads, 0, s>>>(params, g, tiles, K, thr, wrap, keep_border, cand);
-  else k_vpeaks_tile<2><<<grid, kPeakThreads, 0, s>>>(params, g, tiles, K, thr, wrap, keep_border, cand);
+  const size_t lvl1 = ((size_t)tiles + merge_group(K) - 1) / merge_group(K);
+  uint64_t* cand = static_cast<uint64_t*>(ws);
+  uint64_t* cut = cand + (size_t)batch * ((size_t)tiles + lvl1) * K;   // as vpeaks_workspace_bytes lays it out
+  k_fill_keys<<<(batch + 255) / 256, 256, 0, s>>>(cut, batch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  dim3 grid(tiles, batch);
+  const float thr_below = std::nextafter(thr, -INFINITY);   // v >= thr  <=>  v > thr_below
+  if (radius == 1)
+    k_vpeaks_tile<1><<<grid, kPeakThreads, 0, s>>>(params, g, tiles, K, thr_below, wrap, keep_border, cut, cand);
+  else
+    k_vpeaks_tile<2><<<grid, kPeakThreads, 0, s>>>(params, g, tiles, K, thr_below, wrap, keep_border, cut, cand);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const uint64_t* list = nullptr;
-  e = reduce_lists(cand, batch, tiles, K, nullptr, &list, s);
+  e = reduce_lists(cand, batch, tiles, K, cut, &list, s);
   if (e != hipSuccess) return e;
   k_vpeaks_records<<<batch, kMergeThreads, 0, s>>>(params, g, K, list, ns, sp, space_id, peaks, n_found);
   return hipGetLastError();

@@ -132,6 +132,46 @@ def test_volume_peaks_exact_on_shared_volume(shape, radius, flags):
     say(f"  counts {cnt.cpu().numpy().tolist()}")
 
 
+def vpeak_volumes(kind, shape, rng):
+    """|P|-like parameter volumes that drive each path of the 3D tile kernel."""
+    nz, ny, nx = shape
+    if kind == "noise":     # ~1/27 of the cells are maxima: about 76 keys per 8 x 4 x 64 tile
+        return np.abs(rng.standard_normal(shape))
+    if kind == "checker":   # a maximum at every (even, even, even) cell: 256 keys per tile
+        P = 0.1 * rng.random(shape)
+        P[::2, ::2, ::2] += 1.0 + rng.random((nz // 2, ny // 2, nx // 2))
+        return P
+    if kind == "levels":    # five levels: exact ties everywhere
+        return np.floor(rng.random(shape) * 5.0) / 5.0
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("radius,K", [(1, 16), (2, 40)])
+def test_volume_peaks_exact_many_tiles(radius, K):
+    """Parameter volumes of 3,072 tiles each, more than the GPU runs at once,
+    so most tiles see a cutoff published by earlier ones: lists identical to
+    the literal procedure on the same FP32 volumes, for the register sort,
+    the block sort of more than 128 keys and exact ties."""
+    import torch
+    B, Nz, Ny, Nx = 3, 128, 128, 128
+    say(f"volume peaks many tiles radius {radius} K {K}")
+    plan = F.VolumePlan(B, Nz, Ny, Nx)
+    params = plan.forward(torch.zeros((B, Nz, Ny, Nx), dtype=torch.float32, device="cuda"))
+    Pz = plan.views(params)["z"]
+    rng = np.random.default_rng([73, radius, K])
+    kinds = ["noise", "checker", "levels"]
+    host = [vpeak_volumes(k, tuple(Pz.shape[1:]), rng).astype(np.float32) for k in kinds]
+    Pz.copy_(torch.from_numpy(np.stack(host)))
+    rec, cnt = plan.peaks(params, K=K, threshold=0.0, radius=radius)
+    got = [g[0] for g in F.plane_peaks_to_numpy(rec, cnt)]
+    mask = O.volume_boundary_mask(Nz, Ny, Nx, plan.Nzp)
+    for b in range(B):
+        want = O.peaks_list_volume(host[b].astype(np.float64), K, 0.0, radius, mask, True)
+        idx = [(int(g["z"]) * Ny + int(g["row"])) * Nx + int(g["col"]) for g in got[b]]
+        assert idx == want, (kinds[b], idx[:5], want[:5])
+    say(f"  counts {cnt.cpu().numpy().tolist()}")
+
+
 def _close_call(Po, i, delta):
     """Whether FP32 error (delta) could change cell i's place in the order or
     its local-maximum status: a neighbour within 2 delta of its |P|."""
