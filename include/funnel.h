@@ -228,7 +228,11 @@ ft_status funnel_peaks_workspace_size(const ft_plan* plan, int32_t K, size_t* by
  *   peaks   : device, ft_peak [batch][n_spaces][K], entries beyond the count
  *             are left unspecified
  *   n_found : device, int32 [batch][n_spaces]
- * Spaces are ordered regular then inverse, as in the plane layout. */
+ *   ws      : device scratch of funnel_peaks_workspace_size bytes: partial
+ *             lists and one cutoff key per plane, all written by the call
+ *             itself (no initialisation needed)
+ * Spaces are ordered regular then inverse, as in the plane layout.  The
+ * lists are the same on every run. */
 ft_status funnel_peaks(const ft_plan* plan, const float* planes, int32_t K, float threshold,
                        int32_t radius, uint32_t flags, ft_peak* peaks, int32_t* n_found,
                        void* ws, size_t ws_bytes, void* stream);
@@ -447,7 +451,11 @@ ft_status funnel_volume_peaks_workspace_size(const ft_volume_plan* plan, int32_t
  *   K       : 1 .. 256;  radius : 1 or 2
  *   peaks   : device, ft_plane_peak [batch][n_spaces][K] (entries beyond the
  *             count unspecified), spaces in the order z, x, y
- *   n_found : device, int32 [batch][n_spaces] */
+ *   n_found : device, int32 [batch][n_spaces]
+ *   ws      : device scratch of funnel_volume_peaks_workspace_size bytes
+ *             (partial lists and one cutoff key per volume, written by the
+ *             call itself)
+ * The lists are the same on every run. */
 ft_status funnel_volume_peaks(const ft_volume_plan* plan, const float* params, int32_t K, float threshold,
                               int32_t radius, uint32_t flags, ft_plane_peak* peaks, int32_t* n_found, void* ws,
                               size_t ws_bytes, void* stream);
