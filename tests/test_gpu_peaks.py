@@ -154,6 +154,14 @@ def test_peaks_bitwise_full_size_planes(K, T, radius, flags):
     rec, cnt = plan.peaks(planes, K=K, threshold=T, radius=radius, flags=flags)
     torch.cuda.synchronize()
     got = F.peaks_to_numpy(rec, cnt)
+    for rep in range(2):   # which keys the partial lists hold depends on timing; the result does not
+        rec2, cnt2 = plan.peaks(planes, K=K, threshold=T, radius=radius, flags=flags)
+        torch.cuda.synchronize()
+        assert torch.equal(cnt2, cnt)
+        for b in range(B):
+            for s in range(2):
+                n = int(cnt[b, s])
+                assert torch.equal(rec2[b, s, :n], rec[b, s, :n]), (rep, b, s)
     wrap = not (flags & F.FT_PEAK_CLAMP_BORDER)
     mask = O.boundary_mask(N, M, plan.Np)
     for b in range(0, B, 3):   # every kind in both spaces; the oracle sorts 2 M cells per plane

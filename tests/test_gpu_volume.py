@@ -164,6 +164,10 @@ def test_volume_peaks_exact_many_tiles(radius, K):
     Pz.copy_(torch.from_numpy(np.stack(host)))
     rec, cnt = plan.peaks(params, K=K, threshold=0.0, radius=radius)
     got = [g[0] for g in F.plane_peaks_to_numpy(rec, cnt)]
+    for rep in range(2):   # which keys the partial lists hold depends on timing; the result does not
+        rec2, cnt2 = plan.peaks(params, K=K, threshold=0.0, radius=radius)
+        assert [[g.tolist() for g in v] for v in F.plane_peaks_to_numpy(rec2, cnt2)] == \
+            [[g.tolist() for g in v] for v in F.plane_peaks_to_numpy(rec, cnt)], rep
     mask = O.volume_boundary_mask(Nz, Ny, Nx, plan.Nzp)
     for b in range(B):
         want = O.peaks_list_volume(host[b].astype(np.float64), K, 0.0, radius, mask, True)
