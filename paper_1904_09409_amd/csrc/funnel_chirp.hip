@@ -52,7 +52,7 @@ struct ChirpCfg {
   static constexpr int R0 = Fwd::kPlan.r[0];
   static constexpr bool valid = W >= 32 && L <= 4096 && radix_plan(L).n > 0 && P >= 2 && Fwd::EM == Inv::EM &&
                                 (POW2 ? L % E_ == 0 : E * 2 <= 3 * E_) && IPB % ROWS == 0 &&
-                                THREADS <= 1024 && THREADS >= 32 && LayRow<ROWS, L>::size(L) * 8 <= 64 * 1024;
+                                THREADS <= 1024 && THREADS >= 32 && LayRow<ROWS, L>::size(L) * 8 + L * 4 <= 80 * 1024;
 };
 
 template <int W, int E_, int TPB, int IPB, int PF, bool ADJ>
@@ -73,6 +73,7 @@ __global__ void __launch_bounds__((ChirpCfg<W, E_, TPB, IPB, PF>::THREADS))
   static_assert(Inv::template bpt<LAST, false>() == BPT0, "inverse outputs land on the forward input slots");
   using Lay = LayRow<ROWS, L>;
   __shared__ float2 lds[Lay::size(L)];
+  __shared__ float2 twl[L / 2];   // the FFT twiddles: every index a pass reads is below L / R <= L / 2
 
   const int tid = threadIdx.x;
   const int row = tid / P, t = tid % P;
@@ -81,6 +82,12 @@ __global__ void __launch_bounds__((ChirpCfg<W, E_, TPB, IPB, PF>::THREADS))
   const int n2 = lin / groups + 1;
   const int grp = lin % groups;
   if (n2 > h) return;   // uniform over the block
+
+  // The twiddles come from LDS: read from global memory inside the
+  // transforms, each of their waits on the in-order load counter would also
+  // wait for the next image's row loads and void the prefetch.  Staged
+  // first, so the loads after them stay in flight.
+  for (int i = tid; i < L / 2; i += Cfg::THREADS) twl[i] = tw[i];
 
   // this row's tables, held for all images of the block
   const float2* czr = cz + (long long)(n2 - 1) * L;
@@ -110,13 +117,10 @@ __global__ void __launch_bounds__((ChirpCfg<W, E_, TPB, IPB, PF>::THREADS))
   };
   float2 nxt[NIN];
   if constexpr (PF) load_row(grp * IPB + row, nxt);
+  __syncthreads();   // twl
 
 #pragma unroll 1
   for (int it = 0; it < IPB / ROWS; ++it) {
-    // re-read the twiddles every image: hoisted out of the loop they would
-    // hold about a hundred more registers and lower the occupancy
-    const float2* twi = tw;
-    asm volatile("" : "+s"(twi));
     const int img = grp * IPB + it * ROWS + row;
     const bool active = img < batch;
     float2* rowp = data + (long long)(active ? img : 0) * img_stride + (long long)(n2 - 1) * W;
@@ -139,10 +143,10 @@ __global__ void __launch_bounds__((ChirpCfg<W, E_, TPB, IPB, PF>::THREADS))
         if (ADJ) x.y = -x.y;
         v[b * R0 + r] = c_mul(x, wr[b * H0 + r]);
       }
-    Fwd::template run<false, false, false, Lay>(v, row, t, lds, twi);
+    Fwd::template run<false, false, false, Lay>(v, row, t, lds, twl);
 #pragma unroll
     for (int s2 = 0; s2 < BPTL * RL; ++s2) v[s2] = c_mul(v[s2], cr[s2]);
-    Inv::template run<false, false, false, Lay>(v, row, t, lds, twi);
+    Inv::template run<false, false, false, Lay>(v, row, t, lds, twl);
     if (!active) continue;
 #pragma unroll
     for (int b = 0; b < BPT0; ++b)
