@@ -664,11 +664,20 @@ struct VTile {
   };
   __device__ static void load_vec(const float* P, const VolGeom& g, const Origin& o, int wrap, Regs& q) {
     const int tid = threadIdx.x;
+    // most tiles' halo rows lie inside the volume along z and y (uniform over
+    // the block): their offsets need no wrapping or clamping
+    const bool interior = o.z0 >= R && o.z0 + kVTileZ + R <= g.nz && o.y0 >= R && o.y0 + kVTileY + R <= g.ny;
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
       const int i = tid + kPeakThreads * j, r = i / (kVTileX / 4), c = i % (kVTileX / 4);
       bool in;
-      const long long b = row_base(g, o, wrap, r, in);
+      long long b;
+      if (interior) {
+        in = (HZ * HY * (kVTileX / 4)) % kPeakThreads == 0 || r < HZ * HY;
+        b = ((long long)(o.z0 - R + r / HY) * g.ny + (o.y0 - R + r % HY)) * g.nx;
+      } else {
+        b = row_base(g, o, wrap, r, in);
+      }
       q.lin[j] = in;
       // unconditional, so all are in flight at once; a lane with nothing to
       // stage reads the tile's own first row, which the block fetches anyway
@@ -678,7 +687,13 @@ struct VTile {
     for (int j = 0; j < NSD; ++j) {
       const int i = tid + kPeakThreads * j, r = i / (2 * R), e = i % (2 * R);
       bool in;
-      const long long b = row_base(g, o, wrap, r, in);
+      long long b;
+      if (interior) {
+        in = r < HZ * HY;
+        b = ((long long)(o.z0 - R + r / HY) * g.ny + (o.y0 - R + r % HY)) * g.nx;
+      } else {
+        b = row_base(g, o, wrap, r, in);
+      }
       const int x = halo_coord(e < R ? o.x0 - R + e : o.x0 + kVTileX + (e - R), g.nx, wrap, in);
       q.ls[j] = P[in ? b + x : origin_row(g, o) + o.x0];
       q.lsin[j] = in;
