@@ -441,7 +441,8 @@ __global__ void k_fill_keys(uint64_t* __restrict__ p, int n) {
 // Lists [plane][nin][K] -> [plane][nout][K], nout = ceil(nin / G): block
 // (j, plane) gathers the keys of lists j G .. j G + G - 1 that are present
 // and not after the plane's cutoff (cut: NULL for none), sorts them and
-// keeps the first K.
+// keeps the first K.  Before the last level (nout > 1) at most K gathered
+// keys pass on unsorted: only the last level's list has to be in order.
 __global__ void __launch_bounds__(kMergeThreads)
     k_peaks_reduce(const uint64_t* __restrict__ in, int nin, uint64_t* __restrict__ out, int nout, int K, int G,
                    const uint64_t* __restrict__ cut) {
@@ -466,12 +467,16 @@ __global__ void __launch_bounds__(kMergeThreads)
   }
   __syncthreads();
   const int c = count;
+  uint64_t* dst = out + ((long long)plane * nout + j) * K;
+  if (nout > 1 && c <= K) {   // uniform: all of them go on, unsorted (the last level sorts)
+    for (int i = threadIdx.x; i < K; i += kMergeThreads) dst[i] = i < c ? keys[i] : kNoKey;
+    return;
+  }
   int n = 1;   // sort the keys gathered, padded to a power of two (>= K, <= G K)
   while (n < c || n < K) n <<= 1;
   for (int i = c + threadIdx.x; i < n; i += kMergeThreads) keys[i] = kNoKey;
   __syncthreads();
   bitonic_sort_n<kMergeThreads>(keys, n);
-  uint64_t* dst = out + ((long long)plane * nout + j) * K;
   for (int i = threadIdx.x; i < K; i += kMergeThreads) dst[i] = keys[i];
 }
 
