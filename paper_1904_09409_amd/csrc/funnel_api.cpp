@@ -1051,8 +1051,9 @@ ft_status funnel_refine(const ft_plan* p, const float* images, const ft_peak* pe
   float2* Abuf = reinterpret_cast<float2*>(w + L.a_off);
   void* state = w + L.st_off;
   hipError_t e = hipSuccess;
-  // the resampled rows g of each space: passes A and B of the forward, then
-  // the inverse x' DFT
+  // the resampled rows g of each space: pass A of the forward, then the
+  // interpolation of pass B alone (linear NVMT), or pass B and the inverse x'
+  // DFT (chirp-z NVMT, whose resampling is band-limited)
   struct Sp { int role_a, role_b, W, space_id; size_t off; size_t tw; };
   Sp sp[2];
   int k = 0;
@@ -1060,10 +1061,14 @@ ft_status funnel_refine(const ft_plan* p, const float* images, const ft_peak* pe
   if (p->spaces & FT_SPACE_INVERSE) sp[k++] = {FA_INV, FB_INV, c.N, 1, c.ws_inv, c.tw_n};
   for (int i = 0; i < ns && e == hipSuccess; ++i) {
     e = run_role(p, c, sp[i].role_a, c.variant[sp[i].role_a], images, nullptr, w, s);
-    if (e == hipSuccess) e = run_role(p, c, sp[i].role_b, c.variant[sp[i].role_b], nullptr, nullptr, w, s);
-    if (e == hipSuccess)
-      e = funnel::launch_row_idft(sp[i].W, reinterpret_cast<float2*>(w + sp[i].off), h, (long long)h * sp[i].W,
-                                  p->tw + sp[i].tw, B, s);
+    float2* rows = reinterpret_cast<float2*>(w + sp[i].off);
+    if (!p->chirpz) {
+      if (e == hipSuccess) e = funnel::launch_row_lerp(sp[i].W, rows, h, c.Np, (long long)h * sp[i].W, B, s);
+    } else {
+      if (e == hipSuccess) e = run_role(p, c, sp[i].role_b, c.variant[sp[i].role_b], nullptr, nullptr, w, s);
+      if (e == hipSuccess)
+        e = funnel::launch_row_idft(sp[i].W, rows, h, (long long)h * sp[i].W, p->tw + sp[i].tw, B, s);
+    }
   }
   if (e == hipSuccess)
     e = funnel::launch_refine_init(peaks, n_found, B, ns, K, sp[0].W, ns > 1 ? sp[1].W : sp[0].W, c.Np, state, s);

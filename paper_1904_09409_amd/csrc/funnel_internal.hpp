@@ -64,6 +64,9 @@ void chirp_tables(int W, int Np, int h, float2* cz, float2* wz);
 // records (final = 1) for space index s of the plan.
 bool refine_length_supported(int W);
 size_t refine_state_bytes();
+// launch_row_lerp: spectrum rows S -> g by the linear NVMT alone (the row
+// pass without its DFT), in place; rows n2 = 1 .. h, padded length Lp.
+hipError_t launch_row_lerp(int W, float2* data, int h, int Lp, long long img_stride, int batch, hipStream_t s);
 hipError_t launch_row_idft(int W, float2* data, int h, long long img_stride, const float2* tw, int batch,
                            hipStream_t s);
 hipError_t launch_refine_init(const ft_peak* peaks, const int32_t* n_found, int batch, int ns, int K, int W0, int W1,

@@ -7,8 +7,10 @@
 //   A(n2; m) = sum_x' g[n2][x'] exp(-j 2 pi m x' / W),
 // equal to the plane at integer (m, y).  Line parameters (Eqs. 22-25) read at
 // its local maximum near a detected cell are continuous, which is where
-// Eq. 19 focuses a line.  The rows g are the inverse x' DFT of the G rows a
-// forward pass leaves in the workspace.  Each iteration forms, for every
+// Eq. 19 focuses a line.  The rows g are the resampled spectrum rows: the
+// row pass's linear interpolation alone (k_row_lerp), or for the chirp-z
+// NVMT the inverse x' DFT of the G rows its row pass leaves in the
+// workspace (k_row_idft).  Each iteration forms, for every
 // peak, A and its first two m-derivatives over all rows (k_refine_dtft_mfma:
 // a (rows x W) by (W x peaks) product per plane on the matrix cores), then
 // reduces over n2 into P,
@@ -71,6 +73,49 @@ __global__ void __launch_bounds__(kIdftThreads) k_row_idft(float2* __restrict__ 
     }
 }
 
+// ------------------------------------------------------------------ rows S -> g
+//
+// With the linear NVMT the rows g are the row pass's interpolation itself:
+// its DFT followed by the inverse above gives back g[q] = the interpolated
+// sample at x' = q - W/2 exactly (up to rounding).  This gathers them
+// straight from the spectrum rows S (same index algebra as the row pass:
+// x = (x' Lp + W n2) / (2 n2) - W/2 on centred indices, zero outside the row),
+// one block per row, in place through an LDS copy of the row.
+constexpr int kLerpThreads = 256;
+
+template <int W>
+__global__ void __launch_bounds__(kLerpThreads) k_row_lerp(float2* __restrict__ data, int Lp, long long img_stride) {
+  __shared__ float2 srow[W];
+  const int n2 = blockIdx.x + 1;
+  float2* rowp = data + (long long)blockIdx.y * img_stride + (long long)(n2 - 1) * W;
+  constexpr int NL = (W + kLerpThreads - 1) / kLerpThreads;
+  float2 st[NL];
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {   // every load in flight before the first store
+    const int i = threadIdx.x + kLerpThreads * j;
+    st[j] = rowp[i < W ? i : 0];
+  }
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    const int i = threadIdx.x + kLerpThreads * j;
+    if (W % kLerpThreads == 0 || i < W) srow[i] = st[j];
+  }
+  __syncthreads();
+  const int den = 2 * n2, wn2 = W * n2;
+  const float rden = 1.0f / (float)den;
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    const int q = threadIdx.x + kLerpThreads * j;
+    if (W % kLerpThreads != 0 && q >= W) continue;
+    const int num = (q - W / 2) * Lp + wn2;
+    const int i0 = floor_div_rcp(num, den, rden);
+    const float tt = (float)(num - i0 * den) * rden;
+    const float2 f0 = i0 >= 0 && i0 < W ? srow[i0] : make_float2(0.f, 0.f);
+    const float2 f1 = i0 + 1 >= 0 && i0 + 1 < W ? srow[i0 + 1] : make_float2(0.f, 0.f);
+    rowp[q] = make_float2((1.f - tt) * f0.x + tt * f1.x, (1.f - tt) * f0.y + tt * f1.y);
+  }
+}
+
 #define FUNNEL_REFINE_LENGTHS(X) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
 bool refine_length_supported(int W) {
@@ -79,6 +124,19 @@ bool refine_length_supported(int W) {
     FUNNEL_REFINE_LENGTHS(CASE)
 #undef CASE
     default: return false;
+  }
+}
+
+hipError_t launch_row_lerp(int W, float2* data, int h, int Lp, long long img_stride, int batch, hipStream_t s) {
+  if (h <= 0 || batch <= 0) return hipSuccess;
+  switch (W) {
+#define CASE(n)                                                                            \
+  case n:                                                                                  \
+    k_row_lerp<n><<<dim3(h, batch), kLerpThreads, 0, s>>>(data, Lp, img_stride);           \
+    return hipGetLastError();
+    FUNNEL_REFINE_LENGTHS(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
   }
 }
 
