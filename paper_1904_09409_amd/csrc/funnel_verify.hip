@@ -59,22 +59,36 @@ __global__ void __launch_bounds__(kVerifyThreads)
 #pragma unroll
   for (int d = 0; d < kMaxBand; ++d) acc[d] = 0.f;
   int cnt = 0;
-  for (int p = tid; p < npos; p += kVerifyThreads) {
-    const float y = fmaf(pk.slope, (float)p, pk.intercept);
-    const float fl = floorf(y);
-    if (!(fl - D >= 0.f && fl + D + 1 <= (float)(across - 1))) continue;   // also drops NaN
-    const int r0 = (int)fl;
-    const float t = y - fl;
-    const float* base = img + p * pos_step + (long long)(r0 - D) * across_step;
-    float a = base[0];
+  // U positions per thread at a time, every sample load issued before the
+  // first use: positions outside the image or with the band crossing its
+  // edge read a valid band (the first one) and add nothing, and samples
+  // past the band (D < 3) repeat its last row, so every address is in
+  // bounds and no load waits behind a branch
+  constexpr int U = 4;
+  for (int p0 = 0; p0 < npos; p0 += U * kVerifyThreads) {
+    float v[U][kMaxBand + 1], tt[U];
+    bool inn[U];
 #pragma unroll
-    for (int d = 0; d < kMaxBand; ++d) {
-      if (d >= nb) break;
-      const float b = base[(long long)(d + 1) * across_step];
-      acc[d] += fmaf(t, b - a, a);   // (1 - t) a + t b
-      a = b;
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + tid + u * kVerifyThreads;
+      const int pc = p < npos ? p : npos - 1;
+      const float y = fmaf(pk.slope, (float)pc, pk.intercept);
+      const float fl = floorf(y);
+      const bool in = p < npos && fl - D >= 0.f && fl + D + 1 <= (float)(across - 1);   // also drops NaN
+      const int r0 = in ? (int)fl : D;
+      tt[u] = y - fl;
+      inn[u] = in;
+      const float* base = img + (long long)pc * pos_step + (long long)(r0 - D) * across_step;
+#pragma unroll
+      for (int d = 0; d <= kMaxBand; ++d) v[u][d] = base[(long long)(d < nb ? d : nb) * across_step];
     }
-    ++cnt;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int d = 0; d < kMaxBand; ++d)   // (1 - t) a + t b between the samples d and d + 1
+        acc[d] += (inn[u] && d < nb) ? fmaf(tt[u], v[u][d + 1] - v[u][d], v[u][d]) : 0.f;
+      cnt += inn[u] ? 1 : 0;
+    }
   }
 
   // block reduction: within each wave by shuffles, then across the waves in LDS
