@@ -180,6 +180,23 @@ def _ptr(t) -> int:
     return int(t.data_ptr())
 
 
+def _need(t, name: str, dtype, numel: int, device) -> None:
+    """The C calls take bare device pointers, so the extent, type and place of
+    every tensor are checked here: a short or foreign buffer raises instead of
+    being written past its end."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device} (got {t.device})")
+    if t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, {numel} needed")
+
+
 def _stream(stream=None) -> int:
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
@@ -370,8 +387,9 @@ def funnel_volume_workspace_size(plan: int) -> int:
 
 
 def funnel_volume_forward(plan: int, volumes, params, ws, stream=None) -> None:
-    _check(load_library().funnel_volume_forward(plan, _ptr(volumes), _ptr(params), _ptr(ws), ws.numel(),
-                                                _stream(stream)), "funnel_volume_forward")
+    _check(load_library().funnel_volume_forward(plan, _ptr(volumes), _ptr(params), _ptr(ws),
+                                                ws.numel() * ws.element_size(), _stream(stream)),
+           "funnel_volume_forward")
 
 
 def funnel_volume_peaks_workspace_size(plan: int, K: int) -> int:
@@ -384,7 +402,8 @@ def funnel_volume_peaks_workspace_size(plan: int, K: int) -> int:
 def funnel_volume_peaks(plan: int, params, K: int, threshold: float, radius: int, flags: int,
                         peaks, n_found, ws, stream=None) -> None:
     _check(load_library().funnel_volume_peaks(plan, _ptr(params), int(K), float(threshold), int(radius), int(flags),
-                                              _ptr(peaks), _ptr(n_found), _ptr(ws), ws.numel(), _stream(stream)),
+                                              _ptr(peaks), _ptr(n_found), _ptr(ws), ws.numel() * ws.element_size(),
+                                              _stream(stream)),
            "funnel_volume_peaks")
 
 
@@ -479,17 +498,28 @@ class FunnelPlan:
             v.inverse = planes[:, off:off + n].view(self.batch, self.Np, self.N)
         return v
 
-    def _check_images(self, images):
+    def _check_images(self, images, name="images"):
         import torch
-        if images.dtype != torch.float32 or not images.is_contiguous() or images.device != self.device:
-            raise ValueError("images must be contiguous float32 on the plan's device")
+        _need(images, name, torch.float32, self.batch * self.N * self.M, self.device)
         if tuple(images.shape) != (self.batch, self.N, self.M):
-            raise ValueError(f"images must have shape {(self.batch, self.N, self.M)}")
+            raise ValueError(f"{name} must have shape {(self.batch, self.N, self.M)}")
+
+    def _check_planes(self, planes, name="planes"):
+        import torch
+        _need(planes, name, torch.float32, self.batch * self.plane_elems, self.device)
+
+    def _check_peaks(self, rec, cnt, words=PEAK_WORDS):
+        import torch
+        if rec.dim() != 4 or rec.shape[:2] != (self.batch, self.nspaces) or rec.shape[3] != words:
+            raise ValueError(f"peak records must have shape ({self.batch}, {self.nspaces}, K, {words})")
+        _need(rec, "peak records", torch.int32, rec.shape[0] * rec.shape[1] * rec.shape[2] * words, self.device)
+        _need(cnt, "peak counts", torch.int32, self.batch * self.nspaces, self.device)
 
     def forward(self, images, planes=None, stream=None):
         self._check_images(images)
         if planes is None:
             planes = self.new_planes()
+        self._check_planes(planes)
         funnel_forward(self.handle, images, planes, self.ws, stream)
         return planes
 
@@ -498,8 +528,10 @@ class FunnelPlan:
         d_planes = d_planes.reshape(self.batch, self.plane_elems)
         if not d_planes.is_contiguous():
             d_planes = d_planes.contiguous()
+        self._check_planes(d_planes, "d_planes")
         if d_images is None:
             d_images = torch.empty((self.batch, self.N, self.M), dtype=torch.float32, device=self.device)
+        self._check_images(d_images, "d_images")
         funnel_adjoint(self.handle, d_planes, d_images, self.ws, stream)
         return d_images
 
@@ -507,6 +539,7 @@ class FunnelPlan:
               stream=None):
         """Returns (records int32 [B, nspaces, K, 7] on the device, counts int32 [B, nspaces])."""
         import torch
+        self._check_planes(planes)
         ws = torch.empty(max(funnel_peaks_workspace_size(self.handle, K), 256), dtype=torch.uint8,
                          device=self.device)
         rec = torch.empty((self.batch, self.nspaces, K, PEAK_WORDS), dtype=torch.int32, device=self.device)
@@ -520,6 +553,8 @@ class FunnelPlan:
         ft_line_check records as int32 [B, nspaces, K, 10] on the device
         (checks_to_numpy() reads them)."""
         import torch
+        self._check_images(images)
+        self._check_peaks(rec, cnt)
         out = torch.empty((rec.shape[0], rec.shape[1], rec.shape[2], LINE_CHECK_WORDS), dtype=torch.int32,
                           device=self.device)
         funnel_verify(self.handle, images, rec, cnt, rec.shape[2], half_width, min_contrast, min_length, out, stream)
@@ -530,6 +565,8 @@ class FunnelPlan:
         as float32 [B, nspaces, K, 6] on the device (refined_to_numpy() reads
         them)."""
         import torch
+        self._check_images(images)
+        self._check_peaks(rec, cnt)
         K = rec.shape[2]
         ws = torch.empty(funnel_refine_workspace_size(self.handle, K), dtype=torch.uint8, device=self.device)
         out = torch.empty((rec.shape[0], rec.shape[1], K, REFINED_WORDS), dtype=torch.float32, device=self.device)
@@ -602,20 +639,26 @@ class RaggedPlan:
         return torch.zeros(self.plane_floats, dtype=torch.float32, device=self.device)
 
     def forward(self, images_flat, planes=None, stream=None):
+        import torch
+        _need(images_flat, "images", torch.float32, self.image_floats, self.device)
         if planes is None:
             planes = self.new_planes()
+        _need(planes, "planes", torch.float32, self.plane_floats, self.device)
         funnel_forward(self.handle, images_flat, planes, self.ws, stream)
         return planes
 
     def adjoint(self, d_planes, d_images=None, stream=None):
         import torch
+        _need(d_planes, "d_planes", torch.float32, self.plane_floats, self.device)
         if d_images is None:
             d_images = torch.zeros(self.image_floats, dtype=torch.float32, device=self.device)
+        _need(d_images, "d_images", torch.float32, self.image_floats, self.device)
         funnel_adjoint(self.handle, d_planes, d_images, self.ws, stream)
         return d_images
 
     def peaks(self, planes, K: int = 16, threshold: float = 0.0, radius: int = 1, flags: int = 0, stream=None):
         import torch
+        _need(planes, "planes", torch.float32, self.plane_floats, self.device)
         ws = torch.empty(max(funnel_peaks_workspace_size(self.handle, K), 256), dtype=torch.uint8,
                          device=self.device)
         rec = torch.empty((self.batch, self.nspaces, K, PEAK_WORDS), dtype=torch.int32, device=self.device)
@@ -629,6 +672,11 @@ class RaggedPlan:
         ft_line_check records as int32 [B, nspaces, K, 10] on the device
         (checks_to_numpy() reads them)."""
         import torch
+        _need(images, "images", torch.float32, self.image_floats, self.device)
+        if rec.dim() != 4 or rec.shape[:2] != (self.batch, self.nspaces) or rec.shape[3] != PEAK_WORDS:
+            raise ValueError(f"peak records must have shape ({self.batch}, {self.nspaces}, K, {PEAK_WORDS})")
+        _need(rec, "peak records", torch.int32, rec.numel(), self.device)
+        _need(cnt, "peak counts", torch.int32, self.batch * self.nspaces, self.device)
         out = torch.empty((rec.shape[0], rec.shape[1], rec.shape[2], LINE_CHECK_WORDS), dtype=torch.int32,
                           device=self.device)
         funnel_verify(self.handle, images, rec, cnt, rec.shape[2], half_width, min_contrast, min_length, out, stream)
@@ -757,18 +805,19 @@ class VolumePlan:
 
     def forward(self, volumes, params=None, stream=None):
         import torch
-        if volumes.dtype != torch.float32 or not volumes.is_contiguous() or volumes.device != self.device:
-            raise ValueError("volumes must be contiguous float32 on the plan's device")
+        _need(volumes, "volumes", torch.float32, self.batch * self.Nz * self.Ny * self.Nx, self.device)
         if tuple(volumes.shape) != (self.batch, self.Nz, self.Ny, self.Nx):
             raise ValueError(f"volumes must have shape {(self.batch, self.Nz, self.Ny, self.Nx)}")
         if params is None:
             params = self.new_params()
+        _need(params, "params", torch.float32, self.batch * self.param_elems, self.device)
         funnel_volume_forward(self.handle, volumes, params, self.ws, stream)
         return params
 
     def peaks(self, params, K: int = 16, threshold: float = 0.0, radius: int = 1, flags: int = 0, stream=None):
         """Returns (records int32 [B, nspaces, K, 9] on the device, counts int32 [B, nspaces])."""
         import torch
+        _need(params, "params", torch.float32, self.batch * self.param_elems, self.device)
         ws = torch.empty(max(funnel_volume_peaks_workspace_size(self.handle, K), 256), dtype=torch.uint8,
                          device=self.device)
         rec = torch.empty((self.batch, self.nspaces, K, PLANE_PEAK_WORDS), dtype=torch.int32, device=self.device)

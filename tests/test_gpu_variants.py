@@ -1,8 +1,10 @@
 """Every tile variant of every launch against the FP64 oracle.  The plan
 starts from default variants and the autotuner may pick any other, so each
-one must compute the same transform: for v = 0 .. 7, every launch that has a
+one must compute the same transform: for v = 0 .. 11, every launch that has a
 variant v is switched to it and the forward planes and the adjoint are
-compared with the oracle."""
+compared with the oracle.  The shapes include the benchmark's lengths
+(Np = 2048, rows of 1024) and those of the 8 x 2048^2 workload, so every
+kernel instantiation a tuned plan can time there is compared too."""
 import numpy as np
 import pytest
 
@@ -25,6 +27,8 @@ def say(*a):
     (240, 320),     # Np 560 = 16*5*7: LDS-resident column variants
     (720, 1280),    # Np 2000 = 16*5^3
     (1080, 1920),   # Np 3000 = 8*3*5^3
+    (1024, 1024),   # Np 2048, rows 1024: the benchmark's lengths
+    (2048, 2048),   # Np 4096, rows 2048: the 8 x 2048^2 workload's lengths
 ])
 def test_every_variant_matches_oracle(N, M):
     import torch

@@ -1,6 +1,9 @@
-"""Full-size workloads, in the launch configuration the benchmark times,
-checked against the FP64 oracle on sampled images; and the gradient of the
-peak loss against FP64 finite differences and the dense operator."""
+"""Full-size workloads checked against the FP64 oracle on sampled images:
+the 32 x 1024^2 batch both with the tile variants the benchmark times
+(bench.benchmark_variants: the counter table's set, else the autotuner's) and
+with the plan defaults, its peak lists end to end, and the 64 x 512^2 batch;
+the gradient of the peak loss against FP64 finite differences and the dense
+operator."""
 import numpy as np
 import pytest
 
@@ -39,12 +42,54 @@ def loss_gradient(plan, planes, imgs):
     return dP
 
 
-def check_workload(config, B, size, samples):
+def bench_plan(B, size):
+    """A plan set up exactly as bench.py's default run sets up its plan."""
+    import bench
+    plan = F.FunnelPlan(B, size, size)
+    src = bench.benchmark_variants(F, plan)
+    say(f"  tile variants ({src}): {F.funnel_plan_variants(plan.handle)}")
+    return plan
+
+
+def check_peaks_end_to_end(plan, planes, refs, K=16, min_prefix=8):
+    """GPU planes -> GPU peaks against oracle planes -> the literal list of
+    Sec. 4.4.  The margin comes from the stated FP32 bound, not from the
+    run's own error: every cell of the GPU plane must be within
+    1e-5 max|P| of the oracle's (checked), and any two planes that close give
+    the same first k peaks wherever every comparison deciding them is
+    separated by more than twice that (decidable_prefix, with 2.5x).  That
+    prefix is a property of the oracle plane alone, and at least min_prefix
+    of the K peaks must fall in it."""
+    from test_gpu_peaks import nb_max
+    from test_gpu_precision import decidable_prefix
+    rec, cnt = plan.peaks(planes, K=K)
+    got = F.peaks_to_numpy(rec, cnt)
+    v = plan.views(planes)
+    mask = O.boundary_mask(plan.N, plan.M, plan.Np)
+    for b, ref in refs.items():
+        decided = []
+        for s, Pref in enumerate(ref):
+            gp = (v.regular if s == 0 else v.inverse)[b].cpu().numpy()
+            Bp = np.abs(Pref)
+            bound = 1e-5 * Bp.max()
+            delta = np.abs(np.abs(gp) - Bp).max()
+            assert delta <= bound, (b, s, delta, bound)
+            lst = O.peaks_list(Bp, K + 1, 0.0, 1, mask, True)
+            k = decidable_prefix(Bp, lst, nb_max(Bp, 1, True), mask, 2.5 * bound)
+            g = got[b][s]
+            ids = [int(r) * Bp.shape[1] + int(c) for r, c in zip(g["row"], g["col"])]
+            assert ids[:k] == lst[:k], (b, s, k, ids[:k], lst[:k])
+            assert k >= min_prefix, (b, s, k)
+            decided.append(k)
+        say(f"  image {b}: peaks identical to the oracle's on decidable prefixes {decided} of {K}")
+
+
+def check_workload(config, B, size, samples, variants="default", peaks=False):
     import torch
-    say(f"workload {config}: {B} x {size}^2 (samples {samples})")
+    say(f"workload {config}: {B} x {size}^2 (samples {samples}), {variants} tile variants")
     imgs = synth.batch(config, count=B, size=size, seed=0)
     x = torch.from_numpy(synth.stack(imgs)).cuda()
-    plan = F.FunnelPlan(B, size, size)
+    plan = bench_plan(B, size) if variants == "bench" else F.FunnelPlan(B, size, size)
     planes = plan.forward(x)
     dP = loss_gradient(plan, planes, imgs)
     dI = plan.adjoint(dP)
@@ -52,9 +97,11 @@ def check_workload(config, B, size, samples):
     v = plan.views(planes)
     Np = plan.Np
     dPh = dP.cpu().numpy()
+    refs = {}
     for b in samples:
         img = imgs[b].image.astype(np.float64)
         ref_r, ref_i = O.forward(img, Np)
+        refs[b] = (ref_r, ref_i)
         e_r = rel_l2(v.regular[b].cpu().numpy(), ref_r)
         e_i = rel_l2(v.inverse[b].cpu().numpy(), ref_i)
         ref_d = O.adjoint(dPh[b, :Np * size].reshape(Np, size).astype(np.float64),
@@ -62,10 +109,19 @@ def check_workload(config, B, size, samples):
         e_d = rel_l2(dI[b].cpu().numpy(), ref_d)
         say(f"  image {b}: rel L2 regular {e_r:.2e} inverse {e_i:.2e} adjoint {e_d:.2e}")
         assert max(e_r, e_i, e_d) <= TOL
+    if peaks:
+        check_peaks_end_to_end(plan, planes, refs)
 
 
-def test_grad_workload_1024():
-    """32 x 1024^2, both spaces, forward + adjoint of the peak loss."""
+def test_grad_workload_1024_bench_variants():
+    """32 x 1024^2, both spaces, forward + adjoint of the peak loss, in the
+    launch configuration bench.py times (its tile variants), and the peak
+    lists of two images end to end."""
+    check_workload("grad", 32, 1024, samples=(0, 31), variants="bench", peaks=True)
+
+
+def test_grad_workload_1024_default_variants():
+    """The same batch with the plan's default tile variants."""
     check_workload("grad", 32, 1024, samples=(0, 31))
 
 
