@@ -237,6 +237,26 @@ ft_status funnel_peaks(const ft_plan* plan, const float* planes, int32_t K, floa
                        int32_t radius, uint32_t flags, ft_peak* peaks, int32_t* n_found,
                        void* ws, size_t ws_bytes, void* stream);
 
+/* Largest peak scratch funnel_peaks_noalloc can use (64 MiB per GPU). */
+#define FT_PEAKS_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* funnel_peaks for callers that cannot allocate or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same lists, with the partial lists and per-plane cutoffs
+ * in a static device array of FT_PEAKS_SCRATCH_BYTES that each GPU holds
+ * from the first plan created on it until the process ends.  It calls no
+ * allocator.  Arguments, checks and outputs as funnel_peaks; a plan and K
+ * whose funnel_peaks_workspace_size exceeds FT_PEAKS_SCRATCH_BYTES give
+ * FT_ERR_WORKSPACE_TOO_SMALL (use funnel_peaks with a workspace then; the
+ * 32 x 1024^2 batch, both spaces, needs 17 MB at K = 16).  Every call on a
+ * GPU shares that GPU's scratch, which keeps the last call's contents; each
+ * call re-initialises what it reads (the cutoffs) by a fill kernel of its
+ * own, so calls ordered one after the other (on one stream, or synchronised)
+ * are fine, while calls that can run at the same time on one GPU
+ * (unsynchronised streams, or host threads) race and give wrong lists. */
+ft_status funnel_peaks_noalloc(const ft_plan* plan, const float* planes, int32_t K, float threshold,
+                               int32_t radius, uint32_t flags, ft_peak* peaks, int32_t* n_found, void* stream);
+
 /* One checked candidate line (Sec. 4.5). */
 typedef struct {
   float profile[7];   /* mean image value on the line shifted by d = -D..D across it

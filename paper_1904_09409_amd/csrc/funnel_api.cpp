@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -115,6 +116,41 @@ ft_status check_device(const ft_plan* p) {
 
 ft_status hip_fail(hipError_t e, const char* what) {
   return fail(FT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ static peak scratch
+//
+// funnel_peaks_noalloc keeps the partial peak lists and per-plane cutoffs in
+// this array instead of a caller workspace.  Every GPU the library runs on
+// holds its own copy until the process ends.  In host code the name stands
+// for a host-side shadow, not a device address: host code uses only the
+// address hipGetSymbolAddress returns for each device, resolved once per
+// device (with that device current) when a plan is created there.
+constexpr size_t kPeakScratchBytes = FT_PEAKS_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kPeakScratchBytes];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxScratchDevices] = {};
+
+// The device address of `scratch` on device dev (the current device when it
+// is first resolved).
+ft_status scratch_for_device(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(FT_ERR_NO_DEVICE, "device %d is beyond the %d the peak scratch table covers", dev, kMaxScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return FT_OK;
 }
 
 // exp(-i 2 pi m / L), m = 0 .. L-1, evaluated in double and rounded to float
@@ -363,6 +399,9 @@ ft_status finish_plan(ft_plan* p, const std::vector<std::vector<std::pair<long l
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(FT_ERR_NO_DEVICE, "no HIP device");
   if (hipGetDevice(&dev) != hipSuccess) return fail(FT_ERR_NO_DEVICE, "no current HIP device");
   p->device = dev;
+  char* scr = nullptr;   // the no-allocation peak call's scratch, resolved here once per device
+  ft_status sst = scratch_for_device(dev, &scr);
+  if (sst != FT_OK) return sst;
 
   std::vector<float2> host(ntw);
   for (auto& c : p->cls) {
@@ -922,29 +961,33 @@ ft_status funnel_peaks_workspace_size(const ft_plan* p, int32_t K, size_t* bytes
   return ok();
 }
 
-ft_status funnel_peaks(const ft_plan* p, const float* planes, int32_t K, float threshold, int32_t radius,
-                       uint32_t flags, ft_peak* peaks, int32_t* n_found, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Host-side checks of a peak call, everything but the workspace.
+ft_status peaks_args(const ft_plan* p, const float* planes, int32_t K, float threshold, int32_t radius,
+                     uint32_t flags, const ft_peak* peaks, const int32_t* n_found) {
   if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
-  if (!planes || !peaks || !n_found || !ws) return fail(FT_ERR_INVALID_ARG, "pointers must be non-NULL");
+  if (!planes || !peaks || !n_found) return fail(FT_ERR_INVALID_ARG, "pointers must be non-NULL");
   if (K < 1 || K > 256) return fail(FT_ERR_INVALID_ARG, "K must be in 1..256 (got %d)", K);
   if (radius < 1 || radius > 8) return fail(FT_ERR_INVALID_ARG, "radius must be in 1..8 (got %d)", radius);
   if (std::isnan(threshold)) return fail(FT_ERR_INVALID_ARG, "threshold is NaN");
   if (flags & ~(uint32_t)(FT_PEAK_CLAMP_BORDER | FT_PEAK_KEEP_PAD_BOUNDARY))
     return fail(FT_ERR_INVALID_ARG, "unknown peak flags 0x%x", flags);
-  if (!aligned16(planes) || !aligned16(peaks) || !aligned16(n_found) || !aligned16(ws))
+  if (!aligned16(planes) || !aligned16(peaks) || !aligned16(n_found))
     return fail(FT_ERR_MISALIGNED, "device pointers must be 16-byte aligned");
-  size_t need = 0;
-  ft_status st = funnel_peaks_workspace_size(p, K, &need);
-  if (st != FT_OK) return st;
-  if (ws_bytes < need) return fail(FT_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
-  if ((st = check_device(p)) != FT_OK) return st;
-  (void)hipGetLastError();
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  return FT_OK;
+}
+
+// Enqueue the peak kernels of every size class; class c's partial lists and
+// cutoffs take the next peaks_workspace_bytes of w.
+hipError_t peaks_enqueue(const ft_plan* p, const float* planes, int32_t K, float threshold, int32_t radius,
+                         uint32_t flags, ft_peak* peaks, int32_t* n_found, char* w, hipStream_t s) {
   const int ns = (p->spaces == FT_SPACE_BOTH) ? 2 : 1;
   const bool fork = p->cls.size() > 1;
   hipError_t e = hipSuccess;
   if (fork) e = hipEventRecord(p->fork, s);
-  char* w = static_cast<char*>(ws);
   for (size_t ci = 0; ci < p->cls.size() && e == hipSuccess; ++ci) {
     const FtClass& c = p->cls[ci];
     hipStream_t cs = fork ? c.stream : s;
@@ -970,6 +1013,46 @@ ft_status funnel_peaks(const ft_plan* p, const float* planes, int32_t K, float t
   }
   for (size_t ci = 0; fork && ci < p->cls.size() && e == hipSuccess; ++ci)
     e = hipStreamWaitEvent(s, p->cls[ci].done, 0);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+ft_status funnel_peaks(const ft_plan* p, const float* planes, int32_t K, float threshold, int32_t radius,
+                       uint32_t flags, ft_peak* peaks, int32_t* n_found, void* ws, size_t ws_bytes, void* stream) {
+  ft_status st = peaks_args(p, planes, K, threshold, radius, flags, peaks, n_found);
+  if (st != FT_OK) return st;
+  if (!ws) return fail(FT_ERR_INVALID_ARG, "pointers must be non-NULL");
+  if (!aligned16(ws)) return fail(FT_ERR_MISALIGNED, "device pointers must be 16-byte aligned");
+  size_t need = 0;
+  if ((st = funnel_peaks_workspace_size(p, K, &need)) != FT_OK) return st;
+  if (ws_bytes < need) return fail(FT_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+  if ((st = check_device(p)) != FT_OK) return st;
+  (void)hipGetLastError();
+  hipError_t e = peaks_enqueue(p, planes, K, threshold, radius, flags, peaks, n_found, static_cast<char*>(ws),
+                               static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return ok();
+}
+
+ft_status funnel_peaks_noalloc(const ft_plan* p, const float* planes, int32_t K, float threshold, int32_t radius,
+                               uint32_t flags, ft_peak* peaks, int32_t* n_found, void* stream) {
+  ft_status st = peaks_args(p, planes, K, threshold, radius, flags, peaks, n_found);
+  if (st != FT_OK) return st;
+  size_t need = 0;
+  if ((st = funnel_peaks_workspace_size(p, K, &need)) != FT_OK) return st;
+  if (need > kPeakScratchBytes)
+    return fail(FT_ERR_WORKSPACE_TOO_SMALL,
+                "this plan and K need %zu bytes of peak scratch, the static scratch holds %zu; "
+                "use funnel_peaks with a workspace", need, kPeakScratchBytes);
+  if ((st = check_device(p)) != FT_OK) return st;
+  char* w = nullptr;
+  if ((st = scratch_for_device(p->device, &w)) != FT_OK) return st;
+  (void)hipGetLastError();
+  hipError_t e = peaks_enqueue(p, planes, K, threshold, radius, flags, peaks, n_found, w,
+                               static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return ok();
 }

@@ -121,6 +121,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "funnel_adjoint": ([vp, vp, vp, vp, sz, vp], ctypes.c_int),
         "funnel_peaks_workspace_size": ([vp, i32, ctypes.POINTER(sz)], ctypes.c_int),
         "funnel_peaks": ([vp, vp, i32, ctypes.c_float, i32, u32, vp, vp, vp, sz, vp], ctypes.c_int),
+        "funnel_peaks_noalloc": ([vp, vp, i32, ctypes.c_float, i32, u32, vp, vp, vp], ctypes.c_int),
         "funnel_verify": ([vp, vp, vp, vp, i32, i32, ctypes.c_float, i32, vp, vp], ctypes.c_int),
         "funnel_refine_workspace_size": ([vp, i32, ctypes.POINTER(sz)], ctypes.c_int),
         "funnel_refine": ([vp, vp, vp, vp, i32, i32, vp, vp, sz, vp], ctypes.c_int),
@@ -297,6 +298,13 @@ def funnel_peaks(plan: int, planes, K: int, threshold: float, radius: int, flags
     _check(load_library().funnel_peaks(plan, _ptr(planes), int(K), float(threshold), int(radius), int(flags),
                                        _ptr(peaks), _ptr(n_found), _ptr(ws), ws.numel() * ws.element_size(),
                                        _stream(stream)), "funnel_peaks")
+
+
+def funnel_peaks_noalloc(plan: int, planes, K: int, threshold: float, radius: int, flags: int,
+                         peaks, n_found, stream=None) -> None:
+    _check(load_library().funnel_peaks_noalloc(plan, _ptr(planes), int(K), float(threshold), int(radius),
+                                               int(flags), _ptr(peaks), _ptr(n_found), _stream(stream)),
+           "funnel_peaks_noalloc")
 
 
 def funnel_verify(plan: int, images, peaks, n_found, K: int, half_width: int, min_contrast: float,
