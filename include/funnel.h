@@ -145,7 +145,11 @@ ft_status funnel_plan_create(const ft_plan_desc* desc, ft_plan** out);
  * each image's planes (regular then inverse, Np = rows+cols) start at
  * plane_offset.  Offsets are in floats from the images / planes base and must
  * be multiples of 4 (16-byte alignment).  The caller keeps the regions
- * disjoint; the library cannot see the buffers' extent. */
+ * disjoint; the library cannot see the buffers' extent.
+ * Unlike a uniform plan's description, an image has no padded_len (ragged
+ * images always use Np = rows+cols, Sec. 4.2) and a ragged plan has no
+ * precision or NVMT flag: ragged batches run the FP32 path with the linear
+ * NVMT. */
 typedef struct {
   int32_t rows;          /* N, even, >= 4 */
   int32_t cols;          /* M, even, >= 4 */

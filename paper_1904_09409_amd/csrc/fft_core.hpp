@@ -539,10 +539,16 @@ struct FftR {
     }
   }
 
+  // The thread's coordinates pass through an empty asm after the barrier, so
+  // that the exchange's LDS addresses are computed there and not hoisted into
+  // the register-heavy butterflies before it (where they were spilled).
+  __device__ static __forceinline__ void pin(int& line, int& t) { asm volatile("" : "+v"(line), "+v"(t)); }
+
   template <int I, bool PAIRED_OUT, bool PAIRED_IN, bool SPLIT, class Lay, class Buf>
   __device__ static __forceinline__ void exchange(float2 (&v)[EM], int line, int t, Buf* lds) {
     if constexpr (!SPLIT) {
       __syncthreads();
+      pin(line, t);
       xwrite<I, PAIRED_OUT, Lay>(line, t, lds, [&](int s) { return v[s]; });
       __syncthreads();
       xread<I + 1, PAIRED_IN, Lay>(line, t, lds, [&](int s, float2 f) { v[s] = f; });
@@ -550,6 +556,7 @@ struct FftR {
 #pragma unroll
       for (int part = 0; part < 2; ++part) {
         __syncthreads();
+        pin(line, t);
         xwrite<I, PAIRED_OUT, Lay>(line, t, lds, [&](int s) { return part ? v[s].y : v[s].x; });
         __syncthreads();
         xread<I + 1, PAIRED_IN, Lay>(line, t, lds, [&](int s, float f) {

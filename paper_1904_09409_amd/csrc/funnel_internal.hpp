@@ -31,6 +31,7 @@ bool length_supported(int L);
 // precisions: 0 when the length has no matrix-core kernel)
 unsigned col_variant_mask(int L, int prec);
 unsigned row_variant_mask(int M, int prec);
+// (bits 0-7: register tiles, 8-10: LDS-resident tiles)
 constexpr int kMaxVariants = 12;
 
 // real lines (zero-padded to L) -> half spectrum rows 1..L/2-1, times scale*(-1)^k

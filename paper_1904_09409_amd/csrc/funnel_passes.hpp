@@ -344,10 +344,12 @@ struct FastCfg {
                                 (NT == 1 || em() * NT <= 2 * E_);
 };
 
-// column-pass variants: (elements per thread, column pairs per group, groups per block)
-#define FUNNEL_COL_VARIANTS(X) \
-  X(0, 16, 4, 1) X(1, 16, 8, 1) X(2, 16, 16, 1) X(3, 32, 4, 1) X(4, 32, 8, 1) X(5, 32, 16, 1) X(6, 16, 8, 2) X(7, 16, 4, 2)
-constexpr int kColVariants = 8;
+// column-pass variants: (elements per thread, column pairs per group, groups
+// per block, waves per SIMD the registers must leave room for; 1 = no floor)
+#define FUNNEL_COL_VARIANTS(X)                                                                         \
+  X(0, 16, 4, 1, 1) X(1, 16, 8, 1, 1) X(2, 16, 16, 1, 1) X(3, 32, 4, 1, 1) X(4, 32, 8, 1, 1) X(5, 32, 16, 1, 1) \
+  X(6, 16, 8, 2, 1) X(7, 16, 4, 2, 1)
+constexpr int kColVariants = 8;   // register tiles 0-7; 8-10 are the LDS-resident tiles
 
 // Raw buffer access: 32-bit byte offsets from a per-block base, and hardware
 // range checking (offsets at or beyond `bytes`, including negative offsets,
@@ -403,10 +405,13 @@ __device__ __forceinline__ void emit_pair(GBuf dst, int k, float2 zk, float2 zm,
 __device__ __forceinline__ float2 herm_direct(float4 x) { return make_float2(x.x - x.w, x.y + x.z); }  // A + iB
 __device__ __forceinline__ float2 herm_mirror(float4 x) { return make_float2(x.x + x.w, x.z - x.y); }  // conj A + i conj B
 
-template <int L, int E_, int LINES_, int NT, bool TRANS, int PREC>
-__global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS))
+// Both column kernels run one column tile of one image per block on a 1D grid
+// of `total` = tiles x images blocks; consecutive tiles map to one XCD
+// (xcd_remap).
+template <int L, int E_, int LINES_, int NT, bool TRANS, int PREC, int WPE = 1>
+__global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS)) __attribute__((amdgpu_waves_per_eu(WPE)))
     k_r2c_fast(const float* __restrict__ in, float2* __restrict__ out, int nlines, int lin, int off,
-               ImgMap map, float scale, const float2* __restrict__ tw, int tiles) {
+               ImgMap map, float scale, const float2* __restrict__ tw, int tiles, int total) {
   using Cfg = FastCfg<L, E_, LINES_, NT>;
   constexpr int P = Cfg::P, LINES = Cfg::LINES, H = L / 2 - 1;
   using Eng = typename EngSel<PREC, L, P, false, false, LINES, true>::type;
@@ -418,10 +423,10 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS))
   using Lay = LayInterR<LINES>;
   __shared__ float lds[Lay::size(L)];
 
-  const int logical = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-  const int tile = logical % tiles, img = logical / tiles;
-  const int tid = threadIdx.x, pair = tid % LINES, t = tid / LINES;
   const int npairs = nlines >> 1;
+  const int tid = threadIdx.x, pair = tid % LINES, t = tid / LINES;
+  const int logical = xcd_remap(blockIdx.x, total);
+  const int tile = logical % tiles, img = logical / tiles;
   // one image's lin x nlines block (rows of the padded frame off .. off+lin-1)
   const GBuf src(in + map.in(img), (long long)lin * nlines * 4);
 
@@ -485,10 +490,10 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS))
   }
 }
 
-template <int L, int E_, int LINES_, int NT, bool TRANS, bool ACCUM, int PREC>
-__global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS))
+template <int L, int E_, int LINES_, int NT, bool TRANS, bool ACCUM, int PREC, int WPE = 1>
+__global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS)) __attribute__((amdgpu_waves_per_eu(WPE)))
     k_c2r_fast(const float2* __restrict__ in, float* __restrict__ out, int nlines, int r0, int nout,
-               ImgMap map, float scale, const float2* __restrict__ tw, int tiles) {
+               ImgMap map, float scale, const float2* __restrict__ tw, int tiles, int total) {
   using Cfg = FastCfg<L, E_, LINES_, NT>;
   constexpr int P = Cfg::P, LINES = Cfg::LINES;
   using Eng = typename EngSel<PREC, L, P, true, true, LINES, true>::type;
@@ -500,10 +505,10 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS))
   using Lay = LayInterR<LINES>;
   __shared__ float lds[Lay::size(L)];
 
-  const int logical = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-  const int tile = logical % tiles, img = logical / tiles;
-  const int tid = threadIdx.x, pair = tid % LINES, t = tid / LINES;
   const int npairs = nlines >> 1;
+  const int tid = threadIdx.x, pair = tid % LINES, t = tid / LINES;
+  const int logical = xcd_remap(blockIdx.x, total);
+  const int tile = logical % tiles, img = logical / tiles;
   // half-spectrum rows 1 .. L/2-1; row 0 (and anything outside) reads 0
   const GBuf src(in + map.in(img), (long long)(L / 2 - 1) * npairs * 16);
 
@@ -760,7 +765,7 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
 template <int L, int PREC>
 unsigned col_variant_mask_t() {
   unsigned m = 0;
-#define FUNNEL_V(i, e, l, nt)                                                                             \
+#define FUNNEL_V(i, e, l, nt, wpe)                                                                        \
   if constexpr (FastCfg<L, e, l, nt>::valid && (PREC == kPrecFP32 || (nt == 1 && mfma_fits(L, e, FastCfg<L, e, l, nt>::THREADS)))) \
     m |= 1u << i;
   FUNNEL_COL_VARIANTS(FUNNEL_V)
@@ -791,17 +796,16 @@ template <int L, int PREC>
 hipError_t launch_r2c_t(int variant, bool trans, const float* in, float2* out, int nlines, int lin, int off,
                         ImgMap map, float scale, const float2* tw, int batch, hipStream_t s) {
   switch (variant) {
-#define FUNNEL_V(i, e, l, nt)                                                                                \
+#define FUNNEL_V(i, e, l, nt, wpe)                                                                           \
   case i:                                                                                                    \
     if constexpr (FastCfg<L, e, l, nt>::valid &&                                                             \
                   (PREC == kPrecFP32 || (nt == 1 && mfma_fits(L, e, FastCfg<L, e, l, nt>::THREADS)))) {                    \
       using F = FastCfg<L, e, l, nt>;                                                                        \
-      const int tiles = (nlines / 2 + F::LINES * nt - 1) / (F::LINES * nt);                                  \
-      dim3 grid(tiles, batch), block(F::THREADS);                                                            \
+      const int tiles = (nlines / 2 + F::LINES * nt - 1) / (F::LINES * nt), total = tiles * batch;           \
       if (trans)                                                                                             \
-        k_r2c_fast<L, e, l, nt, true, PREC><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, tiles); \
+        k_r2c_fast<L, e, l, nt, true, PREC, wpe><<<total, F::THREADS, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, tiles, total); \
       else                                                                                                   \
-        k_r2c_fast<L, e, l, nt, false, PREC><<<grid, block, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, tiles); \
+        k_r2c_fast<L, e, l, nt, false, PREC, wpe><<<total, F::THREADS, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, tiles, total); \
       return hipGetLastError();                                                                              \
     }                                                                                                        \
     break;
@@ -838,23 +842,21 @@ template <int L, int PREC>
 hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0,
                         int nout, ImgMap map, float scale, const float2* tw, int batch, hipStream_t s) {
   switch (variant) {
-#define FUNNEL_V(i, e, l, nt)                                                                                \
+#define FUNNEL_V(i, e, l, nt, wpe)                                                                           \
   case i:                                                                                                    \
     if constexpr (FastCfg<L, e, l, nt>::valid &&                                                             \
                   (PREC == kPrecFP32 || (nt == 1 && mfma_fits(L, e, FastCfg<L, e, l, nt>::THREADS)))) {                    \
       using F = FastCfg<L, e, l, nt>;                                                                        \
-      const int tiles = (nlines / 2 + F::LINES * nt - 1) / (F::LINES * nt);                                  \
-      dim3 grid(tiles, batch), block(F::THREADS);                                                            \
+      const int tiles = (nlines / 2 + F::LINES * nt - 1) / (F::LINES * nt), total = tiles * batch;           \
+      auto go = [&](auto* k) {                                                                               \
+        k<<<total, F::THREADS, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles, total);              \
+      };                                                                                                     \
       if (trans) {                                                                                           \
-        if (accum)                                                                                           \
-          k_c2r_fast<L, e, l, nt, true, true, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
-        else                                                                                                 \
-          k_c2r_fast<L, e, l, nt, true, false, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
+        if (accum) go(k_c2r_fast<L, e, l, nt, true, true, PREC, wpe>);                                      \
+        else go(k_c2r_fast<L, e, l, nt, true, false, PREC, wpe>);                                           \
       } else {                                                                                               \
-        if (accum)                                                                                           \
-          k_c2r_fast<L, e, l, nt, false, true, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
-        else                                                                                                 \
-          k_c2r_fast<L, e, l, nt, false, false, PREC><<<grid, block, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles); \
+        if (accum) go(k_c2r_fast<L, e, l, nt, false, true, PREC, wpe>);                                     \
+        else go(k_c2r_fast<L, e, l, nt, false, false, PREC, wpe>);                                          \
       }                                                                                                      \
       return hipGetLastError();                                                                              \
     }                                                                                                        \

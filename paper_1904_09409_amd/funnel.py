@@ -43,6 +43,10 @@ FT_PEAK_CLAMP_BORDER = 1
 FT_PEAK_KEEP_PAD_BOUNDARY = 2
 FT_GRAPH_FORWARD = 1
 FT_GRAPH_ADJOINT = 2
+# tile variants per launch (funnel_plan_set_variant): 0-7 register tiles,
+# 8-10 LDS-resident tiles (column passes); 0-3 register and 4-5 LDS-resident
+# tiles (row passes)
+MAX_VARIANTS = 12
 
 
 class ft_plan_desc(ctypes.Structure):

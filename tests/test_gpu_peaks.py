@@ -2,6 +2,7 @@
 import numpy as np
 import pytest
 
+from helpers import nb_max
 from oracle import funnel_oracle as O
 from paper_1904_09409_amd import funnel as F
 from paper_1904_09409_amd import synth
@@ -24,24 +25,6 @@ def plane_shapes(N, M, Np, spaces):
 
 def oracle_peaks(B, K, T, radius, mask, wrap):
     return O.peaks_list(B, K, T, radius, mask, wrap)
-
-
-def nb_max(B, radius, wrap):
-    rows, cols = B.shape
-    out = np.full(B.shape, -np.inf)
-    for dr in range(-radius, radius + 1):
-        for dc in range(-radius, radius + 1):
-            if dr == 0 and dc == 0:
-                continue
-            if wrap:
-                sh = np.roll(np.roll(B, -dr, axis=0), -dc, axis=1)
-            else:
-                sh = np.full(B.shape, -np.inf)
-                r0, r1 = max(0, -dr), min(rows, rows - dr)
-                c0, c1 = max(0, -dc), min(cols, cols - dc)
-                sh[r0:r1, c0:c1] = B[r0 + dr:r1 + dr, c0 + dc:c1 + dc]
-            out = np.maximum(out, sh)
-    return out
 
 
 def clear_margin(B, K, T, radius, mask, wrap, eps):

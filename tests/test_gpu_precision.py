@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import pins
-from helpers import rel_l2
+from helpers import peaks_match_on_decidable_prefix, rel_l2
 from oracle import funnel_oracle as O
 from paper_1904_09409_amd import funnel as F
 from paper_1904_09409_amd import synth
@@ -126,36 +126,15 @@ def workload():
     return _cache
 
 
-def decidable_prefix(Bp, lst, nm, mask, eps):
-    """Largest K such that the first K peaks of any plane within eps/2 of Bp
-    (element-wise) are the oracle's first K: the first K+1 listed values are
-    more than eps apart, and every cell at or above the (K+1)-th value (less
-    eps) differs from its largest neighbour by more than eps, so no local
-    maximum near the cut can appear, vanish or swap.  The threshold is 0 here,
-    which |P| always meets."""
-    vals = [Bp.flat[i] for i in lst]
-    for K in range(len(lst) - 1, 0, -1):
-        if any(abs(a - b) <= eps for a, b in zip(vals[:K], vals[1:K + 1])):
-            continue
-        region = (Bp >= vals[K] - eps) & ~mask
-        if np.any(np.abs(Bp - nm)[region] <= eps):
-            continue
-        return K
-    return 0
-
-
-def check_peaks(got_rec, b, planes_ref, mask, delta, K=16):
-    """GPU peak list against the oracle's on its decidable prefix."""
-    from test_gpu_peaks import nb_max
+def check_peaks(got_rec, b, planes_gpu, planes_ref, mask, prec, K=16):
+    """GPU peak list against the oracle's on the decidable prefix
+    (helpers.peaks_match_on_decidable_prefix, with this precision's stated
+    bound checked cell by cell), at least 12 of the 16 peaks per plane."""
     decided = []
-    for s, Pref in enumerate(planes_ref):
-        Bp = np.abs(Pref)
-        lst = O.peaks_list(Bp, K + 1, 0.0, 1, mask, True)
-        k = decidable_prefix(Bp, lst, nb_max(Bp, 1, True), mask, 2.5 * delta[s])
+    for s, (Pg, Pref) in enumerate(zip(planes_gpu, planes_ref)):
         g = got_rec[b][s]
-        got = [int(r) * Bp.shape[1] + int(c) for r, c in zip(g["row"], g["col"])]
-        assert got[:k] == lst[:k], (b, s, k)
-        decided.append(k)
+        ids = [int(r) * Pref.shape[1] + int(c) for r, c in zip(g["row"], g["col"])]
+        decided.append(peaks_match_on_decidable_prefix(O, ids, Pg, Pref, TOL[prec], mask, K, 12))
     say(f"    image {b}: peaks identical to the oracle's on decidable prefixes {decided}")
     return decided
 
@@ -165,7 +144,7 @@ def test_precision_workload_2048(prec):
     """8 x 2048^2, both spaces, forward + adjoint of the peak loss in the
     given precision: rel L2 of planes and gradient against the oracle on two
     sampled images, and the first 16 peaks of every sampled plane identical to
-    the oracle's wherever its ordering margin exceeds the measured error."""
+    the oracle's on the prefix the measured error decides (at least 12)."""
     import torch
     w = workload()
     say(f"  {NAMES[prec]}")
@@ -184,6 +163,4 @@ def test_precision_workload_2048(prec):
         e_d = rel_l2(dI[b].cpu().numpy(), d)
         say(f"    image {b}: rel L2 regular {e_r:.2e} inverse {e_i:.2e} adjoint {e_d:.2e}")
         assert max(e_r, e_i, e_d) <= TOL[prec]
-        delta = [np.abs(np.abs(gr) - np.abs(pr)).max(), np.abs(np.abs(gi) - np.abs(pi)).max()]
-        decided += check_peaks(got, b, (pr, pi), w["mask"], delta)
-    assert min(decided) >= 1 and sum(decided) >= 8, decided
+        decided += check_peaks(got, b, (gr, gi), (pr, pi), w["mask"], prec)

@@ -1,6 +1,7 @@
 """Every tile variant of every launch against the FP64 oracle.  The plan
 starts from default variants and the autotuner may pick any other, so each
-one must compute the same transform: for v = 0 .. 11, every launch that has a
+one must compute the same transform: for every variant v (register tiles,
+LDS-resident tiles, register tiles on a persistent grid), every launch that has a
 variant v is switched to it and the forward planes and the adjoint are
 compared with the oracle.  The shapes include the benchmark's lengths
 (Np = 2048, rows of 1024) and those of the 8 x 2048^2 workload, so every
@@ -48,7 +49,7 @@ def test_every_variant_matches_oracle(N, M):
     dPc = dP.cuda()
     defaults = F.funnel_plan_variants(plan.handle)
     covered = 0
-    for v in range(12):
+    for v in range(F.MAX_VARIANTS):
         roles = []
         for r in range(12):
             try:

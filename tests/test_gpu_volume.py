@@ -47,8 +47,8 @@ def test_every_volume_variant_matches_oracle(B, Nz, Ny, Nx, pad):
     defaults = F.funnel_volume_variants(plan.handle)
     assert defaults[4:] == [-1] * 8          # z space only
     tried = 0
-    for role in (ROW_ROLE, YCOL_ROLE):
-        for v in range(12):
+    for role in (0, ROW_ROLE, YCOL_ROLE, 3):   # depth DFT, x' pass, y' pass, inverse w3 DFT
+        for v in range(F.MAX_VARIANTS):
             try:
                 F.funnel_volume_set_variant(plan.handle, role, v)
             except F.FunnelError:
