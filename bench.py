@@ -225,16 +225,19 @@ def benchmark_variants(F, plan, nvmt: str = "linear") -> str:
 
 def ragged_bench(args, torch, F, synth, count=256):
     """Forward + adjoint of 256 images drawn from 240x320 / 480x640 /
-    720x1280 / 1080x1920 (H x W), both spaces, in three schedules: the ragged
-    plan's concurrent size classes called eagerly, the same calls replayed as
-    one HIP graph, and one uniform plan per size class run back to back."""
+    720x1280 / 1080x1920 (H x W), both spaces.  The ragged plan runs either
+    schedule: its size classes' launches on concurrent streams, or one
+    persistent launch per pass kind over a work queue of every class's tiles;
+    each is timed eagerly and as one replayed HIP graph, beside one uniform
+    plan per size class run back to back.  value = the graph replay of the
+    schedule the autotuner picked."""
     log(f"generating {count} ragged synthetic images")
     ims = synth.batch("ragged", count=count, seed=0)
     shapes = [im.image.shape for im in ims]
     px = sum(int(np.prod(s)) for s in shapes)
     plan = F.RaggedPlan(shapes)
-    if not args.no_autotune:
-        F.funnel_autotune(plan.handle)
+    tuned = [] if args.no_autotune else F.funnel_autotune(plan.handle)
+    picked = plan.schedule
     x = plan.pack([im.image for im in ims])
     planes = plan.forward(x)
     dP = torch.randn_like(planes)
@@ -253,9 +256,26 @@ def ragged_bench(args, torch, F, synth, count=256):
         torch.cuda.synchronize()
         return s.elapsed_time(e) / args.steps
 
-    eager_ms = timeit(lambda: (plan.forward(x, planes), plan.adjoint(dP, dI)))
-    graph = F.FunnelGraph(plan, F.FT_GRAPH_FORWARD | F.FT_GRAPH_ADJOINT, x, planes, dP, dI)
-    graph_ms = timeit(graph.launch)
+    sched = {}
+    kernels = {}
+    names = {F.FT_SCHEDULE_CLASS_STREAMS: "class_streams", F.FT_SCHEDULE_QUEUE: "queue"}
+    for sc in (F.FT_SCHEDULE_CLASS_STREAMS, F.FT_SCHEDULE_QUEUE):
+        plan.set_schedule(sc)
+        sched[names[sc] + "_eager"] = round(timeit(lambda: (plan.forward(x, planes), plan.adjoint(dP, dI))), 4)
+        graph = F.FunnelGraph(plan, F.FT_GRAPH_FORWARD | F.FT_GRAPH_ADJOINT, x, planes, dP, dI)
+        sched[names[sc] + "_graph"] = round(timeit(graph.launch), 4)
+        del graph
+        F.funnel_profile_enable(plan.handle, args.steps * 64)
+        for _ in range(args.steps):
+            plan.forward(x, planes)
+            plan.adjoint(dP, dI)
+        torch.cuda.synchronize()
+        ks = F.funnel_profile_read(plan.handle, cap=64)
+        F.funnel_profile_disable(plan.handle)
+        kernels[names[sc]] = sorted(({"name": k["name"], "avg_ms": round(k["total_ms"] / k["launches"], 4),
+                                      "gbps": round(k["bytes_per_launch"] / (k["total_ms"] / k["launches"]) / 1e6, 1)}
+                                     for k in ks), key=lambda k: -k["avg_ms"])[:12]
+    plan.set_schedule(picked)
     # per-size baseline: one uniform plan per size class, launched one after another
     by = {}
     for i, s in enumerate(shapes):
@@ -275,16 +295,29 @@ def ragged_bench(args, torch, F, synth, count=256):
             p.forward(xi, pi)
             p.adjoint(dpi, dii)
 
-    seq_ms = timeit(seq)
+    sched["sequential_per_size_plans"] = round(timeit(seq), 4)
+    graph_ms = sched[names[picked] + "_graph"]
+    # algorithmic bytes of the step by the 3-pass model (both spaces, forward + adjoint)
+    step_bytes = 0.0
+    for (N, M), idx in by.items():
+        h = (N + M) // 2 - 1
+        for W in (M, N):
+            step_bytes += 2 * len(idx) * (4.0 * N * M + 32.0 * h * W + 4.0 * (N + M) * W)
+    gbps = step_bytes / (graph_ms * 1e6)
     out = {
         "metric": "Mpixel/s funnel fwd+adjoint, ragged 256-image mix (240x320..1080x1920), fp32",
         "value": round(px / (graph_ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(graph_ms, 4),
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": graph_ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{count} ragged images, {px / 1e6:.1f} Mpixel, both spaces, forward + adjoint",
-                   "size_classes": {f"{s[0]}x{s[1]}": len(v) for s, v in by.items()}},
-        "schedules_ms": {"graph": round(graph_ms, 4), "eager_concurrent_classes": round(eager_ms, 4),
-                         "sequential_per_size_plans": round(seq_ms, 4)},
+                   "size_classes": {f"{s[0]}x{s[1]}": len(v) for s, v in by.items()},
+                   "schedule": names[picked]},
+        "roofline": {"bound": "hbm", "kernel": "whole step (3-pass byte model)", "achieved": round(gbps, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                     "step_bytes": step_bytes},
+        "schedules_ms": sched,
+        "kernels": kernels,
+        "autotune_schedule": [t for t in tuned if t["name"] == "schedule"],
     }
     print(json.dumps(out), flush=True)
 

@@ -165,6 +165,29 @@ typedef struct {
  * must not be used from two host threads at once. */
 ft_status funnel_plan_create_ragged(const ft_image_desc* images, int32_t count, int32_t spaces, ft_plan** out);
 
+/* Schedules of a ragged plan's launches.
+ *   FT_SCHEDULE_CLASS_STREAMS (the default): each size class runs its own
+ *     three launches per direction on a stream of the plan's, concurrently
+ *     with the other classes (forked from and joined back to the caller's
+ *     stream), with the tile variants of each class and launch.
+ *   FT_SCHEDULE_QUEUE: one persistent launch per pass kind for the whole
+ *     batch -- forward A, B, C; adjoint C^T, B^T and A^T (inverse space, then
+ *     regular space) -- whose blocks take (class, space, image, tile) items
+ *     from a device-side work queue, longest transforms first, until it is
+ *     empty.  Each length has a fixed tile shape there (16 or 32 elements per
+ *     thread for the column passes, per launch); the queue counters live in
+ *     the workspace.  Available when every class's lengths have queue
+ *     kernels: Np in {560, 1120, 2000, 3000} and row lengths in {240, 320,
+ *     480, 640, 720, 1080, 1280, 1920} (the camera formats 240x320, 480x640,
+ *     720x1280 and 1080x1920), FP32, linear NVMT, at most 16 class x space
+ *     segments; else FT_ERR_UNSUPPORTED_SIZE.
+ * funnel_autotune times both schedules of a ragged plan and keeps the faster.
+ * Both give the same results (bitwise, when the classes' tile variants have
+ * 16 elements per thread and the queue's column launches shape 0). */
+enum { FT_SCHEDULE_CLASS_STREAMS = 0, FT_SCHEDULE_QUEUE = 1 };
+ft_status funnel_plan_set_schedule(ft_plan* plan, int32_t schedule);
+ft_status funnel_plan_schedule(const ft_plan* plan, int32_t* schedule);
+
 /* Release the plan's tables.  NULL is accepted. */
 void funnel_plan_destroy(ft_plan* plan);
 
@@ -358,7 +381,11 @@ ft_status funnel_profile_disable(ft_plan* plan);
  * times (ft_tune_result.ms, ms_default) are those chain times.  Launches ("roles") are numbered
  *   0..5  forward  regular A, B, C, inverse A, B, C
  *   6..11 adjoint  regular Ct, Bt, At, inverse Ct, Bt, At
- * For a ragged plan, class c's launches are roles 12*c .. 12*c+11.
+ * For a ragged plan, class c's launches are roles 12*c .. 12*c+11; a ragged
+ * plan whose lengths have queue kernels then also times its two schedules
+ * (FT_SCHEDULE_*, with each queue column launch's tile shape) and keeps the
+ * faster, reported as a last result named "schedule" (variant = the
+ * schedule, ms_default = the class-streams time).
  * A plan being tuned must not be used concurrently. */
 typedef struct {
   char name[40];       /* role name, e.g. "fwd.regular.C" */

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "lib", "libfunnel.so")
 SOURCES = ["funnel_kernels.hip", "funnel_peaks.hip", "funnel_api.cpp", "funnel_chirp.hip", "funnel_tables.cpp",
-           "funnel_verify.hip", "funnel_refine.hip", "funnel_volume.hip"] + [
+           "funnel_verify.hip", "funnel_refine.hip", "funnel_volume.hip", "funnel_queue.hip"] + [
     f"funnel_len_g{g}.hip" for g in range(6)] + [
     f"funnel_mfma_{p}_{g}.hip" for p in ("bf16", "fp16") for g in ("a", "b")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

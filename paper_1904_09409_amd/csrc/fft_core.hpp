@@ -544,25 +544,29 @@ struct FftR {
   // the register-heavy butterflies before it (where they were spilled).
   __device__ static __forceinline__ void pin(int& line, int& t) { asm volatile("" : "+v"(line), "+v"(t)); }
 
+  // live = false: a thread of the block that holds no part of a transform
+  // (blocks sized for a larger tile); it keeps every barrier but touches no
+  // LDS.
   template <int I, bool PAIRED_OUT, bool PAIRED_IN, bool SPLIT, class Lay, class Buf>
-  __device__ static __forceinline__ void exchange(float2 (&v)[EM], int line, int t, Buf* lds) {
+  __device__ static __forceinline__ void exchange(float2 (&v)[EM], int line, int t, Buf* lds, bool live) {
     if constexpr (!SPLIT) {
       __syncthreads();
       pin(line, t);
-      xwrite<I, PAIRED_OUT, Lay>(line, t, lds, [&](int s) { return v[s]; });
+      if (live) xwrite<I, PAIRED_OUT, Lay>(line, t, lds, [&](int s) { return v[s]; });
       __syncthreads();
-      xread<I + 1, PAIRED_IN, Lay>(line, t, lds, [&](int s, float2 f) { v[s] = f; });
+      if (live) xread<I + 1, PAIRED_IN, Lay>(line, t, lds, [&](int s, float2 f) { v[s] = f; });
     } else {
 #pragma unroll
       for (int part = 0; part < 2; ++part) {
         __syncthreads();
         pin(line, t);
-        xwrite<I, PAIRED_OUT, Lay>(line, t, lds, [&](int s) { return part ? v[s].y : v[s].x; });
+        if (live) xwrite<I, PAIRED_OUT, Lay>(line, t, lds, [&](int s) { return part ? v[s].y : v[s].x; });
         __syncthreads();
-        xread<I + 1, PAIRED_IN, Lay>(line, t, lds, [&](int s, float f) {
-          if (part) v[s].y = f;
-          else v[s].x = f;
-        });
+        if (live)
+          xread<I + 1, PAIRED_IN, Lay>(line, t, lds, [&](int s, float f) {
+            if (part) v[s].y = f;
+            else v[s].x = f;
+          });
       }
     }
   }
@@ -573,15 +577,15 @@ struct FftR {
   // j + q * (L / R_last), for the slots with ok<last>.
   template <bool PAIRED_FIRST, bool PAIRED_LAST, bool SPLIT, class Lay, class Buf, int I = 0>
   __device__ static __forceinline__ void run(float2 (&v)[EM], int line, int t, Buf* lds,
-                                             const float2* __restrict__ tw) {
+                                             const float2* __restrict__ tw, bool live = true) {
     static_assert(!(PAIRED_FIRST && !REV) && !(PAIRED_LAST && REV), "EM counts the paired pass of this order only");
     constexpr bool FIRST = I == 0, LAST = I == kPlan.n - 1;
     constexpr bool PAIRED = (FIRST && PAIRED_FIRST) || (LAST && PAIRED_LAST);
     compute<I, PAIRED>(v, t, tw);
     if constexpr (!LAST) {
       constexpr bool NEXT_PAIRED = (I + 1 == kPlan.n - 1) && PAIRED_LAST;
-      exchange<I, PAIRED, NEXT_PAIRED, SPLIT, Lay>(v, line, t, lds);
-      run<PAIRED_FIRST, PAIRED_LAST, SPLIT, Lay, Buf, I + 1>(v, line, t, lds, tw);
+      exchange<I, PAIRED, NEXT_PAIRED, SPLIT, Lay>(v, line, t, lds, live);
+      run<PAIRED_FIRST, PAIRED_LAST, SPLIT, Lay, Buf, I + 1>(v, line, t, lds, tw, live);
     }
   }
 };

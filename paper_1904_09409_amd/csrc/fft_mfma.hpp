@@ -332,9 +332,11 @@ struct FftM {
     }
   }
 
+  // (FftR's calling convention; the split-precision kernels always run with
+  // every thread of the block in a transform, so `live` is always true here)
   template <bool PAIRED_FIRST, bool PAIRED_LAST, bool SPLIT, class Lay, class Buf>
   __device__ static __forceinline__ void run(float2 (&v)[E], int line, int t, Buf* lds,
-                                             const float2* __restrict__ tw) {
+                                             const float2* __restrict__ tw, bool /*live*/ = true) {
     constexpr int R0 = kPlan.r[0], NB0 = L / R0;
     constexpr int LAST = kPlan.n - 1, RL = kPlan.r[LAST], NBL = L / RL;
     Coef A;

@@ -27,6 +27,7 @@
 
 #include "../../include/funnel.h"
 #include "funnel_internal.hpp"
+#include "funnel_queue.hpp"
 
 // Event pairs around each launch, filled while profiling is enabled.
 struct FtProfiler {
@@ -41,6 +42,14 @@ enum Role { FA_REG, FB_REG, FC_REG, FA_INV, FB_INV, FC_INV, AC_REG, AB_REG, AA_R
 static const char* const kRoleName[NROLES] = {
     "fwd.regular.A", "fwd.regular.B", "fwd.regular.C", "fwd.inverse.A", "fwd.inverse.B", "fwd.inverse.C",
     "adj.regular.Ct", "adj.regular.Bt", "adj.regular.At", "adj.inverse.Ct", "adj.inverse.Bt", "adj.inverse.At"};
+
+// The launches of the queue schedule: forward A, B, C; adjoint C^T, B^T, and
+// A^T in two launches (the inverse space writes dI, the regular space then
+// adds to it).  Each has its own counter in the workspace.
+enum QLaunch { QF_A, QF_B, QF_C, QA_CT, QA_BT, QA_AT_INV, QA_AT_REG, kQueueLaunches };
+static const char* const kQueueName[kQueueLaunches] = {"queue.fwd.A", "queue.fwd.B", "queue.fwd.C",
+                                                       "queue.adj.Ct", "queue.adj.Bt", "queue.adj.At.inverse",
+                                                       "queue.adj.At.regular"};
 
 struct FtClass {
   int N = 0, M = 0, Np = 0, h = 0, count = 0;
@@ -67,6 +76,15 @@ struct ft_plan {
   int prec = 0;             // FT_PREC_*
   bool chirpz = false;      // FT_PLAN_NVMT_CHIRPZ: band-limited NVMT in the row passes
   bool ragged = false;
+  // ragged plans: FT_SCHEDULE_CLASS_STREAMS (each size class's launches on a
+  // stream of its own) or FT_SCHEDULE_QUEUE (one persistent launch per pass
+  // kind over all classes, funnel_queue.hip), the latter only where every
+  // class's lengths have queue kernels (queue_ok)
+  int schedule = FT_SCHEDULE_CLASS_STREAMS;
+  bool queue_ok = false;
+  int qshape[kQueueLaunches] = {};  // tile shape of each queue launch (column passes: 0 or 1)
+  int qgrid[3][2] = {};             // persistent grid of each queue kernel (pass, shape)
+  size_t ws_queue = 0;              // byte offset of the queue counters in the workspace
   std::vector<FtClass> cls;
   float2* tw = nullptr;
   float2* chirp = nullptr;  // chirp-z plans: per-row chirp spectra and chirps
@@ -302,10 +320,112 @@ std::string role_label(const ft_plan* p, int ci, int r) {
 static const int kForwardOrder[] = {FA_REG, FB_REG, FC_REG, FA_INV, FB_INV, FC_INV};
 static const int kAdjointOrder[] = {AC_INV, AB_INV, AA_INV, AC_REG, AB_REG, AA_REG};
 
+// The queue schedule of a ragged plan: the forward as three persistent
+// launches (A, B, C), the adjoint as four (C^T, B^T, inverse A^T, regular
+// A^T), each over the items of every class and space, longest transforms
+// first.  A fill kernel zeroes the direction's counters first (in the
+// workspace, so concurrent calls with separate workspaces do not share them).
+hipError_t enqueue_queue(const ft_plan* p, bool fwd, const float* src, float* dst, char* w, hipStream_t s) {
+  using funnel::ImgMap;
+  using funnel::QueueArgs;
+  using funnel::QueueSeg;
+  int* counters = reinterpret_cast<int*>(w + p->ws_queue);
+  std::vector<int> order(p->cls.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return p->cls[a].Np > p->cls[b].Np; });
+  const bool reg = p->spaces & FT_SPACE_REGULAR, inv = p->spaces & FT_SPACE_INVERSE;
+
+  // segment of class c in one space for queue launch ql
+  auto segment = [&](int ql, const FtClass& c, bool regular, int first, QueueSeg& g) {
+    const int Np = c.Np, h = c.h, M = c.M, N = c.N;
+    const int W = regular ? M : N;                       // lines of the spectrum
+    float2* S = reinterpret_cast<float2*>(w + (regular ? c.ws_reg : c.ws_inv));
+    const long long ss = (long long)h * W;
+    const size_t plane_off = regular ? 0 : c.off_inv_plane;
+    std::memset(&g, 0, sizeof g);
+    g.first = first;
+    g.tw = p->tw + c.tw_np;
+    g.kind = funnel::queue_col_kind(Np);
+    const int shape = p->qshape[ql];
+    switch (ql) {
+      case QF_A:   // image lines -> S (the inverse space reads image rows)
+        g.trans = regular ? 0 : 1;
+        g.nlines = W; g.a = regular ? N : M; g.b = (Np - (regular ? N : M)) / 2; g.scale = 1.0f;
+        g.map = ImgMap{c.img_stride, ss, c.d_img_off, nullptr};
+        g.in = src; g.out = S;
+        g.tiles = funnel::queue_col_tiles(Np, shape, W);
+        break;
+      case QF_B: case QA_BT:   // rows of S in place
+        g.kind = funnel::queue_row_kind(W);
+        g.accum = ql == QA_BT;
+        g.a = Np; g.b = h; g.stride = ss;
+        g.out = S;
+        g.tw = p->tw + (regular ? c.tw_m : c.tw_n);
+        g.tiles = (h + funnel::queue_row_rows(W) - 1) / funnel::queue_row_rows(W);
+        break;
+      case QF_C:   // S -> plane columns, 1/Np
+        g.nlines = W; g.a = 0; g.b = Np; g.scale = 1.0f / Np;
+        g.map = ImgMap{ss, c.plane_stride, nullptr, c.d_plane_off};
+        g.in = S; g.out = dst + plane_off;
+        g.tiles = funnel::queue_col_tiles(Np, shape, W);
+        break;
+      case QA_CT:   // plane columns -> S, 2/Np
+        g.nlines = W; g.a = Np; g.b = 0; g.scale = 2.0f / Np;
+        g.map = ImgMap{c.plane_stride, ss, c.d_plane_off, nullptr};
+        g.in = src + plane_off; g.out = S;
+        g.tiles = funnel::queue_col_tiles(Np, shape, W);
+        break;
+      case QA_AT_INV: case QA_AT_REG:   // S -> image gradient (inverse: rows, written; regular: columns, added)
+        g.trans = regular ? 0 : 1;
+        g.accum = regular && inv;
+        g.nlines = W; g.a = (Np - (regular ? N : M)) / 2; g.b = regular ? N : M; g.scale = 0.5f;
+        g.map = ImgMap{ss, c.img_stride, nullptr, c.d_img_off};
+        g.in = S; g.out = dst;
+        g.tiles = funnel::queue_col_tiles(Np, shape, W);
+        break;
+    }
+    return g.tiles * c.count;
+  };
+
+  const int first_ql = fwd ? QF_A : QA_CT, last_ql = fwd ? QF_C : QA_AT_REG;
+  hipError_t e = funnel::launch_queue_reset(counters + first_ql, last_ql - first_ql + 1, s);
+  for (int ql = first_ql; ql <= last_ql && e == hipSuccess; ++ql) {
+    QueueArgs q;
+    std::memset(&q, 0, sizeof q);
+    q.counter = counters + ql;
+    double bytes = 0.0;
+    for (int ci : order) {
+      const FtClass& c = p->cls[ci];
+      for (int sp = 0; sp < 2; ++sp) {
+        const bool regular = sp == 0;
+        if (!(regular ? reg : inv)) continue;
+        if (ql == QA_AT_INV && regular) continue;
+        if (ql == QA_AT_REG && !regular) continue;
+        q.total += segment(ql, c, regular, q.total, q.seg[q.nseg]);
+        ++q.nseg;
+      }
+      static const int kRole[kQueueLaunches][2] = {{FA_REG, FA_INV}, {FB_REG, FB_INV}, {FC_REG, FC_INV},
+                                                   {AC_REG, AC_INV}, {AB_REG, AB_INV}, {-1, AA_INV}, {AA_REG, -1}};
+      for (int sp = 0; sp < 2; ++sp)
+        if (kRole[ql][sp] >= 0 && role_active(p, kRole[ql][sp])) bytes += role_bytes(p, c, kRole[ql][sp]);
+    }
+    if (q.nseg == 0) continue;
+    const funnel::QueuePass pass = (ql == QF_B || ql == QA_BT) ? funnel::QueuePass::ROW
+                                   : (ql == QF_A || ql == QA_CT) ? funnel::QueuePass::R2C
+                                                                 : funnel::QueuePass::C2R;
+    const int shape = pass == funnel::QueuePass::ROW ? 0 : p->qshape[ql];
+    const int grid = p->qgrid[(int)pass][shape];
+    e = timed(p, s, kQueueName[ql], bytes, [&] { return funnel::launch_queue(pass, shape, grid, q, s); });
+  }
+  return e;
+}
+
 // Enqueue the roles of `order` for every class: on the caller's stream for a
-// single class, else on the class streams between a fork and a join.
+// single class, else on the class streams between a fork and a join (or, for
+// the queue schedule, as its persistent launches).
 hipError_t enqueue_roles(const ft_plan* p, const int* order, const float* src, float* dst, char* w,
                          hipStream_t s) {
+  if (p->schedule == FT_SCHEDULE_QUEUE) return enqueue_queue(p, order == kForwardOrder, src, dst, w, s);
   const bool fork = p->cls.size() > 1;
   hipError_t e = hipSuccess;
   if (fork) e = hipEventRecord(p->fork, s);
@@ -393,6 +513,11 @@ ft_status finish_plan(ft_plan* p, const std::vector<std::vector<std::pair<long l
         }
     }
   }
+  if (!offsets.empty()) {
+    // the queue schedule's counters, one 4-byte word per launch
+    p->ws_queue = align_up(ws, 256);
+    ws = p->ws_queue + 256;
+  }
   p->ws_bytes = ws;
 
   int dev = -1, ndev = 0;
@@ -402,6 +527,24 @@ ft_status finish_plan(ft_plan* p, const std::vector<std::vector<std::pair<long l
   char* scr = nullptr;   // the no-allocation peak call's scratch, resolved here once per device
   ft_status sst = scratch_for_device(dev, &scr);
   if (sst != FT_OK) return sst;
+
+  if (!offsets.empty() && !p->chirpz && p->prec == FT_PREC_FP32) {
+    // the queue schedule: every class's column length and row lengths need a queue kernel
+    const int ns = (p->spaces == FT_SPACE_BOTH) ? 2 : 1;
+    bool okq = (int)p->cls.size() * ns <= funnel::kQueueSegs;
+    for (const auto& c : p->cls) {
+      okq = okq && funnel::queue_col_kind(c.Np) >= 0;
+      if (p->spaces & FT_SPACE_REGULAR) okq = okq && funnel::queue_row_kind(c.M) >= 0;
+      if (p->spaces & FT_SPACE_INVERSE) okq = okq && funnel::queue_row_kind(c.N) >= 0;
+    }
+    if (okq) {
+      const funnel::QueuePass kinds[3] = {funnel::QueuePass::R2C, funnel::QueuePass::C2R, funnel::QueuePass::ROW};
+      for (int k = 0; k < 3 && okq; ++k)
+        for (int sh = 0; sh < 2 && okq; ++sh)
+          okq = funnel::queue_grid_size(kinds[k], sh, &p->qgrid[k][sh]) == hipSuccess && p->qgrid[k][sh] > 0;
+    }
+    p->queue_ok = okq;
+  }
 
   std::vector<float2> host(ntw);
   for (auto& c : p->cls) {
@@ -833,6 +976,59 @@ ft_status funnel_autotune(ft_plan* p, void* stream, ft_tune_result* out, int32_t
       ++count;
     }
   }
+  if (p->ragged && p->queue_ok) {
+    // the schedule: the classes' tuned launches on their streams, or the
+    // queue's persistent launches (each column launch's tile shape tried)
+    auto chain_ms = [&](float* best_ms) -> hipError_t {
+      float m = 1e30f;
+      hipError_t e = hipSuccess;
+      float* img = static_cast<float*>(a);
+      float* pln = static_cast<float*>(b);
+      for (int rep = 0; rep < 8 && e == hipSuccess; ++rep) {
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = enqueue_roles(p, kForwardOrder, img, pln, static_cast<char*>(w), s);
+        if (e == hipSuccess) e = enqueue_roles(p, kAdjointOrder, pln, img, static_cast<char*>(w), s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && rep > 0 && ms < m) m = ms;
+      }
+      *best_ms = m;
+      return e;
+    };
+    float t_streams = 0.f, t_queue = 0.f, t = 0.f;
+    p->schedule = FT_SCHEDULE_CLASS_STREAMS;
+    hipError_t e = chain_ms(&t_streams);
+    p->schedule = FT_SCHEDULE_QUEUE;
+    for (int ql = 0; ql < kQueueLaunches; ++ql) p->qshape[ql] = 0;
+    if (e == hipSuccess) e = chain_ms(&t_queue);
+    int tried = 2;
+    for (int ql : {QF_A, QF_C, QA_CT, QA_AT_INV, QA_AT_REG}) {
+      if (e != hipSuccess) break;
+      p->qshape[ql] = 1;
+      e = chain_ms(&t);
+      ++tried;
+      if (e == hipSuccess && t < t_queue) t_queue = t;
+      else p->qshape[ql] = 0;
+    }
+    if (e != hipSuccess) {
+      p->schedule = FT_SCHEDULE_CLASS_STREAMS;
+      p->prof = saved;
+      cleanup();
+      return hip_fail(e, "autotune launch");
+    }
+    p->schedule = t_queue < t_streams ? FT_SCHEDULE_QUEUE : FT_SCHEDULE_CLASS_STREAMS;
+    if (count < cap) {
+      std::memset(&out[count], 0, sizeof(ft_tune_result));
+      std::snprintf(out[count].name, sizeof(out[count].name), "schedule");
+      out[count].variant = p->schedule;
+      out[count].n_tried = tried;
+      out[count].ms = p->schedule == FT_SCHEDULE_QUEUE ? t_queue : t_streams;
+      out[count].ms_default = t_streams;
+    }
+    ++count;
+  }
   p->prof = saved;
   cleanup();
   if (n) *n = count < cap ? count : cap;
@@ -855,6 +1051,24 @@ ft_status funnel_plan_set_variant(ft_plan* p, int32_t role, int32_t variant) {
   if (variant < 0 || variant >= funnel::kMaxVariants || !(role_mask(p, p->cls[ci], r) & (1u << variant)))
     return fail(FT_ERR_INVALID_ARG, "variant %d has no kernel for role %s", variant, kRoleName[r]);
   p->cls[ci].variant[r] = variant;
+  return ok();
+}
+
+ft_status funnel_plan_set_schedule(ft_plan* p, int32_t schedule) {
+  if (!p) return fail(FT_ERR_INVALID_ARG, "plan is NULL");
+  if (schedule != FT_SCHEDULE_CLASS_STREAMS && schedule != FT_SCHEDULE_QUEUE)
+    return fail(FT_ERR_INVALID_ARG, "unknown schedule %d", schedule);
+  if (schedule == FT_SCHEDULE_QUEUE && !p->ragged)
+    return fail(FT_ERR_INVALID_ARG, "the queue schedule is for ragged plans");
+  if (schedule == FT_SCHEDULE_QUEUE && !p->queue_ok)
+    return fail(FT_ERR_UNSUPPORTED_SIZE, "a length of this plan has no queue kernel");
+  p->schedule = schedule;
+  return ok();
+}
+
+ft_status funnel_plan_schedule(const ft_plan* p, int32_t* schedule) {
+  if (!p || !schedule) return fail(FT_ERR_INVALID_ARG, "plan and schedule must be non-NULL");
+  *schedule = p->schedule;
   return ok();
 }
 

@@ -344,11 +344,9 @@ struct FastCfg {
                                 (NT == 1 || em() * NT <= 2 * E_);
 };
 
-// column-pass variants: (elements per thread, column pairs per group, groups
-// per block, waves per SIMD the registers must leave room for; 1 = no floor)
-#define FUNNEL_COL_VARIANTS(X)                                                                         \
-  X(0, 16, 4, 1, 1) X(1, 16, 8, 1, 1) X(2, 16, 16, 1, 1) X(3, 32, 4, 1, 1) X(4, 32, 8, 1, 1) X(5, 32, 16, 1, 1) \
-  X(6, 16, 8, 2, 1) X(7, 16, 4, 2, 1)
+// column-pass variants: (elements per thread, column pairs per group, groups per block)
+#define FUNNEL_COL_VARIANTS(X) \
+  X(0, 16, 4, 1) X(1, 16, 8, 1) X(2, 16, 16, 1) X(3, 32, 4, 1) X(4, 32, 8, 1) X(5, 32, 16, 1) X(6, 16, 8, 2) X(7, 16, 4, 2)
 constexpr int kColVariants = 8;   // register tiles 0-7; 8-10 are the LDS-resident tiles
 
 // Raw buffer access: 32-bit byte offsets from a per-block base, and hardware
@@ -405,13 +403,17 @@ __device__ __forceinline__ void emit_pair(GBuf dst, int k, float2 zk, float2 zm,
 __device__ __forceinline__ float2 herm_direct(float4 x) { return make_float2(x.x - x.w, x.y + x.z); }  // A + iB
 __device__ __forceinline__ float2 herm_mirror(float4 x) { return make_float2(x.x + x.w, x.z - x.y); }  // conj A + i conj B
 
-// Both column kernels run one column tile of one image per block on a 1D grid
-// of `total` = tiles x images blocks; consecutive tiles map to one XCD
-// (xcd_remap).
-template <int L, int E_, int LINES_, int NT, bool TRANS, int PREC, int WPE = 1>
-__global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS)) __attribute__((amdgpu_waves_per_eu(WPE)))
-    k_r2c_fast(const float* __restrict__ in, float2* __restrict__ out, int nlines, int lin, int off,
-               ImgMap map, float scale, const float2* __restrict__ tw, int tiles, int total) {
+// The column passes as tile functions: column tile `tile` (NT groups of
+// LINES column pairs) of image `img`, computed by threads tid = 0 ..
+// Cfg::THREADS-1 of a block with the LDS buffer `lds` of
+// LayInterR<LINES>::size(L) floats.  Threads of a larger block past THREADS
+// pass live = false: they keep every barrier and touch no memory.  The
+// kernels below run one tile per block; the work-queue kernels of ragged
+// batches (funnel_queue.hip) run many tiles of several lengths per block.
+template <int L, int E_, int LINES_, int NT, bool TRANS, int PREC>
+__device__ __forceinline__ void r2c_tile(const float* __restrict__ in, float2* __restrict__ out, int nlines, int lin,
+                                         int off, ImgMap map, float scale, const float2* __restrict__ tw, int tile,
+                                         int img, int tid, bool live, float* lds) {
   using Cfg = FastCfg<L, E_, LINES_, NT>;
   constexpr int P = Cfg::P, LINES = Cfg::LINES, H = L / 2 - 1;
   using Eng = typename EngSel<PREC, L, P, false, false, LINES, true>::type;
@@ -421,12 +423,9 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS)) __attri
   constexpr int R0 = PL.r[0], NB0 = L / R0, BPT0 = Eng::template bpt<0, false>();
   constexpr int RL = PL.r[LAST], NBL = L / RL, BPTL = Eng::template bpt<LAST, true>();
   using Lay = LayInterR<LINES>;
-  __shared__ float lds[Lay::size(L)];
 
   const int npairs = nlines >> 1;
-  const int tid = threadIdx.x, pair = tid % LINES, t = tid / LINES;
-  const int logical = xcd_remap(blockIdx.x, total);
-  const int tile = logical % tiles, img = logical / tiles;
+  const int pair = live ? tid % LINES : 0, t = live ? tid / LINES : 0;
   // one image's lin x nlines block (rows of the padded frame off .. off+lin-1)
   const GBuf src(in + map.in(img), (long long)lin * nlines * 4);
 
@@ -466,9 +465,9 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS)) __attri
   const GBuf dst(out + map.out(img), (long long)H * npairs * 16);
 #pragma unroll
   for (int g = 0; g < NT; ++g) {
-    Eng::template run<false, true, true, Lay>(v[g], pair, t, lds, tw);
+    Eng::template run<false, true, true, Lay>(v[g], pair, t, lds, tw, live);
     const int pg = (tile * NT + g) * LINES + pair;
-    if (pg >= npairs) continue;
+    if (!live || pg >= npairs) continue;
 #pragma unroll
     for (int c = 0; c < BPTL / 2; ++c) {
       if (!Eng::template ok<LAST, true>(t, 2 * c)) continue;
@@ -490,10 +489,22 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS)) __attri
   }
 }
 
-template <int L, int E_, int LINES_, int NT, bool TRANS, bool ACCUM, int PREC, int WPE = 1>
-__global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS)) __attribute__((amdgpu_waves_per_eu(WPE)))
-    k_c2r_fast(const float2* __restrict__ in, float* __restrict__ out, int nlines, int r0, int nout,
+// One column tile per block on a 1D grid of `total` = tiles x images blocks;
+// consecutive tiles map to one XCD (xcd_remap).
+template <int L, int E_, int LINES_, int NT, bool TRANS, int PREC>
+__global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS))
+    k_r2c_fast(const float* __restrict__ in, float2* __restrict__ out, int nlines, int lin, int off,
                ImgMap map, float scale, const float2* __restrict__ tw, int tiles, int total) {
+  __shared__ float lds[LayInterR<FastCfg<L, E_, LINES_, NT>::LINES>::size(L)];
+  const int logical = xcd_remap(blockIdx.x, total);
+  r2c_tile<L, E_, LINES_, NT, TRANS, PREC>(in, out, nlines, lin, off, map, scale, tw, logical % tiles,
+                                           logical / tiles, threadIdx.x, true, lds);
+}
+
+template <int L, int E_, int LINES_, int NT, bool TRANS, bool ACCUM, int PREC>
+__device__ __forceinline__ void c2r_tile(const float2* __restrict__ in, float* __restrict__ out, int nlines, int r0,
+                                         int nout, ImgMap map, float scale, const float2* __restrict__ tw, int tile,
+                                         int img, int tid, bool live, float* lds) {
   using Cfg = FastCfg<L, E_, LINES_, NT>;
   constexpr int P = Cfg::P, LINES = Cfg::LINES;
   using Eng = typename EngSel<PREC, L, P, true, true, LINES, true>::type;
@@ -503,12 +514,9 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS)) __attri
   constexpr int R0 = PL.r[0], NB0 = L / R0, BPT0 = Eng::template bpt<0, true>();
   constexpr int RL = PL.r[LAST], NBL = L / RL, BPTL = Eng::template bpt<LAST, false>();
   using Lay = LayInterR<LINES>;
-  __shared__ float lds[Lay::size(L)];
 
   const int npairs = nlines >> 1;
-  const int tid = threadIdx.x, pair = tid % LINES, t = tid / LINES;
-  const int logical = xcd_remap(blockIdx.x, total);
-  const int tile = logical % tiles, img = logical / tiles;
+  const int pair = live ? tid % LINES : 0, t = live ? tid / LINES : 0;
   // half-spectrum rows 1 .. L/2-1; row 0 (and anything outside) reads 0
   const GBuf src(in + map.in(img), (long long)(L / 2 - 1) * npairs * 16);
 
@@ -569,9 +577,9 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS)) __attri
   const int step = TRANS ? 4 : nlines * 4;
 #pragma unroll
   for (int g = 0; g < NT; ++g) {
-    Eng::template run<true, false, true, Lay>(v[g], pair, t, lds, tw);
+    Eng::template run<true, false, true, Lay>(v[g], pair, t, lds, tw, live);
     const int pg = (tile * NT + g) * LINES + pair;
-    if (pg >= npairs) continue;
+    if (!live || pg >= npairs) continue;
     // output row r = t + P b + q NBL - r0: offsets at o0 + (P b + q NBL) * step
     const int o0 = TRANS ? (2 * pg * nout + t - r0) * 4 : ((t - r0) * nlines + 2 * pg) * 4;
     float2 old[E];
@@ -612,6 +620,16 @@ __global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS)) __attri
   }
 }
 
+template <int L, int E_, int LINES_, int NT, bool TRANS, bool ACCUM, int PREC>
+__global__ void __launch_bounds__((FastCfg<L, E_, LINES_, NT>::THREADS))
+    k_c2r_fast(const float2* __restrict__ in, float* __restrict__ out, int nlines, int r0, int nout,
+               ImgMap map, float scale, const float2* __restrict__ tw, int tiles, int total) {
+  __shared__ float lds[LayInterR<FastCfg<L, E_, LINES_, NT>::LINES>::size(L)];
+  const int logical = xcd_remap(blockIdx.x, total);
+  c2r_tile<L, E_, LINES_, NT, TRANS, ACCUM, PREC>(in, out, nlines, r0, nout, map, scale, tw, logical % tiles,
+                                                  logical / tiles, threadIdx.x, true, lds);
+}
+
 // ------------------------------------------------------------------ register-resident row pass
 //
 // Power-of-two row lengths >= 64: 16 elements per thread, ROWS rows per block.
@@ -634,10 +652,14 @@ struct RowFastCfg {
 #define FUNNEL_ROW_VARIANTS(X) X(0, 16, 256) X(1, 16, 128) X(2, 16, 512) X(3, 32, 256)
 constexpr int kRowVariants = 4;
 
+// Rows blk * ROWS .. blk * ROWS + ROWS-1 of image img, by threads tid = 0 ..
+// THREADS-1 with the LDS buffer `lds` of LayRow<ROWS, M>::size(M) float2
+// (threads past THREADS of a larger block pass live = false, as for the
+// column tiles).
 template <int M, int E_, int TPB, bool ADJ, int PREC>
-__global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
-    k_row_fast(float2* __restrict__ data, int Lp, int h, int rpf, long long img_stride,
-               const float2* __restrict__ tw) {
+__device__ __forceinline__ void row_tile(float2* __restrict__ data, int Lp, int h, int rpf, long long img_stride,
+                                         const float2* __restrict__ tw, int blk, int img, int tid, bool live,
+                                         float2* lds) {
   using Cfg = RowFastCfg<M, E_, TPB>;
   constexpr int P = Cfg::P, ROWS = Cfg::ROWS;
   using Eng = typename EngSel<PREC, M, P, ADJ, false, ROWS, false>::type;
@@ -649,14 +671,12 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
   constexpr int ES = cdiv(M / 2, P);   // float4 (two elements) per thread when staging the row
   constexpr int EG = cdiv(M, P);       // elements per thread in the transposed gather
   using Lay = LayRow<ROWS, M>;
-  __shared__ float2 lds[Lay::size(M)];
 
-  const int tid = threadIdx.x;
-  const int row = tid / P, t = tid % P;
-  const int gr = blockIdx.x * ROWS + row;   // data row; frequency row n2 = gr / rpf + 1
+  const int row = live ? tid / P : 0, t = live ? tid % P : 0;
+  const int gr = blk * ROWS + row;   // data row; frequency row n2 = gr / rpf + 1
   const int n2 = gr / rpf + 1;
-  const bool active = gr < h * rpf;
-  float2* rowp = data + (long long)blockIdx.y * img_stride + (long long)gr * M;
+  const bool active = live && gr < h * rpf;
+  float2* rowp = data + (long long)img * img_stride + (long long)gr * M;
 
   {  // stage this thread's share of its row: ES float4 loads, all in flight
     float4 st[ES];
@@ -666,7 +686,7 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
       st[i] = active && ((M / 2) % P == 0 || t + P * i < M / 2) ? src4[t + P * i] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int i = 0; i < ES; ++i) {
-      if ((M / 2) % P != 0 && t + P * i >= M / 2) continue;
+      if (!live || ((M / 2) % P != 0 && t + P * i >= M / 2)) continue;
       const int e0 = 2 * (t + P * i);
       float4 x = st[i];
       if (ADJ) { x.z = -x.z; x.w = -x.w; }   // (-1)^p on the odd element
@@ -698,7 +718,7 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
         const float sg = (q & 1) ? -1.f : 1.f;
         v[b * R0 + r] = make_float2(sg * ((1.f - tt) * f0.x + tt * f1.x), sg * ((1.f - tt) * f0.y + tt * f1.y));
       }
-    Eng::template run<false, false, false, Lay>(v, row, t, lds, tw);
+    Eng::template run<false, false, false, Lay>(v, row, t, lds, tw, live);
     if (!active) return;
 #pragma unroll
     for (int b = 0; b < BPTL; ++b)
@@ -716,13 +736,13 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
 #pragma unroll
       for (int r = 0; r < R0; ++r)
         if (Eng::template ok<0, false>(t, b)) v[b * R0 + r] = lds[Lay::addr(row, t + P * b + r * NB0)];
-    Eng::template run<false, false, false, Lay>(v, row, t, lds, tw);
+    Eng::template run<false, false, false, Lay>(v, row, t, lds, tw, live);
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < BPTL; ++b)
 #pragma unroll
       for (int q = 0; q < RL; ++q) {
-        if (!Eng::template ok<LAST, false>(t, b)) continue;
+        if (!live || !Eng::template ok<LAST, false>(t, b)) continue;
         const int x = t + P * b + q * NBL;
         float2 g = v[b * RL + q];
         if ((x + M / 2) & 1) g = make_float2(-g.x, -g.y);
@@ -757,6 +777,15 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
   }
 }
 
+template <int M, int E_, int TPB, bool ADJ, int PREC>
+__global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
+    k_row_fast(float2* __restrict__ data, int Lp, int h, int rpf, long long img_stride,
+               const float2* __restrict__ tw) {
+  using Cfg = RowFastCfg<M, E_, TPB>;
+  __shared__ float2 lds[LayRow<Cfg::ROWS, M>::size(M)];
+  row_tile<M, E_, TPB, ADJ, PREC>(data, Lp, h, rpf, img_stride, tw, blockIdx.x, blockIdx.y, threadIdx.x, true, lds);
+}
+
 // ------------------------------------------------------------------ launchers
 //
 // PREC = kPrecFP32 runs FftR; the split-precision values run FftM and exist
@@ -765,7 +794,7 @@ __global__ void __launch_bounds__((RowFastCfg<M, E_, TPB>::THREADS))
 template <int L, int PREC>
 unsigned col_variant_mask_t() {
   unsigned m = 0;
-#define FUNNEL_V(i, e, l, nt, wpe)                                                                        \
+#define FUNNEL_V(i, e, l, nt)                                                                             \
   if constexpr (FastCfg<L, e, l, nt>::valid && (PREC == kPrecFP32 || (nt == 1 && mfma_fits(L, e, FastCfg<L, e, l, nt>::THREADS)))) \
     m |= 1u << i;
   FUNNEL_COL_VARIANTS(FUNNEL_V)
@@ -796,16 +825,16 @@ template <int L, int PREC>
 hipError_t launch_r2c_t(int variant, bool trans, const float* in, float2* out, int nlines, int lin, int off,
                         ImgMap map, float scale, const float2* tw, int batch, hipStream_t s) {
   switch (variant) {
-#define FUNNEL_V(i, e, l, nt, wpe)                                                                           \
+#define FUNNEL_V(i, e, l, nt)                                                                                \
   case i:                                                                                                    \
     if constexpr (FastCfg<L, e, l, nt>::valid &&                                                             \
                   (PREC == kPrecFP32 || (nt == 1 && mfma_fits(L, e, FastCfg<L, e, l, nt>::THREADS)))) {                    \
       using F = FastCfg<L, e, l, nt>;                                                                        \
       const int tiles = (nlines / 2 + F::LINES * nt - 1) / (F::LINES * nt), total = tiles * batch;           \
       if (trans)                                                                                             \
-        k_r2c_fast<L, e, l, nt, true, PREC, wpe><<<total, F::THREADS, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, tiles, total); \
+        k_r2c_fast<L, e, l, nt, true, PREC><<<total, F::THREADS, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, tiles, total); \
       else                                                                                                   \
-        k_r2c_fast<L, e, l, nt, false, PREC, wpe><<<total, F::THREADS, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, tiles, total); \
+        k_r2c_fast<L, e, l, nt, false, PREC><<<total, F::THREADS, 0, s>>>(in, out, nlines, lin, off, map, scale, tw, tiles, total); \
       return hipGetLastError();                                                                              \
     }                                                                                                        \
     break;
@@ -842,7 +871,7 @@ template <int L, int PREC>
 hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, float* out, int nlines, int r0,
                         int nout, ImgMap map, float scale, const float2* tw, int batch, hipStream_t s) {
   switch (variant) {
-#define FUNNEL_V(i, e, l, nt, wpe)                                                                           \
+#define FUNNEL_V(i, e, l, nt)                                                                                \
   case i:                                                                                                    \
     if constexpr (FastCfg<L, e, l, nt>::valid &&                                                             \
                   (PREC == kPrecFP32 || (nt == 1 && mfma_fits(L, e, FastCfg<L, e, l, nt>::THREADS)))) {                    \
@@ -852,11 +881,11 @@ hipError_t launch_c2r_t(int variant, bool trans, bool accum, const float2* in, f
         k<<<total, F::THREADS, 0, s>>>(in, out, nlines, r0, nout, map, scale, tw, tiles, total);              \
       };                                                                                                     \
       if (trans) {                                                                                           \
-        if (accum) go(k_c2r_fast<L, e, l, nt, true, true, PREC, wpe>);                                      \
-        else go(k_c2r_fast<L, e, l, nt, true, false, PREC, wpe>);                                           \
+        if (accum) go(k_c2r_fast<L, e, l, nt, true, true, PREC>);                                      \
+        else go(k_c2r_fast<L, e, l, nt, true, false, PREC>);                                           \
       } else {                                                                                               \
-        if (accum) go(k_c2r_fast<L, e, l, nt, false, true, PREC, wpe>);                                     \
-        else go(k_c2r_fast<L, e, l, nt, false, false, PREC, wpe>);                                          \
+        if (accum) go(k_c2r_fast<L, e, l, nt, false, true, PREC>);                                     \
+        else go(k_c2r_fast<L, e, l, nt, false, false, PREC>);                                          \
       }                                                                                                      \
       return hipGetLastError();                                                                              \
     }                                                                                                        \

@@ -43,6 +43,8 @@ FT_PEAK_CLAMP_BORDER = 1
 FT_PEAK_KEEP_PAD_BOUNDARY = 2
 FT_GRAPH_FORWARD = 1
 FT_GRAPH_ADJOINT = 2
+FT_SCHEDULE_CLASS_STREAMS = 0
+FT_SCHEDULE_QUEUE = 1
 # tile variants per launch (funnel_plan_set_variant): 0-7 register tiles,
 # 8-10 LDS-resident tiles (column passes); 0-3 register and 4-5 LDS-resident
 # tiles (row passes)
@@ -115,6 +117,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "funnel_plan_create_ragged": ([ctypes.POINTER(ft_image_desc), i32, i32, ctypes.POINTER(vp)], ctypes.c_int),
         "funnel_buffer_elems": ([vp, ctypes.POINTER(sz), ctypes.POINTER(sz)], ctypes.c_int),
         "funnel_plan_classes": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
+        "funnel_plan_set_schedule": ([vp, i32], ctypes.c_int),
+        "funnel_plan_schedule": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
         "funnel_graph_create": ([vp, u32, vp, vp, vp, vp, vp, sz, ctypes.POINTER(vp)], ctypes.c_int),
         "funnel_graph_launch": ([vp, vp], ctypes.c_int),
         "funnel_graph_destroy": ([vp], None),
@@ -245,6 +249,16 @@ def funnel_plan_classes(plan: int) -> int:
     return v.value
 
 
+def funnel_plan_set_schedule(plan: int, schedule: int) -> None:
+    _check(load_library().funnel_plan_set_schedule(plan, int(schedule)), "funnel_plan_set_schedule")
+
+
+def funnel_plan_schedule(plan: int) -> int:
+    v = ctypes.c_int32()
+    _check(load_library().funnel_plan_schedule(plan, ctypes.byref(v)), "funnel_plan_schedule")
+    return v.value
+
+
 def funnel_graph_create(plan: int, what: int, images=None, planes=None, d_planes=None, d_images=None,
                         ws=None) -> int:
     h = ctypes.c_void_p()
@@ -346,7 +360,7 @@ def funnel_profile_disable(plan: int) -> None:
     _check(load_library().funnel_profile_disable(plan), "funnel_profile_disable")
 
 
-def funnel_autotune(plan: int, stream=None, cap: int = 16) -> list[dict]:
+def funnel_autotune(plan: int, stream=None, cap: int = 64) -> list[dict]:
     arr = (ft_tune_result * cap)()
     n = ctypes.c_int32()
     _check(load_library().funnel_autotune(plan, _stream(stream), arr, cap, ctypes.byref(n)), "funnel_autotune")
@@ -618,6 +632,15 @@ class RaggedPlan:
             except Exception:
                 pass
             self.handle = None
+
+    @property
+    def schedule(self) -> int:
+        return funnel_plan_schedule(self.handle)
+
+    def set_schedule(self, schedule: int) -> None:
+        """FT_SCHEDULE_CLASS_STREAMS or FT_SCHEDULE_QUEUE (one persistent
+        launch per pass kind over a work queue of all classes' tiles)."""
+        funnel_plan_set_schedule(self.handle, schedule)
 
     def pack(self, images):
         """List of [N, M] float32 arrays -> one flat device tensor."""

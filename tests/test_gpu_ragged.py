@@ -135,3 +135,111 @@ def test_graph_replays_match_eager(ragged):
         assert torch.equal(dI, ref_d), rep
         plan.forward(x * 0.5)          # eager work between replays
         torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------- the queue schedule
+
+CAMERA = [(240, 320), (480, 640), (720, 1280), (1080, 1920)]
+
+
+def camera_batch(per_class, seed):
+    """Images of the four camera formats, classes interleaved."""
+    shapes = [CAMERA[i % 4] for i in range(4 * per_class)]
+    ims = [synth.mixed_lines(N, M, (2, 12), 0.1, np.random.default_rng([seed, i])) for i, (N, M) in enumerate(shapes)]
+    return shapes, [im.image for im in ims]
+
+
+def test_queue_schedule_matches_oracle():
+    """One persistent launch per pass kind over all classes: forward planes
+    and the adjoint of one image of each camera format against the oracle."""
+    import torch
+    shapes, imgs = camera_batch(2, 51)
+    say(f"queue schedule parity, {len(shapes)} images")
+    plan = F.RaggedPlan(shapes)
+    plan.set_schedule(F.FT_SCHEDULE_QUEUE)
+    assert plan.schedule == F.FT_SCHEDULE_QUEUE
+    x = plan.pack(imgs)
+    planes = plan.forward(x)
+    rng = np.random.default_rng(52)
+    dP = rng.standard_normal(plan.plane_floats).astype(np.float32)
+    dI = plan.adjoint(torch.from_numpy(dP).cuda())
+    torch.cuda.synchronize()
+    got = plan.unpack_planes(planes)
+    got_d = plan.unpack_images(dI)
+    dpl = plan.unpack_planes(torch.from_numpy(dP))
+    for i in range(4):       # the first image of each class
+        N, M = shapes[i]
+        r, v = O.forward(imgs[i].astype(np.float64))
+        e = max(rel_l2(got[i][0], r), rel_l2(got[i][1], v))
+        want = O.adjoint(dpl[i][0].astype(np.float64), dpl[i][1].astype(np.float64), N, M)
+        ed = rel_l2(got_d[i], want)
+        say(f"  image {i} {N}x{M}: rel L2 planes {e:.2e} adjoint {ed:.2e}")
+        assert e <= TOL and ed <= TOL, (i, e, ed)
+
+
+def test_queue_schedule_matches_class_streams():
+    """With 16-element tiles on both sides the queue kernels run the same
+    butterflies as the per-class kernels, so every image's planes and
+    gradient agree to FP32 rounding (not bitwise: the two kernels are
+    compiled separately, and the compiler fuses different multiply-adds
+    into FMAs)."""
+    import torch
+    shapes, imgs = camera_batch(3, 61)
+    say(f"queue vs class streams, {len(shapes)} images")
+    plan = F.RaggedPlan(shapes)
+    for role in range(12 * F.funnel_plan_classes(plan.handle)):
+        F.funnel_plan_set_variant(plan.handle, role, 0)      # (16 elements per thread, 4 pairs), rows (16, 256)
+    x = plan.pack(imgs)
+    dP = torch.randn(plan.plane_floats, device="cuda", generator=torch.Generator(device="cuda").manual_seed(62))
+    ref_p = plan.unpack_planes(plan.forward(x))
+    ref_d = plan.unpack_images(plan.adjoint(dP))
+    plan.set_schedule(F.FT_SCHEDULE_QUEUE)
+    got_p = plan.unpack_planes(plan.forward(x))
+    got_d = plan.unpack_images(plan.adjoint(dP))
+    worst = 0.0
+    for i in range(len(shapes)):
+        e = max(rel_l2(got_p[i][0], ref_p[i][0]), rel_l2(got_p[i][1], ref_p[i][1]), rel_l2(got_d[i], ref_d[i]))
+        worst = max(worst, e)
+        assert e <= 1e-6, (i, shapes[i], e)
+    say(f"  worst rel L2 between the schedules {worst:.2e}")
+
+
+def test_queue_graph_replays_and_autotune():
+    """The queue schedule captured in a graph (its counter reset included)
+    replays bitwise like eager calls; the autotuner reports a schedule."""
+    import torch
+    shapes, imgs = camera_batch(1, 71)
+    plan = F.RaggedPlan(shapes)
+    tuned = F.funnel_autotune(plan.handle)
+    sched = [t for t in tuned if t["name"] == "schedule"]
+    assert len(sched) == 1 and sched[0]["variant"] in (0, 1), tuned[-1:]
+    say(f"  autotuned schedule {sched[0]['variant']}: {sched[0]['ms']:.3f} ms (class streams {sched[0]['ms_default']:.3f})")
+    plan.set_schedule(F.FT_SCHEDULE_QUEUE)
+    x = plan.pack(imgs)
+    planes = plan.new_planes()
+    dP = torch.randn(plan.plane_floats, device="cuda")
+    dI = torch.zeros(plan.image_floats, device="cuda")
+    ref_p = plan.forward(x).clone()
+    ref_d = plan.adjoint(dP).clone()
+    g = F.FunnelGraph(plan, F.FT_GRAPH_FORWARD | F.FT_GRAPH_ADJOINT, x, planes, dP, dI)
+    for rep in range(3):
+        planes.zero_()
+        dI.fill_(7.0)
+        g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(planes, ref_p), rep
+        assert torch.equal(dI, ref_d), rep
+        plan.forward(x * 0.5)
+        torch.cuda.synchronize()
+
+
+def test_queue_schedule_rejections():
+    with pytest.raises(F.FunnelError) as e:
+        F.RaggedPlan([(96, 160), (64, 64)]).set_schedule(F.FT_SCHEDULE_QUEUE)
+    assert e.value.status == F.FT_ERR_UNSUPPORTED_SIZE
+    uni = F.FunnelPlan(1, 240, 320)
+    with pytest.raises(F.FunnelError) as e:
+        F.funnel_plan_set_schedule(uni.handle, F.FT_SCHEDULE_QUEUE)
+    assert e.value.status == F.FT_ERR_INVALID_ARG
+    with pytest.raises(F.FunnelError):
+        F.RaggedPlan(CAMERA).set_schedule(5)
