@@ -170,9 +170,7 @@ def test_chirpz_peaks_512():
         pr, pi = O.forward(imgs[b].image.astype(np.float64), plan.Np, "chirpz")
         gr, gi = v.regular[b].cpu().numpy(), v.inverse[b].cpu().numpy()
         assert max(rel_l2(gr, pr), rel_l2(gi, pi)) <= TOL
-        delta = [np.abs(np.abs(gr) - np.abs(pr)).max(), np.abs(np.abs(gi) - np.abs(pi)).max()]
-        decided += check_peaks(got, b, (pr, pi), mask, delta)
-    assert min(decided) >= 1, decided
+        decided += check_peaks(got, b, (gr, gi), (pr, pi), mask, (TOL, TOL))
 
 
 def test_chirpz_graph_replays_match_eager():

@@ -2,22 +2,27 @@
 operands, three products, FP32 accumulation) against the FP64 oracle, beside
 the FP32 path.
 
-Tolerances (rel L2 over a plane or an image gradient), from the arithmetic:
-splitting x = hi + lo leaves |x - hi - lo| <= u^2 |x|, and the dropped
-lo*lo product is <= u^2 |a||x|, with u = 2^-8 (BF16) or 2^-11 (FP16), so each
-matrix-core stage adds a relative error of about u^2 rms (1.5e-5 for BF16,
-2.4e-7 for FP16).  A forward or adjoint path has nine such stages (three
-radix-16/8 stages in each of its three passes), which add in quadrature
-(3 u^2), and the last pass (Hermitian inverse DFT, DC and Nyquist rows
-dropped) amplifies relative errors up to about 2x on these images (measured
-on the FP32 path against FP64).  Estimate 6 u^2: 9e-5 (BF16 x3) and 1.5e-6
-(FP16 x3, where the FP32 rounding floor of the radix-16 passes, about 1e-6
-at 2048^2, adds to it).  Bounds: 1.5e-4 and 3e-6.
+Bounds (rel L2 over a plane or an image gradient), derived per image from a
+CPU emulation of the split arithmetic (tests/mfma_emulation.py, pinned in
+tests/test_mfma_emulation.py) and the oracle's own spectrum, not from GPU
+runs: each transform of length L adds the relative error the emulation
+measures for it (BF16 x3 about 5e-6, FP16 x3 about 1.3e-7 at 2048-4096
+points, against 3e-7 for FP32); the first y-DFT's error, spread evenly over
+the frequency rows, is raised against the signal by the NVMT's gain (the
+signal's energy sits in the low rows the NVMT shrinks, gain 13-15 on these
+images), and the three transforms add in quadrature
+(mfma_emulation.predicted_path_error).  Planes are held to 1.5x that
+prediction, gradients to 2x the adjoint's (no NVMT gain for a plane gradient
+spread over the plane; FP32's transform error as the floor).  The FP32
+path keeps the stated 1e-5.
 """
+import hashlib
+
 import numpy as np
 import pytest
 
 import pins
+import mfma_emulation as EMU
 from helpers import peaks_match_on_decidable_prefix, rel_l2
 from oracle import funnel_oracle as O
 from paper_1904_09409_amd import funnel as F
@@ -27,7 +32,28 @@ pytestmark = pytest.mark.gpu
 
 PRECS = [F.FT_PREC_BF16X3, F.FT_PREC_FP16X3]
 NAMES = {F.FT_PREC_FP32: "fp32", F.FT_PREC_BF16X3: "bf16x3", F.FT_PREC_FP16X3: "fp16x3"}
-TOL = {F.FT_PREC_FP32: 1e-5, F.FT_PREC_BF16X3: 1.5e-4, F.FT_PREC_FP16X3: 3e-6}
+TOL_FP32 = 1e-5
+_spectra = {}
+EMU_NAME = {F.FT_PREC_BF16X3: "bf16", F.FT_PREC_FP16X3: "fp16"}
+
+
+def derived_bounds(prec, img, Np, spaces):
+    """(plane bound per space, gradient bound) of precision prec for one image."""
+    N, M = img.shape
+    if prec == F.FT_PREC_FP32:
+        ns = 2 if spaces == F.FT_SPACE_BOTH else 1
+        return [TOL_FP32] * ns, TOL_FP32
+    name = EMU_NAME[prec]
+    planes, widths = [], []
+    for sp, (im, W) in ((F.FT_SPACE_REGULAR, (img, M)), (F.FT_SPACE_INVERSE, (img.T, N))):
+        if spaces & sp:
+            key = (hashlib.sha1(np.ascontiguousarray(im).tobytes()).hexdigest(), Np)
+            if key not in _spectra:   # the oracle's y-DFT, shared by the precisions
+                _spectra[key] = O.spectrum_y(O.expand(np.asarray(im, dtype=np.float64), Np))
+            planes.append(1.5 * EMU.predicted_path_error(_spectra[key], Np, W, name))
+            widths.append(W)
+    grad = 2.0 * max(EMU.predicted_adjoint_error(Np, W, name) for W in widths)
+    return planes, grad
 
 
 def say(*a):
@@ -80,11 +106,14 @@ def test_forward_adjoint_parity(prec, N, M, Np, spaces):
     for b in range(B):
         ref = O.forward(imgs[b].image.astype(np.float64), plan.Np)
         want = [ref[0]] if spaces == 1 else ([ref[1]] if spaces == 2 else list(ref))
+        bp, bg = derived_bounds(prec, imgs[b].image, plan.Np, spaces)
         errs = [rel_l2(got, exp) for got, exp in zip(split_planes(P[b], N, M, plan.Np, spaces), want)]
-        errs.append(rel_l2(G[b], oracle_adjoint(dP[b].numpy(), N, M, plan.Np, spaces)))
-        worst = max(worst, *errs)
+        eg = rel_l2(G[b], oracle_adjoint(dP[b].numpy(), N, M, plan.Np, spaces))
+        say(f"  image {b}: planes {['%.2e' % e for e in errs]} (bounds {['%.2e' % x for x in bp]}), "
+            f"gradient {eg:.2e} (bound {bg:.2e})")
+        assert all(e <= x for e, x in zip(errs, bp)) and eg <= bg
+        worst = max(worst, *errs, eg)
     say(f"  worst rel L2 (planes and gradient) {worst:.2e}")
-    assert worst <= TOL[prec]
 
 
 # ---------------------------------------------------------------- 8 x 2048^2 workload
@@ -122,19 +151,19 @@ def workload():
         d = O.adjoint(dPh[b, :Np * 2048].reshape(Np, 2048).astype(np.float64),
                       dPh[b, Np * 2048:].reshape(Np, 2048).astype(np.float64), 2048, 2048, Np)
         ref[b] = (pr, pi, d)
-    _cache.update(x=x, dP=dP, ref=ref, Np=Np, mask=mask)
+    _cache.update(x=x, dP=dP, ref=ref, Np=Np, mask=mask, imgs=imgs)
     return _cache
 
 
-def check_peaks(got_rec, b, planes_gpu, planes_ref, mask, prec, K=16):
+def check_peaks(got_rec, b, planes_gpu, planes_ref, mask, bounds, K=16):
     """GPU peak list against the oracle's on the decidable prefix
-    (helpers.peaks_match_on_decidable_prefix, with this precision's stated
-    bound checked cell by cell), at least 12 of the 16 peaks per plane."""
+    (helpers.peaks_match_on_decidable_prefix, with the plane's bound checked
+    cell by cell), at least 12 of the 16 peaks per plane."""
     decided = []
     for s, (Pg, Pref) in enumerate(zip(planes_gpu, planes_ref)):
         g = got_rec[b][s]
         ids = [int(r) * Pref.shape[1] + int(c) for r, c in zip(g["row"], g["col"])]
-        decided.append(peaks_match_on_decidable_prefix(O, ids, Pg, Pref, TOL[prec], mask, K, 12))
+        decided.append(peaks_match_on_decidable_prefix(O, ids, Pg, Pref, bounds[s], mask, K, 12))
     say(f"    image {b}: peaks identical to the oracle's on decidable prefixes {decided}")
     return decided
 
@@ -161,6 +190,8 @@ def test_precision_workload_2048(prec):
         gr, gi = v.regular[b].cpu().numpy(), v.inverse[b].cpu().numpy()
         e_r, e_i = rel_l2(gr, pr), rel_l2(gi, pi)
         e_d = rel_l2(dI[b].cpu().numpy(), d)
-        say(f"    image {b}: rel L2 regular {e_r:.2e} inverse {e_i:.2e} adjoint {e_d:.2e}")
-        assert max(e_r, e_i, e_d) <= TOL[prec]
-        decided += check_peaks(got, b, (gr, gi), (pr, pi), w["mask"], prec)
+        bp, bg = derived_bounds(prec, w["imgs"][b].image, w["Np"], F.FT_SPACE_BOTH)
+        say(f"    image {b}: rel L2 regular {e_r:.2e} inverse {e_i:.2e} (bounds {bp[0]:.2e} {bp[1]:.2e}) "
+            f"adjoint {e_d:.2e} (bound {bg:.2e})")
+        assert e_r <= bp[0] and e_i <= bp[1] and e_d <= bg
+        decided += check_peaks(got, b, (gr, gi), (pr, pi), w["mask"], bp)
