@@ -582,18 +582,44 @@ __device__ __forceinline__ void c2r_tile(const float2* __restrict__ in, float* _
     if (!live || pg >= npairs) continue;
     // output row r = t + P b + q NBL - r0: offsets at o0 + (P b + q NBL) * step
     const int o0 = TRANS ? (2 * pg * nout + t - r0) * 4 : ((t - r0) * nlines + 2 * pg) * 4;
-    float2 old[E];
     if constexpr (ACCUM) {
-      // read every old value first so the adds do not serialise on memory
-      // latency (reading them before the transform instead was measured slower)
-#pragma unroll
-      for (int b = 0; b < BPTL; ++b)
+      // read-modify-write, one butterfly slot (RL outputs) at a time with the
+      // next slot's old values already in flight: two slots of registers
+      // instead of all E, so the wide tiles fit in registers.  The slot's
+      // base offset passes through an empty asm after the previous slot's
+      // stores, so the compiler cannot hoist every load to the front.
+      float2 old[2][RL];
+      auto fetch = [&](int b, float2 (&o)[RL]) {
+        int base = o0 + P * b * step;
+        asm volatile("" : "+v"(base));
 #pragma unroll
         for (int q = 0; q < RL; ++q) {
-          const int o = o0 + (P * b + q * NBL) * step;
-          if constexpr (TRANS) old[b * RL + q] = make_float2(dst.ld1(o), dst.ld1(o + nout * 4));
-          else old[b * RL + q] = dst.ld2(o);
+          const int ofs = base + q * NBL * step;
+          if constexpr (TRANS) o[q] = make_float2(dst.ld1(ofs), dst.ld1(ofs + nout * 4));
+          else o[q] = dst.ld2(ofs);
         }
+      };
+      fetch(0, old[0]);
+#pragma unroll
+      for (int b = 0; b < BPTL; ++b) {
+        if (b + 1 < BPTL) fetch(b + 1, old[(b + 1) & 1]);
+        if (!Eng::template ok<LAST, false>(t, b)) continue;
+#pragma unroll
+        for (int q = 0; q < RL; ++q) {
+          const int r = t + P * b + q * NBL - r0;
+          const int o = o0 + (P * b + q * NBL) * step;
+          const float a = scale * v[g][b * RL + q].x + old[b & 1][q].x;
+          const float bb = scale * v[g][b * RL + q].y + old[b & 1][q].y;
+          if constexpr (TRANS) {
+            if (r < 0 || r >= nout) continue;
+            dst.st1(a, o);
+            dst.st1(bb, o + nout * 4);
+          } else {
+            dst.st2(make_float2(a, bb), o);
+          }
+        }
+      }
+      continue;
     }
 #pragma unroll
     for (int b = 0; b < BPTL; ++b) {
@@ -602,11 +628,7 @@ __device__ __forceinline__ void c2r_tile(const float2* __restrict__ in, float* _
       for (int q = 0; q < RL; ++q) {
         const int r = t + P * b + q * NBL - r0;
         const int o = o0 + (P * b + q * NBL) * step;
-        float a = scale * v[g][b * RL + q].x, bb = scale * v[g][b * RL + q].y;
-        if constexpr (ACCUM) {
-          a += old[b * RL + q].x;
-          bb += old[b * RL + q].y;
-        }
+        const float a = scale * v[g][b * RL + q].x, bb = scale * v[g][b * RL + q].y;
         if constexpr (TRANS) {
           // rows outside [0, nout) would land in the neighbouring line
           if (r < 0 || r >= nout) continue;
