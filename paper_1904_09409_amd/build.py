@@ -20,6 +20,8 @@ FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the exhaustive compile-time layout checks of the matrix-core engine
+    "-fconstexpr-steps=200000000",
 ]
 
 

@@ -255,6 +255,7 @@ template <int LINES, int L>
 struct LayRow {
   static constexpr int kStride = L + L / 16 + 1;
   __device__ static __forceinline__ int addr(int line, int idx) { return line * kStride + idx + (idx >> 4); }
+  static constexpr int caddr(int line, int idx) { return line * kStride + idx + (idx >> 4); }   // (same, constexpr)
   static constexpr int size(int) { return kStride * LINES; }
   // addr(line, x + d) = addr(line, x) + coff(d) when (x mod 16) + (d mod 16) < 16
   static constexpr int coff(int d) { return d + (d >> 4); }
@@ -595,6 +596,7 @@ struct FftR {
 template <int LINES>
 struct LayInterR {
   __device__ static __forceinline__ int addr(int line, int idx) { return (idx + (idx >> 4)) * LINES + line; }
+  static constexpr int caddr(int line, int idx) { return (idx + (idx >> 4)) * LINES + line; }   // (same, constexpr)
   static constexpr int size(int L) { return (L + L / 16 + 1) * LINES; }
   // addr(line, x + d) = addr(line, x) + coff(d) when (x mod 16) + (d mod 16) < 16
   static constexpr int coff(int d) { return (d + (d >> 4)) * LINES; }

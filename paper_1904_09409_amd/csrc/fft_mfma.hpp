@@ -22,10 +22,12 @@
 // and imaginary part of one input in adjacent K slots lets a lane read and
 // write whole complex values.
 //
-// Interface: identical to FftR::run.  The caller's registers hold pass 0's
+// Interface: run() is FftR::run's.  The caller's registers hold pass 0's
 // inputs in FftR's layout (including the Hermitian pairing of a paired first
 // pass) and receive the last pass's outputs in FftR's layout; FftM moves
-// them through LDS into its own layout on entry and back on exit.
+// them through LDS into its own layout on entry and back on exit.  run_ex()
+// skips either move for callers that load the inputs, or store the outputs,
+// in FftM's own layout (native_in / native_out give each slot's element).
 #pragma once
 
 #include "fft_core.hpp"
@@ -146,76 +148,198 @@ struct FftM {
   static constexpr int groups() { return E / per<I>(); }
 
   // butterfly id of group c for this lane -> (line, j)
-  template <int I>
-  __device__ static __forceinline__ void which(int c, int& line, int& j) {
-    constexpr int NB = L / kM.r[I];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int B = (w * groups<I>() + c) * 16 + (lane & 15);
-    if constexpr (LINE_FASTEST) {
-      line = B % NLINES;
-      j = B / NLINES;
-    } else {
-      line = B / NB;
-      j = B % NB;
-    }
+  // tid: the thread index, passed through an empty asm after each barrier
+  // (opaque()), so that slot addresses are computed where they are used and
+  // not hoisted to the kernel's start and kept live across the passes
+  __device__ static __forceinline__ int opaque() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t & 1023;   // (blocks hold at most 1024 threads: known range for the index algebra)
   }
-
-  template <bool SPLIT, class Lay, class Buf, class WR, class RD>
-  __device__ static __forceinline__ void xchg(float2 (&v)[E], Buf* lds, WR wr, RD rd) {
-    if constexpr (!SPLIT) {
-      __syncthreads();
-#pragma unroll
-      for (int s = 0; s < E; ++s) {
-        int ln, idx;
-        wr(s, ln, idx);
-        lds[Lay::addr(ln, idx)] = v[s];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int s = 0; s < E; ++s) {
-        int ln, idx;
-        rd(s, ln, idx);
-        v[s] = lds[Lay::addr(ln, idx)];
-      }
+  template <int I>
+  // (unsigned arithmetic: the divisions by powers of two are plain shifts;
+  // constexpr, so that the layout checks below can evaluate them)
+  static constexpr void which(int tid, int c, int& line, int& j) {
+    constexpr unsigned NB = L / kM.r[I];
+    const unsigned ut = (unsigned)tid;
+    const unsigned B = ((ut >> 6) * (unsigned)groups<I>() + (unsigned)c) * 16u + (ut & 15u);
+    if constexpr (LINE_FASTEST) {
+      line = (int)(B % (unsigned)NLINES);
+      j = (int)(B / (unsigned)NLINES);
     } else {
-#pragma unroll
-      for (int part = 0; part < 2; ++part) {
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < E; ++s) {
-          int ln, idx;
-          wr(s, ln, idx);
-          lds[Lay::addr(ln, idx)] = part ? v[s].y : v[s].x;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < E; ++s) {
-          int ln, idx;
-          rd(s, ln, idx);
-          const float f = lds[Lay::addr(ln, idx)];
-          if (part) v[s].y = f;
-          else v[s].x = f;
-        }
-      }
+      line = (int)(B / NB);
+      j = (int)(B % NB);
     }
   }
 
   // inputs of pass I: slot s holds input r = (lane/16) per + s % per of butterfly (group s / per)
   template <int I>
-  __device__ static __forceinline__ void in_pos(int s, int& ln, int& idx) {
-    constexpr int PER = per<I>(), NB = L / kM.r[I];
-    int j;
-    which<I>(s / PER, ln, j);
-    const int r = (int)(threadIdx.x & 63) / 16 * PER + s % PER;
-    idx = j + r * NB;
+  static constexpr void in_pos(int tid, int s, int& ln, int& idx) {
+    constexpr unsigned PER = per<I>(), NB = L / kM.r[I];
+    int j = 0;
+    which<I>(tid, s / PER, ln, j);
+    const unsigned r = (((unsigned)tid & 63u) >> 4) * PER + (unsigned)s % PER;
+    idx = (int)((unsigned)j + r * NB);
   }
   template <int I>
-  __device__ static __forceinline__ void out_pos(int s, int& ln, int& idx) {
-    constexpr int PER = per<I>(), NS = ns<I>(), R = kM.r[I];
-    int j;
-    which<I>(s / PER, ln, j);
-    const int q = (int)(threadIdx.x & 63) / 16 * PER + s % PER;
-    idx = (j / NS) * NS * R + (j % NS) + q * NS;
+  static constexpr void out_pos(int tid, int s, int& ln, int& idx) {
+    constexpr unsigned PER = per<I>(), NS = ns<I>(), R = kM.r[I];
+    int j = 0;
+    which<I>(tid, s / PER, ln, j);
+    const unsigned uj = (unsigned)j;
+    const unsigned q = (((unsigned)tid & 63u) >> 4) * PER + (unsigned)s % PER;
+    idx = (int)((uj / NS) * NS * R + (uj % NS) + q * NS);
+  }
+
+  // LDS slot of element s on one side of an exchange: the outputs of pass I
+  // (OUT) or its inputs.  Where, for every thread of the block, slot s lies
+  // a fixed distance K(s) from the thread's slot 0 (checked exhaustively at
+  // compile time), an exchange computes one address per thread and reaches
+  // the rest by immediate offsets instead of per-slot index arithmetic.
+  template <int I, bool OUT, class Lay>
+  static constexpr int pos_addr(int tid, int s) {
+    int ln = 0, idx = 0;
+    if constexpr (OUT) out_pos<I>(tid, s, ln, idx);
+    else in_pos<I>(tid, s, ln, idx);
+    return Lay::caddr(ln, idx);
+  }
+  struct Offs {
+    int k[E];
+  };
+  template <int I, bool OUT, class Lay>
+  static constexpr Offs offsets() {
+    Offs o{};
+    for (int s = 0; s < E; ++s) o.k[s] = pos_addr<I, OUT, Lay>(0, s) - pos_addr<I, OUT, Lay>(0, 0);
+    return o;
+  }
+  template <int I, bool OUT, class Lay>
+  static constexpr bool lin_pos() {
+    constexpr Offs K = offsets<I, OUT, Lay>();
+    for (int tid = 0; tid < THREADS; ++tid) {
+      const int a0 = pos_addr<I, OUT, Lay>(tid, 0);
+      for (int s = 1; s < E; ++s)
+        if (pos_addr<I, OUT, Lay>(tid, s) - a0 != K.k[s]) return false;
+    }
+    return true;
+  }
+
+  // element index (not LDS slot) of slot s relative to slot 0, the same for
+  // every thread, and slot s in the thread's slot-0 transform: then callers
+  // that load or store in the native layout address slot s as their slot-0
+  // element plus a constant
+  template <int I, bool OUT>
+  static constexpr void pos_idx(int tid, int s, int& ln, int& idx) {
+    if constexpr (OUT) out_pos<I>(tid, s, ln, idx);
+    else in_pos<I>(tid, s, ln, idx);
+  }
+  template <int I, bool OUT>
+  static constexpr Offs idx_offsets() {
+    Offs o{};
+    int l0 = 0, i0 = 0;
+    pos_idx<I, OUT>(0, 0, l0, i0);
+    for (int s = 0; s < E; ++s) {
+      int l = 0, i = 0;
+      pos_idx<I, OUT>(0, s, l, i);
+      o.k[s] = i - i0;
+    }
+    return o;
+  }
+  template <int I, bool OUT>
+  static constexpr bool lin_idx() {
+    constexpr Offs K = idx_offsets<I, OUT>();
+    for (int tid = 0; tid < THREADS; ++tid) {
+      int l0 = 0, i0 = 0;
+      pos_idx<I, OUT>(tid, 0, l0, i0);
+      for (int s = 1; s < E; ++s) {
+        int l = 0, i = 0;
+        pos_idx<I, OUT>(tid, s, l, i);
+        if (l != l0 || i - i0 != K.k[s]) return false;
+      }
+    }
+    return true;
+  }
+
+  // store v to (load v from) the LDS slots of pass I's outputs (OUT) or
+  // inputs; part: the real (0) or imaginary (1) halves of a SPLIT exchange
+  template <int I, bool OUT, bool SPLIT, class Lay, class Buf>
+  __device__ static __forceinline__ void lds_put(const float2 (&v)[E], Buf* lds, int tid, int part) {
+    constexpr bool LIN = lin_pos<I, OUT, Lay>();
+    constexpr Offs K = offsets<I, OUT, Lay>();
+    Buf* base = lds + pos_addr<I, OUT, Lay>(tid, 0);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      Buf* a = LIN ? base + K.k[s] : lds + pos_addr<I, OUT, Lay>(tid, s);
+      if constexpr (SPLIT) *a = part ? v[s].y : v[s].x;
+      else *a = v[s];
+    }
+  }
+  template <int I, bool OUT, bool SPLIT, class Lay, class Buf>
+  __device__ static __forceinline__ void lds_get(float2 (&v)[E], const Buf* lds, int tid, int part) {
+    constexpr bool LIN = lin_pos<I, OUT, Lay>();
+    constexpr Offs K = offsets<I, OUT, Lay>();
+    const Buf* base = lds + pos_addr<I, OUT, Lay>(tid, 0);
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+      const Buf* a = LIN ? base + K.k[s] : lds + pos_addr<I, OUT, Lay>(tid, s);
+      if constexpr (SPLIT) {
+        if (part) v[s].y = *a;
+        else v[s].x = *a;
+      } else {
+        v[s] = *a;
+      }
+    }
+  }
+
+  // exchange between pass I and pass I + 1 (outputs of I -> inputs of I + 1)
+  template <int I, bool SPLIT, class Lay, class Buf>
+  __device__ static __forceinline__ void xchg_pass(float2 (&v)[E], Buf* lds) {
+#pragma unroll
+    for (int part = 0; part < (SPLIT ? 2 : 1); ++part) {
+      __syncthreads();
+      lds_put<I, true, SPLIT, Lay>(v, lds, opaque(), part);
+      __syncthreads();
+      lds_get<I + 1, false, SPLIT, Lay>(v, lds, opaque(), part);
+    }
+  }
+
+  // entry: FftR's layout (slot s = butterfly bfly(t, s / R0), input s % R0)
+  // -> the first pass's inputs; exit: the last pass's outputs -> FftR's
+  // layout (PAIRED map of the first / last pass as the caller uses it)
+  template <bool PAIRED, bool SPLIT, class Lay, class Buf>
+  __device__ static __forceinline__ void xchg_entry(float2 (&v)[E], Buf* lds, int line, int t) {
+    constexpr int R0 = kPlan.r[0], NB0 = L / R0;
+#pragma unroll
+    for (int part = 0; part < (SPLIT ? 2 : 1); ++part) {
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < E; ++s) {
+        Buf* a = lds + Lay::addr(line, Outer::template bfly<0, PAIRED>(t, s / R0) + (s % R0) * NB0);
+        if constexpr (SPLIT) *a = part ? v[s].y : v[s].x;
+        else *a = v[s];
+      }
+      __syncthreads();
+      lds_get<0, false, SPLIT, Lay>(v, lds, opaque(), part);
+    }
+  }
+  template <bool PAIRED, bool SPLIT, class Lay, class Buf>
+  __device__ static __forceinline__ void xchg_exit(float2 (&v)[E], Buf* lds, int line, int t) {
+    constexpr int LAST = kPlan.n - 1, RL = kPlan.r[LAST], NBL = L / RL;
+#pragma unroll
+    for (int part = 0; part < (SPLIT ? 2 : 1); ++part) {
+      __syncthreads();
+      lds_put<kM.n - 1, true, SPLIT, Lay>(v, lds, opaque(), part);
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < E; ++s) {
+        const Buf* a = lds + Lay::addr(line, Outer::template bfly<LAST, PAIRED>(t, s / RL) + (s % RL) * NBL);
+        if constexpr (SPLIT) {
+          if (part) v[s].y = *a;
+          else v[s].x = *a;
+        } else {
+          v[s] = *a;
+        }
+      }
+    }
   }
 
   // A operands of the radix-16 product (rows: outputs; lane holds row n,
@@ -252,17 +376,18 @@ struct FftM {
   template <int I>
   __device__ static __forceinline__ void compute(float2 (&v)[E], const Coef& A, const float2* __restrict__ tw) {
     constexpr int R = kM.r[I], NS = ns<I>(), PER = per<I>();
-    const int g = (int)(threadIdx.x & 63) >> 4;
+    const int tid = opaque();
+    const int g = (tid & 63) >> 4;
 #pragma unroll
     for (int c = 0; c < groups<I>(); ++c) {
       float2* x = v + c * PER;
       if constexpr (NS > 1) {
-        int ln, j;
-        which<I>(c, ln, j);
-        const int st = (j % NS) * (L / (NS * R));
+        int ln = 0, j = 0;
+        which<I>(tid, c, ln, j);
+        const unsigned st = ((unsigned)j % (unsigned)NS) * (unsigned)(L / (NS * R));
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-          float2 w = tw[(g * PER + i) * st];   // each power from the table
+          float2 w = tw[((unsigned)g * PER + i) * st];   // each power from the table
           if (INV) w.y = -w.y;
           x[i] = c_mul(x[i], w);
         }
@@ -325,11 +450,43 @@ struct FftM {
                                                 const float2* __restrict__ tw) {
     compute<I>(v, A, tw);
     if constexpr (I + 1 < kM.n) {
-      xchg<SPLIT, Lay>(
-          v, lds, [](int s, int& ln, int& idx) { out_pos<I>(s, ln, idx); },
-          [](int s, int& ln, int& idx) { in_pos<I + 1>(s, ln, idx); });
+      xchg_pass<I, SPLIT, Lay>(v, lds);
       passes<I + 1, SPLIT, Lay>(v, lds, A, tw);
     }
+  }
+
+  // Native layout: slot s of a lane holds input element idx of transform ln
+  // of the first matrix-core pass (native_in) and receives output element
+  // idx of the last one (native_out).  Callers that load or store in this
+  // layout skip the re-layout through LDS on that side (run_ex).
+  __device__ static __forceinline__ void native_in(int tid, int s, int& ln, int& idx) { in_pos<0>(tid, s, ln, idx); }
+  __device__ static __forceinline__ void native_out(int tid, int s, int& ln, int& idx) {
+    out_pos<kM.n - 1>(tid, s, ln, idx);
+  }
+  // every slot of a thread in its slot-0 transform, element = slot 0's + K(s)
+  static constexpr bool kNativeInLin = lin_idx<0, false>();
+  static constexpr bool kNativeOutLin = lin_idx<kM.n - 1, true>();
+  static constexpr Offs kNativeInOff = idx_offsets<0, false>();
+  static constexpr Offs kNativeOutOff = idx_offsets<kM.n - 1, true>();
+  // every slot of a lane belongs to one transform, in the first and in the
+  // last pass (line-major butterfly numbering and whole waves per line)
+  template <int I>
+  static constexpr bool one_line() {
+    return !LINE_FASTEST && (L / kM.r[I]) % (groups<I>() * 16) == 0;
+  }
+  static constexpr bool kLaneOneLine = one_line<0>() && one_line<kM.n - 1>();
+
+  // NATIVE_IN: v holds the first pass's inputs in the native layout (else in
+  // FftR's, PAIRED_FIRST map); NATIVE_OUT: v receives the last pass's outputs
+  // in the native layout (else FftR's, PAIRED_LAST map).
+  template <bool NATIVE_IN, bool NATIVE_OUT, bool PAIRED_FIRST, bool PAIRED_LAST, bool SPLIT, class Lay, class Buf>
+  __device__ static __forceinline__ void run_ex(float2 (&v)[E], int line, int t, Buf* lds,
+                                                const float2* __restrict__ tw) {
+    Coef A;
+    coefs(A);
+    if constexpr (!NATIVE_IN) xchg_entry<PAIRED_FIRST, SPLIT, Lay>(v, lds, line, t);
+    passes<0, SPLIT, Lay>(v, lds, A, tw);
+    if constexpr (!NATIVE_OUT) xchg_exit<PAIRED_LAST, SPLIT, Lay>(v, lds, line, t);
   }
 
   // (FftR's calling convention; the split-precision kernels always run with
@@ -337,24 +494,7 @@ struct FftM {
   template <bool PAIRED_FIRST, bool PAIRED_LAST, bool SPLIT, class Lay, class Buf>
   __device__ static __forceinline__ void run(float2 (&v)[E], int line, int t, Buf* lds,
                                              const float2* __restrict__ tw, bool /*live*/ = true) {
-    constexpr int R0 = kPlan.r[0], NB0 = L / R0;
-    constexpr int LAST = kPlan.n - 1, RL = kPlan.r[LAST], NBL = L / RL;
-    Coef A;
-    coefs(A);
-    xchg<SPLIT, Lay>(
-        v, lds,
-        [&](int s, int& ln, int& idx) {
-          ln = line;
-          idx = Outer::template bfly<0, PAIRED_FIRST>(t, s / R0) + (s % R0) * NB0;
-        },
-        [](int s, int& ln, int& idx) { in_pos<0>(s, ln, idx); });
-    passes<0, SPLIT, Lay>(v, lds, A, tw);
-    xchg<SPLIT, Lay>(
-        v, lds, [](int s, int& ln, int& idx) { out_pos<kM.n - 1>(s, ln, idx); },
-        [&](int s, int& ln, int& idx) {
-          ln = line;
-          idx = Outer::template bfly<LAST, PAIRED_LAST>(t, s / RL) + (s % RL) * NBL;
-        });
+    run_ex<false, false, PAIRED_FIRST, PAIRED_LAST, SPLIT, Lay>(v, line, t, lds, tw);
   }
 };
 

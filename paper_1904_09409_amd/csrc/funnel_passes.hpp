@@ -403,6 +403,22 @@ __device__ __forceinline__ void emit_pair(GBuf dst, int k, float2 zk, float2 zm,
 __device__ __forceinline__ float2 herm_direct(float4 x) { return make_float2(x.x - x.w, x.y + x.z); }  // A + iB
 __device__ __forceinline__ float2 herm_mirror(float4 x) { return make_float2(x.x + x.w, x.z - x.y); }  // conj A + i conj B
 
+// Slot s of the matrix-core engine's native layout (element idx of transform
+// ln) from slot 0's, by a compile-time offset where the engine's layout
+// checks allow it (OUT: the last pass's outputs, else the first's inputs).
+template <class Eng, bool OUT>
+__device__ __forceinline__ void native_slot(int tid, int s, int ln0, int idx0, int& ln, int& idx) {
+  constexpr bool LIN = OUT ? Eng::kNativeOutLin : Eng::kNativeInLin;
+  if constexpr (LIN) {
+    ln = ln0;
+    idx = idx0 + (OUT ? Eng::kNativeOutOff.k[s] : Eng::kNativeInOff.k[s]);
+  } else if constexpr (OUT) {
+    Eng::native_out(tid, s, ln, idx);
+  } else {
+    Eng::native_in(tid, s, ln, idx);
+  }
+}
+
 // The column passes as tile functions: column tile `tile` (NT groups of
 // LINES column pairs) of image `img`, computed by threads tid = 0 ..
 // Cfg::THREADS-1 of a block with the LDS buffer `lds` of
@@ -430,6 +446,29 @@ __device__ __forceinline__ void r2c_tile(const float* __restrict__ in, float2* _
   const GBuf src(in + map.in(img), (long long)lin * nlines * 4);
 
   float2 v[NT][E];
+  if constexpr (PREC != kPrecFP32) {
+    // the matrix-core engine's own layout: slot s holds element idx of
+    // transform (column pair) ln, so the loads skip its entry re-layout
+    static_assert(NT == 1, "split-precision tiles hold one group");
+    int ln0, idx0;
+    Eng::native_in(tid, 0, ln0, idx0);
+#pragma unroll
+    for (int s2 = 0; s2 < E; ++s2) {
+      int ln, idx;
+      native_slot<Eng, false>(tid, s2, ln0, idx0, ln, idx);
+      const int pg = tile * LINES + ln;
+      const int rr = idx - off;
+      float2 z = make_float2(0.f, 0.f);
+      if constexpr (TRANS) {
+        const int o = (2 * pg * lin + rr) * 4;
+        if (pg < npairs && (unsigned)rr < (unsigned)lin) z = make_float2(src.ld1(o), src.ld1(o + lin * 4));
+      } else {
+        // rows outside [0, lin) fall outside the buffer and read 0
+        if (pg < npairs) z = src.ld2((rr * nlines + 2 * pg) * 4);
+      }
+      v[0][s2] = z;
+    }
+  } else {
 #pragma unroll
   for (int g = 0; g < NT; ++g) {
     const int pg = (tile * NT + g) * LINES + pair;
@@ -460,12 +499,14 @@ __device__ __forceinline__ void r2c_tile(const float* __restrict__ in, float2* _
                                                               : make_float2(0.f, 0.f);
     }
   }
+  }
 
   // half-spectrum rows 1 .. H: rows k outside that range fall outside the buffer
   const GBuf dst(out + map.out(img), (long long)H * npairs * 16);
 #pragma unroll
   for (int g = 0; g < NT; ++g) {
-    Eng::template run<false, true, true, Lay>(v[g], pair, t, lds, tw, live);
+    if constexpr (PREC != kPrecFP32) Eng::template run_ex<true, false, false, true, true, Lay>(v[g], pair, t, lds, tw);
+    else Eng::template run<false, true, true, Lay>(v[g], pair, t, lds, tw, live);
     const int pg = (tile * NT + g) * LINES + pair;
     if (!live || pg >= npairs) continue;
 #pragma unroll
@@ -577,7 +618,38 @@ __device__ __forceinline__ void c2r_tile(const float2* __restrict__ in, float* _
   const int step = TRANS ? 4 : nlines * 4;
 #pragma unroll
   for (int g = 0; g < NT; ++g) {
-    Eng::template run<true, false, true, Lay>(v[g], pair, t, lds, tw, live);
+    if constexpr (PREC != kPrecFP32) {
+      // stores from the matrix-core engine's own layout (no exit re-layout):
+      // slot s holds output row idx of column pair ln
+      static_assert(NT == 1, "split-precision tiles hold one group");
+      Eng::template run_ex<false, true, true, false, true, Lay>(v[0], pair, t, lds, tw);
+      const int ntid = Eng::opaque();
+      int ln0, idx0;
+      Eng::native_out(ntid, 0, ln0, idx0);
+#pragma unroll
+      for (int s2 = 0; s2 < E; ++s2) {
+        int ln, idx;
+        native_slot<Eng, true>(ntid, s2, ln0, idx0, ln, idx);
+        const int pgs = tile * LINES + ln, r = idx - r0;
+        if (pgs >= npairs) continue;
+        float a = scale * v[0][s2].x, bb = scale * v[0][s2].y;
+        if constexpr (TRANS) {
+          if (r < 0 || r >= nout) continue;
+          const int o = (2 * pgs * nout + r) * 4;
+          if constexpr (ACCUM) { a += dst.ld1(o); bb += dst.ld1(o + nout * 4); }
+          dst.st1(a, o);
+          dst.st1(bb, o + nout * 4);
+        } else {
+          // rows outside [0, nout) fall outside the buffer (read 0, store dropped)
+          const int o = (r * nlines + 2 * pgs) * 4;
+          if constexpr (ACCUM) { const float2 old = dst.ld2(o); a += old.x; bb += old.y; }
+          dst.st2(make_float2(a, bb), o);
+        }
+      }
+      continue;
+    } else {
+      Eng::template run<true, false, true, Lay>(v[g], pair, t, lds, tw, live);
+    }
     const int pg = (tile * NT + g) * LINES + pair;
     if (!live || pg >= npairs) continue;
     // output row r = t + P b + q NBL - r0: offsets at o0 + (P b + q NBL) * step
@@ -674,6 +746,13 @@ struct RowFastCfg {
 #define FUNNEL_ROW_VARIANTS(X) X(0, 16, 256) X(1, 16, 128) X(2, 16, 512) X(3, 32, 256)
 constexpr int kRowVariants = 4;
 
+// the row tile runs the matrix-core engine in its own layout on both sides
+template <class Eng, int PREC>
+constexpr bool native_rows() {
+  if constexpr (PREC == kPrecFP32) return false;
+  else return Eng::kLaneOneLine;
+}
+
 // Rows blk * ROWS .. blk * ROWS + ROWS-1 of image img, by threads tid = 0 ..
 // THREADS-1 with the LDS buffer `lds` of LayRow<ROWS, M>::size(M) float2
 // (threads past THREADS of a larger block pass live = false, as for the
@@ -724,7 +803,71 @@ __device__ __forceinline__ void row_tile(float2* __restrict__ data, int Lp, int 
   float2 v[E];
 #pragma unroll
   for (int s2 = 0; s2 < E; ++s2) v[s2] = make_float2(0.f, 0.f);
-  if constexpr (!ADJ) {
+  if constexpr (native_rows<Eng, PREC>()) {
+    // The matrix-core engine in its own layout on both sides: the gather
+    // (forward) or the staged row (adjoint) feeds slot s with element idx of
+    // the lane's row directly, and the outputs leave from the same layout,
+    // so no re-layout through LDS on entry or exit.  Every slot of a lane
+    // lies in one row (kLaneOneLine).
+    int lr, i00;
+    Eng::native_in(tid, 0, lr, i00);
+    const int grl = blk * ROWS + lr, n2l = grl / rpf + 1;
+    const bool act = grl < h * rpf;
+    float2* rowl = data + (long long)img * img_stride + (long long)grl * M;
+    const int denl = 2 * n2l, mnl = M * n2l;
+    const float rdl = 1.0f / (float)denl;
+    if constexpr (!ADJ) {
+#pragma unroll
+      for (int s2 = 0; s2 < E; ++s2) {
+        int ln, q;
+        native_slot<Eng, false>(tid, s2, lr, i00, ln, q);
+        const int num = (q - M / 2) * Lp + mnl;
+        const int i0 = floor_div_rcp(num, denl, rdl);
+        const float tt = (float)(num - i0 * denl) * rdl;
+        float2 f0 = make_float2(0.f, 0.f), f1 = make_float2(0.f, 0.f);
+        if (i0 >= 0 && i0 < M) f0 = lds[Lay::addr(lr, i0)];
+        if (i0 + 1 >= 0 && i0 + 1 < M) f1 = lds[Lay::addr(lr, i0 + 1)];
+        const float sg = (q & 1) ? -1.f : 1.f;
+        v[s2] = make_float2(sg * ((1.f - tt) * f0.x + tt * f1.x), sg * ((1.f - tt) * f0.y + tt * f1.y));
+      }
+      Eng::template run_ex<true, true, false, false, false, Lay>(v, row, t, lds, tw);
+      if (!act) return;
+      const int ntid = Eng::opaque();
+      int lo0, po0;
+      Eng::native_out(ntid, 0, lo0, po0);
+#pragma unroll
+      for (int s2 = 0; s2 < E; ++s2) {
+        int ln, p;
+        native_slot<Eng, true>(ntid, s2, lo0, po0, ln, p);
+        float2 g = v[s2];
+        if ((p + M / 2) & 1) g = make_float2(-g.x, -g.y);
+        rowl[p] = g;
+      }
+      return;
+    } else {
+#pragma unroll
+      for (int s2 = 0; s2 < E; ++s2) {
+        int ln, q;
+        native_slot<Eng, false>(tid, s2, lr, i00, ln, q);
+        v[s2] = lds[Lay::addr(lr, q)];
+      }
+      Eng::template run_ex<true, true, false, false, false, Lay>(v, row, t, lds, tw);
+      __syncthreads();
+      const int ntid = Eng::opaque();
+      int lo0, xo0;
+      Eng::native_out(ntid, 0, lo0, xo0);
+#pragma unroll
+      for (int s2 = 0; s2 < E; ++s2) {
+        int ln, x;
+        native_slot<Eng, true>(ntid, s2, lo0, xo0, ln, x);
+        float2 g = v[s2];
+        if ((x + M / 2) & 1) g = make_float2(-g.x, -g.y);
+        lds[Lay::addr(lr, x)] = g;
+      }
+      __syncthreads();
+      // (the transposed gather below reads each thread's own row)
+    }
+  } else if constexpr (!ADJ) {
 #pragma unroll
     for (int b = 0; b < BPT0; ++b)
 #pragma unroll
@@ -771,6 +914,8 @@ __device__ __forceinline__ void row_tile(float2* __restrict__ data, int Lp, int 
         lds[Lay::addr(row, x)] = g;
       }
     __syncthreads();
+  }
+  if constexpr (ADJ) {
     if (!active) return;
     // transposed interpolation as a gather: at most two samples land on i
 #pragma unroll
