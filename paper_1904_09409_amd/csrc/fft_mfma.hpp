@@ -56,6 +56,25 @@ constexpr RadixPlan mfma_plan(int L) {
   return p;
 }
 
+// Lane twiddle tables of the matrix-core passes, stored after the length-L
+// table w^m = exp(-+i 2 pi m / L): for each pass I >= 1 (NS = the product of
+// the earlier radices, R = its radix, PER = R / 4 inputs per lane), entry
+// (m 4 + g) PER + i holds w^((g PER + i) m L / (NS R)) for m < NS, g < 4,
+// i < PER -- the same table values, ordered so that the lane holding inputs
+// g PER .. g PER + PER-1 of a butterfly with m = j mod NS reads its PER
+// twiddles as consecutive 16-byte loads.  mfma_lane_twiddles(L) entries in
+// all, pass I's from entry mfma_lane_twiddle_offset(L, I).
+constexpr int mfma_lane_twiddle_offset(int L, int I) {
+  const RadixPlan p = mfma_plan(L);
+  int off = 0, ns = 1;
+  for (int i = 0; i < I && i < p.n; ++i) {
+    if (i >= 1) off += ns * p.r[i];
+    ns *= p.r[i];
+  }
+  return off;
+}
+constexpr int mfma_lane_twiddles(int L) { return mfma_plan(L).n > 0 ? mfma_lane_twiddle_offset(L, mfma_plan(L).n) : 0; }
+
 template <int PREC>
 struct Half;
 
@@ -384,12 +403,22 @@ struct FftM {
       if constexpr (NS > 1) {
         int ln = 0, j = 0;
         which<I>(tid, c, ln, j);
-        const unsigned st = ((unsigned)j % (unsigned)NS) * (unsigned)(L / (NS * R));
+        // the lane's PER powers, consecutive in the lane table behind the
+        // length-L table (see mfma_lane_twiddle_offset)
+        const unsigned m = (unsigned)j % (unsigned)NS;
+        const float4* lt = reinterpret_cast<const float4*>(
+            tw + L + mfma_lane_twiddle_offset(L, I) + (m * 4u + (unsigned)g) * PER);
+        float2 w[PER];
+#pragma unroll
+        for (int q = 0; q < PER / 2; ++q) {
+          const float4 t4 = lt[q];
+          w[2 * q] = make_float2(t4.x, t4.y);
+          w[2 * q + 1] = make_float2(t4.z, t4.w);
+        }
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-          float2 w = tw[((unsigned)g * PER + i) * st];   // each power from the table
-          if (INV) w.y = -w.y;
-          x[i] = c_mul(x[i], w);
+          if (INV) w[i].y = -w[i].y;
+          x[i] = c_mul(x[i], w[i]);
         }
       }
       float sc = 1.f, inv = 1.f;

@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "../../include/funnel.h"
+#include "fft_mfma.hpp"   // (the matrix-core passes' radix plan, for their twiddle tables)
 #include "funnel_internal.hpp"
 #include "funnel_queue.hpp"
 
@@ -176,6 +177,26 @@ void fill_twiddles(float2* dst, int L) {
   for (int m = 0; m < L; ++m) {
     const double a = 2.0 * M_PI * (double)m / (double)L;
     dst[m] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
+  }
+}
+
+// The matrix-core passes' lane tables behind the length-L table (entries
+// exp(-i 2 pi e / L) for the exponents the layout of mfma_lane_twiddle_offset
+// names, evaluated in double as fill_twiddles does).
+void fill_mfma_lane_twiddles(float2* dst, int L) {
+  const funnel::RadixPlan pl = funnel::mfma_plan(L);
+  int ns = pl.n > 0 ? pl.r[0] : 1;
+  for (int I = 1; I < pl.n; ++I) {
+    const int R = pl.r[I], per = R / 4;
+    float2* t = dst + funnel::mfma_lane_twiddle_offset(L, I);
+    for (int m = 0; m < ns; ++m)
+      for (int g = 0; g < 4; ++g)
+        for (int i = 0; i < per; ++i) {
+          const long long e = (long long)(g * per + i) * m * (L / (ns * R));
+          const double a = 2.0 * M_PI * (double)e / (double)L;
+          t[(m * 4 + g) * per + i] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
+        }
+    ns *= R;
   }
 }
 
@@ -491,12 +512,14 @@ ft_status finish_plan(ft_plan* p, const std::vector<std::vector<std::pair<long l
     if (p->spaces & FT_SPACE_REGULAR) ws += align_up((size_t)c.count * c.h * c.M * sizeof(float2), 256);
     c.ws_inv = ws;
     if (p->spaces & FT_SPACE_INVERSE) ws += align_up((size_t)c.count * c.h * c.N * sizeof(float2), 256);
+    // (split-precision plans: each table followed by the matrix-core lane tables)
+    const bool lane = p->prec != FT_PREC_FP32;
     c.tw_np = ntw;
-    ntw += c.Np;
+    ntw += c.Np + (lane ? funnel::mfma_lane_twiddles(c.Np) : 0);
     c.tw_m = ntw;
-    ntw += c.M;
+    ntw += c.M + (lane ? funnel::mfma_lane_twiddles(c.M) : 0);
     c.tw_n = ntw;
-    ntw += c.N;
+    ntw += c.N + (lane ? funnel::mfma_lane_twiddles(c.N) : 0);
     if (p->chirpz) {
       c.tw_2m = ntw;
       ntw += 2 * (size_t)c.M;
@@ -551,6 +574,11 @@ ft_status finish_plan(ft_plan* p, const std::vector<std::vector<std::pair<long l
     fill_twiddles(host.data() + c.tw_np, c.Np);
     fill_twiddles(host.data() + c.tw_m, c.M);
     fill_twiddles(host.data() + c.tw_n, c.N);
+    if (p->prec != FT_PREC_FP32) {
+      fill_mfma_lane_twiddles(host.data() + c.tw_np + c.Np, c.Np);
+      fill_mfma_lane_twiddles(host.data() + c.tw_m + c.M, c.M);
+      fill_mfma_lane_twiddles(host.data() + c.tw_n + c.N, c.N);
+    }
     if (p->chirpz) {
       fill_twiddles(host.data() + c.tw_2m, 2 * c.M);
       fill_twiddles(host.data() + c.tw_2n, 2 * c.N);
