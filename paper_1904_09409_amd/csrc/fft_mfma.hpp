@@ -30,6 +30,8 @@
 // in FftM's own layout (native_in / native_out give each slot's element).
 #pragma once
 
+#include <type_traits>
+
 #include "fft_core.hpp"
 #include "funnel_internal.hpp"
 
@@ -112,6 +114,28 @@ template <class T>
 __device__ __forceinline__ void split2(float x, T& hi, T& lo) {
   hi = (T)x;
   lo = (T)(x - (float)hi);
+}
+
+// split2 of a complex value (a, b), the parts packed as (a, b) pairs.  BF16:
+// one packed conversion for the two high parts, whose FP32 values are the
+// packed bits shifted into place (exact), and one for the two low parts --
+// the same values as split2, in a third of the instructions.
+template <class T>
+__device__ __forceinline__ void split2_pair(float a, float b, T& ha, T& hb, T& la, T& lb) {
+  if constexpr (std::is_same<T, __bf16>::value) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+    const b2v h = __builtin_convertvector((f2v){a, b}, b2v);
+    const uint32_t u = __builtin_bit_cast(uint32_t, h);
+    const b2v l = __builtin_convertvector((f2v){a - __uint_as_float(u << 16), b - __uint_as_float(u & 0xffff0000u)}, b2v);
+    ha = h[0];
+    hb = h[1];
+    la = l[0];
+    lb = l[1];
+  } else {
+    split2(a, ha, la);
+    split2(b, hb, lb);
+  }
 }
 
 // Power of two s with m s in [2^14, 2^15) (clamped to normal floats), and 1/s.
@@ -392,84 +416,114 @@ struct FftM {
     }
   }
 
+  // twiddles and (FP16) scale of group c's inputs, then the hi / lo operands
+  template <int I, class V>
+  __device__ static __forceinline__ void operands(float2 (&v)[E], int c, int tid, const float2* __restrict__ tw,
+                                                  V& bh, V& bl, float& inv) {
+    constexpr int R = kM.r[I], NS = ns<I>(), PER = per<I>();
+    const int g = (tid & 63) >> 4;
+    float2* x = v + c * PER;
+    if constexpr (NS > 1) {
+      int ln = 0, j = 0;
+      which<I>(tid, c, ln, j);
+      // the lane's PER powers, consecutive in the lane table behind the
+      // length-L table (see mfma_lane_twiddle_offset)
+      const unsigned m = (unsigned)j % (unsigned)NS;
+      const float4* lt = reinterpret_cast<const float4*>(
+          tw + L + mfma_lane_twiddle_offset(L, I) + (m * 4u + (unsigned)g) * PER);
+      float2 w[PER];
+#pragma unroll
+      for (int q = 0; q < PER / 2; ++q) {
+        const float4 t4 = lt[q];
+        w[2 * q] = make_float2(t4.x, t4.y);
+        w[2 * q + 1] = make_float2(t4.z, t4.w);
+      }
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        if (INV) w[i].y = -w[i].y;
+        x[i] = c_mul(x[i], w[i]);
+      }
+    }
+    float sc = 1.f;
+    inv = 1.f;
+    if constexpr (H::kScaled) {
+      float mx = 0.f;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) mx = fmaxf(mx, fmaxf(fabsf(x[i].x), fabsf(x[i].y)));
+      mx = fmaxf(mx, __shfl_xor(mx, 16));
+      mx = fmaxf(mx, __shfl_xor(mx, 32));
+      fp16_scale(mx, sc, inv);
+    }
+    static_assert(R == 16 || R == 8, "radix 16 or 8");
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      T ha, hb, la, lb;
+      split2_pair(x[i].x * sc, x[i].y * sc, ha, hb, la, lb);
+      bh[2 * i] = ha;
+      bh[2 * i + 1] = hb;
+      bl[2 * i] = la;
+      bl[2 * i + 1] = lb;
+    }
+  }
+
+  // NG groups at a time: their operands first, then their products issued
+  // interleaved, so that 2 NG (radix 16: real and imaginary rows) or NG
+  // (radix 8) independent accumulation chains cover each other's latency
+  // (every chain still accumulates lo.hi, hi.lo, hi.hi in that order)
   template <int I>
   __device__ static __forceinline__ void compute(float2 (&v)[E], const Coef& A, const float2* __restrict__ tw) {
-    constexpr int R = kM.r[I], NS = ns<I>(), PER = per<I>();
+    constexpr int R = kM.r[I], PER = per<I>(), G = groups<I>();
+    constexpr int NG = R == 16 ? 2 : 4;
+    static_assert(G % NG == 0, "whole group sets");
     const int tid = opaque();
-    const int g = (tid & 63) >> 4;
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int c = 0; c < groups<I>(); ++c) {
-      float2* x = v + c * PER;
-      if constexpr (NS > 1) {
-        int ln = 0, j = 0;
-        which<I>(tid, c, ln, j);
-        // the lane's PER powers, consecutive in the lane table behind the
-        // length-L table (see mfma_lane_twiddle_offset)
-        const unsigned m = (unsigned)j % (unsigned)NS;
-        const float4* lt = reinterpret_cast<const float4*>(
-            tw + L + mfma_lane_twiddle_offset(L, I) + (m * 4u + (unsigned)g) * PER);
-        float2 w[PER];
-#pragma unroll
-        for (int q = 0; q < PER / 2; ++q) {
-          const float4 t4 = lt[q];
-          w[2 * q] = make_float2(t4.x, t4.y);
-          w[2 * q + 1] = make_float2(t4.z, t4.w);
-        }
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-          if (INV) w[i].y = -w[i].y;
-          x[i] = c_mul(x[i], w[i]);
-        }
-      }
-      float sc = 1.f, inv = 1.f;
-      if constexpr (H::kScaled) {
-        float m = 0.f;
-#pragma unroll
-        for (int i = 0; i < PER; ++i) m = fmaxf(m, fmaxf(fabsf(x[i].x), fabsf(x[i].y)));
-        m = fmaxf(m, __shfl_xor(m, 16));
-        m = fmaxf(m, __shfl_xor(m, 32));
-        fp16_scale(m, sc, inv);
-      }
+    for (int c0 = 0; c0 < G; c0 += NG) {
       if constexpr (R == 16) {
-        typename H::V8 bh, bl;
+        typename H::V8 bh[NG], bl[NG];
+        float inv[NG];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          T h, l;
-          split2(x[i].x * sc, h, l);
-          bh[2 * i] = h;
-          bl[2 * i] = l;
-          split2(x[i].y * sc, h, l);
-          bh[2 * i + 1] = h;
-          bl[2 * i + 1] = l;
+        for (int k = 0; k < NG; ++k) operands<I>(v, c0 + k, tid, tw, bh[k], bl[k], inv[k]);
+        f32x4 yr[NG], yi[NG];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+          yr[k] = H::mma16(A.re_lo, bh[k], z);
+          yi[k] = H::mma16(A.im_lo, bh[k], z);
         }
-        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-        f32x4 yr = H::mma16(A.re_lo, bh, z);
-        yr = H::mma16(A.re_hi, bl, yr);
-        yr = H::mma16(A.re_hi, bh, yr);
-        f32x4 yi = H::mma16(A.im_lo, bh, z);
-        yi = H::mma16(A.im_hi, bl, yi);
-        yi = H::mma16(A.im_hi, bh, yi);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) x[i] = make_float2(yr[i] * inv, yi[i] * inv);
+        for (int k = 0; k < NG; ++k) {
+          yr[k] = H::mma16(A.re_hi, bl[k], yr[k]);
+          yi[k] = H::mma16(A.im_hi, bl[k], yi[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+          yr[k] = H::mma16(A.re_hi, bh[k], yr[k]);
+          yi[k] = H::mma16(A.im_hi, bh[k], yi[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+          float2* x = v + (c0 + k) * PER;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) x[i] = make_float2(yr[k][i] * inv[k], yi[k][i] * inv[k]);
+        }
       } else {
-        static_assert(R == 8, "radix 16 or 8");
-        typename H::V4 bh, bl;
+        typename H::V4 bh[NG], bl[NG];
+        float inv[NG];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          T h, l;
-          split2(x[i].x * sc, h, l);
-          bh[2 * i] = h;
-          bl[2 * i] = l;
-          split2(x[i].y * sc, h, l);
-          bh[2 * i + 1] = h;
-          bl[2 * i + 1] = l;
+        for (int k = 0; k < NG; ++k) operands<I>(v, c0 + k, tid, tw, bh[k], bl[k], inv[k]);
+        f32x4 y[NG];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) y[k] = H::mma8(A.r8_lo, bh[k], z);
+#pragma unroll
+        for (int k = 0; k < NG; ++k) y[k] = H::mma8(A.r8_hi, bl[k], y[k]);
+#pragma unroll
+        for (int k = 0; k < NG; ++k) y[k] = H::mma8(A.r8_hi, bh[k], y[k]);
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+          float2* x = v + (c0 + k) * PER;
+          x[0] = make_float2(y[k][0] * inv[k], y[k][1] * inv[k]);
+          x[1] = make_float2(y[k][2] * inv[k], y[k][3] * inv[k]);
         }
-        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-        f32x4 y = H::mma8(A.r8_lo, bh, z);
-        y = H::mma8(A.r8_hi, bl, y);
-        y = H::mma8(A.r8_hi, bh, y);
-        x[0] = make_float2(y[0] * inv, y[1] * inv);
-        x[1] = make_float2(y[2] * inv, y[3] * inv);
       }
     }
   }

@@ -626,25 +626,66 @@ __device__ __forceinline__ void c2r_tile(const float2* __restrict__ in, float* _
       const int ntid = Eng::opaque();
       int ln0, idx0;
       Eng::native_out(ntid, 0, ln0, idx0);
-#pragma unroll
-      for (int s2 = 0; s2 < E; ++s2) {
+      // byte offset of slot s2's output (the first of its two values), and
+      // whether the slot stores at all
+      auto where = [&](int s2, int& o, bool& st) {
         int ln, idx;
         native_slot<Eng, true>(ntid, s2, ln0, idx0, ln, idx);
         const int pgs = tile * LINES + ln, r = idx - r0;
-        if (pgs >= npairs) continue;
-        float a = scale * v[0][s2].x, bb = scale * v[0][s2].y;
         if constexpr (TRANS) {
-          if (r < 0 || r >= nout) continue;
-          const int o = (2 * pgs * nout + r) * 4;
-          if constexpr (ACCUM) { a += dst.ld1(o); bb += dst.ld1(o + nout * 4); }
+          o = (2 * pgs * nout + r) * 4;
+          st = pgs < npairs && r >= 0 && r < nout;
+        } else {
+          o = (r * nlines + 2 * pgs) * 4;   // rows outside [0, nout) fall outside the buffer
+          st = pgs < npairs;
+        }
+      };
+      auto put = [&](int s2, float2 old) {
+        int o;
+        bool st;
+        where(s2, o, st);
+        if (!st) return;
+        float a = scale * v[0][s2].x, bb = scale * v[0][s2].y;
+        if constexpr (ACCUM) {
+          a += old.x;
+          bb += old.y;
+        }
+        if constexpr (TRANS) {
           dst.st1(a, o);
           dst.st1(bb, o + nout * 4);
         } else {
-          // rows outside [0, nout) fall outside the buffer (read 0, store dropped)
-          const int o = (r * nlines + 2 * pgs) * 4;
-          if constexpr (ACCUM) { const float2 old = dst.ld2(o); a += old.x; bb += old.y; }
           dst.st2(make_float2(a, bb), o);
         }
+      };
+      if constexpr (ACCUM) {
+        // read-modify-write CH slots at a time, the next CH slots' old values
+        // read before this chunk's stores so that they are in flight together
+        // (every slot is a different output, so the reordering is safe)
+        constexpr int CH = 4;
+        static_assert(E % CH == 0, "whole chunks");
+        auto fetch = [&](int c, float2 (&o2)[CH]) {
+#pragma unroll
+          for (int k = 0; k < CH; ++k) {
+            int o;
+            bool st;
+            where(c * CH + k, o, st);
+            if constexpr (TRANS) o2[k] = st ? make_float2(dst.ld1(o), dst.ld1(o + nout * 4)) : make_float2(0.f, 0.f);
+            else o2[k] = st ? dst.ld2(o) : make_float2(0.f, 0.f);
+          }
+        };
+        float2 cur[CH], nxt[CH];
+        fetch(0, cur);
+#pragma unroll
+        for (int c = 0; c < E / CH; ++c) {
+          if (c + 1 < E / CH) fetch(c + 1, nxt);
+#pragma unroll
+          for (int k = 0; k < CH; ++k) put(c * CH + k, cur[k]);
+#pragma unroll
+          for (int k = 0; k < CH; ++k) cur[k] = nxt[k];
+        }
+      } else {
+#pragma unroll
+        for (int s2 = 0; s2 < E; ++s2) put(s2, make_float2(0.f, 0.f));
       }
       continue;
     } else {
