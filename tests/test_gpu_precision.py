@@ -195,3 +195,54 @@ def test_precision_workload_2048(prec):
             f"adjoint {e_d:.2e} (bound {bg:.2e})")
         assert e_r <= bp[0] and e_i <= bp[1] and e_d <= bg
         decided += check_peaks(got, b, (gr, gi), (pr, pi), w["mask"], bp)
+
+
+# ---------------------------------------------------------------- every tile variant
+
+@pytest.mark.parametrize("prec", PRECS, ids=[NAMES[p] for p in PRECS])
+@pytest.mark.parametrize("N,M", [
+    (256, 256),     # Np 512 = 8*8*8, rows 256
+    (512, 512),     # Np 1024 = 16*8*8, rows 512
+    (1024, 1024),   # Np 2048 = 16*16*8, rows 1024 = 16*8*8
+    (2048, 2048),   # Np 4096 = 16*16*16, rows 2048: the 8 x 2048^2 workload's lengths
+])
+def test_every_split_variant_matches_oracle(prec, N, M):
+    """Every tile variant a split-precision plan can run (the autotuner may
+    pick any), launch by launch, against the oracle within the derived
+    bounds: the matrix-core engine loads and stores in its own lane layout in
+    every one of them, with per-shape compile-time address checks."""
+    import torch
+    B = 1
+    img = synth.mixed_lines(N, M, (3, 6), 0.1, np.random.default_rng([43, N, M]))
+    x = torch.from_numpy(img.image[None].copy()).cuda()
+    plan = F.FunnelPlan(B, N, M, 0, F.FT_SPACE_BOTH, prec)
+    Np = plan.Np
+    g = torch.Generator(device="cpu").manual_seed(N + 11)
+    dP = torch.randn((B, plan.plane_elems), generator=g, dtype=torch.float32)
+    ref = O.forward(img.image.astype(np.float64), Np)
+    refD = oracle_adjoint(dP[0].numpy(), N, M, Np, F.FT_SPACE_BOTH)
+    bp, bg = derived_bounds(prec, img.image, Np, F.FT_SPACE_BOTH)
+    dPc = dP.cuda()
+    defaults = F.funnel_plan_variants(plan.handle)
+    covered = 0
+    for v in range(F.MAX_VARIANTS):
+        roles = []
+        for r in range(12):
+            try:
+                F.funnel_plan_set_variant(plan.handle, r, v)
+                roles.append(r)
+            except F.FunnelError:
+                F.funnel_plan_set_variant(plan.handle, r, defaults[r])
+        if not roles:
+            continue
+        planes = plan.forward(x)
+        dI = plan.adjoint(dPc)
+        torch.cuda.synchronize()
+        P, G = planes.cpu().numpy(), dI.cpu().numpy()
+        errs = [rel_l2(got, exp) for got, exp in zip(split_planes(P[0], N, M, Np, F.FT_SPACE_BOTH), ref)]
+        eg = rel_l2(G[0], refD)
+        say(f"  {NAMES[prec]} {N}x{M} variant {v}: roles {roles} planes {['%.2e' % e for e in errs]} "
+            f"(bounds {['%.2e' % b for b in bp]}) gradient {eg:.2e} (bound {bg:.2e})")
+        assert all(e <= b for e, b in zip(errs, bp)) and eg <= bg, (v, roles)
+        covered += len(roles)
+    assert covered >= 12
