@@ -156,9 +156,11 @@ def main():
     variants = F.funnel_plan_variants(plan.handle)
     traffic = measured_traffic(dom["name"], variants[ROLES_2D.index(dom["name"])], nvmt)
 
-    cpu = None
+    cpu = cpu_fft = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(imgs, dP, plan, N, M, args.cpu_seconds, nvmt)
+        if nvmt == "linear":
+            cpu_fft = cpu_fft_reference(imgs, dP, N, M, Np, 5.0)
 
     out = {
         "metric": ("Mpixel/s funnel fwd+adjoint, 1024^2 fp32 batch; % of HBM roofline" if nvmt == "linear" else
@@ -200,6 +202,7 @@ def main():
         "kernels": [{"name": k["name"], "avg_ms": round(k["avg_ms"], 4),
                      "bytes": k["bytes_per_launch"], "gbps": round(k["gbps"], 1)} for k in kernels],
         "cpu_baseline": cpu,
+        "cpu_fft_reference": cpu_fft,
         "tile_variants": variants,
         "autotuned": tuned is not None,
         "variants_from": variants_from,
@@ -685,6 +688,112 @@ def cpu_baseline(imgs, dP, plan, N, M, seconds, nvmt="linear"):
     dt = time.time() - t0
     return {"value": round(n * N * M / dt / 1e6, 4), "unit": "Mpixel/s", "cores": int(cores), "kind": "oracle",
             "sample": f"{n} of the {plan.batch} {N}x{M} images, forward both spaces + adjoint, {dt:.1f} s"}
+
+
+# ------------------------------------------------------------------ FFT-based CPU reference
+#
+# The same transform as the oracle (linear NVMT), with the three DFTs of each
+# space done by FFTs instead of explicit matrices, FP64: a fair CPU throughput
+# figure beside the GPU's (the oracle's dense DFTs cost O(L) per element).
+# Context only: it is not the oracle, and nothing but this benchmark's report
+# uses it; tests/test_cpu_fft_reference.py pins it to the oracle.
+
+def _fft_space_forward(img, Np, fft):
+    """Parameter plane P[Np, W] of the regular space of img [H, W]: the y DFT
+    of the expanded frame, the NVMT by linear interpolation, the x' DFT and
+    the Hermitian inverse y DFT, with centred coordinates folded into signs
+    (exp(-j 2 pi n y / L) over y = r - L/2 is (-1)^n times the FFT)."""
+    H, W = img.shape
+    h, top = Np // 2 - 1, (Np - H) // 2
+    pad = np.zeros((Np, W))
+    pad[top:top + H] = img
+    n2 = np.arange(1, h + 1)
+    sg = np.where(n2 % 2 == 1, -1.0, 1.0)[:, None]
+    S = fft.fft(pad, axis=0)[1:h + 1] * sg
+    # NVMT: g[n2, x'] = (1 - t) f[i0] + t f[i0 + 1], i0 = floor((x' Np + W n2) / (2 n2))
+    xp = np.arange(W, dtype=np.int64) - W // 2
+    num = xp[None, :] * Np + W * n2[:, None]
+    den = 2 * n2[:, None]
+    i0 = num // den
+    t = (num - i0 * den) / den
+    rows = np.arange(h)[:, None]
+    f0 = np.where((i0 >= 0) & (i0 < W), S[rows, np.clip(i0, 0, W - 1)], 0.0)
+    f1 = np.where((i0 + 1 >= 0) & (i0 + 1 < W), S[rows, np.clip(i0 + 1, 0, W - 1)], 0.0)
+    g = (1.0 - t) * f0 + t * f1
+    # x' DFT over centred x' and m1: G[p] = (-1)^(p + W/2) FFT(g (-1)^q)[p]
+    alt = np.where(np.arange(W) % 2 == 1, -1.0, 1.0)
+    G = fft.fft(g * alt[None, :], axis=1) * (alt * (-1.0) ** (W // 2))[None, :]
+    # P[r, m1] = (2 / Np) Re sum_n2 G[n2] (-1)^n2 exp(+j 2 pi n2 r / Np)
+    X = np.zeros((Np, W), dtype=np.complex128)
+    X[1:h + 1] = G * sg
+    return 2.0 * fft.ifft(X, axis=0).real
+
+
+def _fft_space_adjoint(dP, H, W, Np, fft):
+    """Transpose of _fft_space_forward: dI [H, W] from dP [Np, W]."""
+    h, top = Np // 2 - 1, (Np - H) // 2
+    n2 = np.arange(1, h + 1)
+    sg = np.where(n2 % 2 == 1, -1.0, 1.0)[:, None]
+    dG = (2.0 / Np) * fft.fft(dP, axis=0)[1:h + 1] * sg
+    # conjugate-transposed x' DFT: dg[q] = (-1)^(q + W/2) W IFFT(dG (-1)^p)[q]
+    alt = np.where(np.arange(W) % 2 == 1, -1.0, 1.0)
+    dg = W * fft.ifft(dG * alt[None, :], axis=1) * (alt * (-1.0) ** (W // 2))[None, :]
+    # transposed interpolation: dS[i0] += (1 - t) dg, dS[i0 + 1] += t dg
+    xp = np.arange(W, dtype=np.int64) - W // 2
+    num = xp[None, :] * Np + W * n2[:, None]
+    den = 2 * n2[:, None]
+    i0 = num // den
+    t = (num - i0 * den) / den
+    rows = np.broadcast_to(np.arange(h)[:, None], i0.shape)
+    dS = np.zeros((h, W), dtype=np.complex128)
+    for idx, wgt in ((i0, 1.0 - t), (i0 + 1, t)):
+        ok = (idx >= 0) & (idx < W)
+        np.add.at(dS, (rows[ok], idx[ok]), wgt[ok] * dg[ok])
+    X = np.zeros((Np, W), dtype=np.complex128)
+    X[1:h + 1] = dS * sg
+    return (Np * fft.ifft(X, axis=0).real)[top:top + H]
+
+
+def fft_reference_forward(img, Np, fft=np.fft):
+    """(regular plane [Np, M], inverse plane [Np, N]) of one image."""
+    img = np.asarray(img, dtype=np.float64)
+    return _fft_space_forward(img, Np, fft), _fft_space_forward(img.T, Np, fft)
+
+
+def fft_reference_adjoint(dP_reg, dP_inv, N, M, Np, fft=np.fft):
+    """Image gradient [N, M] of both spaces."""
+    return _fft_space_adjoint(dP_reg, N, M, Np, fft) + _fft_space_adjoint(dP_inv, M, N, Np, fft).T
+
+
+def cpu_fft_reference(imgs, dP, N, M, Np, seconds):
+    """Throughput of the FFT-based reference (scipy.fft on every core the
+    process may use, else numpy's single-threaded FFT) on whole images of the
+    workload, forward both spaces + adjoint, until `seconds` have passed."""
+    try:
+        import functools
+
+        import scipy.fft as sfft
+        cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+        class _F:   # scipy.fft with all workers, the numpy.fft call signature
+            fft = staticmethod(functools.partial(sfft.fft, workers=cores))
+            ifft = staticmethod(functools.partial(sfft.ifft, workers=cores))
+        fft, kind = _F, "scipy.fft FP64"
+    except Exception:
+        fft, kind, cores = np.fft, "numpy.fft FP64", 1
+    dPh = dP.cpu().numpy()
+    t0, n = time.time(), 0
+    for b, im in enumerate(imgs):
+        fft_reference_forward(im.image, Np, fft)
+        fft_reference_adjoint(dPh[b, : Np * M].reshape(Np, M).astype(np.float64),
+                              dPh[b, Np * M:].reshape(Np, N).astype(np.float64), N, M, Np, fft)
+        n += 1
+        if time.time() - t0 >= seconds:
+            break
+    dt = time.time() - t0
+    return {"value": round(n * N * M / dt / 1e6, 4), "unit": "Mpixel/s", "cores": int(cores),
+            "kind": f"FFT-based CPU reference ({kind}), context", 
+            "sample": f"{n} of the {len(imgs)} {N}x{M} images, forward both spaces + adjoint, {dt:.1f} s"}
 
 
 if __name__ == "__main__":
