@@ -573,6 +573,16 @@ class FunnelPlan:
         funnel_peaks(self.handle, planes, K, threshold, radius, flags, rec, cnt, ws, stream)
         return rec, cnt
 
+    def peaks_noalloc(self, planes, rec, cnt, threshold: float = 0.0, radius: int = 1, flags: int = 0,
+                      stream=None) -> None:
+        """peaks() into caller-provided records rec int32 [B, nspaces, K, 7]
+        and counts cnt int32 [B, nspaces], with the library's static scratch
+        instead of a workspace: nothing is allocated (funnel_peaks_noalloc;
+        calls that overlap on one GPU share the scratch and must not)."""
+        self._check_planes(planes)
+        self._check_peaks(rec, cnt)
+        funnel_peaks_noalloc(self.handle, planes, rec.shape[2], threshold, radius, flags, rec, cnt, stream)
+
     def verify(self, images, rec, cnt, half_width: int = 3, min_contrast: float = 0.1, min_length: int = 32,
                stream=None):
         """Sec. 4.5 line verification of peak lists from peaks(): returns the

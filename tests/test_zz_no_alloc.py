@@ -51,6 +51,13 @@ def test_noalloc_matches_workspace_call(first, second):
             for s in range(plan.nspaces):
                 n = int(cnt[b, s])
                 assert torch.equal(rec[b, s, :n], want_rec[b, s, :n]), (call, b, s)
+        # the binding's method (checks the buffers, then the same C call)
+        rec2, cnt2 = torch.full_like(want_rec, -7), torch.full_like(want_cnt, -7)
+        plan.peaks_noalloc(planes, rec2, cnt2, threshold=thr, radius=radius, flags=flags)
+        torch.cuda.synchronize()
+        assert torch.equal(cnt2, cnt) and torch.equal(rec2, rec)
+        with pytest.raises(ValueError):
+            plan.peaks_noalloc(planes, rec2[:, :, :, :3], cnt2)
 
 
 def test_noalloc_rejects_beyond_scratch():
