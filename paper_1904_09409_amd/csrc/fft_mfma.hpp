@@ -190,18 +190,19 @@ struct FftM {
   template <int I>
   static constexpr int groups() { return E / per<I>(); }
 
-  // butterfly id of group c for this lane -> (line, j)
-  // tid: the thread index, passed through an empty asm after each barrier
-  // (opaque()), so that slot addresses are computed where they are used and
-  // not hoisted to the kernel's start and kept live across the passes
+  // The thread index, passed through an empty asm after each barrier, so
+  // that slot addresses are computed where they are used and not hoisted to
+  // the kernel's start and kept live across the passes.
   __device__ static __forceinline__ int opaque() {
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
     return t & 1023;   // (blocks hold at most 1024 threads: known range for the index algebra)
   }
+
+  // butterfly id of group c for thread tid -> (line, j).  Unsigned
+  // arithmetic: the divisions by powers of two are plain shifts; constexpr,
+  // so that the layout checks below can evaluate it.
   template <int I>
-  // (unsigned arithmetic: the divisions by powers of two are plain shifts;
-  // constexpr, so that the layout checks below can evaluate them)
   static constexpr void which(int tid, int c, int& line, int& j) {
     constexpr unsigned NB = L / kM.r[I];
     const unsigned ut = (unsigned)tid;

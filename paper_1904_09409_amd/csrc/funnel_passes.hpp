@@ -470,35 +470,35 @@ __device__ __forceinline__ void r2c_tile(const float* __restrict__ in, float2* _
     }
   } else {
 #pragma unroll
-  for (int g = 0; g < NT; ++g) {
-    const int pg = (tile * NT + g) * LINES + pair;
-    const bool active = pg < npairs;
-    if constexpr (TRANS) {
-      // line 2pg and 2pg+1 of the image rows; rows outside [0, lin) are zero
-      const int o0 = (2 * pg * lin + t - off) * 4;
+    for (int g = 0; g < NT; ++g) {
+      const int pg = (tile * NT + g) * LINES + pair;
+      const bool active = pg < npairs;
+      if constexpr (TRANS) {
+        // line 2pg and 2pg+1 of the image rows; rows outside [0, lin) are zero
+        const int o0 = (2 * pg * lin + t - off) * 4;
 #pragma unroll
-      for (int b = 0; b < BPT0; ++b)
+        for (int b = 0; b < BPT0; ++b)
 #pragma unroll
-        for (int r = 0; r < R0; ++r) {
-          const int rr = t + P * b + r * NB0 - off;
-          const int o = o0 + (P * b + r * NB0) * 4;
-          float2 z = make_float2(0.f, 0.f);
-          if (active && Eng::template ok<0, false>(t, b) && (unsigned)rr < (unsigned)lin)
-            z = make_float2(src.ld1(o), src.ld1(o + lin * 4));
-          v[g][b * R0 + r] = z;
-        }
-    } else {
-      // columns 2pg, 2pg+1; rows outside [0, lin) fall outside the buffer and read 0
-      const int o0 = ((t - off) * nlines + 2 * pg) * 4;
-      const int rs = nlines * 4;
+          for (int r = 0; r < R0; ++r) {
+            const int rr = t + P * b + r * NB0 - off;
+            const int o = o0 + (P * b + r * NB0) * 4;
+            float2 z = make_float2(0.f, 0.f);
+            if (active && Eng::template ok<0, false>(t, b) && (unsigned)rr < (unsigned)lin)
+              z = make_float2(src.ld1(o), src.ld1(o + lin * 4));
+            v[g][b * R0 + r] = z;
+          }
+      } else {
+        // columns 2pg, 2pg+1; rows outside [0, lin) fall outside the buffer and read 0
+        const int o0 = ((t - off) * nlines + 2 * pg) * 4;
+        const int rs = nlines * 4;
 #pragma unroll
-      for (int b = 0; b < BPT0; ++b)
+        for (int b = 0; b < BPT0; ++b)
 #pragma unroll
-        for (int r = 0; r < R0; ++r)
-          v[g][b * R0 + r] = Eng::template ok<0, false>(t, b) ? src.ld2(o0 + (P * b + r * NB0) * rs)
-                                                              : make_float2(0.f, 0.f);
+          for (int r = 0; r < R0; ++r)
+            v[g][b * R0 + r] = Eng::template ok<0, false>(t, b) ? src.ld2(o0 + (P * b + r * NB0) * rs)
+                                                                : make_float2(0.f, 0.f);
+      }
     }
-  }
   }
 
   // half-spectrum rows 1 .. H: rows k outside that range fall outside the buffer
