@@ -25,7 +25,10 @@
 //          fewer than K and write them unsorted, with no selection at all.
 //          Blocks deal the planes round-robin, so every plane's tiles are
 //          spread over the whole launch and its cutoff exists after its
-//          first few tiles.
+//          first few tiles.  For radius 1 on planes of 16-byte aligned rows
+//          a second kernel (k_peaks_r1) does the same from registers: one
+//          wave per 16-row band of 256 columns, no LDS staging, no block
+//          barrier; the selection and the lists are the same.
 // Stage 2: a tree of reductions: each block gathers the keys of G lists of
 //          K (G K <= 2048) that precede the final cutoff, sorts them and
 //          keeps the first K, until one list per plane remains
@@ -142,6 +145,90 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
   if (__popcll(holders) == 1) lo = __builtin_amdgcn_readlane(xl, __ffsll((unsigned long long)holders) - 1);
   else lo = wave_min_u32(xh == hi ? xl : 0xffffffffu);
   return ((uint64_t)hi << 32) | lo;
+}
+
+// Stage 1's end, per wave: its candidate keys (NS slots per lane, kNoKey
+// for none) -> its first K keys at dst.  Keys after the cutoff cmax (a value
+// the plane's cutoff `cut` took) go first; the cutoff only decreases and
+// every value it takes is safe, so a stale value merely prunes less.  Fewer
+// than K are written as they are.  Up
+// to 128 keys are packed into the wave's 128 LDS slots `wk` (lanes placed by
+// their rank among the wave's keys) and sorted in registers by the shuffle
+// bitonic network.  Otherwise each lane sorts its slots, then K rounds of a
+// wave-wide minimum over the lanes' first slots; the lane holding the winner
+// (keys are unique: exactly one) shifts its slots down.  The last two
+// publish their K-th key as the plane's cutoff and return it (the others
+// return kNoKey).  All 64 lanes take part.
+template <int NS>
+__device__ __forceinline__ uint64_t wave_first_k(uint64_t (&mine)[NS], uint64_t* wk, int lane, int K, uint64_t cmax,
+                                                 uint64_t* cut, uint64_t* __restrict__ dst) {
+#pragma unroll
+  for (int j = 0; j < NS; ++j) mine[j] = mine[j] > cmax ? kNoKey : mine[j];
+  uint64_t bal[NS];
+  int total = 0;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    bal[j] = __ballot(mine[j] != kNoKey);
+    total += (int)__popcll(bal[j]);
+  }
+  if (total < K) {   // uniform over the wave; the reduction sorts
+    int base = 0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal[j] >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal[j], 0u));
+      if (mine[j] != kNoKey) dst[base + rank] = mine[j];
+      base += (int)__popcll(bal[j]);
+    }
+    for (int i = total + lane; i < K; i += 64) dst[i] = kNoKey;
+    return kNoKey;
+  }
+  if (total <= 128) {   // uniform over the wave; K <= total
+    int base = 0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal[j] >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal[j], 0u));
+      if (mine[j] != kNoKey) wk[base + rank] = mine[j];
+      base += (int)__popcll(bal[j]);
+    }
+    // the wave's LDS writes complete before its lanes read each other's
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint64_t a = lane < total ? wk[lane] : kNoKey;
+    uint64_t b = lane + 64 < total ? wk[lane + 64] : kNoKey;
+    wave_sort128(a, b, lane);
+    if (lane < K) dst[lane] = a;
+    if (lane + 64 < K) dst[lane + 64] = b;
+    const uint64_t src = K <= 64 ? a : b;   // the K-th key sits in lane (K - 1) mod 64
+    const int kl = (K - 1) & 63;
+    const uint64_t kth = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(src >> 32), kl) << 32) |
+                         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)src, kl);
+    if (lane == 0) atomicMin(reinterpret_cast<unsigned long long*>(cut), (unsigned long long)kth);
+    return kth;
+  }
+#pragma unroll
+  for (int a = 0; a < NS - 1; ++a)
+#pragma unroll
+    for (int b = 0; b < NS - 1 - a; ++b) {
+      const uint64_t x = mine[b], y = mine[b + 1];
+      mine[b] = x < y ? x : y;
+      mine[b + 1] = x < y ? y : x;
+    }
+  uint64_t last = kNoKey;
+  for (int k = 0; k < K; ++k) {   // total > 128 and total >= K: every round finds a key
+    const uint64_t m = wave_min_u64(mine[0]);
+    if (lane == 0) dst[k] = m;
+    last = m;
+    if (mine[0] == m) {
+#pragma unroll
+      for (int j = 0; j < NS - 1; ++j) mine[j] = mine[j + 1];
+      mine[NS - 1] = kNoKey;
+    }
+  }
+  if (lane == 0) atomicMin(reinterpret_cast<unsigned long long*>(cut), (unsigned long long)last);
+  return last;
 }
 
 // RADIUS is the neighbourhood radius (1..8), a template parameter so that the
@@ -350,87 +437,271 @@ __global__ void __launch_bounds__(kPeakThreads, 8)
       if (won & (1u << lr)) mine[lr / 2] = cell_key(val[(lr + radius) * kHaloC + kPadL + lc], (r0 + lr) * g.cols + c);
   }
 
-  // keys after the plane's cutoff go first.  The cutoff only decreases and
-  // every value it takes is safe, so a stale read merely prunes less.
-  const uint64_t cmax = __hip_atomic_load(cut + plane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-  for (int j = 0; j < NS; ++j) mine[j] = mine[j] > cmax ? kNoKey : mine[j];
-
-  // the wave's first K keys.  Fewer than K are written as they are.  Up to
-  // 128 keys are packed into the wave's own LDS slots (lanes placed by their
-  // rank among the wave's keys) and sorted in registers by the shuffle
-  // bitonic network.  Otherwise each lane sorts its slots, then K rounds of
-  // a wave-wide minimum over the lanes' first slots; the lane holding the
-  // winner (keys are unique: exactly one) shifts its slots down.  The last
-  // two publish their K-th key.
   // the sort slots reuse the tile's LDS once every wave has read it
   __syncthreads();
-  uint64_t(*wkeys)[128] = reinterpret_cast<uint64_t(*)[128]>(val);
   static_assert(sizeof(uint64_t) * NW * 128 <= sizeof(val), "sort slots exceed the tile's LDS");
-  uint64_t bal[NS];
-  int total = 0;
-#pragma unroll
-  for (int j = 0; j < NS; ++j) {
-    bal[j] = __ballot(mine[j] != kNoKey);
-    total += (int)__popcll(bal[j]);
-  }
-  if (total < K) {   // uniform over the wave; the reduction sorts
-    int base = 0;
-#pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal[j] >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal[j], 0u));
-      if (mine[j] != kNoKey) dst[base + rank] = mine[j];
-      base += (int)__popcll(bal[j]);
+  wave_first_k(mine, reinterpret_cast<uint64_t*>(val) + wave * 128, lane, K,
+               __hip_atomic_load(cut + plane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), cut + plane, dst);
+}
+
+// ---- radius 1: stage 1 from registers
+//
+// For the default neighbourhood (radius 1) a wave classifies a band of 16
+// rows x 256 columns without staging it in LDS: each lane loads its 4
+// adjacent columns of the band's 18 rows (one halo row above and below) as
+// 16-byte loads, all in flight at once, and one cell of the left (lanes
+// 0-17) or right (lanes 32-49) halo column; the neighbours across lanes come
+// from DPP wave shifts, into which the halo columns enter at lanes 0 and 63.
+// The four waves of a block take four bands stacked down the plane (a 64 x
+// 256 tile) and never wait for each other.  Two cells of a 2 x 2 block are
+// neighbours, so at most one of them is a maximum: each lane keeps one key
+// slot per 2 x 2 block of its 16 x 4 cells, 16 slots at static register
+// indices.  The cutoff read at the start joins the threshold, so a key
+// after it is never taken; cells equal to their neighbourhood maximum or to
+// that bound (rare) are decided from global memory afterwards, by the
+// order's index tie-break and the exact cutoff key.  Wrapping reaches every
+// neighbour in one step for planes of at least 32 rows and 128 columns, and
+// the 16-byte loads need planes whose rows, plane offsets and base are
+// multiples of 4 floats; the launch takes this kernel only for those.
+constexpr int kR1Band = 16;                                // rows per wave
+constexpr int kR1TileR = kR1Band * (kPeakThreads / 64);    // rows per block
+constexpr int kR1TileC = 256;                              // 4 columns per lane
+
+int peaks_r1_tiles(int rows, int cols) {
+  return ((rows + kR1TileR - 1) / kR1TileR) * ((cols + kR1TileC - 1) / kR1TileC);
+}
+
+// The bits of |q| as an int (>= 0, ordered as the floats), or -1 for an
+// absent cell or a NaN (bits above infinity's): such a cell never blocks a
+// neighbour and is never a peak, as under float comparisons.  The presence
+// test selects a limit rather than the loaded value: a select between a
+// load and a constant becomes a branch around the load and a wait for it.
+__device__ __forceinline__ int cell_bits(float q, bool present) {
+  const uint32_t b = __float_as_uint(q) & 0x7fffffffu;
+  const int lim = present ? 0x7f800000 : -1;
+  return (int)b <= lim ? (int)b : -1;
+}
+
+// lane i receives x of lane i - 1 (wave_shr:1); lane 0 receives `edge`
+__device__ __forceinline__ int from_prev_lane(int edge, int x) {
+  return __builtin_amdgcn_update_dpp(edge, x, 0x138, 0xF, 0xF, false);
+}
+// lane i receives x of lane i + 1 (wave_shl:1); lane 63 receives `edge`
+__device__ __forceinline__ int from_next_lane(int edge, int x) {
+  return __builtin_amdgcn_update_dpp(edge, x, 0x130, 0xF, 0xF, false);
+}
+
+// A plane coordinate one step outside [0, n) wrapped back (wrap) or marked
+// absent (!in); one step suffices for |excess| < n.
+__device__ __forceinline__ int wrap1(int c, int n, int wrap, bool& in) {
+  const bool lo = c < 0, hi = c >= n;
+  in = in && (wrap || !(lo || hi));
+  return lo ? c + n : (hi ? c - n : c);
+}
+
+// The exact radius-1 verdict on cell (r, c) of plane P (inside it): at or
+// above the threshold, not after the cutoff key, and preceding each of its 8
+// neighbours (present ones: wrapped, or none beyond a clamped border) in the
+// order |P| descending, linear index ascending.
+__device__ bool r1_exact_peak(const float* __restrict__ P, int rows, int cols, int r, int c, int wrap,
+                              float thr_below, uint64_t cmax) {
+  const uint32_t idx = (uint32_t)(r * cols + c);
+  const float v = fabsf(P[idx]);
+  if (!(v > thr_below) || cell_key(v, (int)idx) > cmax) return false;
+  for (int dr = -1; dr <= 1; ++dr)
+    for (int dc = -1; dc <= 1; ++dc) {
+      if (dr == 0 && dc == 0) continue;
+      bool in = true;
+      const int rr = wrap1(r + dr, rows, wrap, in), cc = wrap1(c + dc, cols, wrap, in);
+      if (!in) continue;
+      const uint32_t j = (uint32_t)(rr * cols + cc);
+      const float u = fabsf(P[j]);
+      if (u > v || (u == v && j < idx)) return false;
     }
-    for (int i = total + lane; i < K; i += 64) dst[i] = kNoKey;
+  return true;
+}
+
+__global__ void __launch_bounds__(kPeakThreads, 4)
+    k_peaks_r1(const float* __restrict__ planes, ImgMap map, PlaneGeom g0, PlaneGeom g1, int nspaces, int nplanes,
+               int tiles, int K, float thr_below, int wrap, int keep_border, uint64_t* __restrict__ cut,
+               uint64_t* __restrict__ out) {
+  constexpr int NW = kPeakThreads / 64, HR = kR1Band + 2, NS = kR1Band / 2 * 2;
+  __shared__ uint64_t wkeys[NW][128];   // the register sort's staging
+  const int plane = blockIdx.x % nplanes;   // planes dealt round-robin
+  const int img = plane / nspaces, sp = plane % nspaces;
+  const PlaneGeom g = sp == 0 ? g0 : g1;
+  const int rows = g.rows, cols = g.cols;
+  const float* P = planes + map.out(img) + g.offset;
+  const int tcn = (cols + kR1TileC - 1) / kR1TileC;
+  const int ntile = tcn * ((rows + kR1TileR - 1) / kR1TileR);
+  const int tile = blockIdx.x / nplanes;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint64_t* dst = out + (((long long)plane * tiles + tile) * NW + wave) * K;
+  const int r0 = (tile / tcn) * kR1TileR + wave * kR1Band, c0 = (tile % tcn) * kR1TileC;
+  if (tile >= ntile || r0 >= rows) {   // the other space's plane has more tiles, or a band past the last row
+    for (int i = lane; i < K; i += 64) dst[i] = kNoKey;
     return;
   }
-  if (total <= 128) {   // uniform over the wave; K <= total
-    int base = 0;
-#pragma unroll
-    for (int j = 0; j < NS; ++j) {
-      const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal[j] >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal[j], 0u));
-      if (mine[j] != kNoKey) wkeys[wave][base + rank] = mine[j];
-      base += (int)__popcll(bal[j]);
-    }
-    // the wave's LDS writes complete before its lanes read each other's
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    uint64_t a = lane < total ? wkeys[wave][lane] : kNoKey;
-    uint64_t b = lane + 64 < total ? wkeys[wave][lane + 64] : kNoKey;
-    wave_sort128(a, b, lane);
-    if (lane < K) dst[lane] = a;
-    if (lane + 64 < K) dst[lane + 64] = b;
-    const uint64_t src = K <= 64 ? a : b;   // the K-th key sits in lane (K - 1) mod 64
-    const int kl = (K - 1) & 63;
-    const uint64_t kth = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(src >> 32), kl) << 32) |
-                         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)src, kl);
-    if (lane == 0) atomicMin(reinterpret_cast<unsigned long long*>(cut + plane), (unsigned long long)kth);
-    return;
+
+  // the plane's cutoff, read before the cells (loads complete in order)
+  const uint64_t cmax = __hip_atomic_load(cut + plane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // Cells are compared as the bits of |P| (an int order equal to the float
+  // order for |P| >= 0), -1 for an absent cell or a NaN.  Band rows lr = 0
+  // .. 17 are plane rows r0 - 1 + lr, wrapped or absent; the lane's columns
+  // cb .. cb + 3 wrap past the right edge to cb - cols < cols (cols >= 128)
+  // and lie on one side of it (cols is a multiple of 4).  Absent cells read
+  // row r0, column 0.
+  const int cb = c0 + 4 * lane;
+  auto row_ptr = [&](int lr, bool& rin) {   // uniform: SGPRs
+    rin = true;
+    const int rr = wrap1(r0 - 1 + lr, rows, wrap, rin);
+    return P + (long long)(rin ? rr : r0) * cols;
+  };
+  // halo columns c0 - 1 (lanes 0-17, row lane) and c0 + 256 (lanes 32-49,
+  // row lane - 32); c0 + 256 - cols may reach cols once.  Issued first: the
+  // first row needs it.
+  int hal;
+  {
+    const int lr = lane & 31;
+    bool in = lr < HR;
+    int c = lane < 32 ? c0 - 1 : c0 + kR1TileC;
+    c = wrap1(c, cols, wrap, in);
+    c = c >= cols ? c - cols : c;
+    const int rr = wrap1(r0 - 1 + lr, rows, wrap, in);
+    hal = cell_bits(P[(long long)(in ? rr : r0) * cols + (in ? c : 0)], in);
   }
+  float4 raw[HR];
+  bool rowin[HR];
+  bool cin = true;
+  {
+    const int cw = wrap1(cb, cols, wrap, cin);
+    const uint32_t co = cin ? (uint32_t)cw : 0u;   // one 32-bit column offset per lane, for every row
 #pragma unroll
-  for (int a = 0; a < NS - 1; ++a)
-#pragma unroll
-    for (int b = 0; b < NS - 1 - a; ++b) {
-      const uint64_t x = mine[b], y = mine[b + 1];
-      mine[b] = x < y ? x : y;
-      mine[b + 1] = x < y ? y : x;
-    }
-  uint64_t last = kNoKey;
-  for (int k = 0; k < K; ++k) {   // total > 128 and total >= K: every round finds a key
-    const uint64_t m = wave_min_u64(mine[0]);
-    if (lane == 0) dst[k] = m;
-    last = m;
-    if (mine[0] == m) {
-#pragma unroll
-      for (int j = 0; j < NS - 1; ++j) mine[j] = mine[j + 1];
-      mine[NS - 1] = kNoKey;
+    for (int lr = 0; lr < HR; ++lr) {
+      // unconditional loads (an absent cell reads column 0) keep all in flight
+      const float* rp = row_ptr(lr, rowin[lr]);
+      raw[lr] = *reinterpret_cast<const float4*>(rp + co);
     }
   }
-  if (lane == 0) atomicMin(reinterpret_cast<unsigned long long*>(cut + plane), (unsigned long long)last);
+  // row lr as cell bits, converted where it is first used (rows arrive in order)
+  int x[HR][4];
+  auto convert = [&](int lr) {
+    const bool in = rowin[lr] && cin;
+    x[lr][0] = cell_bits(raw[lr].x, in);
+    x[lr][1] = cell_bits(raw[lr].y, in);
+    x[lr][2] = cell_bits(raw[lr].z, in);
+    x[lr][3] = cell_bits(raw[lr].w, in);
+  };
+
+  // a key precedes the cutoff key cmax when |P| exceeds the value part of
+  // cmax: that value joins the threshold (bits; -1 when negative: every
+  // |P| >= 0 passes); cells equal to it go to the exact check below
+  const float thr_w = cmax == kNoKey ? thr_below : fmaxf(thr_below, __uint_as_float(~(uint32_t)(cmax >> 32)));
+  const int thr_i = thr_w < 0.f ? -1 : (int)__float_as_uint(thr_w);
+
+  // which cells may be peaks: rows inside the plane (bit cr of the band),
+  // columns inside it, and not both in a border row band (four centred rows
+  // y = e - 2 .. e + 1 around each image edge e = -+himg/2) and within one
+  // column of the centre column, unless the border is kept.  A cell that may
+  // not be a peak gets the bound INT_MAX, above every |P|.
+  const uint32_t rowok = r0 + kR1Band <= rows ? (1u << kR1Band) - 1 : (1u << (rows - r0)) - 1;
+  auto band4 = [&](int first) -> uint32_t {   // bits of band rows first - r0 .. first - r0 + 3
+    const int o = first - r0;
+    return o <= -4 || o >= kR1Band ? 0u : (o >= 0 ? (0xFu << o) : (0xFu >> -o)) & ((1u << kR1Band) - 1);
+  };
+  const uint32_t bandrows = keep_border ? 0u : (band4(rows / 2 - g.himg / 2 - 2) | band4(rows / 2 + g.himg / 2 - 2));
+  bool colok[4], colband[4];
+  int thc[4], thb[4];   // bound of column j in a plain row, in a border-band row
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    colok[j] = cb + j < cols;
+    const int cc = cb + j - cols / 2;
+    colband[j] = cc >= -1 && cc <= 1;
+    thc[j] = colok[j] ? thr_i : INT_MAX;
+    thb[j] = colok[j] && !colband[j] ? thr_i : INT_MAX;
+  }
+
+  // row maxima: me = the larger horizontal neighbour, mi = with the cell
+  auto rowmax = [&](int lr, int (&me)[4], int (&mi)[4]) {
+    convert(lr);
+    const int left = from_prev_lane(__builtin_amdgcn_readlane(hal, lr), x[lr][3]);
+    const int right = from_next_lane(__builtin_amdgcn_readlane(hal, 32 + lr), x[lr][0]);
+    me[0] = max(left, x[lr][1]);
+    me[1] = max(x[lr][0], x[lr][2]);
+    me[2] = max(x[lr][1], x[lr][3]);
+    me[3] = max(x[lr][2], right);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) mi[j] = max(me[j], x[lr][j]);
+  };
+  int sv[NS];         // slot (cr / 2) * 2 + j / 2: |P| bits of its maximum, -1 for none
+  uint32_t so = 0;    // bits 2k, 2k + 1: the maximum's place in slot k's 2 x 2 block, 2 dr + dc
+#pragma unroll
+  for (int k = 0; k < NS; ++k) sv[k] = -1;
+  int miP[4], meC[4], miC[4], tmp[4];
+  rowmax(0, tmp, miP);
+  rowmax(1, meC, miC);
+  uint32_t tierows = 0;
+#pragma unroll
+  for (int cr = 0; cr < kR1Band; ++cr) {   // cell row cr: plane row r0 + cr, band row cr + 1
+    int meN[4], miN[4];
+    rowmax(cr + 2, meN, miN);
+    const bool rok = (rowok >> cr) & 1u, rband = (bandrows >> cr) & 1u;
+    bool tie = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int v = x[cr + 1][j];
+      const int th = rok ? (rband ? thb[j] : thc[j]) : INT_MAX;
+      const int m = max(max(miP[j], meC[j]), max(miN[j], th));
+      const bool take = v > m;
+      tie |= v == m;
+      const int k = (cr / 2) * 2 + j / 2;
+      sv[k] = take ? v : sv[k];
+      so = take ? (so & ~(3u << 2 * k)) | ((uint32_t)((cr & 1) * 2 + (j & 1)) << 2 * k) : so;
+    }
+    tierows |= tie ? (1u << cr) : 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      miP[j] = miC[j];
+      meC[j] = meN[j];
+      miC[j] = miN[j];
+    }
+    // row by row, in load order: keeps the scheduler from starting on the
+    // last rows (and waiting for every load) first
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (__ballot(tierows != 0)) {   // exact verdicts on the rows with a tie (any lane)
+    uint64_t won = 0;
+    for (uint32_t t = tierows; t; t &= t - 1) {
+      const int cr = __builtin_ctz(t);
+      const bool rband = (bandrows >> cr) & 1u;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (colok[j] && !(rband && colband[j]) && r1_exact_peak(P, rows, cols, r0 + cr, cb + j, wrap, thr_below, cmax))
+          won |= 1ull << (cr * 4 + j);
+    }
+    if (won) {
+#pragma unroll
+      for (int cr = 0; cr < kR1Band; ++cr)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if ((won >> (cr * 4 + j)) & 1u) {
+            const int k = (cr / 2) * 2 + j / 2;
+            sv[k] = (int)(__float_as_uint(P[(long long)(r0 + cr) * cols + cb + j]) & 0x7fffffffu);
+            so = (so & ~(3u << 2 * k)) | ((uint32_t)((cr & 1) * 2 + (j & 1)) << 2 * k);
+          }
+    }
+  }
+  uint64_t mine[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const uint32_t first = (uint32_t)((r0 + 2 * (k / 2)) * cols + cb + 2 * (k % 2));
+    const uint32_t place = (so >> 2 * k) & 3u;
+    const uint32_t idx = first + (place >> 1) * (uint32_t)cols + (place & 1u);
+    mine[k] = sv[k] < 0 ? kNoKey : ((uint64_t)(~(uint32_t)sv[k]) << 32) | idx;
+  }
+  // a fresh read of the cutoff prunes more of the keys
+  wave_first_k(mine, wkeys[wave], lane, K, __hip_atomic_load(cut + plane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+               cut + plane, dst);
 }
 
 __global__ void k_fill_keys(uint64_t* __restrict__ p, int n) {
@@ -545,22 +816,37 @@ static hipError_t reduce_lists(uint64_t* cand, int planes_n, int lists, int K, c
   return hipSuccess;
 }
 
-int peaks_tiles(int rows, int cols) { return ((rows + kTileR - 1) / kTileR) * ((cols + kTileC - 1) / kTileC); }
+static int peaks_tiles_lds(int rows, int cols) {
+  return ((rows + kTileR - 1) / kTileR) * ((cols + kTileC - 1) / kTileC);
+}
+// in units of kPeakThreads / 64 lists per plane: the larger need of the two stage-1 kernels
+int peaks_tiles(int rows, int cols) {
+  const int a = peaks_tiles_lds(rows, cols), b = peaks_r1_tiles(rows, cols);
+  return a > b ? a : b;
+}
 
 hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int batch, int nspaces, int space0,
                         const int* rows, const int* cols, const int* himg, const long long* offset, int K, float thr,
                         int radius, int wrap, int keep_border, ft_peak* peaks, int32_t* n_found, void* ws,
                         hipStream_t s) {
   PlaneGeom g[2];
+  // radius 1 on planes of at least 32 x 128 cells, 16-byte aligned rows:
+  // the register kernel (per-image offsets from a table are multiples of 4
+  // floats: ragged plans check their descriptors for it)
+  bool r1 = radius == 1 && ((uintptr_t)planes & 15) == 0 && (map.out_off || (map.out_stride & 3) == 0);
+  for (int i = 0; i < nspaces; ++i)
+    r1 = r1 && rows[i] >= 32 && cols[i] >= 128 && (cols[i] & 3) == 0 && (offset[i] & 3) == 0;
   int tiles = 0;
   for (int i = 0; i < nspaces; ++i) {
     g[i] = PlaneGeom{rows[i], cols[i], himg[i], offset[i]};
-    const int t = peaks_tiles(rows[i], cols[i]);
+    const int t = r1 ? peaks_r1_tiles(rows[i], cols[i]) : peaks_tiles_lds(rows[i], cols[i]);
     tiles = t > tiles ? t : tiles;
   }
   if (nspaces == 1) g[1] = g[0];
   if (radius < 1 || radius > kMaxRadius) return hipErrorInvalidValue;
   const int planes_n = batch * nspaces;
+  // lists per plane: one per wave of a tile (peaks_tiles sizes the
+  // workspace for the larger count of the two kernels)
   const size_t lists = (size_t)tiles * (kPeakThreads / 64);
   const size_t lvl1 = (lists + merge_group(K) - 1) / merge_group(K);
   uint64_t* cand = static_cast<uint64_t*>(ws);
@@ -570,15 +856,20 @@ hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int ba
   if (e != hipSuccess) return e;
   const dim3 grid1((unsigned)(tiles * planes_n));
   const float thr_below = std::nextafter(thr, -INFINITY);   // v >= thr  <=>  v > thr_below
-  switch (radius) {
+  if (r1) {
+    k_peaks_r1<<<grid1, kPeakThreads, 0, s>>>(planes, map, g[0], g[1], nspaces, planes_n, tiles, K, thr_below, wrap,
+                                              keep_border, cut, cand);
+  } else {
+    switch (radius) {
 #define CASE(R)                                                                                              \
   case R:                                                                                                    \
     k_peaks_tile<R><<<grid1, kPeakThreads, 0, s>>>(planes, map, g[0], g[1], nspaces, planes_n, tiles, K, thr_below, \
                                                    wrap, keep_border, cut, cand);                            \
     break;
-    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+      CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
-    default: return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;

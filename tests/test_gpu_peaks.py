@@ -53,20 +53,29 @@ def upload_planes(plan, planes_list_per_image):
     return torch.from_numpy(buf).cuda()
 
 
-@pytest.mark.parametrize("K,T,radius,flags", [
-    (8, 0.0, 1, 0),
-    (16, 0.0, 1, F.FT_PEAK_CLAMP_BORDER),
-    (5, 0.0, 2, F.FT_PEAK_KEEP_PAD_BOUNDARY),
-    (32, 0.5, 1, 0),
-    (256, 0.0, 1, 0),
+@pytest.mark.parametrize("N,M,Np,K,T,radius,flags", [
+    (96, 160, 0, 8, 0.0, 1, 0),
+    (96, 160, 0, 16, 0.0, 1, F.FT_PEAK_CLAMP_BORDER),
+    (96, 160, 0, 5, 0.0, 2, F.FT_PEAK_KEEP_PAD_BOUNDARY),
+    (96, 160, 0, 32, 0.5, 1, 0),
+    (96, 160, 0, 256, 0.0, 1, 0),
+    # planes of >= 128 columns (multiples of 4) take the radius-1 register
+    # kernel: 1080 rows end inside a 16-row band and leave the last block's
+    # last band empty; the 320-column plane ends inside its second column
+    # tile and has more tiles than the 160-column one
+    (160, 320, 1080, 8, 0.0, 1, 0),
+    (160, 320, 1080, 16, 0.0, 1, F.FT_PEAK_CLAMP_BORDER),
+    (160, 320, 1080, 16, 0.0, 1, F.FT_PEAK_KEEP_PAD_BOUNDARY),
+    (160, 320, 1080, 32, 0.5, 1, 0),
+    (160, 320, 1080, 256, 0.0, 1, 0),
 ])
-def test_peaks_bitwise_on_shared_plane(K, T, radius, flags):
+def test_peaks_bitwise_on_shared_plane(N, M, Np, K, T, radius, flags):
     """Both sides read the same FP32 plane (the oracle's, rounded), so the
     orders they compare are identical and the lists must match exactly."""
-    say(f"peaks bitwise K={K} T={T} r={radius} flags={flags}")
+    say(f"peaks bitwise {N}x{M} Np={Np} K={K} T={T} r={radius} flags={flags}")
     import torch
-    N, M, B = 96, 160, 2
-    plan = F.FunnelPlan(B, N, M)
+    B = 2
+    plan = F.FunnelPlan(B, N, M, padded_len=Np)
     imgs = [synth.mixed_lines(N, M, 4, 0.1, np.random.default_rng(40 + i)) for i in range(B)]
     per_image = []
     for im in imgs:
@@ -88,6 +97,41 @@ def test_peaks_bitwise_on_shared_plane(K, T, radius, flags):
                 k, bb = O.peak_params(idx // shape[1], idx % shape[1], N, M, plan.Np, name)
                 assert abs(rec_["slope"] - k) < 1e-5 and abs(rec_["intercept"] - bb) < 1e-3
                 assert rec_["image"] == b and rec_["space"] == s
+
+
+@pytest.mark.parametrize("K,flags", [(16, 0), (64, F.FT_PEAK_CLAMP_BORDER)])
+def test_peaks_isolated_nan_cells(K, flags):
+    """A NaN cell is never a peak and never hides a neighbour, which is what
+    the literal procedure does with NaN sorted last (every real neighbour is
+    visited before it): planes with isolated NaN cells give the oracle's
+    list.  On the radius-1 register kernel the NaN sends its band to the
+    general path."""
+    import torch
+    N, M, Np, B = 160, 320, 1080, 2
+    say(f"peaks with NaN cells K={K} flags={flags}")
+    plan = F.FunnelPlan(B, N, M, padded_len=Np)
+    rng = np.random.default_rng([83, K])
+    per_image = []
+    for b in range(B):
+        planes = []
+        for (rows, cols) in ((Np, M), (Np, N)):
+            P = np.abs(rng.standard_normal((rows, cols))).astype(np.float32)
+            r = 3 * rng.choice(rows // 3, 40, replace=False) + 1     # no two NaN cells touch
+            c = 3 * rng.choice(cols // 3, 40, replace=False) + 1
+            P[r, c] = np.nan
+            planes.append(P)
+        per_image.append(planes)
+    dev = upload_planes(plan, per_image)
+    rec, cnt = plan.peaks(dev, K=K, threshold=0.0, radius=1, flags=flags)
+    torch.cuda.synchronize()
+    got = F.peaks_to_numpy(rec, cnt)
+    wrap = not (flags & F.FT_PEAK_CLAMP_BORDER)
+    for b in range(B):
+        for s, (name, shape, (h, w)) in enumerate(plane_shapes(N, M, Np, 3)):
+            Bp = per_image[b][s].astype(np.float64)
+            want = oracle_peaks(Bp, K, 0.0, 1, O.boundary_mask(h, w, Np), wrap)
+            g = got[b][s]
+            assert [int(r) * shape[1] + int(c) for r, c in zip(g["row"], g["col"])] == want, (b, s)
 
 
 def cutoff_planes(kind, shape, rng):
