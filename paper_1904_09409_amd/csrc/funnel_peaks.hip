@@ -527,22 +527,18 @@ __global__ void __launch_bounds__(kPeakThreads, 4)
                uint64_t* __restrict__ out) {
   constexpr int NW = kPeakThreads / 64, HR = kR1Band + 2, NS = kR1Band / 2 * 2;
   __shared__ uint64_t wkeys[NW][128];   // the register sort's staging
-  // grid (planes, row tiles, column tiles): the planes are dealt
-  // round-robin, and no index needs a division
-  const int plane = blockIdx.x;
-  const int img = nspaces == 2 ? plane >> 1 : plane, sp = nspaces == 2 ? plane & 1 : 0;
+  const int plane = blockIdx.x % nplanes;   // planes dealt round-robin
+  const int img = plane / nspaces, sp = plane % nspaces;
   const PlaneGeom g = sp == 0 ? g0 : g1;
   const int rows = g.rows, cols = g.cols;
-  // the plane's offset is uniform; saying so keeps the buffer resource
-  // below in scalar registers (a table entry is otherwise read per lane)
-  const long long off = map.out(img) + g.offset;
-  const float* P = planes + (((long long)__builtin_amdgcn_readfirstlane((int)(off >> 32)) << 32) |
-                             (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)off));
-  const int tile = blockIdx.y * gridDim.z + blockIdx.z;
+  const float* P = planes + map.out(img) + g.offset;
+  const int tcn = (cols + kR1TileC - 1) / kR1TileC;
+  const int ntile = tcn * ((rows + kR1TileR - 1) / kR1TileR);
+  const int tile = blockIdx.x / nplanes;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint64_t* dst = out + (((long long)plane * tiles + tile) * NW + wave) * K;
-  const int r0 = blockIdx.y * kR1TileR + wave * kR1Band, c0 = blockIdx.z * kR1TileC;
-  if (r0 >= rows || c0 >= cols) {   // a band past the last row or column (the other space's plane is larger)
+  const int r0 = (tile / tcn) * kR1TileR + wave * kR1Band, c0 = (tile % tcn) * kR1TileC;
+  if (tile >= ntile || r0 >= rows) {   // the other space's plane has more tiles, or a band past the last row
     for (int i = lane; i < K; i += 64) dst[i] = kNoKey;
     return;
   }
@@ -556,6 +552,11 @@ __global__ void __launch_bounds__(kPeakThreads, 4)
   // and lie on one side of it (cols is a multiple of 4).  Absent cells read
   // row r0, column 0.
   const int cb = c0 + 4 * lane;
+  auto row_ptr = [&](int lr, bool& rin) {   // uniform: SGPRs
+    rin = true;
+    const int rr = wrap1(r0 - 1 + lr, rows, wrap, rin);
+    return P + (long long)(rin ? rr : r0) * cols;
+  };
   // halo columns c0 - 1 (lanes 0-17, row lane) and c0 + 256 (lanes 32-49,
   // row lane - 32); c0 + 256 - cols may reach cols once.  Issued first: the
   // first row needs it.
@@ -569,42 +570,27 @@ __global__ void __launch_bounds__(kPeakThreads, 4)
     const int rr = wrap1(r0 - 1 + lr, rows, wrap, in);
     hal = cell_bits(P[(long long)(in ? rr : r0) * cols + (in ? c : 0)], in);
   }
-  // The band's rows through a buffer resource over the plane: each lane's
-  // byte offset (its column) is the same for every row, and a row's offset
-  // is one scalar register, so a row costs one load instruction and no
-  // per-lane address arithmetic.  Unconditional loads (an absent cell reads
-  // row r0, column 0) keep all of them in flight.
-  typedef unsigned u4 __attribute__((ext_vector_type(4)));
-  const __amdgpu_buffer_rsrc_t rsrc =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(P), (short)0, rows * cols * 4, 0x00020000);
-  u4 raw[HR];
+  float4 raw[HR];
   bool rowin[HR];
   bool cin = true;
   {
     const int cw = wrap1(cb, cols, wrap, cin);
-    const int co = (cin ? cw : 0) * 4;   // one byte offset per lane, for every row
-    if (r0 >= 1 && r0 + kR1Band < rows) {   // every row inside the plane: consecutive offsets
+    const uint32_t co = cin ? (uint32_t)cw : 0u;   // one 32-bit column offset per lane, for every row
 #pragma unroll
-      for (int lr = 0; lr < HR; ++lr) {
-        rowin[lr] = true;
-        raw[lr] = __builtin_amdgcn_raw_buffer_load_b128(rsrc, co, (r0 - 1 + lr) * cols * 4, 0);
-      }
-    } else {
-#pragma unroll
-      for (int lr = 0; lr < HR; ++lr) {
-        bool rin = true;
-        const int rr = wrap1(r0 - 1 + lr, rows, wrap, rin);
-        rowin[lr] = rin;
-        raw[lr] = __builtin_amdgcn_raw_buffer_load_b128(rsrc, co, (rin ? rr : r0) * cols * 4, 0);
-      }
+    for (int lr = 0; lr < HR; ++lr) {
+      // unconditional loads (an absent cell reads column 0) keep all in flight
+      const float* rp = row_ptr(lr, rowin[lr]);
+      raw[lr] = *reinterpret_cast<const float4*>(rp + co);
     }
   }
   // row lr as cell bits, converted where it is first used (rows arrive in order)
   int x[HR][4];
   auto convert = [&](int lr) {
     const bool in = rowin[lr] && cin;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) x[lr][j] = cell_bits(__uint_as_float(raw[lr][j]), in);
+    x[lr][0] = cell_bits(raw[lr].x, in);
+    x[lr][1] = cell_bits(raw[lr].y, in);
+    x[lr][2] = cell_bits(raw[lr].z, in);
+    x[lr][3] = cell_bits(raw[lr].w, in);
   };
 
   // a key precedes the cutoff key cmax when |P| exceeds the value part of
@@ -850,19 +836,12 @@ hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int ba
   bool r1 = radius == 1 && ((uintptr_t)planes & 15) == 0 && (map.out_off || (map.out_stride & 3) == 0);
   for (int i = 0; i < nspaces; ++i)
     r1 = r1 && rows[i] >= 32 && cols[i] >= 128 && (cols[i] & 3) == 0 && (offset[i] & 3) == 0;
-  // tiles per plane: the LDS kernel's, or the register kernel's grid of row
-  // and column tiles (the larger plane's of each); ws_tiles: what the
-  // workspace was sized for (peaks_tiles, the larger need of the two)
-  int tiles = 0, ws_tiles = 0, nrt = 0, nct = 0;
+  int tiles = 0;
   for (int i = 0; i < nspaces; ++i) {
     g[i] = PlaneGeom{rows[i], cols[i], himg[i], offset[i]};
-    tiles = std::max(tiles, peaks_tiles_lds(rows[i], cols[i]));
-    ws_tiles = std::max(ws_tiles, peaks_tiles(rows[i], cols[i]));
-    nrt = std::max(nrt, (rows[i] + kR1TileR - 1) / kR1TileR);
-    nct = std::max(nct, (cols[i] + kR1TileC - 1) / kR1TileC);
+    const int t = r1 ? peaks_r1_tiles(rows[i], cols[i]) : peaks_tiles_lds(rows[i], cols[i]);
+    tiles = t > tiles ? t : tiles;
   }
-  if (r1) tiles = nrt * nct;
-  if (tiles > ws_tiles) return hipErrorInvalidValue;   // (planes of one launch share their row count)
   if (nspaces == 1) g[1] = g[0];
   if (radius < 1 || radius > kMaxRadius) return hipErrorInvalidValue;
   const int planes_n = batch * nspaces;
@@ -878,8 +857,8 @@ hipError_t launch_peaks(const float* planes, ImgMap map, const int* gidx, int ba
   const dim3 grid1((unsigned)(tiles * planes_n));
   const float thr_below = std::nextafter(thr, -INFINITY);   // v >= thr  <=>  v > thr_below
   if (r1) {
-    k_peaks_r1<<<dim3(planes_n, nrt, nct), kPeakThreads, 0, s>>>(planes, map, g[0], g[1], nspaces, planes_n, tiles,
-                                                                 K, thr_below, wrap, keep_border, cut, cand);
+    k_peaks_r1<<<grid1, kPeakThreads, 0, s>>>(planes, map, g[0], g[1], nspaces, planes_n, tiles, K, thr_below, wrap,
+                                              keep_border, cut, cand);
   } else {
     switch (radius) {
 #define CASE(R)                                                                                              \
