@@ -537,7 +537,13 @@ __global__ void __launch_bounds__(kPeakThreads, 4)
   const int tile = blockIdx.x / nplanes;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint64_t* dst = out + (((long long)plane * tiles + tile) * NW + wave) * K;
-  const int r0 = (tile / tcn) * kR1TileR + wave * kR1Band, c0 = (tile % tcn) * kR1TileC;
+  // Row tiles from the plane's centre outwards.  Any order gives the same
+  // lists; this one publishes high cutoffs first, because a parameter
+  // plane's strongest cells lie in its central rows (where the image itself
+  // maps), so later bands keep fewer keys.
+  const int nrt = (rows + kR1TileR - 1) / kR1TileR, t = tile / tcn;
+  const int rt = nrt / 2 + ((t & 1) ? -((t + 1) >> 1) : (t >> 1));   // a permutation of 0 .. nrt-1
+  const int r0 = rt * kR1TileR + wave * kR1Band, c0 = (tile % tcn) * kR1TileC;
   if (tile >= ntile || r0 >= rows) {   // the other space's plane has more tiles, or a band past the last row
     for (int i = lane; i < K; i += 64) dst[i] = kNoKey;
     return;
