@@ -119,10 +119,21 @@ __device__ __forceinline__ void split2(float x, T& hi, T& lo) {
 // split2 of a complex value (a, b), the parts packed as (a, b) pairs.  BF16:
 // one packed conversion for the two high parts, whose FP32 values are the
 // packed bits shifted into place (exact), and one for the two low parts --
-// the same values as split2, in a third of the instructions.
+// the same values as split2, in a third of the instructions.  FP16: packed
+// conversions for the high and the low parts (both round to nearest, as
+// split2's), the high parts widened back one by one.
 template <class T>
 __device__ __forceinline__ void split2_pair(float a, float b, T& ha, T& hb, T& la, T& lb) {
-  if constexpr (std::is_same<T, __bf16>::value) {
+  if constexpr (std::is_same<T, _Float16>::value) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+    const h2v h = __builtin_convertvector((f2v){a, b}, h2v);
+    const h2v l = __builtin_convertvector((f2v){a - (float)h[0], b - (float)h[1]}, h2v);
+    ha = h[0];
+    hb = h[1];
+    la = l[0];
+    lb = l[1];
+  } else if constexpr (std::is_same<T, __bf16>::value) {
     typedef float f2v __attribute__((ext_vector_type(2)));
     typedef __bf16 b2v __attribute__((ext_vector_type(2)));
     const b2v h = __builtin_convertvector((f2v){a, b}, b2v);
