@@ -353,38 +353,45 @@ constexpr int kColVariants = 8;   // register tiles 0-7; 8-10 are the LDS-reside
 // range checking (offsets at or beyond `bytes`, including negative offsets,
 // read 0 and drop stores), which replaces per-element bounds tests and
 // 64-bit address arithmetic in the column kernels.
-struct GBuf {
+//
+// LD and ST are the cache-policy bits of the loads and the stores (0, or kNT:
+// the non-temporal hint, the line is among the first to be evicted).
+constexpr int kNT = 2;
+template <int LD = 0, int ST = 0>
+struct GBufT {
   __amdgpu_buffer_rsrc_t r;
-  __device__ GBuf(const void* base, long long bytes)
+  __device__ GBufT(const void* base, long long bytes)
       : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
                                             (int)(bytes < 0x7fffffffll ? bytes : 0x7fffffffll), 0x00020000)) {}
   // (values move through vector registers component by component: a bit_cast
   // to HIP's float2/float4 structs would go through scratch memory)
   __device__ __forceinline__ float ld1(int off) const {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, LD));
   }
   __device__ __forceinline__ float2 ld2(int off) const {
-    const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, LD);
     return make_float2(__uint_as_float(u[0]), __uint_as_float(u[1]));
   }
   __device__ __forceinline__ float4 ld4(int off) const {
-    const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, LD);
     return make_float4(__uint_as_float(u[0]), __uint_as_float(u[1]), __uint_as_float(u[2]), __uint_as_float(u[3]));
   }
   __device__ __forceinline__ void st1(float v, int off) const {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, ST);
   }
   __device__ __forceinline__ void st2(float2 v, int off) const {
     typedef unsigned u2 __attribute__((ext_vector_type(2)));
     const u2 u = {__float_as_uint(v.x), __float_as_uint(v.y)};
-    __builtin_amdgcn_raw_buffer_store_b64(u, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(u, r, off, 0, ST);
   }
   __device__ __forceinline__ void st4(float4 v, int off) const {
     typedef unsigned u4 __attribute__((ext_vector_type(4)));
     const u4 u = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w)};
-    __builtin_amdgcn_raw_buffer_store_b128(u, r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(u, r, off, 0, ST);
   }
 };
+
+using GBuf = GBufT<>;
 
 __device__ __forceinline__ float2 sel2(bool c, float2 a, float2 b) {
   return make_float2(c ? a.x : b.x, c ? a.y : b.y);
@@ -394,7 +401,8 @@ __device__ __forceinline__ float2 sel2(bool c, float2 a, float2 b) {
 // of the pair's complex transform: A = (Z_k + conj Z_{L-k})/2 and
 // B = (Z_k - conj Z_{L-k})/(2i), times scale (-1)^k.  Rows outside 1 .. H fall
 // outside the buffer and are dropped.
-__device__ __forceinline__ void emit_pair(GBuf dst, int k, float2 zk, float2 zm, float scale, int npairs, int pg) {
+template <class Buf>
+__device__ __forceinline__ void emit_pair(Buf dst, int k, float2 zk, float2 zm, float scale, int npairs, int pg) {
   const float sc = (k & 1) ? -0.5f * scale : 0.5f * scale;
   const float ux = zk.x - zm.x, uy = zk.y + zm.y;
   dst.st4(make_float4(sc * (zk.x + zm.x), sc * (zk.y - zm.y), sc * uy, -sc * ux), ((k - 1) * npairs + pg) * 16);
@@ -442,8 +450,13 @@ __device__ __forceinline__ void r2c_tile(const float* __restrict__ in, float2* _
 
   const int npairs = nlines >> 1;
   const int pair = live ? tid % LINES : 0, t = live ? tid / LINES : 0;
-  // one image's lin x nlines block (rows of the padded frame off .. off+lin-1)
-  const GBuf src(in + map.in(img), (long long)lin * nlines * 4);
+  // one image's lin x nlines block (rows of the padded frame off .. off+lin-1);
+  // non-temporal loads where each load instruction reads whole 128-byte lines
+  // (FP32 lane layout, one group of at least 16 pairs, not transposed): no
+  // other tile reads them.  Where a line is split between groups or tiles,
+  // the hint would evict it before its second reader.
+  constexpr int kLd = (PREC == kPrecFP32 && !TRANS && NT == 1 && LINES * 8 >= 128) ? kNT : 0;
+  const GBufT<kLd, 0> src(in + map.in(img), (long long)lin * nlines * 4);
 
   float2 v[NT][E];
   if constexpr (PREC != kPrecFP32) {
@@ -558,8 +571,19 @@ __device__ __forceinline__ void c2r_tile(const float2* __restrict__ in, float* _
 
   const int npairs = nlines >> 1;
   const int pair = live ? tid % LINES : 0, t = live ? tid / LINES : 0;
-  // half-spectrum rows 1 .. L/2-1; row 0 (and anything outside) reads 0
-  const GBuf src(in + map.in(img), (long long)(L / 2 - 1) * npairs * 16);
+  // half-spectrum rows 1 .. L/2-1; row 0 (and anything outside) reads 0.
+  // Cache policy as in the column R2C: non-temporal loads of the spectrum
+  // (read in the paired layout at every precision) where each load
+  // instruction covers whole 128-byte lines.  With the FP32 engine's output
+  // layout also non-temporal reads of an accumulated output under the same
+  // rule, and non-temporal stores of the transposed output, whose 4-byte
+  // stores of one instruction fall on as many different lines; from the
+  // matrix-core engine's layout the hint on those stores is measured slower.
+  constexpr bool kF32 = PREC == kPrecFP32;
+  constexpr int kLd = (!TRANS && NT == 1 && LINES * 16 >= 128) ? kNT : 0;
+  constexpr int kLdAcc = (kF32 && !TRANS && NT == 1 && LINES * 8 >= 128) ? kNT : 0;
+  constexpr int kSt = (kF32 && TRANS) ? kNT : 0;
+  const GBufT<kLd, 0> src(in + map.in(img), (long long)(L / 2 - 1) * npairs * 16);
 
   // Butterfly ja reads inputs ja + r NB0.  Below L/2 (r < NA) they are stored
   // coefficients; above, the mirror L - idx = jb + (R0-1-r) NB0 is one of
@@ -614,7 +638,7 @@ __device__ __forceinline__ void c2r_tile(const float2* __restrict__ in, float* _
   }
 
   // one image's nout x nlines block (or nlines x nout, transposed)
-  const GBuf dst(out + map.out(img), (long long)nout * nlines * 4);
+  const GBufT<kLdAcc, kSt> dst(out + map.out(img), (long long)nout * nlines * 4);
   const int step = TRANS ? 4 : nlines * 4;
 #pragma unroll
   for (int g = 0; g < NT; ++g) {
