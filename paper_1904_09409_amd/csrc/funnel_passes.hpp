@@ -576,13 +576,13 @@ __device__ __forceinline__ void c2r_tile(const float2* __restrict__ in, float* _
   // (read in the paired layout at every precision) where each load
   // instruction covers whole 128-byte lines.  With the FP32 engine's output
   // layout also non-temporal reads of an accumulated output under the same
-  // rule, and non-temporal stores of the transposed output, whose 4-byte
-  // stores of one instruction fall on as many different lines; from the
+  // rule, and non-temporal stores of the image gradient (the transposed
+  // output and the accumulated one: no later pass reads it); from the
   // matrix-core engine's layout the hint on those stores is measured slower.
   constexpr bool kF32 = PREC == kPrecFP32;
   constexpr int kLd = (!TRANS && NT == 1 && LINES * 16 >= 128) ? kNT : 0;
   constexpr int kLdAcc = (kF32 && !TRANS && NT == 1 && LINES * 8 >= 128) ? kNT : 0;
-  constexpr int kSt = (kF32 && TRANS) ? kNT : 0;
+  constexpr int kSt = (kF32 && (TRANS || ACCUM)) ? kNT : 0;
   const GBufT<kLd, 0> src(in + map.in(img), (long long)(L / 2 - 1) * npairs * 16);
 
   // Butterfly ja reads inputs ja + r NB0.  Below L/2 (r < NA) they are stored
