@@ -149,6 +149,19 @@ __device__ __forceinline__ void split2_pair(float a, float b, T& ha, T& hb, T& l
   }
 }
 
+// Maximum of m over the four 16-lane rows of the wave (lanes n, n+16, n+32,
+// n+48): each lane swap exchanges rows between two copies of the value, so
+// the larger of the two results is the maximum over the swapped pair, with
+// no trip through the LDS crossbar.
+__device__ __forceinline__ float max_over_rows(float m) {
+  const unsigned u = __float_as_uint(m);
+  const auto p = __builtin_amdgcn_permlane16_swap(u, u, false, false);   // rows 0<->1, 2<->3
+  m = fmaxf(__uint_as_float(p[0]), __uint_as_float(p[1]));
+  const unsigned v = __float_as_uint(m);
+  const auto q = __builtin_amdgcn_permlane32_swap(v, v, false, false);   // halves 0-31 <-> 32-63
+  return fmaxf(__uint_as_float(q[0]), __uint_as_float(q[1]));
+}
+
 // Power of two s with m s in [2^14, 2^15) (clamped to normal floats), and 1/s.
 __device__ __forceinline__ void fp16_scale(float m, float& s, float& inv) {
   const int e = (int)((__float_as_uint(m) >> 23) & 0xff);
@@ -462,9 +475,7 @@ struct FftM {
       float mx = 0.f;
 #pragma unroll
       for (int i = 0; i < PER; ++i) mx = fmaxf(mx, fmaxf(fabsf(x[i].x), fabsf(x[i].y)));
-      mx = fmaxf(mx, __shfl_xor(mx, 16));
-      mx = fmaxf(mx, __shfl_xor(mx, 32));
-      fp16_scale(mx, sc, inv);
+      fp16_scale(max_over_rows(mx), sc, inv);
     }
     static_assert(R == 16 || R == 8, "radix 16 or 8");
 #pragma unroll
